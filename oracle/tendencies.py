@@ -1,0 +1,172 @@
+"""Nonhydrostatic tendencies (everything but the nonhydrostatic pressure).
+
+Momentum: flux-form advection (flux-form-advection equation; momentum
+advection subsection: a high-order centred advecting velocity times a WENO
+reconstruction of the advected component), f-plane Coriolis, buoyancy from a
+linear equation of state, constant-coefficient Laplacian closure
+(ScalarDiffusivity).  Tracers: flux divergence of advective + diffusive
+fluxes (flux-divergence and advection-flux-divergence equations) with a
+prescribed flux through the top wall.
+
+Readings where the paper is silent:
+* the advecting-velocity interpolation for momentum is centred fourth order,
+  (-a0 + 7 a1 + 7 a2 - a3) / 12;
+* Coriolis uses four-point averages of the other horizontal component;
+* buoyancy b = g (alpha (T - T0) - beta (S - S0)) enters G_w averaged to
+  the w faces;
+* walls are impenetrable, free-slip and no-flux except for the prescribed
+  top tracer flux (upward positive).
+
+All tendencies are returned as interior arrays; G_w has nz + 1 faces when z
+is bounded (wall faces hold 0).
+"""
+import numpy as np
+
+from .fv import view
+from .weno import reconstruct
+
+OFFSETS = (-3, -2, -1, 0, 1, 2)
+
+
+def interp4(a0, a1, a2, a3):
+    """Centred fourth-order interpolation to the midpoint of a1 and a2."""
+    return (-a0 + 7.0 * a1 + 7.0 * a2 - a3) / 12.0
+
+
+def _rec(ph, qs, vel):
+    return reconstruct(ph.advection, qs, vel, ph.weno_eps, ph.weno_q)
+
+
+def _div(Fx, Fy, Fz, ph):
+    """Flux divergence on a uniform grid: (1/V) sum over directions of
+    delta(A F); fluxes carry one extra entry along their own axis."""
+    dx, dy, dz = ph.spacing
+    return ((Fx[:, :, 1:] - Fx[:, :, :-1]) / dx
+            + (Fy[:, 1:, :] - Fy[:, :-1, :]) / dy
+            + (Fz[1:] - Fz[:-1]) / dz)
+
+
+def tracer_tendency(c, s, ph, top_flux=0.0):
+    """G_c for a centred tracer c given padded velocities s['u'], s['v'], s['w']."""
+    u, v, w = s["u"], s["v"], s["w"]
+    nx, ny, nz = ph.nx, ph.ny, ph.nz
+    dx, dy, dz = ph.spacing
+    k = ph.kappa
+    # x faces i = 0..nx
+    U = view(u, ni=nx + 1, ph=ph)
+    Fx = U * _rec(ph, [view(c, di=o, ni=nx + 1, ph=ph) for o in OFFSETS], U)
+    Fx = Fx - k * (view(c, ni=nx + 1, ph=ph) - view(c, di=-1, ni=nx + 1, ph=ph)) / dx
+    # y faces j = 0..ny
+    V = view(v, nj=ny + 1, ph=ph)
+    Fy = V * _rec(ph, [view(c, dj=o, nj=ny + 1, ph=ph) for o in OFFSETS], V)
+    Fy = Fy - k * (view(c, nj=ny + 1, ph=ph) - view(c, dj=-1, nj=ny + 1, ph=ph)) / dy
+    # z faces k = 0..nz
+    W = view(w, nk=nz + 1, ph=ph)
+    Fz = W * _rec(ph, [view(c, dk=o, nk=nz + 1, ph=ph) for o in OFFSETS], W)
+    Fz = Fz - k * (view(c, nk=nz + 1, ph=ph) - view(c, dk=-1, nk=nz + 1, ph=ph)) / dz
+    if ph.z_bounded:
+        Fz[0] = 0.0           # bottom wall: no flux
+        Fz[nz] = top_flux     # top wall: prescribed upward flux
+    return -_div(Fx, Fy, Fz, ph)
+
+
+def u_tendency(s, ph):
+    """Advection + diffusion of u at (F, C, C) and the Coriolis term."""
+    u, v, w = s["u"], s["v"], s["w"]
+    nx, ny, nz = ph.nx, ph.ny, ph.nz
+    dx, dy, dz = ph.spacing
+    nu = ph.nu
+    # x: entry i holds the flux at cell centre i-1 (between faces i-1 and i)
+    Ub = interp4(*[view(u, di=o, ni=nx + 1, ph=ph) for o in (-2, -1, 0, 1)])
+    X = Ub * _rec(ph, [view(u, di=o, ni=nx + 1, ph=ph) for o in OFFSETS], Ub)
+    X = X - nu * (view(u, ni=nx + 1, ph=ph) - view(u, di=-1, ni=nx + 1, ph=ph)) / dx
+    # y: corners (x face i, y face j); v interpolated along x to the x face
+    Vt = interp4(*[view(v, di=o, nj=ny + 1, ph=ph) for o in (-2, -1, 0, 1)])
+    Y = Vt * _rec(ph, [view(u, dj=o, nj=ny + 1, ph=ph) for o in OFFSETS], Vt)
+    Y = Y - nu * (view(u, nj=ny + 1, ph=ph) - view(u, dj=-1, nj=ny + 1, ph=ph)) / dy
+    # z: (x face i, centre j, z face k); w interpolated along x to the x face
+    Wt = interp4(*[view(w, di=o, nk=nz + 1, ph=ph) for o in (-2, -1, 0, 1)])
+    Z = Wt * _rec(ph, [view(u, dk=o, nk=nz + 1, ph=ph) for o in OFFSETS], Wt)
+    Z = Z - nu * (view(u, nk=nz + 1, ph=ph) - view(u, dk=-1, nk=nz + 1, ph=ph)) / dz
+    if ph.z_bounded:
+        Z[0] = 0.0
+        Z[nz] = 0.0
+    G = -_div(X, Y, Z, ph)
+    # Coriolis: -f z x u  ->  +f v averaged to the u point
+    vbar = 0.25 * (view(v, di=-1, ph=ph) + view(v, ph=ph)
+                   + view(v, di=-1, dj=1, ph=ph) + view(v, dj=1, ph=ph))
+    return G + ph.f * vbar
+
+
+def v_tendency(s, ph):
+    """Advection + diffusion of v at (C, F, C) and the Coriolis term."""
+    u, v, w = s["u"], s["v"], s["w"]
+    nx, ny, nz = ph.nx, ph.ny, ph.nz
+    dx, dy, dz = ph.spacing
+    nu = ph.nu
+    # x: corners (x face i, y face j); u interpolated along y to the y face
+    Ut = interp4(*[view(u, dj=o, ni=nx + 1, ph=ph) for o in (-2, -1, 0, 1)])
+    X = Ut * _rec(ph, [view(v, di=o, ni=nx + 1, ph=ph) for o in OFFSETS], Ut)
+    X = X - nu * (view(v, ni=nx + 1, ph=ph) - view(v, di=-1, ni=nx + 1, ph=ph)) / dx
+    # y: entry j holds the flux at cell centre j-1
+    Vb = interp4(*[view(v, dj=o, nj=ny + 1, ph=ph) for o in (-2, -1, 0, 1)])
+    Y = Vb * _rec(ph, [view(v, dj=o, nj=ny + 1, ph=ph) for o in OFFSETS], Vb)
+    Y = Y - nu * (view(v, nj=ny + 1, ph=ph) - view(v, dj=-1, nj=ny + 1, ph=ph)) / dy
+    # z: (centre i, y face j, z face k); w interpolated along y
+    Wt = interp4(*[view(w, dj=o, nk=nz + 1, ph=ph) for o in (-2, -1, 0, 1)])
+    Z = Wt * _rec(ph, [view(v, dk=o, nk=nz + 1, ph=ph) for o in OFFSETS], Wt)
+    Z = Z - nu * (view(v, nk=nz + 1, ph=ph) - view(v, dk=-1, nk=nz + 1, ph=ph)) / dz
+    if ph.z_bounded:
+        Z[0] = 0.0
+        Z[nz] = 0.0
+    G = -_div(X, Y, Z, ph)
+    # Coriolis: -f z x u  ->  -f u averaged to the v point
+    ubar = 0.25 * (view(u, dj=-1, ph=ph) + view(u, di=1, dj=-1, ph=ph)
+                   + view(u, ph=ph) + view(u, di=1, ph=ph))
+    return G - ph.f * ubar
+
+
+def buoyancy(s, ph):
+    """Linear equation of state, b = g (alpha (T - T0) - beta (S - S0)), at
+    cell centres (padded array).  The reference values only shift b by a
+    constant, whose face average is a discrete gradient removed exactly by
+    the projection."""
+    return ph.g * (ph.alpha * (s["T"] - ph.t_ref) - ph.beta * (s["S"] - ph.s_ref))
+
+
+def w_tendency(s, ph):
+    """Advection + diffusion of w at (C, C, F) plus buoyancy."""
+    u, v, w = s["u"], s["v"], s["w"]
+    nx, ny, nz = ph.nx, ph.ny, ph.nz
+    dx, dy, dz = ph.spacing
+    nu = ph.nu
+    # faces k = 0..nz-1 are computed; walls are overwritten below
+    # x: (x face i, centre j, z face k); u interpolated along z to the z face
+    Ut = interp4(*[view(u, dk=o, ni=nx + 1, ph=ph) for o in (-2, -1, 0, 1)])
+    X = Ut * _rec(ph, [view(w, di=o, ni=nx + 1, ph=ph) for o in OFFSETS], Ut)
+    X = X - nu * (view(w, ni=nx + 1, ph=ph) - view(w, di=-1, ni=nx + 1, ph=ph)) / dx
+    # y: (centre i, y face j, z face k); v interpolated along z
+    Vt = interp4(*[view(v, dk=o, nj=ny + 1, ph=ph) for o in (-2, -1, 0, 1)])
+    Y = Vt * _rec(ph, [view(w, dj=o, nj=ny + 1, ph=ph) for o in OFFSETS], Vt)
+    Y = Y - nu * (view(w, nj=ny + 1, ph=ph) - view(w, dj=-1, nj=ny + 1, ph=ph)) / dy
+    # z: entry k holds the flux at cell centre k-1 (between faces k-1 and k)
+    Wb = interp4(*[view(w, dk=o, nk=nz + 1, ph=ph) for o in (-2, -1, 0, 1)])
+    Z = Wb * _rec(ph, [view(w, dk=o, nk=nz + 1, ph=ph) for o in OFFSETS], Wb)
+    Z = Z - nu * (view(w, nk=nz + 1, ph=ph) - view(w, dk=-1, nk=nz + 1, ph=ph)) / dz
+    G = -_div(X, Y, Z, ph)
+    if ph.buoyancy:
+        b = buoyancy(s, ph)
+        G = G + 0.5 * (view(b, dk=-1, ph=ph) + view(b, ph=ph))
+    if ph.z_bounded:
+        G = np.concatenate([G, np.zeros((1, ny, nx))], axis=0)
+        G[0] = 0.0
+        G[nz] = 0.0
+    return G
+
+
+def tendencies(s, ph):
+    """All tendencies of the prognostic fields of a padded state dict."""
+    G = {"u": u_tendency(s, ph), "v": v_tendency(s, ph), "w": w_tendency(s, ph)}
+    for name in ph.tracers:
+        G[name] = tracer_tendency(s[name], s, ph, ph.top_flux.get(name, 0.0))
+    return G

@@ -1,0 +1,59 @@
+"""Low-storage third-order Runge-Kutta time stepping with pressure correction
+(time-discretisation appendix, rk3 equation and pressure-correction method).
+
+Substage m = 1, 2, 3:  X~ = X^m + dt (gamma_m G^m - zeta_m G^{m-1}) for every
+prognostic field, gamma = (8/15, 5/12, 3/4), zeta = (0, 17/60, 5/12); then the
+velocity is projected with dt_eff = (gamma_m - zeta_m) dt, the fraction of the
+step the substage spans (8/15, 2/15, 1/3).
+"""
+from .fv import to_padded, interior, w_faces
+from .tendencies import tendencies
+from .pressure import project
+
+GAMMA = (8.0 / 15.0, 5.0 / 12.0, 3.0 / 4.0)
+ZETA = (0.0, 17.0 / 60.0, 5.0 / 12.0)
+
+
+def fields_of(ph):
+    return ("u", "v", "w") + tuple(ph.tracers)
+
+
+def make_state(interiors, ph):
+    """Padded state dict (halos filled) from interior arrays."""
+    return {n: to_padded(interiors[n], ph, n) for n in fields_of(ph)}
+
+
+def state_interior(state, ph):
+    return {n: interior(state[n], ph, n) for n in fields_of(ph)}
+
+
+def rk3_substage(state, G_prev, m, dt, ph, project_velocity=True):
+    """One substage (m = 0, 1, 2).  Returns (new padded state, G^m, p)."""
+    G = tendencies(state, ph)
+    X = state_interior(state, ph)
+    new = {}
+    for n in fields_of(ph):
+        incr = GAMMA[m] * G[n]
+        if m > 0:
+            incr = incr - ZETA[m] * G_prev[n]
+        new[n] = X[n] + dt * incr
+    p = None
+    if project_velocity:
+        dt_eff = (GAMMA[m] - ZETA[m]) * dt
+        new["u"], new["v"], new["w"], p = project(new["u"], new["v"], new["w"], dt_eff, ph)
+    return make_state(new, ph), G, p
+
+
+def rk3_step(state, dt, ph, project_velocity=True):
+    """One full RK3 time step; returns (new state, last pressure)."""
+    G = None
+    p = None
+    for m in range(3):
+        state, G, p = rk3_substage(state, G, m, dt, ph, project_velocity)
+    return state, p
+
+
+def run(state, dt, nsteps, ph):
+    for _ in range(nsteps):
+        state, _ = rk3_step(state, dt, ph)
+    return state

@@ -1,0 +1,304 @@
+"""Seeded synthetic inputs shared by the GPU path, the tests and the benchmark.
+
+This module only *synthesises* data: random numbers, analytic profiles and
+physical parameter sets.  It contains none of the model's arithmetic (no
+reconstruction, flux, time-stepping or pressure-solve code), so a mistake in
+the model cannot hide here behind a shared helper.
+
+Array conventions (interior values only, C order, x fastest):
+
+* tracer-like fields (T, S, c) at cell centres: shape (nz, ny, nx);
+* u at x-faces (face i is the left face of cell i): (nz, ny, nx);
+* v at y-faces: (nz, ny, nx);
+* w at z-faces: (nz + 1, ny, nx) when z is bounded (faces 0 and nz are the
+  walls and hold 0), (nz, ny, nx) when z is periodic.
+
+The staggering is the Arakawa C-grid of the paper (finite-volume appendix,
+staggered-grid listing: "face indices are left of cell indices").
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field, asdict
+import numpy as np
+
+G_EARTH = 9.81
+
+
+@dataclass
+class Physics:
+    """Physical parameters of a nonhydrostatic configuration (plain data)."""
+
+    nx: int
+    ny: int
+    nz: int
+    lx: float
+    ly: float
+    lz: float
+    z_bounded: bool
+    x0: float = 0.0
+    y0: float = 0.0
+    z0: float = 0.0
+    advection: str = "weno5z"          # "weno5z" | "weno5_linear" | "none"
+    weno_eps: float = 1e-15
+    weno_q: int = 2
+    f: float = 0.0                      # f-plane Coriolis parameter
+    g: float = G_EARTH
+    alpha: float = 0.0                  # thermal expansion (linear EOS)
+    beta: float = 0.0                   # haline contraction (linear EOS)
+    t_ref: float = 0.0                  # EOS reference temperature
+    s_ref: float = 0.0                  # EOS reference salinity
+    nu: float = 0.0
+    kappa: float = 0.0
+    tracers: tuple = ("c",)
+    top_flux: dict = field(default_factory=dict)   # tracer -> upward flux at the top wall
+    buoyancy: bool = False
+
+    def as_dict(self):
+        return asdict(self)
+
+    @property
+    def spacing(self):
+        return (self.lx / self.nx, self.ly / self.ny, self.lz / self.nz)
+
+
+# ---------------------------------------------------------------------------
+# Configuration presets
+# ---------------------------------------------------------------------------
+
+def periodic_box_physics(n: int = 32) -> Physics:
+    """Triply periodic box, 2*pi on a side, WENO5 u,v,w,c, nu = kappa = 1e-3."""
+    L = 2.0 * np.pi
+    return Physics(nx=n, ny=n, nz=n, lx=L, ly=L, lz=L, z_bounded=False,
+                   nu=1e-3, kappa=1e-3, tracers=("c",))
+
+
+def convection_physics(n=(256, 256, 256), extent=(512.0, 512.0, 256.0),
+                       surface_buoyancy_flux: float = 1e-8,
+                       nu: float = 1e-5, kappa: float = 1e-5) -> Physics:
+    """Free-convection LES: periodic x,y, walls in z, f-plane, linear EOS.
+
+    The surface buoyancy flux Jb (upward positive: buoyancy leaves through the
+    top, i.e. the surface cools) becomes a temperature flux Jb / (g alpha).
+    """
+    nx, ny, nz = n
+    lx, ly, lz = extent
+    alpha, beta = 2e-4, 8e-4
+    return Physics(nx=nx, ny=ny, nz=nz, lx=lx, ly=ly, lz=lz, z_bounded=True,
+                   z0=-lz, f=1e-4, g=G_EARTH, alpha=alpha, beta=beta,
+                   t_ref=20.0, s_ref=35.0,
+                   nu=nu, kappa=kappa, tracers=("T", "S"), buoyancy=True,
+                   top_flux={"T": surface_buoyancy_flux / (G_EARTH * alpha)})
+
+
+# ---------------------------------------------------------------------------
+# Random velocity fields that are discretely divergence-free by construction
+# ---------------------------------------------------------------------------
+
+def _curl_of_potential(ax, ay, az, dx, dy, dz, bounded):
+    """Staggered curl of an edge-centred vector potential.
+
+    ax lives at (C, F, F), ay at (F, C, F), az at (F, F, C).  All arrays are
+    periodic in x and y; in z they have nz faces (periodic) or nz + 1 faces
+    (bounded, with the wall values already zero).  The discrete divergence of
+    the result is zero identically, so the generator needs no pressure solve.
+    """
+    def dx_f(a):  # forward difference along x, periodic
+        return (np.roll(a, -1, axis=2) - a) / dx
+
+    def dy_f(a):
+        return (np.roll(a, -1, axis=1) - a) / dy
+
+    if bounded:
+        def dz_f(a):  # a has nz + 1 faces -> nz centres
+            return (a[1:] - a[:-1]) / dz
+    else:
+        def dz_f(a):
+            return (np.roll(a, -1, axis=0) - a) / dz
+
+    u = dy_f(az) - dz_f(ay)
+    v = dz_f(ax) - dx_f(az)
+    w = dx_f(ay) - dy_f(ax)
+    return u, v, w
+
+
+def _spectral_potential(rng, n, kmax, slope, shifts, L):
+    """Random trigonometric field with modes 1 <= |k| <= kmax sampled at a
+    staggered offset `shifts` (fractions of a cell per axis)."""
+    nz, ny, nx = n
+    kx = np.fft.fftfreq(nx, d=1.0 / nx)
+    ky = np.fft.fftfreq(ny, d=1.0 / ny)
+    kz = np.fft.fftfreq(nz, d=1.0 / nz)
+    KZ, KY, KX = np.meshgrid(kz, ky, kx, indexing="ij")
+    K = np.sqrt(KX ** 2 + KY ** 2 + KZ ** 2)
+    shell = np.rint(K)
+    mask = (shell >= 1) & (shell <= kmax)
+    amp = np.zeros_like(K)
+    # energy E(K) ~ K^slope spread over the modes of each integer shell; the
+    # potential is one derivative smoother than the velocity.
+    for s in range(1, kmax + 1):
+        sel = mask & (shell == s)
+        nmodes = max(int(sel.sum()), 1)
+        amp[sel] = np.sqrt(s ** slope / nmodes) / s
+    coef = amp * (rng.standard_normal(K.shape) + 1j * rng.standard_normal(K.shape))
+    sx, sy, sz = shifts
+    phase = np.exp(2j * np.pi * (KX * sx / nx + KY * sy / ny + KZ * sz / nz))
+    field_ = np.fft.ifftn(coef * phase).real * (nx * ny * nz)
+    return field_
+
+
+def periodic_box_initial(ph: Physics, seed: int = 0, kmax: int = 8,
+                         slope: float = -5.0 / 3.0, rms: float = 1.0,
+                         nblobs: int = 8, sigma: float = 0.3):
+    """Initial state of the triply periodic box.
+
+    Velocity: curl of a random potential whose modes lie on integer shells
+    1 <= |k| <= kmax with energy ~ K^slope, scaled so that
+    sqrt(mean(u^2 + v^2 + w^2) / 3) = rms.  Tracer c: `nblobs` periodic
+    Gaussian blobs of width sigma and amplitude 1 at seeded positions.
+    """
+    assert not ph.z_bounded
+    rng = np.random.default_rng(seed)
+    n = (ph.nz, ph.ny, ph.nx)
+    dx, dy, dz = ph.spacing
+    L = (ph.lx, ph.ly, ph.lz)
+    ax = _spectral_potential(rng, n, kmax, slope, (0.5, 0.0, 0.0), L)
+    ay = _spectral_potential(rng, n, kmax, slope, (0.0, 0.5, 0.0), L)
+    az = _spectral_potential(rng, n, kmax, slope, (0.0, 0.0, 0.5), L)
+    u, v, w = _curl_of_potential(ax, ay, az, dx, dy, dz, bounded=False)
+    scale = rms / np.sqrt((np.mean(u * u) + np.mean(v * v) + np.mean(w * w)) / 3.0)
+    u, v, w = u * scale, v * scale, w * scale
+
+    xc = ph.x0 + (np.arange(ph.nx) + 0.5) * dx
+    yc = ph.y0 + (np.arange(ph.ny) + 0.5) * dy
+    zc = ph.z0 + (np.arange(ph.nz) + 0.5) * dz
+    Z, Y, X = np.meshgrid(zc, yc, xc, indexing="ij")
+    centres = rng.uniform(0.0, 1.0, size=(nblobs, 3)) * np.array(L) + np.array([ph.x0, ph.y0, ph.z0])
+    c = np.zeros(n)
+    for (bx, by, bz) in centres:
+        for mx in (-1, 0, 1):
+            for my in (-1, 0, 1):
+                for mz in (-1, 0, 1):
+                    r2 = ((X - bx - mx * ph.lx) ** 2 + (Y - by - my * ph.ly) ** 2
+                          + (Z - bz - mz * ph.lz) ** 2)
+                    c += np.exp(-r2 / (2.0 * sigma ** 2))
+    return {"u": u, "v": v, "w": w, "c": c}
+
+
+def convection_initial(ph: Physics, seed: int = 0, noise: float = 1e-3,
+                       t_surface: float = 20.0, n2: float = 1e-5, s0: float = 35.0):
+    """Initial state of the free-convection LES.
+
+    T(z) = t_surface + n2 / (g alpha) * z at cell centres (z <= 0), S = s0.
+    Velocity: curl of an i.i.d. Gaussian edge potential (zero on the walls),
+    scaled to an RMS of `noise` m/s per component; it is discretely
+    divergence-free and has w = 0 on the walls.
+    """
+    assert ph.z_bounded
+    rng = np.random.default_rng(seed)
+    nz, ny, nx = ph.nz, ph.ny, ph.nx
+    dx, dy, dz = ph.spacing
+    ax = rng.standard_normal((nz + 1, ny, nx))
+    ay = rng.standard_normal((nz + 1, ny, nx))
+    az = rng.standard_normal((nz, ny, nx))
+    ax[0] = ax[-1] = 0.0
+    ay[0] = ay[-1] = 0.0
+    u, v, w = _curl_of_potential(ax, ay, az, dx, dy, dz, bounded=True)
+    scale = noise / np.sqrt((np.mean(u * u) + np.mean(v * v) + np.mean(w[1:-1] * w[1:-1])) / 3.0)
+    u, v, w = u * scale, v * scale, w * scale
+    w[0] = 0.0
+    w[-1] = 0.0
+    zc = ph.z0 + (np.arange(nz) + 0.5) * dz
+    T = np.broadcast_to((t_surface + n2 / (ph.g * ph.alpha) * zc)[:, None, None], (nz, ny, nx)).copy()
+    S = np.full((nz, ny, nx), s0)
+    return {"u": u, "v": v, "w": w, "T": T, "S": S}
+
+
+def random_state(ph: Physics, seed: int = 0, vel: float = 1.0, tracer_scale: float = 1.0,
+                 divergence_free: bool = True):
+    """Rough random state for parity tests (every cell independent).
+
+    Velocities are the curl of an i.i.d. potential (divergence-free) unless
+    `divergence_free` is False, in which case they are i.i.d. Gaussian (w = 0
+    on walls).  Tracers are i.i.d. Gaussian around distinct means.
+    """
+    rng = np.random.default_rng(seed)
+    nz, ny, nx = ph.nz, ph.ny, ph.nx
+    nwz = nz + 1 if ph.z_bounded else nz
+    dx, dy, dz = ph.spacing
+    if divergence_free:
+        ax = rng.standard_normal((nwz, ny, nx))
+        ay = rng.standard_normal((nwz, ny, nx))
+        az = rng.standard_normal((nz, ny, nx))
+        if ph.z_bounded:
+            ax[0] = ax[-1] = 0.0
+            ay[0] = ay[-1] = 0.0
+        u, v, w = _curl_of_potential(ax, ay, az, dx, dy, dz, bounded=ph.z_bounded)
+        s = vel / np.sqrt(np.mean(u * u))
+        u, v, w = u * s, v * s, w * s
+    else:
+        u = vel * rng.standard_normal((nz, ny, nx))
+        v = vel * rng.standard_normal((nz, ny, nx))
+        w = vel * rng.standard_normal((nwz, ny, nx))
+    if ph.z_bounded:
+        w[0] = 0.0
+        w[-1] = 0.0
+    out = {"u": u, "v": v, "w": w}
+    for idx, name in enumerate(ph.tracers):
+        out[name] = (10.0 * idx + tracer_scale * rng.standard_normal((nz, ny, nx)))
+    return out
+
+
+def smooth_random_state(ph: Physics, seed: int = 0, kmax: int = 3, vel: float = 1.0):
+    """Smooth random state (low-wavenumber modes) for parity tests where the
+    nonlinear WENO weights should be close to their ideal values."""
+    rng = np.random.default_rng(seed)
+    nz, ny, nx = ph.nz, ph.ny, ph.nx
+    dx, dy, dz = ph.spacing
+    X = (np.arange(nx) + 0.5) / nx
+    Y = (np.arange(ny) + 0.5) / ny
+    Z = (np.arange(nz) + 0.5) / nz
+    Zc, Yc, Xc = np.meshgrid(Z, Y, X, indexing="ij")
+
+    def trig(shift=(0.0, 0.0, 0.0), zparity=None):
+        f = np.zeros((nz, ny, nx))
+        xs = Xc + shift[0] / nx
+        ys = Yc + shift[1] / ny
+        zs = Zc + shift[2] / nz
+        for _ in range(6):
+            kx, ky = rng.integers(-kmax, kmax + 1, size=2)
+            kz = rng.integers(0 if zparity else -kmax, kmax + 1)
+            a = rng.standard_normal()
+            ph_ = rng.uniform(0, 2 * np.pi)
+            arg = 2 * np.pi * (kx * xs + ky * ys) + ph_
+            if zparity == "even":
+                f += a * np.cos(np.pi * kz * zs) * np.cos(arg)
+            elif zparity == "odd":
+                f += a * np.sin(np.pi * max(kz, 1) * zs) * np.cos(arg)
+            else:
+                f += a * np.cos(arg + 2 * np.pi * kz * zs)
+        return f
+
+    even = "even" if ph.z_bounded else None
+    u = vel * trig((-0.5, 0, 0), even)
+    v = vel * trig((0, -0.5, 0), even)
+    if ph.z_bounded:
+        Zf = np.arange(nz + 1) / nz
+        wz = np.zeros((nz + 1, ny, nx))
+        Yw = (np.arange(ny) + 0.5) / ny
+        Xw = (np.arange(nx) + 0.5) / nx
+        Zg, Yg, Xg = np.meshgrid(Zf, Yw, Xw, indexing="ij")
+        for _ in range(6):
+            kx, ky = rng.integers(-kmax, kmax + 1, size=2)
+            kz = rng.integers(1, kmax + 1)
+            a = rng.standard_normal()
+            p = rng.uniform(0, 2 * np.pi)
+            wz += a * np.sin(np.pi * kz * Zg) * np.cos(2 * np.pi * (kx * Xg + ky * Yg) + p)
+        w = vel * wz
+        w[0] = 0.0
+        w[-1] = 0.0
+    else:
+        w = vel * trig((0, 0, -0.5))
+    out = {"u": u, "v": v, "w": w}
+    for idx, name in enumerate(ph.tracers):
+        out[name] = 10.0 * idx + trig((0, 0, 0), even)
+    return out
