@@ -1,0 +1,144 @@
+"""Benchmark: WENO5-Z RK3 nonhydrostatic step of a 256^3 free-convection LES
+on one MI355X, through the C ABI.
+
+Prints ONE JSON line with the whole-job throughput in cell-steps/s of the
+FP32-mixed path (FP32 state and stencils, FP64 Poisson solve and projection),
+the FP64 path beside it, per-kernel times from HIP events recorded on the
+model's stream, the roofline figure of the dominant kernel, and the CPU
+oracle timed on a bounded sample of the same workload.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 256] [--no-cpu]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
+FP32_BYTES_PER_CELL_STAGE = {0: 60, 1: 80, 2: 60}   # 5 fields: read X (+G), write X~ (+G)
+
+
+def algorithmic_tendency_bytes(ncells, nfields, esz, steps):
+    """Bytes the fused tendency + RK3 kernel must move per RK3 step: every
+    field read once and written once per substage, plus the G^{m-1} read
+    (substages 2, 3) and the G^m write (substages 1, 2)."""
+    per_cell = 0
+    for st in range(3):
+        per_cell += 2 * nfields * esz                    # read X^m, write X~
+        per_cell += nfields * esz * ((st > 0) + (st < 2))  # G traffic
+    return per_cell * ncells * steps
+
+
+def run_gpu(ph, s, precision, steps, warmup):
+    import torch
+    from paper_2502_14148_amd import oc
+    m = oc.Model(ph, precision)
+    m.set_states(s)
+    dt = 1.0
+    m.rk3_step(dt, warmup)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    m.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    m.rk3_step(dt, steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    m.profile(False)
+    prof = m.profile_read()
+    ms = e0.elapsed_time(e1)
+    diag = m.diagnostics()   # raises on non-finite state
+    del m
+    torch.cuda.empty_cache()
+    return ms, wall, prof, diag
+
+
+def cpu_baseline(n_sample):
+    """The FP64 oracle (NumPy) on a bounded sample: one RK3 step of the same
+    physics and horizontal grid on a slab of n_sample levels."""
+    from paper_2502_14148_amd import inputs
+    from oracle import timestep
+    ph = inputs.convection_physics((256, 256, n_sample), (512.0, 512.0, float(n_sample)))
+    s = inputs.convection_initial(ph, seed=0)
+    st = timestep.make_state(s, ph)
+    t0 = time.perf_counter()
+    st, _ = timestep.rk3_step(st, 1.0, ph)
+    el = time.perf_counter() - t0
+    cells = ph.nx * ph.ny * ph.nz
+    return {"value": cells / el, "unit": "cell-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"1 RK3 step (FP64 NumPy oracle) of the free-convection physics on a "
+                      f"256x256x{n_sample} slab at 2 m x 2 m x 1 m spacing, {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--cpu-levels", type=int, default=32)
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    from paper_2502_14148_amd import inputs
+    n = a.n
+    ph = inputs.convection_physics((n, n, n), (2.0 * n, 2.0 * n, 1.0 * n))
+    print(f"# generating the {n}^3 initial state", file=sys.stderr, flush=True)
+    s = inputs.convection_initial(ph, seed=0)
+    ncells = n ** 3
+    nf = 5
+
+    print("# FP32-mixed run", file=sys.stderr, flush=True)
+    ms32, wall32, prof32, diag32 = run_gpu(ph, s, "fp32", a.steps, a.warmup)
+    res = {}
+    if not a.no_fp64:
+        print("# FP64 run", file=sys.stderr, flush=True)
+        ms64, wall64, prof64, _ = run_gpu(ph, s, "fp64", a.steps, a.warmup)
+        res = {"value": ncells * a.steps / (ms64 / 1e3), "ms_per_step": ms64 / a.steps,
+               "kernels_ms_per_step": {k: v[0] / a.steps for k, v in prof64.items()}}
+
+    value = ncells * a.steps / (ms32 / 1e3)
+    t_tend_ms, n_tend = prof32["tendency"]
+    tbytes = algorithmic_tendency_bytes(ncells, nf, 4, a.steps)
+    achieved = tbytes / (t_tend_ms / 1e3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "tendency_rk3 (FP32)",
+                "avg_launch_ms": t_tend_ms / max(n_tend, 1),
+                "algorithmic_bytes_per_launch": tbytes / max(n_tend, 1)}
+    out = {
+        "metric": "cell-steps/s (WENO5 RK3 step, 256^3) + tendency-kernel HBM GB/s vs peak",
+        "value": value, "unit": "cell-steps/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": ms32 / a.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"free-convection LES {n}^3, WENO5-Z RK3 with FFT/DCT pressure "
+                               f"projection, FP32 state/stencils + FP64 Poisson",
+                   "grid": [n, n, n], "extent_m": [2.0 * n, 2.0 * n, 1.0 * n], "dt_s": 1.0},
+        "roofline": roofline,
+        "kernels_ms_per_step": {k: v[0] / a.steps for k, v in prof32.items()},
+        "fp64_path": res,
+        "wall_s_timed": wall32,
+        "final_max_w": diag32["max_w"],
+    }
+    if not a.no_cpu:
+        print("# CPU oracle sample", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(a.cpu_levels)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,171 @@
+/*
+ * oc.h -- C ABI of the MI355X (gfx950) hot path of the Oceananigans
+ * nonhydrostatic ocean model (Wagner et al., arXiv 2502.14148).
+ *
+ * The library computes, on one GPU, the per-time-step loop of the
+ * NonhydrostaticModel on a staggered Arakawa C-grid:
+ *   - tendencies of u, v, w and the tracers: flux-form WENO5-Z advection
+ *     (reconstruction subsection and momentum-advection subsection of the
+ *     finite-volume appendix), f-plane Coriolis, linear-EOS buoyancy,
+ *     constant-coefficient Laplacian closure and a prescribed top tracer flux
+ *     (nonhydrostatic momentum and tracer equations);
+ *   - low-storage RK3 substages (rk3 equation of the time-discretisation
+ *     appendix);
+ *   - the pressure correction: an FFT/DCT eigenfunction solve of the
+ *     discrete Poisson equation and the projection of the predictor velocity
+ *     (pressure-correction appendix, pressure-poisson equation).
+ *
+ * Conventions
+ *   Grid: cells i = 0..nx-1 (x fastest), j, k likewise.  Face i is the left
+ *   face of cell i.  u lives at (F,C,C), v at (C,F,C), w at (C,C,F), tracers
+ *   and pressure at (C,C,C).  x and y are periodic; z is periodic or bounded
+ *   by impenetrable, free-slip, no-flux walls (then w has nz+1 faces and the
+ *   wall faces hold 0).
+ *   Memory: all large device memory is BORROWED.  The caller allocates one
+ *   device workspace of oc_model_workspace_size() bytes (e.g. a torch tensor)
+ *   and keeps it alive until oc_model_destroy().  The library owns only small
+ *   host metadata.
+ *   Streams: every call that touches the GPU is enqueued asynchronously on
+ *   the hipStream_t passed as `void* stream` (NULL = the null stream).
+ *   Calls on one model must not overlap from several threads.
+ *   Errors: every function returns OC_OK (0) or a negative OC_ERR_* code;
+ *   oc_last_error() returns a per-thread message.  Arguments are validated
+ *   before anything is enqueued; on error nothing is enqueued and no state
+ *   changes.  Device-side faults surface at the next synchronising call.
+ */
+#ifndef OC_H
+#define OC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  OC_OK = 0,
+  OC_ERR_ARG = -1,          /* null pointer or out-of-range scalar        */
+  OC_ERR_SHAPE = -2,        /* array shape does not match the grid        */
+  OC_ERR_DTYPE = -3,        /* unsupported element type                   */
+  OC_ERR_DEVICE = -4,       /* HIP runtime error                          */
+  OC_ERR_UNSUPPORTED = -5,  /* configuration not supported by the kernels */
+  OC_ERR_NONFINITE = -6     /* a NaN/Inf was detected in the state        */
+};
+
+enum { OC_PERIODIC = 0, OC_BOUNDED = 1 };
+enum { OC_FP64 = 0, OC_FP32_MIXED = 1 };
+enum { OC_ADV_NONE = 0, OC_ADV_WENO5Z = 1, OC_ADV_WENO5_LINEAR = 2 };
+enum { OC_F32 = 0, OC_F64 = 1 };
+/* Field identifiers: velocities, then tracers 0..ntracers-1. */
+enum { OC_U = 0, OC_V = 1, OC_W = 2, OC_TRACER0 = 3 };
+#define OC_MAX_TRACERS 4
+#define OC_NDIAG 8
+
+/* Grid (RectilinearGrid of the library subsection; uniform spacing). */
+typedef struct {
+  int32_t nx, ny, nz;       /* cells; each a supported FFT length (see below) */
+  int32_t topology_z;       /* OC_PERIODIC or OC_BOUNDED (x, y are periodic)  */
+  double x0, lx;            /* domain [x0, x0 + lx) */
+  double y0, ly;
+  double z0, lz;
+} oc_grid_desc;
+
+/* Model physics (NonhydrostaticModel arguments of the equations section). */
+typedef struct {
+  int32_t precision;        /* OC_FP64: everything in FP64.  OC_FP32_MIXED:
+                               state, tendencies and the stencil arithmetic in
+                               FP32; divergence, Poisson solve and projection
+                               arithmetic in FP64.  With buoyancy, FP32 keeps T
+                               and S as anomalies about (t_ref, s_ref) (the
+                               ABI always exchanges full values) */
+  int32_t advection;        /* OC_ADV_*: WENO5-Z, its ideal-weight limit, or none */
+  double weno_eps;          /* WENO-Z regulariser (> 0) */
+  int32_t weno_q;           /* WENO-Z exponent; only 2 is supported */
+  int32_t ntracers;         /* 1..OC_MAX_TRACERS */
+  int32_t buoyancy;         /* 1: tracers 0, 1 are T, S and b = g(alpha(T-T0) - beta(S-S0)) */
+  double f;                 /* f-plane Coriolis parameter */
+  double g, alpha, beta, t_ref, s_ref;
+  double nu, kappa;         /* constant viscosity, diffusivity */
+  double top_flux[OC_MAX_TRACERS]; /* upward tracer flux through the top wall */
+} oc_model_desc;
+
+typedef struct oc_grid oc_grid;
+typedef struct oc_model oc_model;
+
+/* Per-thread message of the last failing call ("" if none). */
+const char* oc_last_error(void);
+
+/* Validate `d` and create a grid handle (host memory only).  Supported
+ * lengths in x, y, z: 8, 16, 32, 64, 96, 128, 256; ny even.
+ * Errors: OC_ERR_ARG, OC_ERR_UNSUPPORTED. */
+int oc_grid_create(const oc_grid_desc* d, oc_grid** out);
+int oc_grid_destroy(oc_grid* g);
+
+/* Bytes of device workspace a model needs (state x2, tendencies, spectrum,
+ * pressure, tables, reduction scratch). */
+int oc_model_workspace_size(const oc_grid* g, const oc_model_desc* m, uint64_t* bytes);
+
+/* Create a model on the current HIP device.  `workspace` is a device pointer
+ * (256-byte aligned) of at least oc_model_workspace_size() bytes, borrowed
+ * for the model's lifetime.  Uploads small tables synchronously and zeroes
+ * the state.  Errors: OC_ERR_ARG, OC_ERR_UNSUPPORTED, OC_ERR_DEVICE. */
+int oc_model_create(const oc_grid* g, const oc_model_desc* m, void* workspace,
+                    uint64_t workspace_bytes, oc_model** out);
+int oc_model_destroy(oc_model* m);
+
+/* Copy interior values of `field` in (set) or out (get).  `buf` holds
+ * shape[0] x shape[1] x shape[2] = (nz_f, ny, nx) elements, x fastest, of
+ * type `dtype` (OC_F32 / OC_F64), in device memory if on_device else host
+ * memory; nz_f = nz + 1 for w with walls, nz otherwise.  Values are
+ * converted to the model precision; oc_set_state then refills the halos
+ * (and sets w = 0 on walls).  Host copies synchronise the stream.  The
+ * state refers to the current time level (after the last completed step). */
+int oc_set_state(oc_model* m, int32_t field, const void* buf, int32_t dtype,
+                 int32_t on_device, const int64_t shape[3], void* stream);
+int oc_get_state(oc_model* m, int32_t field, void* buf, int32_t dtype,
+                 int32_t on_device, const int64_t shape[3], void* stream);
+
+/* Tendencies G of all prognostic fields from the current state, excluding
+ * the nonhydrostatic pressure gradient (momentum-tendency-definition
+ * equation); read them with oc_get_tendency (same layout as oc_get_state;
+ * wall faces of G_w are 0). */
+int oc_tendencies(oc_model* m, void* stream);
+int oc_get_tendency(oc_model* m, int32_t field, void* buf, int32_t dtype,
+                    int32_t on_device, const int64_t shape[3], void* stream);
+
+/* Pressure correction of the current velocity as a predictor:
+ * rhs = div(u)/dt_eff, solve lap p = rhs (mean-zero p), u -= dt_eff grad p
+ * at interior faces, halos refilled.  p is kept in FP64 (oc_get_pressure,
+ * shape (nz, ny, nx), dtype OC_F64).  Errors: OC_ERR_ARG if dt_eff <= 0. */
+int oc_pressure_solve(oc_model* m, double dt_eff, void* stream);
+int oc_get_pressure(oc_model* m, double* buf, int32_t on_device, void* stream);
+
+/* Advance nsteps full RK3 steps of size dt: per substage m the fused
+ * tendency + RK3 combine X~ = X + dt(gamma_m G^m - zeta_m G^{m-1}),
+ * then the pressure correction with dt_eff = (gamma_m - zeta_m) dt. */
+int oc_rk3_step(oc_model* m, double dt, int32_t nsteps, void* stream);
+
+/* Per-kernel-class timing with HIP events recorded on the model's stream
+ * around every launch (classes: OC_PROF_*).  oc_profile(m, 1) clears the
+ * counters and starts recording, oc_profile(m, 0) stops.  oc_profile_read
+ * synchronises on the recorded events and writes OC_NPROF totals: ms (host
+ * double array) and launches (host int64 array). */
+enum {
+  OC_PROF_TENDENCY = 0, OC_PROF_FFT_X_FWD = 1, OC_PROF_FFT_Y_FWD = 2, OC_PROF_Z_SOLVE = 3,
+  OC_PROF_FFT_Y_INV = 4, OC_PROF_FFT_X_INV = 5, OC_PROF_PROJECT = 6, OC_PROF_HALO = 7
+};
+#define OC_NPROF 8
+int oc_profile(oc_model* m, int32_t enable);
+int oc_profile_read(oc_model* m, double* ms, int64_t* launches);
+
+/* FP64 diagnostics of the current state, synchronous; out (host) receives
+ * OC_NDIAG doubles: [0] max|div u| * min(spacing), [1] max|u|, [2] max|v|,
+ * [3] max|w|, [4..7] volume integral of tracers 0..3 (0 if absent).
+ * Returns OC_ERR_NONFINITE if any state value is NaN/Inf. */
+int oc_diagnostics(oc_model* m, double* out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OC_H */

@@ -1,0 +1,644 @@
+// C ABI of liboc (declared in include/oc.h): argument validation, workspace
+// carving, FFT tables, and the orchestration of the RK3 / pressure-correction
+// step on a caller-provided HIP stream.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "oc_internal.h"
+
+namespace oc {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+
+// RK3 coefficients (rk3 equation): gamma = (8/15, 5/12, 3/4),
+// zeta = (0, 17/60, 5/12).
+static const double RK_GAMMA[3] = {8.0 / 15.0, 5.0 / 12.0, 3.0 / 4.0};
+static const double RK_ZETA[3] = {0.0, 17.0 / 60.0, 5.0 / 12.0};
+
+static const int DIAG_BLOCKS = 1024;
+static const int DIAG_PARTS = 9;
+
+}  // namespace oc
+
+using namespace oc;
+
+struct oc_grid {
+  oc_grid_desc d;
+};
+
+struct oc_model {
+  oc_grid_desc gd;
+  oc_model_desc md;
+  Dims dims;
+  int nf;
+  int esz;
+  int kinds[MAXF];
+  char* ws;
+  uint64_t ws_bytes;
+  void* state[2][MAXF];
+  void* G[MAXF];
+  int cur;
+  SpecBufs sb;
+  double offset[MAXF];  // storage offset per field: stored = value - offset
+  void* staging;
+  double* diag_part;
+  double dx, dy, dz;
+  // per-kernel-class event timing
+  int prof_on;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used;
+  std::vector<int> prof_cls;  // class of each recorded (start, stop) pair
+};
+
+namespace {
+
+#define OC_CHECK_HIP(expr)                                                       \
+  do {                                                                           \
+    hipError_t e_ = (expr);                                                      \
+    if (e_ != hipSuccess) {                                                      \
+      set_error("%s failed: %s", #expr, hipGetErrorString(e_));                  \
+      return OC_ERR_DEVICE;                                                      \
+    }                                                                            \
+  } while (0)
+
+struct Layout {
+  uint64_t state[2][MAXF], G[MAXF];
+  uint64_t spec, p, twx, twy, twz, dctz, lamx, lamy, lamz, staging, diag;
+  uint64_t total;
+};
+
+uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
+
+Layout make_layout(const oc_grid_desc& g, const oc_model_desc& m) {
+  Layout L;
+  Dims d = make_dims(g.nx, g.ny, g.nz, g.topology_z == OC_BOUNDED);
+  const int nf = 3 + m.ntracers;
+  const uint64_t esz = (m.precision == OC_FP64) ? 8 : 4;
+  const uint64_t fb = align256((uint64_t)padded_elems(d) * esz);
+  uint64_t off = 0;
+  for (int s = 0; s < 2; ++s)
+    for (int q = 0; q < MAXF; ++q) {
+      L.state[s][q] = off;
+      if (q < nf) off += fb;
+    }
+  for (int q = 0; q < MAXF; ++q) {
+    L.G[q] = off;
+    if (q < nf) off += fb;
+  }
+  const uint64_t nxh = g.nx / 2 + 1;
+  L.spec = off; off += align256((uint64_t)g.nz * g.ny * nxh * 16);
+  L.p = off; off += align256((uint64_t)g.nz * g.ny * g.nx * 8);
+  L.twx = off; off += align256((uint64_t)g.nx * 16);
+  L.twy = off; off += align256((uint64_t)g.ny * 16);
+  L.twz = off; off += align256((uint64_t)g.nz * 16);
+  L.dctz = off; off += align256((uint64_t)g.nz * 16);
+  L.lamx = off; off += align256((uint64_t)g.nx * 8);
+  L.lamy = off; off += align256((uint64_t)g.ny * 8);
+  L.lamz = off; off += align256((uint64_t)g.nz * 8);
+  L.staging = off; off += align256((uint64_t)(g.nz + 1) * g.ny * g.nx * 8);
+  L.diag = off; off += align256((uint64_t)DIAG_BLOCKS * DIAG_PARTS * 8);
+  L.total = off;
+  return L;
+}
+
+int validate_grid(const oc_grid_desc* d) {
+  if (!d) { set_error("grid descriptor is NULL"); return OC_ERR_ARG; }
+  if (!fft_length_supported(d->nx) || !fft_length_supported(d->ny) ||
+      !fft_length_supported(d->nz)) {
+    set_error("unsupported grid size %d x %d x %d (each of 8,16,32,64,96,128,256)", d->nx,
+              d->ny, d->nz);
+    return OC_ERR_UNSUPPORTED;
+  }
+  if (d->topology_z != OC_PERIODIC && d->topology_z != OC_BOUNDED) {
+    set_error("topology_z must be OC_PERIODIC or OC_BOUNDED");
+    return OC_ERR_ARG;
+  }
+  if (!(d->lx > 0) || !(d->ly > 0) || !(d->lz > 0) || !std::isfinite(d->lx) ||
+      !std::isfinite(d->ly) || !std::isfinite(d->lz)) {
+    set_error("domain extents must be positive and finite");
+    return OC_ERR_ARG;
+  }
+  return OC_OK;
+}
+
+int validate_model(const oc_model_desc* m) {
+  if (!m) { set_error("model descriptor is NULL"); return OC_ERR_ARG; }
+  if (m->precision != OC_FP64 && m->precision != OC_FP32_MIXED) {
+    set_error("precision must be OC_FP64 or OC_FP32_MIXED");
+    return OC_ERR_ARG;
+  }
+  if (m->advection < OC_ADV_NONE || m->advection > OC_ADV_WENO5_LINEAR) {
+    set_error("unknown advection scheme %d", m->advection);
+    return OC_ERR_ARG;
+  }
+  if (m->advection == OC_ADV_WENO5Z && (!(m->weno_eps > 0) || m->weno_q != 2)) {
+    set_error("WENO-Z needs weno_eps > 0 and weno_q == 2");
+    return OC_ERR_UNSUPPORTED;
+  }
+  if (m->ntracers < 1 || m->ntracers > OC_MAX_TRACERS) {
+    set_error("ntracers must be in 1..%d", OC_MAX_TRACERS);
+    return OC_ERR_ARG;
+  }
+  if (m->buoyancy && m->ntracers < 2) {
+    set_error("buoyancy needs tracers 0 and 1 (T and S)");
+    return OC_ERR_ARG;
+  }
+  if (!(m->nu >= 0) || !(m->kappa >= 0)) {
+    set_error("nu and kappa must be >= 0");
+    return OC_ERR_ARG;
+  }
+  return OC_OK;
+}
+
+int nzf_of(const oc_model* m, int field) {
+  return (field == OC_W && m->dims.zb) ? m->dims.nz + 1 : m->dims.nz;
+}
+
+int check_field_io(const oc_model* m, int field, const void* buf, int dtype,
+                   const int64_t shape[3]) {
+  if (!m || !buf || !shape) { set_error("NULL argument"); return OC_ERR_ARG; }
+  if (field < 0 || field >= m->nf) {
+    set_error("field %d out of range (model has %d fields)", field, m->nf);
+    return OC_ERR_ARG;
+  }
+  if (dtype != OC_F32 && dtype != OC_F64) { set_error("dtype must be OC_F32 or OC_F64"); return OC_ERR_DTYPE; }
+  if (shape[0] != nzf_of(m, field) || shape[1] != m->dims.ny || shape[2] != m->dims.nx) {
+    set_error("shape (%lld, %lld, %lld) does not match (%d, %d, %d)", (long long)shape[0],
+              (long long)shape[1], (long long)shape[2], nzf_of(m, field), m->dims.ny,
+              m->dims.nx);
+    return OC_ERR_SHAPE;
+  }
+  return OC_OK;
+}
+
+// Event pair around a launch group when profiling is on.
+struct ProfScope {
+  oc_model* m;
+  hipStream_t s;
+  bool on;
+  ProfScope(oc_model* m_, int cls, hipStream_t s_) : m(m_), s(s_), on(m_->prof_on != 0) {
+    if (!on) return;
+    while (m->ev_pool.size() < m->ev_used + 2) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) { on = false; return; }
+      m->ev_pool.push_back(e);
+    }
+    m->prof_cls.push_back(cls);
+    (void)hipEventRecord(m->ev_pool[m->ev_used], s);
+  }
+  ~ProfScope() {
+    if (!on) return;
+    (void)hipEventRecord(m->ev_pool[m->ev_used + 1], s);
+    m->ev_used += 2;
+  }
+};
+
+template <class T>
+int halo_all(oc_model* m, int which, hipStream_t s) {
+  ProfScope ps(m, OC_PROF_HALO, s);
+  T* f[MAXF];
+  for (int q = 0; q < m->nf; ++q) f[q] = (T*)m->state[which][q];
+  OC_CHECK_HIP(launch_halo_fill<T>(m->dims, f, m->kinds, m->nf, s));
+  return OC_OK;
+}
+
+template <class T>
+int halo_one(oc_model* m, int which, int field, hipStream_t s) {
+  T* f[1] = {(T*)m->state[which][field]};
+  int kind[1] = {m->kinds[field]};
+  OC_CHECK_HIP(launch_halo_fill<T>(m->dims, f, kind, 1, s));
+  return OC_OK;
+}
+
+template <class T>
+int halo_velocity(oc_model* m, int which, hipStream_t s) {
+  T* f[3];
+  for (int q = 0; q < 3; ++q) f[q] = (T*)m->state[which][q];
+  OC_CHECK_HIP(launch_halo_fill<T>(m->dims, f, m->kinds, 3, s));
+  return OC_OK;
+}
+
+template <class T>
+TendParams<T> tend_params(const oc_model* m) {
+  TendParams<T> p;
+  const oc_model_desc& d = m->md;
+  p.rdx = (T)(1.0 / m->dx);
+  p.rdy = (T)(1.0 / m->dy);
+  p.rdz = (T)(1.0 / m->dz);
+  p.nu = (T)d.nu;
+  p.kappa = (T)d.kappa;
+  p.f = (T)d.f;
+  p.g_alpha = (T)(d.g * d.alpha);
+  p.g_beta = (T)(d.g * d.beta);
+  // FP32 storage keeps T and S as anomalies about (t_ref, s_ref)
+  p.t_ref = (T)(d.t_ref - m->offset[OC_TRACER0]);
+  p.s_ref = (T)(d.s_ref - m->offset[OC_TRACER0 + 1]);
+  p.buoyancy = d.buoyancy ? 1 : 0;
+  p.ntr = d.ntracers;
+  for (int q = 0; q < OC_MAX_TRACERS; ++q) {
+    p.top_flux[q] = (T)(m->dims.zb ? d.top_flux[q] : 0.0);
+    p.toff[q] = (T)((OC_TRACER0 + q < m->nf) ? m->offset[OC_TRACER0 + q] : 0.0);
+  }
+  p.eps = (T)d.weno_eps;
+  p.dt = 0;
+  p.gam = 0;
+  p.zet = 0;
+  p.stage = 0;
+  p.combine = 0;
+  return p;
+}
+
+template <class T>
+int tendency_call(oc_model* m, int in, int out, int stage, double dt, int combine,
+                  hipStream_t s) {
+  FieldSet<T> fs;
+  for (int q = 0; q < MAXF; ++q) {
+    fs.in[q] = (q < m->nf) ? (const T*)m->state[in][q] : nullptr;
+    fs.out[q] = (q < m->nf) ? (T*)m->state[out][q] : nullptr;
+    fs.G[q] = (q < m->nf) ? (T*)m->G[q] : nullptr;
+  }
+  TendParams<T> p = tend_params<T>(m);
+  ProfScope ps(m, OC_PROF_TENDENCY, s);
+  p.dt = (T)dt;
+  p.gam = (T)RK_GAMMA[stage];
+  p.zet = (T)RK_ZETA[stage];
+  p.stage = stage;
+  p.combine = combine;
+  OC_CHECK_HIP(launch_tendency<T>(m->dims, fs, p, m->md.advection, s));
+  return OC_OK;
+}
+
+template <class T>
+int pressure_call(oc_model* m, int which, double dt_eff, hipStream_t s) {
+  const T* u = (const T*)m->state[which][0];
+  const T* v = (const T*)m->state[which][1];
+  const T* w = (const T*)m->state[which][2];
+  Spacing sp{1.0 / m->dx, 1.0 / m->dy, 1.0 / m->dz};
+  {
+    ProfScope ps(m, OC_PROF_FFT_X_FWD, s);
+    OC_CHECK_HIP(launch_poisson_x_forward<T>(m->dims, u, v, w, 1.0 / dt_eff, sp, m->sb, s));
+  }
+  {
+    ProfScope ps(m, OC_PROF_FFT_Y_FWD, s);
+    OC_CHECK_HIP(launch_poisson_y(m->dims, m->sb, -1, s));
+  }
+  {
+    ProfScope ps(m, OC_PROF_Z_SOLVE, s);
+    OC_CHECK_HIP(launch_poisson_spectral(m->dims, m->sb, s));
+  }
+  {
+    ProfScope ps(m, OC_PROF_FFT_Y_INV, s);
+    OC_CHECK_HIP(launch_poisson_y(m->dims, m->sb, 1, s));
+  }
+  {
+    ProfScope ps(m, OC_PROF_FFT_X_INV, s);
+    OC_CHECK_HIP(launch_poisson_x_inverse(m->dims, m->sb, s));
+  }
+  {
+    ProfScope ps(m, OC_PROF_PROJECT, s);
+    OC_CHECK_HIP(launch_project<T>(m->dims, (T*)m->state[which][0], (T*)m->state[which][1],
+                                   (T*)m->state[which][2], dt_eff, sp.rdx, sp.rdy, sp.rdz,
+                                   m->sb.p, s));
+  }
+  return OC_OK;
+}
+
+template <class T>
+int rk3_steps(oc_model* m, double dt, int nsteps, hipStream_t s) {
+  for (int n = 0; n < nsteps; ++n) {
+    for (int st = 0; st < 3; ++st) {
+      const int in = m->cur, out = 1 - m->cur;
+      int rc = tendency_call<T>(m, in, out, st, dt, 1, s);
+      if (rc) return rc;
+      rc = pressure_call<T>(m, out, (RK_GAMMA[st] - RK_ZETA[st]) * dt, s);
+      if (rc) return rc;
+      rc = halo_all<T>(m, out, s);
+      if (rc) return rc;
+      m->cur = out;
+    }
+  }
+  return OC_OK;
+}
+
+template <class T>
+int field_io(oc_model* m, void* fieldbuf, int nzf, void* buf, int dtype, int on_device,
+             int to_dense, double offset, hipStream_t s) {
+  const uint64_t bytes = (uint64_t)nzf * m->dims.ny * m->dims.nx * (dtype == OC_F32 ? 4 : 8);
+  if (to_dense) {
+    void* dst = on_device ? buf : m->staging;
+    OC_CHECK_HIP(launch_pack<T>(m->dims, nzf, (const T*)fieldbuf, dst, dtype, 1, offset, s));
+    if (!on_device) {
+      OC_CHECK_HIP(hipMemcpyAsync(buf, m->staging, bytes, hipMemcpyDeviceToHost, s));
+      OC_CHECK_HIP(hipStreamSynchronize(s));
+    }
+  } else {
+    const void* src = buf;
+    if (!on_device) {
+      OC_CHECK_HIP(hipMemcpyAsync(m->staging, buf, bytes, hipMemcpyHostToDevice, s));
+      OC_CHECK_HIP(hipStreamSynchronize(s));
+      src = m->staging;
+    }
+    OC_CHECK_HIP(launch_pack<T>(m->dims, nzf, (const T*)fieldbuf, const_cast<void*>(src), dtype,
+                                0, offset, s));
+  }
+  return OC_OK;
+}
+
+template <class T>
+int diagnostics_call(oc_model* m, double* out, hipStream_t s) {
+  T* f[MAXF];
+  for (int q = 0; q < m->nf; ++q) f[q] = (T*)m->state[m->cur][q];
+  OC_CHECK_HIP(launch_diagnostics<T>(m->dims, f, m->nf, 1.0 / m->dx, 1.0 / m->dy, 1.0 / m->dz,
+                                     m->diag_part, DIAG_BLOCKS, s));
+  std::vector<double> part((size_t)DIAG_BLOCKS * DIAG_PARTS);
+  OC_CHECK_HIP(hipMemcpyAsync(part.data(), m->diag_part, part.size() * 8, hipMemcpyDeviceToHost, s));
+  OC_CHECK_HIP(hipStreamSynchronize(s));
+  double acc[DIAG_PARTS] = {0};
+  for (int b = 0; b < DIAG_BLOCKS; ++b)
+    for (int q = 0; q < DIAG_PARTS; ++q) {
+      double x = part[(size_t)b * DIAG_PARTS + q];
+      acc[q] = (q < 4) ? std::fmax(acc[q], x) : acc[q] + x;
+    }
+  const double vol = m->dx * m->dy * m->dz;
+  out[0] = acc[0] * std::fmin(m->dx, std::fmin(m->dy, m->dz));
+  out[1] = acc[1];
+  out[2] = acc[2];
+  out[3] = acc[3];
+  const double ncell = (double)m->dims.nx * m->dims.ny * m->dims.nz;
+  for (int q = 0; q < 4; ++q) {
+    const double off = (OC_TRACER0 + q < m->nf) ? m->offset[OC_TRACER0 + q] : 0.0;
+    out[4 + q] = (acc[4 + q] + off * ncell) * vol;
+  }
+  if (acc[8] > 0) {
+    set_error("state holds %g non-finite cells", acc[8]);
+    return OC_ERR_NONFINITE;
+  }
+  return OC_OK;
+}
+
+void fill_tables(const oc_grid_desc& g, std::vector<double>& twx, std::vector<double>& twy,
+                 std::vector<double>& twz, std::vector<double>& dctz, std::vector<double>& lamx,
+                 std::vector<double>& lamy, std::vector<double>& lamz, double dx, double dy,
+                 double dz) {
+  const double pi = 3.14159265358979323846;
+  auto tw = [&](std::vector<double>& t, int n) {
+    t.resize(2 * n);
+    for (int m = 0; m < n; ++m) {
+      t[2 * m] = std::cos(2.0 * pi * m / n);
+      t[2 * m + 1] = -std::sin(2.0 * pi * m / n);
+    }
+  };
+  tw(twx, g.nx);
+  tw(twy, g.ny);
+  tw(twz, g.nz);
+  dctz.resize(2 * g.nz);
+  for (int k = 0; k < g.nz; ++k) {
+    dctz[2 * k] = std::cos(pi * k / (2.0 * g.nz));
+    dctz[2 * k + 1] = -std::sin(pi * k / (2.0 * g.nz));
+  }
+  auto lam = [&](std::vector<double>& t, int n, double h, bool neumann) {
+    t.resize(n);
+    for (int k = 0; k < n; ++k) {
+      double s = std::sin(pi * k / (neumann ? 2.0 * n : (double)n));
+      t[k] = -(4.0 / (h * h)) * s * s;
+    }
+  };
+  lam(lamx, g.nx, dx, false);
+  lam(lamy, g.ny, dy, false);
+  lam(lamz, g.nz, dz, g.topology_z == OC_BOUNDED);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* oc_last_error(void) { return g_err; }
+
+int oc_grid_create(const oc_grid_desc* d, oc_grid** out) {
+  if (!out) { set_error("out is NULL"); return OC_ERR_ARG; }
+  int rc = validate_grid(d);
+  if (rc) return rc;
+  if (d->ny % 2) { set_error("ny must be even"); return OC_ERR_UNSUPPORTED; }
+  oc_grid* g = new (std::nothrow) oc_grid;
+  if (!g) { set_error("out of host memory"); return OC_ERR_ARG; }
+  g->d = *d;
+  *out = g;
+  return OC_OK;
+}
+
+int oc_grid_destroy(oc_grid* g) {
+  delete g;
+  return OC_OK;
+}
+
+int oc_model_workspace_size(const oc_grid* g, const oc_model_desc* m, uint64_t* bytes) {
+  if (!g || !bytes) { set_error("NULL argument"); return OC_ERR_ARG; }
+  int rc = validate_model(m);
+  if (rc) return rc;
+  *bytes = make_layout(g->d, *m).total;
+  return OC_OK;
+}
+
+int oc_model_create(const oc_grid* g, const oc_model_desc* md, void* workspace,
+                    uint64_t workspace_bytes, oc_model** out) {
+  if (!g || !out || !workspace) { set_error("NULL argument"); return OC_ERR_ARG; }
+  int rc = validate_model(md);
+  if (rc) return rc;
+  if (((uintptr_t)workspace) % 256) { set_error("workspace must be 256-byte aligned"); return OC_ERR_ARG; }
+  const Layout L = make_layout(g->d, *md);
+  if (workspace_bytes < L.total) {
+    set_error("workspace has %llu bytes, needs %llu", (unsigned long long)workspace_bytes,
+              (unsigned long long)L.total);
+    return OC_ERR_ARG;
+  }
+  hipPointerAttribute_t attr;
+  if (hipPointerGetAttributes(&attr, workspace) != hipSuccess || attr.type != hipMemoryTypeDevice) {
+    (void)hipGetLastError();
+    set_error("workspace is not device memory");
+    return OC_ERR_ARG;
+  }
+  oc_model* m = new (std::nothrow) oc_model;
+  if (!m) { set_error("out of host memory"); return OC_ERR_ARG; }
+  m->gd = g->d;
+  m->md = *md;
+  m->dims = make_dims(g->d.nx, g->d.ny, g->d.nz, g->d.topology_z == OC_BOUNDED);
+  m->nf = 3 + md->ntracers;
+  m->esz = md->precision == OC_FP64 ? 8 : 4;
+  for (int q = 0; q < MAXF; ++q) m->kinds[q] = (q == OC_W) ? 1 : 0;
+  for (int q = 0; q < MAXF; ++q) m->offset[q] = 0.0;
+  if (md->precision == OC_FP32_MIXED && md->buoyancy) {
+    // FP32 resolves ~1e-6 of T ~ 20: store T and S as anomalies about the
+    // equation-of-state reference.  The flux form is unchanged except for
+    // offset * div(u), which vanishes for the projected velocity.
+    m->offset[OC_TRACER0] = md->t_ref;
+    m->offset[OC_TRACER0 + 1] = md->s_ref;
+  }
+  m->ws = (char*)workspace;
+  m->ws_bytes = workspace_bytes;
+  for (int s = 0; s < 2; ++s)
+    for (int q = 0; q < MAXF; ++q) m->state[s][q] = m->ws + L.state[s][q];
+  for (int q = 0; q < MAXF; ++q) m->G[q] = m->ws + L.G[q];
+  m->cur = 0;
+  m->prof_on = 0;
+  m->ev_used = 0;
+  m->dx = g->d.lx / g->d.nx;
+  m->dy = g->d.ly / g->d.ny;
+  m->dz = g->d.lz / g->d.nz;
+  m->sb.spec = (double2*)(m->ws + L.spec);
+  m->sb.p = (double*)(m->ws + L.p);
+  m->sb.twx = (const double2*)(m->ws + L.twx);
+  m->sb.twy = (const double2*)(m->ws + L.twy);
+  m->sb.twz = (const double2*)(m->ws + L.twz);
+  m->sb.dctz = (const double2*)(m->ws + L.dctz);
+  m->sb.lamx = (const double*)(m->ws + L.lamx);
+  m->sb.lamy = (const double*)(m->ws + L.lamy);
+  m->sb.lamz = (const double*)(m->ws + L.lamz);
+  m->sb.nxh = g->d.nx / 2 + 1;
+  m->staging = m->ws + L.staging;
+  m->diag_part = (double*)(m->ws + L.diag);
+
+  std::vector<double> twx, twy, twz, dctz, lamx, lamy, lamz;
+  fill_tables(g->d, twx, twy, twz, dctz, lamx, lamy, lamz, m->dx, m->dy, m->dz);
+  hipError_t e = hipMemset(m->ws, 0, L.total);
+  if (e == hipSuccess) e = hipMemcpy(m->ws + L.twx, twx.data(), twx.size() * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(m->ws + L.twy, twy.data(), twy.size() * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(m->ws + L.twz, twz.data(), twz.size() * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(m->ws + L.dctz, dctz.data(), dctz.size() * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(m->ws + L.lamx, lamx.data(), lamx.size() * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(m->ws + L.lamy, lamy.data(), lamy.size() * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(m->ws + L.lamz, lamz.data(), lamz.size() * 8, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    set_error("model setup failed: %s", hipGetErrorString(e));
+    delete m;
+    return OC_ERR_DEVICE;
+  }
+  *out = m;
+  return OC_OK;
+}
+
+int oc_model_destroy(oc_model* m) {
+  if (m) {
+    for (hipEvent_t e : m->ev_pool) (void)hipEventDestroy(e);
+  }
+  delete m;
+  return OC_OK;
+}
+
+int oc_profile(oc_model* m, int32_t enable) {
+  if (!m) { set_error("model is NULL"); return OC_ERR_ARG; }
+  if (enable) {
+    m->ev_used = 0;
+    m->prof_cls.clear();
+  }
+  m->prof_on = enable ? 1 : 0;
+  return OC_OK;
+}
+
+int oc_profile_read(oc_model* m, double* ms, int64_t* launches) {
+  if (!m || !ms || !launches) { set_error("NULL argument"); return OC_ERR_ARG; }
+  for (int c = 0; c < OC_NPROF; ++c) { ms[c] = 0.0; launches[c] = 0; }
+  if (m->ev_used == 0) return OC_OK;
+  OC_CHECK_HIP(hipEventSynchronize(m->ev_pool[m->ev_used - 1]));
+  for (size_t r = 0; r < m->prof_cls.size(); ++r) {
+    float t = 0.f;
+    OC_CHECK_HIP(hipEventElapsedTime(&t, m->ev_pool[2 * r], m->ev_pool[2 * r + 1]));
+    ms[m->prof_cls[r]] += t;
+    launches[m->prof_cls[r]] += 1;
+  }
+  return OC_OK;
+}
+
+int oc_set_state(oc_model* m, int32_t field, const void* buf, int32_t dtype, int32_t on_device,
+                 const int64_t shape[3], void* stream) {
+  int rc = check_field_io(m, field, buf, dtype, shape);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  void* fb = m->state[m->cur][field];
+  const int nzf = nzf_of(m, field);
+  const double off = m->offset[field];
+  if (m->esz == 8) rc = field_io<double>(m, fb, nzf, const_cast<void*>(buf), dtype, on_device, 0, off, s);
+  else rc = field_io<float>(m, fb, nzf, const_cast<void*>(buf), dtype, on_device, 0, off, s);
+  if (rc) return rc;
+  if (field == OC_W && m->dims.zb) {
+    // the bottom wall face carries no flow
+    OC_CHECK_HIP(hipMemsetAsync((char*)fb + (size_t)H * m->dims.sz * m->esz, 0,
+                                (size_t)m->dims.sz * m->esz, s));
+  }
+  return (m->esz == 8) ? halo_one<double>(m, m->cur, field, s) : halo_one<float>(m, m->cur, field, s);
+}
+
+int oc_get_state(oc_model* m, int32_t field, void* buf, int32_t dtype, int32_t on_device,
+                 const int64_t shape[3], void* stream) {
+  int rc = check_field_io(m, field, buf, dtype, shape);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  void* fb = m->state[m->cur][field];
+  const int nzf = nzf_of(m, field);
+  const double off = m->offset[field];
+  return (m->esz == 8) ? field_io<double>(m, fb, nzf, buf, dtype, on_device, 1, off, s)
+                       : field_io<float>(m, fb, nzf, buf, dtype, on_device, 1, off, s);
+}
+
+int oc_tendencies(oc_model* m, void* stream) {
+  if (!m) { set_error("model is NULL"); return OC_ERR_ARG; }
+  hipStream_t s = (hipStream_t)stream;
+  return (m->esz == 8) ? tendency_call<double>(m, m->cur, m->cur, 0, 0.0, 0, s)
+                       : tendency_call<float>(m, m->cur, m->cur, 0, 0.0, 0, s);
+}
+
+int oc_get_tendency(oc_model* m, int32_t field, void* buf, int32_t dtype, int32_t on_device,
+                    const int64_t shape[3], void* stream) {
+  int rc = check_field_io(m, field, buf, dtype, shape);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const int nzf = nzf_of(m, field);
+  return (m->esz == 8) ? field_io<double>(m, m->G[field], nzf, buf, dtype, on_device, 1, 0.0, s)
+                       : field_io<float>(m, m->G[field], nzf, buf, dtype, on_device, 1, 0.0, s);
+}
+
+int oc_pressure_solve(oc_model* m, double dt_eff, void* stream) {
+  if (!m) { set_error("model is NULL"); return OC_ERR_ARG; }
+  if (!(dt_eff > 0) || !std::isfinite(dt_eff)) { set_error("dt_eff must be positive"); return OC_ERR_ARG; }
+  hipStream_t s = (hipStream_t)stream;
+  int rc = (m->esz == 8) ? pressure_call<double>(m, m->cur, dt_eff, s)
+                         : pressure_call<float>(m, m->cur, dt_eff, s);
+  if (rc) return rc;
+  return (m->esz == 8) ? halo_velocity<double>(m, m->cur, s) : halo_velocity<float>(m, m->cur, s);
+}
+
+int oc_get_pressure(oc_model* m, double* buf, int32_t on_device, void* stream) {
+  if (!m || !buf) { set_error("NULL argument"); return OC_ERR_ARG; }
+  hipStream_t s = (hipStream_t)stream;
+  const size_t bytes = (size_t)m->dims.nz * m->dims.ny * m->dims.nx * 8;
+  OC_CHECK_HIP(hipMemcpyAsync(buf, m->sb.p, bytes,
+                              on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+  if (!on_device) OC_CHECK_HIP(hipStreamSynchronize(s));
+  return OC_OK;
+}
+
+int oc_rk3_step(oc_model* m, double dt, int32_t nsteps, void* stream) {
+  if (!m) { set_error("model is NULL"); return OC_ERR_ARG; }
+  if (!(dt > 0) || !std::isfinite(dt)) { set_error("dt must be positive"); return OC_ERR_ARG; }
+  if (nsteps < 0) { set_error("nsteps must be >= 0"); return OC_ERR_ARG; }
+  hipStream_t s = (hipStream_t)stream;
+  return (m->esz == 8) ? rk3_steps<double>(m, dt, nsteps, s) : rk3_steps<float>(m, dt, nsteps, s);
+}
+
+int oc_diagnostics(oc_model* m, double* out, void* stream) {
+  if (!m || !out) { set_error("NULL argument"); return OC_ERR_ARG; }
+  hipStream_t s = (hipStream_t)stream;
+  return (m->esz == 8) ? diagnostics_call<double>(m, out, s) : diagnostics_call<float>(m, out, s);
+}
+
+}  // extern "C"

@@ -1,0 +1,104 @@
+// Internal definitions shared by the HIP translation units of liboc.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "oc.h"
+
+namespace oc {
+
+constexpr int H = 3;            // halo width: the WENO5 stencil reaches 3 cells
+constexpr int MAXF = 3 + OC_MAX_TRACERS;
+
+// Halo-padded layout: (nz + 2H) x (ny + 2H) x (nx + 2H), x fastest.
+struct Dims {
+  int nx, ny, nz;
+  int px, py, pz;
+  long sy, sz;     // strides of j and k in elements (x stride is 1)
+  int zb;          // 1 if z is bounded by walls
+};
+
+__host__ __device__ inline long pidx(const Dims& d, int i, int j, int k) {
+  return (long)(k + H) * d.sz + (long)(j + H) * d.sy + (long)(i + H);
+}
+
+inline Dims make_dims(int nx, int ny, int nz, int zb) {
+  Dims d;
+  d.nx = nx; d.ny = ny; d.nz = nz;
+  d.px = nx + 2 * H; d.py = ny + 2 * H; d.pz = nz + 2 * H;
+  d.sy = d.px; d.sz = (long)d.px * d.py;
+  d.zb = zb;
+  return d;
+}
+
+inline long padded_elems(const Dims& d) { return (long)d.px * d.py * d.pz; }
+
+// Physics and RK3 coefficients handed to the tendency kernel.
+template <class T>
+struct TendParams {
+  T rdx, rdy, rdz;           // inverse spacings
+  T nu, kappa;
+  T f;
+  T g_alpha, g_beta, t_ref, s_ref;
+  int buoyancy;
+  int ntr;                   // number of tracers
+  T top_flux[OC_MAX_TRACERS];
+  T toff[OC_MAX_TRACERS];    // tracer storage offsets (stored = value - toff)
+  T eps;                     // WENO-Z regulariser
+  T dt, gam, zet;            // RK3 substage coefficients (dt * ...)
+  int stage;                 // 0, 1, 2
+  int combine;               // 1: write X~ = X + dt(gam G - zet Gprev); 0: only G
+};
+
+template <class T>
+struct FieldSet {
+  const T* in[MAXF];
+  T* out[MAXF];
+  T* G[MAXF];
+};
+
+// Spectral-solve tables and buffers (FP64).
+struct SpecBufs {
+  double2* spec;             // (nz, ny, nxh) half spectrum, kx fastest
+  double* p;                 // (nz, ny, nx) pressure
+  const double2* twx;        // exp(-2 pi i m / nx), m < nx
+  const double2* twy;
+  const double2* twz;
+  const double2* dctz;       // exp(-i pi k / (2 nz)), k < nz (bounded z only)
+  const double* lamx;        // eigenvalues of delta_x^2 / dx^2, k < nx
+  const double* lamy;
+  const double* lamz;
+  int nxh;
+};
+
+// Host-side error reporting (per thread).
+void set_error(const char* fmt, ...);
+
+// Kernel launchers (defined in the .hip translation units).
+template <class T>
+hipError_t launch_halo_fill(const Dims& d, T* const* fields, const int* kinds, int nf,
+                            hipStream_t s);
+template <class T>
+hipError_t launch_tendency(const Dims& d, const FieldSet<T>& fs, const TendParams<T>& p,
+                           int scheme, hipStream_t s);
+struct Spacing { double rdx, rdy, rdz; };
+template <class T>
+hipError_t launch_poisson_x_forward(const Dims& d, const T* u, const T* v, const T* w,
+                                   double inv_dt, Spacing sp, const SpecBufs& sb, hipStream_t s);
+hipError_t launch_poisson_y(const Dims& d, const SpecBufs& sb, int dir, hipStream_t s);
+hipError_t launch_poisson_spectral(const Dims& d, const SpecBufs& sb, hipStream_t s);
+hipError_t launch_poisson_x_inverse(const Dims& d, const SpecBufs& sb, hipStream_t s);
+template <class T>
+hipError_t launch_project(const Dims& d, T* u, T* v, T* w, double scale, double rdx,
+                          double rdy, double rdz, const double* p, hipStream_t s);
+template <class T>
+hipError_t launch_pack(const Dims& d, int nzf, const T* padded, void* dense, int dtype,
+                       int to_dense, double offset, hipStream_t s);
+template <class T>
+hipError_t launch_diagnostics(const Dims& d, T* const* fields, int nf, double rdx, double rdy,
+                              double rdz, double* scratch, int nblocks, hipStream_t s);
+
+bool fft_length_supported(int n);
+
+}  // namespace oc

@@ -1,0 +1,441 @@
+// FFT/DCT eigenfunction solve of the discrete pressure Poisson equation and
+// the projection of the predictor velocity (pressure-correction appendix of
+// arXiv 2502.14148: lap p = div(u~)/dt, u = u~ - dt grad p; the 7-point
+// Laplacian is diagonalised by Fourier modes in periodic directions and by
+// cosine modes (DCT-II) between no-normal-flow walls).
+//
+// Five passes over a half spectrum held in FP64, kx fastest:
+//   1. x: divergence of the predictor (fused) and a real-to-complex FFT
+//      (two real lines packed into one complex line);
+//   2. y: complex FFT;
+//   3. z: DCT-II (Makhoul's N-point FFT reordering) or FFT, division by the
+//      eigenvalue, and the inverse transform, all in LDS;
+//   4. y: inverse FFT;
+//   5. x: complex-to-real inverse FFT -> p.
+// Then a projection kernel applies u -= dt_eff grad p.
+//
+// Transforms are radix-4/2/3 Stockham passes in LDS, one radix-R butterfly
+// per thread per pass, twiddles from FP64 tables.
+#include "oc_internal.h"
+
+namespace oc {
+
+__device__ inline double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ inline double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ inline double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+__device__ inline double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+// multiply by +i (SIGN = +1) or -i (SIGN = -1)
+template <int SIGN>
+__device__ inline double2 mul_i(double2 a) {
+  return SIGN > 0 ? make_double2(-a.y, a.x) : make_double2(a.y, -a.x);
+}
+
+// In-register DFT of length R; DIR = -1 forward (exp(-2 pi i/R)), +1 inverse.
+template <int R, int DIR>
+__device__ inline void dft(double2* v) {
+  if (R == 2) {
+    double2 a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+  } else if (R == 4) {
+    double2 a = cadd(v[0], v[2]), b = csub(v[0], v[2]);
+    double2 c = cadd(v[1], v[3]), d = csub(v[1], v[3]);
+    v[0] = cadd(a, c);
+    v[2] = csub(a, c);
+    v[1] = cadd(b, mul_i<DIR>(d));
+    v[3] = csub(b, mul_i<DIR>(d));
+  } else {  // R == 3
+    const double h = 0.86602540378443864676;  // sqrt(3)/2
+    double2 t = cadd(v[1], v[2]), s = csub(v[1], v[2]);
+    double2 m = csub(v[0], cscale(t, 0.5));
+    double2 r = cscale(mul_i<DIR>(s), h);
+    v[0] = cadd(v[0], t);
+    v[1] = cadd(m, r);
+    v[2] = csub(m, r);
+  }
+}
+
+// One Stockham pass of radix R over L lines of length N held in LDS at
+// buf[line * ls + n * es].  NS is the length of the sub-transforms already
+// done.  LINE_FAST maps consecutive threads to consecutive lines (used when
+// lines are interleaved, es = L) to avoid LDS bank conflicts.
+template <int N, int R, int NS, int L, int NT, int DIR, bool LINE_FAST>
+__device__ inline void stockham_pass(double2* buf, int ls, int es, const double2* __restrict__ tw) {
+  constexpr int M = N / R;
+  constexpr int NB = L * M;
+  constexpr int BPT = (NB + NT - 1) / NT;
+  double2 v[BPT][R];
+  int line_[BPT], jj_[BPT];
+#pragma unroll
+  for (int q = 0; q < BPT; ++q) {
+    const int b = threadIdx.x + q * NT;
+    line_[q] = LINE_FAST ? (b % L) : (b / M);
+    jj_[q] = LINE_FAST ? (b / L) : (b % M);
+    if (NB % NT == 0 || b < NB) {
+      const int k = jj_[q] % NS;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        double2 x = buf[line_[q] * ls + (jj_[q] + r * M) * es];
+        if (r > 0 && NS > 1) {
+          double2 w = tw[(r * k) * (N / (NS * R))];
+          if (DIR > 0) w = cconj(w);
+          x = cmul(x, w);
+        }
+        v[q][r] = x;
+      }
+      dft<R, DIR>(v[q]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < BPT; ++q) {
+    const int b = threadIdx.x + q * NT;
+    if (NB % NT == 0 || b < NB) {
+      const int k = jj_[q] % NS;
+      const int d = (jj_[q] / NS) * NS * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[line_[q] * ls + (d + r * NS) * es] = v[q][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <int N, int NS, int L, int NT, int DIR, bool LINE_FAST>
+__device__ inline void fft_lines(double2* buf, int ls, int es, const double2* __restrict__ tw) {
+  if constexpr (NS < N) {
+    constexpr int REM = N / NS;
+    constexpr int R = (REM % 4 == 0) ? 4 : ((REM % 2 == 0) ? 2 : 3);
+    stockham_pass<N, R, NS, L, NT, DIR, LINE_FAST>(buf, ls, es, tw);
+    fft_lines<N, NS * R, L, NT, DIR, LINE_FAST>(buf, ls, es, tw);
+  }
+}
+
+constexpr int NT = 256;
+template <int N> struct XCfg { static constexpr int LP = (N >= 1024) ? 1 : 1024 / N; };
+template <int N> struct YZCfg { static constexpr int W = (N >= 512) ? 4 : (N >= 256 ? 8 : 16); };
+
+// ---------------------------------------------------------------------------
+// Pass 1: rhs = div(u~) * inv_dt on line pairs (j, j+1), packed FFT along x.
+// ---------------------------------------------------------------------------
+template <class T, int N>
+__global__ void __launch_bounds__(NT) fwd_x_kernel(Dims d, const T* __restrict__ u,
+                                                   const T* __restrict__ v,
+                                                   const T* __restrict__ w, double inv_dt,
+                                                   double rdx, double rdy, double rdz,
+                                                   SpecBufs sb) {
+  constexpr int LP = XCfg<N>::LP;
+  __shared__ double2 buf[LP * N];
+  const int k = blockIdx.y;
+  const int npairs = d.ny / 2;
+  const int pair0 = blockIdx.x * LP;
+  for (int t = threadIdx.x; t < LP * N; t += NT) {
+    const int l = t / N, i = t % N;
+    const int pr = pair0 + l;
+    double2 z = make_double2(0.0, 0.0);
+    if (pr < npairs) {
+      double dv[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int j = 2 * pr + h;
+        const long c = pidx(d, i, j, k);
+        const int ip = (i + 1 == d.nx) ? 0 : i + 1;
+        const int jp = (j + 1 == d.ny) ? 0 : j + 1;
+        double wb = (double)w[c];
+        double wt;
+        if (d.zb) {
+          if (k == 0) wb = 0.0;
+          wt = (k + 1 == d.nz) ? 0.0 : (double)w[c + d.sz];
+        } else {
+          wt = (double)w[pidx(d, i, j, (k + 1 == d.nz) ? 0 : k + 1)];
+        }
+        dv[h] = (((double)u[pidx(d, ip, j, k)] - (double)u[c]) * rdx +
+                 ((double)v[pidx(d, i, jp, k)] - (double)v[c]) * rdy + (wt - wb) * rdz) * inv_dt;
+      }
+      z = make_double2(dv[0], dv[1]);
+    }
+    buf[t] = z;
+  }
+  __syncthreads();
+  fft_lines<N, 1, LP, NT, -1, false>(buf, N, 1, sb.twx);
+  // unpack the two real spectra: X1 = (Z_k + conj Z_{N-k})/2, X2 = -i (Z_k - conj Z_{N-k})/2
+  const int nxh = sb.nxh;
+  for (int t = threadIdx.x; t < LP * nxh; t += NT) {
+    const int l = t / nxh, kx = t % nxh;
+    const int pr = pair0 + l;
+    if (pr >= npairs) continue;
+    double2 a = buf[l * N + kx];
+    double2 b = cconj(buf[l * N + ((N - kx) % N)]);
+    double2 x1 = cscale(cadd(a, b), 0.5);
+    double2 x2 = cscale(mul_i<-1>(csub(a, b)), 0.5);
+    const long base = ((long)k * d.ny + 2 * pr) * nxh + kx;
+    sb.spec[base] = x1;
+    sb.spec[base + nxh] = x2;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Passes 2 and 4: complex FFT along y for W consecutive kx columns.
+// ---------------------------------------------------------------------------
+template <int N, int DIR>
+__global__ void __launch_bounds__(NT) y_kernel(Dims d, SpecBufs sb) {
+  constexpr int W = YZCfg<N>::W;
+  __shared__ double2 buf[W * N];
+  const int k = blockIdx.y;
+  const int kx0 = blockIdx.x * W;
+  const int nxh = sb.nxh;
+  for (int t = threadIdx.x; t < W * N; t += NT) {
+    const int c = t % W, y = t / W;
+    buf[t] = (kx0 + c < nxh) ? sb.spec[((long)k * d.ny + y) * nxh + kx0 + c]
+                             : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  fft_lines<N, 1, W, NT, DIR, true>(buf, 1, W, sb.twy);
+  for (int t = threadIdx.x; t < W * N; t += NT) {
+    const int c = t % W, y = t / W;
+    if (kx0 + c < nxh) sb.spec[((long)k * d.ny + y) * nxh + kx0 + c] = buf[t];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Pass 3: along z, forward transform, division by the eigenvalue (with the
+// 1/(nx ny nz) normalisation of the unnormalised inverses), inverse.
+// ---------------------------------------------------------------------------
+__device__ inline int makhoul_pos(int m, int n) {
+  // DCT-II via an N-point FFT: v[n'] = x[2n'], v[N-1-n'] = x[2n'+1]
+  return (m & 1) ? (n - 1 - (m >> 1)) : (m >> 1);
+}
+
+template <int N, bool BOUNDED>
+__global__ void __launch_bounds__(NT) z_kernel(Dims d, SpecBufs sb, double norm) {
+  constexpr int W = YZCfg<N>::W;
+  constexpr int PER = (W * N + NT - 1) / NT;
+  __shared__ double2 buf[W * N];
+  const int j = blockIdx.y;
+  const int kx0 = blockIdx.x * W;
+  const int nxh = sb.nxh;
+  const long zs = (long)d.ny * nxh;
+  for (int t = threadIdx.x; t < W * N; t += NT) {
+    const int c = t % W, z = t / W;
+    const int pos = BOUNDED ? makhoul_pos(z, N) : z;
+    buf[pos * W + c] = (kx0 + c < nxh) ? sb.spec[(long)z * zs + (long)j * nxh + kx0 + c]
+                                       : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  fft_lines<N, 1, W, NT, -1, true>(buf, 1, W, sb.twz);
+  // spectral division
+  double2 val[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int t = threadIdx.x + q * NT;
+    if (t >= W * N) continue;
+    const int c = t % W, kz = t / W;
+    double2 x = buf[t];
+    if (BOUNDED) {
+      // X_k = (e^{-i pi k/2N} V_k + e^{i pi k/2N} V_{N-k}) / 2
+      double2 e = sb.dctz[kz];
+      double2 vb = buf[((N - kz) % N) * W + c];
+      x = cscale(cadd(cmul(e, x), cmul(cconj(e), vb)), 0.5);
+    }
+    const int kx = kx0 + c;
+    double lam = (kx < nxh ? sb.lamx[kx] : 1.0) + sb.lamy[j] + sb.lamz[kz];
+    val[q] = (lam == 0.0) ? make_double2(0.0, 0.0) : cscale(x, norm / lam);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int t = threadIdx.x + q * NT;
+    if (t < W * N) buf[t] = val[q];
+  }
+  __syncthreads();
+  if (BOUNDED) {
+    // V_k = e^{i pi k/2N} (X_k - i X_{N-k}), X_N = 0
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int t = threadIdx.x + q * NT;
+      if (t >= W * N) continue;
+      const int c = t % W, kz = t / W;
+      double2 xn = (kz == 0) ? make_double2(0.0, 0.0) : buf[(N - kz) * W + c];
+      val[q] = cmul(cconj(sb.dctz[kz]), csub(buf[t], mul_i<1>(xn)));
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int t = threadIdx.x + q * NT;
+      if (t < W * N) buf[t] = val[q];
+    }
+    __syncthreads();
+  }
+  fft_lines<N, 1, W, NT, 1, true>(buf, 1, W, sb.twz);
+  for (int t = threadIdx.x; t < W * N; t += NT) {
+    const int c = t % W, z = t / W;
+    const int pos = BOUNDED ? makhoul_pos(z, N) : z;
+    if (kx0 + c < nxh) sb.spec[(long)z * zs + (long)j * nxh + kx0 + c] = buf[pos * W + c];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Pass 5: complex-to-real inverse FFT along x for line pairs -> p.
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ void __launch_bounds__(NT) inv_x_kernel(Dims d, SpecBufs sb) {
+  constexpr int LP = XCfg<N>::LP;
+  __shared__ double2 buf[LP * N];
+  const int k = blockIdx.y;
+  const int npairs = d.ny / 2;
+  const int pair0 = blockIdx.x * LP;
+  const int nxh = sb.nxh;
+  for (int t = threadIdx.x; t < LP * N; t += NT) {
+    const int l = t / N, n = t % N;
+    const int pr = pair0 + l;
+    double2 z = make_double2(0.0, 0.0);
+    if (pr < npairs) {
+      const long base = ((long)k * d.ny + 2 * pr) * nxh;
+      const bool lo = n <= N / 2;
+      const int m = lo ? n : N - n;
+      double2 x1 = sb.spec[base + m], x2 = sb.spec[base + nxh + m];
+      if (!lo) { x1 = cconj(x1); x2 = cconj(x2); }
+      z = cadd(x1, mul_i<1>(x2));  // Z = X1 + i X2
+    }
+    buf[t] = z;
+  }
+  __syncthreads();
+  fft_lines<N, 1, LP, NT, 1, false>(buf, N, 1, sb.twx);
+  for (int t = threadIdx.x; t < LP * N; t += NT) {
+    const int l = t / N, i = t % N;
+    const int pr = pair0 + l;
+    if (pr >= npairs) continue;
+    const long base = ((long)k * d.ny + 2 * pr) * d.nx + i;
+    sb.p[base] = buf[t].x;
+    sb.p[base + d.nx] = buf[t].y;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Projection u -= scale grad p at interior faces (wall faces of w untouched).
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void __launch_bounds__(256) project_kernel(Dims d, T* __restrict__ u, T* __restrict__ v,
+                                                      T* __restrict__ w, double scale, double rdx,
+                                                      double rdy, double rdz,
+                                                      const double* __restrict__ p) {
+  const long n = (long)d.nx * d.ny * d.nz;
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const int i = (int)(t % d.nx);
+  const int j = (int)((t / d.nx) % d.ny);
+  const int k = (int)(t / ((long)d.nx * d.ny));
+  const long c = pidx(d, i, j, k);
+  const long row = (long)d.nx, plane = (long)d.nx * d.ny;
+  const double pc = p[t];
+  const double pxm = p[t - i + ((i == 0) ? d.nx - 1 : i - 1)];
+  const double pym = p[t - (long)j * row + (long)((j == 0) ? d.ny - 1 : j - 1) * row];
+  u[c] = (T)((double)u[c] - scale * (pc - pxm) * rdx);
+  v[c] = (T)((double)v[c] - scale * (pc - pym) * rdy);
+  if (d.zb) {
+    if (k > 0) w[c] = (T)((double)w[c] - scale * (pc - p[t - plane]) * rdz);
+  } else {
+    const double pzm = p[t - (long)k * plane + (long)((k == 0) ? d.nz - 1 : k - 1) * plane];
+    w[c] = (T)((double)w[c] - scale * (pc - pzm) * rdz);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers: dispatch on the (compile-time) transform lengths.
+// ---------------------------------------------------------------------------
+bool fft_length_supported(int n) {
+  switch (n) {
+    case 8: case 16: case 32: case 64: case 96: case 128: case 256: return true;
+    default: return false;
+  }
+}
+
+#define OC_FFT_DISPATCH(n, MACRO) \
+  switch (n) {                    \
+    case 8: MACRO(8); break;      \
+    case 16: MACRO(16); break;    \
+    case 32: MACRO(32); break;    \
+    case 64: MACRO(64); break;    \
+    case 96: MACRO(96); break;    \
+    case 128: MACRO(128); break;  \
+    case 256: MACRO(256); break;  \
+    default: return hipErrorInvalidValue; \
+  }
+
+template <class T>
+hipError_t launch_poisson_x_forward(const Dims& d, const T* u, const T* v, const T* w,
+                                   double inv_dt, Spacing sp, const SpecBufs& sb, hipStream_t s) {
+#define OC_LAUNCH_FX(N)                                                                    \
+  {                                                                                        \
+    dim3 grid((d.ny / 2 + XCfg<N>::LP - 1) / XCfg<N>::LP, d.nz);                          \
+    hipLaunchKernelGGL((fwd_x_kernel<T, N>), grid, dim3(NT), 0, s, d, u, v, w, inv_dt,    \
+                       sp.rdx, sp.rdy, sp.rdz, sb);                                        \
+  }
+  OC_FFT_DISPATCH(d.nx, OC_LAUNCH_FX)
+#undef OC_LAUNCH_FX
+  return hipGetLastError();
+}
+
+hipError_t launch_poisson_y(const Dims& d, const SpecBufs& sb, int dir, hipStream_t s) {
+#define OC_LAUNCH_Y(N)                                                                     \
+  {                                                                                        \
+    dim3 grid((sb.nxh + YZCfg<N>::W - 1) / YZCfg<N>::W, d.nz);                            \
+    if (dir < 0)                                                                           \
+      hipLaunchKernelGGL((y_kernel<N, -1>), grid, dim3(NT), 0, s, d, sb);                 \
+    else                                                                                   \
+      hipLaunchKernelGGL((y_kernel<N, 1>), grid, dim3(NT), 0, s, d, sb);                  \
+  }
+  OC_FFT_DISPATCH(d.ny, OC_LAUNCH_Y)
+#undef OC_LAUNCH_Y
+  return hipGetLastError();
+}
+
+hipError_t launch_poisson_spectral(const Dims& d, const SpecBufs& sb, hipStream_t s) {
+  const double norm = 1.0 / ((double)d.nx * d.ny * d.nz);
+#define OC_LAUNCH_Z(N)                                                                     \
+  {                                                                                        \
+    dim3 grid((sb.nxh + YZCfg<N>::W - 1) / YZCfg<N>::W, d.ny);                            \
+    if (d.zb)                                                                              \
+      hipLaunchKernelGGL((z_kernel<N, true>), grid, dim3(NT), 0, s, d, sb, norm);         \
+    else                                                                                   \
+      hipLaunchKernelGGL((z_kernel<N, false>), grid, dim3(NT), 0, s, d, sb, norm);        \
+  }
+  OC_FFT_DISPATCH(d.nz, OC_LAUNCH_Z)
+#undef OC_LAUNCH_Z
+  return hipGetLastError();
+}
+
+hipError_t launch_poisson_x_inverse(const Dims& d, const SpecBufs& sb, hipStream_t s) {
+#define OC_LAUNCH_XI(N)                                                                    \
+  {                                                                                        \
+    dim3 grid((d.ny / 2 + XCfg<N>::LP - 1) / XCfg<N>::LP, d.nz);                          \
+    hipLaunchKernelGGL((inv_x_kernel<N>), grid, dim3(NT), 0, s, d, sb);                   \
+  }
+  OC_FFT_DISPATCH(d.nx, OC_LAUNCH_XI)
+#undef OC_LAUNCH_XI
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_project(const Dims& d, T* u, T* v, T* w, double scale, double rdx, double rdy,
+                          double rdz, const double* p, hipStream_t s) {
+  const long n = (long)d.nx * d.ny * d.nz;
+  hipLaunchKernelGGL(project_kernel<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, d, u,
+                     v, w, scale, rdx, rdy, rdz, p);
+  return hipGetLastError();
+}
+
+template hipError_t launch_poisson_x_forward<float>(const Dims&, const float*, const float*,
+                                                    const float*, double, Spacing,
+                                                    const SpecBufs&, hipStream_t);
+template hipError_t launch_poisson_x_forward<double>(const Dims&, const double*, const double*,
+                                                     const double*, double, Spacing,
+                                                     const SpecBufs&, hipStream_t);
+template hipError_t launch_project<float>(const Dims&, float*, float*, float*, double, double,
+                                          double, double, const double*, hipStream_t);
+template hipError_t launch_project<double>(const Dims&, double*, double*, double*, double, double,
+                                           double, double, const double*, hipStream_t);
+
+}  // namespace oc

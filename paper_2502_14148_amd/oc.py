@@ -1,0 +1,230 @@
+"""Thin ctypes binding of liboc.so (the C ABI in include/oc.h).
+
+Argument marshalling only: every step of the model runs in the HIP kernels
+of the library.  Device memory and streams come from PyTorch: the model's
+workspace is a torch uint8 tensor on the GPU and calls are enqueued on the
+current torch stream.  Loading fails loudly if the library is missing.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "liboc.so")
+
+OC_OK = 0
+OC_ERR = {-1: "OC_ERR_ARG", -2: "OC_ERR_SHAPE", -3: "OC_ERR_DTYPE", -4: "OC_ERR_DEVICE",
+          -5: "OC_ERR_UNSUPPORTED", -6: "OC_ERR_NONFINITE"}
+OC_PERIODIC, OC_BOUNDED = 0, 1
+OC_FP64, OC_FP32_MIXED = 0, 1
+ADVECTION = {"none": 0, "weno5z": 1, "weno5_linear": 2}
+OC_F32, OC_F64 = 0, 1
+OC_MAX_TRACERS = 4
+OC_NDIAG = 8
+
+EXPORTS = ("oc_last_error", "oc_grid_create", "oc_grid_destroy", "oc_model_workspace_size",
+           "oc_model_create", "oc_model_destroy", "oc_set_state", "oc_get_state",
+           "oc_tendencies", "oc_get_tendency", "oc_pressure_solve", "oc_get_pressure",
+           "oc_rk3_step", "oc_diagnostics", "oc_profile", "oc_profile_read")
+OC_NPROF = 8
+PROF_CLASSES = ("tendency", "fft_x_fwd", "fft_y_fwd", "z_solve", "fft_y_inv", "fft_x_inv",
+                "project", "halo")
+
+
+class GridDesc(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("topology_z", ctypes.c_int32),
+                ("x0", ctypes.c_double), ("lx", ctypes.c_double),
+                ("y0", ctypes.c_double), ("ly", ctypes.c_double),
+                ("z0", ctypes.c_double), ("lz", ctypes.c_double)]
+
+
+class ModelDesc(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("advection", ctypes.c_int32),
+                ("weno_eps", ctypes.c_double), ("weno_q", ctypes.c_int32),
+                ("ntracers", ctypes.c_int32), ("buoyancy", ctypes.c_int32),
+                ("f", ctypes.c_double), ("g", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("beta", ctypes.c_double), ("t_ref", ctypes.c_double), ("s_ref", ctypes.c_double),
+                ("nu", ctypes.c_double), ("kappa", ctypes.c_double),
+                ("top_flux", ctypes.c_double * OC_MAX_TRACERS)]
+
+
+class OcError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def load_library(path=_LIB_PATH):
+    """Load liboc.so and declare its signatures (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise OcError(f"{path} is missing: build it with `python -m paper_2502_14148_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64p = ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)
+    lib.oc_last_error.restype = ctypes.c_char_p
+    lib.oc_last_error.argtypes = []
+    sig = {
+        "oc_grid_create": [ctypes.POINTER(GridDesc), ctypes.POINTER(vp)],
+        "oc_grid_destroy": [vp],
+        "oc_model_workspace_size": [vp, ctypes.POINTER(ModelDesc), ctypes.POINTER(ctypes.c_uint64)],
+        "oc_model_create": [vp, ctypes.POINTER(ModelDesc), vp, ctypes.c_uint64, ctypes.POINTER(vp)],
+        "oc_model_destroy": [vp],
+        "oc_set_state": [vp, i32, vp, i32, i32, i64p, vp],
+        "oc_get_state": [vp, i32, vp, i32, i32, i64p, vp],
+        "oc_tendencies": [vp, vp],
+        "oc_get_tendency": [vp, i32, vp, i32, i32, i64p, vp],
+        "oc_pressure_solve": [vp, ctypes.c_double, vp],
+        "oc_get_pressure": [vp, vp, i32, vp],
+        "oc_rk3_step": [vp, ctypes.c_double, i32, vp],
+        "oc_diagnostics": [vp, ctypes.POINTER(ctypes.c_double), vp],
+        "oc_profile": [vp, i32],
+        "oc_profile_read": [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc != OC_OK:
+        msg = _lib.oc_last_error().decode()
+        raise OcError(f"{OC_ERR.get(rc, rc)}: {msg}")
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Model:
+    """A nonhydrostatic model on the GPU, configured from a Physics record
+    (see paper_2502_14148_amd.inputs.Physics)."""
+
+    def __init__(self, ph, precision="fp64", device="cuda:0"):
+        import torch
+        lib = load_library()
+        self.ph = ph
+        self.device = torch.device(device)
+        self.precision = precision
+        self.fields = ("u", "v", "w") + tuple(ph.tracers)
+        gd = GridDesc(ph.nx, ph.ny, ph.nz, OC_BOUNDED if ph.z_bounded else OC_PERIODIC,
+                      ph.x0, ph.lx, ph.y0, ph.ly, ph.z0, ph.lz)
+        md = ModelDesc()
+        md.precision = OC_FP64 if precision == "fp64" else OC_FP32_MIXED
+        md.advection = ADVECTION[ph.advection]
+        md.weno_eps = ph.weno_eps
+        md.weno_q = ph.weno_q
+        md.ntracers = len(ph.tracers)
+        md.buoyancy = 1 if ph.buoyancy else 0
+        md.f, md.g, md.alpha, md.beta = ph.f, ph.g, ph.alpha, ph.beta
+        md.t_ref, md.s_ref = ph.t_ref, ph.s_ref
+        md.nu, md.kappa = ph.nu, ph.kappa
+        for q, name in enumerate(ph.tracers):
+            md.top_flux[q] = ph.top_flux.get(name, 0.0)
+        self._gd, self._md = gd, md
+        self._grid = ctypes.c_void_p()
+        _check(lib.oc_grid_create(ctypes.byref(gd), ctypes.byref(self._grid)))
+        nbytes = ctypes.c_uint64()
+        _check(lib.oc_model_workspace_size(self._grid, ctypes.byref(md), ctypes.byref(nbytes)))
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+            self._model = ctypes.c_void_p()
+            _check(lib.oc_model_create(self._grid, ctypes.byref(md),
+                                       ctypes.c_void_p(self.workspace.data_ptr()),
+                                       ctypes.c_uint64(nbytes.value), ctypes.byref(self._model)))
+
+    def __del__(self):
+        try:
+            if getattr(self, "_model", None):
+                _lib.oc_model_destroy(self._model)
+            if getattr(self, "_grid", None):
+                _lib.oc_grid_destroy(self._grid)
+        except Exception:
+            pass
+
+    # -- helpers -----------------------------------------------------------
+    def field_id(self, name):
+        return self.fields.index(name)
+
+    def shape_of(self, name):
+        nzf = self.ph.nz + 1 if (name == "w" and self.ph.z_bounded) else self.ph.nz
+        return (nzf, self.ph.ny, self.ph.nx)
+
+    def _io(self, fn, name, buf):
+        """Call a set/get entry point with a numpy (host) or torch array."""
+        import torch
+        shape = (ctypes.c_int64 * 3)(*buf.shape)
+        if isinstance(buf, torch.Tensor):
+            assert buf.is_contiguous()
+            dtype = OC_F64 if buf.dtype == torch.float64 else OC_F32
+            ptr, on_dev = buf.data_ptr(), 1 if buf.is_cuda else 0
+        else:
+            assert buf.flags["C_CONTIGUOUS"]
+            dtype = OC_F64 if buf.dtype == np.float64 else OC_F32
+            ptr, on_dev = buf.ctypes.data, 0
+        _check(fn(self._model, self.field_id(name), ctypes.c_void_p(ptr), dtype, on_dev, shape,
+                  _stream()))
+
+    # -- C ABI -------------------------------------------------------------
+    def set_state(self, name, arr):
+        self._io(_lib.oc_set_state, name, arr)
+
+    def set_states(self, d):
+        for name in self.fields:
+            self.set_state(name, d[name])
+
+    def get_state(self, name, out=None, dtype=np.float64):
+        if out is None:
+            out = np.empty(self.shape_of(name), dtype=dtype)
+        self._io(_lib.oc_get_state, name, out)
+        return out
+
+    def get_states(self):
+        return {n: self.get_state(n) for n in self.fields}
+
+    def tendencies(self):
+        _check(_lib.oc_tendencies(self._model, _stream()))
+
+    def get_tendency(self, name, out=None, dtype=np.float64):
+        if out is None:
+            out = np.empty(self.shape_of(name), dtype=dtype)
+        self._io(_lib.oc_get_tendency, name, out)
+        return out
+
+    def pressure_solve(self, dt_eff):
+        _check(_lib.oc_pressure_solve(self._model, ctypes.c_double(dt_eff), _stream()))
+
+    def get_pressure(self, out=None):
+        if out is None:
+            out = np.empty((self.ph.nz, self.ph.ny, self.ph.nx), dtype=np.float64)
+        import torch
+        if isinstance(out, torch.Tensor):
+            _check(_lib.oc_get_pressure(self._model, ctypes.c_void_p(out.data_ptr()), 1, _stream()))
+        else:
+            _check(_lib.oc_get_pressure(self._model, ctypes.c_void_p(out.ctypes.data), 0, _stream()))
+        return out
+
+    def rk3_step(self, dt, nsteps=1):
+        _check(_lib.oc_rk3_step(self._model, ctypes.c_double(dt), ctypes.c_int32(nsteps), _stream()))
+
+    def diagnostics(self):
+        out = (ctypes.c_double * OC_NDIAG)()
+        _check(_lib.oc_diagnostics(self._model, out, _stream()))
+        return {"div_scaled_by_dx": out[0], "max_u": out[1], "max_v": out[2], "max_w": out[3],
+                "tracer_integrals": list(out[4:4 + len(self.ph.tracers)])}
+
+    def profile(self, enable=True):
+        _check(_lib.oc_profile(self._model, 1 if enable else 0))
+
+    def profile_read(self):
+        ms = (ctypes.c_double * OC_NPROF)()
+        n = (ctypes.c_int64 * OC_NPROF)()
+        _check(_lib.oc_profile_read(self._model, ms, n))
+        return {c: (ms[i], n[i]) for i, c in enumerate(PROF_CLASSES)}

@@ -1,0 +1,69 @@
+"""Host-side checks of the C ABI: the library loads, exports every function
+that include/oc.h declares, and rejects bad arguments before touching the GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2502_14148_amd import oc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            names |= set(re.findall(r"^\s*(?:int|const char\*)\s+(oc_\w+)\s*\(", text, re.M))
+    return names
+
+
+def test_header_declares_the_binding_exports():
+    assert declared_functions() == set(oc.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(oc._LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_grid_validation_errors():
+    lib = oc.load_library()
+    g = ctypes.c_void_p()
+    bad = oc.GridDesc(100, 32, 32, oc.OC_PERIODIC, 0, 1, 0, 1, 0, 1)
+    assert lib.oc_grid_create(ctypes.byref(bad), ctypes.byref(g)) == -5
+    assert b"unsupported" in lib.oc_last_error()
+    bad = oc.GridDesc(32, 32, 32, 7, 0, 1, 0, 1, 0, 1)
+    assert lib.oc_grid_create(ctypes.byref(bad), ctypes.byref(g)) == -1
+    bad = oc.GridDesc(32, 32, 32, oc.OC_BOUNDED, 0, -1, 0, 1, 0, 1)
+    assert lib.oc_grid_create(ctypes.byref(bad), ctypes.byref(g)) == -1
+    assert lib.oc_grid_create(None, ctypes.byref(g)) == -1
+
+
+def test_workspace_size_and_model_validation():
+    lib = oc.load_library()
+    g = ctypes.c_void_p()
+    gd = oc.GridDesc(32, 32, 16, oc.OC_BOUNDED, 0, 64, 0, 64, -16, 16)
+    assert lib.oc_grid_create(ctypes.byref(gd), ctypes.byref(g)) == 0
+    md = oc.ModelDesc()
+    md.precision, md.advection, md.weno_eps, md.weno_q = oc.OC_FP32_MIXED, 1, 1e-15, 2
+    md.ntracers, md.buoyancy = 2, 1
+    nbytes = ctypes.c_uint64()
+    assert lib.oc_model_workspace_size(g, ctypes.byref(md), ctypes.byref(nbytes)) == 0
+    padded = (32 + 6) * (32 + 6) * (16 + 6)
+    # two state copies + tendencies for 5 fields in FP32, plus the FP64 spectrum
+    assert nbytes.value >= 3 * 5 * padded * 4 + 16 * 32 * 17 * 16
+    md.weno_q = 3
+    assert lib.oc_model_workspace_size(g, ctypes.byref(md), ctypes.byref(nbytes)) == -5
+    md.weno_q, md.ntracers = 2, 0
+    assert lib.oc_model_workspace_size(g, ctypes.byref(md), ctypes.byref(nbytes)) == -1
+    md.ntracers, md.buoyancy = 1, 1
+    assert lib.oc_model_workspace_size(g, ctypes.byref(md), ctypes.byref(nbytes)) == -1
+    # a null workspace is refused before any device call
+    md.ntracers = 2
+    m = ctypes.c_void_p()
+    assert lib.oc_model_create(g, ctypes.byref(md), None, 0, ctypes.byref(m)) == -1
+    assert lib.oc_grid_destroy(g) == 0
