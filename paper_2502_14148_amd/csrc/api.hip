@@ -205,27 +205,10 @@ struct ProfScope {
 };
 
 template <class T>
-int halo_all(oc_model* m, int which, hipStream_t s) {
-  ProfScope ps(m, OC_PROF_HALO, s);
-  T* f[MAXF];
-  for (int q = 0; q < m->nf; ++q) f[q] = (T*)m->state[which][q];
-  OC_CHECK_HIP(launch_halo_fill<T>(m->dims, f, m->kinds, m->nf, s));
-  return OC_OK;
-}
-
-template <class T>
 int halo_one(oc_model* m, int which, int field, hipStream_t s) {
   T* f[1] = {(T*)m->state[which][field]};
   int kind[1] = {m->kinds[field]};
   OC_CHECK_HIP(launch_halo_fill<T>(m->dims, f, kind, 1, s));
-  return OC_OK;
-}
-
-template <class T>
-int halo_velocity(oc_model* m, int which, hipStream_t s) {
-  T* f[3];
-  for (int q = 0; q < 3; ++q) f[q] = (T*)m->state[which][q];
-  OC_CHECK_HIP(launch_halo_fill<T>(m->dims, f, m->kinds, 3, s));
   return OC_OK;
 }
 
@@ -256,6 +239,7 @@ TendParams<T> tend_params(const oc_model* m) {
   p.zet = 0;
   p.stage = 0;
   p.combine = 0;
+  p.images = 0;
   return p;
 }
 
@@ -275,7 +259,8 @@ int tendency_call(oc_model* m, int in, int out, int stage, double dt, int combin
   p.zet = (T)RK_ZETA[stage];
   p.stage = stage;
   p.combine = combine;
-  OC_CHECK_HIP(launch_tendency<T>(m->dims, fs, p, m->md.advection, s));
+  p.images = combine;  // substage outputs are final for tracers
+  OC_CHECK_HIP(launch_tendency_fast<T>(m->dims, fs, p, m->md.advection, s));
   return OC_OK;
 }
 
@@ -321,9 +306,9 @@ int rk3_steps(oc_model* m, double dt, int nsteps, hipStream_t s) {
       const int in = m->cur, out = 1 - m->cur;
       int rc = tendency_call<T>(m, in, out, st, dt, 1, s);
       if (rc) return rc;
+      // the projection writes the velocity halos, the tendency kernel those
+      // of the tracers
       rc = pressure_call<T>(m, out, (RK_GAMMA[st] - RK_ZETA[st]) * dt, s);
-      if (rc) return rc;
-      rc = halo_all<T>(m, out, s);
       if (rc) return rc;
       m->cur = out;
     }
@@ -611,10 +596,9 @@ int oc_pressure_solve(oc_model* m, double dt_eff, void* stream) {
   if (!m) { set_error("model is NULL"); return OC_ERR_ARG; }
   if (!(dt_eff > 0) || !std::isfinite(dt_eff)) { set_error("dt_eff must be positive"); return OC_ERR_ARG; }
   hipStream_t s = (hipStream_t)stream;
-  int rc = (m->esz == 8) ? pressure_call<double>(m, m->cur, dt_eff, s)
-                         : pressure_call<float>(m, m->cur, dt_eff, s);
-  if (rc) return rc;
-  return (m->esz == 8) ? halo_velocity<double>(m, m->cur, s) : halo_velocity<float>(m, m->cur, s);
+  // the projection also refills the velocity halos
+  return (m->esz == 8) ? pressure_call<double>(m, m->cur, dt_eff, s)
+                       : pressure_call<float>(m, m->cur, dt_eff, s);
 }
 
 int oc_get_pressure(oc_model* m, double* buf, int32_t on_device, void* stream) {

@@ -23,6 +23,40 @@ __host__ __device__ inline long pidx(const Dims& d, int i, int j, int k) {
   return (long)(k + H) * d.sz + (long)(j + H) * d.sy + (long)(i + H);
 }
 
+// Store a value at interior point (i, j, k) of a padded field and at its halo
+// images: periodic wrap in x, y (and z when periodic); in a bounded z, an even
+// mirror for data centred in z (wface = false) or an odd mirror about the
+// wall faces for w (wface = true).  Walls faces of w are never images.
+template <class T>
+__device__ inline void store_with_images(T* __restrict__ f, const Dims& d, int i, int j, int k,
+                                         T val, bool wface) {
+  const int H_ = 3;
+  int xi[2] = {i, i}, yj[2] = {j, j}, zk[2] = {k, k};
+  int nxi = 1, nyj = 1, nzk = 1;
+  T zsign = T(1);
+  if (i < H_) xi[nxi++] = i + d.nx;
+  else if (i >= d.nx - H_) xi[nxi++] = i - d.nx;
+  if (j < H_) yj[nyj++] = j + d.ny;
+  else if (j >= d.ny - H_) yj[nyj++] = j - d.ny;
+  if (!d.zb) {
+    if (k < H_) zk[nzk++] = k + d.nz;
+    else if (k >= d.nz - H_) zk[nzk++] = k - d.nz;
+  } else if (!wface) {
+    if (k < H_) zk[nzk++] = -1 - k;
+    else if (k >= d.nz - H_) zk[nzk++] = 2 * d.nz - 1 - k;
+  } else {
+    zsign = T(-1);
+    if (k >= 1 && k <= H_) zk[nzk++] = -k;
+    else if (k >= d.nz - 2 && k <= d.nz - 1) zk[nzk++] = 2 * d.nz - k;
+  }
+  for (int c = 0; c < nzk; ++c)
+    for (int b = 0; b < nyj; ++b)
+      for (int a = 0; a < nxi; ++a) {
+        const long p = (long)(zk[c] + H_) * d.sz + (long)(yj[b] + H_) * d.sy + (xi[a] + H_);
+        f[p] = (c > 0) ? zsign * val : val;
+      }
+}
+
 inline Dims make_dims(int nx, int ny, int nz, int zb) {
   Dims d;
   d.nx = nx; d.ny = ny; d.nz = nz;
@@ -49,6 +83,7 @@ struct TendParams {
   T dt, gam, zet;            // RK3 substage coefficients (dt * ...)
   int stage;                 // 0, 1, 2
   int combine;               // 1: write X~ = X + dt(gam G - zet Gprev); 0: only G
+  int images;                // 1: also write the halo images of the tracer outputs
 };
 
 template <class T>
@@ -82,6 +117,9 @@ hipError_t launch_halo_fill(const Dims& d, T* const* fields, const int* kinds, i
 template <class T>
 hipError_t launch_tendency(const Dims& d, const FieldSet<T>& fs, const TendParams<T>& p,
                            int scheme, hipStream_t s);
+template <class T>
+hipError_t launch_tendency_fast(const Dims& d, const FieldSet<T>& fs, const TendParams<T>& p,
+                                int scheme, hipStream_t s);
 struct Spacing { double rdx, rdy, rdz; };
 template <class T>
 hipError_t launch_poisson_x_forward(const Dims& d, const T* u, const T* v, const T* w,

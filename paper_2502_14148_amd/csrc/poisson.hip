@@ -332,14 +332,19 @@ __global__ void __launch_bounds__(256) project_kernel(Dims d, T* __restrict__ u,
   const double pc = p[t];
   const double pxm = p[t - i + ((i == 0) ? d.nx - 1 : i - 1)];
   const double pym = p[t - (long)j * row + (long)((j == 0) ? d.ny - 1 : j - 1) * row];
-  u[c] = (T)((double)u[c] - scale * (pc - pxm) * rdx);
-  v[c] = (T)((double)v[c] - scale * (pc - pym) * rdy);
+  const T un = (T)((double)u[c] - scale * (pc - pxm) * rdx);
+  const T vn = (T)((double)v[c] - scale * (pc - pym) * rdy);
+  T wn = w[c];
   if (d.zb) {
-    if (k > 0) w[c] = (T)((double)w[c] - scale * (pc - p[t - plane]) * rdz);
+    if (k > 0) wn = (T)((double)wn - scale * (pc - p[t - plane]) * rdz);
   } else {
     const double pzm = p[t - (long)k * plane + (long)((k == 0) ? d.nz - 1 : k - 1) * plane];
-    w[c] = (T)((double)w[c] - scale * (pc - pzm) * rdz);
+    wn = (T)((double)wn - scale * (pc - pzm) * rdz);
   }
+  // the final velocities, with their halo images
+  store_with_images(u, d, i, j, k, un, false);
+  store_with_images(v, d, i, j, k, vn, false);
+  store_with_images(w, d, i, j, k, wn, true);
 }
 
 // ---------------------------------------------------------------------------
