@@ -53,25 +53,44 @@ enum {
 };
 
 enum { OC_PERIODIC = 0, OC_BOUNDED = 1 };
+enum { OC_RECTILINEAR = 0, OC_LATLON = 1 };
+enum { OC_NONHYDROSTATIC = 0, OC_HYDROSTATIC = 1 };
 enum { OC_FP64 = 0, OC_FP32_MIXED = 1 };
 enum { OC_ADV_NONE = 0, OC_ADV_WENO5Z = 1, OC_ADV_WENO5_LINEAR = 2 };
 enum { OC_F32 = 0, OC_F64 = 1 };
-/* Field identifiers: velocities, then tracers 0..ntracers-1. */
+/* Field identifiers: velocities, then tracers 0..ntracers-1; the
+ * hydrostatic model adds its 2D barotropic fields (FP64): free surface eta
+ * at cell centres (shape (1, ny, nx)), transports U at x faces (1, ny, nx)
+ * and V at y faces (1, ny + 1, nx), and the slow forcing Gbar of U and V
+ * (same shapes as U and V). */
 enum { OC_U = 0, OC_V = 1, OC_W = 2, OC_TRACER0 = 3 };
+enum { OC_ETA = 16, OC_UBT = 17, OC_VBT = 18, OC_GUBT = 19, OC_GVBT = 20 };
 #define OC_MAX_TRACERS 4
 #define OC_NDIAG 8
 
-/* Grid (RectilinearGrid of the library subsection; uniform spacing). */
+/* Grid: RectilinearGrid or LatitudeLongitudeGrid of the library subsection
+ * (uniform spacing in each coordinate).
+ *   OC_RECTILINEAR: domain [x0, x0+lx) x [y0, y0+ly) x [z0, z0+lz) in meters;
+ *     x and y periodic, z per topology_z.
+ *   OC_LATLON (thin spherical shell of `radius`): x0, lx are the longitude
+ *     start and extent in degrees (periodic, lx = 360), y0, ly the latitude
+ *     start and extent in degrees (walls at both ends), z0, lz in meters
+ *     (walls at both ends). */
 typedef struct {
-  int32_t nx, ny, nz;       /* cells; each a supported FFT length (see below) */
-  int32_t topology_z;       /* OC_PERIODIC or OC_BOUNDED (x, y are periodic)  */
-  double x0, lx;            /* domain [x0, x0 + lx) */
+  int32_t nx, ny, nz;       /* cells */
+  int32_t topology_z;       /* OC_PERIODIC or OC_BOUNDED */
+  double x0, lx;
   double y0, ly;
   double z0, lz;
+  int32_t coord;            /* OC_RECTILINEAR or OC_LATLON */
+  double radius;            /* OC_LATLON: sphere radius in meters */
 } oc_grid_desc;
 
 /* Model physics (NonhydrostaticModel arguments of the equations section). */
 typedef struct {
+  int32_t kind;             /* OC_NONHYDROSTATIC (rectilinear grid) or
+                               OC_HYDROSTATIC (lat-lon grid, split-explicit
+                               free surface) */
   int32_t precision;        /* OC_FP64: everything in FP64.  OC_FP32_MIXED:
                                state, tendencies and the stencil arithmetic in
                                FP32; divergence, Poisson solve and projection
@@ -87,6 +106,8 @@ typedef struct {
   double g, alpha, beta, t_ref, s_ref;
   double nu, kappa;         /* constant viscosity, diffusivity */
   double top_flux[OC_MAX_TRACERS]; /* upward tracer flux through the top wall */
+  double depth;             /* OC_HYDROSTATIC: resting depth H (flat bottom) */
+  double omega;             /* OC_HYDROSTATIC: planetary rotation rate */
 } oc_model_desc;
 
 typedef struct oc_grid oc_grid;
@@ -95,9 +116,10 @@ typedef struct oc_model oc_model;
 /* Per-thread message of the last failing call ("" if none). */
 const char* oc_last_error(void);
 
-/* Validate `d` and create a grid handle (host memory only).  Supported
- * lengths in x, y, z: 8, 16, 32, 64, 96, 128, 256; ny even.
- * Errors: OC_ERR_ARG, OC_ERR_UNSUPPORTED. */
+/* Validate `d` and create a grid handle (host memory only).  Rectilinear
+ * grids (for the nonhydrostatic model's FFT solver) support lengths 8, 16,
+ * 32, 64, 96, 128, 256 in x, y, z with ny even; lat-lon grids any nx, ny,
+ * nz >= 8 with nx, ny multiples of 8.  Errors: OC_ERR_ARG, OC_ERR_UNSUPPORTED. */
 int oc_grid_create(const oc_grid_desc* d, oc_grid** out);
 int oc_grid_destroy(oc_grid* g);
 
@@ -157,6 +179,21 @@ enum {
 #define OC_NPROF 8
 int oc_profile(oc_model* m, int32_t enable);
 int oc_profile_read(oc_model* m, double* ms, int64_t* launches);
+
+/* Split-explicit barotropic mode of the hydrostatic model (hydrostatic
+ * time-discretisation appendix): M forward-backward substeps of length
+ * dt / N of the FP64 free surface eta and transports (U, V) under the frozen
+ * slow forcing Gbar,
+ *     eta <- eta - dtau div_h(U, V);  (U, V) <- (U, V) - dtau (g H grad_h eta - Gbar),
+ * accumulating etabar = sum a_n eta^n and (Ubar, Vbar) = sum a_n (U, V)^n
+ * over n = 1..M; then the correction of the baroclinic velocity,
+ * u <- u + (Ubar - sum_k dz u) / H (v likewise at interior y faces), and the
+ * restart eta = etabar, (U, V) = (Ubar, Vbar).  `a` is a host array of M
+ * weights (the filter is the caller's choice).  Linear free surface (H
+ * fixed), no Coriolis in the substeps.  Errors: OC_ERR_UNSUPPORTED for a
+ * nonhydrostatic model, OC_ERR_ARG for N < 1, M < 1, M > 4096 or NULL a. */
+int oc_free_surface_substeps(oc_model* m, double dt, int32_t N, int32_t M, const double* a,
+                             void* stream);
 
 /* FP64 diagnostics of the current state, synchronous; out (host) receives
  * OC_NDIAG doubles: [0] max|div u| * min(spacing), [1] max|u|, [2] max|v|,

@@ -26,7 +26,7 @@ FLAGS = [
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]
 
-SOURCES = ["api.hip", "stencil.hip", "poisson.hip", "tendency.hip"]
+SOURCES = ["api.hip", "stencil.hip", "poisson.hip", "tendency.hip", "barotropic.hip"]
 
 
 def _compile(src, defines=(), build_dir=None):

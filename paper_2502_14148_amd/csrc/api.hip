@@ -54,6 +54,18 @@ struct oc_model {
   void* staging;
   double* diag_part;
   double dx, dy, dz;
+  int kind;              // OC_NONHYDROSTATIC or OC_HYDROSTATIC
+  // hydrostatic model: 2D barotropic state (FP64), ping-pong (eta, U, V)
+  double* eta[2];
+  double* ubt[2];
+  double* vbt[2];
+  double* gubt;
+  double* gvbt;
+  double* etab;
+  double* ubar;
+  double* vbar;
+  double* metric;        // len_u | dx_u | len_v | dy_v | area
+  int bcur;
   // per-kernel-class event timing
   int prof_on;
   std::vector<hipEvent_t> ev_pool;
@@ -75,6 +87,7 @@ namespace {
 struct Layout {
   uint64_t state[2][MAXF], G[MAXF];
   uint64_t spec, p, twx, twy, twz, dctz, lamx, lamy, lamz, staging, diag;
+  uint64_t baro[11], metric;
   uint64_t total;
 };
 
@@ -82,6 +95,7 @@ uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
 
 Layout make_layout(const oc_grid_desc& g, const oc_model_desc& m) {
   Layout L;
+  std::memset(&L, 0, sizeof(L));
   Dims d = make_dims(g.nx, g.ny, g.nz, g.topology_z == OC_BOUNDED);
   const int nf = 3 + m.ntracers;
   const uint64_t esz = (m.precision == OC_FP64) ? 8 : 4;
@@ -96,17 +110,24 @@ Layout make_layout(const oc_grid_desc& g, const oc_model_desc& m) {
     L.G[q] = off;
     if (q < nf) off += fb;
   }
-  const uint64_t nxh = g.nx / 2 + 1;
-  L.spec = off; off += align256((uint64_t)g.nz * g.ny * nxh * 16);
-  L.p = off; off += align256((uint64_t)g.nz * g.ny * g.nx * 8);
-  L.twx = off; off += align256((uint64_t)g.nx * 16);
-  L.twy = off; off += align256((uint64_t)g.ny * 16);
-  L.twz = off; off += align256((uint64_t)g.nz * 16);
-  L.dctz = off; off += align256((uint64_t)g.nz * 16);
-  L.lamx = off; off += align256((uint64_t)g.nx * 8);
-  L.lamy = off; off += align256((uint64_t)g.ny * 8);
-  L.lamz = off; off += align256((uint64_t)g.nz * 8);
-  L.staging = off; off += align256((uint64_t)(g.nz + 1) * g.ny * g.nx * 8);
+  if (m.kind == OC_NONHYDROSTATIC) {
+    const uint64_t nxh = g.nx / 2 + 1;
+    L.spec = off; off += align256((uint64_t)g.nz * g.ny * nxh * 16);
+    L.p = off; off += align256((uint64_t)g.nz * g.ny * g.nx * 8);
+    L.twx = off; off += align256((uint64_t)g.nx * 16);
+    L.twy = off; off += align256((uint64_t)g.ny * 16);
+    L.twz = off; off += align256((uint64_t)g.nz * 16);
+    L.dctz = off; off += align256((uint64_t)g.nz * 16);
+    L.lamx = off; off += align256((uint64_t)g.nx * 8);
+    L.lamy = off; off += align256((uint64_t)g.ny * 8);
+    L.lamz = off; off += align256((uint64_t)g.nz * 8);
+  } else {
+    // eta[2], U[2], V[2], GU, GV, etabar, Ubar, Vbar (V-like: ny + 1 rows)
+    const uint64_t a2 = align256((uint64_t)(g.ny + 1) * g.nx * 8);
+    for (int q = 0; q < 11; ++q) { L.baro[q] = off; off += a2; }
+    L.metric = off; off += align256((uint64_t)(5 * (g.ny + 1)) * 8);
+  }
+  L.staging = off; off += align256((uint64_t)(g.nz + 1) * (g.ny + 1) * g.nx * 8);
   L.diag = off; off += align256((uint64_t)DIAG_BLOCKS * DIAG_PARTS * 8);
   L.total = off;
   return L;
@@ -114,12 +135,6 @@ Layout make_layout(const oc_grid_desc& g, const oc_model_desc& m) {
 
 int validate_grid(const oc_grid_desc* d) {
   if (!d) { set_error("grid descriptor is NULL"); return OC_ERR_ARG; }
-  if (!fft_length_supported(d->nx) || !fft_length_supported(d->ny) ||
-      !fft_length_supported(d->nz)) {
-    set_error("unsupported grid size %d x %d x %d (each of 8,16,32,64,96,128,256)", d->nx,
-              d->ny, d->nz);
-    return OC_ERR_UNSUPPORTED;
-  }
   if (d->topology_z != OC_PERIODIC && d->topology_z != OC_BOUNDED) {
     set_error("topology_z must be OC_PERIODIC or OC_BOUNDED");
     return OC_ERR_ARG;
@@ -129,11 +144,36 @@ int validate_grid(const oc_grid_desc* d) {
     set_error("domain extents must be positive and finite");
     return OC_ERR_ARG;
   }
+  if (d->coord == OC_RECTILINEAR) {
+    if (!fft_length_supported(d->nx) || !fft_length_supported(d->ny) ||
+        !fft_length_supported(d->nz)) {
+      set_error("unsupported grid size %d x %d x %d (each of 8,16,32,64,96,128,256)", d->nx,
+                d->ny, d->nz);
+      return OC_ERR_UNSUPPORTED;
+    }
+    if (d->ny % 2) { set_error("ny must be even"); return OC_ERR_UNSUPPORTED; }
+  } else if (d->coord == OC_LATLON) {
+    if (d->nx < 8 || d->ny < 8 || d->nz < 8 || d->nx % 8 || d->ny % 8) {
+      set_error("lat-lon grids need nx, ny multiples of 8 and nz >= 8");
+      return OC_ERR_UNSUPPORTED;
+    }
+    if (!(d->radius > 0) || d->y0 < -90.0 || d->y0 + d->ly > 90.0 || d->topology_z != OC_BOUNDED) {
+      set_error("lat-lon grid needs radius > 0, latitudes within [-90, 90] and walls in z");
+      return OC_ERR_ARG;
+    }
+  } else {
+    set_error("coord must be OC_RECTILINEAR or OC_LATLON");
+    return OC_ERR_ARG;
+  }
   return OC_OK;
 }
 
 int validate_model(const oc_model_desc* m) {
   if (!m) { set_error("model descriptor is NULL"); return OC_ERR_ARG; }
+  if (m->kind != OC_NONHYDROSTATIC && m->kind != OC_HYDROSTATIC) {
+    set_error("kind must be OC_NONHYDROSTATIC or OC_HYDROSTATIC");
+    return OC_ERR_ARG;
+  }
   if (m->precision != OC_FP64 && m->precision != OC_FP32_MIXED) {
     set_error("precision must be OC_FP64 or OC_FP32_MIXED");
     return OC_ERR_ARG;
@@ -158,27 +198,80 @@ int validate_model(const oc_model_desc* m) {
     set_error("nu and kappa must be >= 0");
     return OC_ERR_ARG;
   }
+  if (m->kind == OC_HYDROSTATIC && !(m->depth > 0)) {
+    set_error("hydrostatic model needs depth > 0");
+    return OC_ERR_ARG;
+  }
   return OC_OK;
 }
 
+int validate_pair(const oc_grid_desc& g, const oc_model_desc& m) {
+  if (m.kind == OC_NONHYDROSTATIC && g.coord != OC_RECTILINEAR) {
+    set_error("the nonhydrostatic model runs on rectilinear grids");
+    return OC_ERR_UNSUPPORTED;
+  }
+  if (m.kind == OC_HYDROSTATIC && g.coord != OC_LATLON) {
+    set_error("the hydrostatic model runs on lat-lon grids");
+    return OC_ERR_UNSUPPORTED;
+  }
+  return OC_OK;
+}
+
+bool is_2d_field(int field) { return field >= OC_ETA && field <= OC_GVBT; }
+
 int nzf_of(const oc_model* m, int field) {
+  if (is_2d_field(field)) return 1;
   return (field == OC_W && m->dims.zb) ? m->dims.nz + 1 : m->dims.nz;
+}
+
+// rows of a field: v-like fields of the hydrostatic model include the
+// northern wall face
+int nyf_of(const oc_model* m, int field) {
+  const bool vlike = field == OC_VBT || field == OC_GVBT ||
+                     (m->kind == OC_HYDROSTATIC && field == OC_V);
+  return vlike ? m->dims.ny + 1 : m->dims.ny;
 }
 
 int check_field_io(const oc_model* m, int field, const void* buf, int dtype,
                    const int64_t shape[3]) {
   if (!m || !buf || !shape) { set_error("NULL argument"); return OC_ERR_ARG; }
-  if (field < 0 || field >= m->nf) {
-    set_error("field %d out of range (model has %d fields)", field, m->nf);
+  const bool f2 = is_2d_field(field) && m->kind == OC_HYDROSTATIC;
+  if (!f2 && (field < 0 || field >= m->nf)) {
+    set_error("field %d is not a field of this model", field);
     return OC_ERR_ARG;
   }
   if (dtype != OC_F32 && dtype != OC_F64) { set_error("dtype must be OC_F32 or OC_F64"); return OC_ERR_DTYPE; }
-  if (shape[0] != nzf_of(m, field) || shape[1] != m->dims.ny || shape[2] != m->dims.nx) {
+  if (f2 && dtype != OC_F64) { set_error("barotropic fields are FP64"); return OC_ERR_DTYPE; }
+  if (shape[0] != nzf_of(m, field) || shape[1] != nyf_of(m, field) || shape[2] != m->dims.nx) {
     set_error("shape (%lld, %lld, %lld) does not match (%d, %d, %d)", (long long)shape[0],
-              (long long)shape[1], (long long)shape[2], nzf_of(m, field), m->dims.ny,
+              (long long)shape[1], (long long)shape[2], nzf_of(m, field), nyf_of(m, field),
               m->dims.nx);
     return OC_ERR_SHAPE;
   }
+  return OC_OK;
+}
+
+double* baro_field(oc_model* m, int field) {
+  switch (field) {
+    case OC_ETA: return m->eta[m->bcur];
+    case OC_UBT: return m->ubt[m->bcur];
+    case OC_VBT: return m->vbt[m->bcur];
+    case OC_GUBT: return m->gubt;
+    default: return m->gvbt;
+  }
+}
+
+int baro_io(oc_model* m, int field, void* buf, int on_device, int to_host, hipStream_t s) {
+  double* f = baro_field(m, field);
+  const size_t bytes = (size_t)nyf_of(m, field) * m->dims.nx * 8;
+  if (to_host) {
+    OC_CHECK_HIP(hipMemcpyAsync(buf, f, bytes,
+                                on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+  } else {
+    OC_CHECK_HIP(hipMemcpyAsync(f, buf, bytes,
+                                on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+  }
+  if (!on_device) OC_CHECK_HIP(hipStreamSynchronize(s));
   return OC_OK;
 }
 
@@ -317,12 +410,12 @@ int rk3_steps(oc_model* m, double dt, int nsteps, hipStream_t s) {
 }
 
 template <class T>
-int field_io(oc_model* m, void* fieldbuf, int nzf, void* buf, int dtype, int on_device,
+int field_io(oc_model* m, void* fieldbuf, int nzf, int nyf, void* buf, int dtype, int on_device,
              int to_dense, double offset, hipStream_t s) {
-  const uint64_t bytes = (uint64_t)nzf * m->dims.ny * m->dims.nx * (dtype == OC_F32 ? 4 : 8);
+  const uint64_t bytes = (uint64_t)nzf * nyf * m->dims.nx * (dtype == OC_F32 ? 4 : 8);
   if (to_dense) {
     void* dst = on_device ? buf : m->staging;
-    OC_CHECK_HIP(launch_pack<T>(m->dims, nzf, (const T*)fieldbuf, dst, dtype, 1, offset, s));
+    OC_CHECK_HIP(launch_pack<T>(m->dims, nzf, nyf, (const T*)fieldbuf, dst, dtype, 1, offset, s));
     if (!on_device) {
       OC_CHECK_HIP(hipMemcpyAsync(buf, m->staging, bytes, hipMemcpyDeviceToHost, s));
       OC_CHECK_HIP(hipStreamSynchronize(s));
@@ -334,8 +427,8 @@ int field_io(oc_model* m, void* fieldbuf, int nzf, void* buf, int dtype, int on_
       OC_CHECK_HIP(hipStreamSynchronize(s));
       src = m->staging;
     }
-    OC_CHECK_HIP(launch_pack<T>(m->dims, nzf, (const T*)fieldbuf, const_cast<void*>(src), dtype,
-                                0, offset, s));
+    OC_CHECK_HIP(launch_pack<T>(m->dims, nzf, nyf, (const T*)fieldbuf, const_cast<void*>(src),
+                                dtype, 0, offset, s));
   }
   return OC_OK;
 }
@@ -404,6 +497,85 @@ void fill_tables(const oc_grid_desc& g, std::vector<double>& twx, std::vector<do
   lam(lamz, g.nz, dz, g.topology_z == OC_BOUNDED);
 }
 
+// Thin-shell metrics of a lat-lon grid, packed as len_u | dx_u | len_v |
+// dy_v | area, each padded to ny + 1 entries.
+void fill_latlon_metrics(const oc_grid_desc& g, std::vector<double>& met) {
+  const double pi = 3.14159265358979323846;
+  const int ny = g.ny;
+  const double dlam = g.lx / g.nx * pi / 180.0;
+  const double dphi = g.ly / ny * pi / 180.0;
+  const double phi0 = g.y0 * pi / 180.0;
+  const double R = g.radius;
+  met.assign(5 * (size_t)(ny + 1), 0.0);
+  double* len_u = met.data();
+  double* dx_u = len_u + (ny + 1);
+  double* len_v = dx_u + (ny + 1);
+  double* dy_v = len_v + (ny + 1);
+  double* area = dy_v + (ny + 1);
+  for (int j = 0; j <= ny; ++j) {
+    const double phf = phi0 + j * dphi;
+    len_v[j] = R * std::cos(phf) * dlam;
+    dy_v[j] = R * dphi;
+    if (j < ny) {
+      const double phc = phf + 0.5 * dphi;
+      len_u[j] = R * dphi;
+      dx_u[j] = R * std::cos(phc) * dlam;
+      area[j] = R * R * dlam * (std::sin(phf + dphi) - std::sin(phf));
+    }
+  }
+}
+
+BaroBufs baro_bufs(oc_model* m) {
+  BaroBufs b;
+  const int ny = m->dims.ny;
+  const int in = m->bcur, out = 1 - m->bcur;
+  b.eta = m->eta[in];
+  b.U = m->ubt[in];
+  b.V = m->vbt[in];
+  b.eta1 = m->eta[out];
+  b.U1 = m->ubt[out];
+  b.V1 = m->vbt[out];
+  b.GU = m->gubt;
+  b.GV = m->gvbt;
+  b.etab = m->etab;
+  b.Ub = m->ubar;
+  b.Vb = m->vbar;
+  b.len_u = m->metric;
+  b.dx_u = m->metric + (ny + 1);
+  b.len_v = m->metric + 2 * (ny + 1);
+  b.dy_v = m->metric + 3 * (ny + 1);
+  b.area = m->metric + 4 * (ny + 1);
+  b.nx = m->dims.nx;
+  b.ny = ny;
+  return b;
+}
+
+template <class T>
+int free_surface_call(oc_model* m, double dt, int N, int M, const double* a, hipStream_t s) {
+  const long n2 = (long)(m->dims.ny + 1) * m->dims.nx;
+  OC_CHECK_HIP(launch_baro_fill(m->etab, 0.0, n2, s));
+  OC_CHECK_HIP(launch_baro_fill(m->ubar, 0.0, n2, s));
+  OC_CHECK_HIP(launch_baro_fill(m->vbar, 0.0, n2, s));
+  const double dtau = dt / N;
+  const double gH = m->md.g * m->md.depth;
+  for (int n = 0; n < M; ++n) {
+    BaroBufs b = baro_bufs(m);
+    OC_CHECK_HIP(launch_baro_substep(b, dtau, gH, a[n], s));
+    m->bcur = 1 - m->bcur;
+  }
+  // correction of the baroclinic velocity: its depth integral becomes Ubar
+  const double dz = m->gd.lz / m->gd.nz;
+  OC_CHECK_HIP(launch_baro_correct<T>(m->dims, (T*)m->state[m->cur][OC_U], m->ubar, 0,
+                                      m->dims.ny, dz, m->md.depth, s));
+  OC_CHECK_HIP(launch_baro_correct<T>(m->dims, (T*)m->state[m->cur][OC_V], m->vbar, 1,
+                                      m->dims.ny, dz, m->md.depth, s));
+  // restart of the barotropic state from the averages
+  OC_CHECK_HIP(launch_baro_copy(m->eta[m->bcur], m->etab, (long)m->dims.ny * m->dims.nx, s));
+  OC_CHECK_HIP(launch_baro_copy(m->ubt[m->bcur], m->ubar, (long)m->dims.ny * m->dims.nx, s));
+  OC_CHECK_HIP(launch_baro_copy(m->vbt[m->bcur], m->vbar, n2, s));
+  return OC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -414,7 +586,6 @@ int oc_grid_create(const oc_grid_desc* d, oc_grid** out) {
   if (!out) { set_error("out is NULL"); return OC_ERR_ARG; }
   int rc = validate_grid(d);
   if (rc) return rc;
-  if (d->ny % 2) { set_error("ny must be even"); return OC_ERR_UNSUPPORTED; }
   oc_grid* g = new (std::nothrow) oc_grid;
   if (!g) { set_error("out of host memory"); return OC_ERR_ARG; }
   g->d = *d;
@@ -431,6 +602,8 @@ int oc_model_workspace_size(const oc_grid* g, const oc_model_desc* m, uint64_t* 
   if (!g || !bytes) { set_error("NULL argument"); return OC_ERR_ARG; }
   int rc = validate_model(m);
   if (rc) return rc;
+  rc = validate_pair(g->d, *m);
+  if (rc) return rc;
   *bytes = make_layout(g->d, *m).total;
   return OC_OK;
 }
@@ -439,6 +612,8 @@ int oc_model_create(const oc_grid* g, const oc_model_desc* md, void* workspace,
                     uint64_t workspace_bytes, oc_model** out) {
   if (!g || !out || !workspace) { set_error("NULL argument"); return OC_ERR_ARG; }
   int rc = validate_model(md);
+  if (rc) return rc;
+  rc = validate_pair(g->d, *md);
   if (rc) return rc;
   if (((uintptr_t)workspace) % 256) { set_error("workspace must be 256-byte aligned"); return OC_ERR_ARG; }
   const Layout L = make_layout(g->d, *md);
@@ -493,16 +668,36 @@ int oc_model_create(const oc_grid* g, const oc_model_desc* md, void* workspace,
   m->staging = m->ws + L.staging;
   m->diag_part = (double*)(m->ws + L.diag);
 
-  std::vector<double> twx, twy, twz, dctz, lamx, lamy, lamz;
-  fill_tables(g->d, twx, twy, twz, dctz, lamx, lamy, lamz, m->dx, m->dy, m->dz);
+  m->kind = md->kind;
+  for (int q = 0; q < 2; ++q) {
+    m->eta[q] = (double*)(m->ws + L.baro[0 + q]);
+    m->ubt[q] = (double*)(m->ws + L.baro[2 + q]);
+    m->vbt[q] = (double*)(m->ws + L.baro[4 + q]);
+  }
+  m->gubt = (double*)(m->ws + L.baro[6]);
+  m->gvbt = (double*)(m->ws + L.baro[7]);
+  m->etab = (double*)(m->ws + L.baro[8]);
+  m->ubar = (double*)(m->ws + L.baro[9]);
+  m->vbar = (double*)(m->ws + L.baro[10]);
+  m->metric = (double*)(m->ws + L.metric);
+  m->bcur = 0;
+
   hipError_t e = hipMemset(m->ws, 0, L.total);
-  if (e == hipSuccess) e = hipMemcpy(m->ws + L.twx, twx.data(), twx.size() * 8, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(m->ws + L.twy, twy.data(), twy.size() * 8, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(m->ws + L.twz, twz.data(), twz.size() * 8, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(m->ws + L.dctz, dctz.data(), dctz.size() * 8, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(m->ws + L.lamx, lamx.data(), lamx.size() * 8, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(m->ws + L.lamy, lamy.data(), lamy.size() * 8, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(m->ws + L.lamz, lamz.data(), lamz.size() * 8, hipMemcpyHostToDevice);
+  if (md->kind == OC_NONHYDROSTATIC) {
+    std::vector<double> twx, twy, twz, dctz, lamx, lamy, lamz;
+    fill_tables(g->d, twx, twy, twz, dctz, lamx, lamy, lamz, m->dx, m->dy, m->dz);
+    if (e == hipSuccess) e = hipMemcpy(m->ws + L.twx, twx.data(), twx.size() * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(m->ws + L.twy, twy.data(), twy.size() * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(m->ws + L.twz, twz.data(), twz.size() * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(m->ws + L.dctz, dctz.data(), dctz.size() * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(m->ws + L.lamx, lamx.data(), lamx.size() * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(m->ws + L.lamy, lamy.data(), lamy.size() * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(m->ws + L.lamz, lamz.data(), lamz.size() * 8, hipMemcpyHostToDevice);
+  } else {
+    std::vector<double> met;
+    fill_latlon_metrics(g->d, met);
+    if (e == hipSuccess) e = hipMemcpy(m->metric, met.data(), met.size() * 8, hipMemcpyHostToDevice);
+  }
   if (e != hipSuccess) {
     set_error("model setup failed: %s", hipGetErrorString(e));
     delete m;
@@ -549,17 +744,31 @@ int oc_set_state(oc_model* m, int32_t field, const void* buf, int32_t dtype, int
   int rc = check_field_io(m, field, buf, dtype, shape);
   if (rc) return rc;
   hipStream_t s = (hipStream_t)stream;
+  if (is_2d_field(field)) {
+    rc = baro_io(m, field, const_cast<void*>(buf), on_device, 0, s);
+    if (rc) return rc;
+    if (field == OC_VBT || field == OC_GVBT) {
+      // the wall faces carry no transport
+      double* f = baro_field(m, field);
+      OC_CHECK_HIP(launch_baro_fill(f, 0.0, m->dims.nx, s));
+      OC_CHECK_HIP(launch_baro_fill(f + (size_t)m->dims.ny * m->dims.nx, 0.0, m->dims.nx, s));
+    }
+    return OC_OK;
+  }
   void* fb = m->state[m->cur][field];
-  const int nzf = nzf_of(m, field);
+  const int nzf = nzf_of(m, field), nyf = nyf_of(m, field);
   const double off = m->offset[field];
-  if (m->esz == 8) rc = field_io<double>(m, fb, nzf, const_cast<void*>(buf), dtype, on_device, 0, off, s);
-  else rc = field_io<float>(m, fb, nzf, const_cast<void*>(buf), dtype, on_device, 0, off, s);
+  if (m->esz == 8)
+    rc = field_io<double>(m, fb, nzf, nyf, const_cast<void*>(buf), dtype, on_device, 0, off, s);
+  else
+    rc = field_io<float>(m, fb, nzf, nyf, const_cast<void*>(buf), dtype, on_device, 0, off, s);
   if (rc) return rc;
   if (field == OC_W && m->dims.zb) {
     // the bottom wall face carries no flow
     OC_CHECK_HIP(hipMemsetAsync((char*)fb + (size_t)H * m->dims.sz * m->esz, 0,
                                 (size_t)m->dims.sz * m->esz, s));
   }
+  if (m->kind == OC_HYDROSTATIC) return OC_OK;  // its halos are filled by its own kernels
   return (m->esz == 8) ? halo_one<double>(m, m->cur, field, s) : halo_one<float>(m, m->cur, field, s);
 }
 
@@ -568,15 +777,17 @@ int oc_get_state(oc_model* m, int32_t field, void* buf, int32_t dtype, int32_t o
   int rc = check_field_io(m, field, buf, dtype, shape);
   if (rc) return rc;
   hipStream_t s = (hipStream_t)stream;
+  if (is_2d_field(field)) return baro_io(m, field, buf, on_device, 1, s);
   void* fb = m->state[m->cur][field];
-  const int nzf = nzf_of(m, field);
+  const int nzf = nzf_of(m, field), nyf = nyf_of(m, field);
   const double off = m->offset[field];
-  return (m->esz == 8) ? field_io<double>(m, fb, nzf, buf, dtype, on_device, 1, off, s)
-                       : field_io<float>(m, fb, nzf, buf, dtype, on_device, 1, off, s);
+  return (m->esz == 8) ? field_io<double>(m, fb, nzf, nyf, buf, dtype, on_device, 1, off, s)
+                       : field_io<float>(m, fb, nzf, nyf, buf, dtype, on_device, 1, off, s);
 }
 
 int oc_tendencies(oc_model* m, void* stream) {
   if (!m) { set_error("model is NULL"); return OC_ERR_ARG; }
+  if (m->kind != OC_NONHYDROSTATIC) { set_error("nonhydrostatic model only"); return OC_ERR_UNSUPPORTED; }
   hipStream_t s = (hipStream_t)stream;
   return (m->esz == 8) ? tendency_call<double>(m, m->cur, m->cur, 0, 0.0, 0, s)
                        : tendency_call<float>(m, m->cur, m->cur, 0, 0.0, 0, s);
@@ -587,13 +798,16 @@ int oc_get_tendency(oc_model* m, int32_t field, void* buf, int32_t dtype, int32_
   int rc = check_field_io(m, field, buf, dtype, shape);
   if (rc) return rc;
   hipStream_t s = (hipStream_t)stream;
-  const int nzf = nzf_of(m, field);
-  return (m->esz == 8) ? field_io<double>(m, m->G[field], nzf, buf, dtype, on_device, 1, 0.0, s)
-                       : field_io<float>(m, m->G[field], nzf, buf, dtype, on_device, 1, 0.0, s);
+  if (is_2d_field(field)) { set_error("barotropic fields have no tendency buffer"); return OC_ERR_ARG; }
+  const int nzf = nzf_of(m, field), nyf = nyf_of(m, field);
+  return (m->esz == 8)
+             ? field_io<double>(m, m->G[field], nzf, nyf, buf, dtype, on_device, 1, 0.0, s)
+             : field_io<float>(m, m->G[field], nzf, nyf, buf, dtype, on_device, 1, 0.0, s);
 }
 
 int oc_pressure_solve(oc_model* m, double dt_eff, void* stream) {
   if (!m) { set_error("model is NULL"); return OC_ERR_ARG; }
+  if (m->kind != OC_NONHYDROSTATIC) { set_error("nonhydrostatic model only"); return OC_ERR_UNSUPPORTED; }
   if (!(dt_eff > 0) || !std::isfinite(dt_eff)) { set_error("dt_eff must be positive"); return OC_ERR_ARG; }
   hipStream_t s = (hipStream_t)stream;
   // the projection also refills the velocity halos
@@ -603,6 +817,7 @@ int oc_pressure_solve(oc_model* m, double dt_eff, void* stream) {
 
 int oc_get_pressure(oc_model* m, double* buf, int32_t on_device, void* stream) {
   if (!m || !buf) { set_error("NULL argument"); return OC_ERR_ARG; }
+  if (m->kind != OC_NONHYDROSTATIC) { set_error("nonhydrostatic model only"); return OC_ERR_UNSUPPORTED; }
   hipStream_t s = (hipStream_t)stream;
   const size_t bytes = (size_t)m->dims.nz * m->dims.ny * m->dims.nx * 8;
   OC_CHECK_HIP(hipMemcpyAsync(buf, m->sb.p, bytes,
@@ -613,6 +828,7 @@ int oc_get_pressure(oc_model* m, double* buf, int32_t on_device, void* stream) {
 
 int oc_rk3_step(oc_model* m, double dt, int32_t nsteps, void* stream) {
   if (!m) { set_error("model is NULL"); return OC_ERR_ARG; }
+  if (m->kind != OC_NONHYDROSTATIC) { set_error("nonhydrostatic model only"); return OC_ERR_UNSUPPORTED; }
   if (!(dt > 0) || !std::isfinite(dt)) { set_error("dt must be positive"); return OC_ERR_ARG; }
   if (nsteps < 0) { set_error("nsteps must be >= 0"); return OC_ERR_ARG; }
   hipStream_t s = (hipStream_t)stream;
@@ -623,6 +839,21 @@ int oc_diagnostics(oc_model* m, double* out, void* stream) {
   if (!m || !out) { set_error("NULL argument"); return OC_ERR_ARG; }
   hipStream_t s = (hipStream_t)stream;
   return (m->esz == 8) ? diagnostics_call<double>(m, out, s) : diagnostics_call<float>(m, out, s);
+}
+
+int oc_free_surface_substeps(oc_model* m, double dt, int32_t N, int32_t M, const double* a,
+                             void* stream) {
+  if (!m || !a) { set_error("NULL argument"); return OC_ERR_ARG; }
+  if (m->kind != OC_HYDROSTATIC) { set_error("hydrostatic model only"); return OC_ERR_UNSUPPORTED; }
+  if (!(dt > 0) || N < 1 || M < 1 || M > 4096) {
+    set_error("need dt > 0, N >= 1 and 1 <= M <= 4096");
+    return OC_ERR_ARG;
+  }
+  for (int n = 0; n < M; ++n)
+    if (!std::isfinite(a[n])) { set_error("weight %d is not finite", n); return OC_ERR_ARG; }
+  hipStream_t s = (hipStream_t)stream;
+  return (m->esz == 8) ? free_surface_call<double>(m, dt, N, M, a, s)
+                       : free_surface_call<float>(m, dt, N, M, a, s);
 }
 
 }  // extern "C"

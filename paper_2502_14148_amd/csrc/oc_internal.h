@@ -107,6 +107,35 @@ struct SpecBufs {
   int nxh;
 };
 
+// 2D barotropic buffers and metric factors of the hydrostatic model (FP64,
+// dense, x fastest; V-like arrays have ny + 1 rows).
+struct BaroBufs {
+  const double* eta;
+  const double* U;
+  const double* V;
+  double* eta1;
+  double* U1;
+  double* V1;
+  const double* GU;
+  const double* GV;
+  double* etab;
+  double* Ub;
+  double* Vb;
+  const double* len_u;   // (ny)     length of an x face
+  const double* dx_u;    // (ny)     centre distance across an x face
+  const double* len_v;   // (ny + 1) length of a y face
+  const double* dy_v;    // (ny + 1) centre distance across a y face
+  const double* area;    // (ny)     cell area
+  int nx, ny;
+};
+
+hipError_t launch_baro_fill(double* a, double v, long n, hipStream_t s);
+hipError_t launch_baro_copy(double* dst, const double* src, long n, hipStream_t s);
+hipError_t launch_baro_substep(const BaroBufs& b, double dtau, double gH, double wn, hipStream_t s);
+template <class T>
+hipError_t launch_baro_correct(const Dims& d, T* f, const double* bar, int j_lo, int j_hi,
+                               double dz, double depth, hipStream_t s);
+
 // Host-side error reporting (per thread).
 void set_error(const char* fmt, ...);
 
@@ -131,7 +160,7 @@ template <class T>
 hipError_t launch_project(const Dims& d, T* u, T* v, T* w, double scale, double rdx,
                           double rdy, double rdz, const double* p, hipStream_t s);
 template <class T>
-hipError_t launch_pack(const Dims& d, int nzf, const T* padded, void* dense, int dtype,
+hipError_t launch_pack(const Dims& d, int nzf, int nyf, const T* padded, void* dense, int dtype,
                        int to_dense, double offset, hipStream_t s);
 template <class T>
 hipError_t launch_diagnostics(const Dims& d, T* const* fields, int nf, double rdx, double rdy,

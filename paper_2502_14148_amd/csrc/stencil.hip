@@ -286,30 +286,30 @@ hipError_t launch_tendency(const Dims& d, const FieldSet<T>& fs, const TendParam
 // `offset` is the storage offset of the field: stored = value - offset
 // (FP32 tracers are kept as anomalies about the equation-of-state reference).
 template <class T, class D>
-__global__ void __launch_bounds__(256) pack_kernel(Dims d, int nzf, T* padded, D* dense,
+__global__ void __launch_bounds__(256) pack_kernel(Dims d, int nzf, int nyf, T* padded, D* dense,
                                                    int to_dense, double offset) {
   long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  long n = (long)nzf * d.ny * d.nx;
+  long n = (long)nzf * nyf * d.nx;
   if (t >= n) return;
   int i = (int)(t % d.nx);
-  int j = (int)((t / d.nx) % d.ny);
-  int k = (int)(t / ((long)d.nx * d.ny));
+  int j = (int)((t / d.nx) % nyf);
+  int k = (int)(t / ((long)d.nx * nyf));
   long p = pidx(d, i, j, k);
   if (to_dense) dense[t] = (D)((double)padded[p] + offset);
   else padded[p] = (T)((double)dense[t] - offset);
 }
 
 template <class T>
-hipError_t launch_pack(const Dims& d, int nzf, const T* padded, void* dense, int dtype,
+hipError_t launch_pack(const Dims& d, int nzf, int nyf, const T* padded, void* dense, int dtype,
                        int to_dense, double offset, hipStream_t s) {
-  long n = (long)nzf * d.ny * d.nx;
+  long n = (long)nzf * nyf * d.nx;
   dim3 grid((unsigned)((n + 255) / 256));
   T* pp = const_cast<T*>(padded);
   if (dtype == OC_F32)
-    hipLaunchKernelGGL((pack_kernel<T, float>), grid, dim3(256), 0, s, d, nzf, pp,
+    hipLaunchKernelGGL((pack_kernel<T, float>), grid, dim3(256), 0, s, d, nzf, nyf, pp,
                        (float*)dense, to_dense, offset);
   else
-    hipLaunchKernelGGL((pack_kernel<T, double>), grid, dim3(256), 0, s, d, nzf, pp,
+    hipLaunchKernelGGL((pack_kernel<T, double>), grid, dim3(256), 0, s, d, nzf, nyf, pp,
                        (double*)dense, to_dense, offset);
   return hipGetLastError();
 }
@@ -389,10 +389,10 @@ template hipError_t launch_tendency<float>(const Dims&, const FieldSet<float>&,
                                            const TendParams<float>&, int, hipStream_t);
 template hipError_t launch_tendency<double>(const Dims&, const FieldSet<double>&,
                                             const TendParams<double>&, int, hipStream_t);
-template hipError_t launch_pack<float>(const Dims&, int, const float*, void*, int, int, double,
-                                       hipStream_t);
-template hipError_t launch_pack<double>(const Dims&, int, const double*, void*, int, int, double,
-                                        hipStream_t);
+template hipError_t launch_pack<float>(const Dims&, int, int, const float*, void*, int, int,
+                                       double, hipStream_t);
+template hipError_t launch_pack<double>(const Dims&, int, int, const double*, void*, int, int,
+                                        double, hipStream_t);
 template hipError_t launch_diagnostics<float>(const Dims&, float* const*, int, double, double,
                                               double, double*, int, hipStream_t);
 template hipError_t launch_diagnostics<double>(const Dims&, double* const*, int, double, double,

@@ -302,3 +302,73 @@ def smooth_random_state(ph: Physics, seed: int = 0, kmax: int = 3, vel: float = 
     for idx, name in enumerate(ph.tracers):
         out[name] = 10.0 * idx + trig((0, 0, 0), even)
     return out
+
+
+# ---------------------------------------------------------------------------
+# Hydrostatic model on a latitude-longitude sector
+# ---------------------------------------------------------------------------
+
+@dataclass
+class HydrostaticPhysics:
+    """Parameters of the hydrostatic model on a lat-lon grid (plain data).
+    Longitude is periodic; walls at the southern/northern edges and in z."""
+
+    nx: int
+    ny: int
+    nz: int
+    lon0: float = 0.0
+    lon_extent: float = 360.0
+    lat0: float = -70.0
+    lat_extent: float = 140.0
+    depth: float = 3000.0
+    radius: float = 6.371e6
+    omega: float = 7.292115e-5
+    g: float = G_EARTH
+    advection: str = "weno5z"
+    weno_eps: float = 1e-15
+    weno_q: int = 2
+    alpha: float = 2e-4
+    beta: float = 8e-4
+    t_ref: float = 0.0
+    s_ref: float = 35.0
+    nu: float = 1e-4                   # vertical viscosity
+    kappa: float = 1e-4                # vertical diffusivity
+    tracers: tuple = ("T", "S")
+    buoyancy: bool = True
+    kind: str = "hydrostatic"
+
+    @property
+    def dz(self):
+        return self.depth / self.nz
+
+
+def sector_physics(n=(1440, 560, 50)) -> HydrostaticPhysics:
+    """Idealised 1/4-degree sector between 70S and 70N, 3000 m deep."""
+    nx, ny, nz = n
+    return HydrostaticPhysics(nx=nx, ny=ny, nz=nz)
+
+
+def averaging_weights(N: int, M: int = None):
+    """Cosine-bell averaging weights a_1..a_M for the barotropic substeps,
+    symmetric about substep N (M = 2N - 1 by default) and summing to one, so
+    the average is centred on the end of the baroclinic step."""
+    M = 2 * N - 1 if M is None else M
+    n = np.arange(1, M + 1)
+    w = np.cos(0.5 * np.pi * (n - N) / N) ** 2
+    return w / w.sum()
+
+
+def barotropic_random_state(ph: HydrostaticPhysics, seed: int = 0, eta_scale: float = 0.5,
+                            transport_scale: float = 50.0, forcing_scale: float = 1e-4):
+    """Random free surface, transports and slow forcing (V = 0 on walls)."""
+    rng = np.random.default_rng(seed)
+    ny, nx = ph.ny, ph.nx
+    out = {"eta": eta_scale * rng.standard_normal((1, ny, nx)),
+           "U": transport_scale * rng.standard_normal((1, ny, nx)),
+           "V": transport_scale * rng.standard_normal((1, ny + 1, nx)),
+           "GU": forcing_scale * rng.standard_normal((1, ny, nx)),
+           "GV": forcing_scale * rng.standard_normal((1, ny + 1, nx))}
+    for k in ("V", "GV"):
+        out[k][:, 0] = 0.0
+        out[k][:, -1] = 0.0
+    return out

@@ -16,6 +16,9 @@ OC_OK = 0
 OC_ERR = {-1: "OC_ERR_ARG", -2: "OC_ERR_SHAPE", -3: "OC_ERR_DTYPE", -4: "OC_ERR_DEVICE",
           -5: "OC_ERR_UNSUPPORTED", -6: "OC_ERR_NONFINITE"}
 OC_PERIODIC, OC_BOUNDED = 0, 1
+OC_RECTILINEAR, OC_LATLON = 0, 1
+OC_NONHYDROSTATIC, OC_HYDROSTATIC = 0, 1
+BARO_FIELDS = {"eta": 16, "U": 17, "V": 18, "GU": 19, "GV": 20}
 OC_FP64, OC_FP32_MIXED = 0, 1
 ADVECTION = {"none": 0, "weno5z": 1, "weno5_linear": 2}
 OC_F32, OC_F64 = 0, 1
@@ -25,7 +28,8 @@ OC_NDIAG = 8
 EXPORTS = ("oc_last_error", "oc_grid_create", "oc_grid_destroy", "oc_model_workspace_size",
            "oc_model_create", "oc_model_destroy", "oc_set_state", "oc_get_state",
            "oc_tendencies", "oc_get_tendency", "oc_pressure_solve", "oc_get_pressure",
-           "oc_rk3_step", "oc_diagnostics", "oc_profile", "oc_profile_read")
+           "oc_rk3_step", "oc_diagnostics", "oc_profile", "oc_profile_read",
+           "oc_free_surface_substeps")
 OC_NPROF = 8
 PROF_CLASSES = ("tendency", "fft_x_fwd", "fft_y_fwd", "z_solve", "fft_y_inv", "fft_x_inv",
                 "project", "halo")
@@ -36,17 +40,20 @@ class GridDesc(ctypes.Structure):
                 ("topology_z", ctypes.c_int32),
                 ("x0", ctypes.c_double), ("lx", ctypes.c_double),
                 ("y0", ctypes.c_double), ("ly", ctypes.c_double),
-                ("z0", ctypes.c_double), ("lz", ctypes.c_double)]
+                ("z0", ctypes.c_double), ("lz", ctypes.c_double),
+                ("coord", ctypes.c_int32), ("radius", ctypes.c_double)]
 
 
 class ModelDesc(ctypes.Structure):
-    _fields_ = [("precision", ctypes.c_int32), ("advection", ctypes.c_int32),
+    _fields_ = [("kind", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("advection", ctypes.c_int32),
                 ("weno_eps", ctypes.c_double), ("weno_q", ctypes.c_int32),
                 ("ntracers", ctypes.c_int32), ("buoyancy", ctypes.c_int32),
                 ("f", ctypes.c_double), ("g", ctypes.c_double), ("alpha", ctypes.c_double),
                 ("beta", ctypes.c_double), ("t_ref", ctypes.c_double), ("s_ref", ctypes.c_double),
                 ("nu", ctypes.c_double), ("kappa", ctypes.c_double),
-                ("top_flux", ctypes.c_double * OC_MAX_TRACERS)]
+                ("top_flux", ctypes.c_double * OC_MAX_TRACERS),
+                ("depth", ctypes.c_double), ("omega", ctypes.c_double)]
 
 
 class OcError(RuntimeError):
@@ -83,6 +90,7 @@ def load_library(path=_LIB_PATH):
         "oc_diagnostics": [vp, ctypes.POINTER(ctypes.c_double), vp],
         "oc_profile": [vp, i32],
         "oc_profile_read": [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)],
+        "oc_free_surface_substeps": [vp, ctypes.c_double, i32, i32, ctypes.POINTER(ctypes.c_double), vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -113,21 +121,31 @@ class Model:
         self.ph = ph
         self.device = torch.device(device)
         self.precision = precision
+        self.hydrostatic = getattr(ph, "kind", "nonhydrostatic") == "hydrostatic"
         self.fields = ("u", "v", "w") + tuple(ph.tracers)
-        gd = GridDesc(ph.nx, ph.ny, ph.nz, OC_BOUNDED if ph.z_bounded else OC_PERIODIC,
-                      ph.x0, ph.lx, ph.y0, ph.ly, ph.z0, ph.lz)
         md = ModelDesc()
+        if self.hydrostatic:
+            gd = GridDesc(ph.nx, ph.ny, ph.nz, OC_BOUNDED, ph.lon0, ph.lon_extent, ph.lat0,
+                          ph.lat_extent, -ph.depth, ph.depth, OC_LATLON, ph.radius)
+            md.kind, md.depth, md.omega = OC_HYDROSTATIC, ph.depth, ph.omega
+            md.f = 0.0
+        else:
+            gd = GridDesc(ph.nx, ph.ny, ph.nz, OC_BOUNDED if ph.z_bounded else OC_PERIODIC,
+                          ph.x0, ph.lx, ph.y0, ph.ly, ph.z0, ph.lz, OC_RECTILINEAR, 0.0)
+            md.kind = OC_NONHYDROSTATIC
+            md.f = ph.f
         md.precision = OC_FP64 if precision == "fp64" else OC_FP32_MIXED
         md.advection = ADVECTION[ph.advection]
         md.weno_eps = ph.weno_eps
         md.weno_q = ph.weno_q
         md.ntracers = len(ph.tracers)
         md.buoyancy = 1 if ph.buoyancy else 0
-        md.f, md.g, md.alpha, md.beta = ph.f, ph.g, ph.alpha, ph.beta
+        md.g, md.alpha, md.beta = ph.g, ph.alpha, ph.beta
         md.t_ref, md.s_ref = ph.t_ref, ph.s_ref
         md.nu, md.kappa = ph.nu, ph.kappa
+        top = getattr(ph, "top_flux", {})
         for q, name in enumerate(ph.tracers):
-            md.top_flux[q] = ph.top_flux.get(name, 0.0)
+            md.top_flux[q] = top.get(name, 0.0)
         self._gd, self._md = gd, md
         self._grid = ctypes.c_void_p()
         _check(lib.oc_grid_create(ctypes.byref(gd), ctypes.byref(self._grid)))
@@ -151,11 +169,18 @@ class Model:
 
     # -- helpers -----------------------------------------------------------
     def field_id(self, name):
+        if name in BARO_FIELDS:
+            return BARO_FIELDS[name]
         return self.fields.index(name)
 
     def shape_of(self, name):
-        nzf = self.ph.nz + 1 if (name == "w" and self.ph.z_bounded) else self.ph.nz
-        return (nzf, self.ph.ny, self.ph.nx)
+        ph = self.ph
+        if name in BARO_FIELDS:
+            return (1, ph.ny + (1 if name in ("V", "GV") else 0), ph.nx)
+        zb = True if self.hydrostatic else ph.z_bounded
+        nzf = ph.nz + 1 if (name == "w" and zb) else ph.nz
+        nyf = ph.ny + 1 if (name == "v" and self.hydrostatic) else ph.ny
+        return (nzf, nyf, ph.nx)
 
     def _io(self, fn, name, buf):
         """Call a set/get entry point with a numpy (host) or torch array."""
@@ -228,3 +253,10 @@ class Model:
         n = (ctypes.c_int64 * OC_NPROF)()
         _check(_lib.oc_profile_read(self._model, ms, n))
         return {c: (ms[i], n[i]) for i, c in enumerate(PROF_CLASSES)}
+
+    def free_surface_substeps(self, dt, N, weights):
+        w = np.ascontiguousarray(weights, dtype=np.float64)
+        _check(_lib.oc_free_surface_substeps(self._model, ctypes.c_double(dt), ctypes.c_int32(N),
+                                             ctypes.c_int32(len(w)),
+                                             w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                             _stream()))

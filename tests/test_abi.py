@@ -33,12 +33,12 @@ def test_library_exports_every_declared_symbol():
 def test_grid_validation_errors():
     lib = oc.load_library()
     g = ctypes.c_void_p()
-    bad = oc.GridDesc(100, 32, 32, oc.OC_PERIODIC, 0, 1, 0, 1, 0, 1)
+    bad = oc.GridDesc(100, 32, 32, oc.OC_PERIODIC, 0, 1, 0, 1, 0, 1, oc.OC_RECTILINEAR, 0.0)
     assert lib.oc_grid_create(ctypes.byref(bad), ctypes.byref(g)) == -5
     assert b"unsupported" in lib.oc_last_error()
-    bad = oc.GridDesc(32, 32, 32, 7, 0, 1, 0, 1, 0, 1)
+    bad = oc.GridDesc(32, 32, 32, 7, 0, 1, 0, 1, 0, 1, oc.OC_RECTILINEAR, 0.0)
     assert lib.oc_grid_create(ctypes.byref(bad), ctypes.byref(g)) == -1
-    bad = oc.GridDesc(32, 32, 32, oc.OC_BOUNDED, 0, -1, 0, 1, 0, 1)
+    bad = oc.GridDesc(32, 32, 32, oc.OC_BOUNDED, 0, -1, 0, 1, 0, 1, oc.OC_RECTILINEAR, 0.0)
     assert lib.oc_grid_create(ctypes.byref(bad), ctypes.byref(g)) == -1
     assert lib.oc_grid_create(None, ctypes.byref(g)) == -1
 
@@ -46,7 +46,7 @@ def test_grid_validation_errors():
 def test_workspace_size_and_model_validation():
     lib = oc.load_library()
     g = ctypes.c_void_p()
-    gd = oc.GridDesc(32, 32, 16, oc.OC_BOUNDED, 0, 64, 0, 64, -16, 16)
+    gd = oc.GridDesc(32, 32, 16, oc.OC_BOUNDED, 0, 64, 0, 64, -16, 16, oc.OC_RECTILINEAR, 0.0)
     assert lib.oc_grid_create(ctypes.byref(gd), ctypes.byref(g)) == 0
     md = oc.ModelDesc()
     md.precision, md.advection, md.weno_eps, md.weno_q = oc.OC_FP32_MIXED, 1, 1e-15, 2
@@ -67,3 +67,25 @@ def test_workspace_size_and_model_validation():
     m = ctypes.c_void_p()
     assert lib.oc_model_create(g, ctypes.byref(md), None, 0, ctypes.byref(m)) == -1
     assert lib.oc_grid_destroy(g) == 0
+
+
+def test_hydrostatic_pairing_is_validated():
+    lib = oc.load_library()
+    g = ctypes.c_void_p()
+    # a lat-lon grid: any multiple of 8 (no FFT constraint), walls in z
+    gd = oc.GridDesc(1440, 560, 50, oc.OC_BOUNDED, 0, 360, -70, 140, -3000, 3000, oc.OC_LATLON,
+                     6.371e6)
+    assert lib.oc_grid_create(ctypes.byref(gd), ctypes.byref(g)) == 0
+    md = oc.ModelDesc()
+    md.kind, md.precision, md.advection, md.weno_eps, md.weno_q = oc.OC_HYDROSTATIC, 1, 1, 1e-15, 2
+    md.ntracers, md.buoyancy, md.depth = 2, 1, 3000.0
+    nbytes = ctypes.c_uint64()
+    assert lib.oc_model_workspace_size(g, ctypes.byref(md), ctypes.byref(nbytes)) == 0
+    md.kind = oc.OC_NONHYDROSTATIC   # needs a rectilinear grid
+    assert lib.oc_model_workspace_size(g, ctypes.byref(md), ctypes.byref(nbytes)) == -5
+    md.kind, md.depth = oc.OC_HYDROSTATIC, 0.0
+    assert lib.oc_model_workspace_size(g, ctypes.byref(md), ctypes.byref(nbytes)) == -1
+    assert lib.oc_grid_destroy(g) == 0
+    bad = oc.GridDesc(1440, 560, 50, oc.OC_BOUNDED, 0, 360, -70, 170, -3000, 3000, oc.OC_LATLON,
+                      6.371e6)
+    assert lib.oc_grid_create(ctypes.byref(bad), ctypes.byref(g)) == -1
