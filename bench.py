@@ -21,7 +21,37 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
-FP32_BYTES_PER_CELL_STAGE = {0: 60, 1: 80, 2: 60}   # 5 fields: read X (+G), write X~ (+G)
+# FP32 vector peak without packed math: 256 CUs x 4 SIMDs x 16 lanes x 2 flops
+# (FMA) x 2.4 GHz.  Packed FP32 instructions are disabled in this build.
+FP32_VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+
+# Algorithmic floating-point operations of one cell-substage of the
+# tendency + RK3 kernel (5 prognostic fields), counting + - * / each as one:
+FLOPS_PER_CELL_STAGE = {
+    "weno5z_flux": 15 * 79,        # 15 face fluxes: candidates 18, indicators 36,
+                                   # tau 1, weights 15, normalisation 8, U*W 1
+    "diffusive_flux": 15 * 3,
+    "advecting_velocity": 9 * 5,   # fourth-order interpolation, momentum fluxes
+    "flux_divergence": 15 * 3,
+    "coriolis": 2 * 5,
+    "buoyancy": 9,
+    "rk3_combine": 5 * 4,
+    "tracer_offset": 2 * 7,
+}
+COUNTERS = os.path.join(ROOT, "profiles", "tendency_rk3_fp32_256cubed_counters.json")
+TENDENCY_SRC = os.path.join(ROOT, "paper_2502_14148_amd", "csrc", "tendency.hip")
+
+
+def measured_traffic():
+    """HBM bytes per tendency launch from the committed rocprofv3 counter
+    record, or None if the kernel source changed since it was taken."""
+    import hashlib
+    try:
+        rec = json.load(open(COUNTERS))
+        src = hashlib.sha256(open(TENDENCY_SRC, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    return rec["traffic_bytes_per_launch"] if rec.get("source_sha256") == src else None
 
 
 def algorithmic_tendency_bytes(ncells, nfields, esz, steps):
@@ -101,7 +131,8 @@ def main():
         src = torch.ones(128 * 1024 * 1024, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
-        dst.copy_(src)
+        dst.copy_(src)                      # runtime copy kernel
+        torch.mul(src, 1.0, out=dst)        # elementwise copy kernel
         torch.cuda.synchronize()
         del src, dst
 
@@ -124,13 +155,20 @@ def main():
 
     value = ncells * a.steps / (ms32 / 1e3)
     t_tend_ms, n_tend = prof32["tendency"]
-    tbytes = algorithmic_tendency_bytes(ncells, nf, 4, a.steps)
-    achieved = tbytes / (t_tend_ms / 1e3) / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "tendency_rk3 (FP32)",
-                "avg_launch_ms": t_tend_ms / max(n_tend, 1),
-                "algorithmic_bytes_per_launch": tbytes / max(n_tend, 1)}
+    t_launch = t_tend_ms / 1e3 / max(n_tend, 1)
+    tbytes = algorithmic_tendency_bytes(ncells, nf, 4, a.steps) / max(n_tend, 1)
+    flops = sum(FLOPS_PER_CELL_STAGE.values()) * ncells
+    achieved_tf = flops / t_launch / 1e12
+    achieved_gbs = tbytes / t_launch / 1e9
+    roofline = {"bound": "alu", "achieved": round(achieved_tf, 2), "peak": FP32_VALU_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved_tf / FP32_VALU_PEAK_TFLOPS, 4),
+                "traffic": measured_traffic(),
+                "kernel": "tendency_rk3 (FP32, WENO5-Z, 256^3)",
+                "avg_launch_ms": t_launch * 1e3,
+                "algorithmic_flops_per_launch": flops,
+                "algorithmic_bytes_per_launch": tbytes,
+                "hbm": {"achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(achieved_gbs / HBM_PEAK_GBS, 4)}}
     out = {
         "metric": "cell-steps/s (WENO5 RK3 step, 256^3) + tendency-kernel HBM GB/s vs peak",
         "value": value, "unit": "cell-steps/s", "n_gpus": 1, "steps": a.steps,
