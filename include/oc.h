@@ -108,6 +108,8 @@ typedef struct {
   double top_flux[OC_MAX_TRACERS]; /* upward tracer flux through the top wall */
   double depth;             /* OC_HYDROSTATIC: resting depth H (flat bottom) */
   double omega;             /* OC_HYDROSTATIC: planetary rotation rate */
+  int32_t closure;          /* 1: reserve workspace for a learned closure
+                               (oc_model_set_closure) */
 } oc_model_desc;
 
 typedef struct oc_grid oc_grid;
@@ -174,9 +176,10 @@ int oc_rk3_step(oc_model* m, double dt, int32_t nsteps, void* stream);
  * double array) and launches (host int64 array). */
 enum {
   OC_PROF_TENDENCY = 0, OC_PROF_FFT_X_FWD = 1, OC_PROF_FFT_Y_FWD = 2, OC_PROF_Z_SOLVE = 3,
-  OC_PROF_FFT_Y_INV = 4, OC_PROF_FFT_X_INV = 5, OC_PROF_PROJECT = 6, OC_PROF_HALO = 7
+  OC_PROF_FFT_Y_INV = 4, OC_PROF_FFT_X_INV = 5, OC_PROF_PROJECT = 6, OC_PROF_HALO = 7,
+  OC_PROF_CLOSURE = 8
 };
-#define OC_NPROF 8
+#define OC_NPROF 9
 int oc_profile(oc_model* m, int32_t enable);
 int oc_profile_read(oc_model* m, double* ms, int64_t* launches);
 
@@ -194,6 +197,61 @@ int oc_profile_read(oc_model* m, double* ms, int64_t* launches);
  * nonhydrostatic model, OC_ERR_ARG for N < 1, M < 1, M > 4096 or NULL a. */
 int oc_free_surface_substeps(oc_model* m, double dt, int32_t N, int32_t M, const double* a,
                              void* stream);
+
+/* ---- Learned subgrid closure (an MLP trained on coarse-grained fluxes) ----
+ * The network maps the standardised 5x5x5 neighbourhood of (u, v, w, b) of a
+ * coarse cell (500 values, variable-major, offsets (dk, dj, di) in C order)
+ * through two 256-wide exact-erf GELU layers to 4 standardised vertical
+ * subgrid fluxes (tau_uw, tau_vw, tau_ww, J_bw).  GEMMs use BF16 operands
+ * with FP32 accumulation (MFMA); master weights and Adam state are FP32.
+ * Parameters are packed FP32: W1 (256 x 500, row = output) | b1 (256) |
+ * W2 (256 x 256) | b2 | W3 (4 x 256) | b3 (4): OC_MLP_NPARAM values.
+ * The paper names trainable parameterizations as a goal (introduction,
+ * conclusions); coarse-graining follows its integral-preserving regridding
+ * (finite-volume appendix). */
+#define OC_MLP_NPARAM 195076
+typedef struct oc_mlp oc_mlp;
+
+/* Device workspace for batches up to max_batch (a multiple of 32). */
+int oc_mlp_workspace_size(int32_t max_batch, uint64_t* bytes);
+/* Create on the current device over a borrowed, 256-byte aligned device
+ * workspace; parameters start at zero. */
+int oc_mlp_create(int32_t max_batch, void* workspace, uint64_t bytes, oc_mlp** out);
+int oc_mlp_destroy(oc_mlp* m);
+/* Upload (host FP32, OC_MLP_NPARAM values; OC_ERR_NONFINITE on NaN/Inf)
+ * and reset the optimiser; synchronous. */
+int oc_mlp_set_params(oc_mlp* m, const float* params, void* stream);
+int oc_mlp_get_params(oc_mlp* m, float* params, void* stream);
+/* y (device, batch x 4 FP32) = MLP(x) for x (device, batch x 500 FP32);
+ * batch a multiple of 32 up to max_batch. */
+int oc_mlp_forward(oc_mlp* m, const float* x, int32_t batch, float* y, void* stream);
+/* Gradients of the mean squared error mean((y - target)^2) over the batch
+ * (target: device, batch x 4) into grad (device, OC_MLP_NPARAM FP32, packed
+ * like the parameters); *loss (host, optional) receives the loss,
+ * synchronising the stream. */
+int oc_mlp_gradients(oc_mlp* m, const float* x, const float* target, int32_t batch, float* grad,
+                     double* loss, void* stream);
+/* One Adam step (beta = 0.9, 0.999, eps = 1e-8) with learning rate lr on
+ * the same loss; *loss (optional) as above. */
+int oc_mlp_train_step(oc_mlp* m, const float* x, const float* target, int32_t batch, float lr,
+                      double* loss, void* stream);
+
+/* Attach (net != NULL) or detach (net == NULL) the learned closure of a
+ * nonhydrostatic model created with closure = 1 (walls in z; tracers 0, 1 =
+ * T, S).  Every substage then gathers the standardised features of all
+ * cells, runs the network (the model's cell count must be a multiple of 32
+ * and at most the network's max_batch) and adds the flux divergence of the
+ * predicted vertical fluxes -d/dz(F) to G: u and v take F at their (x or y
+ * face, z face) edges as the mean of the four adjacent centres, T the mean
+ * of the two centres about a z face (as J_b / (g alpha)), w the difference
+ * of tau_ww across its face; wall fluxes are zero, so column integrals are
+ * conserved.  stats (host, 16 doubles): input mean and std of (u, v, w, b),
+ * output mean and std of (tau_uw, tau_vw, tau_ww, J_b).  The model's
+ * constant-diffusivity closure stays on.  A network whose parameters are not
+ * all finite is refused with OC_ERR_NONFINITE and the model keeps running
+ * without it (the diffusive fallback).  The network must outlive the
+ * attachment. */
+int oc_model_set_closure(oc_model* m, oc_mlp* net, const double* stats, void* stream);
 
 /* FP64 diagnostics of the current state, synchronous; out (host) receives
  * OC_NDIAG doubles: [0] max|div u| * min(spacing), [1] max|u|, [2] max|v|,

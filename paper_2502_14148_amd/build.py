@@ -26,7 +26,8 @@ FLAGS = [
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]
 
-SOURCES = ["api.hip", "stencil.hip", "poisson.hip", "tendency.hip", "barotropic.hip"]
+SOURCES = ["api.hip", "stencil.hip", "poisson.hip", "tendency.hip", "barotropic.hip", "mlp.hip",
+           "closure_api.hip"]
 
 
 def _compile(src, defines=(), build_dir=None):

@@ -66,6 +66,10 @@ struct oc_model {
   double* vbar;
   double* metric;        // len_u | dx_u | len_v | dy_v | area
   int bcur;
+  // learned closure: network, statistics, tendency buffers (u, v, w, T)
+  oc_mlp* net;
+  ClosureStats cst;
+  void* gc[4];
   // per-kernel-class event timing
   int prof_on;
   std::vector<hipEvent_t> ev_pool;
@@ -88,6 +92,7 @@ struct Layout {
   uint64_t state[2][MAXF], G[MAXF];
   uint64_t spec, p, twx, twy, twz, dctz, lamx, lamy, lamz, staging, diag;
   uint64_t baro[11], metric;
+  uint64_t gc[4];
   uint64_t total;
 };
 
@@ -127,6 +132,8 @@ Layout make_layout(const oc_grid_desc& g, const oc_model_desc& m) {
     for (int q = 0; q < 11; ++q) { L.baro[q] = off; off += a2; }
     L.metric = off; off += align256((uint64_t)(5 * (g.ny + 1)) * 8);
   }
+  if (m.closure)
+    for (int q = 0; q < 4; ++q) { L.gc[q] = off; off += fb; }
   L.staging = off; off += align256((uint64_t)(g.nz + 1) * (g.ny + 1) * g.nx * 8);
   L.diag = off; off += align256((uint64_t)DIAG_BLOCKS * DIAG_PARTS * 8);
   L.total = off;
@@ -344,6 +351,20 @@ int tendency_call(oc_model* m, int in, int out, int stage, double dt, int combin
     fs.in[q] = (q < m->nf) ? (const T*)m->state[in][q] : nullptr;
     fs.out[q] = (q < m->nf) ? (T*)m->state[out][q] : nullptr;
     fs.G[q] = (q < m->nf) ? (T*)m->G[q] : nullptr;
+  }
+  for (int q = 0; q < 4; ++q) fs.closure[q] = m->net ? (const T*)m->gc[q] : nullptr;
+  if (m->net) {
+    // learned closure of the current state: features, network, flux divergence
+    ProfScope pc(m, OC_PROF_CLOSURE, s);
+    const T* const* x = fs.in;
+    OC_CHECK_HIP(launch_closure_features<T>(m->dims, x[0], x[1], x[2], x[3], x[4], m->cst,
+                                            mlp_input(m->net), s));
+    const int ncell = m->dims.nx * m->dims.ny * m->dims.nz;
+    int rc = mlp_run_forward(m->net, ncell, s);
+    if (rc) return rc;
+    OC_CHECK_HIP(launch_closure_apply<T>(m->dims, mlp_output(m->net), m->cst, 1.0 / m->dz,
+                                         (T*)m->gc[0], (T*)m->gc[1], (T*)m->gc[2], (T*)m->gc[3],
+                                         s));
   }
   TendParams<T> p = tend_params<T>(m);
   ProfScope ps(m, OC_PROF_TENDENCY, s);
@@ -681,6 +702,8 @@ int oc_model_create(const oc_grid* g, const oc_model_desc* md, void* workspace,
   m->vbar = (double*)(m->ws + L.baro[10]);
   m->metric = (double*)(m->ws + L.metric);
   m->bcur = 0;
+  m->net = nullptr;
+  for (int q = 0; q < 4; ++q) m->gc[q] = md->closure ? (void*)(m->ws + L.gc[q]) : nullptr;
 
   hipError_t e = hipMemset(m->ws, 0, L.total);
   if (md->kind == OC_NONHYDROSTATIC) {
@@ -854,6 +877,46 @@ int oc_free_surface_substeps(oc_model* m, double dt, int32_t N, int32_t M, const
   hipStream_t s = (hipStream_t)stream;
   return (m->esz == 8) ? free_surface_call<double>(m, dt, N, M, a, s)
                        : free_surface_call<float>(m, dt, N, M, a, s);
+}
+
+int oc_model_set_closure(oc_model* m, oc_mlp* net, const double* stats, void* stream) {
+  if (!m) { set_error("model is NULL"); return OC_ERR_ARG; }
+  if (!net) { m->net = nullptr; return OC_OK; }
+  if (m->kind != OC_NONHYDROSTATIC || !m->dims.zb || !m->md.buoyancy || !m->gc[0]) {
+    set_error("the closure needs a wall-bounded nonhydrostatic model with T, S created with closure = 1");
+    return OC_ERR_UNSUPPORTED;
+  }
+  if (!stats) { set_error("stats is NULL"); return OC_ERR_ARG; }
+  const long ncell = (long)m->dims.nx * m->dims.ny * m->dims.nz;
+  if (ncell % 32 || ncell > mlp_max_batch(net)) {
+    set_error("the network's max_batch (%d) must cover the model's %ld cells", mlp_max_batch(net), ncell);
+    return OC_ERR_ARG;
+  }
+  for (int q = 0; q < 4; ++q)
+    if (!(stats[4 + q] > 0) || !(stats[12 + q] > 0)) { set_error("standard deviations must be > 0"); return OC_ERR_ARG; }
+  hipStream_t s = (hipStream_t)stream;
+  const int fin = mlp_params_finite(net, s);
+  if (fin < 0) return fin;
+  if (!fin) {
+    m->net = nullptr;
+    set_error("network parameters are not finite: the diffusive closure alone stays in use");
+    return OC_ERR_NONFINITE;
+  }
+  ClosureStats c;
+  for (int q = 0; q < 4; ++q) {
+    c.in_mean[q] = (float)stats[q];
+    c.in_std[q] = (float)stats[4 + q];
+    c.out_mean[q] = (float)stats[8 + q];
+    c.out_std[q] = (float)stats[12 + q];
+  }
+  c.g_alpha = (float)(m->md.g * m->md.alpha);
+  c.g_beta = (float)(m->md.g * m->md.beta);
+  c.t_ref = (float)(m->md.t_ref - m->offset[OC_TRACER0]);
+  c.s_ref = (float)(m->md.s_ref - m->offset[OC_TRACER0 + 1]);
+  c.inv_galpha = (float)(1.0 / (m->md.g * m->md.alpha));
+  m->cst = c;
+  m->net = net;
+  return OC_OK;
 }
 
 }  // extern "C"

@@ -1,0 +1,334 @@
+// MLP subgrid closure on gfx950: BF16 MFMA GEMMs with FP32 accumulation
+// for the forward and backward passes, fused bias/GELU epilogues, loss and
+// bias-gradient reductions, Adam on FP32 master weights, and the gather of
+// the standardised 5x5x5 (u, v, w, b) neighbourhood of every coarse cell.
+//
+// Network: 500 -> 256 -> 256 -> 4 with exact-erf GELU.  On the device the
+// input width is padded to 512 and the output width to 32 with zero weights
+// so every GEMM dimension is a multiple of the 32-deep MFMA k step.
+#include "oc_internal.h"
+
+namespace oc {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ void mlp_write_bf16(const MlpParams& p, int t, float w) {
+  // master layout: W1 (256 x 500) | b1 | W2 (256 x 256) | b2 | W3 (4 x 256) | b3
+  if (t < MLP_OFF_B1) {
+    const int r = t / 500, c = t % 500;
+    p.W1b[r * 512 + c] = (__bf16)w;
+  } else if (t >= MLP_OFF_W2 && t < MLP_OFF_B2) {
+    p.W2b[t - MLP_OFF_W2] = (__bf16)w;
+  } else if (t >= MLP_OFF_W3 && t < MLP_OFF_B3) {
+    p.W3b[t - MLP_OFF_W3] = (__bf16)w;
+  }
+}
+
+
+namespace {
+
+constexpr int BM = 64, BN = 64, BK = 32, LDP = BK + 8;  // LDS rows padded by 8 bf16
+
+__device__ inline float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+__device__ inline float gelu_prime(float z) {
+  return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) +
+         z * __expf(-0.5f * z * z) * 0.39894228040143268f;
+}
+
+// C[m][n] = sum_k A[m][k] B[k][n].  transA = 0: A[m][k] at A[m*lda + k];
+// 1: at A[k*lda + m].  transB = 0: B[k][n] at B[k*ldb + n]; 1: at B[n*ldb + k].
+// Tiles are staged in LDS with k contiguous, the order the MFMA operands
+// need: lane l holds 8 consecutive k of row (or column) l % 16, k block l / 16.
+__global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) {
+  __shared__ __bf16 As[BM][LDP];
+  __shared__ __bf16 Bs[BN][LDP];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  const int wm = wv >> 1, wn = wv & 1;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  f32x4 acc[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  for (int k0 = 0; k0 < g.K; k0 += BK) {
+    // ---- stage A (BM x BK) and B (BN x BK)
+    if (!g.transA) {
+      const int r = tid >> 2, ks = (tid & 3) * 8;
+      const int m = m0 + r;
+      bf16x8 v;
+      if (m < g.M) v = *(const bf16x8*)(g.A + (long)m * g.lda + k0 + ks);
+      else for (int e = 0; e < 8; ++e) v[e] = (__bf16)0.0f;
+      *(bf16x8*)&As[r][ks] = v;
+    } else {
+      const int kk = tid >> 3, ms = (tid & 7) * 8;
+      const __bf16* src = g.A + (long)(k0 + kk) * g.lda + m0 + ms;
+      for (int e = 0; e < 8; ++e) As[ms + e][kk] = (m0 + ms + e < g.M) ? src[e] : (__bf16)0.0f;
+    }
+    if (g.transB) {
+      const int r = tid >> 2, ks = (tid & 3) * 8;
+      const int n = n0 + r;
+      bf16x8 v;
+      if (n < g.N) v = *(const bf16x8*)(g.B + (long)n * g.ldb + k0 + ks);
+      else for (int e = 0; e < 8; ++e) v[e] = (__bf16)0.0f;
+      *(bf16x8*)&Bs[r][ks] = v;
+    } else {
+      const int kk = tid >> 3, ns = (tid & 7) * 8;
+      const __bf16* src = g.B + (long)(k0 + kk) * g.ldb + n0 + ns;
+      for (int e = 0; e < 8; ++e) Bs[ns + e][kk] = (n0 + ns + e < g.N) ? src[e] : (__bf16)0.0f;
+    }
+    __syncthreads();
+    // ---- 2 x 2 MFMA tiles of 16 x 16 per wave
+    bf16x8 a[2], b[2];
+    for (int i = 0; i < 2; ++i)
+      a[i] = *(const bf16x8*)&As[wm * 32 + i * 16 + (lane & 15)][8 * (lane >> 4)];
+    for (int j = 0; j < 2; ++j)
+      b[j] = *(const bf16x8*)&Bs[wn * 32 + j * 16 + (lane & 15)][8 * (lane >> 4)];
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    __syncthreads();
+  }
+
+  // ---- epilogue: lane holds rows 4*(lane/16) + e of column lane % 16
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) {
+      const int n = n0 + wn * 32 + j * 16 + (lane & 15);
+      if (n >= g.N) continue;
+      for (int e = 0; e < 4; ++e) {
+        const int m = m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + e;
+        if (m >= g.M) continue;
+        const float v = acc[i][j][e];
+        const long o = (long)m * g.ldc + n;
+        switch (g.epi) {
+          case EPI_STORE:
+            g.C[o] = v;
+            break;
+          case EPI_BIAS:
+            g.C[o] = v + g.bias[n];
+            break;
+          case EPI_BIAS_GELU: {
+            const float z = v + g.bias[n];
+            g.C[o] = z;                                   // pre-activation (for backward)
+            g.H[(long)m * g.ldh + n] = (__bf16)gelu(z);    // activation (next layer)
+            break;
+          }
+          case EPI_GELU_BWD: {
+            const float dz = v * gelu_prime(g.Z[o]);
+            g.C[o] = dz;
+            g.H[(long)m * g.ldh + n] = (__bf16)dz;
+            break;
+          }
+        }
+      }
+    }
+}
+
+// dY = 2 (Y - T) / (B * 4) on the 4 real outputs (FP32 and BF16, padded
+// columns zero); per-block partial sums of the squared error.
+__global__ void __launch_bounds__(256) loss_grad_kernel(const float* Y, int ldy, const float* T,
+                                                        int B, float* dY, __bf16* dYb, int ldd,
+                                                        double* partial) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  const float scale = 2.0f / (float)(B * 4);
+  for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < (long)B * ldd;
+       t += (long)gridDim.x * blockDim.x) {
+    const int r = (int)(t / ldd), c = (int)(t % ldd);
+    float d = 0.f;
+    if (c < 4) {
+      const float e = Y[(long)r * ldy + c] - T[(long)r * 4 + c];
+      acc += (double)e * e;
+      d = scale * e;
+    }
+    dY[t] = d;
+    dYb[t] = (__bf16)d;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+// column sums of a (rows x cols) FP32 matrix into out (bias gradients)
+__global__ void colsum_kernel(const float* a, int rows, int cols, int lda, float* out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= cols) return;
+  float s = 0.f;
+  for (int r = 0; r < rows; ++r) s += a[(long)r * lda + c];
+  out[c] = s;
+}
+
+// FP32 features (B x 500) -> BF16 (B x 512), zero padding
+__global__ void features_to_bf16_kernel(const float* x, int B, __bf16* xb) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long)B * 512) return;
+  const int r = (int)(t / 512), c = (int)(t % 512);
+  xb[t] = (c < 500) ? (__bf16)x[(long)r * 500 + c] : (__bf16)0.0f;
+}
+
+// Adam (Kingma & Ba) on the FP32 master parameters; refreshes the padded
+// BF16 copies used by the GEMMs.
+__global__ void adam_kernel(MlpParams p, const float* grad, float* m1, float* m2, int n,
+                            float lr, float b1, float b2, float eps, float c1, float c2) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const float g = grad[t];
+  const float mm = b1 * m1[t] + (1.f - b1) * g;
+  const float vv = b2 * m2[t] + (1.f - b2) * g * g;
+  m1[t] = mm;
+  m2[t] = vv;
+  const float w = p.master[t] - lr * (mm / c1) / (sqrtf(vv / c2) + eps);
+  p.master[t] = w;
+  mlp_write_bf16(p, t, w);
+}
+
+__global__ void refresh_bf16_kernel(MlpParams p, int n) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) mlp_write_bf16(p, t, p.master[t]);
+}
+
+}  // namespace
+
+hipError_t launch_gemm_bf16(const GemmArgs& g, hipStream_t s) {
+  dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM);
+  hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(256), 0, s, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_loss_grad(const float* Y, int ldy, const float* T, int B, float* dY, __bf16* dYb,
+                            int ldd, double* partial, int nblocks, hipStream_t s) {
+  hipLaunchKernelGGL(loss_grad_kernel, dim3(nblocks), dim3(256), 0, s, Y, ldy, T, B, dY, dYb, ldd,
+                     partial);
+  return hipGetLastError();
+}
+
+hipError_t launch_colsum(const float* a, int rows, int cols, int lda, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(colsum_kernel, dim3((cols + 127) / 128), dim3(128), 0, s, a, rows, cols, lda,
+                     out);
+  return hipGetLastError();
+}
+
+hipError_t launch_features_to_bf16(const float* x, int B, __bf16* xb, hipStream_t s) {
+  const long n = (long)B * 512;
+  hipLaunchKernelGGL(features_to_bf16_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                     x, B, xb);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam(const MlpParams& p, const float* grad, float* m1, float* m2, int n, float lr,
+                       int step, hipStream_t s) {
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
+  hipLaunchKernelGGL(adam_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, grad, m1, m2, n, lr,
+                     b1, b2, eps, c1, c2);
+  return hipGetLastError();
+}
+
+hipError_t launch_refresh_bf16(const MlpParams& p, int n, hipStream_t s) {
+  hipLaunchKernelGGL(refresh_bf16_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Closure inside the model: features from the halo-padded state, and the
+// conservative flux divergence of the predicted vertical fluxes.
+// ---------------------------------------------------------------------------
+
+// xb[cell][f], f = var * 125 + (dk+2)*25 + (dj+2)*5 + (di+2), var = u, v, w, b
+template <class T>
+__global__ void __launch_bounds__(256) closure_features_kernel(Dims d, const T* u, const T* v,
+                                                               const T* w, const T* tt,
+                                                               const T* ss, ClosureStats st,
+                                                               __bf16* xb) {
+  const long ncell = (long)d.nx * d.ny * d.nz;
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ncell * 512) return;
+  const long cell = t >> 9;
+  const int f = (int)(t & 511);
+  if (f >= 500) { xb[t] = (__bf16)0.0f; return; }
+  const int i = (int)(cell % d.nx);
+  const int j = (int)((cell / d.nx) % d.ny);
+  const int k = (int)(cell / ((long)d.nx * d.ny));
+  const int var = f / 125, o = f % 125;
+  const int dk = o / 25 - 2, dj = (o / 5) % 5 - 2, di = o % 5 - 2;
+  const long p = pidx(d, i + di, j + dj, k + dk);
+  float x;
+  if (var == 0) x = (float)u[p];
+  else if (var == 1) x = (float)v[p];
+  else if (var == 2) x = (float)w[p];
+  else x = st.g_alpha * ((float)tt[p] - st.t_ref) - st.g_beta * ((float)ss[p] - st.s_ref);
+  xb[t] = (__bf16)((x - st.in_mean[var]) / st.in_std[var]);
+}
+
+// Physical fluxes F_q = y_q std_q + mean_q at cell centres; u takes the
+// flux at (x face, z face) as the mean of the four adjacent centres, v the
+// same in y, tracers the mean of the two centres about each z face (J_b
+// turned into a temperature flux), w the difference of tau_ww across its
+// face.  Wall fluxes are zero.
+template <class T>
+__global__ void __launch_bounds__(256) closure_apply_kernel(Dims d, const float* y, ClosureStats st,
+                                                            double rdz, T* gu, T* gv, T* gw,
+                                                            T* gt) {
+  const long ncell = (long)d.nx * d.ny * d.nz;
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ncell) return;
+  const int i = (int)(t % d.nx);
+  const int j = (int)((t / d.nx) % d.ny);
+  const int k = (int)(t / ((long)d.nx * d.ny));
+  auto F = [&](int q, int ii, int jj, int kk) -> float {
+    ii = (ii + d.nx) % d.nx;
+    jj = (jj + d.ny) % d.ny;
+    const long c = ((long)kk * d.ny + jj) * d.nx + ii;
+    return y[c * 4 + q] * st.out_std[q] + st.out_mean[q];
+  };
+  // flux through the z face kk (0..nz) of quantity q averaged over x or y
+  auto zface = [&](int q, int ax, int kk) -> float {
+    if (kk <= 0 || kk >= d.nz) return 0.f;
+    if (ax == 0) return 0.25f * (F(q, i - 1, j, kk - 1) + F(q, i, j, kk - 1) + F(q, i - 1, j, kk) +
+                                 F(q, i, j, kk));
+    if (ax == 1) return 0.25f * (F(q, i, j - 1, kk - 1) + F(q, i, j, kk - 1) + F(q, i, j - 1, kk) +
+                                 F(q, i, j, kk));
+    return 0.5f * (F(q, i, j, kk - 1) + F(q, i, j, kk));
+  };
+  const long p = pidx(d, i, j, k);
+  const float rz = (float)rdz;
+  gu[p] = (T)(-(zface(0, 0, k + 1) - zface(0, 0, k)) * rz);
+  gv[p] = (T)(-(zface(1, 1, k + 1) - zface(1, 1, k)) * rz);
+  gt[p] = (T)(-(zface(3, 2, k + 1) - zface(3, 2, k)) * rz * st.inv_galpha);
+  gw[p] = (k == 0) ? (T)0 : (T)(-(F(2, i, j, k) - F(2, i, j, k - 1)) * rz);
+}
+
+template <class T>
+hipError_t launch_closure_features(const Dims& d, const T* u, const T* v, const T* w, const T* t,
+                                   const T* s, ClosureStats st, __bf16* xb, hipStream_t stream) {
+  const long n = (long)d.nx * d.ny * d.nz * 512;
+  hipLaunchKernelGGL(closure_features_kernel<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                     stream, d, u, v, w, t, s, st, xb);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_closure_apply(const Dims& d, const float* y, ClosureStats st, double rdz, T* gu,
+                                T* gv, T* gw, T* gt, hipStream_t stream) {
+  const long n = (long)d.nx * d.ny * d.nz;
+  hipLaunchKernelGGL(closure_apply_kernel<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                     stream, d, y, st, rdz, gu, gv, gw, gt);
+  return hipGetLastError();
+}
+
+template hipError_t launch_closure_features<float>(const Dims&, const float*, const float*,
+                                                   const float*, const float*, const float*,
+                                                   ClosureStats, __bf16*, hipStream_t);
+template hipError_t launch_closure_features<double>(const Dims&, const double*, const double*,
+                                                    const double*, const double*, const double*,
+                                                    ClosureStats, __bf16*, hipStream_t);
+template hipError_t launch_closure_apply<float>(const Dims&, const float*, ClosureStats, double,
+                                                float*, float*, float*, float*, hipStream_t);
+template hipError_t launch_closure_apply<double>(const Dims&, const float*, ClosureStats, double,
+                                                 double*, double*, double*, double*, hipStream_t);
+
+}  // namespace oc

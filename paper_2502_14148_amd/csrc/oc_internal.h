@@ -91,6 +91,8 @@ struct FieldSet {
   const T* in[MAXF];
   T* out[MAXF];
   T* G[MAXF];
+  const T* closure[4];   // optional learned-closure tendencies of u, v, w, tracer 0
+                         // (padded layout), added to G; null when off
 };
 
 // Spectral-solve tables and buffers (FP64).
@@ -135,6 +137,71 @@ hipError_t launch_baro_substep(const BaroBufs& b, double dtau, double gH, double
 template <class T>
 hipError_t launch_baro_correct(const Dims& d, T* f, const double* bar, int j_lo, int j_hi,
                                double dz, double depth, hipStream_t s);
+
+// ---- MLP closure (500 -> 256 -> 256 -> 4; device widths 512 and 32)
+constexpr int MLP_NIN = 500, MLP_NH = 256, MLP_NOUT = 4, MLP_KIN = 512, MLP_NOUTP = 32;
+constexpr int MLP_OFF_W1 = 0;
+constexpr int MLP_OFF_B1 = MLP_OFF_W1 + MLP_NH * MLP_NIN;
+constexpr int MLP_OFF_W2 = MLP_OFF_B1 + MLP_NH;
+constexpr int MLP_OFF_B2 = MLP_OFF_W2 + MLP_NH * MLP_NH;
+constexpr int MLP_OFF_W3 = MLP_OFF_B2 + MLP_NH;
+constexpr int MLP_OFF_B3 = MLP_OFF_W3 + MLP_NOUT * MLP_NH;
+constexpr int MLP_NPARAM = MLP_OFF_B3 + MLP_NOUT;
+
+enum { EPI_STORE = 0, EPI_BIAS = 1, EPI_BIAS_GELU = 2, EPI_GELU_BWD = 3 };
+
+struct GemmArgs {
+  const __bf16* A;
+  int lda, transA;          // transA = 0: A[m][k] at A[m*lda + k]; 1: at A[k*lda + m]
+  const __bf16* B;
+  int ldb, transB;          // transB = 0: B[k][n] at B[k*ldb + n]; 1: at B[n*ldb + k]
+  int M, N, K;              // K a multiple of 32
+  int epi;
+  float* C;
+  int ldc;
+  const float* bias;        // EPI_BIAS, EPI_BIAS_GELU
+  const float* Z;           // EPI_GELU_BWD: pre-activation, same layout as C
+  __bf16* H;                // EPI_BIAS_GELU / EPI_GELU_BWD: BF16 copy of the result
+  int ldh;
+};
+
+struct MlpParams {
+  float* master;            // FP32: W1 | b1 | W2 | b2 | W3 | b3
+  __bf16* W1b;              // 256 x 512 (columns >= 500 zero)
+  __bf16* W2b;              // 256 x 256
+  __bf16* W3b;              // 32 x 256 (rows >= 4 zero)
+};
+
+__device__ void mlp_write_bf16(const MlpParams& p, int t, float w);
+hipError_t launch_gemm_bf16(const GemmArgs& g, hipStream_t s);
+hipError_t launch_loss_grad(const float* Y, int ldy, const float* T, int B, float* dY, __bf16* dYb,
+                            int ldd, double* partial, int nblocks, hipStream_t s);
+hipError_t launch_colsum(const float* a, int rows, int cols, int lda, float* out, hipStream_t s);
+hipError_t launch_features_to_bf16(const float* x, int B, __bf16* xb, hipStream_t s);
+hipError_t launch_adam(const MlpParams& p, const float* grad, float* m1, float* m2, int n, float lr,
+                       int step, hipStream_t s);
+hipError_t launch_refresh_bf16(const MlpParams& p, int n, hipStream_t s);
+
+// Closure statistics: input mean/std of (u, v, w, b), output mean/std of the
+// four fluxes; buoyancy parameters to form b from the stored T, S.
+struct ClosureStats {
+  float in_mean[4], in_std[4], out_mean[4], out_std[4];
+  float g_alpha, g_beta, t_ref, s_ref;   // b = g_alpha (T - t_ref) - g_beta (S - s_ref)
+  float inv_galpha;                      // temperature flux = buoyancy flux / (g alpha)
+};
+template <class T>
+hipError_t launch_closure_features(const Dims& d, const T* u, const T* v, const T* w, const T* t,
+                                   const T* s, ClosureStats st, __bf16* xb, hipStream_t stream);
+template <class T>
+hipError_t launch_closure_apply(const Dims& d, const float* y, ClosureStats st, double rdz,
+                                T* gu, T* gv, T* gw, T* gt, hipStream_t stream);
+
+// Access to a network from the model's step (implemented in closure_api.hip).
+__bf16* mlp_input(oc_mlp* net);
+const float* mlp_output(oc_mlp* net);
+int mlp_max_batch(const oc_mlp* net);
+int mlp_run_forward(oc_mlp* net, int batch, hipStream_t s);
+int mlp_params_finite(oc_mlp* net, hipStream_t s);  // 1, 0, or a negative error
 
 // Host-side error reporting (per thread).
 void set_error(const char* fmt, ...);

@@ -363,6 +363,14 @@ tendency_zmarch(Dims d, FieldSet<T> fs, TendParams<T> P, int nbx, int nby, int n
                      (ww[3] - ww[2]) * P.rdz;
 #pragma unroll
       for (int q = 0; q < NTR; ++q) G[3 + q] += -(fzt_c[q] - fzb_c[q]) * P.rdz - P.toff[q] * divu;
+      if (fs.closure[0]) {
+        // learned subgrid closure: precomputed flux divergences
+        const long o = (long)(k + H) * sz + col;
+        G[0] += fs.closure[0][o];
+        G[1] += fs.closure[1][o];
+        G[2] += fs.closure[2][o];
+        G[3] += fs.closure[3][o];
+      }
 
       const long lv = (long)(k + H) * sz;
 #pragma unroll

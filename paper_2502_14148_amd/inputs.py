@@ -52,6 +52,7 @@ class Physics:
     tracers: tuple = ("c",)
     top_flux: dict = field(default_factory=dict)   # tracer -> upward flux at the top wall
     buoyancy: bool = False
+    closure: bool = False               # reserve room for a learned closure
 
     def as_dict(self):
         return asdict(self)

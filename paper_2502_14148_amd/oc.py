@@ -29,10 +29,15 @@ EXPORTS = ("oc_last_error", "oc_grid_create", "oc_grid_destroy", "oc_model_works
            "oc_model_create", "oc_model_destroy", "oc_set_state", "oc_get_state",
            "oc_tendencies", "oc_get_tendency", "oc_pressure_solve", "oc_get_pressure",
            "oc_rk3_step", "oc_diagnostics", "oc_profile", "oc_profile_read",
-           "oc_free_surface_substeps")
-OC_NPROF = 8
+           "oc_free_surface_substeps", "oc_mlp_workspace_size", "oc_mlp_create",
+           "oc_mlp_destroy", "oc_mlp_set_params", "oc_mlp_get_params", "oc_mlp_forward",
+           "oc_mlp_gradients", "oc_mlp_train_step", "oc_model_set_closure")
+OC_MLP_NPARAM = 195076
+MLP_SHAPES = (("W1", (256, 500)), ("b1", (256,)), ("W2", (256, 256)), ("b2", (256,)),
+              ("W3", (4, 256)), ("b3", (4,)))
+OC_NPROF = 9
 PROF_CLASSES = ("tendency", "fft_x_fwd", "fft_y_fwd", "z_solve", "fft_y_inv", "fft_x_inv",
-                "project", "halo")
+                "project", "halo", "closure")
 
 
 class GridDesc(ctypes.Structure):
@@ -53,7 +58,8 @@ class ModelDesc(ctypes.Structure):
                 ("beta", ctypes.c_double), ("t_ref", ctypes.c_double), ("s_ref", ctypes.c_double),
                 ("nu", ctypes.c_double), ("kappa", ctypes.c_double),
                 ("top_flux", ctypes.c_double * OC_MAX_TRACERS),
-                ("depth", ctypes.c_double), ("omega", ctypes.c_double)]
+                ("depth", ctypes.c_double), ("omega", ctypes.c_double),
+                ("closure", ctypes.c_int32)]
 
 
 class OcError(RuntimeError):
@@ -91,6 +97,15 @@ def load_library(path=_LIB_PATH):
         "oc_profile": [vp, i32],
         "oc_profile_read": [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)],
         "oc_free_surface_substeps": [vp, ctypes.c_double, i32, i32, ctypes.POINTER(ctypes.c_double), vp],
+        "oc_mlp_workspace_size": [i32, ctypes.POINTER(ctypes.c_uint64)],
+        "oc_mlp_create": [i32, vp, ctypes.c_uint64, ctypes.POINTER(vp)],
+        "oc_mlp_destroy": [vp],
+        "oc_mlp_set_params": [vp, vp, vp],
+        "oc_mlp_get_params": [vp, vp, vp],
+        "oc_mlp_forward": [vp, vp, i32, vp, vp],
+        "oc_mlp_gradients": [vp, vp, vp, i32, vp, ctypes.POINTER(ctypes.c_double), vp],
+        "oc_mlp_train_step": [vp, vp, vp, i32, ctypes.c_float, ctypes.POINTER(ctypes.c_double), vp],
+        "oc_model_set_closure": [vp, vp, ctypes.POINTER(ctypes.c_double), vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -140,6 +155,7 @@ class Model:
         md.weno_q = ph.weno_q
         md.ntracers = len(ph.tracers)
         md.buoyancy = 1 if ph.buoyancy else 0
+        md.closure = 1 if getattr(ph, "closure", False) else 0
         md.g, md.alpha, md.beta = ph.g, ph.alpha, ph.beta
         md.t_ref, md.s_ref = ph.t_ref, ph.s_ref
         md.nu, md.kappa = ph.nu, ph.kappa
@@ -254,9 +270,97 @@ class Model:
         _check(_lib.oc_profile_read(self._model, ms, n))
         return {c: (ms[i], n[i]) for i, c in enumerate(PROF_CLASSES)}
 
+    def set_closure(self, net, stats=None):
+        """Attach a trained Mlp (stats: 16 numbers, input mean/std of u, v, w, b
+        and output mean/std of the 4 fluxes) or detach it (net=None)."""
+        if net is None:
+            _check(_lib.oc_model_set_closure(self._model, None, None, _stream()))
+            self._net = None
+            return
+        st = np.ascontiguousarray(stats, dtype=np.float64)
+        assert st.size == 16
+        _check(_lib.oc_model_set_closure(self._model, net._h,
+                                         st.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                         _stream()))
+        self._net = net   # the network must outlive the attachment
+
     def free_surface_substeps(self, dt, N, weights):
         w = np.ascontiguousarray(weights, dtype=np.float64)
         _check(_lib.oc_free_surface_substeps(self._model, ctypes.c_double(dt), ctypes.c_int32(N),
                                              ctypes.c_int32(len(w)),
                                              w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                              _stream()))
+
+
+def pack_mlp(params):
+    """Dict of arrays (W1, b1, W2, b2, W3, b3) -> packed FP32 vector."""
+    return np.concatenate([np.asarray(params[k], dtype=np.float32).ravel() for k, _ in MLP_SHAPES])
+
+
+def unpack_mlp(vec):
+    out, o = {}, 0
+    for k, shp in MLP_SHAPES:
+        n = int(np.prod(shp))
+        out[k] = np.asarray(vec[o:o + n], dtype=np.float64).reshape(shp)
+        o += n
+    return out
+
+
+class Mlp:
+    """The MLP closure network on the GPU (BF16 MFMA, FP32 master weights)."""
+
+    def __init__(self, max_batch, device="cuda:0"):
+        import torch
+        lib = load_library()
+        self.device = torch.device(device)
+        nbytes = ctypes.c_uint64()
+        _check(lib.oc_mlp_workspace_size(max_batch, ctypes.byref(nbytes)))
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+            self._h = ctypes.c_void_p()
+            _check(lib.oc_mlp_create(max_batch, ctypes.c_void_p(self.workspace.data_ptr()),
+                                     ctypes.c_uint64(nbytes.value), ctypes.byref(self._h)))
+        self.max_batch = max_batch
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None):
+                _lib.oc_mlp_destroy(self._h)
+        except Exception:
+            pass
+
+    def set_params(self, params):
+        v = np.ascontiguousarray(pack_mlp(params) if isinstance(params, dict) else params,
+                                 dtype=np.float32)
+        assert v.size == OC_MLP_NPARAM
+        _check(_lib.oc_mlp_set_params(self._h, ctypes.c_void_p(v.ctypes.data), _stream()))
+
+    def get_params(self):
+        v = np.empty(OC_MLP_NPARAM, dtype=np.float32)
+        _check(_lib.oc_mlp_get_params(self._h, ctypes.c_void_p(v.ctypes.data), _stream()))
+        return unpack_mlp(v)
+
+    def forward(self, x):
+        import torch
+        x = x.contiguous()
+        y = torch.empty((x.shape[0], 4), dtype=torch.float32, device=x.device)
+        _check(_lib.oc_mlp_forward(self._h, ctypes.c_void_p(x.data_ptr()), x.shape[0],
+                                   ctypes.c_void_p(y.data_ptr()), _stream()))
+        return y
+
+    def gradients(self, x, t):
+        import torch
+        g = torch.empty(OC_MLP_NPARAM, dtype=torch.float32, device=x.device)
+        loss = ctypes.c_double()
+        _check(_lib.oc_mlp_gradients(self._h, ctypes.c_void_p(x.contiguous().data_ptr()),
+                                     ctypes.c_void_p(t.contiguous().data_ptr()), x.shape[0],
+                                     ctypes.c_void_p(g.data_ptr()), ctypes.byref(loss), _stream()))
+        return g, loss.value
+
+    def train_step(self, x, t, lr, want_loss=True):
+        loss = ctypes.c_double()
+        _check(_lib.oc_mlp_train_step(self._h, ctypes.c_void_p(x.contiguous().data_ptr()),
+                                      ctypes.c_void_p(t.contiguous().data_ptr()), x.shape[0],
+                                      ctypes.c_float(lr),
+                                      ctypes.byref(loss) if want_loss else None, _stream()))
+        return loss.value if want_loss else None

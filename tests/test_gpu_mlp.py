@@ -1,0 +1,160 @@
+"""GPU parity of the MLP closure network (BF16 MFMA, FP32 accumulation)
+against the FP64 oracle with BF16 operand rounding: forward outputs,
+gradients of the loss, and Adam steps.  Bars: max relative error 2e-2 and
+relative L2 error 2e-3 (BF16 rounding decisions taken in FP32 on the GPU and
+in FP64-then-FP32 in the oracle differ in rare ties)."""
+import numpy as np
+import pytest
+
+from oracle import closure as cl
+
+pytestmark = pytest.mark.gpu
+
+
+def rel_l2(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def _data(seed, B):
+    rng = np.random.default_rng(seed)
+    p = cl.init_params(seed)
+    p["b1"] = (rng.standard_normal(cl.NH) * 0.1).astype(np.float32).astype(np.float64)
+    p["b2"] = (rng.standard_normal(cl.NH) * 0.1).astype(np.float32).astype(np.float64)
+    p["b3"] = (rng.standard_normal(cl.NOUT) * 0.1).astype(np.float32).astype(np.float64)
+    X = rng.standard_normal((B, cl.NIN)).astype(np.float32).astype(np.float64)
+    T = rng.standard_normal((B, cl.NOUT)).astype(np.float32).astype(np.float64)
+    return p, X, T
+
+
+def _dev(a):
+    import torch
+    return torch.tensor(a, dtype=torch.float32, device="cuda")
+
+
+@pytest.mark.parametrize("B", [32, 96, 4096])
+def test_forward_parity(gpu_lib, B):
+    p, X, _ = _data(1, B)
+    net = gpu_lib.Mlp(4096)
+    net.set_params(p)
+    y = net.forward(_dev(X)).cpu().numpy().astype(np.float64)
+    yo, _ = cl.forward(p, X, use_bf16=True)
+    assert rel_l2(y, yo) < 2e-3, rel_l2(y, yo)
+    assert np.max(np.abs(y - yo)) < 2e-2 * np.max(np.abs(yo))
+
+
+def test_zero_weights_give_bias(gpu_lib):
+    p, X, _ = _data(2, 64)
+    for k in ("W1", "W2", "W3"):
+        p[k] = np.zeros_like(p[k])
+    net = gpu_lib.Mlp(64)
+    net.set_params(p)
+    y = net.forward(_dev(X)).cpu().numpy()
+    assert np.array_equal(y, np.broadcast_to(p["b3"].astype(np.float32), y.shape))
+
+
+@pytest.mark.parametrize("B", [64, 1024])
+def test_gradient_parity(gpu_lib, B):
+    p, X, T = _data(3, B)
+    net = gpu_lib.Mlp(1024)
+    net.set_params(p)
+    g, loss = net.gradients(_dev(X), _dev(T))
+    g = gpu_lib.unpack_mlp(g.cpu().numpy())
+    Y, cache = cl.forward(p, X, use_bf16=True)
+    go = cl.backward(p, cache, Y, T, use_bf16=True)
+    assert abs(loss - cl.mse(Y, T)) < 2e-3 * cl.mse(Y, T)
+    for k in go:
+        assert rel_l2(g[k], go[k]) < 2e-3 * (5 if k.startswith("b") else 1), (k, rel_l2(g[k], go[k]))
+
+
+def test_adam_steps_parity(gpu_lib):
+    """Three Adam steps on the GPU and in the oracle from the same start."""
+    p, X, T = _data(4, 256)
+    net = gpu_lib.Mlp(256)
+    net.set_params(p)
+    state, q = {}, dict(p)
+    for _ in range(3):
+        net.train_step(_dev(X), _dev(T), 1e-3)
+        Y, cache = cl.forward(q, X, use_bf16=True)
+        q = cl.adam_step(q, cl.backward(q, cache, Y, T, use_bf16=True), state, 1e-3)
+    got = net.get_params()
+    for k in q:
+        # relative to the size of the three updates, not of the weights
+        step = np.linalg.norm(q[k] - p[k])
+        assert np.linalg.norm(got[k] - q[k]) < 0.05 * step + 1e-7, k
+
+
+def test_training_reduces_loss(gpu_lib):
+    """A learnable target (a smooth function of the inputs): 200 Adam steps
+    on the GPU cut the loss by more than 5x."""
+    rng = np.random.default_rng(5)
+    X = rng.standard_normal((2048, cl.NIN)).astype(np.float32)
+    A = rng.standard_normal((cl.NIN, 4)).astype(np.float32) / np.sqrt(cl.NIN)
+    T = np.tanh(X @ A).astype(np.float32)
+    net = gpu_lib.Mlp(2048)
+    net.set_params(cl.init_params(6))
+    xd, td = _dev(X), _dev(T)
+    first = net.train_step(xd, td, 1e-3)
+    for _ in range(198):
+        net.train_step(xd, td, 1e-3, want_loss=False)
+    last = net.train_step(xd, td, 1e-3)
+    assert last < first / 5, (first, last)
+
+
+def _closure_case(seed=7):
+    from paper_2502_14148_amd import inputs
+    ph = inputs.convection_physics((32, 32, 16), (64.0, 64.0, 16.0))
+    ph.closure = True
+    s = inputs.random_state(ph, seed=seed, vel=1e-2, tracer_scale=0.05)
+    s["T"] += 20.0
+    s["S"] += 25.0
+    p, _, _ = _data(seed, 32)
+    stats = np.array([0.0, 0.0, 0.0, -0.02, 1e-2, 1e-2, 1e-2, 5e-3,
+                      0.0, 0.0, 1e-6, 1e-9, 1e-5, 1e-5, 1e-5, 1e-8])
+    return ph, s, p, stats
+
+
+def test_closure_tendency_parity(gpu_lib):
+    """The closure's contribution to G (model with the network attached minus
+    the model without it) against the oracle: features -> BF16 MLP ->
+    conservative flux divergence."""
+    from oracle import timestep
+    ph, s, p, stats = _closure_case()
+    net = gpu_lib.Mlp(ph.nx * ph.ny * ph.nz)
+    net.set_params(p)
+    m = gpu_lib.Model(ph, "fp64")
+    m.set_states(s)
+    m.tendencies()
+    G0 = {n: m.get_tendency(n) for n in ("u", "v", "w", "T")}
+    m.set_closure(net, stats)
+    m.tendencies()
+    G1 = {n: m.get_tendency(n) for n in ("u", "v", "w", "T")}
+    st = timestep.make_state(s, ph)
+    padded = {"u": st["u"], "v": st["v"], "w": st["w"],
+              "b": ph.g * (ph.alpha * (st["T"] - ph.t_ref) - ph.beta * (st["S"] - ph.s_ref))}
+    X = cl.features(padded, ph, stats[0:4], stats[4:8])
+    Y, _ = cl.forward(p, X, use_bf16=True)
+    F = (Y * stats[12:16] + stats[8:12]).T.reshape(4, ph.nz, ph.ny, ph.nx)
+    Gc = cl.closure_tendency(F, ph)
+    for n in ("u", "v", "w", "T"):
+        err = rel_l2(G1[n] - G0[n], Gc[n])
+        assert err < 5e-3, (n, err)
+
+
+def test_closure_refuses_diverged_network(gpu_lib):
+    """A network trained into non-finite weights is refused; the model keeps
+    its diffusive closure and steps normally."""
+    ph, s, p, stats = _closure_case(8)
+    net = gpu_lib.Mlp(ph.nx * ph.ny * ph.nz)
+    net.set_params(p)
+    rng = np.random.default_rng(0)
+    X = _dev(rng.standard_normal((64, cl.NIN)) * 1e30)
+    T = _dev(rng.standard_normal((64, 4)))
+    for _ in range(3):
+        net.train_step(X, T, 1e30, want_loss=False)
+    m = gpu_lib.Model(ph, "fp32")
+    m.set_states(s)
+    with pytest.raises(gpu_lib.OcError, match="OC_ERR_NONFINITE"):
+        m.set_closure(net, stats)
+    m.rk3_step(0.5, 2)
+    d = m.diagnostics()
+    assert np.isfinite(d["max_w"])
