@@ -93,6 +93,64 @@ def run_gpu(ph, s, precision, steps, warmup):
     return ms, wall, prof, diag
 
 
+def hydro_tendency_bytes(ncells, esz):
+    """Bytes the hydrostatic tendency + QAB2 kernel must move per launch:
+    reads u, v, T, S, w, zeta, the two pressure gradients and G^{n-1} of
+    u, v, T, S; writes the four predicted fields and G^n (12 + 8 fields)."""
+    return 20 * esz * ncells
+
+
+def run_hydrostatic(steps, warmup, N=30):
+    """The 1440 x 560 x 50 lat-lon sector in FP32: QAB2 baroclinic steps of
+    600 s with N = 30 barotropic substeps per step (cosine-bell filter over
+    M = 2N - 1 substeps)."""
+    import torch
+    from paper_2502_14148_amd import inputs, oc
+    ph = inputs.sector_physics()
+    print("# generating the 1440x560x50 sector state", file=sys.stderr, flush=True)
+    s = inputs.hydrostatic_initial(ph, seed=0, flow=0.1)
+    w = inputs.averaging_weights(N)
+    m = oc.Model(ph, "fp32")
+    m.set_states(s)
+    for k in ("eta", "U", "V", "tau_x", "tau_y"):
+        m.set_state(k, s[k])
+    del s
+    dt = 600.0
+    m.hydrostatic_step(dt, N, w, warmup)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    m.profile(True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    m.hydrostatic_step(dt, N, w, steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    m.profile(False)
+    prof = m.profile_read()
+    ms = e0.elapsed_time(e1)
+    finite = bool(np.isfinite(m.get_state("eta")).all())
+    del m
+    torch.cuda.empty_cache()
+    ncells = ph.nx * ph.ny * ph.nz
+    t_tend, n_tend = prof["hydro_tendency"]
+    t_launch = t_tend / 1e3 / max(n_tend, 1)
+    gbs = hydro_tendency_bytes(ncells, 4) / t_launch / 1e9
+    return {"value": ncells * steps / (ms / 1e3), "unit": "cell-steps/s", "steps": steps,
+            "warmup": warmup, "ms_per_step": ms / steps, "dtype": "f32",
+            "config": {"workload": "hydrostatic lat-lon sector 1440x560x50, 70S-70N, 3000 m, "
+                                   "WENO vector-invariant momentum + WENO tracers, QAB2, "
+                                   "split-explicit free surface (FP64)",
+                       "dt_s": dt, "N": N, "M": len(w)},
+            "kernels_ms_per_step": {k: v[0] / steps for k, v in prof.items() if v[1]},
+            "tendency_hbm": {"achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": round(gbs / HBM_PEAK_GBS, 4),
+                             "avg_launch_ms": t_launch * 1e3,
+                             "algorithmic_bytes_per_launch": hydro_tendency_bytes(ncells, 4)},
+            "finite": finite}
+
+
 def cpu_baseline(n_sample):
     """The FP64 oracle (NumPy) on a bounded sample: one RK3 step of the same
     physics and horizontal grid on a slab of n_sample levels."""
@@ -119,6 +177,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-levels", type=int, default=32)
+    ap.add_argument("--no-hydrostatic", action="store_true")
+    ap.add_argument("--hydro-steps", type=int, default=20)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain 512 MiB device copy (counter calibration)")
     a = ap.parse_args()
@@ -183,6 +243,9 @@ def main():
         "wall_s_timed": wall32,
         "final_max_w": diag32["max_w"],
     }
+    if not a.no_hydrostatic:
+        print("# hydrostatic sector run", file=sys.stderr, flush=True)
+        out["hydrostatic"] = run_hydrostatic(a.hydro_steps, 2)
     if not a.no_cpu:
         print("# CPU oracle sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(a.cpu_levels)

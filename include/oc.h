@@ -61,10 +61,15 @@ enum { OC_F32 = 0, OC_F64 = 1 };
 /* Field identifiers: velocities, then tracers 0..ntracers-1; the
  * hydrostatic model adds its 2D barotropic fields (FP64): free surface eta
  * at cell centres (shape (1, ny, nx)), transports U at x faces (1, ny, nx)
- * and V at y faces (1, ny + 1, nx), and the slow forcing Gbar of U and V
- * (same shapes as U and V). */
+ * and V at y faces (1, ny + 1, nx), the slow forcing Gbar of U and V (same
+ * shapes as U and V), and the kinematic surface stress tau / rho_0
+ * (m^2 s^-2) at u points (OC_TAUX, (1, ny, nx)) and v points (OC_TAUY,
+ * (1, ny + 1, nx)), the surface momentum flux of the baroclinic step.  In the
+ * hydrostatic model v has ny + 1 rows (y faces, walls included) and w is
+ * diagnostic: it can be read (nz + 1 faces) but not set. */
 enum { OC_U = 0, OC_V = 1, OC_W = 2, OC_TRACER0 = 3 };
-enum { OC_ETA = 16, OC_UBT = 17, OC_VBT = 18, OC_GUBT = 19, OC_GVBT = 20 };
+enum { OC_ETA = 16, OC_UBT = 17, OC_VBT = 18, OC_GUBT = 19, OC_GVBT = 20, OC_TAUX = 21,
+       OC_TAUY = 22 };
 #define OC_MAX_TRACERS 4
 #define OC_NDIAG 8
 
@@ -177,9 +182,9 @@ int oc_rk3_step(oc_model* m, double dt, int32_t nsteps, void* stream);
 enum {
   OC_PROF_TENDENCY = 0, OC_PROF_FFT_X_FWD = 1, OC_PROF_FFT_Y_FWD = 2, OC_PROF_Z_SOLVE = 3,
   OC_PROF_FFT_Y_INV = 4, OC_PROF_FFT_X_INV = 5, OC_PROF_PROJECT = 6, OC_PROF_HALO = 7,
-  OC_PROF_CLOSURE = 8
+  OC_PROF_CLOSURE = 8, OC_PROF_HYDRO_DIAG = 9, OC_PROF_HYDRO_TEND = 10, OC_PROF_BAROTROPIC = 11
 };
-#define OC_NPROF 9
+#define OC_NPROF 12
 int oc_profile(oc_model* m, int32_t enable);
 int oc_profile_read(oc_model* m, double* ms, int64_t* launches);
 
@@ -197,6 +202,30 @@ int oc_profile_read(oc_model* m, double* ms, int64_t* launches);
  * nonhydrostatic model, OC_ERR_ARG for N < 1, M < 1, M > 4096 or NULL a. */
 int oc_free_surface_substeps(oc_model* m, double dt, int32_t N, int32_t M, const double* a,
                              void* stream);
+
+/* nsteps baroclinic steps of the hydrostatic model (hydrostatic-model
+ * subsection; hydrostatic time-discretisation appendix).  Per step:
+ *   1. column scans: w from the floor up (dw/dz = -div_h u_h, w = 0 on the
+ *      floor), the hydrostatic pressure gradient from dp/dz = b with p = 0
+ *      at the surface, and the vertical vorticity at cell corners;
+ *   2. tendencies G^n of u, v, T, S: WENO vector-invariant momentum
+ *      advection, f = 2 Omega sin(latitude) Coriolis, hydrostatic pressure
+ *      gradient, vertical viscosity with the surface stress OC_TAUX/OC_TAUY,
+ *      flux-form WENO tracer advection on the shell's metrics, vertical
+ *      diffusion; the QAB2 predictor X~ = X + dt [(3/2 + chi) G^n -
+ *      (1/2 + chi) G^{n-1}] with chi = 0.1, and Gbar = sum_k dz [...] of u, v
+ *      in FP64;
+ *   3. the split-explicit barotropic substeps, correction and restart of
+ *      oc_free_surface_substeps with the same N, M, a.
+ * The first step after model creation or after oc_set_state of a 3D field
+ * is an Euler step (chi = -1/2).  State precision per the model descriptor;
+ * eta, U, V, Gbar FP64.  After the call G (oc_get_tendency) holds G^n of
+ * the last step and w (oc_get_state, OC_W) the diagnosed velocity of the new
+ * state.  Errors: OC_ERR_UNSUPPORTED for a nonhydrostatic model, OC_ERR_ARG
+ * for dt <= 0, N < 1, M < 1, M > 4096, nsteps < 0, a NULL or non-finite a,
+ * OC_ERR_DEVICE on a HIP failure. */
+int oc_hydrostatic_step(oc_model* m, double dt, int32_t N, int32_t M, const double* a,
+                        int32_t nsteps, void* stream);
 
 /* ---- Learned subgrid closure (an MLP trained on coarse-grained fluxes) ----
  * The network maps the standardised 5x5x5 neighbourhood of (u, v, w, b) of a

@@ -27,7 +27,7 @@ FLAGS = [
 ]
 
 SOURCES = ["api.hip", "stencil.hip", "poisson.hip", "tendency.hip", "barotropic.hip", "mlp.hip",
-           "closure_api.hip"]
+           "closure_api.hip", "hydrostatic.hip"]
 
 
 def _compile(src, defines=(), build_dir=None):

@@ -66,6 +66,16 @@ struct oc_model {
   double* vbar;
   double* metric;        // len_u | dx_u | len_v | dy_v | area
   int bcur;
+  // hydrostatic baroclinic step: diagnostic fields (state precision,
+  // padded), row tables, surface stress, and the QAB2 / refresh flags
+  void* hzeta;
+  void* hpx;
+  void* hpy;
+  double* hmet;
+  double* taux;
+  double* tauy;
+  int hfirst;            // the next step is a first (Euler) step
+  int hstale;            // halos and diagnostic fields need a refresh
   // learned closure: network, statistics, tendency buffers (u, v, w, T)
   oc_mlp* net;
   ClosureStats cst;
@@ -91,7 +101,7 @@ namespace {
 struct Layout {
   uint64_t state[2][MAXF], G[MAXF];
   uint64_t spec, p, twx, twy, twz, dctz, lamx, lamy, lamz, staging, diag;
-  uint64_t baro[11], metric;
+  uint64_t baro[13], metric, hzeta, hpx, hpy, hmet;
   uint64_t gc[4];
   uint64_t total;
 };
@@ -127,10 +137,15 @@ Layout make_layout(const oc_grid_desc& g, const oc_model_desc& m) {
     L.lamy = off; off += align256((uint64_t)g.ny * 8);
     L.lamz = off; off += align256((uint64_t)g.nz * 8);
   } else {
-    // eta[2], U[2], V[2], GU, GV, etabar, Ubar, Vbar (V-like: ny + 1 rows)
+    // eta[2], U[2], V[2], GU, GV, etabar, Ubar, Vbar, tau_x, tau_y
+    // (V-like: ny + 1 rows)
     const uint64_t a2 = align256((uint64_t)(g.ny + 1) * g.nx * 8);
-    for (int q = 0; q < 11; ++q) { L.baro[q] = off; off += a2; }
+    for (int q = 0; q < 13; ++q) { L.baro[q] = off; off += a2; }
     L.metric = off; off += align256((uint64_t)(5 * (g.ny + 1)) * 8);
+    L.hzeta = off; off += fb;
+    L.hpx = off; off += fb;
+    L.hpy = off; off += fb;
+    L.hmet = off; off += align256((uint64_t)HYDRO_NMET * (g.ny + 2 * H + 1) * 8);
   }
   if (m.closure)
     for (int q = 0; q < 4; ++q) { L.gc[q] = off; off += fb; }
@@ -209,6 +224,10 @@ int validate_model(const oc_model_desc* m) {
     set_error("hydrostatic model needs depth > 0");
     return OC_ERR_ARG;
   }
+  if (m->kind == OC_HYDROSTATIC && m->ntracers != 2) {
+    set_error("the hydrostatic model carries exactly T and S (ntracers = 2)");
+    return OC_ERR_ARG;
+  }
   return OC_OK;
 }
 
@@ -224,7 +243,7 @@ int validate_pair(const oc_grid_desc& g, const oc_model_desc& m) {
   return OC_OK;
 }
 
-bool is_2d_field(int field) { return field >= OC_ETA && field <= OC_GVBT; }
+bool is_2d_field(int field) { return field >= OC_ETA && field <= OC_TAUY; }
 
 int nzf_of(const oc_model* m, int field) {
   if (is_2d_field(field)) return 1;
@@ -234,7 +253,7 @@ int nzf_of(const oc_model* m, int field) {
 // rows of a field: v-like fields of the hydrostatic model include the
 // northern wall face
 int nyf_of(const oc_model* m, int field) {
-  const bool vlike = field == OC_VBT || field == OC_GVBT ||
+  const bool vlike = field == OC_VBT || field == OC_GVBT || field == OC_TAUY ||
                      (m->kind == OC_HYDROSTATIC && field == OC_V);
   return vlike ? m->dims.ny + 1 : m->dims.ny;
 }
@@ -264,6 +283,8 @@ double* baro_field(oc_model* m, int field) {
     case OC_UBT: return m->ubt[m->bcur];
     case OC_VBT: return m->vbt[m->bcur];
     case OC_GUBT: return m->gubt;
+    case OC_TAUX: return m->taux;
+    case OC_TAUY: return m->tauy;
     default: return m->gvbt;
   }
 }
@@ -546,6 +567,28 @@ void fill_latlon_metrics(const oc_grid_desc& g, std::vector<double>& met) {
   }
 }
 
+// Row tables of the baroclinic step (HydroMetric), rows j = -H .. ny + H.
+void fill_hydro_metrics(const oc_grid_desc& g, double omega, std::vector<double>& met) {
+  const double pi = 3.14159265358979323846;
+  const int ny = g.ny, nt = ny + 2 * H + 1;
+  const double dlam = g.lx / g.nx * pi / 180.0;
+  const double dphi = g.ly / ny * pi / 180.0;
+  const double phi0 = g.y0 * pi / 180.0;
+  const double R = g.radius;
+  met.assign((size_t)HYDRO_NMET * nt, 0.0);
+  for (int r = 0; r < nt; ++r) {
+    const int j = r - H;
+    const double phf = phi0 + j * dphi, phc = phi0 + (j + 0.5) * dphi;
+    const double phf1 = phi0 + (j + 1) * dphi, phcm = phi0 + (j - 0.5) * dphi;
+    met[0 * (size_t)nt + r] = R * std::cos(phc) * dlam;
+    met[1 * (size_t)nt + r] = R * std::cos(phf) * dlam;
+    met[2 * (size_t)nt + r] = R * R * dlam * (std::sin(phf1) - std::sin(phf));
+    met[3 * (size_t)nt + r] = R * R * dlam * (std::sin(phc) - std::sin(phcm));
+    met[4 * (size_t)nt + r] = 2.0 * omega * std::sin(phc);
+    met[5 * (size_t)nt + r] = 2.0 * omega * std::sin(phf);
+  }
+}
+
 BaroBufs baro_bufs(oc_model* m) {
   BaroBufs b;
   const int ny = m->dims.ny;
@@ -569,6 +612,105 @@ BaroBufs baro_bufs(oc_model* m) {
   b.nx = m->dims.nx;
   b.ny = ny;
   return b;
+}
+
+template <class T>
+HydroBufs<T> hydro_bufs(oc_model* m, int in, int out) {
+  HydroBufs<T> a;
+  a.d = m->dims;
+  const int nt = m->dims.ny + 2 * H + 1;
+  // tables of nt rows each; the kernels index them with j + H
+  a.m.dxc = m->hmet + 0 * nt;
+  a.m.dxf = m->hmet + 1 * nt;
+  a.m.areac = m->hmet + 2 * nt;
+  a.m.areaz = m->hmet + 3 * nt;
+  a.m.fc = m->hmet + 4 * nt;
+  a.m.ff = m->hmet + 5 * nt;
+  const double pi = 3.14159265358979323846;
+  a.m.dy = m->gd.radius * (m->gd.ly / m->gd.ny * pi / 180.0);
+  a.m.dz = m->gd.lz / m->gd.nz;
+  const oc_model_desc& d = m->md;
+  a.eps = (T)d.weno_eps;
+  a.nu = (T)d.nu;
+  a.kappa = (T)d.kappa;
+  a.ga = d.buoyancy ? (T)(d.g * d.alpha) : T(0);
+  a.gb = d.buoyancy ? (T)(d.g * d.beta) : T(0);
+  a.tref = (T)(d.t_ref - m->offset[OC_TRACER0]);
+  a.sref = (T)(d.s_ref - m->offset[OC_TRACER0 + 1]);
+  a.u = (const T*)m->state[in][OC_U];
+  a.v = (const T*)m->state[in][OC_V];
+  a.t = (const T*)m->state[in][OC_TRACER0];
+  a.s = (const T*)m->state[in][OC_TRACER0 + 1];
+  a.uo = (T*)m->state[out][OC_U];
+  a.vo = (T*)m->state[out][OC_V];
+  a.to = (T*)m->state[out][OC_TRACER0];
+  a.so = (T*)m->state[out][OC_TRACER0 + 1];
+  a.Gu = (T*)m->G[OC_U];
+  a.Gv = (T*)m->G[OC_V];
+  a.Gt = (T*)m->G[OC_TRACER0];
+  a.Gs = (T*)m->G[OC_TRACER0 + 1];
+  a.w = (T*)m->state[in][OC_W];
+  a.zeta = (T*)m->hzeta;
+  a.px = (T*)m->hpx;
+  a.py = (T*)m->hpy;
+  a.taux = m->taux;
+  a.tauy = m->tauy;
+  a.gub = m->gubt;
+  a.gvb = m->gvbt;
+  return a;
+}
+
+// Halos of the current state, then w, zeta and the pressure gradients.
+template <class T>
+int hydro_refresh(oc_model* m, hipStream_t s) {
+  T* const* st = (T* const*)m->state[m->cur];
+  {
+    ProfScope ps(m, OC_PROF_HALO, s);
+    OC_CHECK_HIP(launch_hydro_halo<T>(m->dims, st[OC_U], st[OC_V], st[OC_TRACER0],
+                                      st[OC_TRACER0 + 1], s));
+  }
+  {
+    ProfScope ps(m, OC_PROF_HYDRO_DIAG, s);
+    OC_CHECK_HIP(launch_hydro_diag<T>(hydro_bufs<T>(m, m->cur, m->cur), s));
+  }
+  m->hstale = 0;
+  return OC_OK;
+}
+
+template <class T>
+int free_surface_call(oc_model* m, double dt, int N, int M, const double* a, hipStream_t s);
+
+// QAB2 baroclinic steps coupled to the split-explicit barotropic mode.
+template <class T>
+int hydro_steps(oc_model* m, double dt, int N, int M, const double* a, int nsteps, hipStream_t s) {
+  const double chi = 0.1;
+  const int scheme = m->md.advection == OC_ADV_NONE ? 0
+                     : (m->md.advection == OC_ADV_WENO5_LINEAR ? 2 : 1);
+  for (int n = 0; n < nsteps; ++n) {
+    if (m->hstale) {
+      int rc = hydro_refresh<T>(m, s);
+      if (rc) return rc;
+    }
+    HydroStep<T> st;
+    st.dt = (T)dt;
+    st.first = m->hfirst;
+    st.a1 = m->hfirst ? T(1) : (T)(1.5 + chi);
+    st.a0 = m->hfirst ? T(0) : (T)(0.5 + chi);
+    {
+      ProfScope ps(m, OC_PROF_HYDRO_TEND, s);
+      OC_CHECK_HIP(launch_hydro_tendency<T>(hydro_bufs<T>(m, m->cur, 1 - m->cur), st, scheme, s));
+    }
+    m->cur = 1 - m->cur;
+    m->hfirst = 0;
+    {
+      ProfScope ps(m, OC_PROF_BAROTROPIC, s);
+      int rc = free_surface_call<T>(m, dt, N, M, a, s);
+      if (rc) return rc;
+    }
+    int rc = hydro_refresh<T>(m, s);
+    if (rc) return rc;
+  }
+  return OC_OK;
 }
 
 template <class T>
@@ -702,6 +844,14 @@ int oc_model_create(const oc_grid* g, const oc_model_desc* md, void* workspace,
   m->vbar = (double*)(m->ws + L.baro[10]);
   m->metric = (double*)(m->ws + L.metric);
   m->bcur = 0;
+  m->hzeta = m->ws + L.hzeta;
+  m->hpx = m->ws + L.hpx;
+  m->hpy = m->ws + L.hpy;
+  m->hmet = (double*)(m->ws + L.hmet);
+  m->taux = (double*)(m->ws + L.baro[11]);
+  m->tauy = (double*)(m->ws + L.baro[12]);
+  m->hfirst = 1;
+  m->hstale = 1;
   m->net = nullptr;
   for (int q = 0; q < 4; ++q) m->gc[q] = md->closure ? (void*)(m->ws + L.gc[q]) : nullptr;
 
@@ -720,6 +870,9 @@ int oc_model_create(const oc_grid* g, const oc_model_desc* md, void* workspace,
     std::vector<double> met;
     fill_latlon_metrics(g->d, met);
     if (e == hipSuccess) e = hipMemcpy(m->metric, met.data(), met.size() * 8, hipMemcpyHostToDevice);
+    std::vector<double> hmet;
+    fill_hydro_metrics(g->d, md->omega, hmet);
+    if (e == hipSuccess) e = hipMemcpy(m->hmet, hmet.data(), hmet.size() * 8, hipMemcpyHostToDevice);
   }
   if (e != hipSuccess) {
     set_error("model setup failed: %s", hipGetErrorString(e));
@@ -770,13 +923,17 @@ int oc_set_state(oc_model* m, int32_t field, const void* buf, int32_t dtype, int
   if (is_2d_field(field)) {
     rc = baro_io(m, field, const_cast<void*>(buf), on_device, 0, s);
     if (rc) return rc;
-    if (field == OC_VBT || field == OC_GVBT) {
+    if (field == OC_VBT || field == OC_GVBT || field == OC_TAUY) {
       // the wall faces carry no transport
       double* f = baro_field(m, field);
       OC_CHECK_HIP(launch_baro_fill(f, 0.0, m->dims.nx, s));
       OC_CHECK_HIP(launch_baro_fill(f + (size_t)m->dims.ny * m->dims.nx, 0.0, m->dims.nx, s));
     }
     return OC_OK;
+  }
+  if (m->kind == OC_HYDROSTATIC && field == OC_W) {
+    set_error("w is diagnosed from continuity in the hydrostatic model");
+    return OC_ERR_ARG;
   }
   void* fb = m->state[m->cur][field];
   const int nzf = nzf_of(m, field), nyf = nyf_of(m, field);
@@ -791,7 +948,13 @@ int oc_set_state(oc_model* m, int32_t field, const void* buf, int32_t dtype, int
     OC_CHECK_HIP(hipMemsetAsync((char*)fb + (size_t)H * m->dims.sz * m->esz, 0,
                                 (size_t)m->dims.sz * m->esz, s));
   }
-  if (m->kind == OC_HYDROSTATIC) return OC_OK;  // its halos are filled by its own kernels
+  if (m->kind == OC_HYDROSTATIC) {
+    // a new initial condition: halos and diagnostics are refreshed, and the
+    // next baroclinic step starts the QAB2 history afresh
+    m->hstale = 1;
+    m->hfirst = 1;
+    return OC_OK;
+  }
   return (m->esz == 8) ? halo_one<double>(m, m->cur, field, s) : halo_one<float>(m, m->cur, field, s);
 }
 
@@ -801,6 +964,10 @@ int oc_get_state(oc_model* m, int32_t field, void* buf, int32_t dtype, int32_t o
   if (rc) return rc;
   hipStream_t s = (hipStream_t)stream;
   if (is_2d_field(field)) return baro_io(m, field, buf, on_device, 1, s);
+  if (m->kind == OC_HYDROSTATIC && field == OC_W && m->hstale) {
+    rc = (m->esz == 8) ? hydro_refresh<double>(m, s) : hydro_refresh<float>(m, s);
+    if (rc) return rc;
+  }
   void* fb = m->state[m->cur][field];
   const int nzf = nzf_of(m, field), nyf = nyf_of(m, field);
   const double off = m->offset[field];
@@ -875,8 +1042,24 @@ int oc_free_surface_substeps(oc_model* m, double dt, int32_t N, int32_t M, const
   for (int n = 0; n < M; ++n)
     if (!std::isfinite(a[n])) { set_error("weight %d is not finite", n); return OC_ERR_ARG; }
   hipStream_t s = (hipStream_t)stream;
+  m->hstale = 1;  // the correction changes u and v
   return (m->esz == 8) ? free_surface_call<double>(m, dt, N, M, a, s)
                        : free_surface_call<float>(m, dt, N, M, a, s);
+}
+
+int oc_hydrostatic_step(oc_model* m, double dt, int32_t N, int32_t M, const double* a,
+                        int32_t nsteps, void* stream) {
+  if (!m || !a) { set_error("NULL argument"); return OC_ERR_ARG; }
+  if (m->kind != OC_HYDROSTATIC) { set_error("hydrostatic model only"); return OC_ERR_UNSUPPORTED; }
+  if (!(dt > 0) || !std::isfinite(dt) || N < 1 || M < 1 || M > 4096 || nsteps < 0) {
+    set_error("need dt > 0, N >= 1, 1 <= M <= 4096 and nsteps >= 0");
+    return OC_ERR_ARG;
+  }
+  for (int n = 0; n < M; ++n)
+    if (!std::isfinite(a[n])) { set_error("weight %d is not finite", n); return OC_ERR_ARG; }
+  hipStream_t s = (hipStream_t)stream;
+  return (m->esz == 8) ? hydro_steps<double>(m, dt, N, M, a, nsteps, s)
+                       : hydro_steps<float>(m, dt, N, M, a, nsteps, s);
 }
 
 int oc_model_set_closure(oc_model* m, oc_mlp* net, const double* stats, void* stream) {

@@ -138,6 +138,48 @@ template <class T>
 hipError_t launch_baro_correct(const Dims& d, T* f, const double* bar, int j_lo, int j_hi,
                                double dz, double depth, hipStream_t s);
 
+// ---- Baroclinic step of the hydrostatic model
+// Row tables of the lat-lon C-grid (FP64), index j + H for rows
+// j = -H .. ny + H (the formulas continue past the walls).
+struct HydroMetric {
+  const double* dxc;     // R cos(phi_c(j)) dlambda: x spacing along row j
+  const double* dxf;     // R cos(phi_f(j)) dlambda: x length of y face j
+  const double* areac;   // area of the cells of row j
+  const double* areaz;   // area of the dual cell around y face j
+  const double* fc;      // 2 Omega sin(phi_c(j))
+  const double* ff;      // 2 Omega sin(phi_f(j))
+  double dy, dz;
+};
+constexpr int HYDRO_NMET = 6;
+
+template <class T>
+struct HydroBufs {
+  Dims d;
+  HydroMetric m;
+  T eps, nu, kappa;
+  T ga, gb, tref, sref;     // b = ga (T - tref) - gb (S - sref) on the stored values
+  const T* u; const T* v; const T* t; const T* s;   // state at step n (halos filled)
+  T* uo; T* vo; T* to; T* so;                       // predicted state (QAB2)
+  T* Gu; T* Gv; T* Gt; T* Gs;                       // G^{n-1} in, G^n out
+  T* w; T* zeta; T* px; T* py;                      // diagnostic fields
+  const double* taux; const double* tauy;           // kinematic surface stress
+  double* gub; double* gvb;                         // slow forcing of U, V
+};
+
+template <class T>
+struct HydroStep {
+  T dt, a1, a0;             // X~ = X + dt (a1 G^n - a0 G^{n-1})
+  int first;                // 1: G^{n-1} is not read
+};
+
+template <class T>
+hipError_t launch_hydro_diag(const HydroBufs<T>& a, hipStream_t s);
+template <class T>
+hipError_t launch_hydro_tendency(const HydroBufs<T>& a, const HydroStep<T>& st, int scheme,
+                                 hipStream_t s);
+template <class T>
+hipError_t launch_hydro_halo(const Dims& d, T* u, T* v, T* t, T* sf, hipStream_t s);
+
 // ---- MLP closure (500 -> 256 -> 256 -> 4; device widths 512 and 32)
 constexpr int MLP_NIN = 500, MLP_NH = 256, MLP_NOUT = 4, MLP_KIN = 512, MLP_NOUTP = 32;
 constexpr int MLP_OFF_W1 = 0;

@@ -373,3 +373,66 @@ def barotropic_random_state(ph: HydrostaticPhysics, seed: int = 0, eta_scale: fl
         out[k][:, 0] = 0.0
         out[k][:, -1] = 0.0
     return out
+
+
+RHO0 = 1026.0
+
+
+def hydrostatic_initial(ph: HydrostaticPhysics, seed: int = 0, flow: float = 0.0,
+                        t_noise: float = 0.1, stress_scale: float = 0.05,
+                        s_noise: float = 0.0):
+    """Seeded state of the lat-lon sector (arrays in the model's field shapes).
+
+    T = T_b + (T_s - T_b)(1 + z / depth) with T_s ~ U(18, 22) and T_b = 2,
+    plus N(0, t_noise^2) K; S = 35 (plus N(0, s_noise^2)); eta = 0.  Zonal wind stress bands
+    tau_x(phi) = sum_{m=1..6} a_m sin(m pi (phi - lat0) / lat_extent) with
+    a_m ~ N(0, stress_scale^2) N m^-2, handed over as the kinematic stress
+    tau_x / rho_0; tau_y = 0.  flow > 0 adds a smooth random velocity of that
+    scale (m/s): a few seeded modes in longitude, latitude (v vanishing on the
+    walls) and depth; U, V are the depth integrals of u, v.
+    """
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = ph.nx, ph.ny, ph.nz
+    dz = ph.depth / nz
+    dlam = np.deg2rad(ph.lon_extent / nx)
+    dphi = np.deg2rad(ph.lat_extent / ny)
+    phi0 = np.deg2rad(ph.lat0)
+    lam_f = np.deg2rad(ph.lon0) + np.arange(nx) * dlam
+    lam_c = lam_f + 0.5 * dlam
+    phi_f = phi0 + np.arange(ny + 1) * dphi
+    phi_c = phi_f[:-1] + 0.5 * dphi
+    z = -ph.depth + (np.arange(nz) + 0.5) * dz
+    Ts = rng.uniform(18.0, 22.0)
+    Tb = 2.0
+    T = (Tb + (Ts - Tb) * (1.0 + z / ph.depth))[:, None, None] * np.ones((1, ny, nx))
+    T = T + t_noise * rng.standard_normal((nz, ny, nx))
+    S = np.full((nz, ny, nx), 35.0)
+    if s_noise > 0:
+        S = S + s_noise * rng.standard_normal((nz, ny, nx))
+    a = stress_scale * rng.standard_normal(6)
+    s = (phi_c - phi0) / (ny * dphi)
+    taux = sum(a[m - 1] * np.sin(m * np.pi * s) for m in range(1, 7)) / RHO0
+    u = np.zeros((nz, ny, nx))
+    v = np.zeros((nz, ny + 1, nx))
+    if flow > 0:
+        for _ in range(6):
+            m = rng.integers(1, 4)
+            n = rng.integers(1, 4)
+            l = rng.integers(0, 3)
+            th = rng.uniform(0, 2 * np.pi, 3)
+            au, av = rng.standard_normal(2)
+            zf = np.cos(l * np.pi * (z + ph.depth) / ph.depth + th[2])[:, None, None]
+            u += au * zf * (np.cos(m * lam_f + th[0])[None, None, :]
+                            * np.cos(n * np.pi * (phi_c - phi0) / (ny * dphi) + th[1])[None, :, None])
+            v += av * zf * (np.cos(m * lam_c + th[0])[None, None, :]
+                            * np.sin(n * np.pi * (phi_f - phi0) / (ny * dphi))[None, :, None])
+        scale = flow / max(np.abs(u).max(), np.abs(v).max())
+        u *= scale
+        v *= scale
+        v[:, 0] = 0.0
+        v[:, ny] = 0.0
+    return {"u": u, "v": v, "T": T, "S": S,
+            "eta": np.zeros((1, ny, nx)),
+            "U": (dz * u.sum(axis=0))[None], "V": (dz * v.sum(axis=0))[None],
+            "tau_x": (taux[:, None] * np.ones((1, nx)))[None],
+            "tau_y": np.zeros((1, ny + 1, nx))}

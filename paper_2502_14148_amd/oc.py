@@ -18,7 +18,7 @@ OC_ERR = {-1: "OC_ERR_ARG", -2: "OC_ERR_SHAPE", -3: "OC_ERR_DTYPE", -4: "OC_ERR_
 OC_PERIODIC, OC_BOUNDED = 0, 1
 OC_RECTILINEAR, OC_LATLON = 0, 1
 OC_NONHYDROSTATIC, OC_HYDROSTATIC = 0, 1
-BARO_FIELDS = {"eta": 16, "U": 17, "V": 18, "GU": 19, "GV": 20}
+BARO_FIELDS = {"eta": 16, "U": 17, "V": 18, "GU": 19, "GV": 20, "tau_x": 21, "tau_y": 22}
 OC_FP64, OC_FP32_MIXED = 0, 1
 ADVECTION = {"none": 0, "weno5z": 1, "weno5_linear": 2}
 OC_F32, OC_F64 = 0, 1
@@ -29,15 +29,16 @@ EXPORTS = ("oc_last_error", "oc_grid_create", "oc_grid_destroy", "oc_model_works
            "oc_model_create", "oc_model_destroy", "oc_set_state", "oc_get_state",
            "oc_tendencies", "oc_get_tendency", "oc_pressure_solve", "oc_get_pressure",
            "oc_rk3_step", "oc_diagnostics", "oc_profile", "oc_profile_read",
-           "oc_free_surface_substeps", "oc_mlp_workspace_size", "oc_mlp_create",
+           "oc_free_surface_substeps", "oc_hydrostatic_step", "oc_mlp_workspace_size",
+           "oc_mlp_create",
            "oc_mlp_destroy", "oc_mlp_set_params", "oc_mlp_get_params", "oc_mlp_forward",
            "oc_mlp_gradients", "oc_mlp_train_step", "oc_model_set_closure")
 OC_MLP_NPARAM = 195076
 MLP_SHAPES = (("W1", (256, 500)), ("b1", (256,)), ("W2", (256, 256)), ("b2", (256,)),
               ("W3", (4, 256)), ("b3", (4,)))
-OC_NPROF = 9
+OC_NPROF = 12
 PROF_CLASSES = ("tendency", "fft_x_fwd", "fft_y_fwd", "z_solve", "fft_y_inv", "fft_x_inv",
-                "project", "halo", "closure")
+                "project", "halo", "closure", "hydro_diag", "hydro_tendency", "barotropic")
 
 
 class GridDesc(ctypes.Structure):
@@ -97,6 +98,8 @@ def load_library(path=_LIB_PATH):
         "oc_profile": [vp, i32],
         "oc_profile_read": [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)],
         "oc_free_surface_substeps": [vp, ctypes.c_double, i32, i32, ctypes.POINTER(ctypes.c_double), vp],
+        "oc_hydrostatic_step": [vp, ctypes.c_double, i32, i32, ctypes.POINTER(ctypes.c_double), i32,
+                                vp],
         "oc_mlp_workspace_size": [i32, ctypes.POINTER(ctypes.c_uint64)],
         "oc_mlp_create": [i32, vp, ctypes.c_uint64, ctypes.POINTER(vp)],
         "oc_mlp_destroy": [vp],
@@ -127,8 +130,9 @@ def _stream():
 
 
 class Model:
-    """A nonhydrostatic model on the GPU, configured from a Physics record
-    (see paper_2502_14148_amd.inputs.Physics)."""
+    """A model on the GPU, configured from a Physics record (nonhydrostatic)
+    or a HydrostaticPhysics record (hydrostatic, lat-lon), see
+    paper_2502_14148_amd.inputs."""
 
     def __init__(self, ph, precision="fp64", device="cuda:0"):
         import torch
@@ -192,7 +196,7 @@ class Model:
     def shape_of(self, name):
         ph = self.ph
         if name in BARO_FIELDS:
-            return (1, ph.ny + (1 if name in ("V", "GV") else 0), ph.nx)
+            return (1, ph.ny + (1 if name in ("V", "GV", "tau_y") else 0), ph.nx)
         zb = True if self.hydrostatic else ph.z_bounded
         nzf = ph.nz + 1 if (name == "w" and zb) else ph.nz
         nyf = ph.ny + 1 if (name == "v" and self.hydrostatic) else ph.ny
@@ -218,8 +222,13 @@ class Model:
         self._io(_lib.oc_set_state, name, arr)
 
     def set_states(self, d):
+        """Set every prognostic field present in d (w of the hydrostatic model
+        is diagnostic and skipped)."""
         for name in self.fields:
-            self.set_state(name, d[name])
+            if self.hydrostatic and name == "w":
+                continue
+            if name in d:
+                self.set_state(name, d[name])
 
     def get_state(self, name, out=None, dtype=np.float64):
         if out is None:
@@ -290,6 +299,13 @@ class Model:
                                              ctypes.c_int32(len(w)),
                                              w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                              _stream()))
+
+    def hydrostatic_step(self, dt, N, weights, nsteps=1):
+        w = np.ascontiguousarray(weights, dtype=np.float64)
+        _check(_lib.oc_hydrostatic_step(self._model, ctypes.c_double(dt), ctypes.c_int32(N),
+                                        ctypes.c_int32(len(w)),
+                                        w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                        ctypes.c_int32(nsteps), _stream()))
 
 
 def pack_mlp(params):

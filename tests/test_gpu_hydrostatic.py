@@ -1,0 +1,182 @@
+"""GPU parity of the hydrostatic baroclinic step (column scans, WENO
+vector-invariant momentum, flux-form tracers on the shell, QAB2, coupling to
+the split-explicit barotropic mode) against the FP64 oracle.
+
+Bars: FP64 state 1e-12 relative L2; FP32 state 1e-5 relative L2 (the FP32
+run starts from the FP64 state rounded to FP32).  Tendencies G^n, which
+difference nearly equal FP32 values (kinetic energy, buoyancy), are held to
+1e-4 in FP32."""
+import numpy as np
+import pytest
+
+from paper_2502_14148_amd import inputs
+from oracle import hydrostatic as hso
+
+pytestmark = pytest.mark.gpu
+
+TWO_D = ("eta", "U", "V", "tau_x", "tau_y")
+
+
+def rel_l2(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def _phys(nx=96, ny=24, nz=10, **kw):
+    base = dict(nx=nx, ny=ny, nz=nz, lat0=-70.0, lat_extent=140.0, depth=3000.0)
+    base.update(kw)
+    return inputs.HydrostaticPhysics(**base)
+
+
+def _initial(ph, seed, precision, flow=0.3):
+    # salinity noise so that the S path carries a signal
+    s = inputs.hydrostatic_initial(ph, seed=seed, flow=flow, s_noise=0.05)
+    if precision == "fp32":
+        for k in ("u", "v", "T", "S"):
+            s[k] = s[k].astype(np.float32).astype(np.float64)
+        dz = ph.depth / ph.nz
+        s["U"] = (dz * s["u"].sum(axis=0))[None]
+        s["V"] = (dz * s["v"].sum(axis=0))[None]
+    return s
+
+
+def _load(gpu_lib, ph, precision, s):
+    m = gpu_lib.Model(ph, precision)
+    m.set_states(s)
+    for k in TWO_D:
+        m.set_state(k, s[k])
+    return m
+
+
+def _oracle_state(s):
+    return {k: (s[k][0] if k in TWO_D else s[k]) for k in ("u", "v", "T", "S", "eta", "U", "V")}
+
+
+def _check_run(gpu_lib, ph, precision, nsteps, seed, dt=600.0, N=10):
+    s = _initial(ph, seed, precision)
+    w = inputs.averaging_weights(N)
+    m = _load(gpu_lib, ph, precision, s)
+    m.hydrostatic_step(dt, N, w, nsteps)
+    ref, G = hso.run(_oracle_state(s), ph, s["tau_x"][0], s["tau_y"][0], dt, N, w, nsteps)
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    for k in ("u", "v", "T", "S"):
+        got = m.get_state(k)
+        assert rel_l2(got, ref[k]) < tol, (k, rel_l2(got, ref[k]))
+        if k in ("T", "S") and precision == "fp64":
+            # the change of the tracers, not hidden by their mean
+            d_ref = ref[k] - s[k]
+            assert rel_l2(got - s[k], d_ref) < 1e-10, (k, rel_l2(got - s[k], d_ref))
+    for k in ("eta", "U", "V"):
+        got = m.get_state(k)[0]
+        assert rel_l2(got, ref[k]) < tol, (k, rel_l2(got, ref[k]))
+    gtol = 1e-11 if precision == "fp64" else 1e-4
+    for k in ("u", "v", "T", "S"):
+        got = m.get_tendency(k)
+        assert rel_l2(got, G[k]) < gtol, ("G" + k, rel_l2(got, G[k]))
+    # the diagnosed w of the new state
+    g = hso.LatLonGrid(ph)
+    w_ref = hso.diagnose_w(hso.pad(ref["u"], "c"), hso.pad(ref["v"], "v"), g)
+    assert rel_l2(m.get_state("w"), w_ref) < (1e-11 if precision == "fp64" else 1e-4)
+    # the corrected baroclinic transport equals the barotropic one
+    dz = ph.depth / ph.nz
+    U = m.get_state("U")[0]
+    assert np.abs(dz * m.get_state("u").sum(axis=0) - U).max() < \
+        (1e-9 if precision == "fp64" else 1e-3) * np.abs(U).max()
+    return m, ref
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("nsteps", [1, 3])
+def test_step_parity(gpu_lib, precision, nsteps):
+    # 96 x 24 x 10: one and a half 64-wide column tiles in x, six in y
+    _check_run(gpu_lib, _phys(), precision, nsteps, seed=1)
+
+
+@pytest.mark.parametrize("scheme", ["weno5_linear", "none"])
+def test_step_parity_other_schemes(gpu_lib, scheme):
+    _check_run(gpu_lib, _phys(nx=64, ny=16, nz=8, advection=scheme), "fp64", 2, seed=2)
+
+
+def test_ragged_small_grid(gpu_lib):
+    # nx below one tile width, ny not a multiple of the tile height
+    _check_run(gpu_lib, _phys(nx=40, ny=8, nz=9), "fp64", 2, seed=3)
+
+
+def test_rest_state_stays_at_rest(gpu_lib):
+    ph = _phys(nx=64, ny=16, nz=8)
+    s = inputs.hydrostatic_initial(ph, seed=4, t_noise=0.0, stress_scale=0.0)
+    m = _load(gpu_lib, ph, "fp64", s)
+    N = 10
+    m.hydrostatic_step(600.0, N, inputs.averaging_weights(N), 3)
+    for k in ("u", "v", "w", "eta", "U", "V"):
+        assert np.max(np.abs(m.get_state(k))) == 0.0, k
+
+
+def test_set_state_restarts_history(gpu_lib):
+    # after new initial conditions the next step is an Euler step again and
+    # halos and diagnostics are rebuilt from the new state
+    ph = _phys(nx=64, ny=16, nz=8)
+    N = 8
+    w = inputs.averaging_weights(N)
+    s1 = _initial(ph, 5, "fp64")
+    s2 = _initial(ph, 6, "fp64")
+    m = _load(gpu_lib, ph, "fp64", s1)
+    m.hydrostatic_step(300.0, N, w, 2)
+    m.set_states(s2)
+    for k in TWO_D:
+        m.set_state(k, s2[k])
+    m.hydrostatic_step(300.0, N, w, 1)
+    ref, _ = hso.run(_oracle_state(s2), ph, s2["tau_x"][0], s2["tau_y"][0], 300.0, N, w, 1)
+    for k in ("u", "v", "T", "eta"):
+        got = m.get_state(k)
+        got = got[0] if k == "eta" else got
+        assert rel_l2(got, ref[k]) < 1e-12, k
+
+
+def test_w_is_not_settable(gpu_lib):
+    ph = _phys(nx=64, ny=16, nz=8)
+    m = gpu_lib.Model(ph, "fp64")
+    with pytest.raises(gpu_lib.OcError):
+        m.set_state("w", np.zeros((ph.nz + 1, ph.ny, ph.nx)))
+
+
+def _window_tendencies(s, ph, j0, j1, i0, i1):
+    """Oracle tendencies of the sub-block rows [j0, j1), columns [i0, i1)
+    treated as a domain of its own; exact away from the block's artificial
+    edges (the stencils reach 4 cells), and at real walls."""
+    dlam = ph.lon_extent / ph.nx
+    dphi = ph.lat_extent / ph.ny
+    sub = inputs.HydrostaticPhysics(nx=i1 - i0, ny=j1 - j0, nz=ph.nz,
+                                    lon0=ph.lon0 + i0 * dlam, lon_extent=(i1 - i0) * dlam,
+                                    lat0=ph.lat0 + j0 * dphi, lat_extent=(j1 - j0) * dphi,
+                                    depth=ph.depth)
+    st = {"u": s["u"][:, j0:j1, i0:i1], "v": s["v"][:, j0:j1 + 1, i0:i1].copy(),
+          "T": s["T"][:, j0:j1, i0:i1], "S": s["S"][:, j0:j1, i0:i1]}
+    G, _ = hso.tendencies(st, sub, hso.LatLonGrid(sub), s["tau_x"][0][j0:j1, i0:i1],
+                          s["tau_y"][0][j0:j1 + 1, i0:i1])
+    return G
+
+
+def test_full_size_sector_sampled_windows(gpu_lib):
+    # the 1440 x 560 x 50 sector in FP32, one step: G^n checked against the
+    # oracle on sampled windows (interior, both walls), and the column
+    # consistency of the corrected velocity everywhere
+    ph = inputs.sector_physics()
+    s = _initial(ph, 7, "fp32")
+    N = 30
+    m = _load(gpu_lib, ph, "fp32", s)
+    m.hydrostatic_step(600.0, N, inputs.averaging_weights(N), 1)
+    G = {k: m.get_tendency(k, dtype=np.float32) for k in ("u", "v", "T", "S")}
+    B, mg = 24, 6
+    cases = [(200, 700, slice(mg, B - mg)), (0, 333, slice(0, B - mg)),
+             (ph.ny - B, 1100, slice(mg, B))]
+    for j0, i0, rows in cases:
+        Gw = _window_tendencies(s, ph, j0, j0 + B, i0, i0 + B)
+        cols = slice(mg, B - mg)
+        for k in ("u", "v", "T", "S"):
+            ref = Gw[k][:, rows, cols]
+            got = G[k][:, j0:j0 + B, i0:i0 + B][:, rows, cols]
+            assert rel_l2(got, ref) < 1e-4, (j0, i0, k, rel_l2(got, ref))
+    dz = ph.depth / ph.nz
+    U = m.get_state("U")[0]
+    u = m.get_state("u", dtype=np.float32)
+    assert np.abs(dz * u.sum(axis=0, dtype=np.float64) - U).max() < 1e-3 * np.abs(U).max()
