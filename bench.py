@@ -151,6 +151,54 @@ def run_hydrostatic(steps, warmup, N=30):
             "finite": finite}
 
 
+def run_ensemble(steps, warmup):
+    """16 x 64^3 + 16 x 96^3 + 16 x 128^3 free-convection members (FP32),
+    stepped together (autotuned fused launches, HIP graph replay) and, for
+    comparison, one by one with oc_rk3_step."""
+    import torch
+    from paper_2502_14148_amd import inputs, oc
+    members = inputs.ensemble_physics()
+    print("# generating 48 ensemble members", file=sys.stderr, flush=True)
+    ms = []
+    for ph, seed in members:
+        m = oc.Model(ph, "fp32")
+        m.set_states(inputs.convection_initial(ph, seed=seed))
+        ms.append(m)
+    ncells = sum(ph.nx * ph.ny * ph.nz for ph, _ in members)
+    dt = 1.0
+    e = oc.Ensemble(ms, tune=True, graph=True)
+    stream = torch.cuda.current_stream()
+    e.step(dt, warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    e.step(dt, steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_ens = e0.elapsed_time(e1)
+    for m in ms:
+        m.rk3_step(dt, 1)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for m in ms:
+        m.rk3_step(dt, steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_seq = e0.elapsed_time(e1)
+    tn = e.tuning()
+    del e, ms
+    torch.cuda.empty_cache()
+    return {"value": ncells * steps / (ms_ens / 1e3), "unit": "cell-steps/s", "steps": steps,
+            "ms_per_step": ms_ens / steps, "dtype": "f32",
+            "config": {"workload": "48 free-convection LES members: 16 x 64^3, 16 x 96^3, "
+                                   "16 x 128^3, 512 x 512 x 256 m, surface flux U(0.5, 2)e-8",
+                       "cells": ncells, "dt_s": dt},
+            "one_by_one": {"value": ncells * steps / (ms_seq / 1e3), "ms_per_step": ms_seq / steps},
+            "speedup_vs_one_by_one": ms_seq / ms_ens,
+            "tuning": tn}
+
+
 def cpu_baseline(n_sample):
     """The FP64 oracle (NumPy) on a bounded sample: one RK3 step of the same
     physics and horizontal grid on a slab of n_sample levels."""
@@ -178,6 +226,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-levels", type=int, default=32)
     ap.add_argument("--no-hydrostatic", action="store_true")
+    ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--ensemble-steps", type=int, default=20)
     ap.add_argument("--hydro-steps", type=int, default=20)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain 512 MiB device copy (counter calibration)")
@@ -246,6 +296,9 @@ def main():
     if not a.no_hydrostatic:
         print("# hydrostatic sector run", file=sys.stderr, flush=True)
         out["hydrostatic"] = run_hydrostatic(a.hydro_steps, 2)
+    if not a.no_ensemble:
+        print("# ensemble run", file=sys.stderr, flush=True)
+        out["ensemble"] = run_ensemble(a.ensemble_steps, 2)
     if not a.no_cpu:
         print("# CPU oracle sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(a.cpu_levels)

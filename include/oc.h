@@ -227,6 +227,44 @@ int oc_free_surface_substeps(oc_model* m, double dt, int32_t N, int32_t M, const
 int oc_hydrostatic_step(oc_model* m, double dt, int32_t N, int32_t M, const double* a,
                         int32_t nsteps, void* stream);
 
+/* ---- Ensembles: many nonhydrostatic models stepped together ----
+ * The paper's case for GPUs is the throughput of many moderate-size
+ * simulations (introduction; ensembles for parameter studies).  An ensemble
+ * borrows existing models (created, filled and read with the calls above;
+ * they must outlive it) and advances all of them by the RK3 step of
+ * oc_rk3_step with one dt: per substage one fused tendency + RK3 launch over
+ * every member's column tiles, and per class of members with equal grids one
+ * launch per Poisson pass.  Results equal those of oc_rk3_step on each
+ * member.  Members: nonhydrostatic, WENO5-Z, tracers T and S, no learned
+ * closure, one precision, nx and ny multiples of 8.
+ * Flags: OC_ENS_TUNE times the candidate launch configurations (column tile
+ * 32x8, 16x8 or 8x8; one workgroup per tile or a persistent grid draining an
+ * atomic work queue; k-chunk length) at creation and keeps the fastest; with
+ * the environment variable OC_TUNE_CACHE naming a file, choices are read
+ * from and appended to it (JSON lines keyed by GPU architecture, precision
+ * and member sizes).  OC_ENS_GRAPH captures one RK3 step per buffer parity
+ * as a HIP graph on the first call (again when dt changes) and replays it.
+ * Workspace: caller-owned device memory of oc_ensemble_workspace_size bytes
+ * (member tables, work list, Poisson pointer tables). */
+typedef struct oc_ensemble oc_ensemble;
+enum { OC_ENS_TUNE = 1, OC_ENS_GRAPH = 2 };
+/* Errors: OC_ERR_ARG (NULL, count outside 1..4096, repeated member, mixed
+ * precision), OC_ERR_UNSUPPORTED (a member outside the list above). */
+int oc_ensemble_workspace_size(oc_model* const* members, int32_t count, uint64_t* bytes);
+int oc_ensemble_create(oc_model* const* members, int32_t count, void* workspace, uint64_t bytes,
+                       int32_t flags, oc_ensemble** out);
+/* nsteps RK3 steps of every member on `stream`; afterwards each member's
+ * state is read as usual.  A member stepped on its own in between is picked
+ * up where it stands.  Errors: OC_ERR_ARG for dt <= 0 or nsteps < 0,
+ * OC_ERR_DEVICE on a HIP failure. */
+int oc_ensemble_step(oc_ensemble* e, double dt, int32_t nsteps, void* stream);
+/* The launch configuration in use: out[0] tile (0: 32x8, 1: 16x8, 2: 8x8),
+ * out[1] persistent grid (0/1), out[2] workgroups of the persistent grid,
+ * out[3] k-chunk divisor, out[4] 0 default / 1 timed / 2 from the cache,
+ * out[5] work items per launch; *ms (optional) the timed launch. */
+int oc_ensemble_tuning(const oc_ensemble* e, int32_t* out, double* ms);
+int oc_ensemble_destroy(oc_ensemble* e);
+
 /* ---- Learned subgrid closure (an MLP trained on coarse-grained fluxes) ----
  * The network maps the standardised 5x5x5 neighbourhood of (u, v, w, b) of a
  * coarse cell (500 values, variable-major, offsets (dk, dj, di) in C order)

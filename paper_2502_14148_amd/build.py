@@ -27,7 +27,8 @@ FLAGS = [
 ]
 
 SOURCES = ["api.hip", "stencil.hip", "poisson.hip", "tendency.hip", "barotropic.hip", "mlp.hip",
-           "closure_api.hip", "hydrostatic.hip"]
+           "closure_api.hip", "hydrostatic.hip",
+           "ensemble_api.hip"]
 
 
 def _compile(src, defines=(), build_dir=None):

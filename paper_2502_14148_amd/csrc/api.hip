@@ -8,7 +8,7 @@
 #include <new>
 #include <vector>
 
-#include "oc_internal.h"
+#include "model.h"
 
 namespace oc {
 
@@ -21,11 +21,6 @@ void set_error(const char* fmt, ...) {
   va_end(ap);
 }
 
-// RK3 coefficients (rk3 equation): gamma = (8/15, 5/12, 3/4),
-// zeta = (0, 17/60, 5/12).
-static const double RK_GAMMA[3] = {8.0 / 15.0, 5.0 / 12.0, 3.0 / 4.0};
-static const double RK_ZETA[3] = {0.0, 17.0 / 60.0, 5.0 / 12.0};
-
 static const int DIAG_BLOCKS = 1024;
 static const int DIAG_PARTS = 9;
 
@@ -33,59 +28,6 @@ static const int DIAG_PARTS = 9;
 
 using namespace oc;
 
-struct oc_grid {
-  oc_grid_desc d;
-};
-
-struct oc_model {
-  oc_grid_desc gd;
-  oc_model_desc md;
-  Dims dims;
-  int nf;
-  int esz;
-  int kinds[MAXF];
-  char* ws;
-  uint64_t ws_bytes;
-  void* state[2][MAXF];
-  void* G[MAXF];
-  int cur;
-  SpecBufs sb;
-  double offset[MAXF];  // storage offset per field: stored = value - offset
-  void* staging;
-  double* diag_part;
-  double dx, dy, dz;
-  int kind;              // OC_NONHYDROSTATIC or OC_HYDROSTATIC
-  // hydrostatic model: 2D barotropic state (FP64), ping-pong (eta, U, V)
-  double* eta[2];
-  double* ubt[2];
-  double* vbt[2];
-  double* gubt;
-  double* gvbt;
-  double* etab;
-  double* ubar;
-  double* vbar;
-  double* metric;        // len_u | dx_u | len_v | dy_v | area
-  int bcur;
-  // hydrostatic baroclinic step: diagnostic fields (state precision,
-  // padded), row tables, surface stress, and the QAB2 / refresh flags
-  void* hzeta;
-  void* hpx;
-  void* hpy;
-  double* hmet;
-  double* taux;
-  double* tauy;
-  int hfirst;            // the next step is a first (Euler) step
-  int hstale;            // halos and diagnostic fields need a refresh
-  // learned closure: network, statistics, tendency buffers (u, v, w, T)
-  oc_mlp* net;
-  ClosureStats cst;
-  void* gc[4];
-  // per-kernel-class event timing
-  int prof_on;
-  std::vector<hipEvent_t> ev_pool;
-  size_t ev_used;
-  std::vector<int> prof_cls;  // class of each recorded (start, stop) pair
-};
 
 namespace {
 
@@ -333,36 +275,6 @@ int halo_one(oc_model* m, int which, int field, hipStream_t s) {
   return OC_OK;
 }
 
-template <class T>
-TendParams<T> tend_params(const oc_model* m) {
-  TendParams<T> p;
-  const oc_model_desc& d = m->md;
-  p.rdx = (T)(1.0 / m->dx);
-  p.rdy = (T)(1.0 / m->dy);
-  p.rdz = (T)(1.0 / m->dz);
-  p.nu = (T)d.nu;
-  p.kappa = (T)d.kappa;
-  p.f = (T)d.f;
-  p.g_alpha = (T)(d.g * d.alpha);
-  p.g_beta = (T)(d.g * d.beta);
-  // FP32 storage keeps T and S as anomalies about (t_ref, s_ref)
-  p.t_ref = (T)(d.t_ref - m->offset[OC_TRACER0]);
-  p.s_ref = (T)(d.s_ref - m->offset[OC_TRACER0 + 1]);
-  p.buoyancy = d.buoyancy ? 1 : 0;
-  p.ntr = d.ntracers;
-  for (int q = 0; q < OC_MAX_TRACERS; ++q) {
-    p.top_flux[q] = (T)(m->dims.zb ? d.top_flux[q] : 0.0);
-    p.toff[q] = (T)((OC_TRACER0 + q < m->nf) ? m->offset[OC_TRACER0 + q] : 0.0);
-  }
-  p.eps = (T)d.weno_eps;
-  p.dt = 0;
-  p.gam = 0;
-  p.zet = 0;
-  p.stage = 0;
-  p.combine = 0;
-  p.images = 0;
-  return p;
-}
 
 template <class T>
 int tendency_call(oc_model* m, int in, int out, int stage, double dt, int combine,

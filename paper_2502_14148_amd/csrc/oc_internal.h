@@ -259,15 +259,60 @@ template <class T>
 hipError_t launch_tendency_fast(const Dims& d, const FieldSet<T>& fs, const TendParams<T>& p,
                                 int scheme, hipStream_t s);
 struct Spacing { double rdx, rdy, rdz; };
+
+// ---- Ensembles: one tendency launch for many models
+// Member descriptor (device table): the state pointers for both buffer
+// parities and the tendency parameters of the three RK3 substages.
+template <class T>
+struct EnsMember {
+  Dims d;
+  int nbx, nby, nbz, kc;     // column tiles and k chunks of this member
+  FieldSet<T> fs[2];         // parity 0: in = A, out = B; parity 1: swapped
+  TendParams<T> P[3];
+};
+// Launch configuration picked by the autotuner: tile 0 = 32 x 8, 1 = 16 x 8,
+// 2 = 8 x 8 columns; persistent grid of nblocks workgroups or one per item.
+struct EnsTuning {
+  int tile;
+  int persistent;
+  int nblocks;
+  int kc_div;
+};
+constexpr int ENS_TILE_X[3] = {32, 16, 8};
+constexpr int ENS_TILE_Y[3] = {8, 8, 8};
+template <class T>
+hipError_t launch_tendency_ensemble(const EnsMember<T>* mem, const int2* items, int nitems,
+                                   int* counter, int parity, int stage, const EnsTuning& tn,
+                                   hipStream_t s);
+
+template <class T>
+int ensemble_blocks_per_cu(int tile);
+
+// Per-member pointers of a batched Poisson launch (member = blockIdx.z).
+constexpr int ENS_MAX_SLOTS = 64;
+struct PoissonSlots {
+  void* u[ENS_MAX_SLOTS];
+  void* v[ENS_MAX_SLOTS];
+  void* w[ENS_MAX_SLOTS];
+  double2* spec[ENS_MAX_SLOTS];
+  double* p[ENS_MAX_SLOTS];
+};
 template <class T>
 hipError_t launch_poisson_x_forward(const Dims& d, const T* u, const T* v, const T* w,
-                                   double inv_dt, Spacing sp, const SpecBufs& sb, hipStream_t s);
-hipError_t launch_poisson_y(const Dims& d, const SpecBufs& sb, int dir, hipStream_t s);
-hipError_t launch_poisson_spectral(const Dims& d, const SpecBufs& sb, hipStream_t s);
-hipError_t launch_poisson_x_inverse(const Dims& d, const SpecBufs& sb, hipStream_t s);
+                                   double inv_dt, Spacing sp, const SpecBufs& sb, hipStream_t s,
+                                   const PoissonSlots* bs = nullptr, int nslots = 1);
+// bs (device table, may be null): nslots members of identical dims and tables
+// transformed in one launch, member z taking its pointers from slot z
+hipError_t launch_poisson_y(const Dims& d, const SpecBufs& sb, int dir, hipStream_t s,
+                            const PoissonSlots* bs = nullptr, int nslots = 1);
+hipError_t launch_poisson_spectral(const Dims& d, const SpecBufs& sb, hipStream_t s,
+                                   const PoissonSlots* bs = nullptr, int nslots = 1);
+hipError_t launch_poisson_x_inverse(const Dims& d, const SpecBufs& sb, hipStream_t s,
+                                    const PoissonSlots* bs = nullptr, int nslots = 1);
 template <class T>
 hipError_t launch_project(const Dims& d, T* u, T* v, T* w, double scale, double rdx,
-                          double rdy, double rdz, const double* p, hipStream_t s);
+                          double rdy, double rdz, const double* p, hipStream_t s,
+                          const PoissonSlots* bs = nullptr, int nslots = 1);
 template <class T>
 hipError_t launch_pack(const Dims& d, int nzf, int nyf, const T* padded, void* dense, int dtype,
                        int to_dense, double offset, hipStream_t s);

@@ -125,7 +125,15 @@ __global__ void __launch_bounds__(NT) fwd_x_kernel(Dims d, const T* __restrict__
                                                    const T* __restrict__ v,
                                                    const T* __restrict__ w, double inv_dt,
                                                    double rdx, double rdy, double rdz,
-                                                   SpecBufs sb) {
+                                                   SpecBufs sb,
+                                                   const PoissonSlots* __restrict__ bs) {
+  if (bs) {
+    const int z = blockIdx.z;
+    u = (const T*)bs->u[z];
+    v = (const T*)bs->v[z];
+    w = (const T*)bs->w[z];
+    sb.spec = bs->spec[z];
+  }
   constexpr int LP = XCfg<N>::LP;
   __shared__ double2 buf[LP * N];
   const int k = blockIdx.y;
@@ -180,7 +188,9 @@ __global__ void __launch_bounds__(NT) fwd_x_kernel(Dims d, const T* __restrict__
 // Passes 2 and 4: complex FFT along y for W consecutive kx columns.
 // ---------------------------------------------------------------------------
 template <int N, int DIR>
-__global__ void __launch_bounds__(NT) y_kernel(Dims d, SpecBufs sb) {
+__global__ void __launch_bounds__(NT) y_kernel(Dims d, SpecBufs sb,
+                                               const PoissonSlots* __restrict__ bs) {
+  if (bs) sb.spec = bs->spec[blockIdx.z];
   constexpr int W = YZCfg<N>::W;
   __shared__ double2 buf[W * N];
   const int k = blockIdx.y;
@@ -209,7 +219,9 @@ __device__ inline int makhoul_pos(int m, int n) {
 }
 
 template <int N, bool BOUNDED>
-__global__ void __launch_bounds__(NT) z_kernel(Dims d, SpecBufs sb, double norm) {
+__global__ void __launch_bounds__(NT) z_kernel(Dims d, SpecBufs sb, double norm,
+                                               const PoissonSlots* __restrict__ bs) {
+  if (bs) sb.spec = bs->spec[blockIdx.z];
   constexpr int W = YZCfg<N>::W;
   constexpr int PER = (W * N + NT - 1) / NT;
   __shared__ double2 buf[W * N];
@@ -280,7 +292,12 @@ __global__ void __launch_bounds__(NT) z_kernel(Dims d, SpecBufs sb, double norm)
 // Pass 5: complex-to-real inverse FFT along x for line pairs -> p.
 // ---------------------------------------------------------------------------
 template <int N>
-__global__ void __launch_bounds__(NT) inv_x_kernel(Dims d, SpecBufs sb) {
+__global__ void __launch_bounds__(NT) inv_x_kernel(Dims d, SpecBufs sb,
+                                                   const PoissonSlots* __restrict__ bs) {
+  if (bs) {
+    sb.spec = bs->spec[blockIdx.z];
+    sb.p = bs->p[blockIdx.z];
+  }
   constexpr int LP = XCfg<N>::LP;
   __shared__ double2 buf[LP * N];
   const int k = blockIdx.y;
@@ -320,7 +337,15 @@ template <class T>
 __global__ void __launch_bounds__(256) project_kernel(Dims d, T* __restrict__ u, T* __restrict__ v,
                                                       T* __restrict__ w, double scale, double rdx,
                                                       double rdy, double rdz,
-                                                      const double* __restrict__ p) {
+                                                      const double* __restrict__ p,
+                                                      const PoissonSlots* __restrict__ bs) {
+  if (bs) {
+    const int z = blockIdx.z;
+    u = (T*)bs->u[z];
+    v = (T*)bs->v[z];
+    w = (T*)bs->w[z];
+    p = bs->p[z];
+  }
   const long n = (long)d.nx * d.ny * d.nz;
   const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
@@ -371,52 +396,56 @@ bool fft_length_supported(int n) {
 
 template <class T>
 hipError_t launch_poisson_x_forward(const Dims& d, const T* u, const T* v, const T* w,
-                                   double inv_dt, Spacing sp, const SpecBufs& sb, hipStream_t s) {
+                                   double inv_dt, Spacing sp, const SpecBufs& sb, hipStream_t s,
+                                   const PoissonSlots* bs, int nslots) {
 #define OC_LAUNCH_FX(N)                                                                    \
   {                                                                                        \
-    dim3 grid((d.ny / 2 + XCfg<N>::LP - 1) / XCfg<N>::LP, d.nz);                          \
+    dim3 grid((d.ny / 2 + XCfg<N>::LP - 1) / XCfg<N>::LP, d.nz, nslots);                  \
     hipLaunchKernelGGL((fwd_x_kernel<T, N>), grid, dim3(NT), 0, s, d, u, v, w, inv_dt,    \
-                       sp.rdx, sp.rdy, sp.rdz, sb);                                        \
+                       sp.rdx, sp.rdy, sp.rdz, sb, bs);                                    \
   }
   OC_FFT_DISPATCH(d.nx, OC_LAUNCH_FX)
 #undef OC_LAUNCH_FX
   return hipGetLastError();
 }
 
-hipError_t launch_poisson_y(const Dims& d, const SpecBufs& sb, int dir, hipStream_t s) {
+hipError_t launch_poisson_y(const Dims& d, const SpecBufs& sb, int dir, hipStream_t s,
+                            const PoissonSlots* bs, int nslots) {
 #define OC_LAUNCH_Y(N)                                                                     \
   {                                                                                        \
-    dim3 grid((sb.nxh + YZCfg<N>::W - 1) / YZCfg<N>::W, d.nz);                            \
+    dim3 grid((sb.nxh + YZCfg<N>::W - 1) / YZCfg<N>::W, d.nz, nslots);                    \
     if (dir < 0)                                                                           \
-      hipLaunchKernelGGL((y_kernel<N, -1>), grid, dim3(NT), 0, s, d, sb);                 \
+      hipLaunchKernelGGL((y_kernel<N, -1>), grid, dim3(NT), 0, s, d, sb, bs);             \
     else                                                                                   \
-      hipLaunchKernelGGL((y_kernel<N, 1>), grid, dim3(NT), 0, s, d, sb);                  \
+      hipLaunchKernelGGL((y_kernel<N, 1>), grid, dim3(NT), 0, s, d, sb, bs);              \
   }
   OC_FFT_DISPATCH(d.ny, OC_LAUNCH_Y)
 #undef OC_LAUNCH_Y
   return hipGetLastError();
 }
 
-hipError_t launch_poisson_spectral(const Dims& d, const SpecBufs& sb, hipStream_t s) {
+hipError_t launch_poisson_spectral(const Dims& d, const SpecBufs& sb, hipStream_t s,
+                                   const PoissonSlots* bs, int nslots) {
   const double norm = 1.0 / ((double)d.nx * d.ny * d.nz);
 #define OC_LAUNCH_Z(N)                                                                     \
   {                                                                                        \
-    dim3 grid((sb.nxh + YZCfg<N>::W - 1) / YZCfg<N>::W, d.ny);                            \
+    dim3 grid((sb.nxh + YZCfg<N>::W - 1) / YZCfg<N>::W, d.ny, nslots);                    \
     if (d.zb)                                                                              \
-      hipLaunchKernelGGL((z_kernel<N, true>), grid, dim3(NT), 0, s, d, sb, norm);         \
+      hipLaunchKernelGGL((z_kernel<N, true>), grid, dim3(NT), 0, s, d, sb, norm, bs);     \
     else                                                                                   \
-      hipLaunchKernelGGL((z_kernel<N, false>), grid, dim3(NT), 0, s, d, sb, norm);        \
+      hipLaunchKernelGGL((z_kernel<N, false>), grid, dim3(NT), 0, s, d, sb, norm, bs);    \
   }
   OC_FFT_DISPATCH(d.nz, OC_LAUNCH_Z)
 #undef OC_LAUNCH_Z
   return hipGetLastError();
 }
 
-hipError_t launch_poisson_x_inverse(const Dims& d, const SpecBufs& sb, hipStream_t s) {
+hipError_t launch_poisson_x_inverse(const Dims& d, const SpecBufs& sb, hipStream_t s,
+                                    const PoissonSlots* bs, int nslots) {
 #define OC_LAUNCH_XI(N)                                                                    \
   {                                                                                        \
-    dim3 grid((d.ny / 2 + XCfg<N>::LP - 1) / XCfg<N>::LP, d.nz);                          \
-    hipLaunchKernelGGL((inv_x_kernel<N>), grid, dim3(NT), 0, s, d, sb);                   \
+    dim3 grid((d.ny / 2 + XCfg<N>::LP - 1) / XCfg<N>::LP, d.nz, nslots);                  \
+    hipLaunchKernelGGL((inv_x_kernel<N>), grid, dim3(NT), 0, s, d, sb, bs);               \
   }
   OC_FFT_DISPATCH(d.nx, OC_LAUNCH_XI)
 #undef OC_LAUNCH_XI
@@ -425,22 +454,27 @@ hipError_t launch_poisson_x_inverse(const Dims& d, const SpecBufs& sb, hipStream
 
 template <class T>
 hipError_t launch_project(const Dims& d, T* u, T* v, T* w, double scale, double rdx, double rdy,
-                          double rdz, const double* p, hipStream_t s) {
+                          double rdz, const double* p, hipStream_t s, const PoissonSlots* bs,
+                          int nslots) {
   const long n = (long)d.nx * d.ny * d.nz;
-  hipLaunchKernelGGL(project_kernel<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, d, u,
-                     v, w, scale, rdx, rdy, rdz, p);
+  hipLaunchKernelGGL(project_kernel<T>, dim3((unsigned)((n + 255) / 256), 1, nslots), dim3(256), 0,
+                     s, d, u, v, w, scale, rdx, rdy, rdz, p, bs);
   return hipGetLastError();
 }
 
 template hipError_t launch_poisson_x_forward<float>(const Dims&, const float*, const float*,
                                                     const float*, double, Spacing,
-                                                    const SpecBufs&, hipStream_t);
+                                                    const SpecBufs&, hipStream_t,
+                                                    const PoissonSlots*, int);
 template hipError_t launch_poisson_x_forward<double>(const Dims&, const double*, const double*,
                                                      const double*, double, Spacing,
-                                                     const SpecBufs&, hipStream_t);
+                                                     const SpecBufs&, hipStream_t,
+                                                     const PoissonSlots*, int);
 template hipError_t launch_project<float>(const Dims&, float*, float*, float*, double, double,
-                                          double, double, const double*, hipStream_t);
+                                          double, double, const double*, hipStream_t,
+                                          const PoissonSlots*, int);
 template hipError_t launch_project<double>(const Dims&, double*, double*, double*, double, double,
-                                           double, double, const double*, hipStream_t);
+                                           double, double, const double*, hipStream_t,
+                                           const PoissonSlots*, int);
 
 }  // namespace oc

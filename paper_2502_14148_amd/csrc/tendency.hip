@@ -110,10 +110,12 @@ __device__ inline void slot_fluxes(T* S, const SlotOff& o, int L, int sd, int se
 #define OC_TEND_WAVES 4
 #endif
 
+// One column tile: tile b of an nbx x nby x nbz decomposition (k chunks of
+// kc levels) of the grid d.
 template <class T, int SCHEME, int NTR, int TX, int TY>
-__global__ void __launch_bounds__(TX * TY)
-__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? OC_TEND_WAVES : 2)))
-tendency_zmarch(Dims d, FieldSet<T> fs, TendParams<T> P, int nbx, int nby, int nbz, int kc) {
+__device__ __attribute__((always_inline)) inline void tendency_tile(
+    const Dims& d, const FieldSet<T>& fs, const TendParams<T>& P, int nbx, int nby, int nbz,
+    int kc, int b) {
   constexpr int NT = TX * TY;
   constexpr int PX = TX + 6, PY = TY + 6, PL = PX * PY;
   constexpr int NXS = (TX + 1) * TY, NYS = TX * (TY + 1);
@@ -126,10 +128,6 @@ tendency_zmarch(Dims d, FieldSet<T> fs, TendParams<T> P, int nbx, int nby, int n
   constexpr int NLDS = OFY + NF * NYS;
   __shared__ T S[NLDS];
 
-  // ---- tile of this workgroup, XCD-major order
-  const int nblk = nbx * nby * nbz;
-  int b = blockIdx.x;
-  if ((nblk & 7) == 0) b = (b & 7) * (nblk >> 3) + (b >> 3);
   const int bx = b % nbx;
   const int by = (b / nbx) % nby;
   const int bz = b / (nbx * nby);
@@ -378,6 +376,52 @@ tendency_zmarch(Dims d, FieldSet<T> fs, TendParams<T> P, int nbx, int nby, int n
   }
 }
 
+#define OC_TEND_ATTRS(T, TX, TY)   \
+  __launch_bounds__(TX * TY)      \
+  __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? OC_TEND_WAVES : 2)))
+
+// One model; tiles are mapped XCD-major, so neighbouring tiles (which share
+// halo loads) land on the same XCD and its L2.
+template <class T, int SCHEME, int NTR, int TX, int TY>
+__global__ void OC_TEND_ATTRS(T, TX, TY)
+tendency_zmarch(Dims d, FieldSet<T> fs, TendParams<T> P, int nbx, int nby, int nbz, int kc) {
+  const int nblk = nbx * nby * nbz;
+  int b = blockIdx.x;
+  if ((nblk & 7) == 0) b = (b & 7) * (nblk >> 3) + (b >> 3);
+  tendency_tile<T, SCHEME, NTR, TX, TY>(d, fs, P, nbx, nby, nbz, kc, b);
+}
+
+// An ensemble of models in one launch.  Work items (member, tile) come from
+// `items`; PERSIST = false: one workgroup per item; PERSIST = true: a grid of
+// resident workgroups takes items from the atomic counter until the list is
+// exhausted (every workgroup leaves the loop once the counter passes nitems).
+template <class T, int SCHEME, int NTR, int TX, int TY, bool PERSIST>
+__global__ void OC_TEND_ATTRS(T, TX, TY)
+tendency_ensemble(const EnsMember<T>* __restrict__ mem, const int2* __restrict__ items,
+                  int nitems, int* __restrict__ counter, int parity, int stage) {
+  if (!PERSIST) {
+    const int2 it = items[blockIdx.x];
+    const EnsMember<T>& M = mem[it.x];
+    tendency_tile<T, SCHEME, NTR, TX, TY>(M.d, M.fs[parity], M.P[stage], M.nbx, M.nby, M.nbz,
+                                          M.kc, it.y);
+    return;
+  }
+  __shared__ int s_item;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+    __syncthreads();
+    const int item = __builtin_amdgcn_readfirstlane(s_item);
+    if (item >= nitems) break;
+    const int2 it = items[item];
+    const EnsMember<T>& M = mem[it.x];
+    tendency_tile<T, SCHEME, NTR, TX, TY>(M.d, M.fs[parity], M.P[stage], M.nbx, M.nby, M.nbz,
+                                          M.kc, it.y);
+    __syncthreads();  // LDS and s_item are reused by the next item
+  }
+}
+
+__global__ void reset_counter_kernel(int* counter) { counter[0] = 0; }
+
 }  // namespace tz
 
 template <class T>
@@ -415,6 +459,60 @@ hipError_t launch_tendency_fast(const Dims& d, const FieldSet<T>& fs, const Tend
 #undef OC_TZ
   return hipGetLastError();
 }
+
+template <class T>
+hipError_t launch_tendency_ensemble(const EnsMember<T>* mem, const int2* items, int nitems,
+                                   int* counter, int parity, int stage, const EnsTuning& tn,
+                                   hipStream_t s) {
+  if (nitems <= 0) return hipSuccess;
+  if (tn.persistent) hipLaunchKernelGGL(tz::reset_counter_kernel, dim3(1), dim3(1), 0, s, counter);
+  const int nblk = tn.persistent ? tn.nblocks : nitems;
+#define OC_TE(TX_, TY_, P_)                                                                  \
+  hipLaunchKernelGGL((tz::tendency_ensemble<T, tz::SCHEME_WENOZ, 2, TX_, TY_, P_>),          \
+                     dim3(nblk), dim3(TX_ * TY_), 0, s, mem, items, nitems, counter, parity, \
+                     stage)
+#define OC_TE_P(TX_, TY_) \
+  if (tn.persistent) { OC_TE(TX_, TY_, true); } else { OC_TE(TX_, TY_, false); }
+  switch (tn.tile) {
+    case 0: OC_TE_P(32, 8); break;
+    case 1: OC_TE_P(16, 8); break;
+    default: OC_TE_P(8, 8); break;
+  }
+#undef OC_TE_P
+#undef OC_TE
+  return hipGetLastError();
+}
+
+// Resident workgroups per CU of the persistent ensemble kernel of a tile
+// shape (from the kernel's registers and LDS).
+template <class T>
+int ensemble_blocks_per_cu(int tile) {
+  int n = 0;
+  hipError_t e;
+  switch (tile) {
+    case 0:
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &n, tz::tendency_ensemble<T, tz::SCHEME_WENOZ, 2, 32, 8, true>, 256, 0);
+      break;
+    case 1:
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &n, tz::tendency_ensemble<T, tz::SCHEME_WENOZ, 2, 16, 8, true>, 128, 0);
+      break;
+    default:
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &n, tz::tendency_ensemble<T, tz::SCHEME_WENOZ, 2, 8, 8, true>, 64, 0);
+  }
+  return (e == hipSuccess && n > 0) ? n : 1;
+}
+template int ensemble_blocks_per_cu<float>(int);
+template int ensemble_blocks_per_cu<double>(int);
+
+template hipError_t launch_tendency_ensemble<float>(const EnsMember<float>*, const int2*, int,
+                                                    int*, int, int, const EnsTuning&,
+                                                    hipStream_t);
+template hipError_t launch_tendency_ensemble<double>(const EnsMember<double>*, const int2*, int,
+                                                     int*, int, int, const EnsTuning&,
+                                                     hipStream_t);
 
 template hipError_t launch_tendency_fast<float>(const Dims&, const FieldSet<float>&,
                                                 const TendParams<float>&, int, hipStream_t);

@@ -214,6 +214,22 @@ def convection_initial(ph: Physics, seed: int = 0, noise: float = 1e-3,
     return {"u": u, "v": v, "w": w, "T": T, "S": S}
 
 
+def ensemble_physics(sizes=(64, 96, 128), per_size: int = 16, seed: int = 0,
+                     extent=(512.0, 512.0, 256.0), flux_range=(0.5e-8, 2.0e-8)):
+    """Members of the uneven-size LES ensemble: `per_size` free-convection
+    runs at each N^3 of `sizes`, all in the same domain, with surface
+    buoyancy fluxes drawn uniformly from flux_range (seeded).  Returns a list
+    of (Physics, member seed)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for n in sizes:
+        for _ in range(per_size):
+            jb = float(rng.uniform(*flux_range))
+            out.append((convection_physics((n, n, n), extent, surface_buoyancy_flux=jb),
+                        int(rng.integers(0, 2 ** 31 - 1))))
+    return out
+
+
 def random_state(ph: Physics, seed: int = 0, vel: float = 1.0, tracer_scale: float = 1.0,
                  divergence_free: bool = True):
     """Rough random state for parity tests (every cell independent).

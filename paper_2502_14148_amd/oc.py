@@ -32,7 +32,10 @@ EXPORTS = ("oc_last_error", "oc_grid_create", "oc_grid_destroy", "oc_model_works
            "oc_free_surface_substeps", "oc_hydrostatic_step", "oc_mlp_workspace_size",
            "oc_mlp_create",
            "oc_mlp_destroy", "oc_mlp_set_params", "oc_mlp_get_params", "oc_mlp_forward",
-           "oc_mlp_gradients", "oc_mlp_train_step", "oc_model_set_closure")
+           "oc_mlp_gradients", "oc_mlp_train_step", "oc_model_set_closure",
+           "oc_ensemble_workspace_size", "oc_ensemble_create", "oc_ensemble_step",
+           "oc_ensemble_tuning", "oc_ensemble_destroy")
+OC_ENS_TUNE, OC_ENS_GRAPH = 1, 2
 OC_MLP_NPARAM = 195076
 MLP_SHAPES = (("W1", (256, 500)), ("b1", (256,)), ("W2", (256, 256)), ("b2", (256,)),
               ("W3", (4, 256)), ("b3", (4,)))
@@ -109,6 +112,12 @@ def load_library(path=_LIB_PATH):
         "oc_mlp_gradients": [vp, vp, vp, i32, vp, ctypes.POINTER(ctypes.c_double), vp],
         "oc_mlp_train_step": [vp, vp, vp, i32, ctypes.c_float, ctypes.POINTER(ctypes.c_double), vp],
         "oc_model_set_closure": [vp, vp, ctypes.POINTER(ctypes.c_double), vp],
+        "oc_ensemble_workspace_size": [ctypes.POINTER(vp), i32, ctypes.POINTER(ctypes.c_uint64)],
+        "oc_ensemble_create": [ctypes.POINTER(vp), i32, vp, ctypes.c_uint64, i32,
+                               ctypes.POINTER(vp)],
+        "oc_ensemble_step": [vp, ctypes.c_double, i32, vp],
+        "oc_ensemble_tuning": [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)],
+        "oc_ensemble_destroy": [vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -380,3 +389,42 @@ class Mlp:
                                       ctypes.c_float(lr),
                                       ctypes.byref(loss) if want_loss else None, _stream()))
         return loss.value if want_loss else None
+
+
+class Ensemble:
+    """Many Model instances stepped together (one fused tendency launch per
+    substage over all members, batched Poisson passes, optional HIP graph
+    replay and autotuned launch configuration)."""
+
+    def __init__(self, models, tune=False, graph=False, device="cuda:0"):
+        import torch
+        lib = load_library()
+        self.models = list(models)           # kept alive: the ensemble borrows them
+        n = len(self.models)
+        arr = (ctypes.c_void_p * n)(*[m._model.value for m in self.models])
+        nbytes = ctypes.c_uint64()
+        _check(lib.oc_ensemble_workspace_size(arr, n, ctypes.byref(nbytes)))
+        flags = (OC_ENS_TUNE if tune else 0) | (OC_ENS_GRAPH if graph else 0)
+        self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=device)
+        self._h = ctypes.c_void_p()
+        _check(lib.oc_ensemble_create(arr, n, ctypes.c_void_p(self.workspace.data_ptr()),
+                                      ctypes.c_uint64(nbytes.value), flags, ctypes.byref(self._h)))
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None):
+                _lib.oc_ensemble_destroy(self._h)
+        except Exception:
+            pass
+
+    def step(self, dt, nsteps=1):
+        _check(_lib.oc_ensemble_step(self._h, ctypes.c_double(dt), ctypes.c_int32(nsteps),
+                                     _stream()))
+
+    def tuning(self):
+        out = (ctypes.c_int32 * 6)()
+        ms = ctypes.c_double()
+        _check(_lib.oc_ensemble_tuning(self._h, out, ctypes.byref(ms)))
+        return {"tile": ("32x8", "16x8", "8x8")[out[0]], "persistent": bool(out[1]),
+                "nblocks": out[2], "kc_div": out[3],
+                "source": ("default", "timed", "cache")[out[4]], "items": out[5], "ms": ms.value}

@@ -89,3 +89,18 @@ def test_hydrostatic_pairing_is_validated():
     bad = oc.GridDesc(1440, 560, 50, oc.OC_BOUNDED, 0, 360, -70, 170, -3000, 3000, oc.OC_LATLON,
                       6.371e6)
     assert lib.oc_grid_create(ctypes.byref(bad), ctypes.byref(g)) == -1
+
+
+def test_ensemble_and_hydrostatic_step_argument_checks():
+    lib = oc.load_library()
+    nbytes = ctypes.c_uint64()
+    assert lib.oc_ensemble_workspace_size(None, 1, ctypes.byref(nbytes)) == -1
+    arr = (ctypes.c_void_p * 1)(None)
+    assert lib.oc_ensemble_workspace_size(arr, 1, ctypes.byref(nbytes)) == -1
+    assert lib.oc_ensemble_workspace_size(arr, 0, ctypes.byref(nbytes)) == -1
+    e = ctypes.c_void_p()
+    assert lib.oc_ensemble_create(arr, 1, None, 0, 0, ctypes.byref(e)) == -1
+    assert lib.oc_ensemble_step(None, ctypes.c_double(1.0), 1, None) == -1
+    assert lib.oc_ensemble_destroy(None) == 0
+    w = (ctypes.c_double * 1)(1.0)
+    assert lib.oc_hydrostatic_step(None, ctypes.c_double(600.0), 30, 1, w, 1, None) == -1
