@@ -320,6 +320,27 @@ int oc_mlp_train_step(oc_mlp* m, const float* x, const float* target, int32_t ba
  * attachment. */
 int oc_model_set_closure(oc_model* m, oc_mlp* net, const double* stats, void* stream);
 
+/* The network input of every cell of the model's current state: x (device,
+ * FP32, ncell x 500, cells in (k, j, i) order, x fastest), standardised with
+ * stats[0..7] (input means and standard deviations of u, v, w, b; stats as
+ * for oc_model_set_closure, the output half unused).  For training data.
+ * Errors: OC_ERR_UNSUPPORTED without walls in z or without T, S buoyancy. */
+int oc_closure_features(oc_model* m, const double* stats, float* x, void* stream);
+
+/* Coarse-graining (the regridding paragraph of the finite-volume appendix:
+ * volume- and area-weighted averages that preserve integrals and the
+ * discrete divergence): the state of `coarse` becomes the average of the
+ * current state of `fine`, refined by one integer factor r in x, y and z
+ * over the same domain: centred fields over r^3 cells, u (v, w) over the r^2
+ * fine faces on each coarse face; halos refilled.  fluxes (device, FP32,
+ * (4, nz, ny, nx) of the coarse grid, may be NULL) receives the vertical
+ * subgrid fluxes <q w> - <q><w> over each r^3 box, q = u, v, w, b, with the
+ * velocities first averaged to the fine cell centres (physical units).
+ * Sums in FP64.  Errors: OC_ERR_UNSUPPORTED (not wall-bounded, no T, S
+ * buoyancy), OC_ERR_SHAPE (grids not related by one factor), OC_ERR_ARG
+ * (different precision, domain or tracer storage). */
+int oc_coarse_grain(oc_model* fine, oc_model* coarse, float* fluxes, void* stream);
+
 /* FP64 diagnostics of the current state, synchronous; out (host) receives
  * OC_NDIAG doubles: [0] max|div u| * min(spacing), [1] max|u|, [2] max|v|,
  * [3] max|w|, [4..7] volume integral of tracers 0..3 (0 if absent).

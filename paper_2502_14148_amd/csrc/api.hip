@@ -526,6 +526,46 @@ BaroBufs baro_bufs(oc_model* m) {
   return b;
 }
 
+ClosureStats closure_stats(const oc_model* m, const double* stats) {
+  ClosureStats c;
+  for (int q = 0; q < 4; ++q) {
+    c.in_mean[q] = (float)stats[q];
+    c.in_std[q] = (float)stats[4 + q];
+    c.out_mean[q] = (float)stats[8 + q];
+    c.out_std[q] = (float)stats[12 + q];
+  }
+  c.g_alpha = (float)(m->md.g * m->md.alpha);
+  c.g_beta = (float)(m->md.g * m->md.beta);
+  c.t_ref = (float)(m->md.t_ref - m->offset[OC_TRACER0]);
+  c.s_ref = (float)(m->md.s_ref - m->offset[OC_TRACER0 + 1]);
+  c.inv_galpha = (float)(1.0 / (m->md.g * m->md.alpha));
+  return c;
+}
+
+template <class T>
+int coarse_grain_call(oc_model* fine, oc_model* coarse, int r, float* fluxes, hipStream_t s) {
+  CoarseArgs<T> a;
+  a.df = fine->dims;
+  a.dc = coarse->dims;
+  a.r = r;
+  T* const* fs = (T* const*)fine->state[fine->cur];
+  T* const* cs = (T* const*)coarse->state[coarse->cur];
+  a.u = fs[0]; a.v = fs[1]; a.w = fs[2]; a.t = fs[3]; a.s = fs[4];
+  a.U = cs[0]; a.V = cs[1]; a.W = cs[2]; a.Tc = cs[3]; a.Sc = cs[4];
+  a.flux = fluxes;
+  const oc_model_desc& d = fine->md;
+  a.ga = d.g * d.alpha;
+  a.gb = d.g * d.beta;
+  a.tref = d.t_ref - fine->offset[OC_TRACER0];
+  a.sref = d.s_ref - fine->offset[OC_TRACER0 + 1];
+  OC_CHECK_HIP(launch_coarse_grain<T>(a, s));
+  // halos (and the wall faces of w) of every coarse field
+  int kinds[MAXF];
+  for (int q = 0; q < coarse->nf; ++q) kinds[q] = coarse->kinds[q];
+  OC_CHECK_HIP(launch_halo_fill<T>(coarse->dims, cs, kinds, coarse->nf, s));
+  return OC_OK;
+}
+
 template <class T>
 HydroBufs<T> hydro_bufs(oc_model* m, int in, int out) {
   HydroBufs<T> a;
@@ -997,21 +1037,59 @@ int oc_model_set_closure(oc_model* m, oc_mlp* net, const double* stats, void* st
     set_error("network parameters are not finite: the diffusive closure alone stays in use");
     return OC_ERR_NONFINITE;
   }
-  ClosureStats c;
-  for (int q = 0; q < 4; ++q) {
-    c.in_mean[q] = (float)stats[q];
-    c.in_std[q] = (float)stats[4 + q];
-    c.out_mean[q] = (float)stats[8 + q];
-    c.out_std[q] = (float)stats[12 + q];
-  }
-  c.g_alpha = (float)(m->md.g * m->md.alpha);
-  c.g_beta = (float)(m->md.g * m->md.beta);
-  c.t_ref = (float)(m->md.t_ref - m->offset[OC_TRACER0]);
-  c.s_ref = (float)(m->md.s_ref - m->offset[OC_TRACER0 + 1]);
-  c.inv_galpha = (float)(1.0 / (m->md.g * m->md.alpha));
-  m->cst = c;
+  m->cst = closure_stats(m, stats);
   m->net = net;
   return OC_OK;
+}
+
+int oc_closure_features(oc_model* m, const double* stats, float* x, void* stream) {
+  if (!m || !stats || !x) { set_error("NULL argument"); return OC_ERR_ARG; }
+  if (m->kind != OC_NONHYDROSTATIC || !m->dims.zb || !m->md.buoyancy) {
+    set_error("features need a wall-bounded nonhydrostatic model with T, S");
+    return OC_ERR_UNSUPPORTED;
+  }
+  for (int q = 0; q < 4; ++q)
+    if (!(stats[4 + q] > 0)) { set_error("standard deviations must be > 0"); return OC_ERR_ARG; }
+  const ClosureStats c = closure_stats(m, stats);
+  hipStream_t s = (hipStream_t)stream;
+  void* const* st = m->state[m->cur];
+  if (m->esz == 8)
+    OC_CHECK_HIP(launch_closure_features_f32<double>(
+        m->dims, (const double*)st[0], (const double*)st[1], (const double*)st[2],
+        (const double*)st[3], (const double*)st[4], c, x, s));
+  else
+    OC_CHECK_HIP(launch_closure_features_f32<float>(
+        m->dims, (const float*)st[0], (const float*)st[1], (const float*)st[2],
+        (const float*)st[3], (const float*)st[4], c, x, s));
+  return OC_OK;
+}
+
+int oc_coarse_grain(oc_model* fine, oc_model* coarse, float* fluxes, void* stream) {
+  if (!fine || !coarse) { set_error("NULL argument"); return OC_ERR_ARG; }
+  if (fine->kind != OC_NONHYDROSTATIC || coarse->kind != OC_NONHYDROSTATIC ||
+      !fine->dims.zb || !coarse->dims.zb || fine->nf < 5 || coarse->nf < 5 ||
+      !fine->md.buoyancy) {
+    set_error("coarse-graining takes wall-bounded nonhydrostatic models with T, S");
+    return OC_ERR_UNSUPPORTED;
+  }
+  if (fine->esz != coarse->esz) { set_error("both models need the same precision"); return OC_ERR_ARG; }
+  const int r = fine->dims.nx / coarse->dims.nx;
+  const Dims& f = fine->dims;
+  const Dims& c = coarse->dims;
+  if (r < 1 || f.nx != r * c.nx || f.ny != r * c.ny || f.nz != r * c.nz) {
+    set_error("fine grid must be the coarse grid refined by one integer factor in x, y and z");
+    return OC_ERR_SHAPE;
+  }
+  auto close = [](double a, double b) { return std::fabs(a - b) <= 1e-12 * std::fabs(b); };
+  if (!close(fine->gd.lx, coarse->gd.lx) || !close(fine->gd.ly, coarse->gd.ly) ||
+      !close(fine->gd.lz, coarse->gd.lz) || fine->offset[OC_TRACER0] != coarse->offset[OC_TRACER0] ||
+      fine->offset[OC_TRACER0 + 1] != coarse->offset[OC_TRACER0 + 1]) {
+    set_error("the models must cover the same domain with the same tracer storage");
+    return OC_ERR_ARG;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  return fine->esz == 8 ? coarse_grain_call<double>(fine, coarse, r, fluxes, s)
+                        : coarse_grain_call<float>(fine, coarse, r, fluxes, s);
 }
 
 }  // extern "C"

@@ -239,17 +239,12 @@ hipError_t launch_refresh_bf16(const MlpParams& p, int n, hipStream_t s) {
 // ---------------------------------------------------------------------------
 
 // xb[cell][f], f = var * 125 + (dk+2)*25 + (dj+2)*5 + (di+2), var = u, v, w, b
+// Standardised input f (0..499) of the cell `cell`: variable f / 125 of
+// (u, v, w, b) at offset (dk, dj, di) = digits of f % 125 in base 5, minus 2.
 template <class T>
-__global__ void __launch_bounds__(256) closure_features_kernel(Dims d, const T* u, const T* v,
-                                                               const T* w, const T* tt,
-                                                               const T* ss, ClosureStats st,
-                                                               __bf16* xb) {
-  const long ncell = (long)d.nx * d.ny * d.nz;
-  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= ncell * 512) return;
-  const long cell = t >> 9;
-  const int f = (int)(t & 511);
-  if (f >= 500) { xb[t] = (__bf16)0.0f; return; }
+__device__ inline float feature_value(const Dims& d, const T* u, const T* v, const T* w,
+                                      const T* tt, const T* ss, const ClosureStats& st, long cell,
+                                      int f) {
   const int i = (int)(cell % d.nx);
   const int j = (int)((cell / d.nx) % d.ny);
   const int k = (int)(cell / ((long)d.nx * d.ny));
@@ -261,7 +256,33 @@ __global__ void __launch_bounds__(256) closure_features_kernel(Dims d, const T* 
   else if (var == 1) x = (float)v[p];
   else if (var == 2) x = (float)w[p];
   else x = st.g_alpha * ((float)tt[p] - st.t_ref) - st.g_beta * ((float)ss[p] - st.s_ref);
-  xb[t] = (__bf16)((x - st.in_mean[var]) / st.in_std[var]);
+  return (x - st.in_mean[var]) / st.in_std[var];
+}
+
+// BF16 rows of 512 (the GEMM's padded K) for the model's own closure.
+template <class T>
+__global__ void __launch_bounds__(256) closure_features_kernel(Dims d, const T* u, const T* v,
+                                                               const T* w, const T* tt,
+                                                               const T* ss, ClosureStats st,
+                                                               __bf16* xb) {
+  const long ncell = (long)d.nx * d.ny * d.nz;
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ncell * 512) return;
+  const long cell = t >> 9;
+  const int f = (int)(t & 511);
+  xb[t] = (f < 500) ? (__bf16)feature_value(d, u, v, w, tt, ss, st, cell, f) : (__bf16)0.0f;
+}
+
+// FP32 rows of 500: the network input of oc_mlp_* (training data).
+template <class T>
+__global__ void __launch_bounds__(256) closure_features_f32_kernel(Dims d, const T* u,
+                                                                   const T* v, const T* w,
+                                                                   const T* tt, const T* ss,
+                                                                   ClosureStats st, float* x) {
+  const long ncell = (long)d.nx * d.ny * d.nz;
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ncell * 500) return;
+  x[t] = feature_value(d, u, v, w, tt, ss, st, t / 500, (int)(t % 500));
 }
 
 // Physical fluxes F_q = y_q std_q + mean_q at cell centres; u takes the
@@ -310,6 +331,23 @@ hipError_t launch_closure_features(const Dims& d, const T* u, const T* v, const 
                      stream, d, u, v, w, t, s, st, xb);
   return hipGetLastError();
 }
+
+template <class T>
+hipError_t launch_closure_features_f32(const Dims& d, const T* u, const T* v, const T* w,
+                                       const T* t, const T* s, ClosureStats st, float* x,
+                                       hipStream_t stream) {
+  const long n = (long)d.nx * d.ny * d.nz * 500;
+  hipLaunchKernelGGL(closure_features_f32_kernel<T>, dim3((unsigned)((n + 255) / 256)), dim3(256),
+                     0, stream, d, u, v, w, t, s, st, x);
+  return hipGetLastError();
+}
+template hipError_t launch_closure_features_f32<float>(const Dims&, const float*, const float*,
+                                                       const float*, const float*, const float*,
+                                                       ClosureStats, float*, hipStream_t);
+template hipError_t launch_closure_features_f32<double>(const Dims&, const double*,
+                                                        const double*, const double*,
+                                                        const double*, const double*,
+                                                        ClosureStats, float*, hipStream_t);
 
 template <class T>
 hipError_t launch_closure_apply(const Dims& d, const float* y, ClosureStats st, double rdz, T* gu,

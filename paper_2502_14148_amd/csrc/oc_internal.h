@@ -238,6 +238,24 @@ template <class T>
 hipError_t launch_closure_apply(const Dims& d, const float* y, ClosureStats st, double rdz,
                                 T* gu, T* gv, T* gw, T* gt, hipStream_t stream);
 
+template <class T>
+hipError_t launch_closure_features_f32(const Dims& d, const T* u, const T* v, const T* w,
+                                       const T* t, const T* s, ClosureStats st, float* x,
+                                       hipStream_t stream);
+
+// Coarse-graining of a fine state (halos filled) onto a grid r times coarser.
+template <class T>
+struct CoarseArgs {
+  Dims df, dc;
+  int r;
+  const T* u; const T* v; const T* w; const T* t; const T* s;   // fine
+  T* U; T* V; T* W; T* Tc; T* Sc;                               // coarse (interior written)
+  float* flux;          // (4, nzc, nyc, nxc) subgrid fluxes, or null
+  double ga, gb, tref, sref;   // b = ga (T - tref) - gb (S - sref) on stored values
+};
+template <class T>
+hipError_t launch_coarse_grain(const CoarseArgs<T>& a, hipStream_t s);
+
 // Access to a network from the model's step (implemented in closure_api.hip).
 __bf16* mlp_input(oc_mlp* net);
 const float* mlp_output(oc_mlp* net);

@@ -34,7 +34,8 @@ EXPORTS = ("oc_last_error", "oc_grid_create", "oc_grid_destroy", "oc_model_works
            "oc_mlp_destroy", "oc_mlp_set_params", "oc_mlp_get_params", "oc_mlp_forward",
            "oc_mlp_gradients", "oc_mlp_train_step", "oc_model_set_closure",
            "oc_ensemble_workspace_size", "oc_ensemble_create", "oc_ensemble_step",
-           "oc_ensemble_tuning", "oc_ensemble_destroy")
+           "oc_ensemble_tuning", "oc_ensemble_destroy", "oc_closure_features",
+           "oc_coarse_grain")
 OC_ENS_TUNE, OC_ENS_GRAPH = 1, 2
 OC_MLP_NPARAM = 195076
 MLP_SHAPES = (("W1", (256, 500)), ("b1", (256,)), ("W2", (256, 256)), ("b2", (256,)),
@@ -118,6 +119,8 @@ def load_library(path=_LIB_PATH):
         "oc_ensemble_step": [vp, ctypes.c_double, i32, vp],
         "oc_ensemble_tuning": [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)],
         "oc_ensemble_destroy": [vp],
+        "oc_closure_features": [vp, ctypes.POINTER(ctypes.c_double), vp, vp],
+        "oc_coarse_grain": [vp, vp, vp, vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -301,6 +304,27 @@ class Model:
                                          st.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                          _stream()))
         self._net = net   # the network must outlive the attachment
+
+    def closure_features(self, stats, out=None):
+        """FP32 device tensor (ncell, 500) of standardised network inputs of
+        the current state; stats: 16 numbers (the first 8 are used)."""
+        import torch
+        n = self.ph.nx * self.ph.ny * self.ph.nz
+        if out is None:
+            out = torch.empty((n, 500), dtype=torch.float32, device=self.device)
+        st = np.ascontiguousarray(stats, dtype=np.float64)
+        _check(_lib.oc_closure_features(self._model,
+                                        st.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                        ctypes.c_void_p(out.data_ptr()), _stream()))
+        return out
+
+    def coarse_grain_from(self, fine, fluxes=None):
+        """This model's state becomes the coarse-grained state of `fine`;
+        fluxes (FP32 device tensor (4, nz, ny, nx) of this grid, optional)
+        receives the vertical subgrid fluxes."""
+        ptr = ctypes.c_void_p(fluxes.data_ptr()) if fluxes is not None else None
+        _check(_lib.oc_coarse_grain(fine._model, self._model, ptr, _stream()))
+        return fluxes
 
     def free_surface_substeps(self, dt, N, weights):
         w = np.ascontiguousarray(weights, dtype=np.float64)
