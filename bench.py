@@ -65,6 +65,27 @@ def algorithmic_tendency_bytes(ncells, nfields, esz, steps):
     return per_cell * ncells * steps
 
 
+# Algorithmic HBM bytes per cell of each Poisson pass (FP32 velocities, FP64
+# half spectrum of (nx/2 + 1) complex values per x line ~ 8 B per cell):
+#   x forward: read u, v, w (12 B), write the half spectrum (8 B);
+#   y forward / inverse, z solve: read and write the half spectrum (16 B);
+#   x inverse: read the half spectrum (8 B), write p (8 B);
+#   projection: read p (8 B), read and write u, v, w (24 B).
+POISSON_BYTES_PER_CELL = {"fft_x_fwd": 20, "fft_y_fwd": 16, "z_solve": 16, "fft_y_inv": 16,
+                          "fft_x_inv": 16, "project": 32}
+
+
+def poisson_hbm(prof, ncells):
+    out = {}
+    for k, b in POISSON_BYTES_PER_CELL.items():
+        ms, n = prof[k]
+        if n:
+            gbs = b * ncells / (ms / 1e3 / n) / 1e9
+            out[k] = {"avg_launch_us": round(ms / n * 1e3, 1), "achieved_gbs": round(gbs, 1),
+                      "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_cell": b}
+    return out
+
+
 def run_gpu(ph, s, precision, steps, warmup):
     import torch
     from paper_2502_14148_amd import oc
@@ -199,6 +220,54 @@ def run_ensemble(steps, warmup):
             "tuning": tn}
 
 
+MLP_FLOPS_PER_ROW = 2 * (500 * 256 + 256 * 256 + 256 * 4)   # forward, one cell
+BF16_PEAK_TFLOPS = 2500.0      # MI355X dense BF16 MFMA
+
+
+def run_closure_mlp(reps=20, batch=4096, cells=64 ** 3):
+    """The closure network on the 64^3 coarse grid: inference over all
+    262 144 cells (one substage's worth) and Adam training steps of 4096
+    cells (forward + backward = 3 x the forward flops)."""
+    import torch
+    from paper_2502_14148_amd import oc
+    rng = np.random.default_rng(0)
+    x = torch.from_numpy(rng.standard_normal((cells, 500)).astype(np.float32)).cuda()
+    t = torch.from_numpy(rng.standard_normal((cells, 4)).astype(np.float32)).cuda()
+    net = oc.Mlp(cells)
+    p = {}
+    for k, shp in oc.MLP_SHAPES:
+        p[k] = rng.standard_normal(shp) / np.sqrt(shp[1]) if k.startswith("W") else np.zeros(shp)
+    net.set_params(p)
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    net.forward(x)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        net.forward(x)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_inf = e0.elapsed_time(e1) / reps / 1e3
+    nb = cells // batch
+    net.train_step(x[:batch], t[:batch], 1e-4, want_loss=False)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for b in range(nb):
+        net.train_step(x[b * batch:(b + 1) * batch], t[b * batch:(b + 1) * batch], 1e-4,
+                       want_loss=False)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_tr = e0.elapsed_time(e1) / nb / 1e3
+    inf_tf = MLP_FLOPS_PER_ROW * cells / t_inf / 1e12
+    tr_tf = 3 * MLP_FLOPS_PER_ROW * batch / t_tr / 1e12
+    return {"inference": {"cells": cells, "ms": t_inf * 1e3, "tflops": round(inf_tf, 1),
+                          "frac_bf16_peak": round(inf_tf / BF16_PEAK_TFLOPS, 4)},
+            "train_step": {"batch": batch, "ms": t_tr * 1e3, "tflops": round(tr_tf, 1),
+                           "frac_bf16_peak": round(tr_tf / BF16_PEAK_TFLOPS, 4)},
+            "flops_per_cell_forward": MLP_FLOPS_PER_ROW, "peak_tflops": BF16_PEAK_TFLOPS}
+
+
 def cpu_baseline(n_sample):
     """The FP64 oracle (NumPy) on a bounded sample: one RK3 step of the same
     physics and horizontal grid on a slab of n_sample levels."""
@@ -216,36 +285,8 @@ def cpu_baseline(n_sample):
                       f"256x256x{n_sample} slab at 2 m x 2 m x 1 m spacing, {el:.1f} s"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--n", type=int, default=256)
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--cpu-levels", type=int, default=32)
-    ap.add_argument("--no-hydrostatic", action="store_true")
-    ap.add_argument("--no-ensemble", action="store_true")
-    ap.add_argument("--ensemble-steps", type=int, default=20)
-    ap.add_argument("--hydro-steps", type=int, default=20)
-    ap.add_argument("--calibrate-copy", action="store_true",
-                    help="first run one plain 512 MiB device copy (counter calibration)")
-    a = ap.parse_args()
-    if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
-        sys.exit(2)
-
-    if a.calibrate_copy:
-        import torch
-        src = torch.ones(128 * 1024 * 1024, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)                      # runtime copy kernel
-        torch.mul(src, 1.0, out=dst)        # elementwise copy kernel
-        torch.cuda.synchronize()
-        del src, dst
-
+def main_leg(a):
+    """The 256^3 nonhydrostatic step: the headline line of the benchmark."""
     from paper_2502_14148_amd import inputs
     n = a.n
     ph = inputs.convection_physics((n, n, n), (2.0 * n, 2.0 * n, 1.0 * n))
@@ -289,13 +330,57 @@ def main():
                    "grid": [n, n, n], "extent_m": [2.0 * n, 2.0 * n, 1.0 * n], "dt_s": 1.0},
         "roofline": roofline,
         "kernels_ms_per_step": {k: v[0] / a.steps for k, v in prof32.items()},
+        "poisson_hbm": poisson_hbm(prof32, ncells),
         "fp64_path": res,
         "wall_s_timed": wall32,
         "final_max_w": diag32["max_w"],
     }
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--cpu-levels", type=int, default=32)
+    ap.add_argument("--no-hydrostatic", action="store_true")
+    ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--no-closure", action="store_true")
+    ap.add_argument("--no-main", action="store_true",
+                    help="skip the 256^3 step (profiling the other legs alone)")
+    ap.add_argument("--ensemble-steps", type=int, default=20)
+    ap.add_argument("--hydro-steps", type=int, default=20)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run one plain 512 MiB device copy (counter calibration)")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    if a.calibrate_copy:
+        import torch
+        src = torch.ones(128 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)                      # runtime copy kernel
+        torch.mul(src, 1.0, out=dst)        # elementwise copy kernel
+        torch.cuda.synchronize()
+        del src, dst
+
+    if a.no_main:
+        out = {"note": "the 256^3 nonhydrostatic leg was skipped (--no-main)"}
+    else:
+        out = main_leg(a)
     if not a.no_hydrostatic:
         print("# hydrostatic sector run", file=sys.stderr, flush=True)
         out["hydrostatic"] = run_hydrostatic(a.hydro_steps, 2)
+    if not a.no_closure:
+        print("# closure network", file=sys.stderr, flush=True)
+        out["closure_mlp"] = run_closure_mlp()
     if not a.no_ensemble:
         print("# ensemble run", file=sys.stderr, flush=True)
         out["ensemble"] = run_ensemble(a.ensemble_steps, 2)

@@ -40,6 +40,7 @@ struct oc_mlp {
   float* dz1;
   __bf16* dz1b;
   double* partial;  // LOSS_BLOCKS
+  float* part;      // split-K and column-sum partials (MLP_PART_FLOATS)
   int step;
 };
 
@@ -47,7 +48,7 @@ namespace {
 
 struct MlpLayout {
   uint64_t master, m1, m2, grad, w1b, w2b, w3b, xb, z1, h1, z2, h2, y, dy, dyb, dz2, dz2b, dz1,
-      dz1b, partial, total;
+      dz1b, partial, part, total;
 };
 
 uint64_t a256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
@@ -76,6 +77,7 @@ MlpLayout mlp_layout(int B) {
   L.dz1 = take((uint64_t)B * MLP_NH * 4);
   L.dz1b = take((uint64_t)B * MLP_NH * 2);
   L.partial = take((uint64_t)LOSS_BLOCKS * 8);
+  L.part = take((uint64_t)MLP_PART_FLOATS * 4);
   L.total = o;
   return L;
 }
@@ -88,6 +90,20 @@ GemmArgs gemm(const __bf16* A, int lda, int ta, const __bf16* B, int ldb, int tb
   g.B = B; g.ldb = ldb; g.transB = tb;
   g.M = M; g.N = N; g.K = K;
   g.epi = epi; g.C = C; g.ldc = ldc; g.bias = bias; g.Z = Z; g.H = Hh; g.ldh = ldh;
+  g.ksplit = 1; g.part = nullptr;
+  return g;
+}
+
+// A weight-gradient GEMM (K = batch) split over K until the grid has about
+// 1024 workgroups, each split covering at least two 32-deep k blocks.
+GemmArgs split_k(GemmArgs g, float* part) {
+  const int tiles = ((g.M + 63) / 64) * ((g.N + 63) / 64);
+  int ks = 1;
+  while (tiles * ks < 1024 && ks < MLP_MAX_KSPLIT && g.K % (64 * ks * 2) == 0 &&
+         (long)2 * ks * g.M * g.N <= MLP_PART_FLOATS)
+    ks *= 2;
+  g.ksplit = ks;
+  g.part = part;
   return g;
 }
 
@@ -121,23 +137,26 @@ int backward(oc_mlp* m, const float* target, int B, hipStream_t s) {
   OC_CHECK_HIP(launch_loss_grad(m->y, MLP_NOUT, target, B, m->dy, m->dyb, MLP_NOUTP, m->partial,
                                 LOSS_BLOCKS, s));
   // layer 3: dW3 = dY^T H2, db3 = colsum dY, dZ2 = (dY W3) * gelu'(Z2)
-  OC_CHECK_HIP(launch_gemm_bf16(gemm(m->dyb, MLP_NOUTP, 1, m->h2, MLP_NH, 0, MLP_NOUT, MLP_NH, B,
-                                     EPI_STORE, g + MLP_OFF_W3, MLP_NH), s));
-  OC_CHECK_HIP(launch_colsum(m->dy, B, MLP_NOUT, MLP_NOUTP, g + MLP_OFF_B3, s));
+  OC_CHECK_HIP(launch_gemm_bf16(split_k(gemm(m->dyb, MLP_NOUTP, 1, m->h2, MLP_NH, 0, MLP_NOUT,
+                                             MLP_NH, B, EPI_STORE, g + MLP_OFF_W3, MLP_NH),
+                                        m->part), s));
+  OC_CHECK_HIP(launch_colsum(m->dy, B, MLP_NOUT, MLP_NOUTP, g + MLP_OFF_B3, m->part, s));
   OC_CHECK_HIP(launch_gemm_bf16(gemm(m->dyb, MLP_NOUTP, 0, m->p.W3b, MLP_NH, 0, B, MLP_NH,
                                      MLP_NOUTP, EPI_GELU_BWD, m->dz2, MLP_NH, nullptr, m->z2,
                                      m->dz2b, MLP_NH), s));
   // layer 2
-  OC_CHECK_HIP(launch_gemm_bf16(gemm(m->dz2b, MLP_NH, 1, m->h1, MLP_NH, 0, MLP_NH, MLP_NH, B,
-                                     EPI_STORE, g + MLP_OFF_W2, MLP_NH), s));
-  OC_CHECK_HIP(launch_colsum(m->dz2, B, MLP_NH, MLP_NH, g + MLP_OFF_B2, s));
+  OC_CHECK_HIP(launch_gemm_bf16(split_k(gemm(m->dz2b, MLP_NH, 1, m->h1, MLP_NH, 0, MLP_NH,
+                                             MLP_NH, B, EPI_STORE, g + MLP_OFF_W2, MLP_NH),
+                                        m->part), s));
+  OC_CHECK_HIP(launch_colsum(m->dz2, B, MLP_NH, MLP_NH, g + MLP_OFF_B2, m->part, s));
   OC_CHECK_HIP(launch_gemm_bf16(gemm(m->dz2b, MLP_NH, 0, m->p.W2b, MLP_NH, 0, B, MLP_NH, MLP_NH,
                                      EPI_GELU_BWD, m->dz1, MLP_NH, nullptr, m->z1, m->dz1b,
                                      MLP_NH), s));
   // layer 1
-  OC_CHECK_HIP(launch_gemm_bf16(gemm(m->dz1b, MLP_NH, 1, m->xb, MLP_KIN, 0, MLP_NH, MLP_NIN, B,
-                                     EPI_STORE, g + MLP_OFF_W1, MLP_NIN), s));
-  OC_CHECK_HIP(launch_colsum(m->dz1, B, MLP_NH, MLP_NH, g + MLP_OFF_B1, s));
+  OC_CHECK_HIP(launch_gemm_bf16(split_k(gemm(m->dz1b, MLP_NH, 1, m->xb, MLP_KIN, 0, MLP_NH,
+                                             MLP_NIN, B, EPI_STORE, g + MLP_OFF_W1, MLP_NIN),
+                                        m->part), s));
+  OC_CHECK_HIP(launch_colsum(m->dz1, B, MLP_NH, MLP_NH, g + MLP_OFF_B1, m->part, s));
   return OC_OK;
 }
 
@@ -225,6 +244,7 @@ int oc_mlp_create(int32_t max_batch, void* workspace, uint64_t bytes, oc_mlp** o
   m->dz1 = (float*)(w + L.dz1);
   m->dz1b = (__bf16*)(w + L.dz1b);
   m->partial = (double*)(w + L.partial);
+  m->part = (float*)(w + L.part);
   m->step = 0;
   // zero everything: padded weight rows/columns stay zero for good
   if (hipMemset(workspace, 0, L.total) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {

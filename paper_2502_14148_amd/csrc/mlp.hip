@@ -47,11 +47,14 @@ __global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) {
   const int lane = tid & 63, wv = tid >> 6;
   const int wm = wv >> 1, wn = wv & 1;
   const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  // split K: this workgroup's range of the reduction
+  const int kspan = g.K / g.ksplit;
+  const int kbeg = blockIdx.z * kspan, kend = kbeg + kspan;
   f32x4 acc[2][2];
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  for (int k0 = 0; k0 < g.K; k0 += BK) {
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
     // ---- stage A (BM x BK) and B (BN x BK)
     if (!g.transA) {
       const int r = tid >> 2, ks = (tid & 3) * 8;
@@ -99,6 +102,10 @@ __global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) {
         const int m = m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + e;
         if (m >= g.M) continue;
         const float v = acc[i][j][e];
+        if (g.ksplit > 1) {
+          g.part[((long)blockIdx.z * g.M + m) * g.N + n] = v;
+          continue;
+        }
         const long o = (long)m * g.ldc + n;
         switch (g.epi) {
           case EPI_STORE:
@@ -154,11 +161,40 @@ __global__ void __launch_bounds__(256) loss_grad_kernel(const float* Y, int ldy,
 }
 
 // column sums of a (rows x cols) FP32 matrix into out (bias gradients)
-__global__ void colsum_kernel(const float* a, int rows, int cols, int lda, float* out) {
+// Sum of the split-K partials in z order: C[m][n] = sum_z part[z][m][n].
+__global__ void splitk_reduce_kernel(const float* part, int ksplit, int M, int N, float* C,
+                                     int ldc) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long)M * N) return;
+  const long mn = (long)M * N;
+  float s = 0.f;
+  for (int z = 0; z < ksplit; ++z) s += part[z * mn + t];
+  C[(t / N) * ldc + t % N] = s;
+}
+
+// Column sums in two levels: chunk q of the rows gives part[q][c] (a block
+// of 64 columns x 4 row lanes, combined in LDS), then the chunks are added
+// in order.
+__global__ void __launch_bounds__(256) colsum_partial_kernel(const float* a, int rows, int cols,
+                                                             int lda, int chunk, float* part) {
+  __shared__ float red[4][64];
+  const int cl = threadIdx.x & 63, rl = threadIdx.x >> 6;
+  const int c = blockIdx.x * 64 + cl;
+  const int r0 = blockIdx.y * chunk, r1 = min(r0 + chunk, rows);
+  float s = 0.f;
+  if (c < cols)
+    for (int r = r0 + rl; r < r1; r += 4) s += a[(long)r * lda + c];
+  red[rl][cl] = s;
+  __syncthreads();
+  if (rl == 0 && c < cols)
+    part[(long)blockIdx.y * cols + c] = ((red[0][cl] + red[1][cl]) + red[2][cl]) + red[3][cl];
+}
+
+__global__ void colsum_final_kernel(const float* part, int nchunk, int cols, float* out) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= cols) return;
   float s = 0.f;
-  for (int r = 0; r < rows; ++r) s += a[(long)r * lda + c];
+  for (int q = 0; q < nchunk; ++q) s += part[(long)q * cols + c];
   out[c] = s;
 }
 
@@ -194,8 +230,19 @@ __global__ void refresh_bf16_kernel(MlpParams p, int n) {
 }  // namespace
 
 hipError_t launch_gemm_bf16(const GemmArgs& g, hipStream_t s) {
-  dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM);
-  hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(256), 0, s, g);
+  const int ks = g.ksplit > 1 ? g.ksplit : 1;
+  if (ks > 1 && (g.epi != EPI_STORE || g.K % (ks * BK) || !g.part ||
+                 (long)ks * g.M * g.N > MLP_PART_FLOATS))
+    return hipErrorInvalidValue;
+  GemmArgs a = g;
+  a.ksplit = ks;
+  dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, ks);
+  hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(256), 0, s, a);
+  if (ks > 1) {
+    const long n = (long)g.M * g.N;
+    hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                       g.part, ks, g.M, g.N, g.C, g.ldc);
+  }
   return hipGetLastError();
 }
 
@@ -206,9 +253,15 @@ hipError_t launch_loss_grad(const float* Y, int ldy, const float* T, int B, floa
   return hipGetLastError();
 }
 
-hipError_t launch_colsum(const float* a, int rows, int cols, int lda, float* out, hipStream_t s) {
-  hipLaunchKernelGGL(colsum_kernel, dim3((cols + 127) / 128), dim3(128), 0, s, a, rows, cols, lda,
-                     out);
+hipError_t launch_colsum(const float* a, int rows, int cols, int lda, float* out, float* part,
+                         hipStream_t s) {
+  int chunk = 128;
+  while ((rows + chunk - 1) / chunk > COLSUM_MAX_CHUNKS) chunk *= 2;
+  const int nchunk = (rows + chunk - 1) / chunk;
+  hipLaunchKernelGGL(colsum_partial_kernel, dim3((cols + 63) / 64, nchunk), dim3(256), 0, s, a,
+                     rows, cols, lda, chunk, part);
+  hipLaunchKernelGGL(colsum_final_kernel, dim3((cols + 127) / 128), dim3(128), 0, s, part, nchunk,
+                     cols, out);
   return hipGetLastError();
 }
 

@@ -205,7 +205,13 @@ struct GemmArgs {
   const float* Z;           // EPI_GELU_BWD: pre-activation, same layout as C
   __bf16* H;                // EPI_BIAS_GELU / EPI_GELU_BWD: BF16 copy of the result
   int ldh;
+  int ksplit;               // > 1: K split over blockIdx.z (EPI_STORE only), partial
+  float* part;              // results in part[z][M][N], summed in z order into C
 };
+constexpr int MLP_MAX_KSPLIT = 64;
+// FP32 scratch of the split-K partials and the column-sum partials
+constexpr long MLP_PART_FLOATS = (long)MLP_MAX_KSPLIT * MLP_NH * MLP_KIN;
+constexpr int COLSUM_MAX_CHUNKS = 256;
 
 struct MlpParams {
   float* master;            // FP32: W1 | b1 | W2 | b2 | W3 | b3
@@ -218,7 +224,8 @@ __device__ void mlp_write_bf16(const MlpParams& p, int t, float w);
 hipError_t launch_gemm_bf16(const GemmArgs& g, hipStream_t s);
 hipError_t launch_loss_grad(const float* Y, int ldy, const float* T, int B, float* dY, __bf16* dYb,
                             int ldd, double* partial, int nblocks, hipStream_t s);
-hipError_t launch_colsum(const float* a, int rows, int cols, int lda, float* out, hipStream_t s);
+hipError_t launch_colsum(const float* a, int rows, int cols, int lda, float* out, float* part,
+                         hipStream_t s);
 hipError_t launch_features_to_bf16(const float* x, int B, __bf16* xb, hipStream_t s);
 hipError_t launch_adam(const MlpParams& p, const float* grad, float* m1, float* m2, int n, float lr,
                        int step, hipStream_t s);
