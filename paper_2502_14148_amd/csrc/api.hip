@@ -287,14 +287,12 @@ int tendency_call(oc_model* m, int in, int out, int stage, double dt, int combin
   }
   for (int q = 0; q < 4; ++q) fs.closure[q] = m->net ? (const T*)m->gc[q] : nullptr;
   if (m->net) {
-    // learned closure of the current state: features, network, flux divergence
+    // learned closure of the current state: the fused gather + network, then
+    // the flux divergence of its outputs
     ProfScope pc(m, OC_PROF_CLOSURE, s);
     const T* const* x = fs.in;
-    OC_CHECK_HIP(launch_closure_features<T>(m->dims, x[0], x[1], x[2], x[3], x[4], m->cst,
-                                            mlp_input(m->net), s));
-    const int ncell = m->dims.nx * m->dims.ny * m->dims.nz;
-    int rc = mlp_run_forward(m->net, ncell, s);
-    if (rc) return rc;
+    OC_CHECK_HIP(launch_closure_mlp_fused<T>(m->dims, x[0], x[1], x[2], x[3], x[4], m->cst,
+                                             mlp_params(m->net), mlp_output_rw(m->net), s));
     OC_CHECK_HIP(launch_closure_apply<T>(m->dims, mlp_output(m->net), m->cst, 1.0 / m->dz,
                                          (T*)m->gc[0], (T*)m->gc[1], (T*)m->gc[2], (T*)m->gc[3],
                                          s));
@@ -531,6 +529,7 @@ ClosureStats closure_stats(const oc_model* m, const double* stats) {
   for (int q = 0; q < 4; ++q) {
     c.in_mean[q] = (float)stats[q];
     c.in_std[q] = (float)stats[4 + q];
+    c.in_rstd[q] = (float)(1.0 / stats[4 + q]);
     c.out_mean[q] = (float)stats[8 + q];
     c.out_std[q] = (float)stats[12 + q];
   }

@@ -47,7 +47,7 @@ struct oc_mlp {
 namespace {
 
 struct MlpLayout {
-  uint64_t master, m1, m2, grad, w1b, w2b, w3b, xb, z1, h1, z2, h2, y, dy, dyb, dz2, dz2b, dz1,
+  uint64_t master, m1, m2, grad, w1b, w2b, w2bt, w3b, xb, z1, h1, z2, h2, y, dy, dyb, dz2, dz2b, dz1,
       dz1b, partial, part, total;
 };
 
@@ -63,6 +63,7 @@ MlpLayout mlp_layout(int B) {
   L.grad = take((uint64_t)MLP_NPARAM * 4);
   L.w1b = take((uint64_t)MLP_NH * MLP_KIN * 2);
   L.w2b = take((uint64_t)MLP_NH * MLP_NH * 2);
+  L.w2bt = take((uint64_t)MLP_NH * MLP_NH * 2);
   L.w3b = take((uint64_t)MLP_NOUTP * MLP_NH * 2);
   L.xb = take((uint64_t)B * MLP_KIN * 2);
   L.z1 = take((uint64_t)B * MLP_NH * 4);
@@ -149,7 +150,7 @@ int backward(oc_mlp* m, const float* target, int B, hipStream_t s) {
                                              MLP_NH, B, EPI_STORE, g + MLP_OFF_W2, MLP_NH),
                                         m->part), s));
   OC_CHECK_HIP(launch_colsum(m->dz2, B, MLP_NH, MLP_NH, g + MLP_OFF_B2, m->part, s));
-  OC_CHECK_HIP(launch_gemm_bf16(gemm(m->dz2b, MLP_NH, 0, m->p.W2b, MLP_NH, 0, B, MLP_NH, MLP_NH,
+  OC_CHECK_HIP(launch_gemm_bf16(gemm(m->dz2b, MLP_NH, 0, m->p.W2bT, MLP_NH, 1, B, MLP_NH, MLP_NH,
                                      EPI_GELU_BWD, m->dz1, MLP_NH, nullptr, m->z1, m->dz1b,
                                      MLP_NH), s));
   // layer 1
@@ -177,6 +178,8 @@ namespace oc {
 
 __bf16* mlp_input(oc_mlp* net) { return net->xb; }
 const float* mlp_output(oc_mlp* net) { return net->y; }
+float* mlp_output_rw(oc_mlp* net) { return net->y; }
+const MlpParams& mlp_params(const oc_mlp* net) { return net->p; }
 int mlp_max_batch(const oc_mlp* net) { return net->max_batch; }
 int mlp_run_forward(oc_mlp* net, int batch, hipStream_t s) { return forward_from_xb(net, batch, s); }
 
@@ -227,6 +230,7 @@ int oc_mlp_create(int32_t max_batch, void* workspace, uint64_t bytes, oc_mlp** o
   m->p.master = (float*)(w + L.master);
   m->p.W1b = (__bf16*)(w + L.w1b);
   m->p.W2b = (__bf16*)(w + L.w2b);
+  m->p.W2bT = (__bf16*)(w + L.w2bt);
   m->p.W3b = (__bf16*)(w + L.w3b);
   m->m1 = (float*)(w + L.m1);
   m->m2 = (float*)(w + L.m2);

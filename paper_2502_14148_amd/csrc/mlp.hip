@@ -19,7 +19,9 @@ __device__ void mlp_write_bf16(const MlpParams& p, int t, float w) {
     const int r = t / 500, c = t % 500;
     p.W1b[r * 512 + c] = (__bf16)w;
   } else if (t >= MLP_OFF_W2 && t < MLP_OFF_B2) {
-    p.W2b[t - MLP_OFF_W2] = (__bf16)w;
+    const int r = (t - MLP_OFF_W2) / MLP_NH, c = (t - MLP_OFF_W2) % MLP_NH;
+    p.W2b[r * MLP_NH + c] = (__bf16)w;
+    p.W2bT[c * MLP_NH + r] = (__bf16)w;   // transposed copy for the backward pass
   } else if (t >= MLP_OFF_W3 && t < MLP_OFF_B3) {
     p.W3b[t - MLP_OFF_W3] = (__bf16)w;
   }
@@ -34,6 +36,31 @@ __device__ inline float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.707
 __device__ inline float gelu_prime(float z) {
   return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) +
          z * __expf(-0.5f * z * z) * 0.39894228040143268f;
+}
+
+// Epilogue of one output element (m, n) of a GEMM.
+__device__ inline void epilogue(const GemmArgs& g, int m, int n, float v) {
+  const long o = (long)m * g.ldc + n;
+  switch (g.epi) {
+    case EPI_STORE:
+      g.C[o] = v;
+      break;
+    case EPI_BIAS:
+      g.C[o] = v + g.bias[n];
+      break;
+    case EPI_BIAS_GELU: {
+      const float z = v + g.bias[n];
+      g.C[o] = z;                                   // pre-activation (for backward)
+      g.H[(long)m * g.ldh + n] = (__bf16)gelu(z);    // activation (next layer)
+      break;
+    }
+    case EPI_GELU_BWD: {
+      const float dz = v * gelu_prime(g.Z[o]);
+      g.C[o] = dz;
+      g.H[(long)m * g.ldh + n] = (__bf16)dz;
+      break;
+    }
+  }
 }
 
 // C[m][n] = sum_k A[m][k] B[k][n].  transA = 0: A[m][k] at A[m*lda + k];
@@ -106,33 +133,92 @@ __global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) {
           g.part[((long)blockIdx.z * g.M + m) * g.N + n] = v;
           continue;
         }
-        const long o = (long)m * g.ldc + n;
-        switch (g.epi) {
-          case EPI_STORE:
-            g.C[o] = v;
-            break;
-          case EPI_BIAS:
-            g.C[o] = v + g.bias[n];
-            break;
-          case EPI_BIAS_GELU: {
-            const float z = v + g.bias[n];
-            g.C[o] = z;                                   // pre-activation (for backward)
-            g.H[(long)m * g.ldh + n] = (__bf16)gelu(z);    // activation (next layer)
-            break;
-          }
-          case EPI_GELU_BWD: {
-            const float dz = v * gelu_prime(g.Z[o]);
-            g.C[o] = dz;
-            g.H[(long)m * g.ldh + n] = (__bf16)dz;
-            break;
-          }
-        }
+        epilogue(g, m, n, v);
       }
     }
 }
 
 // dY = 2 (Y - T) / (B * 4) on the 4 real outputs (FP32 and BF16, padded
 // columns zero); per-block partial sums of the squared error.
+// C = A B with both operands k-contiguous (A[m][k] at A[m*lda + k], B[k][n]
+// at B[n*ldb + k]), M any multiple of 32, N a multiple of 128, K a multiple
+// of 64.  Workgroup tile 128 x 128, k step 64, four waves of 64 x 64 (4 x 4
+// MFMA 16x16x32 tiles); 16-byte global loads into registers for the next
+// k step while the current one is multiplied out of double-buffered LDS.
+constexpr int NT_BM = 128, NT_BN = 128, NT_BK = 64, NT_LDP = NT_BK + 8;
+
+__global__ void __launch_bounds__(256) gemm_bf16_nt_kernel(GemmArgs g) {
+  __shared__ __bf16 As[2][NT_BM][NT_LDP];
+  __shared__ __bf16 Bs[2][NT_BN][NT_LDP];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  const int wm = wv >> 1, wn = wv & 1;
+  const int m0 = blockIdx.y * NT_BM, n0 = blockIdx.x * NT_BN;
+  // each thread moves 4 chunks of 8 bf16 per operand and k step: rows
+  // (tid >> 3) + 32 c, k offset 8 (tid & 7)
+  const int lr = tid >> 3, lk = (tid & 7) * 8;
+  bf16x8 ra[4], rb[4];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int m = m0 + lr + 32 * c;
+      if (m < g.M) ra[c] = *(const bf16x8*)(g.A + (long)m * g.lda + k0 + lk);
+      else for (int e = 0; e < 8; ++e) ra[c][e] = (__bf16)0.0f;
+      const int n = n0 + lr + 32 * c;
+      rb[c] = *(const bf16x8*)(g.B + (long)n * g.ldb + k0 + lk);
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      *(bf16x8*)&As[buf][lr + 32 * c][lk] = ra[c];
+      *(bf16x8*)&Bs[buf][lr + 32 * c][lk] = rb[c];
+    }
+  };
+  f32x4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int nk = g.K / NT_BK;
+  load(0);
+  stash(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) load((kt + 1) * NT_BK);
+#pragma unroll
+    for (int ks = 0; ks < NT_BK; ks += 32) {
+      bf16x8 a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        a[i] = *(const bf16x8*)&As[buf][wm * 64 + i * 16 + (lane & 15)][ks + 8 * (lane >> 4)];
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        b[j] = *(const bf16x8*)&Bs[buf][wn * 64 + j * 16 + (lane & 15)][ks + 8 * (lane >> 4)];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    if (kt + 1 < nk) stash(buf ^ 1);
+    __syncthreads();
+  }
+  // lane holds rows 4 (lane / 16) + e of column lane % 16 of each 16 x 16 tile
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int n = n0 + wn * 64 + j * 16 + (lane & 15);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int m = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + e;
+        if (m < g.M) epilogue(g, m, n, acc[i][j][e]);
+      }
+    }
+}
+
 __global__ void __launch_bounds__(256) loss_grad_kernel(const float* Y, int ldy, const float* T,
                                                         int B, float* dY, __bf16* dYb, int ldd,
                                                         double* partial) {
@@ -236,6 +322,11 @@ hipError_t launch_gemm_bf16(const GemmArgs& g, hipStream_t s) {
     return hipErrorInvalidValue;
   GemmArgs a = g;
   a.ksplit = ks;
+  if (ks == 1 && !g.transA && g.transB && g.N % NT_BN == 0 && g.K % NT_BK == 0) {
+    dim3 grid(g.N / NT_BN, (g.M + NT_BM - 1) / NT_BM);
+    hipLaunchKernelGGL(gemm_bf16_nt_kernel, grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+  }
   dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, ks);
   hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(256), 0, s, a);
   if (ks > 1) {
@@ -326,6 +417,327 @@ __global__ void __launch_bounds__(256) closure_features_kernel(Dims d, const T* 
   xb[t] = (f < 500) ? (__bf16)feature_value(d, u, v, w, tt, ss, st, cell, f) : (__bf16)0.0f;
 }
 
+// The closure network on every cell of a model, fused.  A workgroup (4
+// waves) takes 64 consecutive cells, gathers their standardised 5x5x5
+// (u, v, w, b) neighbourhoods 64 features at a time (im2col: the walk over
+// (variable, offset) is uniform per wave and runs on the scalar unit) and
+// multiplies them by W1 with MFMA.  The 64 x 256 activations stay in LDS as
+// the A operand of the second layer; the third layer is one MFMA column
+// block (outputs padded to 16).  The next k chunk's features and weights are
+// loaded into registers while the current one is multiplied.  Only y (4 per
+// cell) goes to memory.  Operand rounding matches the unfused path: BF16
+// inputs, weights and activations, FP32 accumulation.
+constexpr int FZ_BM = 64, FZ_BK = 64, FZ_LDP = FZ_BK + 8, FZ_HP = MLP_NH + 8;
+
+template <class T>
+__global__ void __launch_bounds__(256) closure_mlp_fused_kernel(Dims d, const T* u, const T* v,
+                                                               const T* w, const T* tt,
+                                                               const T* ss, ClosureStats st,
+                                                               MlpParams p, float* y) {
+  __shared__ __bf16 Ws[MLP_NH][FZ_LDP];      // weight chunk, rows = outputs
+  __shared__ __bf16 Hs[FZ_BM][FZ_HP];        // layer activations; layer 1 uses its
+                                             // first FZ_LDP columns for the features
+  const long ncell = (long)d.nx * d.ny * d.nz;
+  const long c0 = (long)blockIdx.x * FZ_BM;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;   // wave wv: output columns [64 wv, +64)
+  const float* b1 = p.master + MLP_OFF_B1;
+  const float* b2 = p.master + MLP_OFF_B2;
+  const float* b3 = p.master + MLP_OFF_B3;
+
+  f32x4 acc[4][4];
+  auto zero = [&]() {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  };
+  // acc += A[64 rows][ka .. ka + 64) * Ws^T (A = Hs, pitch FZ_HP)
+  auto mma = [&](int ka) {
+#pragma unroll
+    for (int ks = 0; ks < FZ_BK; ks += 32) {
+      bf16x8 a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        a[i] = *(const bf16x8*)&Hs[i * 16 + (lane & 15)][ka + ks + 8 * (lane >> 4)];
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        b[j] = *(const bf16x8*)&Ws[wv * 64 + j * 16 + (lane & 15)][ks + 8 * (lane >> 4)];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+  };
+  // weight chunk in registers: rows (tid >> 3) + 32 c, k offset 8 (tid & 7)
+  bf16x8 wreg[8];
+  auto load_w = [&](const __bf16* W, int ldw, int k0) {
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+      wreg[c] = *(const bf16x8*)(W + (long)((tid >> 3) + 32 * c) * ldw + k0 + (tid & 7) * 8);
+  };
+  auto stash_w = [&]() {
+#pragma unroll
+    for (int c = 0; c < 8; ++c) *(bf16x8*)&Ws[(tid >> 3) + 32 * c][(tid & 7) * 8] = wreg[c];
+  };
+  auto store_h = [&](const float* bias) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int n = wv * 64 + j * 16 + (lane & 15);
+        const float bn = bias[n];
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          Hs[i * 16 + 4 * (lane >> 4) + e][n] = (__bf16)gelu(acc[i][j][e] + bn);
+      }
+  };
+
+  // ---- gather: cell gc (lane), features gf .. gf + 15 (gf uniform per wave)
+  const int gc = lane;
+  const int gf = __builtin_amdgcn_readfirstlane(wv * 16);
+  const long cell = c0 + gc;
+  const bool live = cell < ncell;
+  int corner = 0;   // padded offset of the neighbourhood corner (i-2, j-2, k-2)
+  if (live) {
+    const int ci = (int)(cell % d.nx);
+    const int cj = (int)((cell / d.nx) % d.ny);
+    const int ck = (int)(cell / ((long)d.nx * d.ny));
+    corner = (int)pidx(d, ci - 2, cj - 2, ck - 2);
+  }
+  const int sy = (int)d.sy, sz = (int)d.sz;
+  float graw[16], sraw[16];
+  bf16x8 xreg[2];
+  auto gather_load = [&](int k0) {
+    int f = k0 + gf;   // uniform: the walk below is scalar
+    int var = f / 125, o = f - var * 125;
+    int dk = o / 25, dj = (o - dk * 25) / 5, di = o - dk * 25 - dj * 5;
+#pragma unroll
+    for (int q = 0; q < 16; ++q, ++f) {
+      const int off = dk * sz + dj * sy + di;
+      graw[q] = 0.f;
+      sraw[q] = 0.f;
+      if (f < MLP_NIN) {
+        if (var == 0) graw[q] = (float)u[corner + off];
+        else if (var == 1) graw[q] = (float)v[corner + off];
+        else if (var == 2) graw[q] = (float)w[corner + off];
+        else { graw[q] = (float)tt[corner + off]; sraw[q] = (float)ss[corner + off]; }
+      }
+      if (++di == 5) { di = 0; if (++dj == 5) { dj = 0; if (++dk == 5) { dk = 0; ++var; } } }
+    }
+  };
+  auto gather_convert = [&](int k0) {
+    int f = k0 + gf;
+    int var = f / 125;
+    int o = f - var * 125;
+#pragma unroll
+    for (int q = 0; q < 16; ++q, ++f) {
+      const int vq = var < 4 ? var : 3;
+      const float raw = vq == 3 ? st.g_alpha * (graw[q] - st.t_ref) - st.g_beta * (sraw[q] - st.s_ref)
+                                : graw[q];
+      const float x = (live && f < MLP_NIN) ? (raw - st.in_mean[vq]) * st.in_rstd[vq] : 0.f;
+      xreg[q >> 3][q & 7] = (__bf16)x;
+      if (++o == 125) { o = 0; ++var; }
+    }
+  };
+
+  // ---- layer 1: 8 chunks of 64 features (500 real, zero padding to 512),
+  // staged in the first FZ_BK columns of Hs
+  zero();
+  gather_load(0);
+  gather_convert(0);
+  load_w(p.W1b, MLP_KIN, 0);
+  for (int k0 = 0; k0 < MLP_KIN; k0 += FZ_BK) {
+    *(bf16x8*)&Hs[gc][gf] = xreg[0];
+    *(bf16x8*)&Hs[gc][gf + 8] = xreg[1];
+    stash_w();
+    __syncthreads();
+    const bool more = k0 + FZ_BK < MLP_KIN;
+    if (more) {                   // next chunk's loads in flight during the multiply
+      gather_load(k0 + FZ_BK);
+      load_w(p.W1b, MLP_KIN, k0 + FZ_BK);
+    }
+    mma(0);
+    if (more) gather_convert(k0 + FZ_BK);
+    __syncthreads();
+  }
+  store_h(b1);
+
+  // ---- layer 2: A = the layer-1 activations in Hs, 4 chunks of W2
+  zero();
+  load_w(p.W2b, MLP_NH, 0);
+  for (int k0 = 0; k0 < MLP_NH; k0 += FZ_BK) {
+    stash_w();
+    __syncthreads();    // (first chunk: also orders the Hs writes above)
+    if (k0 + FZ_BK < MLP_NH) load_w(p.W2b, MLP_NH, k0 + FZ_BK);
+    mma(k0);
+    __syncthreads();
+  }
+  store_h(b2);          // every wave has finished reading Hs (barrier above)
+  __syncthreads();
+
+  // ---- layer 3: wave wv takes rows [16 wv, +16) against W3 rows 0..15
+  // (rows >= 4 are zero): 8 MFMAs over k
+  {
+    f32x4 c3 = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < MLP_NH; ks += 32) {
+      const bf16x8 a = *(const bf16x8*)&Hs[wv * 16 + (lane & 15)][ks + 8 * (lane >> 4)];
+      const bf16x8 b = *(const bf16x8*)(p.W3b + (long)(lane & 15) * MLP_NH + ks + 8 * (lane >> 4));
+      c3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c3, 0, 0, 0);
+    }
+    const int o = lane & 15;
+    if (o < MLP_NOUT)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const long c = c0 + wv * 16 + 4 * (lane >> 4) + e;
+        if (c < ncell) y[c * MLP_NOUT + o] = c3[e] + b3[o];
+      }
+  }
+}
+
+// The same network for grids whose x rows hold a multiple of 64 cells: the
+// 64 cells of a workgroup share one x row, so the standardised BF16 values
+// of (u, v, w, b) over their whole 5 x 5 x 68 neighbourhood region are
+// loaded once (coalesced along x) into LDS, and every k chunk of features is
+// copied out of that region (im2col in LDS).  Weight chunks are 32 deep.
+constexpr int RG_X = FZ_BM + 4, RG_P = RG_X + 4, RG_K = 32, RG_WP = RG_K + 8;
+
+template <class T>
+__global__ void __launch_bounds__(256) closure_mlp_region_kernel(Dims d, const T* u, const T* v,
+                                                                const T* w, const T* tt,
+                                                                const T* ss, ClosureStats st,
+                                                                MlpParams p, float* y) {
+  __shared__ __bf16 Rg[4][25][RG_P];         // (var, 5 dk + dj, x - (i0 - 2))
+  __shared__ __bf16 Ws[MLP_NH][RG_WP];       // weight chunk, rows = outputs
+  __shared__ __bf16 Hs[FZ_BM][FZ_HP];        // activations; layer 1 stages features here
+  const long c0 = (long)blockIdx.x * FZ_BM;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  const int i0 = (int)(c0 % d.nx);
+  const int j0 = (int)((c0 / d.nx) % d.ny);
+  const int k0c = (int)(c0 / ((long)d.nx * d.ny));
+  const float* b1 = p.master + MLP_OFF_B1;
+  const float* b2 = p.master + MLP_OFF_B2;
+  const float* b3 = p.master + MLP_OFF_B3;
+
+  // ---- the neighbourhood region, standardised, in BF16
+  for (int e = tid; e < 25 * RG_X; e += 256) {
+    const int row = e / RG_X, x = e - row * RG_X;
+    const int dk = row / 5, dj = row - dk * 5;
+    const long pp = pidx(d, i0 - 2 + x, j0 - 2 + dj, k0c - 2 + dk);
+    Rg[0][row][x] = (__bf16)(((float)u[pp] - st.in_mean[0]) * st.in_rstd[0]);
+    Rg[1][row][x] = (__bf16)(((float)v[pp] - st.in_mean[1]) * st.in_rstd[1]);
+    Rg[2][row][x] = (__bf16)(((float)w[pp] - st.in_mean[2]) * st.in_rstd[2]);
+    const float b = st.g_alpha * ((float)tt[pp] - st.t_ref) - st.g_beta * ((float)ss[pp] - st.s_ref);
+    Rg[3][row][x] = (__bf16)((b - st.in_mean[3]) * st.in_rstd[3]);
+  }
+
+  f32x4 acc[4][4];
+  auto zero = [&]() {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  };
+  auto mma = [&](int ka) {   // one 32-deep k step: A = Hs columns [ka, ka + 32)
+    bf16x8 a[4], b[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      a[i] = *(const bf16x8*)&Hs[i * 16 + (lane & 15)][ka + 8 * (lane >> 4)];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      b[j] = *(const bf16x8*)&Ws[wv * 64 + j * 16 + (lane & 15)][8 * (lane >> 4)];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+  };
+  bf16x8 wreg[4];   // weight chunk rows (tid >> 2) + 64 c, k offset 8 (tid & 3)
+  auto load_w = [&](const __bf16* W, int ldw, int kk) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      wreg[c] = *(const bf16x8*)(W + (long)((tid >> 2) + 64 * c) * ldw + kk + (tid & 3) * 8);
+  };
+  auto stash_w = [&]() {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) *(bf16x8*)&Ws[(tid >> 2) + 64 * c][(tid & 3) * 8] = wreg[c];
+  };
+  auto store_h = [&](const float* bias) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int n = wv * 64 + j * 16 + (lane & 15);
+        const float bn = bias[n];
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          Hs[i * 16 + 4 * (lane >> 4) + e][n] = (__bf16)gelu(acc[i][j][e] + bn);
+      }
+  };
+  // features [kk, kk + 32) of cell `lane`: wave wv writes features kk + 8 wv .. + 7
+  auto stage_x = [&](int kk) {
+    int f = __builtin_amdgcn_readfirstlane(kk + 8 * wv);
+    int var = f / 125, o = f - var * 125;
+    int dk = o / 25, dj = (o - dk * 25) / 5, di = o - dk * 25 - dj * 5;
+    bf16x8 xv;
+#pragma unroll
+    for (int q = 0; q < 8; ++q, ++f) {
+      xv[q] = f < MLP_NIN ? Rg[var < 3 ? var : 3][dk * 5 + dj][lane + di] : (__bf16)0.0f;
+      if (++di == 5) { di = 0; if (++dj == 5) { dj = 0; if (++dk == 5) { dk = 0; ++var; } } }
+    }
+    *(bf16x8*)&Hs[lane][kk % 64 + 8 * wv] = xv;
+  };
+
+  // ---- layer 1: 16 chunks of 32 features, staged alternately in columns
+  // [0, 32) and [32, 64) of Hs
+  zero();
+  load_w(p.W1b, MLP_KIN, 0);
+  __syncthreads();                  // the region is complete
+  for (int kk = 0; kk < MLP_KIN; kk += RG_K) {
+    stage_x(kk);
+    stash_w();
+    __syncthreads();
+    if (kk + RG_K < MLP_KIN) load_w(p.W1b, MLP_KIN, kk + RG_K);
+    mma(kk % 64);
+    __syncthreads();
+  }
+  store_h(b1);
+
+  // ---- layer 2
+  zero();
+  load_w(p.W2b, MLP_NH, 0);
+  for (int kk = 0; kk < MLP_NH; kk += RG_K) {
+    stash_w();
+    __syncthreads();
+    if (kk + RG_K < MLP_NH) load_w(p.W2b, MLP_NH, kk + RG_K);
+    mma(kk);
+    __syncthreads();
+  }
+  store_h(b2);
+  __syncthreads();
+
+  // ---- layer 3 (outputs padded to 16 columns)
+  {
+    f32x4 c3 = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < MLP_NH; ks += 32) {
+      const bf16x8 a = *(const bf16x8*)&Hs[wv * 16 + (lane & 15)][ks + 8 * (lane >> 4)];
+      const bf16x8 b = *(const bf16x8*)(p.W3b + (long)(lane & 15) * MLP_NH + ks + 8 * (lane >> 4));
+      c3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c3, 0, 0, 0);
+    }
+    const int o = lane & 15;
+    if (o < MLP_NOUT)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const long c = c0 + wv * 16 + 4 * (lane >> 4) + e;
+        y[c * MLP_NOUT + o] = c3[e] + b3[o];
+      }
+  }
+}
+
 // FP32 rows of 500: the network input of oc_mlp_* (training data).
 template <class T>
 __global__ void __launch_bounds__(256) closure_features_f32_kernel(Dims d, const T* u,
@@ -384,6 +796,28 @@ hipError_t launch_closure_features(const Dims& d, const T* u, const T* v, const 
                      stream, d, u, v, w, t, s, st, xb);
   return hipGetLastError();
 }
+
+template <class T>
+hipError_t launch_closure_mlp_fused(const Dims& d, const T* u, const T* v, const T* w, const T* t,
+                                    const T* s, ClosureStats st, const MlpParams& p, float* y,
+                                    hipStream_t stream) {
+  const long n = (long)d.nx * d.ny * d.nz;
+  if (d.nx % FZ_BM == 0)
+    hipLaunchKernelGGL(closure_mlp_region_kernel<T>, dim3((unsigned)(n / FZ_BM)), dim3(256), 0,
+                       stream, d, u, v, w, t, s, st, p, y);
+  else
+    hipLaunchKernelGGL(closure_mlp_fused_kernel<T>, dim3((unsigned)((n + FZ_BM - 1) / FZ_BM)),
+                       dim3(256), 0, stream, d, u, v, w, t, s, st, p, y);
+  return hipGetLastError();
+}
+template hipError_t launch_closure_mlp_fused<float>(const Dims&, const float*, const float*,
+                                                    const float*, const float*, const float*,
+                                                    ClosureStats, const MlpParams&, float*,
+                                                    hipStream_t);
+template hipError_t launch_closure_mlp_fused<double>(const Dims&, const double*, const double*,
+                                                     const double*, const double*, const double*,
+                                                     ClosureStats, const MlpParams&, float*,
+                                                     hipStream_t);
 
 template <class T>
 hipError_t launch_closure_features_f32(const Dims& d, const T* u, const T* v, const T* w,

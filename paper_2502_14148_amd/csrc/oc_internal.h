@@ -217,6 +217,7 @@ struct MlpParams {
   float* master;            // FP32: W1 | b1 | W2 | b2 | W3 | b3
   __bf16* W1b;              // 256 x 512 (columns >= 500 zero)
   __bf16* W2b;              // 256 x 256
+  __bf16* W2bT;             // its transpose (backward pass)
   __bf16* W3b;              // 32 x 256 (rows >= 4 zero)
 };
 
@@ -235,6 +236,7 @@ hipError_t launch_refresh_bf16(const MlpParams& p, int n, hipStream_t s);
 // four fluxes; buoyancy parameters to form b from the stored T, S.
 struct ClosureStats {
   float in_mean[4], in_std[4], out_mean[4], out_std[4];
+  float in_rstd[4];                      // 1 / in_std
   float g_alpha, g_beta, t_ref, s_ref;   // b = g_alpha (T - t_ref) - g_beta (S - s_ref)
   float inv_galpha;                      // temperature flux = buoyancy flux / (g alpha)
 };
@@ -245,6 +247,10 @@ template <class T>
 hipError_t launch_closure_apply(const Dims& d, const float* y, ClosureStats st, double rdz,
                                 T* gu, T* gv, T* gw, T* gt, hipStream_t stream);
 
+template <class T>
+hipError_t launch_closure_mlp_fused(const Dims& d, const T* u, const T* v, const T* w, const T* t,
+                                    const T* s, ClosureStats st, const MlpParams& p, float* y,
+                                    hipStream_t stream);
 template <class T>
 hipError_t launch_closure_features_f32(const Dims& d, const T* u, const T* v, const T* w,
                                        const T* t, const T* s, ClosureStats st, float* x,
@@ -266,6 +272,8 @@ hipError_t launch_coarse_grain(const CoarseArgs<T>& a, hipStream_t s);
 // Access to a network from the model's step (implemented in closure_api.hip).
 __bf16* mlp_input(oc_mlp* net);
 const float* mlp_output(oc_mlp* net);
+float* mlp_output_rw(oc_mlp* net);
+const MlpParams& mlp_params(const oc_mlp* net);
 int mlp_max_batch(const oc_mlp* net);
 int mlp_run_forward(oc_mlp* net, int batch, hipStream_t s);
 int mlp_params_finite(oc_mlp* net, hipStream_t s);  // 1, 0, or a negative error

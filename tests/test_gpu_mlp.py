@@ -100,9 +100,9 @@ def test_training_reduces_loss(gpu_lib):
     assert last < first / 5, (first, last)
 
 
-def _closure_case(seed=7):
+def _closure_case(seed=7, n=(32, 32, 16)):
     from paper_2502_14148_amd import inputs
-    ph = inputs.convection_physics((32, 32, 16), (64.0, 64.0, 16.0))
+    ph = inputs.convection_physics(n, (2.0 * n[0], 2.0 * n[1], 1.0 * n[2]))
     ph.closure = True
     s = inputs.random_state(ph, seed=seed, vel=1e-2, tracer_scale=0.05)
     s["T"] += 20.0
@@ -113,21 +113,24 @@ def _closure_case(seed=7):
     return ph, s, p, stats
 
 
-def test_closure_tendency_parity(gpu_lib):
+@pytest.mark.parametrize("n,precision", [((32, 32, 16), "fp64"), ((64, 16, 16), "fp64"),
+                                         ((128, 8, 16), "fp32"), ((32, 16, 16), "fp32")])
+def test_closure_tendency_parity(gpu_lib, n, precision):
     """The closure's contribution to G (model with the network attached minus
     the model without it) against the oracle: features -> BF16 MLP ->
-    conservative flux divergence."""
+    conservative flux divergence.  x rows of 64k cells take the kernel that
+    stages the neighbourhood region in LDS, others the direct gather."""
     from oracle import timestep
-    ph, s, p, stats = _closure_case()
+    ph, s, p, stats = _closure_case(n=n)
     net = gpu_lib.Mlp(ph.nx * ph.ny * ph.nz)
     net.set_params(p)
-    m = gpu_lib.Model(ph, "fp64")
+    m = gpu_lib.Model(ph, precision)
     m.set_states(s)
     m.tendencies()
-    G0 = {n: m.get_tendency(n) for n in ("u", "v", "w", "T")}
+    G0 = {f: m.get_tendency(f) for f in ("u", "v", "w", "T")}
     m.set_closure(net, stats)
     m.tendencies()
-    G1 = {n: m.get_tendency(n) for n in ("u", "v", "w", "T")}
+    G1 = {f: m.get_tendency(f) for f in ("u", "v", "w", "T")}
     st = timestep.make_state(s, ph)
     padded = {"u": st["u"], "v": st["v"], "w": st["w"],
               "b": ph.g * (ph.alpha * (st["T"] - ph.t_ref) - ph.beta * (st["S"] - ph.s_ref))}
@@ -135,9 +138,9 @@ def test_closure_tendency_parity(gpu_lib):
     Y, _ = cl.forward(p, X, use_bf16=True)
     F = (Y * stats[12:16] + stats[8:12]).T.reshape(4, ph.nz, ph.ny, ph.nx)
     Gc = cl.closure_tendency(F, ph)
-    for n in ("u", "v", "w", "T"):
-        err = rel_l2(G1[n] - G0[n], Gc[n])
-        assert err < 5e-3, (n, err)
+    for f in ("u", "v", "w", "T"):
+        err = rel_l2(G1[f] - G0[f], Gc[f])
+        assert err < 5e-3, (f, err)
 
 
 def test_closure_refuses_diverged_network(gpu_lib):
