@@ -186,13 +186,16 @@ def periodic_box_initial(ph: Physics, seed: int = 0, kmax: int = 8,
 
 
 def convection_initial(ph: Physics, seed: int = 0, noise: float = 1e-3,
-                       t_surface: float = 20.0, n2: float = 1e-5, s0: float = 35.0):
+                       t_surface: float = 20.0, n2: float = 1e-5, s0: float = 35.0,
+                       tracer_noise: float = 0.0):
     """Initial state of the free-convection LES.
 
     T(z) = t_surface + n2 / (g alpha) * z at cell centres (z <= 0), S = s0.
     Velocity: curl of an i.i.d. Gaussian edge potential (zero on the walls),
     scaled to an RMS of `noise` m/s per component; it is discretely
-    divergence-free and has w = 0 on the walls.
+    divergence-free and has w = 0 on the walls.  tracer_noise > 0 adds i.i.d.
+    Gaussian perturbations of that standard deviation to T and S (drawn after
+    the velocity, so the velocity does not depend on it).
     """
     assert ph.z_bounded
     rng = np.random.default_rng(seed)
@@ -211,6 +214,9 @@ def convection_initial(ph: Physics, seed: int = 0, noise: float = 1e-3,
     zc = ph.z0 + (np.arange(nz) + 0.5) * dz
     T = np.broadcast_to((t_surface + n2 / (ph.g * ph.alpha) * zc)[:, None, None], (nz, ny, nx)).copy()
     S = np.full((nz, ny, nx), s0)
+    if tracer_noise > 0:
+        T += tracer_noise * rng.standard_normal((nz, ny, nx))
+        S += tracer_noise * rng.standard_normal((nz, ny, nx))
     return {"u": u, "v": v, "w": w, "T": T, "S": S}
 
 
