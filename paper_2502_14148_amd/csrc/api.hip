@@ -68,8 +68,7 @@ Layout make_layout(const oc_grid_desc& g, const oc_model_desc& m) {
     if (q < nf) off += fb;
   }
   if (m.kind == OC_NONHYDROSTATIC) {
-    const uint64_t nxh = g.nx / 2 + 1;
-    L.spec = off; off += align256((uint64_t)g.nz * g.ny * nxh * 16);
+    L.spec = off; off += align256((uint64_t)g.nz * g.ny * spec_pitch(g.nx) * 16);
     L.p = off; off += align256((uint64_t)g.nz * g.ny * g.nx * 8);
     L.twx = off; off += align256((uint64_t)g.nx * 16);
     L.twy = off; off += align256((uint64_t)g.ny * 16);
@@ -779,6 +778,7 @@ int oc_model_create(const oc_grid* g, const oc_model_desc* md, void* workspace,
   m->sb.lamy = (const double*)(m->ws + L.lamy);
   m->sb.lamz = (const double*)(m->ws + L.lamz);
   m->sb.nxh = g->d.nx / 2 + 1;
+  m->sb.nxp = spec_pitch(g->d.nx);
   m->staging = m->ws + L.staging;
   m->diag_part = (double*)(m->ws + L.diag);
 

@@ -97,7 +97,7 @@ struct FieldSet {
 
 // Spectral-solve tables and buffers (FP64).
 struct SpecBufs {
-  double2* spec;             // (nz, ny, nxh) half spectrum, kx fastest
+  double2* spec;             // (nz, ny, nxp) half spectrum, kx fastest
   double* p;                 // (nz, ny, nx) pressure
   const double2* twx;        // exp(-2 pi i m / nx), m < nx
   const double2* twy;
@@ -106,8 +106,13 @@ struct SpecBufs {
   const double* lamx;        // eigenvalues of delta_x^2 / dx^2, k < nx
   const double* lamy;
   const double* lamz;
-  int nxh;
+  int nxh;                   // nx / 2 + 1 stored wavenumbers
+  int nxp;                   // row pitch: nxh rounded up to 8 (128-byte rows)
 };
+
+// Row pitch of the half spectrum in complex elements: column groups of 8 start
+// on 128-byte boundaries, so the y and z passes fetch whole cache lines.
+inline int spec_pitch(int nx) { return ((nx / 2 + 1) + 7) / 8 * 8; }
 
 // 2D barotropic buffers and metric factors of the hydrostatic model (FP64,
 // dense, x fastest; V-like arrays have ny + 1 rows).

@@ -114,6 +114,17 @@ __device__ inline void fft_lines(double2* buf, int ls, int es, const double2* __
 }
 
 constexpr int NT = 256;
+// Twiddle table staged in LDS by the whole workgroup (made visible by the
+// barrier that follows the tile load), so that the Stockham passes read
+// their factors from LDS instead of waiting on global memory between barriers.
+template <int N>
+__device__ inline void stage_twiddles(double2* tws, const double2* __restrict__ tw) {
+#pragma unroll
+  for (int q = 0; q < (N + NT - 1) / NT; ++q) {
+    const int t = threadIdx.x + q * NT;
+    if (N % NT == 0 || t < N) tws[t] = tw[t];
+  }
+}
 template <int N> struct XCfg { static constexpr int LP = (N >= 1024) ? 1 : 1024 / N; };
 template <int N> struct YZCfg { static constexpr int W = (N >= 512) ? 4 : (N >= 256 ? 8 : 16); };
 
@@ -136,10 +147,18 @@ __global__ void __launch_bounds__(NT) fwd_x_kernel(Dims d, const T* __restrict__
   }
   constexpr int LP = XCfg<N>::LP;
   __shared__ double2 buf[LP * N];
+  __shared__ double2 tws[N];
+  stage_twiddles<N>(tws, sb.twx);
   const int k = blockIdx.y;
   const int npairs = d.ny / 2;
   const int pair0 = blockIdx.x * LP;
-  for (int t = threadIdx.x; t < LP * N; t += NT) {
+  // compile-time trip counts, so that every load of the tile is in flight
+  // before the first one is used
+  constexpr int LOADS = (LP * N + NT - 1) / NT;
+#pragma unroll
+  for (int q = 0; q < LOADS; ++q) {
+    const int t = threadIdx.x + q * NT;
+    if ((LP * N) % NT != 0 && t >= LP * N) break;
     const int l = t / N, i = t % N;
     const int pr = pair0 + l;
     double2 z = make_double2(0.0, 0.0);
@@ -167,7 +186,7 @@ __global__ void __launch_bounds__(NT) fwd_x_kernel(Dims d, const T* __restrict__
     buf[t] = z;
   }
   __syncthreads();
-  fft_lines<N, 1, LP, NT, -1, false>(buf, N, 1, sb.twx);
+  fft_lines<N, 1, LP, NT, -1, false>(buf, N, 1, tws);
   // unpack the two real spectra: X1 = (Z_k + conj Z_{N-k})/2, X2 = -i (Z_k - conj Z_{N-k})/2
   const int nxh = sb.nxh;
   for (int t = threadIdx.x; t < LP * nxh; t += NT) {
@@ -178,9 +197,9 @@ __global__ void __launch_bounds__(NT) fwd_x_kernel(Dims d, const T* __restrict__
     double2 b = cconj(buf[l * N + ((N - kx) % N)]);
     double2 x1 = cscale(cadd(a, b), 0.5);
     double2 x2 = cscale(mul_i<-1>(csub(a, b)), 0.5);
-    const long base = ((long)k * d.ny + 2 * pr) * nxh + kx;
+    const long base = ((long)k * d.ny + 2 * pr) * sb.nxp + kx;
     sb.spec[base] = x1;
-    sb.spec[base + nxh] = x2;
+    sb.spec[base + sb.nxp] = x2;
   }
 }
 
@@ -193,19 +212,25 @@ __global__ void __launch_bounds__(NT) y_kernel(Dims d, SpecBufs sb,
   if (bs) sb.spec = bs->spec[blockIdx.z];
   constexpr int W = YZCfg<N>::W;
   __shared__ double2 buf[W * N];
+  __shared__ double2 tws[N];
+  stage_twiddles<N>(tws, sb.twy);
   const int k = blockIdx.y;
   const int kx0 = blockIdx.x * W;
-  const int nxh = sb.nxh;
-  for (int t = threadIdx.x; t < W * N; t += NT) {
+  const int nxh = sb.nxh, nxp = sb.nxp;
+  constexpr int PER = (W * N + NT - 1) / NT;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int t = threadIdx.x + q * NT;
+    if ((W * N) % NT != 0 && t >= W * N) break;
     const int c = t % W, y = t / W;
-    buf[t] = (kx0 + c < nxh) ? sb.spec[((long)k * d.ny + y) * nxh + kx0 + c]
+    buf[t] = (kx0 + c < nxh) ? sb.spec[((long)k * d.ny + y) * nxp + kx0 + c]
                              : make_double2(0.0, 0.0);
   }
   __syncthreads();
-  fft_lines<N, 1, W, NT, DIR, true>(buf, 1, W, sb.twy);
+  fft_lines<N, 1, W, NT, DIR, true>(buf, 1, W, tws);
   for (int t = threadIdx.x; t < W * N; t += NT) {
     const int c = t % W, y = t / W;
-    if (kx0 + c < nxh) sb.spec[((long)k * d.ny + y) * nxh + kx0 + c] = buf[t];
+    if (kx0 + c < nxh) sb.spec[((long)k * d.ny + y) * nxp + kx0 + c] = buf[t];
   }
 }
 
@@ -225,18 +250,23 @@ __global__ void __launch_bounds__(NT) z_kernel(Dims d, SpecBufs sb, double norm,
   constexpr int W = YZCfg<N>::W;
   constexpr int PER = (W * N + NT - 1) / NT;
   __shared__ double2 buf[W * N];
+  __shared__ double2 tws[N];
+  stage_twiddles<N>(tws, sb.twz);
   const int j = blockIdx.y;
   const int kx0 = blockIdx.x * W;
-  const int nxh = sb.nxh;
-  const long zs = (long)d.ny * nxh;
-  for (int t = threadIdx.x; t < W * N; t += NT) {
+  const int nxh = sb.nxh, nxp = sb.nxp;
+  const long zs = (long)d.ny * nxp;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int t = threadIdx.x + q * NT;
+    if ((W * N) % NT != 0 && t >= W * N) break;
     const int c = t % W, z = t / W;
     const int pos = BOUNDED ? makhoul_pos(z, N) : z;
-    buf[pos * W + c] = (kx0 + c < nxh) ? sb.spec[(long)z * zs + (long)j * nxh + kx0 + c]
+    buf[pos * W + c] = (kx0 + c < nxh) ? sb.spec[(long)z * zs + (long)j * nxp + kx0 + c]
                                        : make_double2(0.0, 0.0);
   }
   __syncthreads();
-  fft_lines<N, 1, W, NT, -1, true>(buf, 1, W, sb.twz);
+  fft_lines<N, 1, W, NT, -1, true>(buf, 1, W, tws);
   // spectral division
   double2 val[PER];
 #pragma unroll
@@ -280,11 +310,11 @@ __global__ void __launch_bounds__(NT) z_kernel(Dims d, SpecBufs sb, double norm,
     }
     __syncthreads();
   }
-  fft_lines<N, 1, W, NT, 1, true>(buf, 1, W, sb.twz);
+  fft_lines<N, 1, W, NT, 1, true>(buf, 1, W, tws);
   for (int t = threadIdx.x; t < W * N; t += NT) {
     const int c = t % W, z = t / W;
     const int pos = BOUNDED ? makhoul_pos(z, N) : z;
-    if (kx0 + c < nxh) sb.spec[(long)z * zs + (long)j * nxh + kx0 + c] = buf[pos * W + c];
+    if (kx0 + c < nxh) sb.spec[(long)z * zs + (long)j * nxp + kx0 + c] = buf[pos * W + c];
   }
 }
 
@@ -300,26 +330,31 @@ __global__ void __launch_bounds__(NT) inv_x_kernel(Dims d, SpecBufs sb,
   }
   constexpr int LP = XCfg<N>::LP;
   __shared__ double2 buf[LP * N];
+  __shared__ double2 tws[N];
+  stage_twiddles<N>(tws, sb.twx);
   const int k = blockIdx.y;
   const int npairs = d.ny / 2;
   const int pair0 = blockIdx.x * LP;
-  const int nxh = sb.nxh;
-  for (int t = threadIdx.x; t < LP * N; t += NT) {
+  constexpr int LOADS = (LP * N + NT - 1) / NT;
+#pragma unroll
+  for (int q = 0; q < LOADS; ++q) {
+    const int t = threadIdx.x + q * NT;
+    if ((LP * N) % NT != 0 && t >= LP * N) break;
     const int l = t / N, n = t % N;
     const int pr = pair0 + l;
     double2 z = make_double2(0.0, 0.0);
     if (pr < npairs) {
-      const long base = ((long)k * d.ny + 2 * pr) * nxh;
+      const long base = ((long)k * d.ny + 2 * pr) * sb.nxp;
       const bool lo = n <= N / 2;
       const int m = lo ? n : N - n;
-      double2 x1 = sb.spec[base + m], x2 = sb.spec[base + nxh + m];
+      double2 x1 = sb.spec[base + m], x2 = sb.spec[base + sb.nxp + m];
       if (!lo) { x1 = cconj(x1); x2 = cconj(x2); }
       z = cadd(x1, mul_i<1>(x2));  // Z = X1 + i X2
     }
     buf[t] = z;
   }
   __syncthreads();
-  fft_lines<N, 1, LP, NT, 1, false>(buf, N, 1, sb.twx);
+  fft_lines<N, 1, LP, NT, 1, false>(buf, N, 1, tws);
   for (int t = threadIdx.x; t < LP * N; t += NT) {
     const int l = t / N, i = t % N;
     const int pr = pair0 + l;
@@ -332,13 +367,16 @@ __global__ void __launch_bounds__(NT) inv_x_kernel(Dims d, SpecBufs sb,
 
 // ---------------------------------------------------------------------------
 // Projection u -= scale grad p at interior faces (wall faces of w untouched).
+// A workgroup covers 64 x 4 columns and marches up PJ_KC planes, keeping the
+// pressure of the plane below in a register, so p is fetched once per cell
+// (plus one plane per chunk).
 // ---------------------------------------------------------------------------
+constexpr int PJ_X = 64, PJ_Y = 4, PJ_KC = 16;
+
 template <class T>
-__global__ void __launch_bounds__(256) project_kernel(Dims d, T* __restrict__ u, T* __restrict__ v,
-                                                      T* __restrict__ w, double scale, double rdx,
-                                                      double rdy, double rdz,
-                                                      const double* __restrict__ p,
-                                                      const PoissonSlots* __restrict__ bs) {
+__global__ void __launch_bounds__(PJ_X * PJ_Y) project_kernel(
+    Dims d, T* __restrict__ u, T* __restrict__ v, T* __restrict__ w, double scale, double rdx,
+    double rdy, double rdz, const double* __restrict__ p, const PoissonSlots* __restrict__ bs) {
   if (bs) {
     const int z = blockIdx.z;
     u = (T*)bs->u[z];
@@ -346,30 +384,62 @@ __global__ void __launch_bounds__(256) project_kernel(Dims d, T* __restrict__ u,
     w = (T*)bs->w[z];
     p = bs->p[z];
   }
-  const long n = (long)d.nx * d.ny * d.nz;
-  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n) return;
-  const int i = (int)(t % d.nx);
-  const int j = (int)((t / d.nx) % d.ny);
-  const int k = (int)(t / ((long)d.nx * d.ny));
-  const long c = pidx(d, i, j, k);
-  const long row = (long)d.nx, plane = (long)d.nx * d.ny;
-  const double pc = p[t];
-  const double pxm = p[t - i + ((i == 0) ? d.nx - 1 : i - 1)];
-  const double pym = p[t - (long)j * row + (long)((j == 0) ? d.ny - 1 : j - 1) * row];
-  const T un = (T)((double)u[c] - scale * (pc - pxm) * rdx);
-  const T vn = (T)((double)v[c] - scale * (pc - pym) * rdy);
-  T wn = w[c];
-  if (d.zb) {
-    if (k > 0) wn = (T)((double)wn - scale * (pc - p[t - plane]) * rdz);
-  } else {
-    const double pzm = p[t - (long)k * plane + (long)((k == 0) ? d.nz - 1 : k - 1) * plane];
-    wn = (T)((double)wn - scale * (pc - pzm) * rdz);
+  // Workgroups are dealt round-robin to the 8 XCDs; renumber them so that
+  // each XCD takes a contiguous run of tiles (x fastest, then y, then the z
+  // chunk), and the cache lines shared by neighbouring tiles stay in one L2.
+  const int nbx = (d.nx + PJ_X - 1) / PJ_X;
+  const int ntile = (int)(gridDim.x * gridDim.y);
+  int lin = (int)(blockIdx.x + blockIdx.y * gridDim.x);
+  if (ntile % 8 == 0) lin = (lin % 8) * (ntile / 8) + lin / 8;
+  const int txy = lin % (int)gridDim.x;
+  const int i = (txy % nbx) * PJ_X + (int)(threadIdx.x % PJ_X);
+  const int j = (txy / nbx) * PJ_Y + (int)(threadIdx.x / PJ_X);
+  if (i >= d.nx || j >= d.ny) return;
+  const int k0 = (lin / (int)gridDim.x) * PJ_KC;
+  const int k1 = min(k0 + PJ_KC, d.nz);
+  const long plane = (long)d.nx * d.ny;
+  const double* __restrict__ pc = p + (long)j * d.nx + i;
+  const long oxm = ((i == 0) ? d.nx - 1 : i - 1) - i;
+  const long oym = (long)(((j == 0) ? d.ny - 1 : j - 1) - j) * d.nx;
+  // pressure below the first plane of the chunk (periodic wrap in z)
+  double pb = 0.0;
+  if (k0 > 0) pb = pc[(long)(k0 - 1) * plane];
+  else if (!d.zb) pb = pc[(long)(d.nz - 1) * plane];
+  // planes in batches of PJ_B: all loads of a batch are issued before its
+  // stores (the stores may alias later loads of the same field)
+  constexpr int PJ_B = 4;
+  for (int kb = k0; kb < k1; kb += PJ_B) {
+    double p0[PJ_B], pxm[PJ_B], pym[PJ_B];
+    T uu[PJ_B], vv[PJ_B], ww[PJ_B];
+#pragma unroll
+    for (int q = 0; q < PJ_B; ++q) {
+      if (kb + q < k1) {
+        const long t = (long)(kb + q) * plane;
+        p0[q] = pc[t];
+        pxm[q] = pc[t + oxm];
+        pym[q] = pc[t + oym];
+        const long c = pidx(d, i, j, kb + q);
+        uu[q] = u[c];
+        vv[q] = v[c];
+        ww[q] = w[c];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < PJ_B; ++q) {
+      const int k = kb + q;
+      if (k < k1) {
+        const T un = (T)((double)uu[q] - scale * (p0[q] - pxm[q]) * rdx);
+        const T vn = (T)((double)vv[q] - scale * (p0[q] - pym[q]) * rdy);
+        T wn = ww[q];
+        if (!d.zb || k > 0) wn = (T)((double)wn - scale * (p0[q] - pb) * rdz);
+        pb = p0[q];
+        // the final velocities, with their halo images
+        store_with_images(u, d, i, j, k, un, false);
+        store_with_images(v, d, i, j, k, vn, false);
+        store_with_images(w, d, i, j, k, wn, true);
+      }
+    }
   }
-  // the final velocities, with their halo images
-  store_with_images(u, d, i, j, k, un, false);
-  store_with_images(v, d, i, j, k, vn, false);
-  store_with_images(w, d, i, j, k, wn, true);
 }
 
 // ---------------------------------------------------------------------------
@@ -456,9 +526,9 @@ template <class T>
 hipError_t launch_project(const Dims& d, T* u, T* v, T* w, double scale, double rdx, double rdy,
                           double rdz, const double* p, hipStream_t s, const PoissonSlots* bs,
                           int nslots) {
-  const long n = (long)d.nx * d.ny * d.nz;
-  hipLaunchKernelGGL(project_kernel<T>, dim3((unsigned)((n + 255) / 256), 1, nslots), dim3(256), 0,
-                     s, d, u, v, w, scale, rdx, rdy, rdz, p, bs);
+  const unsigned nb = (unsigned)(((d.nx + PJ_X - 1) / PJ_X) * ((d.ny + PJ_Y - 1) / PJ_Y));
+  hipLaunchKernelGGL(project_kernel<T>, dim3(nb, (d.nz + PJ_KC - 1) / PJ_KC, nslots),
+                     dim3(PJ_X * PJ_Y), 0, s, d, u, v, w, scale, rdx, rdy, rdz, p, bs);
   return hipGetLastError();
 }
 
