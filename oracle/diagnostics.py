@@ -6,13 +6,14 @@ values (finite-volume appendix, discrete integral identity).
 """
 import numpy as np
 
-from .fv import interior
+from .fv import interior, z_spacings
 from .pressure import divergence
 
 
 def volume_integral(field_interior, ph):
-    dx, dy, dz = ph.spacing
-    return float(np.sum(field_interior)) * dx * dy * dz
+    dx, dy, _ = ph.spacing
+    dzc, _ = z_spacings(ph)
+    return float(np.sum(field_interior * dzc[:, None, None])) * dx * dy
 
 
 def max_abs_divergence(state, ph):
@@ -26,11 +27,13 @@ def scaled_divergence(state, ph):
     """max|div u| * min(spacing) / max|u|: dimensionless, 0 for an exactly
     divergence-free field."""
     vmax = max(float(np.max(np.abs(interior(state[n], ph, n)))) for n in ("u", "v", "w"))
-    return max_abs_divergence(state, ph) * min(ph.spacing) / max(vmax, 1e-300)
+    hmin = min(ph.spacing[0], ph.spacing[1], float(np.min(z_spacings(ph)[0])))
+    return max_abs_divergence(state, ph) * hmin / max(vmax, 1e-300)
 
 
 def cfl(state, dt, ph):
-    dx, dy, dz = ph.spacing
+    dx, dy, _ = ph.spacing
+    dzc, _ = z_spacings(ph)
     return dt * max(float(np.max(np.abs(interior(state["u"], ph, "u")))) / dx,
                     float(np.max(np.abs(interior(state["v"], ph, "v")))) / dy,
-                    float(np.max(np.abs(interior(state["w"], ph, "w")))) / dz)
+                    float(np.max(np.abs(interior(state["w"], ph, "w")))) / float(np.min(dzc)))

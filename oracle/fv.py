@@ -56,6 +56,39 @@ def fill_halo(a, ph, kind):
     return a
 
 
+def z_spacings(ph):
+    """Vertical spacings of a (possibly stretched) grid, from its faces
+    (one-dimensional staggered-grid listing: cells between unevenly spaced
+    faces, centres at the midpoints).
+
+    Returns (dzc, dzf): dzc[k] = z_f[k+1] - z_f[k], the thickness of cell k
+    (k = 0..nz-1), and dzf[k] = z_c[k] - z_c[k-1], the distance between the
+    centres on either side of face k (k = 0..nz).  At a wall face the outside
+    centre is the mirror image of the inside one, so dzf[0] = dzc[0] and
+    dzf[nz] = dzc[nz-1]; periodic z wraps.  A uniform grid has dzc = dzf = dz.
+    """
+    nz = ph.nz
+    if getattr(ph, "z_faces", None) is None:
+        dz = ph.lz / nz
+        return np.full(nz, dz), np.full(nz + 1, dz)
+    zf = np.asarray(ph.z_faces, dtype=np.float64)
+    assert zf.shape == (nz + 1,) and np.all(np.diff(zf) > 0)
+    dzc = zf[1:] - zf[:-1]
+    zc = 0.5 * (zf[1:] + zf[:-1])
+    dzf = np.empty(nz + 1)
+    dzf[1:nz] = zc[1:] - zc[:-1]
+    if ph.z_bounded:
+        dzf[0] = dzc[0]
+        dzf[nz] = dzc[nz - 1]
+    else:
+        dzf[0] = dzf[nz] = 0.5 * (dzc[0] + dzc[nz - 1])
+    return dzc, dzf
+
+
+def is_stretched(ph):
+    return getattr(ph, "z_faces", None) is not None
+
+
 FIELD_KIND = {"u": "c", "v": "c", "w": "w"}
 
 

@@ -17,12 +17,23 @@ Readings where the paper is silent:
 * walls are impenetrable, free-slip and no-flux except for the prescribed
   top tracer flux (upward positive).
 
+Vertically stretched grids (unevenly spaced z faces, staggered-grid listing
+of the finite-volume appendix): flux divergences divide the z difference of
+the fluxes by the thickness of the control volume (dzc[k] for cells, dzf[k]
+for the w cells around face k) and vertical diffusive fluxes divide by the
+distance between the two values they difference.  Readings: the WENO
+reconstructions, the fourth-order advecting-velocity interpolation and the
+buoyancy average to w faces keep their uniform-grid coefficients in index
+space along z.  With implicit vertical diffusion (vertically implicit
+time-discretisation paragraph) the z diffusive fluxes are left out of G;
+the prescribed top flux stays explicit.
+
 All tendencies are returned as interior arrays; G_w has nz + 1 faces when z
 is bounded (wall faces hold 0).
 """
 import numpy as np
 
-from .fv import view
+from .fv import view, z_spacings
 from .weno import reconstruct
 
 OFFSETS = (-3, -2, -1, 0, 1, 2)
@@ -37,21 +48,40 @@ def _rec(ph, qs, vel):
     return reconstruct(ph.advection, qs, vel, ph.weno_eps, ph.weno_q)
 
 
-def _div(Fx, Fy, Fz, ph):
-    """Flux divergence on a uniform grid: (1/V) sum over directions of
-    delta(A F); fluxes carry one extra entry along their own axis."""
-    dx, dy, dz = ph.spacing
+def _div(Fx, Fy, Fz, ph, hz):
+    """Flux divergence (1/V) sum over directions of delta(A F) on a grid
+    uniform in x and y: A_x / V = 1/dx, A_y / V = 1/dy, A_z / V = 1/hz with
+    hz the control-volume thickness per level, shape (nz, 1, 1).  Fluxes carry
+    one extra entry along their own axis."""
+    dx, dy, _ = ph.spacing
     return ((Fx[:, :, 1:] - Fx[:, :, :-1]) / dx
             + (Fy[:, 1:, :] - Fy[:, :-1, :]) / dy
-            + (Fz[1:] - Fz[:-1]) / dz)
+            + (Fz[1:] - Fz[:-1]) / hz)
+
+
+def _zgrid(ph):
+    """(dzc, dzf) as (n, 1, 1) columns, and the centre thicknesses on the
+    w-flux positions (centres -1..nz-1: the mirror or periodic image first)."""
+    dzc, dzf = z_spacings(ph)
+    below = dzc[0] if ph.z_bounded else dzc[-1]
+    dzc_w = np.concatenate([[below], dzc])
+    return dzc[:, None, None], dzf[:, None, None], dzc_w[:, None, None]
+
+
+def _zdiff(ph, coef):
+    """Coefficient of the explicit vertical diffusive flux: zero when the
+    vertical diffusion is implicit."""
+    return 0.0 if getattr(ph, "implicit_z", False) else coef
 
 
 def tracer_tendency(c, s, ph, top_flux=0.0):
     """G_c for a centred tracer c given padded velocities s['u'], s['v'], s['w']."""
     u, v, w = s["u"], s["v"], s["w"]
     nx, ny, nz = ph.nx, ph.ny, ph.nz
-    dx, dy, dz = ph.spacing
+    dx, dy, _ = ph.spacing
+    dzc, dzf, _ = _zgrid(ph)
     k = ph.kappa
+    kz = _zdiff(ph, k)
     # x faces i = 0..nx
     U = view(u, ni=nx + 1, ph=ph)
     Fx = U * _rec(ph, [view(c, di=o, ni=nx + 1, ph=ph) for o in OFFSETS], U)
@@ -63,19 +93,21 @@ def tracer_tendency(c, s, ph, top_flux=0.0):
     # z faces k = 0..nz
     W = view(w, nk=nz + 1, ph=ph)
     Fz = W * _rec(ph, [view(c, dk=o, nk=nz + 1, ph=ph) for o in OFFSETS], W)
-    Fz = Fz - k * (view(c, nk=nz + 1, ph=ph) - view(c, dk=-1, nk=nz + 1, ph=ph)) / dz
+    Fz = Fz - kz * (view(c, nk=nz + 1, ph=ph) - view(c, dk=-1, nk=nz + 1, ph=ph)) / dzf
     if ph.z_bounded:
         Fz[0] = 0.0           # bottom wall: no flux
         Fz[nz] = top_flux     # top wall: prescribed upward flux
-    return -_div(Fx, Fy, Fz, ph)
+    return -_div(Fx, Fy, Fz, ph, dzc)
 
 
 def u_tendency(s, ph):
     """Advection + diffusion of u at (F, C, C) and the Coriolis term."""
     u, v, w = s["u"], s["v"], s["w"]
     nx, ny, nz = ph.nx, ph.ny, ph.nz
-    dx, dy, dz = ph.spacing
+    dx, dy, _ = ph.spacing
+    dzc, dzf, _ = _zgrid(ph)
     nu = ph.nu
+    nuz = _zdiff(ph, nu)
     # x: entry i holds the flux at cell centre i-1 (between faces i-1 and i)
     Ub = interp4(*[view(u, di=o, ni=nx + 1, ph=ph) for o in (-2, -1, 0, 1)])
     X = Ub * _rec(ph, [view(u, di=o, ni=nx + 1, ph=ph) for o in OFFSETS], Ub)
@@ -87,11 +119,11 @@ def u_tendency(s, ph):
     # z: (x face i, centre j, z face k); w interpolated along x to the x face
     Wt = interp4(*[view(w, di=o, nk=nz + 1, ph=ph) for o in (-2, -1, 0, 1)])
     Z = Wt * _rec(ph, [view(u, dk=o, nk=nz + 1, ph=ph) for o in OFFSETS], Wt)
-    Z = Z - nu * (view(u, nk=nz + 1, ph=ph) - view(u, dk=-1, nk=nz + 1, ph=ph)) / dz
+    Z = Z - nuz * (view(u, nk=nz + 1, ph=ph) - view(u, dk=-1, nk=nz + 1, ph=ph)) / dzf
     if ph.z_bounded:
         Z[0] = 0.0
         Z[nz] = 0.0
-    G = -_div(X, Y, Z, ph)
+    G = -_div(X, Y, Z, ph, dzc)
     # Coriolis: -f z x u  ->  +f v averaged to the u point
     vbar = 0.25 * (view(v, di=-1, ph=ph) + view(v, ph=ph)
                    + view(v, di=-1, dj=1, ph=ph) + view(v, dj=1, ph=ph))
@@ -102,8 +134,10 @@ def v_tendency(s, ph):
     """Advection + diffusion of v at (C, F, C) and the Coriolis term."""
     u, v, w = s["u"], s["v"], s["w"]
     nx, ny, nz = ph.nx, ph.ny, ph.nz
-    dx, dy, dz = ph.spacing
+    dx, dy, _ = ph.spacing
+    dzc, dzf, _ = _zgrid(ph)
     nu = ph.nu
+    nuz = _zdiff(ph, nu)
     # x: corners (x face i, y face j); u interpolated along y to the y face
     Ut = interp4(*[view(u, dj=o, ni=nx + 1, ph=ph) for o in (-2, -1, 0, 1)])
     X = Ut * _rec(ph, [view(v, di=o, ni=nx + 1, ph=ph) for o in OFFSETS], Ut)
@@ -115,11 +149,11 @@ def v_tendency(s, ph):
     # z: (centre i, y face j, z face k); w interpolated along y
     Wt = interp4(*[view(w, dj=o, nk=nz + 1, ph=ph) for o in (-2, -1, 0, 1)])
     Z = Wt * _rec(ph, [view(v, dk=o, nk=nz + 1, ph=ph) for o in OFFSETS], Wt)
-    Z = Z - nu * (view(v, nk=nz + 1, ph=ph) - view(v, dk=-1, nk=nz + 1, ph=ph)) / dz
+    Z = Z - nuz * (view(v, nk=nz + 1, ph=ph) - view(v, dk=-1, nk=nz + 1, ph=ph)) / dzf
     if ph.z_bounded:
         Z[0] = 0.0
         Z[nz] = 0.0
-    G = -_div(X, Y, Z, ph)
+    G = -_div(X, Y, Z, ph, dzc)
     # Coriolis: -f z x u  ->  -f u averaged to the v point
     ubar = 0.25 * (view(u, dj=-1, ph=ph) + view(u, di=1, dj=-1, ph=ph)
                    + view(u, ph=ph) + view(u, di=1, ph=ph))
@@ -138,8 +172,10 @@ def w_tendency(s, ph):
     """Advection + diffusion of w at (C, C, F) plus buoyancy."""
     u, v, w = s["u"], s["v"], s["w"]
     nx, ny, nz = ph.nx, ph.ny, ph.nz
-    dx, dy, dz = ph.spacing
+    dx, dy, _ = ph.spacing
+    _, dzf, dzc_w = _zgrid(ph)
     nu = ph.nu
+    nuz = _zdiff(ph, nu)
     # faces k = 0..nz-1 are computed; walls are overwritten below
     # x: (x face i, centre j, z face k); u interpolated along z to the z face
     Ut = interp4(*[view(u, dk=o, ni=nx + 1, ph=ph) for o in (-2, -1, 0, 1)])
@@ -152,8 +188,9 @@ def w_tendency(s, ph):
     # z: entry k holds the flux at cell centre k-1 (between faces k-1 and k)
     Wb = interp4(*[view(w, dk=o, nk=nz + 1, ph=ph) for o in (-2, -1, 0, 1)])
     Z = Wb * _rec(ph, [view(w, dk=o, nk=nz + 1, ph=ph) for o in OFFSETS], Wb)
-    Z = Z - nu * (view(w, nk=nz + 1, ph=ph) - view(w, dk=-1, nk=nz + 1, ph=ph)) / dz
-    G = -_div(X, Y, Z, ph)
+    Z = Z - nuz * (view(w, nk=nz + 1, ph=ph) - view(w, dk=-1, nk=nz + 1, ph=ph)) / dzc_w
+    # the w cell around face k spans the centres k-1 and k: thickness dzf[k]
+    G = -_div(X, Y, Z, ph, dzf[:nz])
     if ph.buoyancy:
         b = buoyancy(s, ph)
         G = G + 0.5 * (view(b, dk=-1, ph=ph) + view(b, ph=ph))

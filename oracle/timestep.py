@@ -2,13 +2,17 @@
 (time-discretisation appendix, rk3 equation and pressure-correction method).
 
 Substage m = 1, 2, 3:  X~ = X^m + dt (gamma_m G^m - zeta_m G^{m-1}) for every
-prognostic field, gamma = (8/15, 5/12, 3/4), zeta = (0, 17/60, 5/12); then the
-velocity is projected with dt_eff = (gamma_m - zeta_m) dt, the fraction of the
-step the substage spans (8/15, 2/15, 1/3).
+prognostic field, gamma = (8/15, 5/12, 3/4), zeta = (0, 17/60, 5/12); with
+vertically implicit diffusion every field then solves
+(1 - dt_eff d/dz K d/dz) X = X~ (predictor-velocity and tracer
+time-discretisation equations); then the velocity is projected with
+dt_eff = (gamma_m - zeta_m) dt, the fraction of the step the substage spans
+(8/15, 2/15, 1/3).
 """
 from .fv import to_padded, interior, w_faces
 from .tendencies import tendencies
 from .pressure import project
+from .implicit import implicit_diffusion
 
 GAMMA = (8.0 / 15.0, 5.0 / 12.0, 3.0 / 4.0)
 ZETA = (0.0, 17.0 / 60.0, 5.0 / 12.0)
@@ -37,9 +41,12 @@ def rk3_substage(state, G_prev, m, dt, ph, project_velocity=True):
         if m > 0:
             incr = incr - ZETA[m] * G_prev[n]
         new[n] = X[n] + dt * incr
+    dt_eff = (GAMMA[m] - ZETA[m]) * dt
+    if getattr(ph, "implicit_z", False):
+        for n in fields_of(ph):
+            new[n] = implicit_diffusion(n, new[n], ph, dt_eff)
     p = None
     if project_velocity:
-        dt_eff = (GAMMA[m] - ZETA[m]) * dt
         new["u"], new["v"], new["w"], p = project(new["u"], new["v"], new["w"], dt_eff, ph)
     return make_state(new, ph), G, p
 

@@ -291,9 +291,6 @@ template <class T>
 hipError_t launch_halo_fill(const Dims& d, T* const* fields, const int* kinds, int nf,
                             hipStream_t s);
 template <class T>
-hipError_t launch_tendency(const Dims& d, const FieldSet<T>& fs, const TendParams<T>& p,
-                           int scheme, hipStream_t s);
-template <class T>
 hipError_t launch_tendency_fast(const Dims& d, const FieldSet<T>& fs, const TendParams<T>& p,
                                 int scheme, hipStream_t s);
 struct Spacing { double rdx, rdy, rdz; };

@@ -1,25 +1,9 @@
-// Stencil kernels of the nonhydrostatic hot path on gfx950:
-//   halo fill, fused tendency + RK3 combine, dense<->padded copies,
-//   FP64 diagnostics.
-//
-// Discretisation (finite-volume appendix of arXiv 2502.14148):
-//   * C-grid staggering, face i left of cell i;
-//   * tracer flux divergence (1/V) sum delta(A F) with F = U W(c) - kappa dc/dx
-//     at faces (flux-divergence, advection-flux-divergence equations);
-//   * momentum in flux form: a centred fourth-order advecting velocity times a
-//     WENO5-Z reconstruction of the advected component (momentum-advection
-//     subsection);
-//   * WENO5-Z: Jiang-Shu candidates and indicators, Borges et al. weights
-//     with tau = |beta0 - beta2|, exponent 2 (the printed candidate stencils of
-//     the fifth-order WENO equation are garbled; these are the standard ones);
-//   * f-plane Coriolis with four-point averages, buoyancy b = g(alpha(T-T0) -
-//     beta(S-S0)) averaged to w faces, Laplacian closure;
-//   * RK3 substage X~ = X + dt (gamma_m G^m - zeta_m G^{m-1}) (rk3 equation).
+// Stencil kernels of the nonhydrostatic model on gfx950: halo fill (C-grid
+// staggering of the finite-volume appendix of arXiv 2502.14148, face i left
+// of cell i), dense <-> padded copies and FP64 diagnostics.
 #include "oc_internal.h"
 
 namespace oc {
-
-enum { SCHEME_NONE = 0, SCHEME_WENOZ = 1, SCHEME_LINEAR = 2 };
 
 // ---------------------------------------------------------------------------
 // Halo fill: one thread per padded element; every halo element copies an
@@ -79,204 +63,6 @@ hipError_t launch_halo_fill(const Dims& d, T* const* fields, const int* kinds, i
   long total = padded_elems(d);
   dim3 grid((unsigned)((total + 255) / 256), nf);
   hipLaunchKernelGGL(halo_fill_kernel<T>, grid, dim3(256), 0, s, d, a, total);
-  return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// Reconstruction helpers
-// ---------------------------------------------------------------------------
-__device__ inline float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ inline double rcp(double x) { return 1.0 / x; }
-
-template <class T>
-__device__ inline T interp4(T a0, T a1, T a2, T a3) {
-  // centred fourth-order midpoint interpolation between a1 and a2
-  return ((a1 + a2) * T(7) - (a0 + a3)) * T(1.0 / 12.0);
-}
-
-// Upwind-selected reconstruction at the interface left of q[0] from
-// q[-3s .. 2s]; `vel` is the advecting velocity at the interface.
-template <class T, int SCHEME>
-__device__ inline T reconstruct(const T* __restrict__ q, long s, T vel, T eps) {
-  const T m3 = q[-3 * s], m2 = q[-2 * s], m1 = q[-s];
-  const T p0 = q[0], p1 = q[s], p2 = q[2 * s];
-  const bool pos = vel > T(0);
-  const T a = pos ? m3 : p2;
-  const T b = pos ? m2 : p1;
-  const T c = pos ? m1 : p0;
-  const T d = pos ? p0 : m1;
-  const T e = pos ? p1 : m2;
-  if (SCHEME == SCHEME_LINEAR) {
-    return (T(2) * a - T(13) * b + T(47) * c + T(27) * d - T(3) * e) * T(1.0 / 60.0);
-  }
-  // candidates (times 6)
-  const T r0 = T(2) * a - T(7) * b + T(11) * c;
-  const T r1 = -b + T(5) * c + T(2) * d;
-  const T r2 = T(2) * c + T(5) * d - e;
-  // smoothness indicators
-  const T t0 = a - T(2) * b + c, u0 = a - T(4) * b + T(3) * c;
-  const T t1 = b - T(2) * c + d, u1 = b - d;
-  const T t2 = c - T(2) * d + e, u2 = T(3) * c - T(4) * d + e;
-  const T b0 = T(13.0 / 12.0) * t0 * t0 + T(0.25) * u0 * u0;
-  const T b1 = T(13.0 / 12.0) * t1 * t1 + T(0.25) * u1 * u1;
-  const T b2 = T(13.0 / 12.0) * t2 * t2 + T(0.25) * u2 * u2;
-  const T tau = fabs(b0 - b2);
-  const T q0 = tau * rcp(b0 + eps), q1 = tau * rcp(b1 + eps), q2 = tau * rcp(b2 + eps);
-  const T w0 = T(0.1) * (T(1) + q0 * q0);
-  const T w1 = T(0.6) * (T(1) + q1 * q1);
-  const T w2 = T(0.3) * (T(1) + q2 * q2);
-  return (w0 * r0 + w1 * r1 + w2 * r2) * rcp(T(6) * (w0 + w1 + w2));
-}
-
-// ---------------------------------------------------------------------------
-// Fused tendency + RK3 combine, one thread per cell index (i, j, k).  Each
-// thread computes the tendency of every prognostic field located at that
-// index (u at face i, v at face j, w at face k, tracers at the centre).
-// ---------------------------------------------------------------------------
-template <class T, int SCHEME>
-__device__ inline T adv_flux(const T* __restrict__ q, long s, T vel, T eps) {
-  if (SCHEME == SCHEME_NONE) return T(0);
-  return vel * reconstruct<T, SCHEME>(q, s, vel, eps);
-}
-
-template <class T, int SCHEME>
-__global__ void __launch_bounds__(256) tendency_kernel(Dims d, FieldSet<T> fs, TendParams<T> P) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y;
-  const int k = blockIdx.z;
-  if (i >= d.nx) return;
-  const long c = pidx(d, i, j, k);
-  const long sx = 1, sy = d.sy, sz = d.sz;
-  const T* __restrict__ u = fs.in[0];
-  const T* __restrict__ v = fs.in[1];
-  const T* __restrict__ w = fs.in[2];
-  const T eps = P.eps;
-  const bool bottom_wall = d.zb && (k == 0);
-  const bool top_face_wall = d.zb && (k + 1 == d.nz);
-  T G[MAXF];
-
-  // ---- u at (face i, centre j, centre k)
-  {
-    auto X = [&](long p) {
-      T ub = interp4(u[p - 2], u[p - 1], u[p], u[p + 1]);
-      return adv_flux<T, SCHEME>(u + p, sx, ub, eps) - P.nu * (u[p] - u[p - 1]) * P.rdx;
-    };
-    auto Y = [&](long p) {
-      T vt = interp4(v[p - 2], v[p - 1], v[p], v[p + 1]);
-      return adv_flux<T, SCHEME>(u + p, sy, vt, eps) - P.nu * (u[p] - u[p - sy]) * P.rdy;
-    };
-    auto Z = [&](long p) {
-      T wt = interp4(w[p - 2], w[p - 1], w[p], w[p + 1]);
-      return adv_flux<T, SCHEME>(u + p, sz, wt, eps) - P.nu * (u[p] - u[p - sz]) * P.rdz;
-    };
-    T zb = bottom_wall ? T(0) : Z(c);
-    T zt = top_face_wall ? T(0) : Z(c + sz);
-    T g = -(X(c + 1) - X(c)) * P.rdx - (Y(c + sy) - Y(c)) * P.rdy - (zt - zb) * P.rdz;
-    g += P.f * T(0.25) * (v[c - 1] + v[c] + v[c - 1 + sy] + v[c + sy]);
-    G[0] = g;
-  }
-  // ---- v at (centre i, face j, centre k)
-  {
-    auto X = [&](long p) {
-      T ut = interp4(u[p - 2 * sy], u[p - sy], u[p], u[p + sy]);
-      return adv_flux<T, SCHEME>(v + p, sx, ut, eps) - P.nu * (v[p] - v[p - 1]) * P.rdx;
-    };
-    auto Y = [&](long p) {
-      T vb = interp4(v[p - 2 * sy], v[p - sy], v[p], v[p + sy]);
-      return adv_flux<T, SCHEME>(v + p, sy, vb, eps) - P.nu * (v[p] - v[p - sy]) * P.rdy;
-    };
-    auto Z = [&](long p) {
-      T wt = interp4(w[p - 2 * sy], w[p - sy], w[p], w[p + sy]);
-      return adv_flux<T, SCHEME>(v + p, sz, wt, eps) - P.nu * (v[p] - v[p - sz]) * P.rdz;
-    };
-    T zb = bottom_wall ? T(0) : Z(c);
-    T zt = top_face_wall ? T(0) : Z(c + sz);
-    T g = -(X(c + 1) - X(c)) * P.rdx - (Y(c + sy) - Y(c)) * P.rdy - (zt - zb) * P.rdz;
-    g -= P.f * T(0.25) * (u[c - sy] + u[c + 1 - sy] + u[c] + u[c + 1]);
-    G[1] = g;
-  }
-  // ---- w at (centre i, centre j, face k)
-  {
-    auto X = [&](long p) {
-      T ut = interp4(u[p - 2 * sz], u[p - sz], u[p], u[p + sz]);
-      return adv_flux<T, SCHEME>(w + p, sx, ut, eps) - P.nu * (w[p] - w[p - 1]) * P.rdx;
-    };
-    auto Y = [&](long p) {
-      T vt = interp4(v[p - 2 * sz], v[p - sz], v[p], v[p + sz]);
-      return adv_flux<T, SCHEME>(w + p, sy, vt, eps) - P.nu * (w[p] - w[p - sy]) * P.rdy;
-    };
-    auto Z = [&](long p) {
-      T wb = interp4(w[p - 2 * sz], w[p - sz], w[p], w[p + sz]);
-      return adv_flux<T, SCHEME>(w + p, sz, wb, eps) - P.nu * (w[p] - w[p - sz]) * P.rdz;
-    };
-    T g = T(0);
-    if (!bottom_wall) {
-      g = -(X(c + 1) - X(c)) * P.rdx - (Y(c + sy) - Y(c)) * P.rdy - (Z(c + sz) - Z(c)) * P.rdz;
-      if (P.buoyancy) {
-        const T* __restrict__ Tt = fs.in[3];
-        const T* __restrict__ Ss = fs.in[4];
-        T bl = P.g_alpha * (Tt[c - sz] - P.t_ref) - P.g_beta * (Ss[c - sz] - P.s_ref);
-        T bu = P.g_alpha * (Tt[c] - P.t_ref) - P.g_beta * (Ss[c] - P.s_ref);
-        g += T(0.5) * (bl + bu);
-      }
-    }
-    G[2] = g;
-  }
-  // ---- tracers at (centre i, centre j, centre k)
-  for (int q = 0; q < P.ntr; ++q) {
-    const T* __restrict__ cq = fs.in[3 + q];
-    auto X = [&](long p) {
-      return adv_flux<T, SCHEME>(cq + p, sx, u[p], eps) - P.kappa * (cq[p] - cq[p - 1]) * P.rdx;
-    };
-    auto Y = [&](long p) {
-      return adv_flux<T, SCHEME>(cq + p, sy, v[p], eps) - P.kappa * (cq[p] - cq[p - sy]) * P.rdy;
-    };
-    auto Z = [&](long p) {
-      return adv_flux<T, SCHEME>(cq + p, sz, w[p], eps) - P.kappa * (cq[p] - cq[p - sz]) * P.rdz;
-    };
-    T zb = bottom_wall ? T(0) : Z(c);
-    T zt = top_face_wall ? P.top_flux[q] : Z(c + sz);
-    T g = -(X(c + 1) - X(c)) * P.rdx - (Y(c + sy) - Y(c)) * P.rdy - (zt - zb) * P.rdz;
-    // a tracer stored as c - toff loses the advective flux divergence of the
-    // constant toff, toff * div(u); add it back
-    if (P.toff[q] != T(0))
-      g -= P.toff[q] * ((u[c + 1] - u[c]) * P.rdx + (v[c + sy] - v[c]) * P.rdy +
-                        (w[c + sz] - w[c]) * P.rdz);
-    G[3 + q] = g;
-  }
-
-  const int nf = 3 + P.ntr;
-  for (int q = 0; q < nf; ++q) {
-    const T g = G[q];
-    if (P.combine) {
-      T incr = P.gam * g;
-      if (P.stage > 0) incr -= P.zet * fs.G[q][c];
-      T x = fs.in[q][c] + P.dt * incr;
-      if (q == 2 && bottom_wall) x = T(0);
-      fs.out[q][c] = x;
-      if (P.stage < 2) fs.G[q][c] = g;
-    } else {
-      fs.G[q][c] = g;
-    }
-  }
-}
-
-template <class T>
-hipError_t launch_tendency(const Dims& d, const FieldSet<T>& fs, const TendParams<T>& p,
-                           int scheme, hipStream_t s) {
-  dim3 block(64);
-  dim3 grid((d.nx + 63) / 64, d.ny, d.nz);
-  switch (scheme) {
-    case SCHEME_NONE:
-      hipLaunchKernelGGL((tendency_kernel<T, SCHEME_NONE>), grid, block, 0, s, d, fs, p);
-      break;
-    case SCHEME_WENOZ:
-      hipLaunchKernelGGL((tendency_kernel<T, SCHEME_WENOZ>), grid, block, 0, s, d, fs, p);
-      break;
-    default:
-      hipLaunchKernelGGL((tendency_kernel<T, SCHEME_LINEAR>), grid, block, 0, s, d, fs, p);
-      break;
-  }
   return hipGetLastError();
 }
 
@@ -385,10 +171,6 @@ hipError_t launch_diagnostics(const Dims& d, T* const* fields, int nf, double rd
 
 template hipError_t launch_halo_fill<float>(const Dims&, float* const*, const int*, int, hipStream_t);
 template hipError_t launch_halo_fill<double>(const Dims&, double* const*, const int*, int, hipStream_t);
-template hipError_t launch_tendency<float>(const Dims&, const FieldSet<float>&,
-                                           const TendParams<float>&, int, hipStream_t);
-template hipError_t launch_tendency<double>(const Dims&, const FieldSet<double>&,
-                                            const TendParams<double>&, int, hipStream_t);
 template hipError_t launch_pack<float>(const Dims&, int, int, const float*, void*, int, int,
                                        double, hipStream_t);
 template hipError_t launch_pack<double>(const Dims&, int, int, const double*, void*, int, int,

@@ -53,6 +53,8 @@ class Physics:
     top_flux: dict = field(default_factory=dict)   # tracer -> upward flux at the top wall
     buoyancy: bool = False
     closure: bool = False               # reserve room for a learned closure
+    z_faces: tuple = None               # nz + 1 ascending z faces (bounded z); None: uniform
+    implicit_z: bool = False            # vertical diffusion treated implicitly per substage
 
     def as_dict(self):
         return asdict(self)
@@ -91,6 +93,43 @@ def convection_physics(n=(256, 256, 256), extent=(512.0, 512.0, 256.0),
                    top_flux={"T": surface_buoyancy_flux / (G_EARTH * alpha)})
 
 
+def stretched_faces(nz: int, lz: float, z0: float, sigma: float = 1.5) -> tuple:
+    """z faces refined toward the top (the ocean surface): z_k = z0 + lz
+    tanh(sigma k / nz) / tanh(sigma), k = 0..nz.  sigma = 1.5 makes the top
+    cell about 5.5 times thinner than the bottom one."""
+    xi = np.arange(nz + 1) / nz
+    zf = z0 + lz * np.tanh(sigma * xi) / np.tanh(sigma)
+    zf[0], zf[-1] = z0, z0 + lz
+    return tuple(float(x) for x in zf)
+
+
+def cell_thickness(ph: Physics) -> np.ndarray:
+    """Thickness of each cell layer, shape (nz, 1, 1) (the face differences
+    of ph.z_faces, or lz / nz)."""
+    if ph.z_faces is None:
+        return np.full((ph.nz, 1, 1), ph.lz / ph.nz)
+    return np.diff(np.asarray(ph.z_faces, dtype=np.float64))[:, None, None]
+
+
+def cell_centres_z(ph: Physics) -> np.ndarray:
+    """z of the cell centres (midpoints of the faces), shape (nz,)."""
+    if ph.z_faces is None:
+        return ph.z0 + (np.arange(ph.nz) + 0.5) * (ph.lz / ph.nz)
+    zf = np.asarray(ph.z_faces, dtype=np.float64)
+    return 0.5 * (zf[1:] + zf[:-1])
+
+
+def stretched_convection_physics(n=(256, 256, 256), extent=(512.0, 512.0, 256.0),
+                                 sigma: float = 1.5, implicit_z: bool = True,
+                                 **kw) -> Physics:
+    """The free-convection LES on a vertically stretched grid (surface-refined
+    tanh faces), optionally with vertically implicit diffusion."""
+    ph = convection_physics(n, extent, **kw)
+    ph.z_faces = stretched_faces(n[2], extent[2], -extent[2], sigma)
+    ph.implicit_z = implicit_z
+    return ph
+
+
 # ---------------------------------------------------------------------------
 # Random velocity fields that are discretely divergence-free by construction
 # ---------------------------------------------------------------------------
@@ -100,8 +139,10 @@ def _curl_of_potential(ax, ay, az, dx, dy, dz, bounded):
 
     ax lives at (C, F, F), ay at (F, C, F), az at (F, F, C).  All arrays are
     periodic in x and y; in z they have nz faces (periodic) or nz + 1 faces
-    (bounded, with the wall values already zero).  The discrete divergence of
-    the result is zero identically, so the generator needs no pressure solve.
+    (bounded, with the wall values already zero).  dz is a scalar or the
+    per-layer thickness, shape (nz, 1, 1).  The discrete divergence of the
+    result (z differences over the layer thickness) is zero identically, so
+    the generator needs no pressure solve.
     """
     def dx_f(a):  # forward difference along x, periodic
         return (np.roll(a, -1, axis=2) - a) / dx
@@ -200,7 +241,8 @@ def convection_initial(ph: Physics, seed: int = 0, noise: float = 1e-3,
     assert ph.z_bounded
     rng = np.random.default_rng(seed)
     nz, ny, nx = ph.nz, ph.ny, ph.nx
-    dx, dy, dz = ph.spacing
+    dx, dy, _ = ph.spacing
+    dz = cell_thickness(ph)
     ax = rng.standard_normal((nz + 1, ny, nx))
     ay = rng.standard_normal((nz + 1, ny, nx))
     az = rng.standard_normal((nz, ny, nx))
@@ -211,7 +253,7 @@ def convection_initial(ph: Physics, seed: int = 0, noise: float = 1e-3,
     u, v, w = u * scale, v * scale, w * scale
     w[0] = 0.0
     w[-1] = 0.0
-    zc = ph.z0 + (np.arange(nz) + 0.5) * dz
+    zc = cell_centres_z(ph)
     T = np.broadcast_to((t_surface + n2 / (ph.g * ph.alpha) * zc)[:, None, None], (nz, ny, nx)).copy()
     S = np.full((nz, ny, nx), s0)
     if tracer_noise > 0:
@@ -247,7 +289,8 @@ def random_state(ph: Physics, seed: int = 0, vel: float = 1.0, tracer_scale: flo
     rng = np.random.default_rng(seed)
     nz, ny, nx = ph.nz, ph.ny, ph.nx
     nwz = nz + 1 if ph.z_bounded else nz
-    dx, dy, dz = ph.spacing
+    dx, dy, _ = ph.spacing
+    dz = cell_thickness(ph)
     if divergence_free:
         ax = rng.standard_normal((nwz, ny, nx))
         ay = rng.standard_normal((nwz, ny, nx))
