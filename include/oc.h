@@ -73,10 +73,16 @@ enum { OC_ETA = 16, OC_UBT = 17, OC_VBT = 18, OC_GUBT = 19, OC_GVBT = 20, OC_TAU
 #define OC_MAX_TRACERS 4
 #define OC_NDIAG 8
 
-/* Grid: RectilinearGrid or LatitudeLongitudeGrid of the library subsection
- * (uniform spacing in each coordinate).
+/* Grid: RectilinearGrid or LatitudeLongitudeGrid of the library subsection.
  *   OC_RECTILINEAR: domain [x0, x0+lx) x [y0, y0+ly) x [z0, z0+lz) in meters;
- *     x and y periodic, z per topology_z.
+ *     x and y periodic and uniformly spaced, z per topology_z.  z is uniform,
+ *     or stretched when z_faces is given: nz + 1 strictly increasing face
+ *     positions (host array, copied at oc_grid_create) from z0 to z0 + lz,
+ *     cells between consecutive faces, centres at the midpoints
+ *     (one-dimensional staggered-grid listing of the finite-volume
+ *     appendix).  Stretched z needs topology_z = OC_BOUNDED and 4 <= nz <=
+ *     256; its pressure solve is the mixed FFT(x, y) - tridiagonal(z) one
+ *     (pressure-correction appendix).
  *   OC_LATLON (thin spherical shell of `radius`): x0, lx are the longitude
  *     start and extent in degrees (periodic, lx = 360), y0, ly the latitude
  *     start and extent in degrees (walls at both ends), z0, lz in meters
@@ -89,6 +95,8 @@ typedef struct {
   double z0, lz;
   int32_t coord;            /* OC_RECTILINEAR or OC_LATLON */
   double radius;            /* OC_LATLON: sphere radius in meters */
+  const double* z_faces;    /* OC_RECTILINEAR, bounded z: NULL (uniform) or
+                               nz + 1 face positions (see above) */
 } oc_grid_desc;
 
 /* Model physics (NonhydrostaticModel arguments of the equations section). */
@@ -115,6 +123,15 @@ typedef struct {
   double omega;             /* OC_HYDROSTATIC: planetary rotation rate */
   int32_t closure;          /* 1: reserve workspace for a learned closure
                                (oc_model_set_closure) */
+  int32_t implicit_z;       /* OC_NONHYDROSTATIC with bounded z: 1 treats the
+                               vertical part of the nu and kappa diffusion
+                               implicitly (vertically implicit time
+                               discretisation of the time-stepping appendix):
+                               it leaves the tendencies, and after each RK3
+                               combine every field solves
+                               (1 - dt_eff d/dz K d/dz) X = X~ column by
+                               column, dt_eff = (gamma_m - zeta_m) dt, before
+                               the pressure correction */
 } oc_model_desc;
 
 typedef struct oc_grid oc_grid;
@@ -171,8 +188,21 @@ int oc_get_pressure(oc_model* m, double* buf, int32_t on_device, void* stream);
 
 /* Advance nsteps full RK3 steps of size dt: per substage m the fused
  * tendency + RK3 combine X~ = X + dt(gamma_m G^m - zeta_m G^{m-1}),
- * then the pressure correction with dt_eff = (gamma_m - zeta_m) dt. */
+ * with implicit_z the implicit vertical diffusion over dt_eff, then the
+ * pressure correction with dt_eff = (gamma_m - zeta_m) dt. */
 int oc_rk3_step(oc_model* m, double dt, int32_t nsteps, void* stream);
+
+/* One implicit vertical-diffusion solve of the current state (the step that
+ * oc_rk3_step applies after each combine when implicit_z is set; tracer- and
+ * predictor-velocity time-discretisation equations): every column of u, v
+ * and the tracers solves (1 - dt_eff d/dz K d/dz) X^new = X with no
+ * diffusive flux through the walls (K = nu for u, v; kappa for tracers),
+ * and w on the interior faces with w = 0 on the walls (K = nu); second-order
+ * operator on the (stretched) z grid; halos refilled.  Tridiagonal
+ * elimination with factors precomputed in FP64 per (dt_eff, K).  Needs a
+ * nonhydrostatic model with bounded z.  Errors: OC_ERR_ARG (dt_eff <= 0),
+ * OC_ERR_UNSUPPORTED. */
+int oc_implicit_vertical_diffusion(oc_model* m, double dt_eff, void* stream);
 
 /* Per-kernel-class timing with HIP events recorded on the model's stream
  * around every launch (classes: OC_PROF_*).  oc_profile(m, 1) clears the
@@ -182,9 +212,10 @@ int oc_rk3_step(oc_model* m, double dt, int32_t nsteps, void* stream);
 enum {
   OC_PROF_TENDENCY = 0, OC_PROF_FFT_X_FWD = 1, OC_PROF_FFT_Y_FWD = 2, OC_PROF_Z_SOLVE = 3,
   OC_PROF_FFT_Y_INV = 4, OC_PROF_FFT_X_INV = 5, OC_PROF_PROJECT = 6, OC_PROF_HALO = 7,
-  OC_PROF_CLOSURE = 8, OC_PROF_HYDRO_DIAG = 9, OC_PROF_HYDRO_TEND = 10, OC_PROF_BAROTROPIC = 11
+  OC_PROF_CLOSURE = 8, OC_PROF_HYDRO_DIAG = 9, OC_PROF_HYDRO_TEND = 10, OC_PROF_BAROTROPIC = 11,
+  OC_PROF_IMPLICIT_Z = 12
 };
-#define OC_NPROF 12
+#define OC_NPROF 13
 int oc_profile(oc_model* m, int32_t enable);
 int oc_profile_read(oc_model* m, double* ms, int64_t* launches);
 
@@ -236,7 +267,8 @@ int oc_hydrostatic_step(oc_model* m, double dt, int32_t N, int32_t M, const doub
  * every member's column tiles, and per class of members with equal grids one
  * launch per Poisson pass.  Results equal those of oc_rk3_step on each
  * member.  Members: nonhydrostatic, WENO5-Z, tracers T and S, no learned
- * closure, one precision, nx and ny multiples of 8.
+ * closure, uniform grids without implicit vertical diffusion, one
+ * precision, nx and ny multiples of 8.
  * Flags: OC_ENS_TUNE times the candidate launch configurations (column tile
  * 32x8, 16x8 or 8x8; one workgroup per tile or a persistent grid draining an
  * atomic work queue; k-chunk length) at creation and keeps the fastest; with
@@ -304,8 +336,8 @@ int oc_mlp_train_step(oc_mlp* m, const float* x, const float* target, int32_t ba
                       double* loss, void* stream);
 
 /* Attach (net != NULL) or detach (net == NULL) the learned closure of a
- * nonhydrostatic model created with closure = 1 (walls in z; tracers 0, 1 =
- * T, S).  Every substage then gathers the standardised features of all
+ * nonhydrostatic model created with closure = 1 (walls in z, uniform
+ * spacing; tracers 0, 1 = T, S).  Every substage then gathers the standardised features of all
  * cells, runs the network (the model's cell count must be a multiple of 32
  * and at most the network's max_batch) and adds the flux divergence of the
  * predicted vertical fluxes -d/dz(F) to G: u and v take F at their (x or y
@@ -324,7 +356,8 @@ int oc_model_set_closure(oc_model* m, oc_mlp* net, const double* stats, void* st
  * FP32, ncell x 500, cells in (k, j, i) order, x fastest), standardised with
  * stats[0..7] (input means and standard deviations of u, v, w, b; stats as
  * for oc_model_set_closure, the output half unused).  For training data.
- * Errors: OC_ERR_UNSUPPORTED without walls in z or without T, S buoyancy. */
+ * Errors: OC_ERR_UNSUPPORTED without walls in z, with stretched z or
+ * without T, S buoyancy. */
 int oc_closure_features(oc_model* m, const double* stats, float* x, void* stream);
 
 /* Coarse-graining (the regridding paragraph of the finite-volume appendix:
@@ -336,8 +369,8 @@ int oc_closure_features(oc_model* m, const double* stats, float* x, void* stream
  * (4, nz, ny, nx) of the coarse grid, may be NULL) receives the vertical
  * subgrid fluxes <q w> - <q><w> over each r^3 box, q = u, v, w, b, with the
  * velocities first averaged to the fine cell centres (physical units).
- * Sums in FP64.  Errors: OC_ERR_UNSUPPORTED (not wall-bounded, no T, S
- * buoyancy), OC_ERR_SHAPE (grids not related by one factor), OC_ERR_ARG
+ * Sums in FP64.  Errors: OC_ERR_UNSUPPORTED (not wall-bounded, stretched
+ * z, no T, S buoyancy), OC_ERR_SHAPE (grids not related by one factor), OC_ERR_ARG
  * (different precision, domain or tracer storage). */
 int oc_coarse_grain(oc_model* fine, oc_model* coarse, float* fluxes, void* stream);
 

@@ -1,6 +1,7 @@
 // C ABI of liboc (declared in include/oc.h): argument validation, workspace
 // carving, FFT tables, and the orchestration of the RK3 / pressure-correction
 // step on a caller-provided HIP stream.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -45,6 +46,7 @@ struct Layout {
   uint64_t spec, p, twx, twy, twz, dctz, lamx, lamy, lamz, staging, diag;
   uint64_t baro[13], metric, hzeta, hpx, hpy, hmet;
   uint64_t gc[4];
+  uint64_t zt64, ztT, vfac;
   uint64_t total;
 };
 
@@ -90,6 +92,9 @@ Layout make_layout(const oc_grid_desc& g, const oc_model_desc& m) {
   }
   if (m.closure)
     for (int q = 0; q < 4; ++q) { L.gc[q] = off; off += fb; }
+  L.zt64 = off; off += align256((uint64_t)zt64_len(g.nz) * 8);
+  L.ztT = off; off += align256((uint64_t)ztT_len(g.nz) * esz);
+  L.vfac = off; off += align256((uint64_t)vfac_len(g.nz) * esz);
   L.staging = off; off += align256((uint64_t)(g.nz + 1) * (g.ny + 1) * g.nx * 8);
   L.diag = off; off += align256((uint64_t)DIAG_BLOCKS * DIAG_PARTS * 8);
   L.total = off;
@@ -107,11 +112,31 @@ int validate_grid(const oc_grid_desc* d) {
     set_error("domain extents must be positive and finite");
     return OC_ERR_ARG;
   }
+  if (d->z_faces && d->coord != OC_RECTILINEAR) {
+    set_error("z_faces are supported on rectilinear grids only");
+    return OC_ERR_UNSUPPORTED;
+  }
+  if (d->z_faces) {
+    if (d->topology_z != OC_BOUNDED || d->nz < 4 || d->nz > 256) {
+      set_error("a stretched z needs topology_z = OC_BOUNDED and 4 <= nz <= 256");
+      return OC_ERR_UNSUPPORTED;
+    }
+    const double tol = 1e-9 * d->lz;
+    for (int k = 0; k <= d->nz; ++k)
+      if (!std::isfinite(d->z_faces[k]) || (k > 0 && !(d->z_faces[k] > d->z_faces[k - 1]))) {
+        set_error("z_faces must be finite and strictly increasing (face %d)", k);
+        return OC_ERR_ARG;
+      }
+    if (std::fabs(d->z_faces[0] - d->z0) > tol || std::fabs(d->z_faces[d->nz] - (d->z0 + d->lz)) > tol) {
+      set_error("z_faces must run from z0 to z0 + lz");
+      return OC_ERR_ARG;
+    }
+  }
   if (d->coord == OC_RECTILINEAR) {
     if (!fft_length_supported(d->nx) || !fft_length_supported(d->ny) ||
-        !fft_length_supported(d->nz)) {
-      set_error("unsupported grid size %d x %d x %d (each of 8,16,32,64,96,128,256)", d->nx,
-                d->ny, d->nz);
+        (!d->z_faces && !fft_length_supported(d->nz))) {
+      set_error("unsupported grid size %d x %d x %d (each of 8,16,32,64,96,128,256; a "
+                "stretched z any 4..256)", d->nx, d->ny, d->nz);
       return OC_ERR_UNSUPPORTED;
     }
     if (d->ny % 2) { set_error("ny must be even"); return OC_ERR_UNSUPPORTED; }
@@ -165,6 +190,10 @@ int validate_model(const oc_model_desc* m) {
     set_error("hydrostatic model needs depth > 0");
     return OC_ERR_ARG;
   }
+  if (m->implicit_z != 0 && m->implicit_z != 1) {
+    set_error("implicit_z must be 0 or 1");
+    return OC_ERR_ARG;
+  }
   if (m->kind == OC_HYDROSTATIC && m->ntracers != 2) {
     set_error("the hydrostatic model carries exactly T and S (ntracers = 2)");
     return OC_ERR_ARG;
@@ -179,6 +208,14 @@ int validate_pair(const oc_grid_desc& g, const oc_model_desc& m) {
   }
   if (m.kind == OC_HYDROSTATIC && g.coord != OC_LATLON) {
     set_error("the hydrostatic model runs on lat-lon grids");
+    return OC_ERR_UNSUPPORTED;
+  }
+  if (m.implicit_z && (m.kind != OC_NONHYDROSTATIC || g.topology_z != OC_BOUNDED)) {
+    set_error("implicit vertical diffusion needs the nonhydrostatic model with walls in z");
+    return OC_ERR_UNSUPPORTED;
+  }
+  if (m.closure && g.z_faces) {
+    set_error("the learned closure needs a uniform z");
     return OC_ERR_UNSUPPORTED;
   }
   return OC_OK;
@@ -313,7 +350,8 @@ int pressure_call(oc_model* m, int which, double dt_eff, hipStream_t s) {
   const T* u = (const T*)m->state[which][0];
   const T* v = (const T*)m->state[which][1];
   const T* w = (const T*)m->state[which][2];
-  Spacing sp{1.0 / m->dx, 1.0 / m->dy, 1.0 / m->dz};
+  const int nz = m->dims.nz;
+  Spacing sp{1.0 / m->dx, 1.0 / m->dy, m->zt64 + zt_rdzc(nz), m->zt64 + zt_rdzf(nz)};
   {
     ProfScope ps(m, OC_PROF_FFT_X_FWD, s);
     OC_CHECK_HIP(launch_poisson_x_forward<T>(m->dims, u, v, w, 1.0 / dt_eff, sp, m->sb, s));
@@ -324,7 +362,11 @@ int pressure_call(oc_model* m, int which, double dt_eff, hipStream_t s) {
   }
   {
     ProfScope ps(m, OC_PROF_Z_SOLVE, s);
-    OC_CHECK_HIP(launch_poisson_spectral(m->dims, m->sb, s));
+    if (m->stretched)
+      OC_CHECK_HIP(launch_poisson_tridiag(m->dims, m->sb, m->zt64 + zt_lo(nz), m->zt64 + zt_up(nz),
+                                          m->zt64 + zt_dzc(nz), m->zt64 + zt_dzf(nz), s));
+    else
+      OC_CHECK_HIP(launch_poisson_spectral(m->dims, m->sb, s));
   }
   {
     ProfScope ps(m, OC_PROF_FFT_Y_INV, s);
@@ -337,19 +379,71 @@ int pressure_call(oc_model* m, int which, double dt_eff, hipStream_t s) {
   {
     ProfScope ps(m, OC_PROF_PROJECT, s);
     OC_CHECK_HIP(launch_project<T>(m->dims, (T*)m->state[which][0], (T*)m->state[which][1],
-                                   (T*)m->state[which][2], dt_eff, sp.rdx, sp.rdy, sp.rdz,
-                                   m->sb.p, s));
+                                   (T*)m->state[which][2], dt_eff, sp, m->sb.p, s));
+  }
+  return OC_OK;
+}
+
+// Elimination factors of the implicit vertical diffusion (FP64 on the host,
+// stored in state precision).  stage >= 0: the three RK3 substages of a step
+// dt (slot = substage, dt_eff = (gamma - zeta) dt), kept while dt repeats;
+// stage < 0: one solve with dt_eff = dt in slot 0.  The upload is ordered on
+// the stream after the work that used the previous factors.
+template <class T>
+int implicit_factors(oc_model* m, double dt, int stage, hipStream_t s) {
+  if (stage >= 0 && m->vfac_dt == dt) return OC_OK;
+  const int nz = m->dims.nz;
+  std::vector<double> f64(vfac_len(nz), 0.0);
+  const int nstage = stage < 0 ? 1 : 3;
+  for (int st = 0; st < nstage; ++st) {
+    const double dte = stage < 0 ? dt : (RK_GAMMA[st] - RK_ZETA[st]) * dt;
+    double* base = f64.data() + (size_t)st * 9 * nz;
+    vertical_factors(m->hdzc.data(), m->hdzf.data(), nz, m->md.nu, dte, 0, base);
+    vertical_factors(m->hdzc.data(), m->hdzf.data(), nz, m->md.nu, dte, 1, base + 3 * nz);
+    vertical_factors(m->hdzc.data(), m->hdzf.data(), nz, m->md.kappa, dte, 0, base + 6 * nz);
+  }
+  m->vfac_host.resize(f64.size() * m->esz);
+  for (size_t q = 0; q < f64.size(); ++q) {
+    if (m->esz == 8) std::memcpy(&m->vfac_host[q * 8], &f64[q], 8);
+    else { const float f = (float)f64[q]; std::memcpy(&m->vfac_host[q * 4], &f, 4); }
+  }
+  OC_CHECK_HIP(hipMemcpyAsync(m->vfac, m->vfac_host.data(), m->vfac_host.size(),
+                              hipMemcpyHostToDevice, s));
+  // the host buffer is rewritten by the next change of dt
+  OC_CHECK_HIP(hipStreamSynchronize(s));
+  m->vfac_dt = stage < 0 ? std::nan("") : dt;
+  return OC_OK;
+}
+
+// Implicit vertical diffusion of state `which` with the factors of slot st.
+template <class T>
+int implicit_call(oc_model* m, int which, int st, hipStream_t s) {
+  ProfScope ps(m, OC_PROF_IMPLICIT_Z, s);
+  const int nz = m->dims.nz;
+  const T* base = (const T*)m->vfac + (size_t)st * 9 * nz;
+  for (int q = 0; q < m->nf; ++q) {
+    const int cls = (q < 2) ? 0 : (q == 2 ? 1 : 2);
+    OC_CHECK_HIP(launch_vertical_implicit<T>(m->dims, (T*)m->state[which][q], q == 2 ? 1 : 0,
+                                             base + 3 * nz * cls, s));
   }
   return OC_OK;
 }
 
 template <class T>
 int rk3_steps(oc_model* m, double dt, int nsteps, hipStream_t s) {
+  if (m->md.implicit_z) {
+    int rc = implicit_factors<T>(m, dt, 0, s);
+    if (rc) return rc;
+  }
   for (int n = 0; n < nsteps; ++n) {
     for (int st = 0; st < 3; ++st) {
       const int in = m->cur, out = 1 - m->cur;
       int rc = tendency_call<T>(m, in, out, st, dt, 1, s);
       if (rc) return rc;
+      if (m->md.implicit_z) {
+        rc = implicit_call<T>(m, out, st, s);
+        if (rc) return rc;
+      }
       // the projection writes the velocity halos, the tendency kernel those
       // of the tracers
       rc = pressure_call<T>(m, out, (RK_GAMMA[st] - RK_ZETA[st]) * dt, s);
@@ -388,8 +482,10 @@ template <class T>
 int diagnostics_call(oc_model* m, double* out, hipStream_t s) {
   T* f[MAXF];
   for (int q = 0; q < m->nf; ++q) f[q] = (T*)m->state[m->cur][q];
-  OC_CHECK_HIP(launch_diagnostics<T>(m->dims, f, m->nf, 1.0 / m->dx, 1.0 / m->dy, 1.0 / m->dz,
-                                     m->diag_part, DIAG_BLOCKS, s));
+  const int nz = m->dims.nz;
+  OC_CHECK_HIP(launch_diagnostics<T>(m->dims, f, m->nf, 1.0 / m->dx, 1.0 / m->dy,
+                                     m->zt64 + zt_rdzc(nz), m->zt64 + zt_dzc(nz), m->diag_part,
+                                     DIAG_BLOCKS, s));
   std::vector<double> part((size_t)DIAG_BLOCKS * DIAG_PARTS);
   OC_CHECK_HIP(hipMemcpyAsync(part.data(), m->diag_part, part.size() * 8, hipMemcpyDeviceToHost, s));
   OC_CHECK_HIP(hipStreamSynchronize(s));
@@ -399,21 +495,65 @@ int diagnostics_call(oc_model* m, double* out, hipStream_t s) {
       double x = part[(size_t)b * DIAG_PARTS + q];
       acc[q] = (q < 4) ? std::fmax(acc[q], x) : acc[q] + x;
     }
-  const double vol = m->dx * m->dy * m->dz;
-  out[0] = acc[0] * std::fmin(m->dx, std::fmin(m->dy, m->dz));
+  // tracer sums are already weighted by the layer thickness
+  const double area = m->dx * m->dy;
+  out[0] = acc[0] * std::fmin(m->dx, std::fmin(m->dy, m->dzmin));
   out[1] = acc[1];
   out[2] = acc[2];
   out[3] = acc[3];
   const double ncell = (double)m->dims.nx * m->dims.ny * m->dims.nz;
   for (int q = 0; q < 4; ++q) {
     const double off = (OC_TRACER0 + q < m->nf) ? m->offset[OC_TRACER0 + q] : 0.0;
-    out[4 + q] = (acc[4 + q] + off * ncell) * vol;
+    out[4 + q] = (acc[4 + q] + off * ncell * m->dz) * area;
   }
   if (acc[8] > 0) {
     set_error("state holds %g non-finite cells", acc[8]);
     return OC_ERR_NONFINITE;
   }
   return OC_OK;
+}
+
+// Vertical tables of a grid (uniform or stretched z), in the layout of
+// oc_model::zt64 (FP64) and oc_model::ztT (state precision, esz bytes).
+void fill_z_tables(const oc_grid_desc& g, const std::vector<double>& zf, int esz,
+                   std::vector<double>& z64, std::vector<char>& zT) {
+  const int nz = g.nz;
+  const bool bounded = g.topology_z == OC_BOUNDED;
+  std::vector<double> dzc(nz), dzf(nz + 1);
+  if (zf.empty()) {
+    for (int k = 0; k < nz; ++k) dzc[k] = g.lz / nz;
+    for (int k = 0; k <= nz; ++k) dzf[k] = g.lz / nz;
+  } else {
+    for (int k = 0; k < nz; ++k) dzc[k] = zf[k + 1] - zf[k];
+    for (int k = 1; k < nz; ++k) dzf[k] = 0.5 * (zf[k + 1] - zf[k - 1]);
+    dzf[0] = dzc[0];        // mirror image of the first centre below the wall
+    dzf[nz] = dzc[nz - 1];
+  }
+  z64.assign(zt64_len(nz), 0.0);
+  for (int k = 0; k < nz; ++k) {
+    z64[zt_dzc(nz) + k] = dzc[k];
+    z64[zt_rdzc(nz) + k] = 1.0 / dzc[k];
+  }
+  for (int k = 0; k <= nz; ++k) {
+    z64[zt_dzf(nz) + k] = dzf[k];
+    z64[zt_rdzf(nz) + k] = 1.0 / dzf[k];
+  }
+  // off-diagonals of the vertical part of the Laplacian (no flux at walls)
+  for (int k = 0; k < nz; ++k) {
+    z64[zt_lo(nz) + k] = (k > 0) ? 1.0 / (dzc[k] * dzf[k]) : 0.0;
+    z64[zt_up(nz) + k] = (k < nz - 1) ? 1.0 / (dzc[k] * dzf[k + 1]) : 0.0;
+  }
+  // state precision: rdzc for k = -1..nz (images below and above), rdzf
+  std::vector<double> t(ztT_len(nz));
+  t[0] = 1.0 / (bounded ? dzc[0] : dzc[nz - 1]);
+  for (int k = 0; k < nz; ++k) t[1 + k] = 1.0 / dzc[k];
+  t[nz + 1] = 1.0 / (bounded ? dzc[nz - 1] : dzc[0]);
+  for (int k = 0; k <= nz; ++k) t[nz + 2 + k] = 1.0 / dzf[k];
+  zT.assign(t.size() * esz, 0);
+  for (size_t q = 0; q < t.size(); ++q) {
+    if (esz == 8) std::memcpy(&zT[q * 8], &t[q], 8);
+    else { const float f = (float)t[q]; std::memcpy(&zT[q * 4], &f, 4); }
+  }
 }
 
 void fill_tables(const oc_grid_desc& g, std::vector<double>& twx, std::vector<double>& twy,
@@ -702,6 +842,10 @@ int oc_grid_create(const oc_grid_desc* d, oc_grid** out) {
   oc_grid* g = new (std::nothrow) oc_grid;
   if (!g) { set_error("out of host memory"); return OC_ERR_ARG; }
   g->d = *d;
+  if (d->z_faces) {
+    g->zf.assign(d->z_faces, d->z_faces + d->nz + 1);
+    g->d.z_faces = g->zf.data();  // the grid's own copy
+  }
   *out = g;
   return OC_OK;
 }
@@ -744,6 +888,8 @@ int oc_model_create(const oc_grid* g, const oc_model_desc* md, void* workspace,
   oc_model* m = new (std::nothrow) oc_model;
   if (!m) { set_error("out of host memory"); return OC_ERR_ARG; }
   m->gd = g->d;
+  m->gd.z_faces = nullptr;  // the model keeps only the device tables
+  m->stretched = g->zf.empty() ? 0 : 1;
   m->md = *md;
   m->dims = make_dims(g->d.nx, g->d.ny, g->d.nz, g->d.topology_z == OC_BOUNDED);
   m->nf = 3 + md->ntracers;
@@ -781,6 +927,10 @@ int oc_model_create(const oc_grid* g, const oc_model_desc* md, void* workspace,
   m->sb.nxp = spec_pitch(g->d.nx);
   m->staging = m->ws + L.staging;
   m->diag_part = (double*)(m->ws + L.diag);
+  m->zt64 = (double*)(m->ws + L.zt64);
+  m->ztT = m->ws + L.ztT;
+  m->vfac = m->ws + L.vfac;
+  m->vfac_dt = std::nan("");
 
   m->kind = md->kind;
   for (int q = 0; q < 2; ++q) {
@@ -807,6 +957,17 @@ int oc_model_create(const oc_grid* g, const oc_model_desc* md, void* workspace,
   for (int q = 0; q < 4; ++q) m->gc[q] = md->closure ? (void*)(m->ws + L.gc[q]) : nullptr;
 
   hipError_t e = hipMemset(m->ws, 0, L.total);
+  {
+    std::vector<double> z64;
+    std::vector<char> zT;
+    fill_z_tables(g->d, g->zf, m->esz, z64, zT);
+    const int nz = g->d.nz;
+    m->hdzc.assign(z64.begin() + zt_dzc(nz), z64.begin() + zt_dzc(nz) + nz);
+    m->hdzf.assign(z64.begin() + zt_dzf(nz), z64.begin() + zt_dzf(nz) + nz + 1);
+    m->dzmin = *std::min_element(m->hdzc.begin(), m->hdzc.end());
+    if (e == hipSuccess) e = hipMemcpy(m->zt64, z64.data(), z64.size() * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(m->ztT, zT.data(), zT.size(), hipMemcpyHostToDevice);
+  }
   if (md->kind == OC_NONHYDROSTATIC) {
     std::vector<double> twx, twy, twz, dctz, lamx, lamy, lamz;
     fill_tables(g->d, twx, twy, twz, dctz, lamx, lamy, lamz, m->dx, m->dy, m->dz);
@@ -976,6 +1137,21 @@ int oc_rk3_step(oc_model* m, double dt, int32_t nsteps, void* stream) {
   return (m->esz == 8) ? rk3_steps<double>(m, dt, nsteps, s) : rk3_steps<float>(m, dt, nsteps, s);
 }
 
+int oc_implicit_vertical_diffusion(oc_model* m, double dt_eff, void* stream) {
+  if (!m) { set_error("model is NULL"); return OC_ERR_ARG; }
+  if (m->kind != OC_NONHYDROSTATIC || !m->dims.zb) {
+    set_error("implicit vertical diffusion needs a nonhydrostatic model with walls in z");
+    return OC_ERR_UNSUPPORTED;
+  }
+  if (!(dt_eff > 0) || !std::isfinite(dt_eff)) { set_error("dt_eff must be positive"); return OC_ERR_ARG; }
+  hipStream_t s = (hipStream_t)stream;
+  int rc = (m->esz == 8) ? implicit_factors<double>(m, dt_eff, -1, s)
+                         : implicit_factors<float>(m, dt_eff, -1, s);
+  if (rc) return rc;
+  return (m->esz == 8) ? implicit_call<double>(m, m->cur, 0, s)
+                       : implicit_call<float>(m, m->cur, 0, s);
+}
+
 int oc_diagnostics(oc_model* m, double* out, void* stream) {
   if (!m || !out) { set_error("NULL argument"); return OC_ERR_ARG; }
   hipStream_t s = (hipStream_t)stream;
@@ -1016,8 +1192,10 @@ int oc_hydrostatic_step(oc_model* m, double dt, int32_t N, int32_t M, const doub
 int oc_model_set_closure(oc_model* m, oc_mlp* net, const double* stats, void* stream) {
   if (!m) { set_error("model is NULL"); return OC_ERR_ARG; }
   if (!net) { m->net = nullptr; return OC_OK; }
-  if (m->kind != OC_NONHYDROSTATIC || !m->dims.zb || !m->md.buoyancy || !m->gc[0]) {
-    set_error("the closure needs a wall-bounded nonhydrostatic model with T, S created with closure = 1");
+  if (m->kind != OC_NONHYDROSTATIC || !m->dims.zb || !m->md.buoyancy || !m->gc[0] ||
+      m->stretched) {
+    set_error("the closure needs a wall-bounded, uniformly spaced nonhydrostatic model with T, S "
+              "created with closure = 1");
     return OC_ERR_UNSUPPORTED;
   }
   if (!stats) { set_error("stats is NULL"); return OC_ERR_ARG; }
@@ -1043,8 +1221,8 @@ int oc_model_set_closure(oc_model* m, oc_mlp* net, const double* stats, void* st
 
 int oc_closure_features(oc_model* m, const double* stats, float* x, void* stream) {
   if (!m || !stats || !x) { set_error("NULL argument"); return OC_ERR_ARG; }
-  if (m->kind != OC_NONHYDROSTATIC || !m->dims.zb || !m->md.buoyancy) {
-    set_error("features need a wall-bounded nonhydrostatic model with T, S");
+  if (m->kind != OC_NONHYDROSTATIC || !m->dims.zb || !m->md.buoyancy || m->stretched) {
+    set_error("features need a wall-bounded, uniformly spaced nonhydrostatic model with T, S");
     return OC_ERR_UNSUPPORTED;
   }
   for (int q = 0; q < 4; ++q)
@@ -1067,8 +1245,8 @@ int oc_coarse_grain(oc_model* fine, oc_model* coarse, float* fluxes, void* strea
   if (!fine || !coarse) { set_error("NULL argument"); return OC_ERR_ARG; }
   if (fine->kind != OC_NONHYDROSTATIC || coarse->kind != OC_NONHYDROSTATIC ||
       !fine->dims.zb || !coarse->dims.zb || fine->nf < 5 || coarse->nf < 5 ||
-      !fine->md.buoyancy) {
-    set_error("coarse-graining takes wall-bounded nonhydrostatic models with T, S");
+      !fine->md.buoyancy || fine->stretched || coarse->stretched) {
+    set_error("coarse-graining takes wall-bounded, uniformly spaced nonhydrostatic models with T, S");
     return OC_ERR_UNSUPPORTED;
   }
   if (fine->esz != coarse->esz) { set_error("both models need the same precision"); return OC_ERR_ARG; }

@@ -85,9 +85,9 @@ int validate_members(oc_model* const* members, int count) {
     const oc_model* m = members[i];
     if (!m) { set_error("member %d is NULL", i); return OC_ERR_ARG; }
     if (m->kind != OC_NONHYDROSTATIC || m->md.advection != OC_ADV_WENO5Z ||
-        m->md.ntracers != 2 || m->net) {
-      set_error("member %d: ensembles take nonhydrostatic WENO5-Z models with tracers T, S and "
-                "no learned closure", i);
+        m->md.ntracers != 2 || m->net || m->stretched || m->md.implicit_z) {
+      set_error("member %d: ensembles take nonhydrostatic WENO5-Z models with tracers T, S, "
+                "uniform grids, explicit diffusion and no learned closure", i);
       return OC_ERR_UNSUPPORTED;
     }
     if (m->esz != members[0]->esz) {
@@ -250,7 +250,10 @@ int enqueue_step(oc_ensemble* e, int p, double dt, hipStream_t s) {
       const oc_model* m0 = e->mem[c.idx[0]];
       const int ns = (int)c.idx.size();
       const PoissonSlots* bs = c.slots[par];
-      Spacing sp{1.0 / m0->dx, 1.0 / m0->dy, 1.0 / m0->dz};
+      // members of a class share their uniform spacings, so member 0's
+      // vertical tables serve all of them
+      const int nz = m0->dims.nz;
+      Spacing sp{1.0 / m0->dx, 1.0 / m0->dy, m0->zt64 + zt_rdzc(nz), m0->zt64 + zt_rdzf(nz)};
       OC_CHECK_HIP(launch_poisson_x_forward<T>(m0->dims, nullptr, nullptr, nullptr, 1.0 / dt_eff,
                                                sp, m0->sb, s, bs, ns));
       OC_CHECK_HIP(launch_poisson_y(m0->dims, m0->sb, -1, s, bs, ns));
@@ -258,7 +261,7 @@ int enqueue_step(oc_ensemble* e, int p, double dt, hipStream_t s) {
       OC_CHECK_HIP(launch_poisson_y(m0->dims, m0->sb, 1, s, bs, ns));
       OC_CHECK_HIP(launch_poisson_x_inverse(m0->dims, m0->sb, s, bs, ns));
       OC_CHECK_HIP(launch_project<T>(m0->dims, (T*)nullptr, (T*)nullptr, (T*)nullptr, dt_eff,
-                                     sp.rdx, sp.rdy, sp.rdz, nullptr, s, bs, ns));
+                                     sp, nullptr, s, bs, ns));
     }
   }
   return OC_OK;

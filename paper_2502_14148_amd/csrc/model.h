@@ -13,12 +13,24 @@ namespace oc {
 constexpr double RK_GAMMA[3] = {8.0 / 15.0, 5.0 / 12.0, 3.0 / 4.0};
 constexpr double RK_ZETA[3] = {0.0, 17.0 / 60.0, 5.0 / 12.0};
 
+// Offsets of the FP64 vertical tables in oc_model::zt64, and table lengths.
+inline int zt_dzc(int)       { return 0; }
+inline int zt_dzf(int nz)    { return nz; }
+inline int zt_rdzc(int nz)   { return 2 * nz + 1; }
+inline int zt_rdzf(int nz)   { return 3 * nz + 1; }
+inline int zt_lo(int nz)     { return 4 * nz + 2; }
+inline int zt_up(int nz)     { return 5 * nz + 2; }
+inline int zt64_len(int nz)  { return 6 * nz + 2; }
+inline int ztT_len(int nz)   { return 2 * nz + 3; }
+inline int vfac_len(int nz)  { return 27 * nz; }
+
 }  // namespace oc
 
 using namespace oc;
 
 struct oc_grid {
   oc_grid_desc d;
+  std::vector<double> zf;   // stretched z: the nz + 1 faces (empty: uniform)
 };
 
 struct oc_model {
@@ -37,8 +49,21 @@ struct oc_model {
   double offset[MAXF];  // storage offset per field: stored = value - offset
   void* staging;
   double* diag_part;
-  double dx, dy, dz;
+  double dx, dy, dz;      // dz: lz / nz (the mean thickness on a stretched grid)
   int kind;              // OC_NONHYDROSTATIC or OC_HYDROSTATIC
+  // vertical grid tables (device, in the workspace).  zt64 (FP64): dzc[nz],
+  // dzf[nz+1], rdzc[nz], rdzf[nz+1], the pressure operator's off-diagonals
+  // lo[nz], up[nz].  ztT (state precision): rdzc for k = -1..nz, then rdzf.
+  // vfac: implicit-diffusion factors [stage][u/v, w, tracer][3][nz] (state
+  // precision) for the step size vfac_dt.
+  int stretched;
+  double dzmin;          // thinnest cell
+  std::vector<double> hdzc, hdzf;   // host copies of dzc, dzf
+  double* zt64;
+  void* ztT;
+  void* vfac;
+  double vfac_dt;
+  std::vector<char> vfac_host;
   // hydrostatic model: 2D barotropic state (FP64), ping-pong (eta, U, V)
   double* eta[2];
   double* ubt[2];
@@ -81,9 +106,12 @@ inline TendParams<T> tend_params(const oc_model* m) {
   const oc_model_desc& d = m->md;
   p.rdx = (T)(1.0 / m->dx);
   p.rdy = (T)(1.0 / m->dy);
-  p.rdz = (T)(1.0 / m->dz);
+  p.rdzc = (const T*)m->ztT + 1;
+  p.rdzf = (const T*)m->ztT + (m->dims.nz + 2);
   p.nu = (T)d.nu;
   p.kappa = (T)d.kappa;
+  p.nuz = d.implicit_z ? T(0) : (T)d.nu;
+  p.kappaz = d.implicit_z ? T(0) : (T)d.kappa;
   p.f = (T)d.f;
   p.g_alpha = (T)(d.g * d.alpha);
   p.g_beta = (T)(d.g * d.beta);

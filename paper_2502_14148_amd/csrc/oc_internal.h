@@ -71,8 +71,15 @@ inline long padded_elems(const Dims& d) { return (long)d.px * d.py * d.pz; }
 // Physics and RK3 coefficients handed to the tendency kernel.
 template <class T>
 struct TendParams {
-  T rdx, rdy, rdz;           // inverse spacings
-  T nu, kappa;
+  T rdx, rdy;                // inverse horizontal spacings
+  // inverse vertical spacings (device tables): rdzc[k] = 1/dzc_k, the cell
+  // thickness, valid for k = -1..nz (mirror images at -1 and nz);
+  // rdzf[k] = 1/dzf_k, the distance between the centres about face k,
+  // k = 0..nz.  Uniform grids hold 1/dz everywhere.
+  const T* rdzc;
+  const T* rdzf;
+  T nu, kappa;               // horizontal (and explicit vertical) diffusion
+  T nuz, kappaz;             // explicit vertical diffusion (0 when implicit)
   T f;
   T g_alpha, g_beta, t_ref, s_ref;
   int buoyancy;
@@ -293,7 +300,13 @@ hipError_t launch_halo_fill(const Dims& d, T* const* fields, const int* kinds, i
 template <class T>
 hipError_t launch_tendency_fast(const Dims& d, const FieldSet<T>& fs, const TendParams<T>& p,
                                 int scheme, hipStream_t s);
-struct Spacing { double rdx, rdy, rdz; };
+// Spacings of the pressure passes: rdzc (nz) and rdzf (nz + 1) are device
+// tables of 1/dzc_k and 1/dzf_k as in TendParams.
+struct Spacing {
+  double rdx, rdy;
+  const double* rdzc;
+  const double* rdzf;
+};
 
 // ---- Ensembles: one tendency launch for many models
 // Member descriptor (device table): the state pointers for both buffer
@@ -345,15 +358,34 @@ hipError_t launch_poisson_spectral(const Dims& d, const SpecBufs& sb, hipStream_
 hipError_t launch_poisson_x_inverse(const Dims& d, const SpecBufs& sb, hipStream_t s,
                                     const PoissonSlots* bs = nullptr, int nslots = 1);
 template <class T>
-hipError_t launch_project(const Dims& d, T* u, T* v, T* w, double scale, double rdx,
-                          double rdy, double rdz, const double* p, hipStream_t s,
-                          const PoissonSlots* bs = nullptr, int nslots = 1);
+hipError_t launch_project(const Dims& d, T* u, T* v, T* w, double scale, const Spacing& sp,
+                          const double* p, hipStream_t s, const PoissonSlots* bs = nullptr,
+                          int nslots = 1);
+// Stretched z: the tridiagonal solve along z of every (kx, ky) mode in place
+// of the z transform pass; lo, up (nz) are the off-diagonals of the vertical
+// operator, dzc (nz) the cell thicknesses and dzf (nz + 1) the centre
+// distances about the faces (the horizontally uniform mode is integrated).
+hipError_t launch_poisson_tridiag(const Dims& d, const SpecBufs& sb, const double* lo,
+                                  const double* up, const double* dzc, const double* dzf,
+                                  hipStream_t s);
+// Implicit vertical diffusion of one field in place: fac holds the
+// elimination factors (sub, 1/pivot, sup/pivot: three rows of nunk values)
+// of the columns' common tridiagonal matrix; wface selects w on the interior
+// faces 1..nz-1 (nunk = nz - 1), otherwise the nz centres.
+template <class T>
+hipError_t launch_vertical_implicit(const Dims& d, T* f, int wface, const T* fac, hipStream_t s);
+// Host: elimination factors of 1 - dt L for the vertical diffusion operator
+// L with coefficient K (no flux through the walls for centred fields; w = 0
+// on the walls for wface), written as three rows of nunk values.
+void vertical_factors(const double* dzc, const double* dzf, int nz, double K, double dt,
+                      int wface, double* out);
 template <class T>
 hipError_t launch_pack(const Dims& d, int nzf, int nyf, const T* padded, void* dense, int dtype,
                        int to_dense, double offset, hipStream_t s);
 template <class T>
 hipError_t launch_diagnostics(const Dims& d, T* const* fields, int nf, double rdx, double rdy,
-                              double rdz, double* scratch, int nblocks, hipStream_t s);
+                              const double* rdzc, const double* dzc, double* scratch,
+                              int nblocks, hipStream_t s);
 
 bool fft_length_supported(int n);
 

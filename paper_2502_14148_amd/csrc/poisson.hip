@@ -9,7 +9,8 @@
 //      (two real lines packed into one complex line);
 //   2. y: complex FFT;
 //   3. z: DCT-II (Makhoul's N-point FFT reordering) or FFT, division by the
-//      eigenvalue, and the inverse transform, all in LDS;
+//      eigenvalue, and the inverse transform, all in LDS; on a stretched z a
+//      tridiagonal solve per (kx, ky) mode instead;
 //   4. y: inverse FFT;
 //   5. x: complex-to-real inverse FFT -> p.
 // Then a projection kernel applies u -= dt_eff grad p.
@@ -135,8 +136,8 @@ template <class T, int N>
 __global__ void __launch_bounds__(NT) fwd_x_kernel(Dims d, const T* __restrict__ u,
                                                    const T* __restrict__ v,
                                                    const T* __restrict__ w, double inv_dt,
-                                                   double rdx, double rdy, double rdz,
-                                                   SpecBufs sb,
+                                                   double rdx, double rdy,
+                                                   const double* __restrict__ rdzc, SpecBufs sb,
                                                    const PoissonSlots* __restrict__ bs) {
   if (bs) {
     const int z = blockIdx.z;
@@ -150,6 +151,7 @@ __global__ void __launch_bounds__(NT) fwd_x_kernel(Dims d, const T* __restrict__
   __shared__ double2 tws[N];
   stage_twiddles<N>(tws, sb.twx);
   const int k = blockIdx.y;
+  const double rdz = rdzc[k];
   const int npairs = d.ny / 2;
   const int pair0 = blockIdx.x * LP;
   // compile-time trip counts, so that every load of the tile is in flight
@@ -319,6 +321,121 @@ __global__ void __launch_bounds__(NT) z_kernel(Dims d, SpecBufs sb, double norm,
 }
 
 // ---------------------------------------------------------------------------
+// Pass 3 on a stretched z (the mixed FFT-tridiagonal solver): every (kx, ky)
+// mode solves along z
+//   lo_k p_{k-1} + (lam_x + lam_y - lo_k - up_k) p_k + up_k p_{k+1} = r_k / (nx ny)
+// by parallel cyclic reduction in LDS: PCR_W modes per workgroup, each
+// equation kept normalised to a unit diagonal (a x_{k-s} + x_k + c x_{k+s}
+// = r), log2(nz) elimination rounds.  The systems are strictly diagonally
+// dominant (lam_x + lam_y < 0), so no pivoting is needed.  The horizontally
+// uniform mode is singular (no-flux walls) and is integrated directly: the
+// face gradient obeys g_{k+1} = g_k + dzc_k r_k from g_0 = 0, then p_k =
+// p_{k-1} + dzf_k g_k, and the volume-weighted mean is removed.
+// ---------------------------------------------------------------------------
+constexpr int PCR_W = 8, PCR_NMAX = 256;
+
+__global__ void __launch_bounds__(NT) z_tridiag_kernel(Dims d, SpecBufs sb, double norm,
+                                                       const double* __restrict__ lo,
+                                                       const double* __restrict__ up,
+                                                       const double* __restrict__ dzc,
+                                                       const double* __restrict__ dzf) {
+  __shared__ double sa[PCR_W * PCR_NMAX];
+  __shared__ double sc[PCR_W * PCR_NMAX];
+  __shared__ double2 sr[PCR_W * PCR_NMAX];
+  constexpr int PER = PCR_W * PCR_NMAX / NT;
+  const int nz = d.nz, neq = PCR_W * nz;
+  const int j = blockIdx.y, kx0 = blockIdx.x * PCR_W;
+  const int nxh = sb.nxh, nxp = sb.nxp;
+  const long zs = (long)d.ny * nxp;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int e = threadIdx.x + q * NT;
+    if (e >= neq) break;
+    const int c = e % PCR_W, z = e / PCR_W, kx = kx0 + c;
+    double a = 0.0, cc = 0.0;
+    double2 r = make_double2(0.0, 0.0);
+    if (kx < nxh && (kx | j) != 0) {
+      const double l = lo[z], u = up[z];
+      const double ib = 1.0 / (sb.lamx[kx] + sb.lamy[j] - l - u);
+      a = l * ib;
+      cc = u * ib;
+      r = cscale(sb.spec[z * zs + (long)j * nxp + kx], norm * ib);
+    }
+    sa[e] = a;
+    sc[e] = cc;
+    sr[e] = r;
+  }
+  __syncthreads();
+  for (int st = 1; st < nz; st <<= 1) {
+    double na[PER], nc[PER];
+    double2 nr[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = threadIdx.x + q * NT;
+      if (e >= neq) break;
+      const int z = e / PCR_W;
+      const double a = sa[e], c = sc[e];
+      double am = 0.0, cm = 0.0, ap = 0.0, cp = 0.0;
+      double2 rm = make_double2(0.0, 0.0), rp = make_double2(0.0, 0.0);
+      if (z >= st) {
+        const int m = e - st * PCR_W;
+        am = sa[m];
+        cm = sc[m];
+        rm = sr[m];
+      }
+      if (z + st < nz) {
+        const int m = e + st * PCR_W;
+        ap = sa[m];
+        cp = sc[m];
+        rp = sr[m];
+      }
+      const double ib = 1.0 / (1.0 - a * cm - c * ap);
+      na[q] = -a * am * ib;
+      nc[q] = -c * cp * ib;
+      nr[q] = cscale(csub(csub(sr[e], cscale(rm, a)), cscale(rp, c)), ib);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = threadIdx.x + q * NT;
+      if (e >= neq) break;
+      sa[e] = na[q];
+      sc[e] = nc[q];
+      sr[e] = nr[q];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int e = threadIdx.x + q * NT;
+    if (e >= neq) break;
+    const int c = e % PCR_W, z = e / PCR_W, kx = kx0 + c;
+    if (kx < nxh && (kx | j) != 0) sb.spec[z * zs + (long)j * nxp + kx] = sr[e];
+  }
+  if (blockIdx.x != 0 || j != 0) return;  // uniform within the workgroup
+  // ---- the horizontally uniform mode (kx = 0, ky = 0)
+  __syncthreads();
+  for (int z = threadIdx.x; z < nz; z += NT) sr[z] = sb.spec[z * zs];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double2 g = make_double2(0.0, 0.0), pk = make_double2(0.0, 0.0), acc = make_double2(0.0, 0.0);
+    double vol = 0.0;
+    for (int z = 0; z < nz; ++z) {
+      if (z > 0) pk = cadd(pk, cscale(g, dzf[z]));
+      g = cadd(g, cscale(sr[z], dzc[z] * norm));
+      sr[z] = pk;
+      acc = cadd(acc, cscale(pk, dzc[z]));
+      vol += dzc[z];
+    }
+    sa[0] = acc.x / vol;
+    sa[1] = acc.y / vol;
+  }
+  __syncthreads();
+  const double2 mean = make_double2(sa[0], sa[1]);
+  for (int z = threadIdx.x; z < nz; z += NT) sb.spec[z * zs] = csub(sr[z], mean);
+}
+
+// ---------------------------------------------------------------------------
 // Pass 5: complex-to-real inverse FFT along x for line pairs -> p.
 // ---------------------------------------------------------------------------
 template <int N>
@@ -376,7 +493,8 @@ constexpr int PJ_X = 64, PJ_Y = 4, PJ_KC = 16;
 template <class T>
 __global__ void __launch_bounds__(PJ_X * PJ_Y) project_kernel(
     Dims d, T* __restrict__ u, T* __restrict__ v, T* __restrict__ w, double scale, double rdx,
-    double rdy, double rdz, const double* __restrict__ p, const PoissonSlots* __restrict__ bs) {
+    double rdy, const double* __restrict__ rdzf, const double* __restrict__ p,
+    const PoissonSlots* __restrict__ bs) {
   if (bs) {
     const int z = blockIdx.z;
     u = (T*)bs->u[z];
@@ -431,7 +549,7 @@ __global__ void __launch_bounds__(PJ_X * PJ_Y) project_kernel(
         const T un = (T)((double)uu[q] - scale * (p0[q] - pxm[q]) * rdx);
         const T vn = (T)((double)vv[q] - scale * (p0[q] - pym[q]) * rdy);
         T wn = ww[q];
-        if (!d.zb || k > 0) wn = (T)((double)wn - scale * (p0[q] - pb) * rdz);
+        if (!d.zb || k > 0) wn = (T)((double)wn - scale * (p0[q] - pb) * rdzf[k]);
         pb = p0[q];
         // the final velocities, with their halo images
         store_with_images(u, d, i, j, k, un, false);
@@ -472,7 +590,7 @@ hipError_t launch_poisson_x_forward(const Dims& d, const T* u, const T* v, const
   {                                                                                        \
     dim3 grid((d.ny / 2 + XCfg<N>::LP - 1) / XCfg<N>::LP, d.nz, nslots);                  \
     hipLaunchKernelGGL((fwd_x_kernel<T, N>), grid, dim3(NT), 0, s, d, u, v, w, inv_dt,    \
-                       sp.rdx, sp.rdy, sp.rdz, sb, bs);                                    \
+                       sp.rdx, sp.rdy, sp.rdzc, sb, bs);                                   \
   }
   OC_FFT_DISPATCH(d.nx, OC_LAUNCH_FX)
 #undef OC_LAUNCH_FX
@@ -510,6 +628,16 @@ hipError_t launch_poisson_spectral(const Dims& d, const SpecBufs& sb, hipStream_
   return hipGetLastError();
 }
 
+hipError_t launch_poisson_tridiag(const Dims& d, const SpecBufs& sb, const double* lo,
+                                  const double* up, const double* dzc, const double* dzf,
+                                  hipStream_t s) {
+  if (d.nz > PCR_NMAX || !d.zb) return hipErrorInvalidValue;
+  const double norm = 1.0 / ((double)d.nx * d.ny);
+  dim3 grid((sb.nxh + PCR_W - 1) / PCR_W, d.ny);
+  hipLaunchKernelGGL(z_tridiag_kernel, grid, dim3(NT), 0, s, d, sb, norm, lo, up, dzc, dzf);
+  return hipGetLastError();
+}
+
 hipError_t launch_poisson_x_inverse(const Dims& d, const SpecBufs& sb, hipStream_t s,
                                     const PoissonSlots* bs, int nslots) {
 #define OC_LAUNCH_XI(N)                                                                    \
@@ -523,12 +651,11 @@ hipError_t launch_poisson_x_inverse(const Dims& d, const SpecBufs& sb, hipStream
 }
 
 template <class T>
-hipError_t launch_project(const Dims& d, T* u, T* v, T* w, double scale, double rdx, double rdy,
-                          double rdz, const double* p, hipStream_t s, const PoissonSlots* bs,
-                          int nslots) {
+hipError_t launch_project(const Dims& d, T* u, T* v, T* w, double scale, const Spacing& sp,
+                          const double* p, hipStream_t s, const PoissonSlots* bs, int nslots) {
   const unsigned nb = (unsigned)(((d.nx + PJ_X - 1) / PJ_X) * ((d.ny + PJ_Y - 1) / PJ_Y));
   hipLaunchKernelGGL(project_kernel<T>, dim3(nb, (d.nz + PJ_KC - 1) / PJ_KC, nslots),
-                     dim3(PJ_X * PJ_Y), 0, s, d, u, v, w, scale, rdx, rdy, rdz, p, bs);
+                     dim3(PJ_X * PJ_Y), 0, s, d, u, v, w, scale, sp.rdx, sp.rdy, sp.rdzf, p, bs);
   return hipGetLastError();
 }
 
@@ -540,11 +667,11 @@ template hipError_t launch_poisson_x_forward<double>(const Dims&, const double*,
                                                      const double*, double, Spacing,
                                                      const SpecBufs&, hipStream_t,
                                                      const PoissonSlots*, int);
-template hipError_t launch_project<float>(const Dims&, float*, float*, float*, double, double,
-                                          double, double, const double*, hipStream_t,
+template hipError_t launch_project<float>(const Dims&, float*, float*, float*, double,
+                                          const Spacing&, const double*, hipStream_t,
                                           const PoissonSlots*, int);
-template hipError_t launch_project<double>(const Dims&, double*, double*, double*, double, double,
-                                           double, double, const double*, hipStream_t,
+template hipError_t launch_project<double>(const Dims&, double*, double*, double*, double,
+                                           const Spacing&, const double*, hipStream_t,
                                            const PoissonSlots*, int);
 
 }  // namespace oc

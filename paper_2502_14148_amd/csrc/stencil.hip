@@ -115,7 +115,8 @@ struct DiagArgs {
 
 template <class T>
 __global__ void __launch_bounds__(256) diag_kernel(Dims d, DiagArgs<T> a, double rdx, double rdy,
-                                                   double rdz, double* part) {
+                                                   const double* __restrict__ rdzc,
+                                                   const double* __restrict__ dzc, double* part) {
   __shared__ double red[NPART][256];
   double acc[NPART];
   for (int q = 0; q < NPART; ++q) acc[q] = 0.0;
@@ -132,7 +133,7 @@ __global__ void __launch_bounds__(256) diag_kernel(Dims d, DiagArgs<T> a, double
     if (d.zb) wt = (k + 1 == d.nz) ? 0.0 : (double)a.f[2][c + d.sz];
     else wt = (double)a.f[2][pidx(d, i, j, (k + 1) % d.nz)];
     double div = ((double)a.f[0][pidx(d, ip, j, k)] - uu) * rdx +
-                 ((double)a.f[1][pidx(d, i, jp, k)] - vv) * rdy + (wt - ww) * rdz;
+                 ((double)a.f[1][pidx(d, i, jp, k)] - vv) * rdy + (wt - ww) * rdzc[k];
     acc[0] = fmax(acc[0], fabs(div));
     acc[1] = fmax(acc[1], fabs(uu));
     acc[2] = fmax(acc[2], fabs(vv));
@@ -140,7 +141,7 @@ __global__ void __launch_bounds__(256) diag_kernel(Dims d, DiagArgs<T> a, double
     bool bad = !isfinite(uu) || !isfinite(vv) || !isfinite(ww);
     for (int q = 3; q < a.nf; ++q) {
       double x = (double)a.f[q][c];
-      acc[1 + q] += x;
+      acc[1 + q] += x * dzc[k];  // layer thickness weight
       bad = bad || !isfinite(x);
     }
     if (bad) acc[8] += 1.0;
@@ -161,11 +162,13 @@ __global__ void __launch_bounds__(256) diag_kernel(Dims d, DiagArgs<T> a, double
 
 template <class T>
 hipError_t launch_diagnostics(const Dims& d, T* const* fields, int nf, double rdx, double rdy,
-                              double rdz, double* scratch, int nblocks, hipStream_t s) {
+                              const double* rdzc, const double* dzc, double* scratch,
+                              int nblocks, hipStream_t s) {
   DiagArgs<T> a;
   for (int q = 0; q < nf; ++q) a.f[q] = fields[q];
   a.nf = nf;
-  hipLaunchKernelGGL(diag_kernel<T>, dim3(nblocks), dim3(256), 0, s, d, a, rdx, rdy, rdz, scratch);
+  hipLaunchKernelGGL(diag_kernel<T>, dim3(nblocks), dim3(256), 0, s, d, a, rdx, rdy, rdzc, dzc,
+                     scratch);
   return hipGetLastError();
 }
 
@@ -176,8 +179,10 @@ template hipError_t launch_pack<float>(const Dims&, int, int, const float*, void
 template hipError_t launch_pack<double>(const Dims&, int, int, const double*, void*, int, int,
                                         double, hipStream_t);
 template hipError_t launch_diagnostics<float>(const Dims&, float* const*, int, double, double,
-                                              double, double*, int, hipStream_t);
+                                              const double*, const double*, double*, int,
+                                              hipStream_t);
 template hipError_t launch_diagnostics<double>(const Dims&, double* const*, int, double, double,
-                                               double, double*, int, hipStream_t);
+                                               const double*, const double*, double*, int,
+                                               hipStream_t);
 
 }  // namespace oc

@@ -7,6 +7,13 @@
 // averages); buoyancy b = g(alpha(T-T0) - beta(S-S0)) averaged to w faces;
 // RK3 substage X~ = X + dt(gamma G^m - zeta G^{m-1}) (rk3 equation).
 //
+// Vertically stretched grids: z flux differences are divided by the
+// thickness of the control volume (cell k, or the w cell about face k) and
+// vertical diffusive fluxes by the distance between the differenced values,
+// from per-level tables read once per level; reconstructions and the
+// advecting-velocity interpolation keep their index-space coefficients.
+// Implicit vertical diffusion zeroes the explicit vertical coefficients.
+//
 // Schedule: a workgroup owns a TX x TY column tile and marches up a chunk of
 // k levels.  Every face flux is computed exactly once:
 //   * z fluxes per column from a 7-level register window (the flux through
@@ -206,16 +213,17 @@ __device__ __attribute__((always_inline)) inline void tendency_tile(
     z[0] = (gu + lv)[col];
 #pragma unroll
     for (int o = 1; o < 6; ++o) z[o] = wu[o - 1];
-    fzb_u = wall ? T(0) : flux_reg<T, SCHEME>(z, wt_u, eps) - P.nu * (z[3] - z[2]) * P.rdz;
+    const T rzb = P.rdzf[kb];  // face kb
+    fzb_u = wall ? T(0) : flux_reg<T, SCHEME>(z, wt_u, eps) - P.nuz * (z[3] - z[2]) * rzb;
     z[0] = (gv + lv)[col];
 #pragma unroll
     for (int o = 1; o < 6; ++o) z[o] = wv[o - 1];
-    fzb_v = wall ? T(0) : flux_reg<T, SCHEME>(z, wt_v, eps) - P.nu * (z[3] - z[2]) * P.rdz;
+    fzb_v = wall ? T(0) : flux_reg<T, SCHEME>(z, wt_v, eps) - P.nuz * (z[3] - z[2]) * rzb;
     z[0] = (gw + lv)[col];
 #pragma unroll
     for (int o = 1; o < 6; ++o) z[o] = ww[o - 1];
     const T wb = interp4(z[1], z[2], z[3], z[4]);
-    fzb_w = flux_reg<T, SCHEME>(z, wb, eps) - P.nu * (z[3] - z[2]) * P.rdz;
+    fzb_w = flux_reg<T, SCHEME>(z, wb, eps) - P.nuz * (z[3] - z[2]) * P.rdzc[kb - 1];
     const T wface = z[3];
 #pragma unroll
     for (int q = 0; q < NTR; ++q) {
@@ -223,7 +231,7 @@ __device__ __attribute__((always_inline)) inline void tendency_tile(
 #pragma unroll
       for (int o = 1; o < 6; ++o) z[o] = wc[q][o - 1];
       fzb_c[q] = wall ? T(0)
-                      : flux_reg<T, SCHEME>(z, wface, eps) - P.kappa * (z[3] - z[2]) * P.rdz;
+                      : flux_reg<T, SCHEME>(z, wface, eps) - P.kappaz * (z[3] - z[2]) * rzb;
     }
   }
 
@@ -272,20 +280,23 @@ __device__ __attribute__((always_inline)) inline void tendency_tile(
 
     // ---- z fluxes through the top face of level k (w: at centre k)
     const bool top_wall = d.zb && (k + 1 == d.nz);
+    // inverse spacings of this level (uniform across the workgroup): the top
+    // face k+1, the cell k, and face k (the thickness of the w cell)
+    const T rzft = P.rdzf[k + 1], rzc = P.rdzc[k], rzf = P.rdzf[k];
     T fzt_u, fzt_v, fzt_w, fzt_c[NTR];
     {
       const T* wp = S + rw(k + 1);
       const T wt_u = interp4(wp[Lc - 2], wp[Lc - 1], wp[Lc], wp[Lc + 1]);
       const T wt_v = interp4(wp[Lc - 2 * PX], wp[Lc - PX], wp[Lc], wp[Lc + PX]);
-      fzt_u = top_wall ? T(0) : flux_reg<T, SCHEME>(wu, wt_u, eps) - P.nu * (wu[3] - wu[2]) * P.rdz;
-      fzt_v = top_wall ? T(0) : flux_reg<T, SCHEME>(wv, wt_v, eps) - P.nu * (wv[3] - wv[2]) * P.rdz;
+      fzt_u = top_wall ? T(0) : flux_reg<T, SCHEME>(wu, wt_u, eps) - P.nuz * (wu[3] - wu[2]) * rzft;
+      fzt_v = top_wall ? T(0) : flux_reg<T, SCHEME>(wv, wt_v, eps) - P.nuz * (wv[3] - wv[2]) * rzft;
       const T wb = interp4(ww[1], ww[2], ww[3], ww[4]);
-      fzt_w = flux_reg<T, SCHEME>(ww, wb, eps) - P.nu * (ww[3] - ww[2]) * P.rdz;
+      fzt_w = flux_reg<T, SCHEME>(ww, wb, eps) - P.nuz * (ww[3] - ww[2]) * rzc;
 #pragma unroll
       for (int q = 0; q < NTR; ++q)
         fzt_c[q] = top_wall ? P.top_flux[q]
                             : flux_reg<T, SCHEME>(wc[q], ww[3], eps) -
-                                  P.kappa * (wc[q][3] - wc[q][2]) * P.rdz;
+                                  P.kappaz * (wc[q][3] - wc[q][2]) * rzft;
     }
     __syncthreads();  // all x/y fluxes of level k are in LDS
 
@@ -300,11 +311,11 @@ __device__ __attribute__((always_inline)) inline void tendency_tile(
                (S[OFY + f * NYS + iy + TX] - S[OFY + f * NYS + iy]) * P.rdy;
       const T* uk = S + ru(k);
       const T* vk = S + rv(k);
-      G[0] += -(fzt_u - fzb_u) * P.rdz +
+      G[0] += -(fzt_u - fzb_u) * rzc +
               P.f * T(0.25) * (vk[Lc - 1] + vk[Lc] + vk[Lc - 1 + PX] + vk[Lc + PX]);
-      G[1] += -(fzt_v - fzb_v) * P.rdz -
+      G[1] += -(fzt_v - fzb_v) * rzc -
               P.f * T(0.25) * (uk[Lc - PX] + uk[Lc + 1 - PX] + uk[Lc] + uk[Lc + 1]);
-      G[2] += -(fzt_w - fzb_w) * P.rdz;
+      G[2] += -(fzt_w - fzb_w) * rzf;
       if (NTR >= 2 && P.buoyancy) {
         const T bl = P.g_alpha * (wc[0][1] - P.t_ref) - P.g_beta * (wc[1][1] - P.s_ref);
         const T bu = P.g_alpha * (wc[0][2] - P.t_ref) - P.g_beta * (wc[1][2] - P.s_ref);
@@ -313,9 +324,9 @@ __device__ __attribute__((always_inline)) inline void tendency_tile(
       const bool bottom_wall = d.zb && k == 0;
       if (bottom_wall) G[2] = T(0);
       const T divu = (uk[Lc + 1] - uk[Lc]) * P.rdx + (vk[Lc + PX] - vk[Lc]) * P.rdy +
-                     (ww[3] - ww[2]) * P.rdz;
+                     (ww[3] - ww[2]) * rzc;
 #pragma unroll
-      for (int q = 0; q < NTR; ++q) G[3 + q] += -(fzt_c[q] - fzb_c[q]) * P.rdz - P.toff[q] * divu;
+      for (int q = 0; q < NTR; ++q) G[3 + q] += -(fzt_c[q] - fzb_c[q]) * rzc - P.toff[q] * divu;
       if (fs.closure[0]) {
         // learned subgrid closure: precomputed flux divergences
         const long o = (long)(k + H) * sz + col;

@@ -35,14 +35,15 @@ EXPORTS = ("oc_last_error", "oc_grid_create", "oc_grid_destroy", "oc_model_works
            "oc_mlp_gradients", "oc_mlp_train_step", "oc_model_set_closure",
            "oc_ensemble_workspace_size", "oc_ensemble_create", "oc_ensemble_step",
            "oc_ensemble_tuning", "oc_ensemble_destroy", "oc_closure_features",
-           "oc_coarse_grain")
+           "oc_coarse_grain", "oc_implicit_vertical_diffusion")
 OC_ENS_TUNE, OC_ENS_GRAPH = 1, 2
 OC_MLP_NPARAM = 195076
 MLP_SHAPES = (("W1", (256, 500)), ("b1", (256,)), ("W2", (256, 256)), ("b2", (256,)),
               ("W3", (4, 256)), ("b3", (4,)))
-OC_NPROF = 12
+OC_NPROF = 13
 PROF_CLASSES = ("tendency", "fft_x_fwd", "fft_y_fwd", "z_solve", "fft_y_inv", "fft_x_inv",
-                "project", "halo", "closure", "hydro_diag", "hydro_tendency", "barotropic")
+                "project", "halo", "closure", "hydro_diag", "hydro_tendency", "barotropic",
+                "implicit_z")
 
 
 class GridDesc(ctypes.Structure):
@@ -51,7 +52,8 @@ class GridDesc(ctypes.Structure):
                 ("x0", ctypes.c_double), ("lx", ctypes.c_double),
                 ("y0", ctypes.c_double), ("ly", ctypes.c_double),
                 ("z0", ctypes.c_double), ("lz", ctypes.c_double),
-                ("coord", ctypes.c_int32), ("radius", ctypes.c_double)]
+                ("coord", ctypes.c_int32), ("radius", ctypes.c_double),
+                ("z_faces", ctypes.POINTER(ctypes.c_double))]
 
 
 class ModelDesc(ctypes.Structure):
@@ -64,7 +66,7 @@ class ModelDesc(ctypes.Structure):
                 ("nu", ctypes.c_double), ("kappa", ctypes.c_double),
                 ("top_flux", ctypes.c_double * OC_MAX_TRACERS),
                 ("depth", ctypes.c_double), ("omega", ctypes.c_double),
-                ("closure", ctypes.c_int32)]
+                ("closure", ctypes.c_int32), ("implicit_z", ctypes.c_int32)]
 
 
 class OcError(RuntimeError):
@@ -121,6 +123,7 @@ def load_library(path=_LIB_PATH):
         "oc_ensemble_destroy": [vp],
         "oc_closure_features": [vp, ctypes.POINTER(ctypes.c_double), vp, vp],
         "oc_coarse_grain": [vp, vp, vp, vp],
+        "oc_implicit_vertical_diffusion": [vp, ctypes.c_double, vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -163,8 +166,14 @@ class Model:
         else:
             gd = GridDesc(ph.nx, ph.ny, ph.nz, OC_BOUNDED if ph.z_bounded else OC_PERIODIC,
                           ph.x0, ph.lx, ph.y0, ph.ly, ph.z0, ph.lz, OC_RECTILINEAR, 0.0)
+            zf = getattr(ph, "z_faces", None)
+            if zf is not None:
+                # copied by oc_grid_create
+                self._zf = (ctypes.c_double * len(zf))(*[float(z) for z in zf])
+                gd.z_faces = ctypes.cast(self._zf, ctypes.POINTER(ctypes.c_double))
             md.kind = OC_NONHYDROSTATIC
             md.f = ph.f
+            md.implicit_z = 1 if getattr(ph, "implicit_z", False) else 0
         md.precision = OC_FP64 if precision == "fp64" else OC_FP32_MIXED
         md.advection = ADVECTION[ph.advection]
         md.weno_eps = ph.weno_eps
@@ -275,6 +284,9 @@ class Model:
 
     def rk3_step(self, dt, nsteps=1):
         _check(_lib.oc_rk3_step(self._model, ctypes.c_double(dt), ctypes.c_int32(nsteps), _stream()))
+
+    def implicit_vertical_diffusion(self, dt_eff):
+        _check(_lib.oc_implicit_vertical_diffusion(self._model, ctypes.c_double(dt_eff), _stream()))
 
     def diagnostics(self):
         out = (ctypes.c_double * OC_NDIAG)()

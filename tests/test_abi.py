@@ -104,3 +104,51 @@ def test_ensemble_and_hydrostatic_step_argument_checks():
     assert lib.oc_ensemble_destroy(None) == 0
     w = (ctypes.c_double * 1)(1.0)
     assert lib.oc_hydrostatic_step(None, ctypes.c_double(600.0), 30, 1, w, 1, None) == -1
+
+
+def _faces(vals):
+    arr = (ctypes.c_double * len(vals))(*vals)
+    return arr, ctypes.cast(arr, ctypes.POINTER(ctypes.c_double))
+
+
+def test_stretched_grid_validation():
+    """z faces: strictly increasing, from z0 to z0 + lz, bounded z, 4..256
+    levels (any count: the tridiagonal solve replaces the z transform);
+    implicit vertical diffusion needs walls; the learned closure a uniform z."""
+    from paper_2502_14148_amd import inputs
+    lib = oc.load_library()
+    g = ctypes.c_void_p()
+    zf = inputs.stretched_faces(50, 100.0, -100.0, 1.5)
+    keep, ptr = _faces(zf)
+    gd = oc.GridDesc(32, 32, 50, oc.OC_BOUNDED, 0, 64, 0, 64, -100, 100, oc.OC_RECTILINEAR, 0.0)
+    gd.z_faces = ptr
+    assert lib.oc_grid_create(ctypes.byref(gd), ctypes.byref(g)) == 0
+    md = oc.ModelDesc()
+    md.precision, md.advection, md.weno_eps, md.weno_q = oc.OC_FP32_MIXED, 1, 1e-15, 2
+    md.ntracers, md.buoyancy, md.implicit_z = 2, 1, 1
+    nbytes = ctypes.c_uint64()
+    assert lib.oc_model_workspace_size(g, ctypes.byref(md), ctypes.byref(nbytes)) == 0
+    md.closure = 1
+    assert lib.oc_model_workspace_size(g, ctypes.byref(md), ctypes.byref(nbytes)) == -5
+    md.closure, md.implicit_z = 0, 2
+    assert lib.oc_model_workspace_size(g, ctypes.byref(md), ctypes.byref(nbytes)) == -1
+    assert lib.oc_grid_destroy(g) == 0
+    # faces out of order, not spanning the domain, periodic z, too many levels
+    bad = list(zf)
+    bad[10], bad[11] = bad[11], bad[10]
+    keep, gd.z_faces = _faces(bad)
+    assert lib.oc_grid_create(ctypes.byref(gd), ctypes.byref(g)) == -1
+    keep, gd.z_faces = _faces([z + 1.0 for z in zf])
+    assert lib.oc_grid_create(ctypes.byref(gd), ctypes.byref(g)) == -1
+    keep, gd.z_faces = _faces(zf)
+    gd.topology_z = oc.OC_PERIODIC
+    assert lib.oc_grid_create(ctypes.byref(gd), ctypes.byref(g)) == -5
+    gd.topology_z, gd.nz = oc.OC_BOUNDED, 300
+    keep, gd.z_faces = _faces(inputs.stretched_faces(300, 100.0, -100.0))
+    assert lib.oc_grid_create(ctypes.byref(gd), ctypes.byref(g)) == -5
+    # implicit vertical diffusion with a periodic z
+    gd = oc.GridDesc(32, 32, 32, oc.OC_PERIODIC, 0, 1, 0, 1, 0, 1, oc.OC_RECTILINEAR, 0.0)
+    assert lib.oc_grid_create(ctypes.byref(gd), ctypes.byref(g)) == 0
+    md.implicit_z, md.buoyancy = 1, 0
+    assert lib.oc_model_workspace_size(g, ctypes.byref(md), ctypes.byref(nbytes)) == -5
+    assert lib.oc_grid_destroy(g) == 0
