@@ -220,6 +220,44 @@ def run_ensemble(steps, warmup):
             "tuning": tn}
 
 
+# Algorithmic HBM bytes per cell of the stretched-grid kernels (FP32 state):
+#   z_solve (tridiagonal, FP64 half spectrum): read and write it, 16 B;
+#   implicit_z: read and write the 5 fields once, 40 B per substage.
+STRETCHED_BYTES_PER_CELL = {"z_solve": 16, "implicit_z": 40}
+
+
+def run_stretched(steps, warmup, n):
+    """The 256^3 free-convection step on a surface-refined grid (tanh faces,
+    top cell 5.5x thinner than the bottom one) with vertically implicit
+    diffusion: FFT-tridiagonal pressure solve and one implicit solve of every
+    field per substage (FP32 state, FP64 Poisson)."""
+    from paper_2502_14148_amd import inputs
+    ph = inputs.stretched_convection_physics((n, n, n), (2.0 * n, 2.0 * n, 1.0 * n), sigma=1.5,
+                                             implicit_z=True)
+    print(f"# generating the stretched {n}^3 initial state", file=sys.stderr, flush=True)
+    s = inputs.convection_initial(ph, seed=0)
+    ms, _, prof, diag = run_gpu(ph, s, "fp32", steps, warmup)
+    del s
+    ncells = n ** 3
+    kern = {}
+    for k, b in STRETCHED_BYTES_PER_CELL.items():
+        t, c = prof[k]
+        if c:
+            gbs = b * ncells / (t / 1e3 / c) / 1e9
+            kern[k] = {"avg_launch_us": round(t / c * 1e3, 1), "achieved_gbs": round(gbs, 1),
+                       "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_cell": b}
+    zf = np.asarray(ph.z_faces)
+    return {"value": ncells * steps / (ms / 1e3), "unit": "cell-steps/s", "steps": steps,
+            "warmup": warmup, "ms_per_step": ms / steps, "dtype": "f32",
+            "config": {"workload": f"free-convection LES {n}^3 on a surface-refined z grid "
+                                   f"(tanh, sigma 1.5), implicit vertical diffusion, "
+                                   f"FFT-tridiagonal pressure solve",
+                       "dz_top_m": float(zf[-1] - zf[-2]), "dz_bottom_m": float(zf[1] - zf[0]),
+                       "dt_s": 1.0},
+            "kernels_ms_per_step": {k: v[0] / steps for k, v in prof.items() if v[1]},
+            "hbm": kern, "final_max_w": diag["max_w"]}
+
+
 MLP_FLOPS_PER_ROW = 2 * (500 * 256 + 256 * 256 + 256 * 4)   # forward, one cell
 BF16_PEAK_TFLOPS = 2500.0      # MI355X dense BF16 MFMA
 
@@ -370,6 +408,7 @@ def main():
     ap.add_argument("--no-hydrostatic", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-closure", action="store_true")
+    ap.add_argument("--no-stretched", action="store_true")
     ap.add_argument("--no-main", action="store_true",
                     help="skip the 256^3 step (profiling the other legs alone)")
     ap.add_argument("--ensemble-steps", type=int, default=20)
@@ -398,6 +437,9 @@ def main():
     if not a.no_hydrostatic:
         print("# hydrostatic sector run", file=sys.stderr, flush=True)
         out["hydrostatic"] = run_hydrostatic(a.hydro_steps, 2)
+    if not a.no_stretched:
+        print("# stretched-grid run", file=sys.stderr, flush=True)
+        out["stretched"] = run_stretched(a.steps, a.warmup, a.n)
     if not a.no_closure:
         print("# closure network", file=sys.stderr, flush=True)
         out["closure_mlp"] = run_closure_mlp()

@@ -395,12 +395,13 @@ int implicit_factors(oc_model* m, double dt, int stage, hipStream_t s) {
   const int nz = m->dims.nz;
   std::vector<double> f64(vfac_len(nz), 0.0);
   const int nstage = stage < 0 ? 1 : 3;
+  const int L = vertical_factors_len(nz);
   for (int st = 0; st < nstage; ++st) {
     const double dte = stage < 0 ? dt : (RK_GAMMA[st] - RK_ZETA[st]) * dt;
-    double* base = f64.data() + (size_t)st * 9 * nz;
+    double* base = f64.data() + (size_t)st * 3 * L;
     vertical_factors(m->hdzc.data(), m->hdzf.data(), nz, m->md.nu, dte, 0, base);
-    vertical_factors(m->hdzc.data(), m->hdzf.data(), nz, m->md.nu, dte, 1, base + 3 * nz);
-    vertical_factors(m->hdzc.data(), m->hdzf.data(), nz, m->md.kappa, dte, 0, base + 6 * nz);
+    vertical_factors(m->hdzc.data(), m->hdzf.data(), nz, m->md.nu, dte, 1, base + L);
+    vertical_factors(m->hdzc.data(), m->hdzf.data(), nz, m->md.kappa, dte, 0, base + 2 * L);
   }
   m->vfac_host.resize(f64.size() * m->esz);
   for (size_t q = 0; q < f64.size(); ++q) {
@@ -419,13 +420,16 @@ int implicit_factors(oc_model* m, double dt, int stage, hipStream_t s) {
 template <class T>
 int implicit_call(oc_model* m, int which, int st, hipStream_t s) {
   ProfScope ps(m, OC_PROF_IMPLICIT_Z, s);
-  const int nz = m->dims.nz;
-  const T* base = (const T*)m->vfac + (size_t)st * 9 * nz;
+  const int L = vertical_factors_len(m->dims.nz);
+  const T* base = (const T*)m->vfac + (size_t)st * 3 * L;
+  VImplicitArgs<T> a;
   for (int q = 0; q < m->nf; ++q) {
-    const int cls = (q < 2) ? 0 : (q == 2 ? 1 : 2);
-    OC_CHECK_HIP(launch_vertical_implicit<T>(m->dims, (T*)m->state[which][q], q == 2 ? 1 : 0,
-                                             base + 3 * nz * cls, s));
+    const int cls = (q < 2) ? 0 : (q == 2 ? 1 : 2);  // u, v | w | tracers
+    a.f[q] = (T*)m->state[which][q];
+    a.fac[q] = base + (size_t)L * cls;
+    a.wface[q] = (q == 2) ? 1 : 0;
   }
+  OC_CHECK_HIP(launch_vertical_implicit<T>(m->dims, a, m->nf, s));
   return OC_OK;
 }
 

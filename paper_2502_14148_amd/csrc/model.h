@@ -22,7 +22,7 @@ inline int zt_lo(int nz)     { return 4 * nz + 2; }
 inline int zt_up(int nz)     { return 5 * nz + 2; }
 inline int zt64_len(int nz)  { return 6 * nz + 2; }
 inline int ztT_len(int nz)   { return 2 * nz + 3; }
-inline int vfac_len(int nz)  { return 27 * nz; }
+inline int vfac_len(int nz)  { return 9 * vertical_factors_len(nz); }
 
 }  // namespace oc
 
@@ -54,8 +54,8 @@ struct oc_model {
   // vertical grid tables (device, in the workspace).  zt64 (FP64): dzc[nz],
   // dzf[nz+1], rdzc[nz], rdzf[nz+1], the pressure operator's off-diagonals
   // lo[nz], up[nz].  ztT (state precision): rdzc for k = -1..nz, then rdzf.
-  // vfac: implicit-diffusion factors [stage][u/v, w, tracer][3][nz] (state
-  // precision) for the step size vfac_dt.
+  // vfac: implicit-diffusion tables [stage][u/v, w, tracer] of
+  // vertical_factors_len(nz) values (state precision) for the step vfac_dt.
   int stretched;
   double dzmin;          // thinnest cell
   std::vector<double> hdzc, hdzf;   // host copies of dzc, dzf

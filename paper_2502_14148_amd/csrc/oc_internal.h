@@ -368,17 +368,27 @@ hipError_t launch_project(const Dims& d, T* u, T* v, T* w, double scale, const S
 hipError_t launch_poisson_tridiag(const Dims& d, const SpecBufs& sb, const double* lo,
                                   const double* up, const double* dzc, const double* dzf,
                                   hipStream_t s);
-// Implicit vertical diffusion of one field in place: fac holds the
-// elimination factors (sub, 1/pivot, sup/pivot: three rows of nunk values)
-// of the columns' common tridiagonal matrix; wface selects w on the interior
-// faces 1..nz-1 (nunk = nz - 1), otherwise the nz centres.
+// Implicit vertical diffusion of several fields in place (one launch, field
+// = blockIdx.y): fac[q] holds the recurrence tables of vertical_factors for
+// field q's matrix; wface[q] selects w on the interior faces 1..nz-1,
+// otherwise the nz centres.  Needs bounded z and nz <= 256.
 template <class T>
-hipError_t launch_vertical_implicit(const Dims& d, T* f, int wface, const T* fac, hipStream_t s);
-// Host: elimination factors of 1 - dt L for the vertical diffusion operator
-// L with coefficient K (no flux through the walls for centred fields; w = 0
-// on the walls for wface), written as three rows of nunk values.
+struct VImplicitArgs {
+  T* f[MAXF];
+  const T* fac[MAXF];
+  int wface[MAXF];
+};
+template <class T>
+hipError_t launch_vertical_implicit(const Dims& d, const VImplicitArgs<T>& a, int nfields,
+                                    hipStream_t s);
+// Host: the tables of the implicit solve of 1 - dt L for the vertical
+// diffusion operator L with coefficient K (no flux through the walls for
+// centred fields; w = 0 on the walls for wface): A, I, P, B, Q rows of n
+// values (n = nz, or nz - 1 for wface) and the per-chunk products PE, QS;
+// vertical_factors_len(nz) values in all.
 void vertical_factors(const double* dzc, const double* dzf, int nz, double K, double dt,
                       int wface, double* out);
+int vertical_factors_len(int nz);
 template <class T>
 hipError_t launch_pack(const Dims& d, int nzf, int nyf, const T* padded, void* dense, int dtype,
                        int to_dense, double offset, hipStream_t s);

@@ -324,10 +324,11 @@ __global__ void __launch_bounds__(NT) z_kernel(Dims d, SpecBufs sb, double norm,
 // Pass 3 on a stretched z (the mixed FFT-tridiagonal solver): every (kx, ky)
 // mode solves along z
 //   lo_k p_{k-1} + (lam_x + lam_y - lo_k - up_k) p_k + up_k p_{k+1} = r_k / (nx ny)
-// by parallel cyclic reduction in LDS: PCR_W modes per workgroup, each
-// equation kept normalised to a unit diagonal (a x_{k-s} + x_k + c x_{k+s}
-// = r), log2(nz) elimination rounds.  The systems are strictly diagonally
-// dominant (lam_x + lam_y < 0), so no pivoting is needed.  The horizontally
+// in LDS, PCR_W modes per workgroup, each equation kept normalised to a unit
+// diagonal (a x_{k-s} + x_k + c x_{k+s} = r): parallel cyclic reduction
+// rounds until every mode has split into S interleaved systems of about 8
+// equations, then one Thomas elimination per system and thread.  The systems
+// are strictly diagonally dominant (lam_x + lam_y < 0): no pivoting.  The horizontally
 // uniform mode is singular (no-flux walls) and is integrated directly: the
 // face gradient obeys g_{k+1} = g_k + dzc_k r_k from g_0 = 0, then p_k =
 // p_{k-1} + dzf_k g_k, and the volume-weighted mean is removed.
@@ -366,7 +367,11 @@ __global__ void __launch_bounds__(NT) z_tridiag_kernel(Dims d, SpecBufs sb, doub
     sr[e] = r;
   }
   __syncthreads();
-  for (int st = 1; st < nz; st <<= 1) {
+  // reduction rounds until the stride S splits every mode into S interleaved
+  // systems of at most nz / S equations (about 8; S * PCR_W <= NT threads)
+  int S = 1;
+  while (S * 8 < nz && S * PCR_W * 2 <= NT) S <<= 1;
+  for (int st = 1; st < S; st <<= 1) {
     double na[PER], nc[PER];
     double2 nr[PER];
 #pragma unroll
@@ -405,6 +410,31 @@ __global__ void __launch_bounds__(NT) z_tridiag_kernel(Dims d, SpecBufs sb, doub
     }
     __syncthreads();
   }
+  // Thomas elimination of each interleaved system (equations z = res,
+  // res + S, ... of mode c), one thread per system, in place in LDS
+  if ((int)threadIdx.x < PCR_W * S) {
+    const int c = threadIdx.x % PCR_W, res = threadIdx.x / PCR_W;
+    double cp = 0.0;
+    double2 rp = make_double2(0.0, 0.0);
+    int zl = res;
+    for (int z = res; z < nz; z += S) {
+      const int e = z * PCR_W + c;
+      const double a = sa[e];
+      const double ib = 1.0 / (1.0 - a * cp);
+      cp = sc[e] * ib;
+      rp = cscale(csub(sr[e], cscale(rp, a)), ib);
+      sc[e] = cp;
+      sr[e] = rp;
+      zl = z;
+    }
+    double2 xz = make_double2(0.0, 0.0);
+    for (int z = zl; z >= 0; z -= S) {
+      const int e = z * PCR_W + c;
+      xz = csub(sr[e], cscale(xz, sc[e]));
+      sr[e] = xz;
+    }
+  }
+  __syncthreads();
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int e = threadIdx.x + q * NT;

@@ -1,5 +1,6 @@
-"""Full-size checks in the configuration the benchmark times: the 256^3
-free-convection LES (512 x 512 x 256 m, walls in z).
+"""Full-size checks in the configurations the benchmark times: the 256^3
+free-convection LES (512 x 512 x 256 m, walls in z), on the uniform grid and
+on the surface-refined grid with implicit vertical diffusion.
 
 * Tendencies on sampled windows: the tendency of a cell depends on its
   neighbours within three cells, so the oracle evaluated on a 24 x 24 column
@@ -33,8 +34,10 @@ def rel_l2(a, b):
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
 
 
-@pytest.fixture(scope="module")
-def physics():
+def _physics(kind):
+    if kind == "stretched":
+        return inputs.stretched_convection_physics((N, N, N), (2.0 * N, 2.0 * N, 1.0 * N),
+                                                   sigma=1.5, implicit_z=True)
     return inputs.convection_physics((N, N, N), (2.0 * N, 2.0 * N, 1.0 * N))
 
 
@@ -45,9 +48,10 @@ def _window_tendencies(s, ph, i0, j0):
     return td.tendencies(timestep.make_state(st, sub), sub)
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_full_size_tendency_windows(gpu_lib, physics, precision):
-    ph = physics
+@pytest.mark.parametrize("kind,precision", [("uniform", "fp64"), ("uniform", "fp32"),
+                                            ("stretched", "fp32")])
+def test_full_size_tendency_windows(gpu_lib, kind, precision):
+    ph = _physics(kind)
     s = inputs.convection_initial(ph, seed=0, tracer_noise=0.1)
     if precision == "fp32":
         s = {k: v.astype(np.float32).astype(np.float64) for k, v in s.items()}
@@ -65,9 +69,11 @@ def test_full_size_tendency_windows(gpu_lib, physics, precision):
             assert err <= tol, (precision, name, i0, j0, err)
 
 
-def test_full_size_step_divergence_and_heat_budget(gpu_lib, physics):
-    """On the benchmark's own initial state."""
-    ph = physics
+@pytest.mark.parametrize("kind", ["uniform", "stretched"])
+def test_full_size_step_divergence_and_heat_budget(gpu_lib, kind):
+    """On the benchmark's own initial state (the stretched grid with implicit
+    vertical diffusion: the tridiagonal pressure solve)."""
+    ph = _physics(kind)
     s = inputs.convection_initial(ph, seed=0)
     m = gpu_lib.Model(ph, "fp64")
     m.set_states(s)
