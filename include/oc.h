@@ -58,6 +58,7 @@ enum { OC_NONHYDROSTATIC = 0, OC_HYDROSTATIC = 1 };
 enum { OC_FP64 = 0, OC_FP32_MIXED = 1 };
 enum { OC_ADV_NONE = 0, OC_ADV_WENO5Z = 1, OC_ADV_WENO5_LINEAR = 2 };
 enum { OC_F32 = 0, OC_F64 = 1 };
+enum { OC_LES_NONE = 0, OC_LES_SMAGORINSKY = 1, OC_LES_AMD = 2 };
 /* Field identifiers: velocities, then tracers 0..ntracers-1; the
  * hydrostatic model adds its 2D barotropic fields (FP64): free surface eta
  * at cell centres (shape (1, ny, nx)), transports U at x faces (1, ny, nx)
@@ -132,6 +133,26 @@ typedef struct {
                                (1 - dt_eff d/dz K d/dz) X = X~ column by
                                column, dt_eff = (gamma_m - zeta_m) dt, before
                                the pressure correction */
+  int32_t les;              /* OC_NONHYDROSTATIC: an eddy-viscosity LES closure
+                               added to the constant nu, kappa (closure
+                               paragraph of the nonhydrostatic model section):
+                               OC_LES_SMAGORINSKY, nu_e = (C Delta)^2 |S|
+                               sqrt(max(0, 1 - C_b N^2/|S|^2)), |S|^2 =
+                               2 S_ij S_ij, Delta = (dx dy dz_c)^(1/3),
+                               kappa_e = nu_e / Pr; or OC_LES_AMD (anisotropic
+                               minimum dissipation), nu_e = max(0, -C sum_k
+                               Delta_k^2 d_k u_i d_k u_j S_ij / |grad u|^2) and
+                               per tracer kappa_e = max(0, -C sum_k Delta_k^2
+                               d_k u_i d_k c d_i c / |grad c|^2).  The closure
+                               adds d_j(2 nu_e S_ij) to G_u_i and
+                               d_i(kappa_e d_i c) to G_c (stresses on the C-grid
+                               edges, viscosities averaged from the centres; no
+                               flux through walls).  Not with closure = 1. */
+  double les_c;             /* C (C_s for Smagorinsky-Lilly, e.g. 0.16; the
+                               AMD constant, e.g. 1/12); > 0 */
+  double les_cb;            /* Smagorinsky-Lilly: C_b of the stratification
+                               factor (>= 0; N^2 from the T, S buoyancy) */
+  double les_pr;            /* Smagorinsky-Lilly: turbulent Prandtl number (> 0) */
 } oc_model_desc;
 
 typedef struct oc_grid oc_grid;
@@ -213,9 +234,9 @@ enum {
   OC_PROF_TENDENCY = 0, OC_PROF_FFT_X_FWD = 1, OC_PROF_FFT_Y_FWD = 2, OC_PROF_Z_SOLVE = 3,
   OC_PROF_FFT_Y_INV = 4, OC_PROF_FFT_X_INV = 5, OC_PROF_PROJECT = 6, OC_PROF_HALO = 7,
   OC_PROF_CLOSURE = 8, OC_PROF_HYDRO_DIAG = 9, OC_PROF_HYDRO_TEND = 10, OC_PROF_BAROTROPIC = 11,
-  OC_PROF_IMPLICIT_Z = 12
+  OC_PROF_IMPLICIT_Z = 12, OC_PROF_LES = 13
 };
-#define OC_NPROF 13
+#define OC_NPROF 14
 int oc_profile(oc_model* m, int32_t enable);
 int oc_profile_read(oc_model* m, double* ms, int64_t* launches);
 

@@ -282,13 +282,15 @@ def tracer_diffusion(s, name, kap_e, ph):
 
 
 def les_tendencies(s, ph, kind):
-    """The closure's contribution to G for kind 'smagorinsky' or 'amd'."""
+    """The closure's contribution to G for kind 'smagorinsky' or 'amd'
+    (constants from the physics record when it carries them)."""
     if kind == "smagorinsky":
-        nu = smagorinsky_viscosity(s, ph)
-        kap = {n: nu / PR for n in ph.tracers}
+        nu = smagorinsky_viscosity(s, ph, getattr(ph, "les_cs", CS), getattr(ph, "les_cb", CB))
+        kap = {n: nu / getattr(ph, "les_pr", PR) for n in ph.tracers}
     elif kind == "amd":
-        nu = amd_viscosity(s, ph)
-        kap = {n: amd_diffusivity(s, n, ph) for n in ph.tracers}
+        c = getattr(ph, "les_camd", CAMD)
+        nu = amd_viscosity(s, ph, c)
+        kap = {n: amd_diffusivity(s, n, ph, c) for n in ph.tracers}
     else:
         raise ValueError(kind)
     Gu, Gv, Gw = stress_divergence(s, nu, ph)

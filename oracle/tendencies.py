@@ -202,8 +202,15 @@ def w_tendency(s, ph):
 
 
 def tendencies(s, ph):
-    """All tendencies of the prognostic fields of a padded state dict."""
+    """All tendencies of the prognostic fields of a padded state dict, with
+    the eddy-viscosity LES closure's contribution when one is configured."""
     G = {"u": u_tendency(s, ph), "v": v_tendency(s, ph), "w": w_tendency(s, ph)}
     for name in ph.tracers:
         G[name] = tracer_tendency(s[name], s, ph, ph.top_flux.get(name, 0.0))
+    kind = getattr(ph, "les", "none")
+    if kind != "none":
+        from .les import les_tendencies
+        L = les_tendencies(s, ph, kind)
+        for name in G:
+            G[name] = G[name] + L[name]
     return G

@@ -28,7 +28,7 @@ FLAGS = [
 
 SOURCES = ["api.hip", "stencil.hip", "poisson.hip", "tendency.hip", "barotropic.hip", "mlp.hip",
            "closure_api.hip", "hydrostatic.hip",
-           "ensemble_api.hip", "coarse.hip", "vertical.hip"]
+           "ensemble_api.hip", "coarse.hip", "vertical.hip", "les.hip"]
 
 
 def _compile(src, defines=(), build_dir=None):

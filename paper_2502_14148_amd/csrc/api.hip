@@ -45,7 +45,8 @@ struct Layout {
   uint64_t state[2][MAXF], G[MAXF];
   uint64_t spec, p, twx, twy, twz, dctz, lamx, lamy, lamz, staging, diag;
   uint64_t baro[13], metric, hzeta, hpx, hpy, hmet;
-  uint64_t gc[4];
+  uint64_t gc[MAXF];
+  uint64_t les_nu, les_kap[OC_MAX_TRACERS], les_d2;
   uint64_t zt64, ztT, vfac;
   uint64_t total;
 };
@@ -90,8 +91,15 @@ Layout make_layout(const oc_grid_desc& g, const oc_model_desc& m) {
     L.hpy = off; off += fb;
     L.hmet = off; off += align256((uint64_t)HYDRO_NMET * (g.ny + 2 * H + 1) * 8);
   }
-  if (m.closure)
-    for (int q = 0; q < 4; ++q) { L.gc[q] = off; off += fb; }
+  // closure tendencies: u, v, w, T for the learned closure, every field for LES
+  const int ngc = m.closure ? 4 : (m.les ? nf : 0);
+  for (int q = 0; q < ngc; ++q) { L.gc[q] = off; off += fb; }
+  if (m.les) {
+    L.les_nu = off; off += fb;
+    if (m.les == OC_LES_AMD)
+      for (int q = 0; q < m.ntracers; ++q) { L.les_kap[q] = off; off += fb; }
+    L.les_d2 = off; off += align256((uint64_t)g.nz * esz);
+  }
   L.zt64 = off; off += align256((uint64_t)zt64_len(g.nz) * 8);
   L.ztT = off; off += align256((uint64_t)ztT_len(g.nz) * esz);
   L.vfac = off; off += align256((uint64_t)vfac_len(g.nz) * esz);
@@ -190,6 +198,15 @@ int validate_model(const oc_model_desc* m) {
     set_error("hydrostatic model needs depth > 0");
     return OC_ERR_ARG;
   }
+  if (m->les < OC_LES_NONE || m->les > OC_LES_AMD) {
+    set_error("unknown LES closure %d", m->les);
+    return OC_ERR_ARG;
+  }
+  if (m->les && (!(m->les_c > 0) || !(m->les_cb >= 0) ||
+                 (m->les == OC_LES_SMAGORINSKY && !(m->les_pr > 0)))) {
+    set_error("LES constants: les_c > 0, les_cb >= 0, les_pr > 0");
+    return OC_ERR_ARG;
+  }
   if (m->implicit_z != 0 && m->implicit_z != 1) {
     set_error("implicit_z must be 0 or 1");
     return OC_ERR_ARG;
@@ -212,6 +229,10 @@ int validate_pair(const oc_grid_desc& g, const oc_model_desc& m) {
   }
   if (m.implicit_z && (m.kind != OC_NONHYDROSTATIC || g.topology_z != OC_BOUNDED)) {
     set_error("implicit vertical diffusion needs the nonhydrostatic model with walls in z");
+    return OC_ERR_UNSUPPORTED;
+  }
+  if (m.les && (m.kind != OC_NONHYDROSTATIC || m.closure)) {
+    set_error("the LES closure needs the nonhydrostatic model without a learned closure");
     return OC_ERR_UNSUPPORTED;
   }
   if (m.closure && g.z_faces) {
@@ -321,7 +342,7 @@ int tendency_call(oc_model* m, int in, int out, int stage, double dt, int combin
     fs.out[q] = (q < m->nf) ? (T*)m->state[out][q] : nullptr;
     fs.G[q] = (q < m->nf) ? (T*)m->G[q] : nullptr;
   }
-  for (int q = 0; q < 4; ++q) fs.closure[q] = m->net ? (const T*)m->gc[q] : nullptr;
+  for (int q = 0; q < MAXF; ++q) fs.closure[q] = (m->net && q < 4) ? (const T*)m->gc[q] : nullptr;
   if (m->net) {
     // learned closure of the current state: the fused gather + network, then
     // the flux divergence of its outputs
@@ -334,6 +355,40 @@ int tendency_call(oc_model* m, int in, int out, int stage, double dt, int combin
                                          s));
   }
   TendParams<T> p = tend_params<T>(m);
+  if (m->md.les) {
+    // eddy-viscosity closure of the current state: viscosity at the centres,
+    // then the closure tendencies of every field, added by the tendency kernel
+    ProfScope pl(m, OC_PROF_LES, s);
+    LesArgs<T> a;
+    std::memset(&a, 0, sizeof(a));
+    a.u = fs.in[0];
+    a.v = fs.in[1];
+    a.w = fs.in[2];
+    a.c0 = fs.in[3];
+    a.c1 = (m->nf > 4) ? fs.in[4] : fs.in[3];
+    a.ntr = m->nf - 3;
+    for (int q = 0; q < a.ntr; ++q) {
+      a.tr[q] = fs.in[3 + q];
+      a.kap[q] = (T*)m->les_kap[q];
+    }
+    a.nu = (T*)m->les_nu;
+    for (int q = 0; q < m->nf; ++q) a.gc[q] = (T*)m->gc[q];
+    a.rdx = p.rdx;
+    a.rdy = p.rdy;
+    a.rdzc = p.rdzc;
+    a.rdzf = p.rdzf;
+    a.delta2 = (const T*)m->les_d2;
+    a.cb = (T)m->md.les_cb;
+    a.camd = (T)m->md.les_c;
+    a.rpr = (T)(m->md.les == OC_LES_SMAGORINSKY ? 1.0 / m->md.les_pr : 1.0);
+    a.buoyancy = (m->md.buoyancy && m->nf > 4) ? 1 : 0;
+    a.g_alpha = p.g_alpha;
+    a.g_beta = p.g_beta;
+    a.t_ref = p.t_ref;
+    a.s_ref = p.s_ref;
+    OC_CHECK_HIP(launch_les<T>(m->dims, a, m->md.les, s));
+    for (int q = 0; q < m->nf; ++q) fs.closure[q] = (const T*)m->gc[q];
+  }
   ProfScope ps(m, OC_PROF_TENDENCY, s);
   p.dt = (T)dt;
   p.gam = (T)RK_GAMMA[stage];
@@ -958,7 +1013,15 @@ int oc_model_create(const oc_grid* g, const oc_model_desc* md, void* workspace,
   m->hfirst = 1;
   m->hstale = 1;
   m->net = nullptr;
-  for (int q = 0; q < 4; ++q) m->gc[q] = md->closure ? (void*)(m->ws + L.gc[q]) : nullptr;
+  {
+    const int ngc = md->closure ? 4 : (md->les ? m->nf : 0);
+    for (int q = 0; q < MAXF; ++q) m->gc[q] = (q < ngc) ? (void*)(m->ws + L.gc[q]) : nullptr;
+    m->les_nu = md->les ? (void*)(m->ws + L.les_nu) : nullptr;
+    for (int q = 0; q < OC_MAX_TRACERS; ++q)
+      m->les_kap[q] = (md->les == OC_LES_AMD && q < md->ntracers) ? (void*)(m->ws + L.les_kap[q])
+                                                                   : nullptr;
+    m->les_d2 = md->les ? (void*)(m->ws + L.les_d2) : nullptr;
+  }
 
   hipError_t e = hipMemset(m->ws, 0, L.total);
   {
@@ -971,6 +1034,16 @@ int oc_model_create(const oc_grid* g, const oc_model_desc* md, void* workspace,
     m->dzmin = *std::min_element(m->hdzc.begin(), m->hdzc.end());
     if (e == hipSuccess) e = hipMemcpy(m->zt64, z64.data(), z64.size() * 8, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(m->ztT, zT.data(), zT.size(), hipMemcpyHostToDevice);
+    if (md->les) {
+      // Smagorinsky-Lilly: (C_s Delta_k)^2, Delta_k = (dx dy dzc_k)^(1/3)
+      std::vector<char> d2((size_t)nz * m->esz);
+      for (int k = 0; k < nz; ++k) {
+        const double v = std::pow(md->les_c * std::cbrt(m->dx * m->dy * m->hdzc[k]), 2.0);
+        if (m->esz == 8) std::memcpy(&d2[(size_t)k * 8], &v, 8);
+        else { const float f = (float)v; std::memcpy(&d2[(size_t)k * 4], &f, 4); }
+      }
+      if (e == hipSuccess) e = hipMemcpy(m->les_d2, d2.data(), d2.size(), hipMemcpyHostToDevice);
+    }
   }
   if (md->kind == OC_NONHYDROSTATIC) {
     std::vector<double> twx, twy, twz, dctz, lamx, lamy, lamz;
@@ -1196,7 +1269,7 @@ int oc_hydrostatic_step(oc_model* m, double dt, int32_t N, int32_t M, const doub
 int oc_model_set_closure(oc_model* m, oc_mlp* net, const double* stats, void* stream) {
   if (!m) { set_error("model is NULL"); return OC_ERR_ARG; }
   if (!net) { m->net = nullptr; return OC_OK; }
-  if (m->kind != OC_NONHYDROSTATIC || !m->dims.zb || !m->md.buoyancy || !m->gc[0] ||
+  if (m->kind != OC_NONHYDROSTATIC || !m->dims.zb || !m->md.buoyancy || !m->md.closure ||
       m->stretched) {
     set_error("the closure needs a wall-bounded, uniformly spaced nonhydrostatic model with T, S "
               "created with closure = 1");

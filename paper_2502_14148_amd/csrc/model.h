@@ -88,7 +88,12 @@ struct oc_model {
   // learned closure: network, statistics, tendency buffers (u, v, w, T)
   oc_mlp* net;
   ClosureStats cst;
-  void* gc[4];
+  void* gc[MAXF];
+  // LES closure: viscosity at the centres, AMD's per-tracer diffusivities
+  // (padded, state precision) and the (C_s Delta_k)^2 table
+  void* les_nu;
+  void* les_kap[OC_MAX_TRACERS];
+  void* les_d2;
   // per-kernel-class event timing
   int prof_on;
   std::vector<hipEvent_t> ev_pool;

@@ -98,8 +98,9 @@ struct FieldSet {
   const T* in[MAXF];
   T* out[MAXF];
   T* G[MAXF];
-  const T* closure[4];   // optional learned-closure tendencies of u, v, w, tracer 0
-                         // (padded layout), added to G; null when off
+  const T* closure[MAXF];  // optional closure tendencies per field (learned
+                           // closure: u, v, w, tracer 0; LES: every field),
+                           // padded layout, added to G; null when off
 };
 
 // Spectral-solve tables and buffers (FP64).
@@ -372,6 +373,32 @@ hipError_t launch_poisson_tridiag(const Dims& d, const SpecBufs& sb, const doubl
 // = blockIdx.y): fac[q] holds the recurrence tables of vertical_factors for
 // field q's matrix; wface[q] selects w on the interior faces 1..nz-1,
 // otherwise the nz centres.  Needs bounded z and nz <= 256.
+// Eddy-viscosity LES closure of one substage (les.hip): inputs, the
+// viscosity (and AMD's per-tracer diffusivity) buffers written with halo
+// images, and the closure tendencies gc[f] (padded layout, interior).
+template <class T>
+struct LesArgs {
+  const T* u;
+  const T* v;
+  const T* w;
+  const T* c0;               // T and S (Smagorinsky-Lilly buoyancy)
+  const T* c1;
+  const T* tr[OC_MAX_TRACERS];
+  int ntr;
+  T* nu;
+  T* kap[OC_MAX_TRACERS];    // AMD; null for Smagorinsky-Lilly (kappa = nu/Pr)
+  T* gc[MAXF];
+  T rdx, rdy;
+  const T* rdzc;             // as in TendParams
+  const T* rdzf;
+  const T* delta2;           // Smagorinsky-Lilly: (C_s Delta_k)^2 per level
+  T cb, camd, rpr;
+  int buoyancy;
+  T g_alpha, g_beta, t_ref, s_ref;
+};
+template <class T>
+hipError_t launch_les(const Dims& d, const LesArgs<T>& a, int kind, hipStream_t s);
+
 template <class T>
 struct VImplicitArgs {
   T* f[MAXF];

@@ -327,13 +327,12 @@ __device__ __attribute__((always_inline)) inline void tendency_tile(
                      (ww[3] - ww[2]) * rzc;
 #pragma unroll
       for (int q = 0; q < NTR; ++q) G[3 + q] += -(fzt_c[q] - fzb_c[q]) * rzc - P.toff[q] * divu;
-      if (fs.closure[0]) {
-        // learned subgrid closure: precomputed flux divergences
+      {
+        // closure tendencies computed beforehand (learned or LES closure)
         const long o = (long)(k + H) * sz + col;
-        G[0] += fs.closure[0][o];
-        G[1] += fs.closure[1][o];
-        G[2] += fs.closure[2][o];
-        G[3] += fs.closure[3][o];
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+          if (fs.closure[f]) G[f] += fs.closure[f][o];
       }
 
       const long lv = (long)(k + H) * sz;

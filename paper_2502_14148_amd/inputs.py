@@ -55,6 +55,11 @@ class Physics:
     closure: bool = False               # reserve room for a learned closure
     z_faces: tuple = None               # nz + 1 ascending z faces (bounded z); None: uniform
     implicit_z: bool = False            # vertical diffusion treated implicitly per substage
+    les: str = "none"                   # "none" | "smagorinsky" | "amd"
+    les_cs: float = 0.16                # Smagorinsky constant C_s
+    les_cb: float = 1.0                 # Lilly stratification coefficient C_b
+    les_pr: float = 1.0                 # turbulent Prandtl number
+    les_camd: float = 1.0 / 12.0        # AMD constant C
 
     def as_dict(self):
         return asdict(self)

@@ -40,10 +40,11 @@ OC_ENS_TUNE, OC_ENS_GRAPH = 1, 2
 OC_MLP_NPARAM = 195076
 MLP_SHAPES = (("W1", (256, 500)), ("b1", (256,)), ("W2", (256, 256)), ("b2", (256,)),
               ("W3", (4, 256)), ("b3", (4,)))
-OC_NPROF = 13
+OC_NPROF = 14
 PROF_CLASSES = ("tendency", "fft_x_fwd", "fft_y_fwd", "z_solve", "fft_y_inv", "fft_x_inv",
                 "project", "halo", "closure", "hydro_diag", "hydro_tendency", "barotropic",
-                "implicit_z")
+                "implicit_z", "les")
+LES = {"none": 0, "smagorinsky": 1, "amd": 2}
 
 
 class GridDesc(ctypes.Structure):
@@ -66,7 +67,9 @@ class ModelDesc(ctypes.Structure):
                 ("nu", ctypes.c_double), ("kappa", ctypes.c_double),
                 ("top_flux", ctypes.c_double * OC_MAX_TRACERS),
                 ("depth", ctypes.c_double), ("omega", ctypes.c_double),
-                ("closure", ctypes.c_int32), ("implicit_z", ctypes.c_int32)]
+                ("closure", ctypes.c_int32), ("implicit_z", ctypes.c_int32),
+                ("les", ctypes.c_int32), ("les_c", ctypes.c_double), ("les_cb", ctypes.c_double),
+                ("les_pr", ctypes.c_double)]
 
 
 class OcError(RuntimeError):
@@ -174,6 +177,11 @@ class Model:
             md.kind = OC_NONHYDROSTATIC
             md.f = ph.f
             md.implicit_z = 1 if getattr(ph, "implicit_z", False) else 0
+            md.les = LES[getattr(ph, "les", "none")]
+            if md.les == LES["smagorinsky"]:
+                md.les_c, md.les_cb, md.les_pr = ph.les_cs, ph.les_cb, ph.les_pr
+            elif md.les == LES["amd"]:
+                md.les_c, md.les_cb, md.les_pr = ph.les_camd, 0.0, 1.0
         md.precision = OC_FP64 if precision == "fp64" else OC_FP32_MIXED
         md.advection = ADVECTION[ph.advection]
         md.weno_eps = ph.weno_eps

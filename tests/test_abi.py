@@ -152,3 +152,27 @@ def test_stretched_grid_validation():
     md.implicit_z, md.buoyancy = 1, 0
     assert lib.oc_model_workspace_size(g, ctypes.byref(md), ctypes.byref(nbytes)) == -5
     assert lib.oc_grid_destroy(g) == 0
+
+
+def test_les_validation():
+    lib = oc.load_library()
+    g = ctypes.c_void_p()
+    gd = oc.GridDesc(32, 32, 16, oc.OC_BOUNDED, 0, 64, 0, 64, -16, 16, oc.OC_RECTILINEAR, 0.0)
+    assert lib.oc_grid_create(ctypes.byref(gd), ctypes.byref(g)) == 0
+    md = oc.ModelDesc()
+    md.precision, md.advection, md.weno_eps, md.weno_q = oc.OC_FP32_MIXED, 1, 1e-15, 2
+    md.ntracers, md.buoyancy = 2, 1
+    md.les, md.les_c, md.les_cb, md.les_pr = 1, 0.16, 1.0, 1.0
+    nbytes = ctypes.c_uint64()
+    assert lib.oc_model_workspace_size(g, ctypes.byref(md), ctypes.byref(nbytes)) == 0
+    plain = ctypes.c_uint64()
+    md.les = 0
+    assert lib.oc_model_workspace_size(g, ctypes.byref(md), ctypes.byref(plain)) == 0
+    assert nbytes.value > plain.value          # viscosity and closure-tendency buffers
+    md.les = 3
+    assert lib.oc_model_workspace_size(g, ctypes.byref(md), ctypes.byref(nbytes)) == -1
+    md.les, md.les_c = 2, 0.0
+    assert lib.oc_model_workspace_size(g, ctypes.byref(md), ctypes.byref(nbytes)) == -1
+    md.les_c, md.closure = 1.0 / 12.0, 1
+    assert lib.oc_model_workspace_size(g, ctypes.byref(md), ctypes.byref(nbytes)) == -5
+    assert lib.oc_grid_destroy(g) == 0
