@@ -258,6 +258,41 @@ def run_stretched(steps, warmup, n):
             "hbm": kern, "final_max_w": diag["max_w"]}
 
 
+# Algorithmic HBM bytes per cell of the LES kernels (FP32): the viscosity
+# kernel reads u, v, w, T, S (20 B) and writes nu_e (+ AMD's two tracer
+# diffusivities); the flux kernel reads u, v, w, T, S, nu_e (+ the
+# diffusivities) and writes the five closure tendencies (20 B).
+LES_BYTES_PER_CELL = {"smagorinsky": (20 + 4) + (24 + 20), "amd": (20 + 12) + (32 + 20)}
+
+
+def run_les(steps, warmup, n):
+    """The 256^3 free-convection step with an eddy-viscosity closure
+    (Smagorinsky-Lilly, then AMD) beside the constant molecular nu, kappa."""
+    from paper_2502_14148_amd import inputs
+    out = {}
+    for kind in ("smagorinsky", "amd"):
+        ph = inputs.convection_physics((n, n, n), (2.0 * n, 2.0 * n, 1.0 * n))
+        ph.les = kind
+        print(f"# {kind} {n}^3 run", file=sys.stderr, flush=True)
+        s = inputs.convection_initial(ph, seed=0)
+        ms, _, prof, diag = run_gpu(ph, s, "fp32", steps, warmup)
+        del s
+        ncells = n ** 3
+        t, c = prof["les"]
+        gbs = LES_BYTES_PER_CELL[kind] * ncells / (t / 1e3 / c) / 1e9
+        out[kind] = {"value": ncells * steps / (ms / 1e3), "unit": "cell-steps/s",
+                     "ms_per_step": ms / steps,
+                     "kernels_ms_per_step": {k: v[0] / steps for k, v in prof.items() if v[1]},
+                     "les_hbm": {"avg_substage_us": round(t / c * 1e3, 1), "achieved_gbs": round(gbs, 1),
+                                 "frac": round(gbs / HBM_PEAK_GBS, 4),
+                                 "bytes_per_cell": LES_BYTES_PER_CELL[kind]},
+                     "final_max_w": diag["max_w"]}
+    out["config"] = {"workload": f"free-convection LES {n}^3 with Smagorinsky-Lilly (C_s 0.16, "
+                                 f"C_b 1, Pr 1) or AMD (C 1/12) eddy viscosity, FP32", "dt_s": 1.0,
+                     "steps": steps, "warmup": warmup, "dtype": "f32"}
+    return out
+
+
 MLP_FLOPS_PER_ROW = 2 * (500 * 256 + 256 * 256 + 256 * 4)   # forward, one cell
 BF16_PEAK_TFLOPS = 2500.0      # MI355X dense BF16 MFMA
 
@@ -409,6 +444,7 @@ def main():
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-closure", action="store_true")
     ap.add_argument("--no-stretched", action="store_true")
+    ap.add_argument("--no-les", action="store_true")
     ap.add_argument("--no-main", action="store_true",
                     help="skip the 256^3 step (profiling the other legs alone)")
     ap.add_argument("--ensemble-steps", type=int, default=20)
@@ -440,6 +476,9 @@ def main():
     if not a.no_stretched:
         print("# stretched-grid run", file=sys.stderr, flush=True)
         out["stretched"] = run_stretched(a.steps, a.warmup, a.n)
+    if not a.no_les:
+        print("# LES closure runs", file=sys.stderr, flush=True)
+        out["les"] = run_les(a.steps, a.warmup, a.n)
     if not a.no_closure:
         print("# closure network", file=sys.stderr, flush=True)
         out["closure_mlp"] = run_closure_mlp()

@@ -25,6 +25,14 @@ namespace oc {
 
 namespace {
 
+// Linear cell index of a thread.  Workgroups are dealt round-robin to the
+// 8 XCDs; renumbering them gives each XCD a contiguous run of cells, so the
+// neighbouring rows and planes a stencil reads stay in one L2.
+__device__ inline int cell_of_block(unsigned b, unsigned nb, unsigned tid, unsigned bs) {
+  if (nb % 8 == 0) b = (b % 8) * (nb / 8) + b / 8;
+  return (int)(b * bs + tid);
+}
+
 template <class T>
 struct Acc {
   const T* __restrict__ f;
@@ -39,7 +47,7 @@ struct Acc {
 template <class T, int KIND>
 __global__ void __launch_bounds__(256) les_viscosity_kernel(Dims d, LesArgs<T> a) {
   const int n = d.nx * d.ny * d.nz;
-  const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  const int t = cell_of_block(blockIdx.x, gridDim.x, threadIdx.x, blockDim.x);
   if (t >= n) return;
   const int i = t % d.nx, j = (t / d.nx) % d.ny, k = t / (d.nx * d.ny);
   const long c = pidx(d, i, j, k);
@@ -148,7 +156,7 @@ __global__ void __launch_bounds__(256) les_viscosity_kernel(Dims d, LesArgs<T> a
 template <class T>
 __global__ void __launch_bounds__(256) les_flux_kernel(Dims d, LesArgs<T> a) {
   const int n = d.nx * d.ny * d.nz;
-  const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  const int t = cell_of_block(blockIdx.x, gridDim.x, threadIdx.x, blockDim.x);
   if (t >= n) return;
   const int i = t % d.nx, j = (t / d.nx) % d.ny, k = t / (d.nx * d.ny);
   const long c = pidx(d, i, j, k);

@@ -119,7 +119,10 @@ __device__ inline void slot_fluxes(T* S, const SlotOff& o, int L, int sd, int se
 
 // One column tile: tile b of an nbx x nby x nbz decomposition (k chunks of
 // kc levels) of the grid d.
-template <class T, int SCHEME, int NTR, int TX, int TY>
+// CLO: add the closure tendencies computed beforehand (fs.closure; learned
+// closure: u, v, w and tracer 0, LES closure: every field).  A separate
+// instantiation keeps the plain kernel's registers free of them.
+template <class T, int SCHEME, int NTR, int TX, int TY, bool CLO = false>
 __device__ __attribute__((always_inline)) inline void tendency_tile(
     const Dims& d, const FieldSet<T>& fs, const TendParams<T>& P, int nbx, int nby, int nbz,
     int kc, int b) {
@@ -327,18 +330,12 @@ __device__ __attribute__((always_inline)) inline void tendency_tile(
                      (ww[3] - ww[2]) * rzc;
 #pragma unroll
       for (int q = 0; q < NTR; ++q) G[3 + q] += -(fzt_c[q] - fzb_c[q]) * rzc - P.toff[q] * divu;
-      {
-        // closure tendencies computed beforehand (learned or LES closure)
-        const long o = (long)(k + H) * sz + col;
-#pragma unroll
-        for (int f = 0; f < NF; ++f)
-          if (fs.closure[f]) G[f] += fs.closure[f][o];
-      }
 
       const long lv = (long)(k + H) * sz;
 #pragma unroll
       for (int f = 0; f < NF; ++f) {
-        const T g = G[f];
+        // plus the closure tendency computed beforehand
+        const T g = (CLO && fs.closure[f]) ? G[f] + (fs.closure[f] + lv)[col] : G[f];
         T* __restrict__ Gf = fs.G[f] + lv;
         if (P.combine) {
           T x;
@@ -392,13 +389,13 @@ __device__ __attribute__((always_inline)) inline void tendency_tile(
 
 // One model; tiles are mapped XCD-major, so neighbouring tiles (which share
 // halo loads) land on the same XCD and its L2.
-template <class T, int SCHEME, int NTR, int TX, int TY>
+template <class T, int SCHEME, int NTR, int TX, int TY, bool CLO>
 __global__ void OC_TEND_ATTRS(T, TX, TY)
 tendency_zmarch(Dims d, FieldSet<T> fs, TendParams<T> P, int nbx, int nby, int nbz, int kc) {
   const int nblk = nbx * nby * nbz;
   int b = blockIdx.x;
   if ((nblk & 7) == 0) b = (b & 7) * (nblk >> 3) + (b >> 3);
-  tendency_tile<T, SCHEME, NTR, TX, TY>(d, fs, P, nbx, nby, nbz, kc, b);
+  tendency_tile<T, SCHEME, NTR, TX, TY, CLO>(d, fs, P, nbx, nby, nbz, kc, b);
 }
 
 // An ensemble of models in one launch.  Work items (member, tile) come from
@@ -447,9 +444,15 @@ hipError_t launch_tendency_fast(const Dims& d, const FieldSet<T>& fs, const Tend
   if (kc > d.nz) kc = d.nz;
   const int nbz = (d.nz + kc - 1) / kc;
   const dim3 grid(nbx * nby * nbz);
-#define OC_TZ(SCH, NTR_, TX_, TY_)                                                          \
-  hipLaunchKernelGGL((tz::tendency_zmarch<T, SCH, NTR_, TX_, TY_>), grid, dim3(TX_ * TY_), 0, \
-                     s, d, fs, p, nbx, nby, nbz, kc)
+  bool clo = false;
+  for (int f = 0; f < MAXF; ++f) clo = clo || fs.closure[f] != nullptr;
+#define OC_TZ(SCH, NTR_, TX_, TY_)                                                            \
+  if (clo)                                                                                    \
+    hipLaunchKernelGGL((tz::tendency_zmarch<T, SCH, NTR_, TX_, TY_, true>), grid,              \
+                       dim3(TX_ * TY_), 0, s, d, fs, p, nbx, nby, nbz, kc);                   \
+  else                                                                                        \
+    hipLaunchKernelGGL((tz::tendency_zmarch<T, SCH, NTR_, TX_, TY_, false>), grid,             \
+                       dim3(TX_ * TY_), 0, s, d, fs, p, nbx, nby, nbz, kc)
 #define OC_TZ_NTR(SCH, TX_, TY_)                \
   switch (p.ntr) {                              \
     case 1: OC_TZ(SCH, 1, TX_, TY_); break;     \
