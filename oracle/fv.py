@@ -1,7 +1,8 @@
 """Halo-padded staggered fields (finite-volume appendix, C-grid staggering).
 
 Fields are float64 arrays of shape (nz + 2H, ny + 2H, nx + 2H), indexed
-[k, j, i] with x fastest, H = 3 halo cells on every side.  Interior cell i
+[k, j, i] with x fastest, H = 5 halo cells on every side (the reach of
+the widest reconstruction, fifth-order-in-radius WENO9).  Interior cell i
 (0-based) sits at padded index H + i.  Face i is the left face of cell i
 ("face indices are left of cell indices", composable-operator subsection), so
 u[face i] is at padded index H + i too.  A bounded z axis has nz + 1 w faces;
@@ -15,7 +16,7 @@ appendix); the wall mirroring is the reading adopted for walls.
 """
 import numpy as np
 
-H = 3
+H = 5
 
 
 def padded_shape(ph):

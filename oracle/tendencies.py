@@ -9,8 +9,10 @@ fluxes (flux-divergence and advection-flux-divergence equations) with a
 prescribed flux through the top wall.
 
 Readings where the paper is silent:
-* the advecting-velocity interpolation for momentum is centred fourth order,
-  (-a0 + 7 a1 + 7 a2 - a3) / 12;
+* the advecting-velocity interpolation for momentum is the centred
+  reconstruction one order below the WENO order: fourth order,
+  (-a0 + 7 a1 + 7 a2 - a3) / 12, with WENO5; sixth order with WENO7 and
+  eighth order with WENO9 (stencils widened symmetrically);
 * Coriolis uses four-point averages of the other horizontal component;
 * buoyancy b = g (alpha (T - T0) - beta (S - S0)) enters G_w averaged to
   the w faces;
@@ -34,14 +36,31 @@ is bounded (wall faces hold 0).
 import numpy as np
 
 from .fv import view, z_spacings
-from .weno import reconstruct
-
-OFFSETS = (-3, -2, -1, 0, 1, 2)
+from .weno import RADIUS, centred, reconstruct
 
 
 def interp4(a0, a1, a2, a3):
     """Centred fourth-order interpolation to the midpoint of a1 and a2."""
     return (-a0 + 7.0 * a1 + 7.0 * a2 - a3) / 12.0
+
+
+def _offsets(ph):
+    """Offsets of the 2R values a reconstruction at x_{i-1/2} reads."""
+    R = RADIUS[ph.advection]
+    return tuple(range(-R, R))
+
+
+def _ioffsets(ph):
+    """Offsets of the values the advecting-velocity interpolation reads."""
+    R = RADIUS[ph.advection]
+    return tuple(range(-(R - 1), R - 1))
+
+
+def _interp(ph, vals):
+    """Centred interpolation of the advecting velocity (order 2R - 2)."""
+    if len(vals) == 4:
+        return interp4(*vals)
+    return centred(len(vals), vals)
 
 
 def _rec(ph, qs, vel):
@@ -84,15 +103,15 @@ def tracer_tendency(c, s, ph, top_flux=0.0):
     kz = _zdiff(ph, k)
     # x faces i = 0..nx
     U = view(u, ni=nx + 1, ph=ph)
-    Fx = U * _rec(ph, [view(c, di=o, ni=nx + 1, ph=ph) for o in OFFSETS], U)
+    Fx = U * _rec(ph, [view(c, di=o, ni=nx + 1, ph=ph) for o in _offsets(ph)], U)
     Fx = Fx - k * (view(c, ni=nx + 1, ph=ph) - view(c, di=-1, ni=nx + 1, ph=ph)) / dx
     # y faces j = 0..ny
     V = view(v, nj=ny + 1, ph=ph)
-    Fy = V * _rec(ph, [view(c, dj=o, nj=ny + 1, ph=ph) for o in OFFSETS], V)
+    Fy = V * _rec(ph, [view(c, dj=o, nj=ny + 1, ph=ph) for o in _offsets(ph)], V)
     Fy = Fy - k * (view(c, nj=ny + 1, ph=ph) - view(c, dj=-1, nj=ny + 1, ph=ph)) / dy
     # z faces k = 0..nz
     W = view(w, nk=nz + 1, ph=ph)
-    Fz = W * _rec(ph, [view(c, dk=o, nk=nz + 1, ph=ph) for o in OFFSETS], W)
+    Fz = W * _rec(ph, [view(c, dk=o, nk=nz + 1, ph=ph) for o in _offsets(ph)], W)
     Fz = Fz - kz * (view(c, nk=nz + 1, ph=ph) - view(c, dk=-1, nk=nz + 1, ph=ph)) / dzf
     if ph.z_bounded:
         Fz[0] = 0.0           # bottom wall: no flux
@@ -109,16 +128,16 @@ def u_tendency(s, ph):
     nu = ph.nu
     nuz = _zdiff(ph, nu)
     # x: entry i holds the flux at cell centre i-1 (between faces i-1 and i)
-    Ub = interp4(*[view(u, di=o, ni=nx + 1, ph=ph) for o in (-2, -1, 0, 1)])
-    X = Ub * _rec(ph, [view(u, di=o, ni=nx + 1, ph=ph) for o in OFFSETS], Ub)
+    Ub = _interp(ph, [view(u, di=o, ni=nx + 1, ph=ph) for o in _ioffsets(ph)])
+    X = Ub * _rec(ph, [view(u, di=o, ni=nx + 1, ph=ph) for o in _offsets(ph)], Ub)
     X = X - nu * (view(u, ni=nx + 1, ph=ph) - view(u, di=-1, ni=nx + 1, ph=ph)) / dx
     # y: corners (x face i, y face j); v interpolated along x to the x face
-    Vt = interp4(*[view(v, di=o, nj=ny + 1, ph=ph) for o in (-2, -1, 0, 1)])
-    Y = Vt * _rec(ph, [view(u, dj=o, nj=ny + 1, ph=ph) for o in OFFSETS], Vt)
+    Vt = _interp(ph, [view(v, di=o, nj=ny + 1, ph=ph) for o in _ioffsets(ph)])
+    Y = Vt * _rec(ph, [view(u, dj=o, nj=ny + 1, ph=ph) for o in _offsets(ph)], Vt)
     Y = Y - nu * (view(u, nj=ny + 1, ph=ph) - view(u, dj=-1, nj=ny + 1, ph=ph)) / dy
     # z: (x face i, centre j, z face k); w interpolated along x to the x face
-    Wt = interp4(*[view(w, di=o, nk=nz + 1, ph=ph) for o in (-2, -1, 0, 1)])
-    Z = Wt * _rec(ph, [view(u, dk=o, nk=nz + 1, ph=ph) for o in OFFSETS], Wt)
+    Wt = _interp(ph, [view(w, di=o, nk=nz + 1, ph=ph) for o in _ioffsets(ph)])
+    Z = Wt * _rec(ph, [view(u, dk=o, nk=nz + 1, ph=ph) for o in _offsets(ph)], Wt)
     Z = Z - nuz * (view(u, nk=nz + 1, ph=ph) - view(u, dk=-1, nk=nz + 1, ph=ph)) / dzf
     if ph.z_bounded:
         Z[0] = 0.0
@@ -139,16 +158,16 @@ def v_tendency(s, ph):
     nu = ph.nu
     nuz = _zdiff(ph, nu)
     # x: corners (x face i, y face j); u interpolated along y to the y face
-    Ut = interp4(*[view(u, dj=o, ni=nx + 1, ph=ph) for o in (-2, -1, 0, 1)])
-    X = Ut * _rec(ph, [view(v, di=o, ni=nx + 1, ph=ph) for o in OFFSETS], Ut)
+    Ut = _interp(ph, [view(u, dj=o, ni=nx + 1, ph=ph) for o in _ioffsets(ph)])
+    X = Ut * _rec(ph, [view(v, di=o, ni=nx + 1, ph=ph) for o in _offsets(ph)], Ut)
     X = X - nu * (view(v, ni=nx + 1, ph=ph) - view(v, di=-1, ni=nx + 1, ph=ph)) / dx
     # y: entry j holds the flux at cell centre j-1
-    Vb = interp4(*[view(v, dj=o, nj=ny + 1, ph=ph) for o in (-2, -1, 0, 1)])
-    Y = Vb * _rec(ph, [view(v, dj=o, nj=ny + 1, ph=ph) for o in OFFSETS], Vb)
+    Vb = _interp(ph, [view(v, dj=o, nj=ny + 1, ph=ph) for o in _ioffsets(ph)])
+    Y = Vb * _rec(ph, [view(v, dj=o, nj=ny + 1, ph=ph) for o in _offsets(ph)], Vb)
     Y = Y - nu * (view(v, nj=ny + 1, ph=ph) - view(v, dj=-1, nj=ny + 1, ph=ph)) / dy
     # z: (centre i, y face j, z face k); w interpolated along y
-    Wt = interp4(*[view(w, dj=o, nk=nz + 1, ph=ph) for o in (-2, -1, 0, 1)])
-    Z = Wt * _rec(ph, [view(v, dk=o, nk=nz + 1, ph=ph) for o in OFFSETS], Wt)
+    Wt = _interp(ph, [view(w, dj=o, nk=nz + 1, ph=ph) for o in _ioffsets(ph)])
+    Z = Wt * _rec(ph, [view(v, dk=o, nk=nz + 1, ph=ph) for o in _offsets(ph)], Wt)
     Z = Z - nuz * (view(v, nk=nz + 1, ph=ph) - view(v, dk=-1, nk=nz + 1, ph=ph)) / dzf
     if ph.z_bounded:
         Z[0] = 0.0
@@ -178,16 +197,16 @@ def w_tendency(s, ph):
     nuz = _zdiff(ph, nu)
     # faces k = 0..nz-1 are computed; walls are overwritten below
     # x: (x face i, centre j, z face k); u interpolated along z to the z face
-    Ut = interp4(*[view(u, dk=o, ni=nx + 1, ph=ph) for o in (-2, -1, 0, 1)])
-    X = Ut * _rec(ph, [view(w, di=o, ni=nx + 1, ph=ph) for o in OFFSETS], Ut)
+    Ut = _interp(ph, [view(u, dk=o, ni=nx + 1, ph=ph) for o in _ioffsets(ph)])
+    X = Ut * _rec(ph, [view(w, di=o, ni=nx + 1, ph=ph) for o in _offsets(ph)], Ut)
     X = X - nu * (view(w, ni=nx + 1, ph=ph) - view(w, di=-1, ni=nx + 1, ph=ph)) / dx
     # y: (centre i, y face j, z face k); v interpolated along z
-    Vt = interp4(*[view(v, dk=o, nj=ny + 1, ph=ph) for o in (-2, -1, 0, 1)])
-    Y = Vt * _rec(ph, [view(w, dj=o, nj=ny + 1, ph=ph) for o in OFFSETS], Vt)
+    Vt = _interp(ph, [view(v, dk=o, nj=ny + 1, ph=ph) for o in _ioffsets(ph)])
+    Y = Vt * _rec(ph, [view(w, dj=o, nj=ny + 1, ph=ph) for o in _offsets(ph)], Vt)
     Y = Y - nu * (view(w, nj=ny + 1, ph=ph) - view(w, dj=-1, nj=ny + 1, ph=ph)) / dy
     # z: entry k holds the flux at cell centre k-1 (between faces k-1 and k)
-    Wb = interp4(*[view(w, dk=o, nk=nz + 1, ph=ph) for o in (-2, -1, 0, 1)])
-    Z = Wb * _rec(ph, [view(w, dk=o, nk=nz + 1, ph=ph) for o in OFFSETS], Wb)
+    Wb = _interp(ph, [view(w, dk=o, nk=nz + 1, ph=ph) for o in _ioffsets(ph)])
+    Z = Wb * _rec(ph, [view(w, dk=o, nk=nz + 1, ph=ph) for o in _offsets(ph)], Wb)
     Z = Z - nuz * (view(w, nk=nz + 1, ph=ph) - view(w, dk=-1, nk=nz + 1, ph=ph)) / dzc_w
     # the w cell around face k spans the centres k-1 and k: thickness dzf[k]
     G = -_div(X, Y, Z, ph, dzf[:nz])

@@ -38,7 +38,7 @@ class Physics:
     x0: float = 0.0
     y0: float = 0.0
     z0: float = 0.0
-    advection: str = "weno5z"          # "weno5z" | "weno5_linear" | "none"
+    advection: str = "weno5z"          # "weno{5,7,9}z" | "weno{5,7,9}_linear" | "none"
     weno_eps: float = 1e-15
     weno_q: int = 2
     f: float = 0.0                      # f-plane Coriolis parameter
