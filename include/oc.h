@@ -56,7 +56,15 @@ enum { OC_PERIODIC = 0, OC_BOUNDED = 1 };
 enum { OC_RECTILINEAR = 0, OC_LATLON = 1 };
 enum { OC_NONHYDROSTATIC = 0, OC_HYDROSTATIC = 1 };
 enum { OC_FP64 = 0, OC_FP32_MIXED = 1 };
-enum { OC_ADV_NONE = 0, OC_ADV_WENO5Z = 1, OC_ADV_WENO5_LINEAR = 2 };
+enum {
+  OC_ADV_NONE = 0,
+  OC_ADV_WENO5Z = 1,
+  OC_ADV_WENO5_LINEAR = 2,
+  OC_ADV_WENO7Z = 3,
+  OC_ADV_WENO7_LINEAR = 4,
+  OC_ADV_WENO9Z = 5,
+  OC_ADV_WENO9_LINEAR = 6
+};
 enum { OC_F32 = 0, OC_F64 = 1 };
 enum { OC_LES_NONE = 0, OC_LES_SMAGORINSKY = 1, OC_LES_AMD = 2 };
 /* Field identifiers: velocities, then tracers 0..ntracers-1; the
@@ -81,7 +89,7 @@ enum { OC_ETA = 16, OC_UBT = 17, OC_VBT = 18, OC_GUBT = 19, OC_GVBT = 20, OC_TAU
  *     positions (host array, copied at oc_grid_create) from z0 to z0 + lz,
  *     cells between consecutive faces, centres at the midpoints
  *     (one-dimensional staggered-grid listing of the finite-volume
- *     appendix).  Stretched z needs topology_z = OC_BOUNDED and 4 <= nz <=
+ *     appendix).  Stretched z needs topology_z = OC_BOUNDED and 8 <= nz <=
  *     256; its pressure solve is the mixed FFT(x, y) - tridiagonal(z) one
  *     (pressure-correction appendix).
  *   OC_LATLON (thin spherical shell of `radius`): x0, lx are the longitude
@@ -111,7 +119,14 @@ typedef struct {
                                arithmetic in FP64.  With buoyancy, FP32 keeps T
                                and S as anomalies about (t_ref, s_ref) (the
                                ABI always exchanges full values) */
-  int32_t advection;        /* OC_ADV_*: WENO5-Z, its ideal-weight limit, or none */
+  int32_t advection;        /* OC_ADV_*: WENO-Z of order 5, 7 or 9 (r shifted
+                               order-r stencils, r = 3, 4, 5; reconstruction
+                               subsection), the ideal-weight limit of each,
+                               or none.  Momentum's advecting velocity is the
+                               centred reconstruction one order lower (4, 6,
+                               8).  Orders 7 and 9 widen the halo to 4 and 5
+                               cells and are nonhydrostatic-only; ensembles
+                               take WENO5-Z */
   double weno_eps;          /* WENO-Z regulariser (> 0) */
   int32_t weno_q;           /* WENO-Z exponent; only 2 is supported */
   int32_t ntracers;         /* 1..OC_MAX_TRACERS */

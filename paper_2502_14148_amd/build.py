@@ -26,7 +26,8 @@ FLAGS = [
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]
 
-SOURCES = ["api.hip", "stencil.hip", "poisson.hip", "tendency.hip", "barotropic.hip", "mlp.hip",
+SOURCES = ["tendency_r5.hip", "tendency_r4.hip", "tendency.hip",
+           "api.hip", "stencil.hip", "poisson.hip", "barotropic.hip", "mlp.hip",
            "closure_api.hip", "hydrostatic.hip",
            "ensemble_api.hip", "coarse.hip", "vertical.hip", "les.hip"]
 

@@ -56,7 +56,7 @@ uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
 Layout make_layout(const oc_grid_desc& g, const oc_model_desc& m) {
   Layout L;
   std::memset(&L, 0, sizeof(L));
-  Dims d = make_dims(g.nx, g.ny, g.nz, g.topology_z == OC_BOUNDED);
+  Dims d = make_dims(g.nx, g.ny, g.nz, g.topology_z == OC_BOUNDED, halo_width(m.advection));
   const int nf = 3 + m.ntracers;
   const uint64_t esz = (m.precision == OC_FP64) ? 8 : 4;
   const uint64_t fb = align256((uint64_t)padded_elems(d) * esz);
@@ -89,7 +89,7 @@ Layout make_layout(const oc_grid_desc& g, const oc_model_desc& m) {
     L.hzeta = off; off += fb;
     L.hpx = off; off += fb;
     L.hpy = off; off += fb;
-    L.hmet = off; off += align256((uint64_t)HYDRO_NMET * (g.ny + 2 * H + 1) * 8);
+    L.hmet = off; off += align256((uint64_t)HYDRO_NMET * (g.ny + 2 * d.h + 1) * 8);
   }
   // closure tendencies: u, v, w, T for the learned closure, every field for LES
   const int ngc = m.closure ? 4 : (m.les ? nf : 0);
@@ -125,8 +125,8 @@ int validate_grid(const oc_grid_desc* d) {
     return OC_ERR_UNSUPPORTED;
   }
   if (d->z_faces) {
-    if (d->topology_z != OC_BOUNDED || d->nz < 4 || d->nz > 256) {
-      set_error("a stretched z needs topology_z = OC_BOUNDED and 4 <= nz <= 256");
+    if (d->topology_z != OC_BOUNDED || d->nz < 8 || d->nz > 256) {
+      set_error("a stretched z needs topology_z = OC_BOUNDED and 8 <= nz <= 256");
       return OC_ERR_UNSUPPORTED;
     }
     const double tol = 1e-9 * d->lz;
@@ -144,7 +144,7 @@ int validate_grid(const oc_grid_desc* d) {
     if (!fft_length_supported(d->nx) || !fft_length_supported(d->ny) ||
         (!d->z_faces && !fft_length_supported(d->nz))) {
       set_error("unsupported grid size %d x %d x %d (each of 8,16,32,64,96,128,256; a "
-                "stretched z any 4..256)", d->nx, d->ny, d->nz);
+                "stretched z any 8..256)", d->nx, d->ny, d->nz);
       return OC_ERR_UNSUPPORTED;
     }
     if (d->ny % 2) { set_error("ny must be even"); return OC_ERR_UNSUPPORTED; }
@@ -174,11 +174,17 @@ int validate_model(const oc_model_desc* m) {
     set_error("precision must be OC_FP64 or OC_FP32_MIXED");
     return OC_ERR_ARG;
   }
-  if (m->advection < OC_ADV_NONE || m->advection > OC_ADV_WENO5_LINEAR) {
+  if (m->advection < OC_ADV_NONE || m->advection > OC_ADV_WENO9_LINEAR) {
     set_error("unknown advection scheme %d", m->advection);
     return OC_ERR_ARG;
   }
-  if (m->advection == OC_ADV_WENO5Z && (!(m->weno_eps > 0) || m->weno_q != 2)) {
+  if (m->kind == OC_HYDROSTATIC && m->advection > OC_ADV_WENO5_LINEAR) {
+    set_error("the hydrostatic model supports WENO5 advection only");
+    return OC_ERR_UNSUPPORTED;
+  }
+  const bool wenoz = m->advection == OC_ADV_WENO5Z || m->advection == OC_ADV_WENO7Z ||
+                     m->advection == OC_ADV_WENO9Z;
+  if (wenoz && (!(m->weno_eps > 0) || m->weno_q != 2)) {
     set_error("WENO-Z needs weno_eps > 0 and weno_q == 2");
     return OC_ERR_UNSUPPORTED;
   }
@@ -675,8 +681,9 @@ void fill_latlon_metrics(const oc_grid_desc& g, std::vector<double>& met) {
   }
 }
 
-// Row tables of the baroclinic step (HydroMetric), rows j = -H .. ny + H.
-void fill_hydro_metrics(const oc_grid_desc& g, double omega, std::vector<double>& met) {
+// Row tables of the baroclinic step (HydroMetric), rows j = -h .. ny + h
+// for halo width h.
+void fill_hydro_metrics(const oc_grid_desc& g, double omega, int H, std::vector<double>& met) {
   const double pi = 3.14159265358979323846;
   const int ny = g.ny, nt = ny + 2 * H + 1;
   const double dlam = g.lx / g.nx * pi / 180.0;
@@ -767,8 +774,8 @@ template <class T>
 HydroBufs<T> hydro_bufs(oc_model* m, int in, int out) {
   HydroBufs<T> a;
   a.d = m->dims;
-  const int nt = m->dims.ny + 2 * H + 1;
-  // tables of nt rows each; the kernels index them with j + H
+  const int nt = m->dims.ny + 2 * m->dims.h + 1;
+  // tables of nt rows each; the kernels index them with j + h
   a.m.dxc = m->hmet + 0 * nt;
   a.m.dxf = m->hmet + 1 * nt;
   a.m.areac = m->hmet + 2 * nt;
@@ -950,7 +957,8 @@ int oc_model_create(const oc_grid* g, const oc_model_desc* md, void* workspace,
   m->gd.z_faces = nullptr;  // the model keeps only the device tables
   m->stretched = g->zf.empty() ? 0 : 1;
   m->md = *md;
-  m->dims = make_dims(g->d.nx, g->d.ny, g->d.nz, g->d.topology_z == OC_BOUNDED);
+  m->dims = make_dims(g->d.nx, g->d.ny, g->d.nz, g->d.topology_z == OC_BOUNDED,
+                      halo_width(md->advection));
   m->nf = 3 + md->ntracers;
   m->esz = md->precision == OC_FP64 ? 8 : 4;
   for (int q = 0; q < MAXF; ++q) m->kinds[q] = (q == OC_W) ? 1 : 0;
@@ -1060,7 +1068,7 @@ int oc_model_create(const oc_grid* g, const oc_model_desc* md, void* workspace,
     fill_latlon_metrics(g->d, met);
     if (e == hipSuccess) e = hipMemcpy(m->metric, met.data(), met.size() * 8, hipMemcpyHostToDevice);
     std::vector<double> hmet;
-    fill_hydro_metrics(g->d, md->omega, hmet);
+    fill_hydro_metrics(g->d, md->omega, m->dims.h, hmet);
     if (e == hipSuccess) e = hipMemcpy(m->hmet, hmet.data(), hmet.size() * 8, hipMemcpyHostToDevice);
   }
   if (e != hipSuccess) {
@@ -1134,7 +1142,7 @@ int oc_set_state(oc_model* m, int32_t field, const void* buf, int32_t dtype, int
   if (rc) return rc;
   if (field == OC_W && m->dims.zb) {
     // the bottom wall face carries no flow
-    OC_CHECK_HIP(hipMemsetAsync((char*)fb + (size_t)H * m->dims.sz * m->esz, 0,
+    OC_CHECK_HIP(hipMemsetAsync((char*)fb + (size_t)m->dims.h * m->dims.sz * m->esz, 0,
                                 (size_t)m->dims.sz * m->esz, s));
   }
   if (m->kind == OC_HYDROSTATIC) {

@@ -26,7 +26,7 @@
 //     (chi = -1/2 on a first step), and the slow forcing of the barotropic
 //     mode Gbar = sum_k dz [...] accumulated in FP64 per column.
 //
-// Layout: halo-padded fields (H = 3), x fastest; v on the ny + 1 y faces (face
+// Layout: halo-padded fields (halo width h = 3), x fastest; v on the ny + 1 y faces (face
 // ny in the first upper halo row), w on the nz + 1 z faces (face nz in the
 // first upper halo plane).  Kernels: the column scans (zeta, w, pressure
 // gradients), the tendency + QAB2 kernel (one thread per column, register
@@ -54,8 +54,8 @@ __global__ void __launch_bounds__(HTX * HTY) hydro_diag_kernel(HydroBufs<T> a) {
 
   // vertical vorticity at corner (x face i, y face j)
   {
-    const T dxj = (T)m.dxc[j + H], dxjm = (T)m.dxc[j - 1 + H];
-    const T rza = T(1) / (T)m.areaz[j + H];
+    const T dxj = (T)m.dxc[j + d.h], dxjm = (T)m.dxc[j - 1 + d.h];
+    const T rza = T(1) / (T)m.areaz[j + d.h];
     long c = c0;
     for (int k = 0; k < d.nz; ++k, c += sz) {
       const T circ = dy * (a.v[c] - a.v[c - 1]) - (dxj * a.u[c] - dxjm * a.u[c - sy]);
@@ -65,8 +65,8 @@ __global__ void __launch_bounds__(HTX * HTY) hydro_diag_kernel(HydroBufs<T> a) {
 
   // w on the faces of columns i in [-1, nx), j in [0, ny)
   if (i >= -1 && i < d.nx && j >= 0 && j < d.ny) {
-    const T dxf0 = (T)m.dxf[j + H], dxf1 = (T)m.dxf[j + 1 + H];
-    const T rar = T(1) / (T)m.areac[j + H];
+    const T dxf0 = (T)m.dxf[j + d.h], dxf1 = (T)m.dxf[j + 1 + d.h];
+    const T rar = T(1) / (T)m.areac[j + d.h];
     double wacc = 0.0;
     long c = c0;
     a.w[c] = T(0);
@@ -80,7 +80,7 @@ __global__ void __launch_bounds__(HTX * HTY) hydro_diag_kernel(HydroBufs<T> a) {
   // pressure-gradient terms, integrated from the surface down:
   //   px = (p_i - p_{i-1}) / dx at u points, py = (p_j - p_{j-1}) / dy at v points
   if (i >= 0 && i < d.nx && j >= 0 && j < d.ny) {
-    const T rdx = T(1) / (T)m.dxc[j + H];
+    const T rdx = T(1) / (T)m.dxc[j + d.h];
     const T rdy = T(1) / dy;
     const bool vpt = j > 0;
     double sx = 0.0, sy_ = 0.0;
@@ -119,11 +119,11 @@ __global__ void __launch_bounds__(HTX * HTY) hydro_tend_kernel(HydroBufs<T> a, H
   const T eps = a.eps;
   const T dy = (T)m.dy, rdy = T(1) / dy;
   const T dz = (T)m.dz, rdz = T(1) / dz;
-  const T rdxc = T(1) / (T)m.dxc[j + H];
-  const T fc = (T)m.fc[j + H], ff = (T)m.ff[j + H];
+  const T rdxc = T(1) / (T)m.dxc[j + d.h];
+  const T fc = (T)m.fc[j + d.h], ff = (T)m.ff[j + d.h];
   const T Ax = dy * dz;
-  const T Ay0 = (T)m.dxf[j + H] * dz, Ay1 = (T)m.dxf[j + 1 + H] * dz;
-  const T Az = (T)m.areac[j + H];
+  const T Ay0 = (T)m.dxf[j + d.h] * dz, Ay1 = (T)m.dxf[j + 1 + d.h] * dz;
+  const T Az = (T)m.areac[j + d.h];
   const T rvol = T(1) / (Az * dz);
   const T nu = a.nu, kappa = a.kappa;
   const T dt = st.dt, a1 = st.a1, a0 = st.a0;
@@ -276,7 +276,7 @@ __global__ void hydro_halo_kernel(Dims d, T* u, T* v, T* t, T* s) {
   const int pi = (int)(p % d.px);
   const int pj = (int)((p / d.px) % d.py);
   const int pk = (int)(p / ((long)d.px * d.py));
-  const int i = pi - H, j = pj - H, k = pk - H;
+  const int i = pi - d.h, j = pj - d.h, k = pk - d.h;
   const bool xin = i >= 0 && i < d.nx, yin = j >= 0 && j < d.ny, zin = k >= 0 && k < d.nz;
   const bool vwall = (j == 0 || j == d.ny);
   const bool c_interior = xin && yin && zin;

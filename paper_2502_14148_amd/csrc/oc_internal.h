@@ -8,59 +8,82 @@
 
 namespace oc {
 
-constexpr int H = 3;            // halo width: the WENO5 stencil reaches 3 cells
 constexpr int MAXF = 3 + OC_MAX_TRACERS;
+constexpr int HMAX = 5;         // widest halo: the WENO9 stencil reaches 5 cells
 
-// Halo-padded layout: (nz + 2H) x (ny + 2H) x (nx + 2H), x fastest.
+// Halo width a model's advection scheme needs: the reach of its
+// reconstruction (3 cells for WENO5, 4 for WENO7, 5 for WENO9).
+inline int halo_width(int advection) {
+  return advection == OC_ADV_WENO9Z || advection == OC_ADV_WENO9_LINEAR   ? 5
+         : advection == OC_ADV_WENO7Z || advection == OC_ADV_WENO7_LINEAR ? 4
+                                                                          : 3;
+}
+
+// Halo-padded layout: (nz + 2h) x (ny + 2h) x (nx + 2h), x fastest.
 struct Dims {
   int nx, ny, nz;
   int px, py, pz;
   long sy, sz;     // strides of j and k in elements (x stride is 1)
   int zb;          // 1 if z is bounded by walls
+  int h;           // halo width
 };
 
 __host__ __device__ inline long pidx(const Dims& d, int i, int j, int k) {
-  return (long)(k + H) * d.sz + (long)(j + H) * d.sy + (long)(i + H);
+  return (long)(k + d.h) * d.sz + (long)(j + d.h) * d.sy + (long)(i + d.h);
 }
 
 // Store a value at interior point (i, j, k) of a padded field and at its halo
 // images: periodic wrap in x, y (and z when periodic); in a bounded z, an even
 // mirror for data centred in z (wface = false) or an odd mirror about the
-// wall faces for w (wface = true).  Walls faces of w are never images.
+// wall faces for w (wface = true).  Wall faces of w are never images.  A
+// point within h of both ends of a short axis has an image at each end.
 template <class T>
 __device__ inline void store_with_images(T* __restrict__ f, const Dims& d, int i, int j, int k,
                                          T val, bool wface) {
-  const int H_ = 3;
-  int xi[2] = {i, i}, yj[2] = {j, j}, zk[2] = {k, k};
-  int nxi = 1, nyj = 1, nzk = 1;
-  T zsign = T(1);
-  if (i < H_) xi[nxi++] = i + d.nx;
-  else if (i >= d.nx - H_) xi[nxi++] = i - d.nx;
-  if (j < H_) yj[nyj++] = j + d.ny;
-  else if (j >= d.ny - H_) yj[nyj++] = j - d.ny;
+  const int H = d.h;
+  // element offsets of the images along each axis (0: none; an image is
+  // never at offset 0)
+  const long xa = (i < H) ? d.nx : 0, xb = (i >= d.nx - H) ? -(long)d.nx : 0;
+  const long ya = (j < H) ? d.ny * d.sy : 0, yb = (j >= d.ny - H) ? -(long)d.ny * d.sy : 0;
+  long za = 0, zb = 0;
+  T zs = T(1);
   if (!d.zb) {
-    if (k < H_) zk[nzk++] = k + d.nz;
-    else if (k >= d.nz - H_) zk[nzk++] = k - d.nz;
+    if (k < H) za = d.nz * d.sz;
+    if (k >= d.nz - H) zb = -(long)d.nz * d.sz;
   } else if (!wface) {
-    if (k < H_) zk[nzk++] = -1 - k;
-    else if (k >= d.nz - H_) zk[nzk++] = 2 * d.nz - 1 - k;
+    if (k < H) za = (long)(-1 - 2 * k) * d.sz;                // image -1 - k
+    if (k >= d.nz - H) zb = (long)(2 * d.nz - 1 - 2 * k) * d.sz;  // image 2nz - 1 - k
   } else {
-    zsign = T(-1);
-    if (k >= 1 && k <= H_) zk[nzk++] = -k;
-    else if (k >= d.nz - 2 && k <= d.nz - 1) zk[nzk++] = 2 * d.nz - k;
+    zs = T(-1);
+    if (k >= 1 && k <= H) za = (long)(-2 * k) * d.sz;          // image -k
+    if (k >= d.nz - H + 1 && k <= d.nz - 1) zb = (long)(2 * d.nz - 2 * k) * d.sz;  // 2nz - k
   }
-  for (int c = 0; c < nzk; ++c)
-    for (int b = 0; b < nyj; ++b)
-      for (int a = 0; a < nxi; ++a) {
-        const long p = (long)(zk[c] + H_) * d.sz + (long)(yj[b] + H_) * d.sy + (xi[a] + H_);
-        f[p] = (c > 0) ? zsign * val : val;
-      }
+  T* __restrict__ p0 = f + pidx(d, i, j, k);
+  auto plane = [&](T* q, T v) {
+    q[0] = v;
+    if (xa) q[xa] = v;
+    if (xb) q[xb] = v;
+    if (ya) {
+      q[ya] = v;
+      if (xa) q[ya + xa] = v;
+      if (xb) q[ya + xb] = v;
+    }
+    if (yb) {
+      q[yb] = v;
+      if (xa) q[yb + xa] = v;
+      if (xb) q[yb + xb] = v;
+    }
+  };
+  plane(p0, val);
+  if (za) plane(p0 + za, zs * val);
+  if (zb) plane(p0 + zb, zs * val);
 }
 
-inline Dims make_dims(int nx, int ny, int nz, int zb) {
+inline Dims make_dims(int nx, int ny, int nz, int zb, int h) {
   Dims d;
   d.nx = nx; d.ny = ny; d.nz = nz;
-  d.px = nx + 2 * H; d.py = ny + 2 * H; d.pz = nz + 2 * H;
+  d.h = h;
+  d.px = nx + 2 * h; d.py = ny + 2 * h; d.pz = nz + 2 * h;
   d.sy = d.px; d.sz = (long)d.px * d.py;
   d.zb = zb;
   return d;
@@ -298,9 +321,10 @@ void set_error(const char* fmt, ...);
 template <class T>
 hipError_t launch_halo_fill(const Dims& d, T* const* fields, const int* kinds, int nf,
                             hipStream_t s);
+// Fused tendency (+ RK3 combine) of one model; advection is OC_ADV_*.
 template <class T>
 hipError_t launch_tendency_fast(const Dims& d, const FieldSet<T>& fs, const TendParams<T>& p,
-                                int scheme, hipStream_t s);
+                                int advection, hipStream_t s);
 // Spacings of the pressure passes: rdzc (nz) and rdzf (nz + 1) are device
 // tables of 1/dzc_k and 1/dzf_k as in TendParams.
 struct Spacing {

@@ -26,7 +26,7 @@ __global__ void __launch_bounds__(256) halo_fill_kernel(Dims d, HaloArgs<T> a, l
   const int pi = (int)(t % d.px);
   const int pj = (int)((t / d.px) % d.py);
   const int pk = (int)(t / ((long)d.px * d.py));
-  int i = pi - H, j = pj - H, k = pk - H;
+  int i = pi - d.h, j = pj - d.h, k = pk - d.h;
   const bool inx = (i >= 0 && i < d.nx), iny = (j >= 0 && j < d.ny);
   const int kind = a.kind[fld];
   bool inz;

@@ -151,19 +151,31 @@ __global__ void __launch_bounds__(64 * VCH) vimplicit_kernel(Dims d, VImplicitAr
   if (!valid) return;
 #pragma unroll
   for (int r = 0; r < VCMAX; ++r) x[r] += Q[min(q0 + r, n - 1)] * xin;
-  // plain stores, plus the periodic x / y images of the three columns next
-  // to each side (per-lane offsets; masked off everywhere else)
-  const long oxi = (i < H) ? d.nx : (i >= d.nx - H ? -(long)d.nx : 0);
-  const long oyi = (j < H) ? (long)d.ny * d.sy : (j >= d.ny - H ? -(long)d.ny * d.sy : 0);
+  // plain stores, plus the periodic x / y images of the h columns next to
+  // each side (per-lane offsets, masked off everywhere else; a column of an
+  // axis shorter than 2H has an image at both ends)
+  const long sy = d.sy;
+  const int H = d.h;
+  const long oxa = (i < H) ? d.nx : 0, oxb = (i >= d.nx - H) ? -(long)d.nx : 0;
+  const long oya = (j < H) ? d.ny * sy : 0, oyb = (j >= d.ny - H) ? -(long)d.ny * sy : 0;
 #pragma unroll
   for (int r = 0; r < VCMAX; ++r) {
     const int q = q0 + r;
     if (q < q1) {
       T* p = base + (long)q * sz;
       p[0] = x[r];
-      if (oxi) p[oxi] = x[r];
-      if (oyi) p[oyi] = x[r];
-      if (oxi && oyi) p[oxi + oyi] = x[r];
+      if (oxa) p[oxa] = x[r];
+      if (oxb) p[oxb] = x[r];
+      if (oya) {
+        p[oya] = x[r];
+        if (oxa) p[oya + oxa] = x[r];
+        if (oxb) p[oya + oxb] = x[r];
+      }
+      if (oyb) {
+        p[oyb] = x[r];
+        if (oxa) p[oyb + oxa] = x[r];
+        if (oxb) p[oyb + oxb] = x[r];
+      }
     }
   }
   // the mirror images of the levels next to the walls (first and last

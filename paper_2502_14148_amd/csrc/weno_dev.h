@@ -1,11 +1,14 @@
 // Device helpers shared by the tendency kernels: reciprocal, the centred
-// fourth-order interpolation and the five-point WENO reconstructions
+// interpolations of the advecting velocity and the WENO reconstructions of
+// orders 5, 7 and 9
 // (finite-volume appendix of arXiv 2502.14148: upwind-biased WENO5 with the
 // WENO-Z weights of Borges et al. 2008, q = 2; Jiang & Shu 1996 candidate
 // stencils and smoothness indicators).
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include "weno_coeffs.h"
 
 namespace oc {
 namespace tz {
@@ -54,6 +57,81 @@ __device__ inline T rec6(T m3, T m2, T m1, T p0, T p1, T p2, T vel, T eps) {
   const T w1 = T(0.6) * (T(1) + q1 * q1);
   const T w2 = T(0.3) * (T(1) + q2 * q2);
   return (w0 * r0 + w1 * r1 + w2 * r2) * rcp(T(6) * (w0 + w1 + w2));
+}
+
+// Centred reconstruction of order 2R - 2 at the midpoint of a[R-2] and
+// a[R-1] from a[0 .. 2R-3] (order 4: interp4).
+template <class T, int R>
+__device__ inline T interpc(const T* a) {
+  if constexpr (R == 3) {
+    return interp4(a[0], a[1], a[2], a[3]);
+  } else {
+    using C = WenoCoef<R>;
+    T s = T(0);
+#pragma unroll
+    for (int o = 0; o < R - 1; ++o) s += T(C::centred[o]) * (a[o] + a[2 * R - 3 - o]);
+    return s;
+  }
+}
+
+// Reconstruction of order 2R - 1 (R = 4, 5) at the interface between q[R-1]
+// and q[R] from q[0 .. 2R-1]; `vel` selects the upwind side.  Every
+// combination is taken on deviations from the upwind neighbour of the
+// interface, and the indicators on differences of neighbouring values, so
+// that a large mean of the data does not cost precision.
+template <class T, int SCHEME, int R>
+__device__ inline T recw(const T* q, T vel, T eps) {
+  using C = WenoCoef<R>;
+  constexpr int N = 2 * R - 1;
+  const bool pos = vel > T(0);
+  T v[N];
+#pragma unroll
+  for (int t = 0; t < N; ++t) v[t] = pos ? q[t] : q[2 * R - 1 - t];
+  const T base = v[R - 1];
+  T dv[N];
+#pragma unroll
+  for (int t = 0; t < N; ++t) dv[t] = v[t] - base;
+  if constexpr (SCHEME == SCHEME_LINEAR) {
+    T s = T(0);
+#pragma unroll
+    for (int t = 0; t < N; ++t)
+      if (t != R - 1) s += T(C::full[t]) * dv[t];
+    return base + s;
+  } else {
+    T dl[N - 1];
+#pragma unroll
+    for (int t = 0; t < N - 1; ++t) dl[t] = v[t + 1] - v[t];
+    T beta[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      T b = T(0);
+#pragma unroll
+      for (int m = 0; m < R - 1; ++m) {
+        T y = dl[k + m];
+#pragma unroll
+        for (int t = m + 1; t < R - 1; ++t) y += T(C::Lt[k][m][t]) * dl[k + t];
+        b += T(C::D[k][m]) * y * y;
+      }
+      beta[k] = b;
+    }
+    T tau = T(0);
+#pragma unroll
+    for (int k = 0; k < R; ++k) tau += T(C::tau[k]) * beta[k];
+    tau = fabs(tau);
+    T num = T(0), den = T(0);
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      T rk = T(0);
+#pragma unroll
+      for (int t = 0; t < R; ++t)
+        if (k + t != R - 1) rk += T(C::cand[k][t]) * dv[k + t];
+      const T qk = tau * rcp(beta[k] + eps);
+      const T a = T(C::ideal[k]) * (T(1) + qk * qk);
+      num += a * rk;
+      den += a;
+    }
+    return base + num * rcp(den);
+  }
 }
 
 }  // namespace tz

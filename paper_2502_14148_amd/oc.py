@@ -20,7 +20,8 @@ OC_RECTILINEAR, OC_LATLON = 0, 1
 OC_NONHYDROSTATIC, OC_HYDROSTATIC = 0, 1
 BARO_FIELDS = {"eta": 16, "U": 17, "V": 18, "GU": 19, "GV": 20, "tau_x": 21, "tau_y": 22}
 OC_FP64, OC_FP32_MIXED = 0, 1
-ADVECTION = {"none": 0, "weno5z": 1, "weno5_linear": 2}
+ADVECTION = {"none": 0, "weno5z": 1, "weno5_linear": 2, "weno7z": 3, "weno7_linear": 4,
+             "weno9z": 5, "weno9_linear": 6}
 OC_F32, OC_F64 = 0, 1
 OC_MAX_TRACERS = 4
 OC_NDIAG = 8

@@ -176,3 +176,40 @@ def test_les_validation():
     md.les_c, md.closure = 1.0 / 12.0, 1
     assert lib.oc_model_workspace_size(g, ctypes.byref(md), ctypes.byref(nbytes)) == -5
     assert lib.oc_grid_destroy(g) == 0
+
+
+def test_weno_order_validation():
+    """WENO7/9 widen the halo (the workspace grows); the hydrostatic model
+    takes WENO5 only; unknown schemes are refused."""
+    lib = oc.load_library()
+    g = ctypes.c_void_p()
+    gd = oc.GridDesc(32, 32, 16, oc.OC_BOUNDED, 0, 64, 0, 64, -16, 16, oc.OC_RECTILINEAR, 0.0)
+    assert lib.oc_grid_create(ctypes.byref(gd), ctypes.byref(g)) == 0
+    md = oc.ModelDesc()
+    md.precision, md.weno_eps, md.weno_q = oc.OC_FP32_MIXED, 1e-15, 2
+    md.ntracers, md.buoyancy = 2, 1
+    sizes = {}
+    for name in ("weno5z", "weno7z", "weno7_linear", "weno9z", "weno9_linear"):
+        md.advection = oc.ADVECTION[name]
+        n = ctypes.c_uint64()
+        assert lib.oc_model_workspace_size(g, ctypes.byref(md), ctypes.byref(n)) == 0, name
+        sizes[name] = n.value
+    assert sizes["weno5z"] < sizes["weno7z"] == sizes["weno7_linear"] < sizes["weno9z"]
+    md.advection = 7
+    n = ctypes.c_uint64()
+    assert lib.oc_model_workspace_size(g, ctypes.byref(md), ctypes.byref(n)) == -1
+    md.advection, md.weno_q = oc.ADVECTION["weno9z"], 3
+    assert lib.oc_model_workspace_size(g, ctypes.byref(md), ctypes.byref(n)) == -5
+    assert lib.oc_grid_destroy(g) == 0
+    gl = ctypes.c_void_p()
+    gdl = oc.GridDesc(64, 32, 8, oc.OC_BOUNDED, 0, 64, -40, 80, -3000, 3000, oc.OC_LATLON,
+                      6.371e6)
+    assert lib.oc_grid_create(ctypes.byref(gdl), ctypes.byref(gl)) == 0
+    mh = oc.ModelDesc()
+    mh.kind, mh.precision, mh.weno_eps, mh.weno_q = oc.OC_HYDROSTATIC, oc.OC_FP32_MIXED, 1e-15, 2
+    mh.ntracers, mh.buoyancy, mh.depth = 2, 1, 3000.0
+    mh.advection = oc.ADVECTION["weno5z"]
+    assert lib.oc_model_workspace_size(gl, ctypes.byref(mh), ctypes.byref(n)) == 0
+    mh.advection = oc.ADVECTION["weno7z"]
+    assert lib.oc_model_workspace_size(gl, ctypes.byref(mh), ctypes.byref(n)) == -5
+    assert lib.oc_grid_destroy(gl) == 0
