@@ -38,17 +38,47 @@ FLOPS_PER_CELL_STAGE = {
     "rk3_combine": 5 * 4,
     "tracer_offset": 2 * 7,
 }
+
+
+def weno_flux_flops(r):
+    """One WENO-Z face flux of order 2r - 1 (r = 4, 5) as the kernel forms it:
+    2r - 2 deviations and 2r - 2 differences, r indicators of r - 1 squares
+    ((r - 1)(r + 1) each), tau 2r, r candidates of r - 1 products 2(r - 1),
+    weights 9 per candidate, normalisation 3, U * W 1."""
+    return (4 * r - 4) + r * (r - 1) * (r + 1) + 2 * r + 2 * r * (r - 1) + 9 * r + 3 + 1
+
+
+def flops_per_cell_stage(r):
+    """FLOPS_PER_CELL_STAGE for stencil radius r (3: WENO5, 4: WENO7, 5: WENO9);
+    the advecting velocity of order 2r - 2 costs 3r - 4."""
+    if r == 3:
+        return dict(FLOPS_PER_CELL_STAGE)
+    out = dict(FLOPS_PER_CELL_STAGE)
+    del out["weno5z_flux"]
+    out[f"weno{2 * r - 1}z_flux"] = 15 * weno_flux_flops(r)
+    out["advecting_velocity"] = 9 * (3 * r - 4)
+    return out
 COUNTERS = os.path.join(ROOT, "profiles", "tendency_rk3_fp32_256cubed_counters.json")
-TENDENCY_SRC = os.path.join(ROOT, "paper_2502_14148_amd", "csrc", "tendency.hip")
+# the sources the WENO5 tendency kernel is compiled from
+TENDENCY_SRC = [os.path.join(ROOT, "paper_2502_14148_amd", "csrc", f)
+                for f in ("tendency.hip", "tendency_tile.h", "weno_dev.h", "weno_coeffs.h",
+                          "oc_internal.h")]
+
+
+def tendency_source_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in TENDENCY_SRC:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
 
 
 def measured_traffic():
     """HBM bytes per tendency launch from the committed rocprofv3 counter
-    record, or None if the kernel source changed since it was taken."""
-    import hashlib
+    record, or None if the kernel sources changed since it was taken."""
     try:
         rec = json.load(open(COUNTERS))
-        src = hashlib.sha256(open(TENDENCY_SRC, "rb").read()).hexdigest()
+        src = tendency_source_sha256()
     except (OSError, ValueError):
         return None
     return rec["traffic_bytes_per_launch"] if rec.get("source_sha256") == src else None
@@ -293,6 +323,45 @@ def run_les(steps, warmup, n):
     return out
 
 
+def run_weno_high(steps, warmup, n):
+    """The 256^3 free-convection step with WENO7-Z and WENO9-Z advection (the
+    paper's choice for LES and its global-ocean runs): the same physics and
+    initial state as the headline line; the tendency kernel's ALU roofline
+    with the flops of the wider reconstructions."""
+    from paper_2502_14148_amd import inputs
+    ph = inputs.convection_physics((n, n, n), (2.0 * n, 2.0 * n, 1.0 * n))
+    print(f"# generating the {n}^3 initial state (WENO7/9 runs)", file=sys.stderr, flush=True)
+    s = inputs.convection_initial(ph, seed=0)
+    ncells = n ** 3
+    out = {}
+    for scheme, r in (("weno7z", 4), ("weno9z", 5)):
+        ph.advection = scheme
+        print(f"# {scheme} {n}^3 run", file=sys.stderr, flush=True)
+        ms, _, prof, diag = run_gpu(ph, s, "fp32", steps, warmup)
+        t, c = prof["tendency"]
+        t_launch = t / 1e3 / c
+        flops = sum(flops_per_cell_stage(r).values()) * ncells
+        tf = flops / t_launch / 1e12
+        tbytes = algorithmic_tendency_bytes(ncells, 5, 4, steps) / c
+        gbs = tbytes / t_launch / 1e9
+        out[scheme] = {"value": ncells * steps / (ms / 1e3), "unit": "cell-steps/s",
+                       "ms_per_step": ms / steps,
+                       "kernels_ms_per_step": {k: v[0] / steps for k, v in prof.items() if v[1]},
+                       "tendency_roofline": {
+                           "bound": "alu", "achieved": round(tf, 2),
+                           "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                           "frac": round(tf / FP32_VALU_PEAK_TFLOPS, 4),
+                           "avg_launch_ms": t_launch * 1e3,
+                           "algorithmic_flops_per_launch": flops,
+                           "hbm": {"achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                                   "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4)}},
+                       "final_max_w": diag["max_w"]}
+    out["config"] = {"workload": f"free-convection LES {n}^3 (as the headline line) with "
+                                 f"WENO7-Z / WENO9-Z advection, FP32", "dt_s": 1.0,
+                     "steps": steps, "warmup": warmup, "dtype": "f32"}
+    return out
+
+
 MLP_FLOPS_PER_ROW = 2 * (500 * 256 + 256 * 256 + 256 * 4)   # forward, one cell
 BF16_PEAK_TFLOPS = 2500.0      # MI355X dense BF16 MFMA
 
@@ -445,6 +514,7 @@ def main():
     ap.add_argument("--no-closure", action="store_true")
     ap.add_argument("--no-stretched", action="store_true")
     ap.add_argument("--no-les", action="store_true")
+    ap.add_argument("--no-weno-high", action="store_true")
     ap.add_argument("--no-main", action="store_true",
                     help="skip the 256^3 step (profiling the other legs alone)")
     ap.add_argument("--ensemble-steps", type=int, default=20)
@@ -479,6 +549,9 @@ def main():
     if not a.no_les:
         print("# LES closure runs", file=sys.stderr, flush=True)
         out["les"] = run_les(a.steps, a.warmup, a.n)
+    if not a.no_weno_high:
+        print("# WENO7/9 runs", file=sys.stderr, flush=True)
+        out["weno_high"] = run_weno_high(a.steps, a.warmup, a.n)
     if not a.no_closure:
         print("# closure network", file=sys.stderr, flush=True)
         out["closure_mlp"] = run_closure_mlp()

@@ -434,7 +434,7 @@ __device__ __attribute__((always_inline)) inline void tendency_tile(
 // reconstructions need more registers than WENO5's.
 template <class T, int R>
 struct TendWaves {
-  static constexpr int value = sizeof(T) == 8 ? 2 : (R == 3 ? OC_TEND_WAVES : 2);
+  static constexpr int value = sizeof(T) == 8 ? 2 : (R == 3 ? OC_TEND_WAVES : 3);
 };
 
 // One model; tiles are mapped XCD-major, so neighbouring tiles (which share

@@ -79,6 +79,15 @@ __device__ inline T interpc(const T* a) {
 // combination is taken on deviations from the upwind neighbour of the
 // interface, and the indicators on differences of neighbouring values, so
 // that a large mean of the data does not cost precision.
+// A value the optimiser cannot trace back to the load that produced it: a
+// choice between two elements of a register array stays a choice between
+// two values instead of becoming a dynamically indexed array access.
+template <class T>
+__device__ inline T opaque(T x) {
+  asm("" : "+v"(x));
+  return x;
+}
+
 template <class T, int SCHEME, int R>
 __device__ inline T recw(const T* q, T vel, T eps) {
   using C = WenoCoef<R>;
@@ -86,7 +95,10 @@ __device__ inline T recw(const T* q, T vel, T eps) {
   const bool pos = vel > T(0);
   T v[N];
 #pragma unroll
-  for (int t = 0; t < N; ++t) v[t] = pos ? q[t] : q[2 * R - 1 - t];
+  for (int t = 0; t < N; ++t) {
+    const T a = opaque(q[t]), b = opaque(q[2 * R - 1 - t]);
+    v[t] = pos ? a : b;
+  }
   const T base = v[R - 1];
   T dv[N];
 #pragma unroll
