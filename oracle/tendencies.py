@@ -17,7 +17,10 @@ Readings where the paper is silent:
 * buoyancy b = g (alpha (T - T0) - beta (S - S0)) enters G_w averaged to
   the w faces;
 * walls are impenetrable, free-slip and no-flux except for the prescribed
-  top tracer flux (upward positive).
+  top tracer flux (upward positive);
+* immersed cells (grid-fitted boundary, oracle/immersed.py) close their
+  faces: zero velocity and velocity tendency there, no diffusive tracer flux
+  through them, no top flux into an immersed top cell.
 
 Vertically stretched grids (unevenly spaced z faces, staggered-grid listing
 of the finite-volume appendix): flux divergences divide the z difference of
@@ -35,6 +38,7 @@ is bounded (wall faces hold 0).
 """
 import numpy as np
 
+from . import immersed
 from .fv import view, z_spacings
 from .weno import RADIUS, centred, reconstruct
 
@@ -101,22 +105,37 @@ def tracer_tendency(c, s, ph, top_flux=0.0):
     dzc, dzf, _ = _zgrid(ph)
     k = ph.kappa
     kz = _zdiff(ph, k)
+    ox, oy, oz = _open(ph)
     # x faces i = 0..nx
     U = view(u, ni=nx + 1, ph=ph)
     Fx = U * _rec(ph, [view(c, di=o, ni=nx + 1, ph=ph) for o in _offsets(ph)], U)
-    Fx = Fx - k * (view(c, ni=nx + 1, ph=ph) - view(c, di=-1, ni=nx + 1, ph=ph)) / dx
+    Fx = Fx - ox * k * (view(c, ni=nx + 1, ph=ph) - view(c, di=-1, ni=nx + 1, ph=ph)) / dx
     # y faces j = 0..ny
     V = view(v, nj=ny + 1, ph=ph)
     Fy = V * _rec(ph, [view(c, dj=o, nj=ny + 1, ph=ph) for o in _offsets(ph)], V)
-    Fy = Fy - k * (view(c, nj=ny + 1, ph=ph) - view(c, dj=-1, nj=ny + 1, ph=ph)) / dy
+    Fy = Fy - oy * k * (view(c, nj=ny + 1, ph=ph) - view(c, dj=-1, nj=ny + 1, ph=ph)) / dy
     # z faces k = 0..nz
     W = view(w, nk=nz + 1, ph=ph)
     Fz = W * _rec(ph, [view(c, dk=o, nk=nz + 1, ph=ph) for o in _offsets(ph)], W)
-    Fz = Fz - kz * (view(c, nk=nz + 1, ph=ph) - view(c, dk=-1, nk=nz + 1, ph=ph)) / dzf
+    Fz = Fz - oz * kz * (view(c, nk=nz + 1, ph=ph) - view(c, dk=-1, nk=nz + 1, ph=ph)) / dzf
     if ph.z_bounded:
         Fz[0] = 0.0           # bottom wall: no flux
-        Fz[nz] = top_flux     # top wall: prescribed upward flux
+        # top wall: prescribed upward flux (into fluid top cells only)
+        Fz[nz] = top_flux * immersed.fluid(ph)[nz - 1] if immersed.has_immersed(ph) else top_flux
     return -_div(Fx, Fy, Fz, ph, dzc)
+
+
+def _open(ph):
+    """Open flags of the x, y, z faces with one extra entry along each
+    axis (1 everywhere without immersed cells)."""
+    if not immersed.has_immersed(ph):
+        return 1.0, 1.0, 1.0
+    ox, oy, oz = immersed.open_faces(ph)
+    ox = np.concatenate([ox, ox[:, :, :1]], axis=2)
+    oy = np.concatenate([oy, oy[:, :1, :]], axis=1)
+    if not ph.z_bounded:
+        oz = np.concatenate([oz, oz[:1]], axis=0)
+    return ox, oy, oz
 
 
 def u_tendency(s, ph):
@@ -224,6 +243,9 @@ def tendencies(s, ph):
     """All tendencies of the prognostic fields of a padded state dict, with
     the eddy-viscosity LES closure's contribution when one is configured."""
     G = {"u": u_tendency(s, ph), "v": v_tendency(s, ph), "w": w_tendency(s, ph)}
+    if immersed.has_immersed(ph):
+        # velocities on closed faces do not change
+        G["u"], G["v"], G["w"] = immersed.mask_velocities(G["u"], G["v"], G["w"], ph)
     for name in ph.tracers:
         G[name] = tracer_tendency(s[name], s, ph, ph.top_flux.get(name, 0.0))
     kind = getattr(ph, "les", "none")

@@ -13,6 +13,7 @@ from .fv import to_padded, interior, w_faces
 from .tendencies import tendencies
 from .pressure import project
 from .implicit import implicit_diffusion
+from . import immersed
 
 GAMMA = (8.0 / 15.0, 5.0 / 12.0, 3.0 / 4.0)
 ZETA = (0.0, 17.0 / 60.0, 5.0 / 12.0)
@@ -23,8 +24,12 @@ def fields_of(ph):
 
 
 def make_state(interiors, ph):
-    """Padded state dict (halos filled) from interior arrays."""
-    return {n: to_padded(interiors[n], ph, n) for n in fields_of(ph)}
+    """Padded state dict (halos filled) from interior arrays; with immersed
+    cells the velocities on closed faces are set to zero first."""
+    it = dict(interiors)
+    if immersed.has_immersed(ph):
+        it["u"], it["v"], it["w"] = immersed.mask_velocities(it["u"], it["v"], it["w"], ph)
+    return {n: to_padded(it[n], ph, n) for n in fields_of(ph)}
 
 
 def state_interior(state, ph):
@@ -47,7 +52,8 @@ def rk3_substage(state, G_prev, m, dt, ph, project_velocity=True):
             new[n] = implicit_diffusion(n, new[n], ph, dt_eff)
     p = None
     if project_velocity:
-        new["u"], new["v"], new["w"], p = project(new["u"], new["v"], new["w"], dt_eff, ph)
+        proj = immersed.project_immersed if immersed.has_immersed(ph) else project
+        new["u"], new["v"], new["w"], p = proj(new["u"], new["v"], new["w"], dt_eff, ph)
     return make_state(new, ph), G, p
 
 

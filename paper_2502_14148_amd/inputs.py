@@ -60,6 +60,9 @@ class Physics:
     les_cb: float = 1.0                 # Lilly stratification coefficient C_b
     les_pr: float = 1.0                 # turbulent Prandtl number
     les_camd: float = 1.0 / 12.0        # AMD constant C
+    solid: object = None                # (nz, ny, nx) bool: immersed cells (None: none)
+    cg_tol: float = 1e-13               # relative residual of the immersed pressure solve
+    cg_maxiter: int = 200
 
     def as_dict(self):
         return asdict(self)
@@ -138,6 +141,40 @@ def stretched_convection_physics(n=(256, 256, 256), extent=(512.0, 512.0, 256.0)
 # ---------------------------------------------------------------------------
 # Random velocity fields that are discretely divergence-free by construction
 # ---------------------------------------------------------------------------
+
+def grid_fitted_bottom(ph: Physics, height) -> np.ndarray:
+    """Immersed cells of a bottom at z0 + height(x, y) (grid-fitted: a cell is
+    immersed when its centre lies below the bottom).  `height` takes the
+    (ny, nx) arrays of cell-centre x and y."""
+    dx, dy, _ = ph.spacing
+    xc = ph.x0 + (np.arange(ph.nx) + 0.5) * dx
+    yc = ph.y0 + (np.arange(ph.ny) + 0.5) * dy
+    X, Y = np.meshgrid(xc, yc)
+    zc = cell_centres_z(ph)
+    return zc[:, None, None] < ph.z0 + np.asarray(height(X, Y))[None, :, :]
+
+
+def seamount(ph: Physics, height_frac: float = 0.4, width_frac: float = 0.15,
+             centre=(0.5, 0.5)) -> np.ndarray:
+    """A Gaussian seamount of height height_frac * lz and e-folding width
+    width_frac * lx, centred at `centre` (fractions of the extents)."""
+    x0 = ph.x0 + centre[0] * ph.lx
+    y0 = ph.y0 + centre[1] * ph.ly
+    sig = width_frac * ph.lx
+    return grid_fitted_bottom(
+        ph, lambda X, Y: height_frac * ph.lz * np.exp(-((X - x0) ** 2 + (Y - y0) ** 2)
+                                                      / (2.0 * sig ** 2)))
+
+
+def seamount_convection_physics(n=(256, 256, 256), extent=(512.0, 512.0, 256.0),
+                                height_frac: float = 0.4, width_frac: float = 0.15,
+                                **kw) -> Physics:
+    """The free-convection workload over a Gaussian seamount (immersed
+    grid-fitted bottom)."""
+    ph = convection_physics(n, extent, **kw)
+    ph.solid = seamount(ph, height_frac, width_frac)
+    return ph
+
 
 def _curl_of_potential(ax, ay, az, dx, dy, dz, bounded):
     """Staggered curl of an edge-centred vector potential.
