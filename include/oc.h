@@ -168,6 +168,25 @@ typedef struct {
   double les_cb;            /* Smagorinsky-Lilly: C_b of the stratification
                                factor (>= 0; N^2 from the T, S buoyancy) */
   double les_pr;            /* Smagorinsky-Lilly: turbulent Prandtl number (> 0) */
+  int32_t immersed;         /* OC_NONHYDROSTATIC on a uniform rectilinear grid:
+                               1 reserves a grid-fitted immersed boundary
+                               (immersed-boundary grid of the paper's examples;
+                               set the immersed cells with oc_set_immersed).
+                               Faces next to an immersed cell are closed: zero
+                               velocity and velocity tendency, no diffusive
+                               tracer flux, no top flux into an immersed top
+                               cell.  The pressure then solves the Poisson
+                               equation on the fluid cells with no flux through
+                               closed faces by conjugate gradients
+                               preconditioned with the FFT solver of the whole
+                               box applied to the masked residual (pressure
+                               solver for irregular domains of the
+                               pressure-correction appendix); gauge: zero mean
+                               over the fluid cells.  WENO5 or no advection; not
+                               with implicit_z, les or closure */
+  double cg_tol;            /* immersed: relative residual at which the
+                               iteration stops (> 0, e.g. 1e-13 in FP64) */
+  int32_t cg_maxiter;       /* immersed: at most this many iterations (1..10000) */
 } oc_model_desc;
 
 typedef struct oc_grid oc_grid;
@@ -240,6 +259,23 @@ int oc_rk3_step(oc_model* m, double dt, int32_t nsteps, void* stream);
  * OC_ERR_UNSUPPORTED. */
 int oc_implicit_vertical_diffusion(oc_model* m, double dt_eff, void* stream);
 
+/* Immersed cells of a model created with immersed = 1 (grid-fitted
+ * immersed boundary; see oc_model_desc.immersed).  solid: HOST array of
+ * nz * ny * nx bytes, x fastest, nonzero = immersed (the library copies it;
+ * the caller keeps ownership).  All cells are fluid until the first call.
+ * The call also zeroes the velocities of the current state on the faces it
+ * closes and refills their halos; so does every later oc_set_state of u, v
+ * or w on such a model.  Synchronous with respect to the host.
+ * Errors: OC_ERR_ARG (NULL arguments), OC_ERR_UNSUPPORTED (immersed = 0, or
+ * no fluid cell left). */
+int oc_set_immersed(oc_model* m, const uint8_t* solid, void* stream);
+
+/* Conjugate-gradient statistics of the last pressure solve of an immersed
+ * model: iterations taken and the final relative residual |r| / |b| (host
+ * outputs; synchronises the stream).  Errors: OC_ERR_ARG, OC_ERR_UNSUPPORTED
+ * (immersed = 0). */
+int oc_pressure_stats(oc_model* m, int32_t* iterations, double* rel_residual, void* stream);
+
 /* Per-kernel-class timing with HIP events recorded on the model's stream
  * around every launch (classes: OC_PROF_*).  oc_profile(m, 1) clears the
  * counters and starts recording, oc_profile(m, 0) stops.  oc_profile_read
@@ -249,9 +285,9 @@ enum {
   OC_PROF_TENDENCY = 0, OC_PROF_FFT_X_FWD = 1, OC_PROF_FFT_Y_FWD = 2, OC_PROF_Z_SOLVE = 3,
   OC_PROF_FFT_Y_INV = 4, OC_PROF_FFT_X_INV = 5, OC_PROF_PROJECT = 6, OC_PROF_HALO = 7,
   OC_PROF_CLOSURE = 8, OC_PROF_HYDRO_DIAG = 9, OC_PROF_HYDRO_TEND = 10, OC_PROF_BAROTROPIC = 11,
-  OC_PROF_IMPLICIT_Z = 12, OC_PROF_LES = 13
+  OC_PROF_IMPLICIT_Z = 12, OC_PROF_LES = 13, OC_PROF_CG = 14
 };
-#define OC_NPROF 14
+#define OC_NPROF 15
 int oc_profile(oc_model* m, int32_t enable);
 int oc_profile_read(oc_model* m, double* ms, int64_t* launches);
 

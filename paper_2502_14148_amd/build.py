@@ -29,7 +29,7 @@ FLAGS = [
 SOURCES = ["tendency_r5.hip", "tendency_r4.hip", "tendency.hip",
            "api.hip", "stencil.hip", "poisson.hip", "barotropic.hip", "mlp.hip",
            "closure_api.hip", "hydrostatic.hip",
-           "ensemble_api.hip", "coarse.hip", "vertical.hip", "les.hip"]
+           "ensemble_api.hip", "coarse.hip", "vertical.hip", "les.hip", "immersed.hip"]
 
 
 def _compile(src, defines=(), build_dir=None):

@@ -47,6 +47,7 @@ struct Layout {
   uint64_t baro[13], metric, hzeta, hpx, hpy, hmet;
   uint64_t gc[MAXF];
   uint64_t les_nu, les_kap[OC_MAX_TRACERS], les_d2;
+  uint64_t mask, cg_x, cg_r, cg_q, cg_aq, cg_part, cg_scal;
   uint64_t zt64, ztT, vfac;
   uint64_t total;
 };
@@ -99,6 +100,16 @@ Layout make_layout(const oc_grid_desc& g, const oc_model_desc& m) {
     if (m.les == OC_LES_AMD)
       for (int q = 0; q < m.ntracers; ++q) { L.les_kap[q] = off; off += fb; }
     L.les_d2 = off; off += align256((uint64_t)g.nz * esz);
+  }
+  if (m.immersed) {
+    const uint64_t nv = align256((uint64_t)g.nx * g.ny * g.nz * 8);
+    L.mask = off; off += fb;
+    L.cg_x = off; off += nv;
+    L.cg_r = off; off += nv;
+    L.cg_q = off; off += nv;
+    L.cg_aq = off; off += nv;
+    L.cg_part = off; off += align256((uint64_t)IB_NPART * 8);
+    L.cg_scal = off; off += align256((uint64_t)CG_NSCAL * 8);
   }
   L.zt64 = off; off += align256((uint64_t)zt64_len(g.nz) * 8);
   L.ztT = off; off += align256((uint64_t)ztT_len(g.nz) * esz);
@@ -221,6 +232,23 @@ int validate_model(const oc_model_desc* m) {
     set_error("the hydrostatic model carries exactly T and S (ntracers = 2)");
     return OC_ERR_ARG;
   }
+  if (m->immersed != 0 && m->immersed != 1) {
+    set_error("immersed must be 0 or 1");
+    return OC_ERR_ARG;
+  }
+  if (m->immersed) {
+    if (!(m->cg_tol > 0) || !std::isfinite(m->cg_tol) || m->cg_maxiter < 1 ||
+        m->cg_maxiter > 10000) {
+      set_error("immersed boundary: cg_tol > 0 and 1 <= cg_maxiter <= 10000");
+      return OC_ERR_ARG;
+    }
+    if (m->kind != OC_NONHYDROSTATIC || m->advection > OC_ADV_WENO5_LINEAR || m->implicit_z ||
+        m->les || m->closure) {
+      set_error("an immersed boundary needs the nonhydrostatic model with WENO5 or no advection "
+                "and no implicit_z, LES or learned closure");
+      return OC_ERR_UNSUPPORTED;
+    }
+  }
   return OC_OK;
 }
 
@@ -243,6 +271,10 @@ int validate_pair(const oc_grid_desc& g, const oc_model_desc& m) {
   }
   if (m.closure && g.z_faces) {
     set_error("the learned closure needs a uniform z");
+    return OC_ERR_UNSUPPORTED;
+  }
+  if (m.immersed && g.z_faces) {
+    set_error("an immersed boundary needs a uniform z");
     return OC_ERR_UNSUPPORTED;
   }
   return OC_OK;
@@ -339,6 +371,30 @@ int halo_one(oc_model* m, int which, int field, hipStream_t s) {
 }
 
 
+// The immersed-boundary mask in the padded layout, state precision: 1 in
+// fluid cells, 0 in immersed ones (solid: nz * ny * nx bytes, nonzero =
+// immersed; NULL: all fluid), with periodic images in x, y (and a periodic
+// z) and mirror images below and above walls.
+std::vector<char> padded_mask(const oc_model* m, const uint8_t* solid) {
+  const Dims& d = m->dims;
+  std::vector<char> out((size_t)padded_elems(d) * m->esz);
+  for (int pk = 0; pk < d.pz; ++pk)
+    for (int pj = 0; pj < d.py; ++pj)
+      for (int pi = 0; pi < d.px; ++pi) {
+        const int i = ((pi - d.h) % d.nx + d.nx) % d.nx;
+        const int j = ((pj - d.h) % d.ny + d.ny) % d.ny;
+        int k = pk - d.h;
+        if (d.zb) k = (k < 0) ? -1 - k : (k >= d.nz ? 2 * d.nz - 1 - k : k);
+        else k = (k % d.nz + d.nz) % d.nz;
+        const bool imm = solid && solid[((size_t)k * d.ny + j) * d.nx + i] != 0;
+        const double v = imm ? 0.0 : 1.0;
+        const size_t at = (((size_t)pk * d.py + pj) * d.px + pi) * m->esz;
+        if (m->esz == 8) std::memcpy(&out[at], &v, 8);
+        else { const float f = (float)v; std::memcpy(&out[at], &f, 4); }
+      }
+  return out;
+}
+
 template <class T>
 int tendency_call(oc_model* m, int in, int out, int stage, double dt, int combine,
                   hipStream_t s) {
@@ -349,6 +405,7 @@ int tendency_call(oc_model* m, int in, int out, int stage, double dt, int combin
     fs.G[q] = (q < m->nf) ? (T*)m->G[q] : nullptr;
   }
   for (int q = 0; q < MAXF; ++q) fs.closure[q] = (m->net && q < 4) ? (const T*)m->gc[q] : nullptr;
+  fs.mask = m->md.immersed ? (const T*)m->mask : nullptr;
   if (m->net) {
     // learned closure of the current state: the fused gather + network, then
     // the flux divergence of its outputs
@@ -406,8 +463,105 @@ int tendency_call(oc_model* m, int in, int out, int stage, double dt, int combin
   return OC_OK;
 }
 
+// The FFT/DCT solve of the whole box applied to a dense FP64 field: sb.p =
+// L^-1 src (the preconditioner of the immersed-boundary iteration).
+int fft_solve_dense(oc_model* m, const double* src, hipStream_t s) {
+  {
+    ProfScope ps(m, OC_PROF_FFT_X_FWD, s);
+    OC_CHECK_HIP(launch_poisson_x_forward_dense(m->dims, src, m->sb, s));
+  }
+  {
+    ProfScope ps(m, OC_PROF_FFT_Y_FWD, s);
+    OC_CHECK_HIP(launch_poisson_y(m->dims, m->sb, -1, s));
+  }
+  {
+    ProfScope ps(m, OC_PROF_Z_SOLVE, s);
+    OC_CHECK_HIP(launch_poisson_spectral(m->dims, m->sb, s));
+  }
+  {
+    ProfScope ps(m, OC_PROF_FFT_Y_INV, s);
+    OC_CHECK_HIP(launch_poisson_y(m->dims, m->sb, 1, s));
+  }
+  {
+    ProfScope ps(m, OC_PROF_FFT_X_INV, s);
+    OC_CHECK_HIP(launch_poisson_x_inverse(m->dims, m->sb, s));
+  }
+  return OC_OK;
+}
+
+// Pressure correction with an immersed boundary: conjugate gradients on the
+// masked Poisson equation, preconditioned by the FFT solve of the whole box
+// (the residual is zero in immersed cells; the result is masked), until
+// |r| <= cg_tol |b| or cg_maxiter iterations.  The scalars of an iteration
+// stay on the device; the host reads the stop flag once per iteration.
+template <class T>
+int pressure_call_immersed(oc_model* m, int which, double dt_eff, hipStream_t s) {
+  T* u = (T*)m->state[which][0];
+  T* v = (T*)m->state[which][1];
+  T* w = (T*)m->state[which][2];
+  const T* mask = (const T*)m->mask;
+  const Dims& d = m->dims;
+  const CgBufs& cg = m->cg;
+  const double tol2 = m->md.cg_tol * m->md.cg_tol;
+  const int maxit = m->md.cg_maxiter;
+  const double* z = m->sb.p;
+  {
+    ProfScope pc(m, OC_PROF_CG, s);
+    OC_CHECK_HIP(launch_ib_rhs<T>(d, u, v, w, mask, 1.0 / dt_eff, 1.0 / m->dx, 1.0 / m->dy,
+                                  1.0 / m->dz, cg, s));
+    OC_CHECK_HIP(launch_ib_finalize(cg, CG_FIN_BNORM, tol2, maxit, s));
+  }
+  int rc = fft_solve_dense(m, cg.r, s);
+  if (rc) return rc;
+  {
+    ProfScope pc(m, OC_PROF_CG, s);
+    OC_CHECK_HIP(launch_ib_dot(d, cg, z, s));
+    OC_CHECK_HIP(launch_ib_finalize(cg, CG_FIN_RZ0, tol2, maxit, s));
+    OC_CHECK_HIP(launch_ib_dir<T>(d, mask, cg, z, s));
+  }
+  const double rdx2 = 1.0 / (m->dx * m->dx), rdy2 = 1.0 / (m->dy * m->dy);
+  const double rdz2 = 1.0 / (m->dz * m->dz);
+  for (int it = 0; it < maxit; ++it) {
+    {
+      ProfScope pc(m, OC_PROF_CG, s);
+      OC_CHECK_HIP(launch_ib_apply<T>(d, mask, rdx2, rdy2, rdz2, cg, s));
+      OC_CHECK_HIP(launch_ib_finalize(cg, CG_FIN_ALPHA, tol2, maxit, s));
+      OC_CHECK_HIP(launch_ib_update(d, cg, s));
+      OC_CHECK_HIP(launch_ib_finalize(cg, CG_FIN_RES, tol2, maxit, s));
+    }
+    OC_CHECK_HIP(hipMemcpyAsync(m->cg_host, cg.scal, CG_NSCAL * sizeof(double),
+                                hipMemcpyDeviceToHost, s));
+    OC_CHECK_HIP(hipStreamSynchronize(s));
+    if (m->cg_host[CG_DONE] != 0.0) break;
+    rc = fft_solve_dense(m, cg.r, s);
+    if (rc) return rc;
+    {
+      ProfScope pc(m, OC_PROF_CG, s);
+      OC_CHECK_HIP(launch_ib_dot(d, cg, z, s));
+      OC_CHECK_HIP(launch_ib_finalize(cg, CG_FIN_BETA, tol2, maxit, s));
+      OC_CHECK_HIP(launch_ib_dir<T>(d, mask, cg, z, s));
+    }
+  }
+  m->cg_iterations = (int)m->cg_host[CG_IT];
+  m->cg_residual = m->cg_host[CG_BNORM2] > 0
+                       ? std::sqrt(m->cg_host[CG_RNORM2] / m->cg_host[CG_BNORM2]) : 0.0;
+  Spacing sp{1.0 / m->dx, 1.0 / m->dy, m->zt64 + zt_rdzc(d.nz), m->zt64 + zt_rdzf(d.nz)};
+  {
+    ProfScope pc(m, OC_PROF_CG, s);
+    OC_CHECK_HIP(launch_ib_gauge<T>(d, mask, cg, m->nfluid, s));
+    OC_CHECK_HIP(hipMemcpyAsync(m->sb.p, cg.x, (size_t)d.nx * d.ny * d.nz * sizeof(double),
+                                hipMemcpyDeviceToDevice, s));
+  }
+  {
+    ProfScope ps(m, OC_PROF_PROJECT, s);
+    OC_CHECK_HIP(launch_project<T>(d, u, v, w, dt_eff, sp, cg.x, s, nullptr, 1, mask));
+  }
+  return OC_OK;
+}
+
 template <class T>
 int pressure_call(oc_model* m, int which, double dt_eff, hipStream_t s) {
+  if (m->md.immersed) return pressure_call_immersed<T>(m, which, dt_eff, s);
   const T* u = (const T*)m->state[which][0];
   const T* v = (const T*)m->state[which][1];
   const T* w = (const T*)m->state[which][2];
@@ -895,6 +1049,37 @@ int free_surface_call(oc_model* m, double dt, int N, int M, const double* a, hip
   return OC_OK;
 }
 
+// Zero the current velocities on closed faces and refill their halos.
+template <class T>
+int mask_velocities_call(oc_model* m, hipStream_t s) {
+  const int c = m->cur;
+  OC_CHECK_HIP(launch_ib_mask_velocity<T>(m->dims, (T*)m->state[c][0], (T*)m->state[c][1],
+                                          (T*)m->state[c][2], (const T*)m->mask, s));
+  for (int q = 0; q < 3; ++q) {
+    int rc = halo_one<T>(m, c, q, s);
+    if (rc) return rc;
+  }
+  return OC_OK;
+}
+
+template <class T>
+int set_immersed_call(oc_model* m, const uint8_t* solid, hipStream_t s) {
+  std::vector<char> host = padded_mask(m, solid);
+  const long n = (long)m->dims.nx * m->dims.ny * m->dims.nz;
+  long nfluid = 0;
+  for (long c = 0; c < n; ++c) nfluid += solid[c] == 0;
+  if (nfluid == 0) {
+    set_error("oc_set_immersed: no fluid cell left");
+    return OC_ERR_UNSUPPORTED;
+  }
+  OC_CHECK_HIP(hipMemcpyAsync(m->mask, host.data(), host.size(), hipMemcpyHostToDevice, s));
+  const int rc = mask_velocities_call<T>(m, s);
+  if (rc) return rc;
+  OC_CHECK_HIP(hipStreamSynchronize(s));  // the host copy of the mask goes out of scope
+  m->nfluid = (double)nfluid;
+  return OC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1030,6 +1215,17 @@ int oc_model_create(const oc_grid* g, const oc_model_desc* md, void* workspace,
                                                                    : nullptr;
     m->les_d2 = md->les ? (void*)(m->ws + L.les_d2) : nullptr;
   }
+  m->mask = md->immersed ? (void*)(m->ws + L.mask) : nullptr;
+  m->cg.x = (double*)(m->ws + L.cg_x);
+  m->cg.r = (double*)(m->ws + L.cg_r);
+  m->cg.q = (double*)(m->ws + L.cg_q);
+  m->cg.aq = (double*)(m->ws + L.cg_aq);
+  m->cg.part = (double*)(m->ws + L.cg_part);
+  m->cg.scal = (double*)(m->ws + L.cg_scal);
+  m->cg_host = nullptr;
+  m->cg_iterations = 0;
+  m->cg_residual = 0.0;
+  m->nfluid = (double)g->d.nx * g->d.ny * g->d.nz;
 
   hipError_t e = hipMemset(m->ws, 0, L.total);
   {
@@ -1071,8 +1267,16 @@ int oc_model_create(const oc_grid* g, const oc_model_desc* md, void* workspace,
     fill_hydro_metrics(g->d, md->omega, m->dims.h, hmet);
     if (e == hipSuccess) e = hipMemcpy(m->hmet, hmet.data(), hmet.size() * 8, hipMemcpyHostToDevice);
   }
+  if (md->immersed) {
+    // every cell fluid until oc_set_immersed; pinned host room for the
+    // iteration's scalars
+    std::vector<char> ones = padded_mask(m, nullptr);
+    if (e == hipSuccess) e = hipMemcpy(m->mask, ones.data(), ones.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&m->cg_host, CG_NSCAL * sizeof(double));
+  }
   if (e != hipSuccess) {
     set_error("model setup failed: %s", hipGetErrorString(e));
+    if (m->cg_host) (void)hipHostFree(m->cg_host);
     delete m;
     return OC_ERR_DEVICE;
   }
@@ -1083,6 +1287,7 @@ int oc_model_create(const oc_grid* g, const oc_model_desc* md, void* workspace,
 int oc_model_destroy(oc_model* m) {
   if (m) {
     for (hipEvent_t e : m->ev_pool) (void)hipEventDestroy(e);
+    if (m->cg_host) (void)hipHostFree(m->cg_host);
   }
   delete m;
   return OC_OK;
@@ -1152,6 +1357,8 @@ int oc_set_state(oc_model* m, int32_t field, const void* buf, int32_t dtype, int
     m->hfirst = 1;
     return OC_OK;
   }
+  if (m->md.immersed && field <= OC_W)  // no flow through closed faces
+    return (m->esz == 8) ? mask_velocities_call<double>(m, s) : mask_velocities_call<float>(m, s);
   return (m->esz == 8) ? halo_one<double>(m, m->cur, field, s) : halo_one<float>(m, m->cur, field, s);
 }
 
@@ -1235,6 +1442,28 @@ int oc_implicit_vertical_diffusion(oc_model* m, double dt_eff, void* stream) {
   if (rc) return rc;
   return (m->esz == 8) ? implicit_call<double>(m, m->cur, 0, s)
                        : implicit_call<float>(m, m->cur, 0, s);
+}
+
+int oc_set_immersed(oc_model* m, const uint8_t* solid, void* stream) {
+  if (!m || !solid) { set_error("NULL argument"); return OC_ERR_ARG; }
+  if (!m->md.immersed) {
+    set_error("the model was created without an immersed boundary (immersed = 0)");
+    return OC_ERR_UNSUPPORTED;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  return m->esz == 8 ? set_immersed_call<double>(m, solid, s) : set_immersed_call<float>(m, solid, s);
+}
+
+int oc_pressure_stats(oc_model* m, int32_t* iterations, double* rel_residual, void* stream) {
+  if (!m || !iterations || !rel_residual) { set_error("NULL argument"); return OC_ERR_ARG; }
+  if (!m->md.immersed) {
+    set_error("the model has no immersed boundary (no iterative solve)");
+    return OC_ERR_UNSUPPORTED;
+  }
+  OC_CHECK_HIP(hipStreamSynchronize((hipStream_t)stream));
+  *iterations = m->cg_iterations;
+  *rel_residual = m->cg_residual;
+  return OC_OK;
 }
 
 int oc_diagnostics(oc_model* m, double* out, void* stream) {

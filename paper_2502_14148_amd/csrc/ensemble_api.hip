@@ -85,9 +85,11 @@ int validate_members(oc_model* const* members, int count) {
     const oc_model* m = members[i];
     if (!m) { set_error("member %d is NULL", i); return OC_ERR_ARG; }
     if (m->kind != OC_NONHYDROSTATIC || m->md.advection != OC_ADV_WENO5Z ||
-        m->md.ntracers != 2 || m->net || m->stretched || m->md.implicit_z || m->md.les) {
+        m->md.ntracers != 2 || m->net || m->stretched || m->md.implicit_z || m->md.les ||
+        m->md.immersed) {
       set_error("member %d: ensembles take nonhydrostatic WENO5-Z models with tracers T, S, "
-                "uniform grids, explicit diffusion and no learned closure", i);
+                "uniform grids, explicit diffusion, no learned closure and no immersed "
+                "boundary", i);
       return OC_ERR_UNSUPPORTED;
     }
     if (m->esz != members[0]->esz) {
@@ -190,6 +192,7 @@ void fill_member_params(const oc_ensemble* e, std::vector<EnsMember<T>>& hm, dou
         fs.G[q] = (q < m->nf) ? (T*)m->G[q] : nullptr;
       }
       for (int q = 0; q < MAXF; ++q) fs.closure[q] = nullptr;
+      fs.mask = nullptr;
     }
     for (int st = 0; st < 3; ++st) {
       TendParams<T> p = tend_params<T>(m);

@@ -1,0 +1,344 @@
+// Grid-fitted immersed boundaries: the vector kernels of the preconditioned
+// conjugate-gradient pressure solve (pressure solver for irregular domains of
+// the pressure-correction appendix of arXiv 2502.14148) and the masking of
+// velocities on closed faces.
+//
+// The equation: on the fluid cells, the 7-point Laplacian with no flux
+// through faces next to an immersed cell (or a wall) equals div(u~)/dt_eff;
+// gauge: zero mean over the fluid cells.  The preconditioner is the FFT/DCT
+// solve of the whole box (poisson.hip) applied to the residual, which is zero
+// in immersed cells, with its result masked to the fluid.
+//
+// Vectors are dense FP64 (nz, ny, nx), x fastest.  Reductions are
+// deterministic: every reducing kernel runs a fixed grid of IB_NPART
+// workgroups over a fixed grid-stride partition, each writing one partial
+// sum, and a single-workgroup kernel adds the partials in a fixed order and
+// updates the iteration's scalars on the device (no host round trip inside
+// an iteration).
+#include "oc_internal.h"
+
+namespace oc {
+
+namespace {
+
+constexpr int IB_NT = 256;
+
+__device__ inline double block_sum(double v, double* sh) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+#pragma unroll
+  for (int s = IB_NT / 2; s > 0; s >>= 1) {
+    if (t < s) sh[t] += sh[t + s];
+    __syncthreads();
+  }
+  return sh[0];
+}
+
+__device__ inline void cell_of(const Dims& d, long n, int& i, int& j, int& k) {
+  i = (int)(n % d.nx);
+  const long r = n / d.nx;
+  j = (int)(r % d.ny);
+  k = (int)(r / d.ny);
+}
+
+// b = div(u~) / dt_eff in fluid cells (face velocities times their open
+// flags), 0 in immersed cells; r = b, x = 0; partial sums of b^2.
+template <class T>
+__global__ void __launch_bounds__(IB_NT) ib_rhs_kernel(Dims d, const T* __restrict__ u,
+                                                       const T* __restrict__ v,
+                                                       const T* __restrict__ w,
+                                                       const T* __restrict__ mask, double inv_dt,
+                                                       double rdx, double rdy, double rdz,
+                                                       CgBufs cg) {
+  __shared__ double sh[IB_NT];
+  const long N = (long)d.nx * d.ny * d.nz;
+  double acc = 0.0;
+  for (long n = blockIdx.x * (long)IB_NT + threadIdx.x; n < N; n += (long)gridDim.x * IB_NT) {
+    int i, j, k;
+    cell_of(d, n, i, j, k);
+    const long c = pidx(d, i, j, k);
+    const double m0 = (double)mask[c];
+    double b = 0.0;
+    if (m0 != 0.0) {
+      const long cx = pidx(d, (i + 1 == d.nx) ? 0 : i + 1, j, k);
+      const long cy = pidx(d, i, (j + 1 == d.ny) ? 0 : j + 1, k);
+      const double ul = (double)u[c] * (double)mask[c - 1];
+      const double ur = (double)u[cx] * (double)mask[cx] * (double)mask[cx - 1];
+      const double vl = (double)v[c] * (double)mask[c - d.sy];
+      const double vr = (double)v[cy] * (double)mask[cy] * (double)mask[cy - d.sy];
+      double wb, wt;
+      if (d.zb) {
+        wb = (k == 0) ? 0.0 : (double)w[c] * (double)mask[c - d.sz];
+        wt = (k + 1 == d.nz) ? 0.0 : (double)w[c + d.sz] * (double)mask[c + d.sz];
+      } else {
+        const long cz = pidx(d, i, j, (k + 1 == d.nz) ? 0 : k + 1);
+        wb = (double)w[c] * (double)mask[c - d.sz];
+        wt = (double)w[cz] * (double)mask[cz] * (double)mask[cz - d.sz];
+      }
+      b = ((ur - ul) * rdx + (vr - vl) * rdy + (wt - wb) * rdz) * inv_dt;
+    }
+    cg.r[n] = b;
+    cg.x[n] = 0.0;
+    acc += b * b;
+  }
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) cg.part[blockIdx.x] = s;
+}
+
+// aq = A q (the masked 7-point operator, zero in immersed cells); partial
+// sums of q . aq.
+template <class T>
+__global__ void __launch_bounds__(IB_NT) ib_apply_kernel(Dims d, const T* __restrict__ mask,
+                                                         double rdx2, double rdy2, double rdz2,
+                                                         CgBufs cg) {
+  __shared__ double sh[IB_NT];
+  if (cg.scal[CG_DONE] != 0.0) return;
+  const long N = (long)d.nx * d.ny * d.nz;
+  const long plane = (long)d.nx * d.ny;
+  const double* __restrict__ q = cg.q;
+  double acc = 0.0;
+  for (long n = blockIdx.x * (long)IB_NT + threadIdx.x; n < N; n += (long)gridDim.x * IB_NT) {
+    int i, j, k;
+    cell_of(d, n, i, j, k);
+    const long c = pidx(d, i, j, k);
+    double a = 0.0;
+    const double q0 = q[n];
+    if ((double)mask[c] != 0.0) {
+      const long nxm = (i == 0) ? n + d.nx - 1 : n - 1;
+      const long nxp = (i + 1 == d.nx) ? n - (d.nx - 1) : n + 1;
+      const long nym = (j == 0) ? n + plane - d.nx : n - d.nx;
+      const long nyp = (j + 1 == d.ny) ? n - plane + d.nx : n + d.nx;
+      a += (double)mask[c - 1] * (q[nxm] - q0) * rdx2;
+      a += (double)mask[c + 1] * (q[nxp] - q0) * rdx2;
+      a += (double)mask[c - d.sy] * (q[nym] - q0) * rdy2;
+      a += (double)mask[c + d.sy] * (q[nyp] - q0) * rdy2;
+      if (d.zb) {
+        if (k > 0) a += (double)mask[c - d.sz] * (q[n - plane] - q0) * rdz2;
+        if (k + 1 < d.nz) a += (double)mask[c + d.sz] * (q[n + plane] - q0) * rdz2;
+      } else {
+        const long nzm = (k == 0) ? n + (long)(d.nz - 1) * plane : n - plane;
+        const long nzp = (k + 1 == d.nz) ? n - (long)(d.nz - 1) * plane : n + plane;
+        a += (double)mask[c - d.sz] * (q[nzm] - q0) * rdz2;
+        a += (double)mask[c + d.sz] * (q[nzp] - q0) * rdz2;
+      }
+    }
+    cg.aq[n] = a;
+    acc += q0 * a;
+  }
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) cg.part[blockIdx.x] = s;
+}
+
+// x += alpha q, r -= alpha aq; partial sums of r^2.
+__global__ void __launch_bounds__(IB_NT) ib_update_kernel(long N, CgBufs cg) {
+  __shared__ double sh[IB_NT];
+  if (cg.scal[CG_DONE] != 0.0) return;
+  const double alpha = cg.scal[CG_ALPHA];
+  double acc = 0.0;
+  for (long n = blockIdx.x * (long)IB_NT + threadIdx.x; n < N; n += (long)gridDim.x * IB_NT) {
+    cg.x[n] += alpha * cg.q[n];
+    const double r = cg.r[n] - alpha * cg.aq[n];
+    cg.r[n] = r;
+    acc += r * r;
+  }
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) cg.part[blockIdx.x] = s;
+}
+
+// partial sums of r . z (z, the preconditioned residual, need not be masked:
+// r is zero in immersed cells)
+__global__ void __launch_bounds__(IB_NT) ib_dot_kernel(long N, CgBufs cg,
+                                                       const double* __restrict__ z) {
+  __shared__ double sh[IB_NT];
+  if (cg.scal[CG_DONE] != 0.0) return;
+  double acc = 0.0;
+  for (long n = blockIdx.x * (long)IB_NT + threadIdx.x; n < N; n += (long)gridDim.x * IB_NT)
+    acc += cg.r[n] * z[n];
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) cg.part[blockIdx.x] = s;
+}
+
+// q = mask z + beta q
+template <class T>
+__global__ void __launch_bounds__(IB_NT) ib_dir_kernel(Dims d, const T* __restrict__ mask,
+                                                       CgBufs cg, const double* __restrict__ z) {
+  if (cg.scal[CG_DONE] != 0.0) return;
+  const long N = (long)d.nx * d.ny * d.nz;
+  const double beta = cg.scal[CG_BETA];
+  for (long n = blockIdx.x * (long)IB_NT + threadIdx.x; n < N; n += (long)gridDim.x * IB_NT) {
+    int i, j, k;
+    cell_of(d, n, i, j, k);
+    cg.q[n] = (double)mask[pidx(d, i, j, k)] * z[n] + beta * cg.q[n];
+  }
+}
+
+// partial sums of x (zero in immersed cells) for the gauge
+__global__ void __launch_bounds__(IB_NT) ib_sum_kernel(long N, CgBufs cg) {
+  __shared__ double sh[IB_NT];
+  double acc = 0.0;
+  for (long n = blockIdx.x * (long)IB_NT + threadIdx.x; n < N; n += (long)gridDim.x * IB_NT)
+    acc += cg.x[n];
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) cg.part[blockIdx.x] = s;
+}
+
+// x -= mean over the fluid cells, in fluid cells
+template <class T>
+__global__ void __launch_bounds__(IB_NT) ib_shift_kernel(Dims d, const T* __restrict__ mask,
+                                                         CgBufs cg) {
+  const long N = (long)d.nx * d.ny * d.nz;
+  const double mean = cg.scal[CG_MEAN];
+  for (long n = blockIdx.x * (long)IB_NT + threadIdx.x; n < N; n += (long)gridDim.x * IB_NT) {
+    int i, j, k;
+    cell_of(d, n, i, j, k);
+    cg.x[n] = (double)mask[pidx(d, i, j, k)] * (cg.x[n] - mean);
+  }
+}
+
+// Add the IB_NPART partials in a fixed order and update the scalars.
+__global__ void __launch_bounds__(IB_NT) ib_finalize_kernel(CgBufs cg, int what, double tol2,
+                                                            int maxiter, double nfluid) {
+  __shared__ double sh[IB_NT];
+  double* sc = cg.scal;
+  if (what != CG_FIN_MEAN && what != CG_FIN_BNORM && sc[CG_DONE] != 0.0) return;
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < IB_NPART; b += IB_NT) acc += cg.part[b];
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x != 0) return;
+  switch (what) {
+    case CG_FIN_BNORM:
+      sc[CG_BNORM2] = s;
+      sc[CG_RNORM2] = s;
+      sc[CG_IT] = 0.0;
+      sc[CG_DONE] = (s == 0.0) ? 1.0 : 0.0;
+      break;
+    case CG_FIN_RZ0:
+      sc[CG_RZ] = s;
+      sc[CG_BETA] = 0.0;
+      break;
+    case CG_FIN_ALPHA:
+      sc[CG_ALPHA] = sc[CG_RZ] / s;
+      break;
+    case CG_FIN_RES:
+      sc[CG_RNORM2] = s;
+      sc[CG_IT] += 1.0;
+      if (s <= tol2 * sc[CG_BNORM2] || sc[CG_IT] >= (double)maxiter) sc[CG_DONE] = 1.0;
+      break;
+    case CG_FIN_BETA:
+      sc[CG_BETA] = s / sc[CG_RZ];
+      sc[CG_RZ] = s;
+      break;
+    default:  // CG_FIN_MEAN
+      sc[CG_MEAN] = s / nfluid;
+  }
+}
+
+// Velocities on closed faces set to zero (interior faces; halos refilled by
+// the caller).  Wall faces of w are zero already.
+template <class T>
+__global__ void __launch_bounds__(IB_NT) ib_mask_velocity_kernel(Dims d, T* __restrict__ u,
+                                                                 T* __restrict__ v,
+                                                                 T* __restrict__ w,
+                                                                 const T* __restrict__ mask) {
+  const long N = (long)d.nx * d.ny * d.nz;
+  for (long n = blockIdx.x * (long)IB_NT + threadIdx.x; n < N; n += (long)gridDim.x * IB_NT) {
+    int i, j, k;
+    cell_of(d, n, i, j, k);
+    const long c = pidx(d, i, j, k);
+    const T m0 = mask[c];
+    u[c] = u[c] * (m0 * mask[c - 1]);
+    v[c] = v[c] * (m0 * mask[c - d.sy]);
+    if (!d.zb || k > 0) w[c] = w[c] * (m0 * mask[c - d.sz]);
+  }
+}
+
+int ib_grid(long N) {
+  const long b = (N + IB_NT - 1) / IB_NT;
+  return (int)(b < IB_NPART ? b : IB_NPART);
+}
+
+}  // namespace
+
+// Every reducing kernel uses exactly IB_NPART workgroups (the partial array
+// is read whole); the others use up to that many.
+template <class T>
+hipError_t launch_ib_rhs(const Dims& d, const T* u, const T* v, const T* w, const T* mask,
+                         double inv_dt, double rdx, double rdy, double rdz, const CgBufs& cg,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(ib_rhs_kernel<T>, dim3(IB_NPART), dim3(IB_NT), 0, s, d, u, v, w, mask,
+                     inv_dt, rdx, rdy, rdz, cg);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_ib_apply(const Dims& d, const T* mask, double rdx2, double rdy2, double rdz2,
+                           const CgBufs& cg, hipStream_t s) {
+  hipLaunchKernelGGL(ib_apply_kernel<T>, dim3(IB_NPART), dim3(IB_NT), 0, s, d, mask, rdx2, rdy2,
+                     rdz2, cg);
+  return hipGetLastError();
+}
+
+hipError_t launch_ib_update(const Dims& d, const CgBufs& cg, hipStream_t s) {
+  hipLaunchKernelGGL(ib_update_kernel, dim3(IB_NPART), dim3(IB_NT), 0, s,
+                     (long)d.nx * d.ny * d.nz, cg);
+  return hipGetLastError();
+}
+
+hipError_t launch_ib_dot(const Dims& d, const CgBufs& cg, const double* z, hipStream_t s) {
+  hipLaunchKernelGGL(ib_dot_kernel, dim3(IB_NPART), dim3(IB_NT), 0, s, (long)d.nx * d.ny * d.nz,
+                     cg, z);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_ib_dir(const Dims& d, const T* mask, const CgBufs& cg, const double* z,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(ib_dir_kernel<T>, dim3(ib_grid((long)d.nx * d.ny * d.nz)), dim3(IB_NT), 0, s,
+                     d, mask, cg, z);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_ib_gauge(const Dims& d, const T* mask, const CgBufs& cg, double nfluid,
+                           hipStream_t s) {
+  const long N = (long)d.nx * d.ny * d.nz;
+  hipLaunchKernelGGL(ib_sum_kernel, dim3(IB_NPART), dim3(IB_NT), 0, s, N, cg);
+  hipLaunchKernelGGL(ib_finalize_kernel, dim3(1), dim3(IB_NT), 0, s, cg, (int)CG_FIN_MEAN, 0.0, 0,
+                     nfluid);
+  hipLaunchKernelGGL(ib_shift_kernel<T>, dim3(ib_grid(N)), dim3(IB_NT), 0, s, d, mask, cg);
+  return hipGetLastError();
+}
+
+hipError_t launch_ib_finalize(const CgBufs& cg, int what, double tol2, int maxiter,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(ib_finalize_kernel, dim3(1), dim3(IB_NT), 0, s, cg, what, tol2, maxiter,
+                     1.0);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_ib_mask_velocity(const Dims& d, T* u, T* v, T* w, const T* mask,
+                                   hipStream_t s) {
+  hipLaunchKernelGGL(ib_mask_velocity_kernel<T>, dim3(ib_grid((long)d.nx * d.ny * d.nz)),
+                     dim3(IB_NT), 0, s, d, u, v, w, mask);
+  return hipGetLastError();
+}
+
+#define OC_IB_INST(T)                                                                        \
+  template hipError_t launch_ib_rhs<T>(const Dims&, const T*, const T*, const T*, const T*,   \
+                                       double, double, double, double, const CgBufs&,         \
+                                       hipStream_t);                                          \
+  template hipError_t launch_ib_apply<T>(const Dims&, const T*, double, double, double,       \
+                                         const CgBufs&, hipStream_t);                         \
+  template hipError_t launch_ib_dir<T>(const Dims&, const T*, const CgBufs&, const double*,   \
+                                       hipStream_t);                                          \
+  template hipError_t launch_ib_gauge<T>(const Dims&, const T*, const CgBufs&, double,        \
+                                         hipStream_t);                                        \
+  template hipError_t launch_ib_mask_velocity<T>(const Dims&, T*, T*, T*, const T*,           \
+                                                 hipStream_t);
+OC_IB_INST(float)
+OC_IB_INST(double)
+#undef OC_IB_INST
+
+}  // namespace oc

@@ -94,6 +94,15 @@ struct oc_model {
   void* les_nu;
   void* les_kap[OC_MAX_TRACERS];
   void* les_d2;
+  // immersed boundary: the padded mask (state precision, 1 = fluid), the
+  // conjugate-gradient vectors and scalars, pinned host copy of the scalars,
+  // the number of fluid cells and the last solve's statistics
+  void* mask;
+  CgBufs cg;
+  double* cg_host;
+  double nfluid;
+  int cg_iterations;
+  double cg_residual;
   // per-kernel-class event timing
   int prof_on;
   std::vector<hipEvent_t> ev_pool;

@@ -124,6 +124,8 @@ struct FieldSet {
   const T* closure[MAXF];  // optional closure tendencies per field (learned
                            // closure: u, v, w, tracer 0; LES: every field),
                            // padded layout, added to G; null when off
+  const T* mask;           // immersed boundary: 1 in fluid, 0 in immersed
+                           // cells (padded, with halo images); null when off
 };
 
 // Spectral-solve tables and buffers (FP64).
@@ -385,7 +387,47 @@ hipError_t launch_poisson_x_inverse(const Dims& d, const SpecBufs& sb, hipStream
 template <class T>
 hipError_t launch_project(const Dims& d, T* u, T* v, T* w, double scale, const Spacing& sp,
                           const double* p, hipStream_t s, const PoissonSlots* bs = nullptr,
-                          int nslots = 1);
+                          int nslots = 1, const T* mask = nullptr);
+// The forward x transform of a dense FP64 (nz, ny, nx) field into sb.spec
+// (the first pass of the FFT solve applied to a given right-hand side).
+hipError_t launch_poisson_x_forward_dense(const Dims& d, const double* src, const SpecBufs& sb,
+                                          hipStream_t s);
+
+// ---- Immersed boundaries (immersed.hip): preconditioned conjugate gradients
+// on dense FP64 (nz, ny, nx) vectors.  Reducing kernels run IB_NPART
+// workgroups and leave one partial sum each in part; launch_ib_finalize adds
+// them in a fixed order and updates the scalars in scal (indices CG_*).
+constexpr int IB_NPART = 1024;
+enum { CG_RZ = 0, CG_ALPHA, CG_BETA, CG_BNORM2, CG_RNORM2, CG_IT, CG_DONE, CG_MEAN, CG_NSCAL };
+enum { CG_FIN_BNORM = 0, CG_FIN_RZ0, CG_FIN_ALPHA, CG_FIN_RES, CG_FIN_BETA, CG_FIN_MEAN };
+struct CgBufs {
+  double* x;     // iterate (the pressure)
+  double* r;     // residual
+  double* q;     // search direction
+  double* aq;    // A q
+  double* part;  // IB_NPART partial sums
+  double* scal;  // CG_NSCAL scalars
+};
+template <class T>
+hipError_t launch_ib_rhs(const Dims& d, const T* u, const T* v, const T* w, const T* mask,
+                         double inv_dt, double rdx, double rdy, double rdz, const CgBufs& cg,
+                         hipStream_t s);
+template <class T>
+hipError_t launch_ib_apply(const Dims& d, const T* mask, double rdx2, double rdy2, double rdz2,
+                           const CgBufs& cg, hipStream_t s);
+hipError_t launch_ib_update(const Dims& d, const CgBufs& cg, hipStream_t s);
+hipError_t launch_ib_dot(const Dims& d, const CgBufs& cg, const double* z, hipStream_t s);
+template <class T>
+hipError_t launch_ib_dir(const Dims& d, const T* mask, const CgBufs& cg, const double* z,
+                         hipStream_t s);
+template <class T>
+hipError_t launch_ib_gauge(const Dims& d, const T* mask, const CgBufs& cg, double nfluid,
+                           hipStream_t s);
+hipError_t launch_ib_finalize(const CgBufs& cg, int what, double tol2, int maxiter,
+                              hipStream_t s);
+template <class T>
+hipError_t launch_ib_mask_velocity(const Dims& d, T* u, T* v, T* w, const T* mask,
+                                   hipStream_t s);
 // Stretched z: the tridiagonal solve along z of every (kx, ky) mode in place
 // of the z transform pass; lo, up (nz) are the off-diagonals of the vertical
 // operator, dzc (nz) the cell thicknesses and dzf (nz + 1) the centre

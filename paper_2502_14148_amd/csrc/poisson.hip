@@ -132,13 +132,16 @@ template <int N> struct YZCfg { static constexpr int W = (N >= 512) ? 4 : (N >= 
 // ---------------------------------------------------------------------------
 // Pass 1: rhs = div(u~) * inv_dt on line pairs (j, j+1), packed FFT along x.
 // ---------------------------------------------------------------------------
+// dense != null: transform that dense FP64 (nz, ny, nx) field instead (the
+// preconditioner of the immersed-boundary solve).
 template <class T, int N>
 __global__ void __launch_bounds__(NT) fwd_x_kernel(Dims d, const T* __restrict__ u,
                                                    const T* __restrict__ v,
                                                    const T* __restrict__ w, double inv_dt,
                                                    double rdx, double rdy,
                                                    const double* __restrict__ rdzc, SpecBufs sb,
-                                                   const PoissonSlots* __restrict__ bs) {
+                                                   const PoissonSlots* __restrict__ bs,
+                                                   const double* __restrict__ dense) {
   if (bs) {
     const int z = blockIdx.z;
     u = (const T*)bs->u[z];
@@ -151,7 +154,7 @@ __global__ void __launch_bounds__(NT) fwd_x_kernel(Dims d, const T* __restrict__
   __shared__ double2 tws[N];
   stage_twiddles<N>(tws, sb.twx);
   const int k = blockIdx.y;
-  const double rdz = rdzc[k];
+  const double rdz = dense ? 0.0 : rdzc[k];  // the dense path carries no spacing table
   const int npairs = d.ny / 2;
   const int pair0 = blockIdx.x * LP;
   // compile-time trip counts, so that every load of the tile is in flight
@@ -164,7 +167,10 @@ __global__ void __launch_bounds__(NT) fwd_x_kernel(Dims d, const T* __restrict__
     const int l = t / N, i = t % N;
     const int pr = pair0 + l;
     double2 z = make_double2(0.0, 0.0);
-    if (pr < npairs) {
+    if (pr < npairs && dense) {
+      const long o = ((long)k * d.ny + 2 * pr) * d.nx + i;
+      z = make_double2(dense[o], dense[o + d.nx]);
+    } else if (pr < npairs) {
       double dv[2];
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
@@ -520,11 +526,12 @@ __global__ void __launch_bounds__(NT) inv_x_kernel(Dims d, SpecBufs sb,
 // ---------------------------------------------------------------------------
 constexpr int PJ_X = 64, PJ_Y = 4, PJ_KC = 16;
 
+// mask != null (immersed boundary): velocities on closed faces are set to 0.
 template <class T>
 __global__ void __launch_bounds__(PJ_X * PJ_Y) project_kernel(
     Dims d, T* __restrict__ u, T* __restrict__ v, T* __restrict__ w, double scale, double rdx,
     double rdy, const double* __restrict__ rdzf, const double* __restrict__ p,
-    const PoissonSlots* __restrict__ bs) {
+    const PoissonSlots* __restrict__ bs, const T* __restrict__ mask) {
   if (bs) {
     const int z = blockIdx.z;
     u = (T*)bs->u[z];
@@ -576,11 +583,18 @@ __global__ void __launch_bounds__(PJ_X * PJ_Y) project_kernel(
     for (int q = 0; q < PJ_B; ++q) {
       const int k = kb + q;
       if (k < k1) {
-        const T un = (T)((double)uu[q] - scale * (p0[q] - pxm[q]) * rdx);
-        const T vn = (T)((double)vv[q] - scale * (p0[q] - pym[q]) * rdy);
+        T un = (T)((double)uu[q] - scale * (p0[q] - pxm[q]) * rdx);
+        T vn = (T)((double)vv[q] - scale * (p0[q] - pym[q]) * rdy);
         T wn = ww[q];
         if (!d.zb || k > 0) wn = (T)((double)wn - scale * (p0[q] - pb) * rdzf[k]);
         pb = p0[q];
+        if (mask) {
+          const long c = pidx(d, i, j, k);
+          const T m0 = mask[c];
+          un = un * (m0 * mask[c - 1]);
+          vn = vn * (m0 * mask[c - d.sy]);
+          if (!d.zb || k > 0) wn = wn * (m0 * mask[c - d.sz]);
+        }
         // the final velocities, with their halo images
         store_with_images(u, d, i, j, k, un, false);
         store_with_images(v, d, i, j, k, vn, false);
@@ -620,10 +634,25 @@ hipError_t launch_poisson_x_forward(const Dims& d, const T* u, const T* v, const
   {                                                                                        \
     dim3 grid((d.ny / 2 + XCfg<N>::LP - 1) / XCfg<N>::LP, d.nz, nslots);                  \
     hipLaunchKernelGGL((fwd_x_kernel<T, N>), grid, dim3(NT), 0, s, d, u, v, w, inv_dt,    \
-                       sp.rdx, sp.rdy, sp.rdzc, sb, bs);                                   \
+                       sp.rdx, sp.rdy, sp.rdzc, sb, bs, (const double*)nullptr);           \
   }
   OC_FFT_DISPATCH(d.nx, OC_LAUNCH_FX)
 #undef OC_LAUNCH_FX
+  return hipGetLastError();
+}
+
+hipError_t launch_poisson_x_forward_dense(const Dims& d, const double* src, const SpecBufs& sb,
+                                          hipStream_t s) {
+#define OC_LAUNCH_FXD(N)                                                                   \
+  {                                                                                        \
+    dim3 grid((d.ny / 2 + XCfg<N>::LP - 1) / XCfg<N>::LP, d.nz, 1);                       \
+    hipLaunchKernelGGL((fwd_x_kernel<double, N>), grid, dim3(NT), 0, s, d,                \
+                       (const double*)nullptr, (const double*)nullptr,                     \
+                       (const double*)nullptr, 0.0, 0.0, 0.0, (const double*)nullptr, sb,  \
+                       (const PoissonSlots*)nullptr, src);                                 \
+  }
+  OC_FFT_DISPATCH(d.nx, OC_LAUNCH_FXD)
+#undef OC_LAUNCH_FXD
   return hipGetLastError();
 }
 
@@ -682,10 +711,12 @@ hipError_t launch_poisson_x_inverse(const Dims& d, const SpecBufs& sb, hipStream
 
 template <class T>
 hipError_t launch_project(const Dims& d, T* u, T* v, T* w, double scale, const Spacing& sp,
-                          const double* p, hipStream_t s, const PoissonSlots* bs, int nslots) {
+                          const double* p, hipStream_t s, const PoissonSlots* bs, int nslots,
+                          const T* mask) {
   const unsigned nb = (unsigned)(((d.nx + PJ_X - 1) / PJ_X) * ((d.ny + PJ_Y - 1) / PJ_Y));
   hipLaunchKernelGGL(project_kernel<T>, dim3(nb, (d.nz + PJ_KC - 1) / PJ_KC, nslots),
-                     dim3(PJ_X * PJ_Y), 0, s, d, u, v, w, scale, sp.rdx, sp.rdy, sp.rdzf, p, bs);
+                     dim3(PJ_X * PJ_Y), 0, s, d, u, v, w, scale, sp.rdx, sp.rdy, sp.rdzf, p, bs,
+                     mask);
   return hipGetLastError();
 }
 
@@ -699,9 +730,9 @@ template hipError_t launch_poisson_x_forward<double>(const Dims&, const double*,
                                                      const PoissonSlots*, int);
 template hipError_t launch_project<float>(const Dims&, float*, float*, float*, double,
                                           const Spacing&, const double*, hipStream_t,
-                                          const PoissonSlots*, int);
+                                          const PoissonSlots*, int, const float*);
 template hipError_t launch_project<double>(const Dims&, double*, double*, double*, double,
                                            const Spacing&, const double*, hipStream_t,
-                                           const PoissonSlots*, int);
+                                           const PoissonSlots*, int, const double*);
 
 }  // namespace oc

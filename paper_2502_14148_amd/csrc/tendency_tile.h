@@ -96,9 +96,11 @@ struct SlotOff {
   int Fc0, Fstride;       // first tracer flux array and the array pitch
 };
 
-template <class T, int SCHEME, int NTR, int PL, int R>
+// IMM: no diffusive tracer flux through a face next to an immersed cell (the
+// mask plane at S + om).
+template <class T, int SCHEME, int NTR, int PL, int R, bool IMM = false>
 __device__ inline void slot_fluxes(T* S, const SlotOff& o, int L, int sd, int se, int fi, T rd,
-                                   T nu, T kappa, T eps) {
+                                   T nu, T kappa, T eps, int om = 0) {
   {
     const T* vd = S + o.vd;
     const T adv = interp_lds<T, R>(vd, L, sd);
@@ -122,6 +124,7 @@ __device__ inline void slot_fluxes(T* S, const SlotOff& o, int L, int sd, int se
     S[o.Fw + fi] = flux_lds<T, SCHEME, R>(wk, L, sd, adv, eps) - nu * (wk[L] - wk[L - sd]) * rd;
   }
   const T un = S[o.vd + L];
+  const T kap = IMM ? kappa * (S[om + L] * S[om + L - sd]) : kappa;
 #pragma unroll
   for (int q = 0; q < NTR; ++q) {
 #if OC_TEND_FLUXBAR
@@ -129,7 +132,7 @@ __device__ inline void slot_fluxes(T* S, const SlotOff& o, int L, int sd, int se
 #endif
     const T* c = S + o.c0 + q * PL;
     S[o.Fc0 + q * o.Fstride + fi] =
-        flux_lds<T, SCHEME, R>(c, L, sd, un, eps) - kappa * (c[L] - c[L - sd]) * rd;
+        flux_lds<T, SCHEME, R>(c, L, sd, un, eps) - kap * (c[L] - c[L - sd]) * rd;
   }
 }
 
@@ -138,7 +141,11 @@ __device__ inline void slot_fluxes(T* S, const SlotOff& o, int L, int sd, int se
 // CLO: add the closure tendencies computed beforehand (fs.closure; learned
 // closure: u, v, w and tracer 0, LES closure: every field).  A separate
 // instantiation keeps the plain kernel's registers free of them.
-template <class T, int SCHEME, int NTR, int TX, int TY, int R, bool CLO = false>
+// IMM: grid-fitted immersed boundary (fs.mask, 1 in fluid cells): zero
+// velocity tendencies on faces next to an immersed cell, no diffusive tracer
+// flux through them, no top flux into an immersed top cell.
+template <class T, int SCHEME, int NTR, int TX, int TY, int R, bool CLO = false,
+          bool IMM = false>
 __device__ __attribute__((always_inline)) inline void tendency_tile(
     const Dims& d, const FieldSet<T>& fs, const TendParams<T>& P, int nbx, int nby, int nbz,
     int kc, int b) {
@@ -156,7 +163,8 @@ __device__ __attribute__((always_inline)) inline void tendency_tile(
   // z-interpolated u at x faces and v at y faces, the edge rings, then the
   // x-face fluxes (NF arrays of NXS) and y-face fluxes (NF arrays of NYS)
   constexpr int OU = 0, OV = PL, OW = 2 * PL, OC = 4 * PL;
-  constexpr int OAX = (4 + NTR) * PL, OAY = OAX + NXS;
+  constexpr int OM = (4 + NTR) * PL;   // mask plane (level k), IMM only
+  constexpr int OAX = (4 + NTR + (IMM ? 1 : 0)) * PL, OAY = OAX + NXS;
   constexpr int OER = OAY + NYS;
   constexpr int OFX = OER + NRING * NE, OFY = OFX + NF * NXS;
   constexpr int NLDS = OFY + NF * NYS;
@@ -233,6 +241,13 @@ __device__ __attribute__((always_inline)) inline void tendency_tile(
       S[ering(kk)] = ecol[(long)(kk + hh) * sz];
     }
   }
+  // immersed boundary: the own column's mask at levels k-1, k, k+1
+  T mkm = T(1), mk0 = T(1), mkp = T(1);
+  if (IMM) {
+    mkm = (fs.mask + (long)(kb - 1 + hh) * sz)[col];
+    mk0 = (fs.mask + (long)(kb + hh) * sz)[col];
+    mkp = (fs.mask + (long)(kb + 1 + hh) * sz)[col];
+  }
 
   // ---- prologue: w at level kb
   fill(rw(kb), gw, kb);
@@ -270,7 +285,7 @@ __device__ __attribute__((always_inline)) inline void tendency_tile(
       for (int o = 1; o < NW; ++o) z[o] = wc[q][o - 1];
       fzb_c[q] = wall ? T(0)
                       : flux_reg<T, SCHEME, R>(z, wface, eps) -
-                            P.kappaz * (z[R] - z[R - 1]) * rzb;
+                            (IMM ? P.kappaz * (mkm * mk0) : P.kappaz) * (z[R] - z[R - 1]) * rzb;
     }
   }
 
@@ -281,6 +296,7 @@ __device__ __attribute__((always_inline)) inline void tendency_tile(
     fill(rw(k + 1), gw, k + 1);
 #pragma unroll
     for (int q = 0; q < NTR; ++q) fill(OC + q * PL, fs.in[3 + q], k);
+    if (IMM) fill(OM, fs.mask, k);
     // u and v interpolated in z to face k (levels k-R+1 .. k+R-2): own
     // column from the register window, edge columns from their rings
     S[OAX + ty * (TX + 1) + tx] = interpc<T, R>(wu);
@@ -306,10 +322,11 @@ __device__ __attribute__((always_inline)) inline void tendency_tile(
     oy.Fself = OFY + 1 * NYS; oy.Fcross = OFY + 0 * NYS; oy.Fw = OFY + 2 * NYS;
     oy.Fc0 = OFY + 3 * NYS; oy.Fstride = NYS;
     // main rounds: the left x face and the bottom y face of the own cell
-    slot_fluxes<T, SCHEME, NTR, PL, R>(S, ox, Lc, 1, PX, ty * (TX + 1) + tx, P.rdx, P.nu, P.kappa,
-                                       eps);
+    slot_fluxes<T, SCHEME, NTR, PL, R, IMM>(S, ox, Lc, 1, PX, ty * (TX + 1) + tx, P.rdx, P.nu,
+                                            P.kappa, eps, OM);
     __builtin_amdgcn_sched_barrier(0);
-    slot_fluxes<T, SCHEME, NTR, PL, R>(S, oy, Lc, PX, 1, ty * TX + tx, P.rdy, P.nu, P.kappa, eps);
+    slot_fluxes<T, SCHEME, NTR, PL, R, IMM>(S, oy, Lc, PX, 1, ty * TX + tx, P.rdy, P.nu, P.kappa,
+                                            eps, OM);
     __builtin_amdgcn_sched_barrier(0);
     // edge round: right x faces of the last column, top y faces of the last row
     if (edge) {
@@ -322,8 +339,8 @@ __device__ __attribute__((always_inline)) inline void tendency_tile(
       oe.Fself = xs ? ox.Fself : oy.Fself; oe.Fcross = xs ? ox.Fcross : oy.Fcross;
       oe.Fw = xs ? ox.Fw : oy.Fw; oe.Fc0 = xs ? ox.Fc0 : oy.Fc0;
       oe.Fstride = xs ? NXS : NYS;
-      slot_fluxes<T, SCHEME, NTR, PL, R>(S, oe, L, xs ? 1 : PX, xs ? PX : 1, fi,
-                                         xs ? P.rdx : P.rdy, P.nu, P.kappa, eps);
+      slot_fluxes<T, SCHEME, NTR, PL, R, IMM>(S, oe, L, xs ? 1 : PX, xs ? PX : 1, fi,
+                                              xs ? P.rdx : P.rdy, P.nu, P.kappa, eps, OM);
     }
 
     // ---- z fluxes through the top face of level k (w: at centre k)
@@ -342,11 +359,12 @@ __device__ __attribute__((always_inline)) inline void tendency_tile(
                        : flux_reg<T, SCHEME, R>(wv, wt_v, eps) - P.nuz * (wv[R] - wv[R - 1]) * rzft;
       const T wb = interpc<T, R>(ww + 1);
       fzt_w = flux_reg<T, SCHEME, R>(ww, wb, eps) - P.nuz * (ww[R] - ww[R - 1]) * rzc;
+      const T kapz = IMM ? P.kappaz * (mk0 * mkp) : P.kappaz;
 #pragma unroll
       for (int q = 0; q < NTR; ++q)
-        fzt_c[q] = top_wall ? P.top_flux[q]
+        fzt_c[q] = top_wall ? (IMM ? P.top_flux[q] * mk0 : P.top_flux[q])
                             : flux_reg<T, SCHEME, R>(wc[q], ww[R], eps) -
-                                  P.kappaz * (wc[q][R] - wc[q][R - 1]) * rzft;
+                                  kapz * (wc[q][R] - wc[q][R - 1]) * rzft;
     }
     __syncthreads();  // all x/y fluxes of level k are in LDS
 
@@ -373,6 +391,13 @@ __device__ __attribute__((always_inline)) inline void tendency_tile(
       }
       const bool bottom_wall = d.zb && k == 0;
       if (bottom_wall) G[2] = T(0);
+      if (IMM) {
+        // velocities on faces next to an immersed cell do not change
+        const T* mk = S + OM;
+        G[0] *= mk[Lc - 1] * mk[Lc];
+        G[1] *= mk[Lc - PX] * mk[Lc];
+        G[2] *= mkm * mk0;
+      }
       const T divu = (uk[Lc + 1] - uk[Lc]) * P.rdx + (vk[Lc + PX] - vk[Lc]) * P.rdy +
                      (ww[R] - ww[R - 1]) * rzc;
 #pragma unroll
@@ -411,6 +436,11 @@ __device__ __attribute__((always_inline)) inline void tendency_tile(
     fzb_w = fzt_w;
 #pragma unroll
     for (int q = 0; q < NTR; ++q) fzb_c[q] = fzt_c[q];
+    if (IMM && k + 1 < ke) {
+      mkm = mk0;
+      mk0 = mkp;
+      mkp = (fs.mask + (long)(k + 2 + hh) * sz)[col];
+    }
     if (k + 1 < ke) {
       const long lv = (long)(k + R + 1 + hh) * sz;
 #pragma unroll
@@ -439,14 +469,14 @@ struct TendWaves {
 
 // One model; tiles are mapped XCD-major, so neighbouring tiles (which share
 // halo loads) land on the same XCD and its L2.
-template <class T, int SCHEME, int NTR, int TX, int TY, int R, bool CLO>
+template <class T, int SCHEME, int NTR, int TX, int TY, int R, bool CLO, bool IMM = false>
 __global__ void __launch_bounds__(TX * TY)
     __attribute__((amdgpu_waves_per_eu(TendWaves<T, R>::value)))
     tendency_zmarch(Dims d, FieldSet<T> fs, TendParams<T> P, int nbx, int nby, int nbz, int kc) {
   const int nblk = nbx * nby * nbz;
   int b = blockIdx.x;
   if ((nblk & 7) == 0) b = (b & 7) * (nblk >> 3) + (b >> 3);
-  tendency_tile<T, SCHEME, NTR, TX, TY, R, CLO>(d, fs, P, nbx, nby, nbz, kc, b);
+  tendency_tile<T, SCHEME, NTR, TX, TY, R, CLO, IMM>(d, fs, P, nbx, nby, nbz, kc, b);
 }
 
 }  // namespace tz
@@ -466,8 +496,14 @@ hipError_t launch_tendency_radius(const Dims& d, const FieldSet<T>& fs, const Te
   const dim3 grid(nbx * nby * nbz);
   bool clo = false;
   for (int f = 0; f < MAXF; ++f) clo = clo || fs.closure[f] != nullptr;
+  const bool imm = fs.mask != nullptr;
+  if (imm && (R != 3 || clo)) return hipErrorInvalidValue;
 #define OC_TZ(SCH, NTR_, TX_, TY_)                                                            \
-  if (clo)                                                                                    \
+  if (imm) {                                                                                  \
+    if constexpr (R == 3)                                                                     \
+      hipLaunchKernelGGL((tz::tendency_zmarch<T, SCH, NTR_, TX_, TY_, R, false, true>), grid,  \
+                         dim3(TX_ * TY_), 0, s, d, fs, p, nbx, nby, nbz, kc);                 \
+  } else if (clo)                                                                             \
     hipLaunchKernelGGL((tz::tendency_zmarch<T, SCH, NTR_, TX_, TY_, R, true>), grid,           \
                        dim3(TX_ * TY_), 0, s, d, fs, p, nbx, nby, nbz, kc);                   \
   else                                                                                        \

@@ -36,15 +36,16 @@ EXPORTS = ("oc_last_error", "oc_grid_create", "oc_grid_destroy", "oc_model_works
            "oc_mlp_gradients", "oc_mlp_train_step", "oc_model_set_closure",
            "oc_ensemble_workspace_size", "oc_ensemble_create", "oc_ensemble_step",
            "oc_ensemble_tuning", "oc_ensemble_destroy", "oc_closure_features",
-           "oc_coarse_grain", "oc_implicit_vertical_diffusion")
+           "oc_coarse_grain", "oc_implicit_vertical_diffusion", "oc_set_immersed",
+           "oc_pressure_stats")
 OC_ENS_TUNE, OC_ENS_GRAPH = 1, 2
 OC_MLP_NPARAM = 195076
 MLP_SHAPES = (("W1", (256, 500)), ("b1", (256,)), ("W2", (256, 256)), ("b2", (256,)),
               ("W3", (4, 256)), ("b3", (4,)))
-OC_NPROF = 14
+OC_NPROF = 15
 PROF_CLASSES = ("tendency", "fft_x_fwd", "fft_y_fwd", "z_solve", "fft_y_inv", "fft_x_inv",
                 "project", "halo", "closure", "hydro_diag", "hydro_tendency", "barotropic",
-                "implicit_z", "les")
+                "implicit_z", "les", "cg")
 LES = {"none": 0, "smagorinsky": 1, "amd": 2}
 
 
@@ -70,7 +71,8 @@ class ModelDesc(ctypes.Structure):
                 ("depth", ctypes.c_double), ("omega", ctypes.c_double),
                 ("closure", ctypes.c_int32), ("implicit_z", ctypes.c_int32),
                 ("les", ctypes.c_int32), ("les_c", ctypes.c_double), ("les_cb", ctypes.c_double),
-                ("les_pr", ctypes.c_double)]
+                ("les_pr", ctypes.c_double), ("immersed", ctypes.c_int32),
+                ("cg_tol", ctypes.c_double), ("cg_maxiter", ctypes.c_int32)]
 
 
 class OcError(RuntimeError):
@@ -128,6 +130,9 @@ def load_library(path=_LIB_PATH):
         "oc_closure_features": [vp, ctypes.POINTER(ctypes.c_double), vp, vp],
         "oc_coarse_grain": [vp, vp, vp, vp],
         "oc_implicit_vertical_diffusion": [vp, ctypes.c_double, vp],
+        "oc_set_immersed": [vp, vp, vp],
+        "oc_pressure_stats": [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double),
+                              vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -183,6 +188,11 @@ class Model:
                 md.les_c, md.les_cb, md.les_pr = ph.les_cs, ph.les_cb, ph.les_pr
             elif md.les == LES["amd"]:
                 md.les_c, md.les_cb, md.les_pr = ph.les_camd, 0.0, 1.0
+            solid = getattr(ph, "solid", None)
+            if solid is not None:
+                md.immersed = 1
+                md.cg_tol = getattr(ph, "cg_tol", 1e-13)
+                md.cg_maxiter = getattr(ph, "cg_maxiter", 200)
         md.precision = OC_FP64 if precision == "fp64" else OC_FP32_MIXED
         md.advection = ADVECTION[ph.advection]
         md.weno_eps = ph.weno_eps
@@ -207,6 +217,8 @@ class Model:
             _check(lib.oc_model_create(self._grid, ctypes.byref(md),
                                        ctypes.c_void_p(self.workspace.data_ptr()),
                                        ctypes.c_uint64(nbytes.value), ctypes.byref(self._model)))
+        if md.immersed:
+            self.set_immersed(ph.solid)
 
     def __del__(self):
         try:
@@ -293,6 +305,19 @@ class Model:
 
     def rk3_step(self, dt, nsteps=1):
         _check(_lib.oc_rk3_step(self._model, ctypes.c_double(dt), ctypes.c_int32(nsteps), _stream()))
+
+    def set_immersed(self, solid):
+        """Immersed cells ((nz, ny, nx) booleans, True = immersed)."""
+        a = np.ascontiguousarray(np.asarray(solid, dtype=np.uint8))
+        assert a.shape == (self.ph.nz, self.ph.ny, self.ph.nx)
+        _check(_lib.oc_set_immersed(self._model, ctypes.c_void_p(a.ctypes.data), _stream()))
+
+    def pressure_stats(self):
+        """(iterations, relative residual) of the last immersed pressure solve."""
+        it = ctypes.c_int32()
+        res = ctypes.c_double()
+        _check(_lib.oc_pressure_stats(self._model, ctypes.byref(it), ctypes.byref(res), _stream()))
+        return it.value, res.value
 
     def implicit_vertical_diffusion(self, dt_eff):
         _check(_lib.oc_implicit_vertical_diffusion(self._model, ctypes.c_double(dt_eff), _stream()))

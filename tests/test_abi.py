@@ -213,3 +213,41 @@ def test_weno_order_validation():
     mh.advection = oc.ADVECTION["weno7z"]
     assert lib.oc_model_workspace_size(gl, ctypes.byref(mh), ctypes.byref(n)) == -5
     assert lib.oc_grid_destroy(gl) == 0
+
+
+def test_immersed_validation():
+    """An immersed boundary reserves the mask and the iteration's vectors;
+    it needs WENO5 (or none), a uniform z, no implicit diffusion, LES or
+    learned closure, and sane iteration limits."""
+    lib = oc.load_library()
+    g = ctypes.c_void_p()
+    gd = oc.GridDesc(32, 32, 16, oc.OC_BOUNDED, 0, 64, 0, 64, -16, 16, oc.OC_RECTILINEAR, 0.0)
+    assert lib.oc_grid_create(ctypes.byref(gd), ctypes.byref(g)) == 0
+    md = oc.ModelDesc()
+    md.precision, md.advection, md.weno_eps, md.weno_q = oc.OC_FP32_MIXED, 1, 1e-15, 2
+    md.ntracers, md.buoyancy = 2, 1
+    plain, imm = ctypes.c_uint64(), ctypes.c_uint64()
+    assert lib.oc_model_workspace_size(g, ctypes.byref(md), ctypes.byref(plain)) == 0
+    md.immersed, md.cg_tol, md.cg_maxiter = 1, 1e-13, 200
+    assert lib.oc_model_workspace_size(g, ctypes.byref(md), ctypes.byref(imm)) == 0
+    assert imm.value >= plain.value + 4 * 32 * 32 * 16 * 8     # four FP64 vectors at least
+    n = ctypes.c_uint64()
+    for field, bad, rc in (("cg_tol", 0.0, -1), ("cg_maxiter", 0, -1), ("immersed", 2, -1),
+                           ("advection", oc.ADVECTION["weno9z"], -5), ("implicit_z", 1, -5),
+                           ("les", 1, -5), ("closure", 1, -5)):
+        good = getattr(md, field)
+        setattr(md, field, bad)
+        if field == "les":
+            md.les_c, md.les_cb, md.les_pr = 0.16, 1.0, 1.0
+        assert lib.oc_model_workspace_size(g, ctypes.byref(md), ctypes.byref(n)) == rc, field
+        setattr(md, field, good)
+    assert lib.oc_grid_destroy(g) == 0
+    # a stretched z is refused
+    zf = (ctypes.c_double * 17)(*[-16.0 + 16.0 * (k / 16) ** 1.3 for k in range(17)])
+    gs = oc.GridDesc(32, 32, 16, oc.OC_BOUNDED, 0, 64, 0, 64, -16, 16, oc.OC_RECTILINEAR, 0.0)
+    gs.z_faces = ctypes.cast(zf, ctypes.POINTER(ctypes.c_double))
+    assert lib.oc_grid_create(ctypes.byref(gs), ctypes.byref(g)) == 0
+    assert lib.oc_model_workspace_size(g, ctypes.byref(md), ctypes.byref(n)) == -5
+    assert lib.oc_grid_destroy(g) == 0
+    assert lib.oc_set_immersed(None, None, None) == -1
+    assert lib.oc_pressure_stats(None, None, None, None) == -1
