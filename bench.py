@@ -362,6 +362,67 @@ def run_weno_high(steps, warmup, n):
     return out
 
 
+# Algorithmic HBM bytes per cell of one conjugate-gradient iteration of the
+# immersed-boundary pressure solve (FP64 vectors, FP32 mask): A q reads q and
+# the mask, writes A q (20 B); the update reads x, q, r, A q and writes x, r
+# (48 B); r . z reads r and z (16 B); the new direction reads z, q, the mask
+# and writes q (28 B).  The preconditioner's five FFT passes come on top.
+CG_BYTES_PER_CELL_ITER = 20 + 48 + 16 + 28
+
+
+def run_immersed(steps, warmup, n):
+    """The 256^3 free-convection step over a Gaussian seamount (grid-fitted
+    immersed bottom, 40 % of the depth high): masked tendencies and the
+    conjugate-gradient pressure solve preconditioned by the FFT/DCT solve."""
+    from paper_2502_14148_amd import inputs, oc
+    import torch
+    ph = inputs.seamount_convection_physics((n, n, n), (2.0 * n, 2.0 * n, 1.0 * n), 0.4, 0.15)
+    print(f"# generating the {n}^3 seamount initial state", file=sys.stderr, flush=True)
+    s = inputs.convection_initial(ph, seed=0)
+    m = oc.Model(ph, "fp32")
+    m.set_states(s)
+    del s
+    m.rk3_step(1.0, warmup)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    m.profile(True)
+    e0.record(stream)
+    m.rk3_step(1.0, steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    m.profile(False)
+    prof = m.profile_read()
+    ms = e0.elapsed_time(e1)
+    it, res = m.pressure_stats()
+    diag = m.diagnostics()
+    del m
+    torch.cuda.empty_cache()
+    ncells = n ** 3
+    solves = 3 * steps
+    t_fft = sum(prof[k][0] for k in ("fft_x_fwd", "fft_y_fwd", "z_solve", "fft_y_inv", "fft_x_inv"))
+    n_fft = prof["fft_x_fwd"][1]           # preconditioner applications
+    iters_per_solve = n_fft / solves - 1   # one application before the first iteration
+    cg_ms = prof["cg"][0]
+    gbs = CG_BYTES_PER_CELL_ITER * ncells * (n_fft - solves) / (cg_ms / 1e3) / 1e9
+    return {"value": ncells * steps / (ms / 1e3), "unit": "cell-steps/s", "steps": steps,
+            "warmup": warmup, "ms_per_step": ms / steps, "dtype": "f32",
+            "config": {"workload": f"free-convection LES {n}^3 over a Gaussian seamount "
+                                   f"(grid-fitted bottom, 0.4 lz high, e-folding width 0.15 lx), "
+                                   f"WENO5-Z, conjugate-gradient pressure solve preconditioned "
+                                   f"by the FFT/DCT solve", "dt_s": 1.0,
+                       "immersed_fraction": float(np.mean(ph.solid)), "cg_tol": ph.cg_tol},
+            "kernels_ms_per_step": {k: v[0] / steps for k, v in prof.items() if v[1]},
+            "cg": {"iterations_per_solve": iters_per_solve, "last_solve": {"iterations": it,
+                                                                           "rel_residual": res},
+                   "ms_per_solve": (cg_ms + t_fft) / solves,
+                   "vector_kernels_hbm": {"achieved_gbs": round(gbs, 1),
+                                          "frac": round(gbs / HBM_PEAK_GBS, 4),
+                                          "bytes_per_cell_iteration": CG_BYTES_PER_CELL_ITER}},
+            "final_max_w": diag["max_w"]}
+
+
 MLP_FLOPS_PER_ROW = 2 * (500 * 256 + 256 * 256 + 256 * 4)   # forward, one cell
 BF16_PEAK_TFLOPS = 2500.0      # MI355X dense BF16 MFMA
 
@@ -515,6 +576,7 @@ def main():
     ap.add_argument("--no-stretched", action="store_true")
     ap.add_argument("--no-les", action="store_true")
     ap.add_argument("--no-weno-high", action="store_true")
+    ap.add_argument("--no-immersed", action="store_true")
     ap.add_argument("--no-main", action="store_true",
                     help="skip the 256^3 step (profiling the other legs alone)")
     ap.add_argument("--ensemble-steps", type=int, default=20)
@@ -552,6 +614,9 @@ def main():
     if not a.no_weno_high:
         print("# WENO7/9 runs", file=sys.stderr, flush=True)
         out["weno_high"] = run_weno_high(a.steps, a.warmup, a.n)
+    if not a.no_immersed:
+        print("# immersed seamount run", file=sys.stderr, flush=True)
+        out["immersed"] = run_immersed(a.steps, a.warmup, a.n)
     if not a.no_closure:
         print("# closure network", file=sys.stderr, flush=True)
         out["closure_mlp"] = run_closure_mlp()

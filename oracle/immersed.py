@@ -24,7 +24,7 @@ and its preconditioner to other works):
   the predictor is corrected on open faces only.
 
 The oracle solves that equation directly (a sparse LU factorisation of the
-operator bordered by the gauge constraint); the GPU iterates to it with
+operator with one cell's value fixed, then the gauge); the GPU iterates to it with
 conjugate gradients preconditioned by the FFT solver of the whole box
 applied to the masked residual (the preconditioner the appendix describes).
 """
@@ -131,16 +131,23 @@ def operator_matrix(ph):
 
 def solve_poisson_immersed(rhs, ph):
     """Solve the masked Poisson equation on the fluid cells with zero mean
-    there (the operator bordered by the gauge row and column), p = 0 in
-    immersed cells."""
+    there, p = 0 in immersed cells.  On a connected fluid region the
+    operator's null space is the constants and the equations are consistent
+    (the right-hand side, a divergence, sums to zero), so the solution is
+    found with the first fluid cell's value fixed at zero (its equation then
+    holds by consistency) and the fluid mean removed afterwards."""
     A, cells = operator_matrix(ph)
-    n = cells.size
-    ones = np.ones((n, 1))
-    K = sp.bmat([[A, sp.csr_matrix(ones)], [sp.csr_matrix(ones.T), None]], format="csc")
-    b = np.concatenate([rhs.ravel()[cells], [0.0]])
-    x = spla.spsolve(K, b)
+    A = A.tocsc()
+    b = rhs.ravel()[cells]
+    x = np.zeros(cells.size)
+    # the reduced operator is symmetric definite: no pivoting, a symmetric
+    # fill-reducing ordering
+    lu = spla.splu(A[1:, 1:], permc_spec="MMD_AT_PLUS_A", diag_pivot_thresh=0.0,
+                   options={"SymmetricMode": True})
+    x[1:] = lu.solve(b[1:])
+    x -= np.mean(x)
     p = np.zeros(ph.nz * ph.ny * ph.nx)
-    p[cells] = x[:n]
+    p[cells] = x
     return p.reshape(ph.nz, ph.ny, ph.nx)
 
 
