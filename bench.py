@@ -377,6 +377,9 @@ def run_immersed(steps, warmup, n):
     from paper_2502_14148_amd import inputs, oc
     import torch
     ph = inputs.seamount_convection_physics((n, n, n), (2.0 * n, 2.0 * n, 1.0 * n), 0.4, 0.15)
+    # FP32 state: a residual of 1e-10 leaves a divergence far below what the
+    # FP32 velocities resolve (the parity tests solve to 1e-13)
+    ph.cg_tol = 1e-10
     print(f"# generating the {n}^3 seamount initial state", file=sys.stderr, flush=True)
     s = inputs.convection_initial(ph, seed=0)
     m = oc.Model(ph, "fp32")

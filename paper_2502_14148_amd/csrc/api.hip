@@ -47,7 +47,7 @@ struct Layout {
   uint64_t baro[13], metric, hzeta, hpx, hpy, hmet;
   uint64_t gc[MAXF];
   uint64_t les_nu, les_kap[OC_MAX_TRACERS], les_d2;
-  uint64_t mask, cg_x, cg_r, cg_q, cg_aq, cg_part, cg_scal;
+  uint64_t mask, ibits, cg_x, cg_r, cg_q, cg_aq, cg_part, cg_scal;
   uint64_t zt64, ztT, vfac;
   uint64_t total;
 };
@@ -104,6 +104,7 @@ Layout make_layout(const oc_grid_desc& g, const oc_model_desc& m) {
   if (m.immersed) {
     const uint64_t nv = align256((uint64_t)g.nx * g.ny * g.nz * 8);
     L.mask = off; off += fb;
+    L.ibits = off; off += align256((uint64_t)g.nx * g.ny * g.nz);
     L.cg_x = off; off += nv;
     L.cg_r = off; off += nv;
     L.cg_q = off; off += nv;
@@ -395,6 +396,34 @@ std::vector<char> padded_mask(const oc_model* m, const uint8_t* solid) {
   return out;
 }
 
+// The per-cell geometry bytes of the conjugate-gradient kernels (IB_*):
+// fluid, and which faces are open (both neighbours fluid; walls closed).
+std::vector<uint8_t> geometry_bits(const oc_model* m, const uint8_t* solid) {
+  const Dims& d = m->dims;
+  const long n = (long)d.nx * d.ny * d.nz;
+  std::vector<uint8_t> out(n, 0);
+  auto fluid = [&](int i, int j, int k) {
+    i = (i + d.nx) % d.nx;
+    j = (j + d.ny) % d.ny;
+    k = (k + d.nz) % d.nz;
+    return !solid || solid[((size_t)k * d.ny + j) * d.nx + i] == 0;
+  };
+  for (int k = 0; k < d.nz; ++k)
+    for (int j = 0; j < d.ny; ++j)
+      for (int i = 0; i < d.nx; ++i) {
+        if (!fluid(i, j, k)) continue;
+        uint8_t b = IB_FLUID;
+        if (fluid(i - 1, j, k)) b |= IB_XM;
+        if (fluid(i + 1, j, k)) b |= IB_XP;
+        if (fluid(i, j - 1, k)) b |= IB_YM;
+        if (fluid(i, j + 1, k)) b |= IB_YP;
+        if ((!d.zb || k > 0) && fluid(i, j, k - 1)) b |= IB_ZM;
+        if ((!d.zb || k + 1 < d.nz) && fluid(i, j, k + 1)) b |= IB_ZP;
+        out[((size_t)k * d.ny + j) * d.nx + i] = b;
+      }
+  return out;
+}
+
 template <class T>
 int tendency_call(oc_model* m, int in, int out, int stage, double dt, int combine,
                   hipStream_t s) {
@@ -507,8 +536,8 @@ int pressure_call_immersed(oc_model* m, int which, double dt_eff, hipStream_t s)
   const double* z = m->sb.p;
   {
     ProfScope pc(m, OC_PROF_CG, s);
-    OC_CHECK_HIP(launch_ib_rhs<T>(d, u, v, w, mask, 1.0 / dt_eff, 1.0 / m->dx, 1.0 / m->dy,
-                                  1.0 / m->dz, cg, s));
+    OC_CHECK_HIP(launch_ib_rhs<T>(d, u, v, w, m->ibits, 1.0 / dt_eff, 1.0 / m->dx,
+                                  1.0 / m->dy, 1.0 / m->dz, cg, s));
     OC_CHECK_HIP(launch_ib_finalize(cg, CG_FIN_BNORM, tol2, maxit, s));
   }
   int rc = fft_solve_dense(m, cg.r, s);
@@ -517,14 +546,14 @@ int pressure_call_immersed(oc_model* m, int which, double dt_eff, hipStream_t s)
     ProfScope pc(m, OC_PROF_CG, s);
     OC_CHECK_HIP(launch_ib_dot(d, cg, z, s));
     OC_CHECK_HIP(launch_ib_finalize(cg, CG_FIN_RZ0, tol2, maxit, s));
-    OC_CHECK_HIP(launch_ib_dir<T>(d, mask, cg, z, s));
+    OC_CHECK_HIP(launch_ib_dir(d, m->ibits, cg, z, s));
   }
   const double rdx2 = 1.0 / (m->dx * m->dx), rdy2 = 1.0 / (m->dy * m->dy);
   const double rdz2 = 1.0 / (m->dz * m->dz);
   for (int it = 0; it < maxit; ++it) {
     {
       ProfScope pc(m, OC_PROF_CG, s);
-      OC_CHECK_HIP(launch_ib_apply<T>(d, mask, rdx2, rdy2, rdz2, cg, s));
+      OC_CHECK_HIP(launch_ib_apply(d, m->ibits, rdx2, rdy2, rdz2, cg, s));
       OC_CHECK_HIP(launch_ib_finalize(cg, CG_FIN_ALPHA, tol2, maxit, s));
       OC_CHECK_HIP(launch_ib_update(d, cg, s));
       OC_CHECK_HIP(launch_ib_finalize(cg, CG_FIN_RES, tol2, maxit, s));
@@ -539,7 +568,7 @@ int pressure_call_immersed(oc_model* m, int which, double dt_eff, hipStream_t s)
       ProfScope pc(m, OC_PROF_CG, s);
       OC_CHECK_HIP(launch_ib_dot(d, cg, z, s));
       OC_CHECK_HIP(launch_ib_finalize(cg, CG_FIN_BETA, tol2, maxit, s));
-      OC_CHECK_HIP(launch_ib_dir<T>(d, mask, cg, z, s));
+      OC_CHECK_HIP(launch_ib_dir(d, m->ibits, cg, z, s));
     }
   }
   m->cg_iterations = (int)m->cg_host[CG_IT];
@@ -548,7 +577,7 @@ int pressure_call_immersed(oc_model* m, int which, double dt_eff, hipStream_t s)
   Spacing sp{1.0 / m->dx, 1.0 / m->dy, m->zt64 + zt_rdzc(d.nz), m->zt64 + zt_rdzf(d.nz)};
   {
     ProfScope pc(m, OC_PROF_CG, s);
-    OC_CHECK_HIP(launch_ib_gauge<T>(d, mask, cg, m->nfluid, s));
+    OC_CHECK_HIP(launch_ib_gauge(d, m->ibits, cg, m->nfluid, s));
     OC_CHECK_HIP(hipMemcpyAsync(m->sb.p, cg.x, (size_t)d.nx * d.ny * d.nz * sizeof(double),
                                 hipMemcpyDeviceToDevice, s));
   }
@@ -1073,6 +1102,8 @@ int set_immersed_call(oc_model* m, const uint8_t* solid, hipStream_t s) {
     return OC_ERR_UNSUPPORTED;
   }
   OC_CHECK_HIP(hipMemcpyAsync(m->mask, host.data(), host.size(), hipMemcpyHostToDevice, s));
+  std::vector<uint8_t> bits = geometry_bits(m, solid);
+  OC_CHECK_HIP(hipMemcpyAsync(m->ibits, bits.data(), bits.size(), hipMemcpyHostToDevice, s));
   const int rc = mask_velocities_call<T>(m, s);
   if (rc) return rc;
   OC_CHECK_HIP(hipStreamSynchronize(s));  // the host copy of the mask goes out of scope
@@ -1216,6 +1247,7 @@ int oc_model_create(const oc_grid* g, const oc_model_desc* md, void* workspace,
     m->les_d2 = md->les ? (void*)(m->ws + L.les_d2) : nullptr;
   }
   m->mask = md->immersed ? (void*)(m->ws + L.mask) : nullptr;
+  m->ibits = md->immersed ? (uint8_t*)(m->ws + L.ibits) : nullptr;
   m->cg.x = (double*)(m->ws + L.cg_x);
   m->cg.r = (double*)(m->ws + L.cg_r);
   m->cg.q = (double*)(m->ws + L.cg_q);
@@ -1272,6 +1304,8 @@ int oc_model_create(const oc_grid* g, const oc_model_desc* md, void* workspace,
     // iteration's scalars
     std::vector<char> ones = padded_mask(m, nullptr);
     if (e == hipSuccess) e = hipMemcpy(m->mask, ones.data(), ones.size(), hipMemcpyHostToDevice);
+    std::vector<uint8_t> bits = geometry_bits(m, nullptr);
+    if (e == hipSuccess) e = hipMemcpy(m->ibits, bits.data(), bits.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipHostMalloc((void**)&m->cg_host, CG_NSCAL * sizeof(double));
   }
   if (e != hipSuccess) {

@@ -9,7 +9,9 @@
 // solve of the whole box (poisson.hip) applied to the residual, which is zero
 // in immersed cells, with its result masked to the fluid.
 //
-// Vectors are dense FP64 (nz, ny, nx), x fastest.  Reductions are
+// Vectors are dense FP64 (nz, ny, nx), x fastest; the geometry comes as one
+// byte per cell (IB_* bits: the cell is fluid, and which of its six faces
+// are open).  Reductions are
 // deterministic: every reducing kernel runs a fixed grid of IB_NPART
 // workgroups over a fixed grid-stride partition, each writing one partial
 // sum, and a single-workgroup kernel adds the partials in a fixed order and
@@ -35,11 +37,23 @@ __device__ inline double block_sum(double v, double* sh) {
   return sh[0];
 }
 
+// Workgroups are dealt round-robin to the 8 XCDs; the stencil kernels
+// renumber them so that each XCD sweeps a contiguous range of cells in every
+// round of the grid-stride loop, and the neighbouring planes a cell reads
+// stay in that XCD's L2.
+__device__ inline long first_cell() {
+  const unsigned nb = gridDim.x, b = blockIdx.x;
+  const unsigned vb = (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
+  return (long)vb * IB_NT + threadIdx.x;
+}
+
+// (i, j, k) of a dense index (32-bit arithmetic: N < 2^31)
 __device__ inline void cell_of(const Dims& d, long n, int& i, int& j, int& k) {
-  i = (int)(n % d.nx);
-  const long r = n / d.nx;
-  j = (int)(r % d.ny);
-  k = (int)(r / d.ny);
+  const unsigned u = (unsigned)n, nx = (unsigned)d.nx, ny = (unsigned)d.ny;
+  const unsigned r = u / nx;
+  i = (int)(u - r * nx);
+  k = (int)(r / ny);
+  j = (int)(r - (unsigned)k * ny);
 }
 
 // b = div(u~) / dt_eff in fluid cells (face velocities times their open
@@ -48,34 +62,25 @@ template <class T>
 __global__ void __launch_bounds__(IB_NT) ib_rhs_kernel(Dims d, const T* __restrict__ u,
                                                        const T* __restrict__ v,
                                                        const T* __restrict__ w,
-                                                       const T* __restrict__ mask, double inv_dt,
-                                                       double rdx, double rdy, double rdz,
-                                                       CgBufs cg) {
+                                                       const uint8_t* __restrict__ bits,
+                                                       double inv_dt, double rdx, double rdy,
+                                                       double rdz, CgBufs cg) {
   __shared__ double sh[IB_NT];
   const long N = (long)d.nx * d.ny * d.nz;
   double acc = 0.0;
-  for (long n = blockIdx.x * (long)IB_NT + threadIdx.x; n < N; n += (long)gridDim.x * IB_NT) {
-    int i, j, k;
-    cell_of(d, n, i, j, k);
-    const long c = pidx(d, i, j, k);
-    const double m0 = (double)mask[c];
+  for (long n = first_cell(); n < N; n += (long)gridDim.x * IB_NT) {
+    const unsigned fb = bits[n];
     double b = 0.0;
-    if (m0 != 0.0) {
-      const long cx = pidx(d, (i + 1 == d.nx) ? 0 : i + 1, j, k);
-      const long cy = pidx(d, i, (j + 1 == d.ny) ? 0 : j + 1, k);
-      const double ul = (double)u[c] * (double)mask[c - 1];
-      const double ur = (double)u[cx] * (double)mask[cx] * (double)mask[cx - 1];
-      const double vl = (double)v[c] * (double)mask[c - d.sy];
-      const double vr = (double)v[cy] * (double)mask[cy] * (double)mask[cy - d.sy];
-      double wb, wt;
-      if (d.zb) {
-        wb = (k == 0) ? 0.0 : (double)w[c] * (double)mask[c - d.sz];
-        wt = (k + 1 == d.nz) ? 0.0 : (double)w[c + d.sz] * (double)mask[c + d.sz];
-      } else {
-        const long cz = pidx(d, i, j, (k + 1 == d.nz) ? 0 : k + 1);
-        wb = (double)w[c] * (double)mask[c - d.sz];
-        wt = (double)w[cz] * (double)mask[cz] * (double)mask[cz - d.sz];
-      }
+    if (fb & IB_FLUID) {
+      int i, j, k;
+      cell_of(d, n, i, j, k);
+      const long c = pidx(d, i, j, k);
+      const double ul = (fb & IB_XM) ? (double)u[c] : 0.0;
+      const double ur = (fb & IB_XP) ? (double)u[pidx(d, (i + 1 == d.nx) ? 0 : i + 1, j, k)] : 0.0;
+      const double vl = (fb & IB_YM) ? (double)v[c] : 0.0;
+      const double vr = (fb & IB_YP) ? (double)v[pidx(d, i, (j + 1 == d.ny) ? 0 : j + 1, k)] : 0.0;
+      const double wb = (fb & IB_ZM) ? (double)w[c] : 0.0;
+      const double wt = (fb & IB_ZP) ? (double)w[pidx(d, i, j, (k + 1 == d.nz) ? 0 : k + 1)] : 0.0;
       b = ((ur - ul) * rdx + (vr - vl) * rdy + (wt - wb) * rdz) * inv_dt;
     }
     cg.r[n] = b;
@@ -88,8 +93,7 @@ __global__ void __launch_bounds__(IB_NT) ib_rhs_kernel(Dims d, const T* __restri
 
 // aq = A q (the masked 7-point operator, zero in immersed cells); partial
 // sums of q . aq.
-template <class T>
-__global__ void __launch_bounds__(IB_NT) ib_apply_kernel(Dims d, const T* __restrict__ mask,
+__global__ void __launch_bounds__(IB_NT) ib_apply_kernel(Dims d, const uint8_t* __restrict__ bits,
                                                          double rdx2, double rdy2, double rdz2,
                                                          CgBufs cg) {
   __shared__ double sh[IB_NT];
@@ -98,31 +102,24 @@ __global__ void __launch_bounds__(IB_NT) ib_apply_kernel(Dims d, const T* __rest
   const long plane = (long)d.nx * d.ny;
   const double* __restrict__ q = cg.q;
   double acc = 0.0;
-  for (long n = blockIdx.x * (long)IB_NT + threadIdx.x; n < N; n += (long)gridDim.x * IB_NT) {
+  for (long n = first_cell(); n < N; n += (long)gridDim.x * IB_NT) {
+    // every neighbour is loaded (all loads in flight at once) and weighted
+    // by its face's open flag; z neighbours beyond a wall are read from the
+    // periodic image, which the flag then discards
+    const unsigned fb = bits[n];
+    const double q0 = q[n];
     int i, j, k;
     cell_of(d, n, i, j, k);
-    const long c = pidx(d, i, j, k);
-    double a = 0.0;
-    const double q0 = q[n];
-    if ((double)mask[c] != 0.0) {
-      const long nxm = (i == 0) ? n + d.nx - 1 : n - 1;
-      const long nxp = (i + 1 == d.nx) ? n - (d.nx - 1) : n + 1;
-      const long nym = (j == 0) ? n + plane - d.nx : n - d.nx;
-      const long nyp = (j + 1 == d.ny) ? n - plane + d.nx : n + d.nx;
-      a += (double)mask[c - 1] * (q[nxm] - q0) * rdx2;
-      a += (double)mask[c + 1] * (q[nxp] - q0) * rdx2;
-      a += (double)mask[c - d.sy] * (q[nym] - q0) * rdy2;
-      a += (double)mask[c + d.sy] * (q[nyp] - q0) * rdy2;
-      if (d.zb) {
-        if (k > 0) a += (double)mask[c - d.sz] * (q[n - plane] - q0) * rdz2;
-        if (k + 1 < d.nz) a += (double)mask[c + d.sz] * (q[n + plane] - q0) * rdz2;
-      } else {
-        const long nzm = (k == 0) ? n + (long)(d.nz - 1) * plane : n - plane;
-        const long nzp = (k + 1 == d.nz) ? n - (long)(d.nz - 1) * plane : n + plane;
-        a += (double)mask[c - d.sz] * (q[nzm] - q0) * rdz2;
-        a += (double)mask[c + d.sz] * (q[nzp] - q0) * rdz2;
-      }
-    }
+    const double qxm = q[(i == 0) ? n + d.nx - 1 : n - 1];
+    const double qxp = q[(i + 1 == d.nx) ? n - (d.nx - 1) : n + 1];
+    const double qym = q[(j == 0) ? n + plane - d.nx : n - d.nx];
+    const double qyp = q[(j + 1 == d.ny) ? n - plane + d.nx : n + d.nx];
+    const double qzm = q[(k == 0) ? n + (long)(d.nz - 1) * plane : n - plane];
+    const double qzp = q[(k + 1 == d.nz) ? n - (long)(d.nz - 1) * plane : n + plane];
+    auto on = [fb](unsigned bit) { return (fb & bit) ? 1.0 : 0.0; };
+    const double a = (on(IB_XM) * (qxm - q0) + on(IB_XP) * (qxp - q0)) * rdx2 +
+                     (on(IB_YM) * (qym - q0) + on(IB_YP) * (qyp - q0)) * rdy2 +
+                     (on(IB_ZM) * (qzm - q0) + on(IB_ZP) * (qzp - q0)) * rdz2;
     cg.aq[n] = a;
     acc += q0 * a;
   }
@@ -159,18 +156,13 @@ __global__ void __launch_bounds__(IB_NT) ib_dot_kernel(long N, CgBufs cg,
   if (threadIdx.x == 0) cg.part[blockIdx.x] = s;
 }
 
-// q = mask z + beta q
-template <class T>
-__global__ void __launch_bounds__(IB_NT) ib_dir_kernel(Dims d, const T* __restrict__ mask,
+// q = (z in fluid cells) + beta q
+__global__ void __launch_bounds__(IB_NT) ib_dir_kernel(long N, const uint8_t* __restrict__ bits,
                                                        CgBufs cg, const double* __restrict__ z) {
   if (cg.scal[CG_DONE] != 0.0) return;
-  const long N = (long)d.nx * d.ny * d.nz;
   const double beta = cg.scal[CG_BETA];
-  for (long n = blockIdx.x * (long)IB_NT + threadIdx.x; n < N; n += (long)gridDim.x * IB_NT) {
-    int i, j, k;
-    cell_of(d, n, i, j, k);
-    cg.q[n] = (double)mask[pidx(d, i, j, k)] * z[n] + beta * cg.q[n];
-  }
+  for (long n = blockIdx.x * (long)IB_NT + threadIdx.x; n < N; n += (long)gridDim.x * IB_NT)
+    cg.q[n] = ((bits[n] & IB_FLUID) ? z[n] : 0.0) + beta * cg.q[n];
 }
 
 // partial sums of x (zero in immersed cells) for the gauge
@@ -184,16 +176,11 @@ __global__ void __launch_bounds__(IB_NT) ib_sum_kernel(long N, CgBufs cg) {
 }
 
 // x -= mean over the fluid cells, in fluid cells
-template <class T>
-__global__ void __launch_bounds__(IB_NT) ib_shift_kernel(Dims d, const T* __restrict__ mask,
+__global__ void __launch_bounds__(IB_NT) ib_shift_kernel(long N, const uint8_t* __restrict__ bits,
                                                          CgBufs cg) {
-  const long N = (long)d.nx * d.ny * d.nz;
   const double mean = cg.scal[CG_MEAN];
-  for (long n = blockIdx.x * (long)IB_NT + threadIdx.x; n < N; n += (long)gridDim.x * IB_NT) {
-    int i, j, k;
-    cell_of(d, n, i, j, k);
-    cg.x[n] = (double)mask[pidx(d, i, j, k)] * (cg.x[n] - mean);
-  }
+  for (long n = blockIdx.x * (long)IB_NT + threadIdx.x; n < N; n += (long)gridDim.x * IB_NT)
+    cg.x[n] = (bits[n] & IB_FLUID) ? cg.x[n] - mean : 0.0;
 }
 
 // Add the IB_NPART partials in a fixed order and update the scalars.
@@ -263,18 +250,17 @@ int ib_grid(long N) {
 // Every reducing kernel uses exactly IB_NPART workgroups (the partial array
 // is read whole); the others use up to that many.
 template <class T>
-hipError_t launch_ib_rhs(const Dims& d, const T* u, const T* v, const T* w, const T* mask,
-                         double inv_dt, double rdx, double rdy, double rdz, const CgBufs& cg,
-                         hipStream_t s) {
-  hipLaunchKernelGGL(ib_rhs_kernel<T>, dim3(IB_NPART), dim3(IB_NT), 0, s, d, u, v, w, mask,
+hipError_t launch_ib_rhs(const Dims& d, const T* u, const T* v, const T* w,
+                         const uint8_t* bits, double inv_dt, double rdx, double rdy, double rdz,
+                         const CgBufs& cg, hipStream_t s) {
+  hipLaunchKernelGGL(ib_rhs_kernel<T>, dim3(IB_NPART), dim3(IB_NT), 0, s, d, u, v, w, bits,
                      inv_dt, rdx, rdy, rdz, cg);
   return hipGetLastError();
 }
 
-template <class T>
-hipError_t launch_ib_apply(const Dims& d, const T* mask, double rdx2, double rdy2, double rdz2,
-                           const CgBufs& cg, hipStream_t s) {
-  hipLaunchKernelGGL(ib_apply_kernel<T>, dim3(IB_NPART), dim3(IB_NT), 0, s, d, mask, rdx2, rdy2,
+hipError_t launch_ib_apply(const Dims& d, const uint8_t* bits, double rdx2, double rdy2,
+                           double rdz2, const CgBufs& cg, hipStream_t s) {
+  hipLaunchKernelGGL(ib_apply_kernel, dim3(IB_NPART), dim3(IB_NT), 0, s, d, bits, rdx2, rdy2,
                      rdz2, cg);
   return hipGetLastError();
 }
@@ -291,22 +277,20 @@ hipError_t launch_ib_dot(const Dims& d, const CgBufs& cg, const double* z, hipSt
   return hipGetLastError();
 }
 
-template <class T>
-hipError_t launch_ib_dir(const Dims& d, const T* mask, const CgBufs& cg, const double* z,
+hipError_t launch_ib_dir(const Dims& d, const uint8_t* bits, const CgBufs& cg, const double* z,
                          hipStream_t s) {
-  hipLaunchKernelGGL(ib_dir_kernel<T>, dim3(ib_grid((long)d.nx * d.ny * d.nz)), dim3(IB_NT), 0, s,
-                     d, mask, cg, z);
+  const long N = (long)d.nx * d.ny * d.nz;
+  hipLaunchKernelGGL(ib_dir_kernel, dim3(ib_grid(N)), dim3(IB_NT), 0, s, N, bits, cg, z);
   return hipGetLastError();
 }
 
-template <class T>
-hipError_t launch_ib_gauge(const Dims& d, const T* mask, const CgBufs& cg, double nfluid,
+hipError_t launch_ib_gauge(const Dims& d, const uint8_t* bits, const CgBufs& cg, double nfluid,
                            hipStream_t s) {
   const long N = (long)d.nx * d.ny * d.nz;
   hipLaunchKernelGGL(ib_sum_kernel, dim3(IB_NPART), dim3(IB_NT), 0, s, N, cg);
   hipLaunchKernelGGL(ib_finalize_kernel, dim3(1), dim3(IB_NT), 0, s, cg, (int)CG_FIN_MEAN, 0.0, 0,
                      nfluid);
-  hipLaunchKernelGGL(ib_shift_kernel<T>, dim3(ib_grid(N)), dim3(IB_NT), 0, s, d, mask, cg);
+  hipLaunchKernelGGL(ib_shift_kernel, dim3(ib_grid(N)), dim3(IB_NT), 0, s, N, bits, cg);
   return hipGetLastError();
 }
 
@@ -326,15 +310,9 @@ hipError_t launch_ib_mask_velocity(const Dims& d, T* u, T* v, T* w, const T* mas
 }
 
 #define OC_IB_INST(T)                                                                        \
-  template hipError_t launch_ib_rhs<T>(const Dims&, const T*, const T*, const T*, const T*,   \
-                                       double, double, double, double, const CgBufs&,         \
-                                       hipStream_t);                                          \
-  template hipError_t launch_ib_apply<T>(const Dims&, const T*, double, double, double,       \
-                                         const CgBufs&, hipStream_t);                         \
-  template hipError_t launch_ib_dir<T>(const Dims&, const T*, const CgBufs&, const double*,   \
-                                       hipStream_t);                                          \
-  template hipError_t launch_ib_gauge<T>(const Dims&, const T*, const CgBufs&, double,        \
-                                         hipStream_t);                                        \
+  template hipError_t launch_ib_rhs<T>(const Dims&, const T*, const T*, const T*,             \
+                                       const uint8_t*, double, double, double, double,        \
+                                       const CgBufs&, hipStream_t);                           \
   template hipError_t launch_ib_mask_velocity<T>(const Dims&, T*, T*, T*, const T*,           \
                                                  hipStream_t);
 OC_IB_INST(float)

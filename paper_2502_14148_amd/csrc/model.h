@@ -98,6 +98,7 @@ struct oc_model {
   // conjugate-gradient vectors and scalars, pinned host copy of the scalars,
   // the number of fluid cells and the last solve's statistics
   void* mask;
+  uint8_t* ibits;        // per-cell geometry bytes (IB_*), dense
   CgBufs cg;
   double* cg_host;
   double nfluid;

@@ -397,7 +397,7 @@ hipError_t launch_poisson_x_forward_dense(const Dims& d, const double* src, cons
 // on dense FP64 (nz, ny, nx) vectors.  Reducing kernels run IB_NPART
 // workgroups and leave one partial sum each in part; launch_ib_finalize adds
 // them in a fixed order and updates the scalars in scal (indices CG_*).
-constexpr int IB_NPART = 1024;
+constexpr int IB_NPART = 4096;
 enum { CG_RZ = 0, CG_ALPHA, CG_BETA, CG_BNORM2, CG_RNORM2, CG_IT, CG_DONE, CG_MEAN, CG_NSCAL };
 enum { CG_FIN_BNORM = 0, CG_FIN_RZ0, CG_FIN_ALPHA, CG_FIN_RES, CG_FIN_BETA, CG_FIN_MEAN };
 struct CgBufs {
@@ -408,20 +408,20 @@ struct CgBufs {
   double* part;  // IB_NPART partial sums
   double* scal;  // CG_NSCAL scalars
 };
+// Per-cell geometry byte (dense, x fastest): the cell is fluid, and which of
+// its faces are open (both neighbours fluid; walls closed).
+enum { IB_XM = 1, IB_XP = 2, IB_YM = 4, IB_YP = 8, IB_ZM = 16, IB_ZP = 32, IB_FLUID = 64 };
 template <class T>
-hipError_t launch_ib_rhs(const Dims& d, const T* u, const T* v, const T* w, const T* mask,
-                         double inv_dt, double rdx, double rdy, double rdz, const CgBufs& cg,
-                         hipStream_t s);
-template <class T>
-hipError_t launch_ib_apply(const Dims& d, const T* mask, double rdx2, double rdy2, double rdz2,
-                           const CgBufs& cg, hipStream_t s);
+hipError_t launch_ib_rhs(const Dims& d, const T* u, const T* v, const T* w,
+                         const uint8_t* bits, double inv_dt, double rdx, double rdy, double rdz,
+                         const CgBufs& cg, hipStream_t s);
+hipError_t launch_ib_apply(const Dims& d, const uint8_t* bits, double rdx2, double rdy2,
+                           double rdz2, const CgBufs& cg, hipStream_t s);
 hipError_t launch_ib_update(const Dims& d, const CgBufs& cg, hipStream_t s);
 hipError_t launch_ib_dot(const Dims& d, const CgBufs& cg, const double* z, hipStream_t s);
-template <class T>
-hipError_t launch_ib_dir(const Dims& d, const T* mask, const CgBufs& cg, const double* z,
+hipError_t launch_ib_dir(const Dims& d, const uint8_t* bits, const CgBufs& cg, const double* z,
                          hipStream_t s);
-template <class T>
-hipError_t launch_ib_gauge(const Dims& d, const T* mask, const CgBufs& cg, double nfluid,
+hipError_t launch_ib_gauge(const Dims& d, const uint8_t* bits, const CgBufs& cg, double nfluid,
                            hipStream_t s);
 hipError_t launch_ib_finalize(const CgBufs& cg, int what, double tol2, int maxiter,
                               hipStream_t s);
