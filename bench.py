@@ -363,11 +363,12 @@ def run_weno_high(steps, warmup, n):
 
 
 # Algorithmic HBM bytes per cell of one conjugate-gradient iteration of the
-# immersed-boundary pressure solve (FP64 vectors, FP32 mask): A q reads q and
-# the mask, writes A q (20 B); the update reads x, q, r, A q and writes x, r
-# (48 B); r . z reads r and z (16 B); the new direction reads z, q, the mask
-# and writes q (28 B).  The preconditioner's five FFT passes come on top.
-CG_BYTES_PER_CELL_ITER = 20 + 48 + 16 + 28
+# immersed-boundary pressure solve (FP64 vectors, a geometry byte per cell,
+# counted as 4 B): A q reads q and the geometry, writes A q (20 B); the
+# residual update reads r and A q and writes r (24 B); the direction update
+# reads x, q, z and writes x, q (40 B).  The preconditioner's five FFT passes
+# (r . z is summed in the last one) come on top.
+CG_BYTES_PER_CELL_ITER = 20 + 24 + 40
 
 
 def run_immersed(steps, warmup, n):

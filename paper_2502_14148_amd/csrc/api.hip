@@ -109,7 +109,7 @@ Layout make_layout(const oc_grid_desc& g, const oc_model_desc& m) {
     L.cg_r = off; off += nv;
     L.cg_q = off; off += nv;
     L.cg_aq = off; off += nv;
-    L.cg_part = off; off += align256((uint64_t)IB_NPART * 8);
+    L.cg_part = off; off += align256((uint64_t)IB_PART_CAP * 8);
     L.cg_scal = off; off += align256((uint64_t)CG_NSCAL * 8);
   }
   L.zt64 = off; off += align256((uint64_t)zt64_len(g.nz) * 8);
@@ -493,8 +493,9 @@ int tendency_call(oc_model* m, int in, int out, int stage, double dt, int combin
 }
 
 // The FFT/DCT solve of the whole box applied to a dense FP64 field: sb.p =
-// L^-1 src (the preconditioner of the immersed-boundary iteration).
-int fft_solve_dense(oc_model* m, const double* src, hipStream_t s) {
+// L^-1 src (the preconditioner of the immersed-boundary iteration); the last
+// pass also leaves the partial sums of src . sb.p in cg.part (*npart).
+int fft_solve_dense(oc_model* m, const double* src, int* npart, hipStream_t s) {
   {
     ProfScope ps(m, OC_PROF_FFT_X_FWD, s);
     OC_CHECK_HIP(launch_poisson_x_forward_dense(m->dims, src, m->sb, s));
@@ -513,7 +514,8 @@ int fft_solve_dense(oc_model* m, const double* src, hipStream_t s) {
   }
   {
     ProfScope ps(m, OC_PROF_FFT_X_INV, s);
-    OC_CHECK_HIP(launch_poisson_x_inverse(m->dims, m->sb, s));
+    OC_CHECK_HIP(launch_poisson_x_inverse_dot(m->dims, m->sb, src, m->cg.part, IB_PART_CAP, npart,
+                                              s));
   }
   return OC_OK;
 }
@@ -540,12 +542,12 @@ int pressure_call_immersed(oc_model* m, int which, double dt_eff, hipStream_t s)
                                   1.0 / m->dy, 1.0 / m->dz, cg, s));
     OC_CHECK_HIP(launch_ib_finalize(cg, CG_FIN_BNORM, tol2, maxit, s));
   }
-  int rc = fft_solve_dense(m, cg.r, s);
+  int npart = 0;
+  int rc = fft_solve_dense(m, cg.r, &npart, s);
   if (rc) return rc;
   {
     ProfScope pc(m, OC_PROF_CG, s);
-    OC_CHECK_HIP(launch_ib_dot(d, cg, z, s));
-    OC_CHECK_HIP(launch_ib_finalize(cg, CG_FIN_RZ0, tol2, maxit, s));
+    OC_CHECK_HIP(launch_ib_finalize(cg, CG_FIN_RZ0, tol2, maxit, s, npart));
     OC_CHECK_HIP(launch_ib_dir(d, m->ibits, cg, z, s));
   }
   const double rdx2 = 1.0 / (m->dx * m->dx), rdy2 = 1.0 / (m->dy * m->dy);
@@ -562,14 +564,17 @@ int pressure_call_immersed(oc_model* m, int which, double dt_eff, hipStream_t s)
                                 hipMemcpyDeviceToHost, s));
     OC_CHECK_HIP(hipStreamSynchronize(s));
     if (m->cg_host[CG_DONE] != 0.0) break;
-    rc = fft_solve_dense(m, cg.r, s);
+    rc = fft_solve_dense(m, cg.r, &npart, s);
     if (rc) return rc;
     {
       ProfScope pc(m, OC_PROF_CG, s);
-      OC_CHECK_HIP(launch_ib_dot(d, cg, z, s));
-      OC_CHECK_HIP(launch_ib_finalize(cg, CG_FIN_BETA, tol2, maxit, s));
+      OC_CHECK_HIP(launch_ib_finalize(cg, CG_FIN_BETA, tol2, maxit, s, npart));
       OC_CHECK_HIP(launch_ib_dir(d, m->ibits, cg, z, s));
     }
+  }
+  {
+    ProfScope pc(m, OC_PROF_CG, s);
+    OC_CHECK_HIP(launch_ib_xfinal(d, cg, s));
   }
   m->cg_iterations = (int)m->cg_host[CG_IT];
   m->cg_residual = m->cg_host[CG_BNORM2] > 0

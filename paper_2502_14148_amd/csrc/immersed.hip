@@ -127,14 +127,14 @@ __global__ void __launch_bounds__(IB_NT) ib_apply_kernel(Dims d, const uint8_t* 
   if (threadIdx.x == 0) cg.part[blockIdx.x] = s;
 }
 
-// x += alpha q, r -= alpha aq; partial sums of r^2.
+// r -= alpha aq; partial sums of r^2 (x takes alpha q in ib_dir_kernel, or
+// in ib_xfinal_kernel after the last iteration).
 __global__ void __launch_bounds__(IB_NT) ib_update_kernel(long N, CgBufs cg) {
   __shared__ double sh[IB_NT];
   if (cg.scal[CG_DONE] != 0.0) return;
   const double alpha = cg.scal[CG_ALPHA];
   double acc = 0.0;
   for (long n = blockIdx.x * (long)IB_NT + threadIdx.x; n < N; n += (long)gridDim.x * IB_NT) {
-    cg.x[n] += alpha * cg.q[n];
     const double r = cg.r[n] - alpha * cg.aq[n];
     cg.r[n] = r;
     acc += r * r;
@@ -143,26 +143,26 @@ __global__ void __launch_bounds__(IB_NT) ib_update_kernel(long N, CgBufs cg) {
   if (threadIdx.x == 0) cg.part[blockIdx.x] = s;
 }
 
-// partial sums of r . z (z, the preconditioned residual, need not be masked:
-// r is zero in immersed cells)
-__global__ void __launch_bounds__(IB_NT) ib_dot_kernel(long N, CgBufs cg,
-                                                       const double* __restrict__ z) {
-  __shared__ double sh[IB_NT];
-  if (cg.scal[CG_DONE] != 0.0) return;
-  double acc = 0.0;
-  for (long n = blockIdx.x * (long)IB_NT + threadIdx.x; n < N; n += (long)gridDim.x * IB_NT)
-    acc += cg.r[n] * z[n];
-  const double s = block_sum(acc, sh);
-  if (threadIdx.x == 0) cg.part[blockIdx.x] = s;
-}
-
-// q = (z in fluid cells) + beta q
+// x += alpha q (the step of the iteration that just ended; alpha = 0 before
+// the first), then q = (z in fluid cells) + beta q
 __global__ void __launch_bounds__(IB_NT) ib_dir_kernel(long N, const uint8_t* __restrict__ bits,
                                                        CgBufs cg, const double* __restrict__ z) {
   if (cg.scal[CG_DONE] != 0.0) return;
   const double beta = cg.scal[CG_BETA];
+  const double alpha = cg.scal[CG_IT] > 0.0 ? cg.scal[CG_ALPHA] : 0.0;
+  for (long n = blockIdx.x * (long)IB_NT + threadIdx.x; n < N; n += (long)gridDim.x * IB_NT) {
+    const double q = cg.q[n];
+    if (alpha != 0.0) cg.x[n] += alpha * q;
+    cg.q[n] = ((bits[n] & IB_FLUID) ? z[n] : 0.0) + (beta != 0.0 ? beta * q : 0.0);
+  }
+}
+
+// after the last iteration: x += alpha q (nothing if no iteration ran)
+__global__ void __launch_bounds__(IB_NT) ib_xfinal_kernel(long N, CgBufs cg) {
+  if (cg.scal[CG_IT] == 0.0) return;
+  const double alpha = cg.scal[CG_ALPHA];
   for (long n = blockIdx.x * (long)IB_NT + threadIdx.x; n < N; n += (long)gridDim.x * IB_NT)
-    cg.q[n] = ((bits[n] & IB_FLUID) ? z[n] : 0.0) + beta * cg.q[n];
+    cg.x[n] += alpha * cg.q[n];
 }
 
 // partial sums of x (zero in immersed cells) for the gauge
@@ -185,12 +185,13 @@ __global__ void __launch_bounds__(IB_NT) ib_shift_kernel(long N, const uint8_t* 
 
 // Add the IB_NPART partials in a fixed order and update the scalars.
 __global__ void __launch_bounds__(IB_NT) ib_finalize_kernel(CgBufs cg, int what, double tol2,
-                                                            int maxiter, double nfluid) {
+                                                            int maxiter, double nfluid,
+                                                            int npart) {
   __shared__ double sh[IB_NT];
   double* sc = cg.scal;
   if (what != CG_FIN_MEAN && what != CG_FIN_BNORM && sc[CG_DONE] != 0.0) return;
   double acc = 0.0;
-  for (int b = threadIdx.x; b < IB_NPART; b += IB_NT) acc += cg.part[b];
+  for (int b = threadIdx.x; b < npart; b += IB_NT) acc += cg.part[b];
   const double s = block_sum(acc, sh);
   if (threadIdx.x != 0) return;
   switch (what) {
@@ -271,12 +272,6 @@ hipError_t launch_ib_update(const Dims& d, const CgBufs& cg, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_ib_dot(const Dims& d, const CgBufs& cg, const double* z, hipStream_t s) {
-  hipLaunchKernelGGL(ib_dot_kernel, dim3(IB_NPART), dim3(IB_NT), 0, s, (long)d.nx * d.ny * d.nz,
-                     cg, z);
-  return hipGetLastError();
-}
-
 hipError_t launch_ib_dir(const Dims& d, const uint8_t* bits, const CgBufs& cg, const double* z,
                          hipStream_t s) {
   const long N = (long)d.nx * d.ny * d.nz;
@@ -289,15 +284,21 @@ hipError_t launch_ib_gauge(const Dims& d, const uint8_t* bits, const CgBufs& cg,
   const long N = (long)d.nx * d.ny * d.nz;
   hipLaunchKernelGGL(ib_sum_kernel, dim3(IB_NPART), dim3(IB_NT), 0, s, N, cg);
   hipLaunchKernelGGL(ib_finalize_kernel, dim3(1), dim3(IB_NT), 0, s, cg, (int)CG_FIN_MEAN, 0.0, 0,
-                     nfluid);
+                     nfluid, (int)IB_NPART);
   hipLaunchKernelGGL(ib_shift_kernel, dim3(ib_grid(N)), dim3(IB_NT), 0, s, N, bits, cg);
   return hipGetLastError();
 }
 
 hipError_t launch_ib_finalize(const CgBufs& cg, int what, double tol2, int maxiter,
-                              hipStream_t s) {
+                              hipStream_t s, int npart) {
   hipLaunchKernelGGL(ib_finalize_kernel, dim3(1), dim3(IB_NT), 0, s, cg, what, tol2, maxiter,
-                     1.0);
+                     1.0, npart);
+  return hipGetLastError();
+}
+
+hipError_t launch_ib_xfinal(const Dims& d, const CgBufs& cg, hipStream_t s) {
+  const long N = (long)d.nx * d.ny * d.nz;
+  hipLaunchKernelGGL(ib_xfinal_kernel, dim3(ib_grid(N)), dim3(IB_NT), 0, s, N, cg);
   return hipGetLastError();
 }
 

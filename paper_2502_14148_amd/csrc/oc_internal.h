@@ -392,12 +392,17 @@ hipError_t launch_project(const Dims& d, T* u, T* v, T* w, double scale, const S
 // (the first pass of the FFT solve applied to a given right-hand side).
 hipError_t launch_poisson_x_forward_dense(const Dims& d, const double* src, const SpecBufs& sb,
                                           hipStream_t s);
+// The inverse x pass that also leaves partial sums of rdot . p (one per
+// workgroup, *npart of them, at most part_cap) in part.
+hipError_t launch_poisson_x_inverse_dot(const Dims& d, const SpecBufs& sb, const double* rdot,
+                                        double* part, int part_cap, int* npart, hipStream_t s);
 
 // ---- Immersed boundaries (immersed.hip): preconditioned conjugate gradients
 // on dense FP64 (nz, ny, nx) vectors.  Reducing kernels run IB_NPART
 // workgroups and leave one partial sum each in part; launch_ib_finalize adds
 // them in a fixed order and updates the scalars in scal (indices CG_*).
 constexpr int IB_NPART = 4096;
+constexpr int IB_PART_CAP = 16384;   // room for the partials of the fused inverse pass
 enum { CG_RZ = 0, CG_ALPHA, CG_BETA, CG_BNORM2, CG_RNORM2, CG_IT, CG_DONE, CG_MEAN, CG_NSCAL };
 enum { CG_FIN_BNORM = 0, CG_FIN_RZ0, CG_FIN_ALPHA, CG_FIN_RES, CG_FIN_BETA, CG_FIN_MEAN };
 struct CgBufs {
@@ -418,13 +423,13 @@ hipError_t launch_ib_rhs(const Dims& d, const T* u, const T* v, const T* w,
 hipError_t launch_ib_apply(const Dims& d, const uint8_t* bits, double rdx2, double rdy2,
                            double rdz2, const CgBufs& cg, hipStream_t s);
 hipError_t launch_ib_update(const Dims& d, const CgBufs& cg, hipStream_t s);
-hipError_t launch_ib_dot(const Dims& d, const CgBufs& cg, const double* z, hipStream_t s);
 hipError_t launch_ib_dir(const Dims& d, const uint8_t* bits, const CgBufs& cg, const double* z,
                          hipStream_t s);
 hipError_t launch_ib_gauge(const Dims& d, const uint8_t* bits, const CgBufs& cg, double nfluid,
                            hipStream_t s);
 hipError_t launch_ib_finalize(const CgBufs& cg, int what, double tol2, int maxiter,
-                              hipStream_t s);
+                              hipStream_t s, int npart = IB_NPART);
+hipError_t launch_ib_xfinal(const Dims& d, const CgBufs& cg, hipStream_t s);
 template <class T>
 hipError_t launch_ib_mask_velocity(const Dims& d, T* u, T* v, T* w, const T* mask,
                                    hipStream_t s);

@@ -474,9 +474,14 @@ __global__ void __launch_bounds__(NT) z_tridiag_kernel(Dims d, SpecBufs sb, doub
 // ---------------------------------------------------------------------------
 // Pass 5: complex-to-real inverse FFT along x for line pairs -> p.
 // ---------------------------------------------------------------------------
+// rdot != null: also the partial sum of rdot . p over the values this
+// workgroup writes, into part[blockIdx.y * gridDim.x + blockIdx.x] (the r . z
+// of the immersed-boundary iteration).
 template <int N>
 __global__ void __launch_bounds__(NT) inv_x_kernel(Dims d, SpecBufs sb,
-                                                   const PoissonSlots* __restrict__ bs) {
+                                                   const PoissonSlots* __restrict__ bs,
+                                                   const double* __restrict__ rdot,
+                                                   double* __restrict__ part) {
   if (bs) {
     sb.spec = bs->spec[blockIdx.z];
     sb.p = bs->p[blockIdx.z];
@@ -508,6 +513,7 @@ __global__ void __launch_bounds__(NT) inv_x_kernel(Dims d, SpecBufs sb,
   }
   __syncthreads();
   fft_lines<N, 1, LP, NT, 1, false>(buf, N, 1, tws);
+  double acc = 0.0;
   for (int t = threadIdx.x; t < LP * N; t += NT) {
     const int l = t / N, i = t % N;
     const int pr = pair0 + l;
@@ -515,6 +521,18 @@ __global__ void __launch_bounds__(NT) inv_x_kernel(Dims d, SpecBufs sb,
     const long base = ((long)k * d.ny + 2 * pr) * d.nx + i;
     sb.p[base] = buf[t].x;
     sb.p[base + d.nx] = buf[t].y;
+    if (rdot) acc += rdot[base] * buf[t].x + rdot[base + d.nx] * buf[t].y;
+  }
+  if (rdot) {
+    __shared__ double red[NT];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+#pragma unroll
+    for (int h = NT / 2; h > 0; h >>= 1) {
+      if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.y * gridDim.x + blockIdx.x] = red[0];
   }
 }
 
@@ -702,10 +720,26 @@ hipError_t launch_poisson_x_inverse(const Dims& d, const SpecBufs& sb, hipStream
 #define OC_LAUNCH_XI(N)                                                                    \
   {                                                                                        \
     dim3 grid((d.ny / 2 + XCfg<N>::LP - 1) / XCfg<N>::LP, d.nz, nslots);                  \
-    hipLaunchKernelGGL((inv_x_kernel<N>), grid, dim3(NT), 0, s, d, sb, bs);               \
+    hipLaunchKernelGGL((inv_x_kernel<N>), grid, dim3(NT), 0, s, d, sb, bs,                \
+                       (const double*)nullptr, (double*)nullptr);                          \
   }
   OC_FFT_DISPATCH(d.nx, OC_LAUNCH_XI)
 #undef OC_LAUNCH_XI
+  return hipGetLastError();
+}
+
+hipError_t launch_poisson_x_inverse_dot(const Dims& d, const SpecBufs& sb, const double* rdot,
+                                        double* part, int part_cap, int* npart, hipStream_t s) {
+#define OC_LAUNCH_XID(N)                                                                   \
+  {                                                                                        \
+    dim3 grid((d.ny / 2 + XCfg<N>::LP - 1) / XCfg<N>::LP, d.nz, 1);                       \
+    *npart = (int)(grid.x * grid.y);                                                       \
+    if (*npart > part_cap) return hipErrorInvalidValue;                                    \
+    hipLaunchKernelGGL((inv_x_kernel<N>), grid, dim3(NT), 0, s, d, sb,                    \
+                       (const PoissonSlots*)nullptr, rdot, part);                          \
+  }
+  OC_FFT_DISPATCH(d.nx, OC_LAUNCH_XID)
+#undef OC_LAUNCH_XID
   return hipGetLastError();
 }
 
