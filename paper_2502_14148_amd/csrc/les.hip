@@ -9,7 +9,10 @@
 //     nu_e = max(0, -C sum_k Delta_k^2 d_k u_i d_k u_j S_ij / |grad u|^2),
 //     kappa_e = max(0, -C sum_k Delta_k^2 d_k u_i d_k c d_i c / |grad c|^2).
 //
-// Two data-parallel kernels per substage, one thread per cell:
+// Two kernels per substage; each workgroup owns a column tile and marches
+// up a chunk of levels, keeping three levels (k-1, k, k+1, with a one-cell
+// halo) of every field it reads in LDS rings, so each value is fetched from
+// memory once per tile instead of once per neighbour that reads it:
 //   1. the eddy viscosity (and AMD's per-tracer diffusivity) at the centres
 //      from the resolved gradients: diagonal strain at the centre, the
 //      off-diagonal components on the twelve surrounding edges (squared then
@@ -25,34 +28,111 @@ namespace oc {
 
 namespace {
 
-// Linear cell index of a thread.  Workgroups are dealt round-robin to the
-// 8 XCDs; renumbering them gives each XCD a contiguous run of cells, so the
-// neighbouring rows and planes a stencil reads stay in one L2.
-__device__ inline int cell_of_block(unsigned b, unsigned nb, unsigned tid, unsigned bs) {
+// Tiles: TX x TY columns, chunks of LES_KC levels.  Workgroups are dealt
+// round-robin to the 8 XCDs; renumbering them gives each XCD a contiguous
+// run of tiles, so the halo rows shared by neighbouring tiles stay in one L2.
+constexpr int LES_KC = 16;
+
+struct LesTile {
+  int i0, j0, kb, ke;
+};
+
+__device__ inline LesTile les_tile(const Dims& d, int tx, int ty) {
+  const unsigned nb = gridDim.x;
+  unsigned b = blockIdx.x;
   if (nb % 8 == 0) b = (b % 8) * (nb / 8) + b / 8;
-  return (int)(b * bs + tid);
+  const int nbx = d.nx / tx, nby = d.ny / ty;
+  LesTile t;
+  t.i0 = (int)(b % nbx) * tx;
+  t.j0 = (int)((b / nbx) % nby) * ty;
+  t.kb = (int)(b / (nbx * nby)) * LES_KC;
+  t.ke = min(t.kb + LES_KC, d.nz);
+  return t;
 }
 
-template <class T>
-struct Acc {
-  const T* __restrict__ f;
-  long c;
-  int sy;
-  long sz;
-  __device__ T operator()(int di, int dj, int dk) const {
-    return f[c + di + (long)dj * sy + (long)dk * sz];
+// Values of field f around the own cell, read from the LDS rings: level
+// k + dk sits at ring offset off[dk + 1] of the field's three planes.
+template <class T, int PX, int PL>
+struct Ring {
+  const T* S;      // ring planes of all fields, 3 PL each
+  int L;           // own position in a plane
+  int off[3];      // plane offsets of levels k-1, k, k+1
+  __device__ T operator()(int f, int di, int dj, int dk) const {
+    return S[f * 3 * PL + off[dk + 1] + L + dj * PX + di];
   }
 };
 
-template <class T, int KIND>
-__global__ void __launch_bounds__(256) les_viscosity_kernel(Dims d, LesArgs<T> a) {
-  const int n = d.nx * d.ny * d.nz;
-  const int t = cell_of_block(blockIdx.x, gridDim.x, threadIdx.x, blockDim.x);
-  if (t >= n) return;
-  const int i = t % d.nx, j = (t / d.nx) % d.ny, k = t / (d.nx * d.ny);
-  const long c = pidx(d, i, j, k);
-  const int sy = (int)d.sy;
-  const Acc<T> U{a.u, c, sy, d.sz}, V{a.v, c, sy, d.sz}, W{a.w, c, sy, d.sz};
+// Load level kk of nf <= NFMAX fields into ring slot `slot` (tile plus a
+// one-cell halo).  Every load of the level is issued before the first LDS
+// store, so the fetches overlap.  goff: the thread's element offsets within
+// a level, relative to the tile corner.
+template <class T, int TX, int TY, int NFMAX>
+__device__ inline void les_fill(T* S, const T* const* fld, int nf, const Dims& d, const LesTile& t,
+                                const int* goff, int slot, int kk) {
+  constexpr int PX = TX + 2, PY = TY + 2, PL = PX * PY, NT = TX * TY;
+  constexpr int NR = (PL + NT - 1) / NT;
+  const long base = (long)(kk + d.h) * d.sz + (long)(t.j0 - 1 + d.h) * d.sy + (t.i0 - 1 + d.h);
+  T v[NFMAX][NR];
+#pragma unroll
+  for (int f = 0; f < NFMAX; ++f)
+    if (f < nf) {
+      const T* __restrict__ src = fld[f] + base;
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+        if (PL % NT == 0 || threadIdx.x + r * NT < PL) v[f][r] = src[goff[r]];
+    }
+#pragma unroll
+  for (int f = 0; f < NFMAX; ++f)
+    if (f < nf) {
+      T* dst = S + f * 3 * PL + slot * PL;
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        const int e = threadIdx.x + r * NT;
+        if (PL % NT == 0 || e < PL) dst[e] = v[f][r];
+      }
+    }
+}
+
+// The z-march of a tile: cell(i, j, k, ring) runs for every cell of every
+// level, with the rings holding levels k-1, k, k+1.
+template <class T, int TX, int TY, int NFMAX, class Cell>
+__device__ inline void les_march(const Dims& d, const T* const* fld, int nf, Cell cell) {
+  constexpr int PX = TX + 2, PY = TY + 2, PL = PX * PY;
+  __shared__ T S[NFMAX * 3 * PL];
+  constexpr int NT = TX * TY, NR = (PL + NT - 1) / NT;
+  const LesTile t = les_tile(d, TX, TY);
+  const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+  int goff[NR];
+#pragma unroll
+  for (int q = 0; q < NR; ++q) {
+    const int e = threadIdx.x + q * NT;
+    const int ly = e / PX, lx = e - ly * PX;
+    goff[q] = (int)(ly * d.sy) + lx;
+  }
+  les_fill<T, TX, TY, NFMAX>(S, fld, nf, d, t, goff, (t.kb + 2) % 3, t.kb - 1);
+  les_fill<T, TX, TY, NFMAX>(S, fld, nf, d, t, goff, t.kb % 3, t.kb);
+  Ring<T, PX, PL> r;
+  r.S = S;
+  r.L = (ty + 1) * PX + (tx + 1);
+  for (int k = t.kb; k < t.ke; ++k) {
+    __syncthreads();  // the slot of level k-2 is free
+    les_fill<T, TX, TY, NFMAX>(S, fld, nf, d, t, goff, (k + 1) % 3, k + 1);
+    __syncthreads();
+    r.off[0] = ((k + 2) % 3) * PL;
+    r.off[1] = (k % 3) * PL;
+    r.off[2] = ((k + 1) % 3) * PL;
+    cell(t.i0 + tx, t.j0 + ty, k, r);
+  }
+}
+
+// Ring fields of the viscosity pass: 0 u, 1 v, 2 w, then the tracers
+// (Smagorinsky-Lilly: T and S when buoyant; AMD: every tracer).
+template <class T, int KIND, class R>
+__device__ inline void les_viscosity_cell(const Dims& d, const LesArgs<T>& a, int i, int j, int k,
+                                          const R& r) {
+  auto U = [&](int di, int dj, int dk) { return r(0, di, dj, dk); };
+  auto V = [&](int di, int dj, int dk) { return r(1, di, dj, dk); };
+  auto W = [&](int di, int dj, int dk) { return r(2, di, dj, dk); };
   const T rdx = a.rdx, rdy = a.rdy, rzc = a.rdzc[k];
   const T rzf0 = a.rdzf[k], rzf1 = a.rdzf[k + 1];
   const bool wall0 = d.zb && k == 0, wall1 = d.zb && k + 1 == d.nz;
@@ -93,9 +173,8 @@ __global__ void __launch_bounds__(256) les_viscosity_kernel(Dims d, LesArgs<T> a
     const T s2 = T(2) * (ux * ux + vy * vy + wz * wz) + (sxy2 + sxz2 + syz2);  // 4 x (1/4) sums
     T n2 = T(0);
     if (a.buoyancy) {
-      const Acc<T> TT{a.c0, c, sy, d.sz}, SS{a.c1, c, sy, d.sz};
       auto b = [&](int dk) {
-        return a.g_alpha * (TT(0, 0, dk) - a.t_ref) - a.g_beta * (SS(0, 0, dk) - a.s_ref);
+        return a.g_alpha * (r(3, 0, 0, dk) - a.t_ref) - a.g_beta * (r(4, 0, 0, dk) - a.s_ref);
       };
       const T b0 = b(0);
       const T g0 = wall0 ? T(0) : (b0 - b(-1)) * rzf0;
@@ -131,7 +210,7 @@ __global__ void __launch_bounds__(256) les_viscosity_kernel(Dims d, LesArgs<T> a
     nu = (den > T(0)) ? fmax(T(0), -a.camd * num / den) : T(0);
     // per-tracer diffusivities
     for (int q = 0; q < a.ntr; ++q) {
-      const Acc<T> C{a.tr[q], c, sy, d.sz};
+      auto C = [&](int di, int dj, int dk) { return r(3 + q, di, dj, dk); };
       const T c0 = C(0, 0, 0);
       const T gx = T(0.5) * (C(1, 0, 0) - C(-1, 0, 0)) * rdx;
       const T gy = T(0.5) * (C(0, 1, 0) - C(0, -1, 0)) * rdy;
@@ -151,18 +230,33 @@ __global__ void __launch_bounds__(256) les_viscosity_kernel(Dims d, LesArgs<T> a
   store_with_images(a.nu, d, i, j, k, nu, false);
 }
 
+template <class T, int KIND, int TX, int TY>
+__global__ void __launch_bounds__(TX * TY) les_viscosity_kernel(Dims d, LesArgs<T> a) {
+  const T* fld[3 + OC_MAX_TRACERS] = {a.u, a.v, a.w};
+  int nf = 3;
+  if (KIND == OC_LES_SMAGORINSKY) {
+    if (a.buoyancy) { fld[3] = a.c0; fld[4] = a.c1; nf = 5; }
+  } else {
+    for (int q = 0; q < a.ntr; ++q) fld[3 + q] = a.tr[q];
+    nf = 3 + a.ntr;
+  }
+  les_march<T, TX, TY, 3 + OC_MAX_TRACERS>(
+      d, fld, nf, [&](int i, int j, int k, const auto& r) {
+        les_viscosity_cell<T, KIND>(d, a, i, j, k, r);
+      });
+}
+
 // The closure tendencies of the cell index (i, j, k): u at x face i, v at y
-// face j, w at z face k, tracers at the centre.
-template <class T>
-__global__ void __launch_bounds__(256) les_flux_kernel(Dims d, LesArgs<T> a) {
-  const int n = d.nx * d.ny * d.nz;
-  const int t = cell_of_block(blockIdx.x, gridDim.x, threadIdx.x, blockDim.x);
-  if (t >= n) return;
-  const int i = t % d.nx, j = (t / d.nx) % d.ny, k = t / (d.nx * d.ny);
+// face j, w at z face k, tracers at the centre.  Ring fields: 0 u, 1 v, 2 w,
+// 3 nu, 4 + q tracer q, 4 + ntr + q AMD's kappa of tracer q.
+template <class T, class R>
+__device__ inline void les_flux_cell(const Dims& d, const LesArgs<T>& a, int i, int j, int k,
+                                     const R& r) {
   const long c = pidx(d, i, j, k);
-  const int sy = (int)d.sy;
-  const Acc<T> U{a.u, c, sy, d.sz}, V{a.v, c, sy, d.sz}, W{a.w, c, sy, d.sz};
-  const Acc<T> N{a.nu, c, sy, d.sz};
+  auto U = [&](int di, int dj, int dk) { return r(0, di, dj, dk); };
+  auto V = [&](int di, int dj, int dk) { return r(1, di, dj, dk); };
+  auto W = [&](int di, int dj, int dk) { return r(2, di, dj, dk); };
+  auto N = [&](int di, int dj, int dk) { return r(3, di, dj, dk); };
   const T rdx = a.rdx, rdy = a.rdy;
   const T rzc = a.rdzc[k], rzf0 = a.rdzf[k], rzf1 = a.rdzf[k + 1];
   const bool wall0 = d.zb && k == 0, wall1 = d.zb && k + 1 == d.nz;
@@ -218,8 +312,9 @@ __global__ void __launch_bounds__(256) les_flux_kernel(Dims d, LesArgs<T> a) {
   }
   // tracers: d_i(kappa d_i c), face diffusivities the mean of two centres
   for (int q = 0; q < a.ntr; ++q) {
-    const Acc<T> C{a.tr[q], c, sy, d.sz};
-    const Acc<T> K{a.kap[q] ? a.kap[q] : a.nu, c, sy, d.sz};
+    const int fk = a.kap[q] ? 4 + a.ntr + q : 3;
+    auto C = [&](int di, int dj, int dk) { return r(4 + q, di, dj, dk); };
+    auto K = [&](int di, int dj, int dk) { return r(fk, di, dj, dk); };
     const T s = a.kap[q] ? T(1) : a.rpr;
     const T c0 = C(0, 0, 0), k0 = K(0, 0, 0);
     const T fxm = T(0.5) * (K(-1, 0, 0) + k0) * (c0 - C(-1, 0, 0)) * rdx;
@@ -232,22 +327,42 @@ __global__ void __launch_bounds__(256) les_flux_kernel(Dims d, LesArgs<T> a) {
   }
 }
 
+template <class T, int TX, int TY>
+__global__ void __launch_bounds__(TX * TY) les_flux_kernel(Dims d, LesArgs<T> a) {
+  const T* fld[4 + 2 * OC_MAX_TRACERS] = {a.u, a.v, a.w, a.nu};
+  int nf = 4;
+  for (int q = 0; q < a.ntr; ++q) fld[nf++] = a.tr[q];
+  if (a.kap[0])
+    for (int q = 0; q < a.ntr; ++q) fld[nf++] = a.kap[q];
+  les_march<T, TX, TY, 4 + 2 * OC_MAX_TRACERS>(
+      d, fld, nf, [&](int i, int j, int k, const auto& r) { les_flux_cell<T>(d, a, i, j, k, r); });
+}
+
 }  // namespace
 
-template <class T>
-hipError_t launch_les(const Dims& d, const LesArgs<T>& a, int kind, hipStream_t s) {
-  const int n = d.nx * d.ny * d.nz;
-  const dim3 grid((n + 255) / 256);
+template <class T, int TX, int TY>
+hipError_t launch_les_tiles(const Dims& d, const LesArgs<T>& a, int kind, hipStream_t s) {
+  const dim3 grid((d.nx / TX) * (d.ny / TY) * ((d.nz + LES_KC - 1) / LES_KC));
   if (kind == OC_LES_SMAGORINSKY)
-    hipLaunchKernelGGL((les_viscosity_kernel<T, OC_LES_SMAGORINSKY>), grid, dim3(256), 0, s, d, a);
+    hipLaunchKernelGGL((les_viscosity_kernel<T, OC_LES_SMAGORINSKY, TX, TY>), grid, dim3(TX * TY), 0,
+                       s, d, a);
   else if (kind == OC_LES_AMD)
-    hipLaunchKernelGGL((les_viscosity_kernel<T, OC_LES_AMD>), grid, dim3(256), 0, s, d, a);
+    hipLaunchKernelGGL((les_viscosity_kernel<T, OC_LES_AMD, TX, TY>), grid, dim3(TX * TY), 0, s, d,
+                       a);
   else
     return hipErrorInvalidValue;
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(les_flux_kernel<T>, grid, dim3(256), 0, s, d, a);
+  hipLaunchKernelGGL((les_flux_kernel<T, TX, TY>), grid, dim3(TX * TY), 0, s, d, a);
   return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_les(const Dims& d, const LesArgs<T>& a, int kind, hipStream_t s) {
+  if (a.ntr < 1 || a.ntr > OC_MAX_TRACERS || d.h < 1) return hipErrorInvalidValue;
+  if (d.nx % 32 == 0 && d.ny % 8 == 0) return launch_les_tiles<T, 32, 8>(d, a, kind, s);
+  if (d.nx % 8 == 0 && d.ny % 8 == 0) return launch_les_tiles<T, 8, 8>(d, a, kind, s);
+  return hipErrorInvalidValue;
 }
 
 template hipError_t launch_les<float>(const Dims&, const LesArgs<float>&, int, hipStream_t);
