@@ -151,6 +151,16 @@ def hydro_tendency_bytes(ncells, esz):
     return 20 * esz * ncells
 
 
+# Algorithmic flops per cell of the hydrostatic tendency + QAB2 kernel: ten
+# WENO-Z reconstructions (the x and y faces of T and S, counted once per
+# face; the z faces of u, v, T, S; the vorticity at the u and v points), and
+# the rest of the cell's arithmetic: vertical fluxes and viscous fluxes 20,
+# kinetic energy 8, each momentum point 35 (averages, Coriolis, gradients,
+# vertical advection, viscosity, QAB2), each tracer 13 (area factors, flux
+# divergence, QAB2).
+HYDRO_FLOPS_PER_CELL = 10 * 79 + 20 + 8 + 2 * 35 + 2 * 13
+
+
 def run_hydrostatic(steps, warmup, N=30):
     """The 1440 x 560 x 50 lat-lon sector in FP32: QAB2 baroclinic steps of
     600 s with N = 30 barotropic substeps per step (cosine-bell filter over
@@ -188,6 +198,7 @@ def run_hydrostatic(steps, warmup, N=30):
     t_tend, n_tend = prof["hydro_tendency"]
     t_launch = t_tend / 1e3 / max(n_tend, 1)
     gbs = hydro_tendency_bytes(ncells, 4) / t_launch / 1e9
+    tfs = HYDRO_FLOPS_PER_CELL * ncells / t_launch / 1e12
     return {"value": ncells * steps / (ms / 1e3), "unit": "cell-steps/s", "steps": steps,
             "warmup": warmup, "ms_per_step": ms / steps, "dtype": "f32",
             "config": {"workload": "hydrostatic lat-lon sector 1440x560x50, 70S-70N, 3000 m, "
@@ -195,6 +206,9 @@ def run_hydrostatic(steps, warmup, N=30):
                                    "split-explicit free surface (FP64)",
                        "dt_s": dt, "N": N, "M": len(w)},
             "kernels_ms_per_step": {k: v[0] / steps for k, v in prof.items() if v[1]},
+            "tendency_alu": {"achieved": round(tfs, 2), "peak": FP32_VALU_PEAK_TFLOPS,
+                             "unit": "TFLOP/s", "frac": round(tfs / FP32_VALU_PEAK_TFLOPS, 4),
+                             "flops_per_cell": HYDRO_FLOPS_PER_CELL},
             "tendency_hbm": {"achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                              "frac": round(gbs / HBM_PEAK_GBS, 4),
                              "avg_launch_ms": t_launch * 1e3,

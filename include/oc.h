@@ -112,7 +112,9 @@ typedef struct {
 typedef struct {
   int32_t kind;             /* OC_NONHYDROSTATIC (rectilinear grid) or
                                OC_HYDROSTATIC (lat-lon grid, split-explicit
-                               free surface) */
+                               free surface; each field with its
+                               three-cell halos under 2^32 bytes, else
+                               OC_ERR_UNSUPPORTED) */
   int32_t precision;        /* OC_FP64: everything in FP64.  OC_FP32_MIXED:
                                state, tendencies and the stencil arithmetic in
                                FP32; divergence, Poisson solve and projection

@@ -1159,6 +1159,14 @@ int oc_model_create(const oc_grid* g, const oc_model_desc* md, void* workspace,
   if (rc) return rc;
   rc = validate_pair(g->d, *md);
   if (rc) return rc;
+  if (md->kind == OC_HYDROSTATIC) {
+    const Dims hd = make_dims(g->d.nx, g->d.ny, g->d.nz, true, halo_width(md->advection));
+    const long esz = md->precision == OC_FP64 ? 8 : 4;
+    if ((long)hd.px * hd.py * hd.pz * esz >= (1L << 32)) {
+      set_error("the hydrostatic model needs fields of fewer than 2^32 bytes with halos");
+      return OC_ERR_UNSUPPORTED;
+    }
+  }
   if (((uintptr_t)workspace) % 256) { set_error("workspace must be 256-byte aligned"); return OC_ERR_ARG; }
   const Layout L = make_layout(g->d, *md);
   if (workspace_bytes < L.total) {

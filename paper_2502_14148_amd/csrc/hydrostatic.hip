@@ -29,8 +29,9 @@
 // Layout: halo-padded fields (halo width h = 3), x fastest; v on the ny + 1 y faces (face
 // ny in the first upper halo row), w on the nz + 1 z faces (face nz in the
 // first upper halo plane).  Kernels: the column scans (zeta, w, pressure
-// gradients), the tendency + QAB2 kernel (one thread per column, register
-// windows along z), and the halo fill of the prognostic fields.
+// gradients), the tendency + QAB2 kernel (column tiles marching up the
+// levels with horizontally staged planes in LDS and register windows along
+// z), and the halo fill of the prognostic fields.
 #include "oc_internal.h"
 #include "weno_dev.h"
 
@@ -39,6 +40,10 @@ namespace oc {
 namespace {
 
 constexpr int HTX = 64, HTY = 4;
+// Levels whose loads the column scans issue together (the scans store
+// between levels, so without batching every level would wait on its own
+// loads).
+constexpr int DKB = 8;
 
 template <class T>
 __global__ void __launch_bounds__(HTX * HTY) hydro_diag_kernel(HydroBufs<T> a) {
@@ -56,10 +61,20 @@ __global__ void __launch_bounds__(HTX * HTY) hydro_diag_kernel(HydroBufs<T> a) {
   {
     const T dxj = (T)m.dxc[j + d.h], dxjm = (T)m.dxc[j - 1 + d.h];
     const T rza = T(1) / (T)m.areaz[j + d.h];
-    long c = c0;
-    for (int k = 0; k < d.nz; ++k, c += sz) {
-      const T circ = dy * (a.v[c] - a.v[c - 1]) - (dxj * a.u[c] - dxjm * a.u[c - sy]);
-      a.zeta[c] = circ * rza;
+    for (int k0 = 0; k0 < d.nz; k0 += DKB) {
+      T v0[DKB], v1[DKB], u0[DKB], u1[DKB];
+#pragma unroll
+      for (int q = 0; q < DKB; ++q) {
+        const long c = c0 + (long)min(k0 + q, d.nz - 1) * sz;
+        v0[q] = a.v[c]; v1[q] = a.v[c - 1]; u0[q] = a.u[c]; u1[q] = a.u[c - sy];
+      }
+#pragma unroll
+      for (int q = 0; q < DKB; ++q) {
+        if (k0 + q < d.nz) {
+          const T circ = dy * (v0[q] - v1[q]) - (dxj * u0[q] - dxjm * u1[q]);
+          a.zeta[c0 + (long)(k0 + q) * sz] = circ * rza;
+        }
+      }
     }
   }
 
@@ -68,12 +83,22 @@ __global__ void __launch_bounds__(HTX * HTY) hydro_diag_kernel(HydroBufs<T> a) {
     const T dxf0 = (T)m.dxf[j + d.h], dxf1 = (T)m.dxf[j + 1 + d.h];
     const T rar = T(1) / (T)m.areac[j + d.h];
     double wacc = 0.0;
-    long c = c0;
-    a.w[c] = T(0);
-    for (int k = 0; k < d.nz; ++k, c += sz) {
-      const T div = (dy * (a.u[c + 1] - a.u[c]) + (dxf1 * a.v[c + sy] - dxf0 * a.v[c])) * rar;
-      wacc -= dz * (double)div;
-      a.w[c + sz] = (T)wacc;
+    a.w[c0] = T(0);
+    for (int k0 = 0; k0 < d.nz; k0 += DKB) {
+      T ue[DKB], uc[DKB], vn[DKB], vc[DKB];
+#pragma unroll
+      for (int q = 0; q < DKB; ++q) {
+        const long c = c0 + (long)min(k0 + q, d.nz - 1) * sz;
+        ue[q] = a.u[c + 1]; uc[q] = a.u[c]; vn[q] = a.v[c + sy]; vc[q] = a.v[c];
+      }
+#pragma unroll
+      for (int q = 0; q < DKB; ++q) {
+        if (k0 + q < d.nz) {
+          const T div = (dy * (ue[q] - uc[q]) + (dxf1 * vn[q] - dxf0 * vc[q])) * rar;
+          wacc -= dz * (double)div;
+          a.w[c0 + (long)(k0 + q + 1) * sz] = (T)wacc;
+        }
+      }
     }
   }
 
@@ -84,18 +109,30 @@ __global__ void __launch_bounds__(HTX * HTY) hydro_diag_kernel(HydroBufs<T> a) {
     const T rdy = T(1) / dy;
     const bool vpt = j > 0;
     double sx = 0.0, sy_ = 0.0;
-    long c = c0 + (long)(d.nz - 1) * sz;
-    for (int k = d.nz - 1; k >= 0; --k, c -= sz) {
-      const T b = a.ga * (a.t[c] - a.tref) - a.gb * (a.s[c] - a.sref);
-      const T bw = a.ga * (a.t[c - 1] - a.tref) - a.gb * (a.s[c - 1] - a.sref);
-      const double dbx = (double)(b - bw);
-      a.px[c] = (T)(-dz * (0.5 * dbx + sx)) * rdx;
-      sx += dbx;
-      if (vpt) {
-        const T bs = a.ga * (a.t[c - sy] - a.tref) - a.gb * (a.s[c - sy] - a.sref);
-        const double dby = (double)(b - bs);
-        a.py[c] = (T)(-dz * (0.5 * dby + sy_)) * rdy;
-        sy_ += dby;
+    for (int k1 = d.nz - 1; k1 >= 0; k1 -= DKB) {
+      T tc[DKB], sc[DKB], tw[DKB], sw[DKB], ts[DKB], ss[DKB];
+#pragma unroll
+      for (int q = 0; q < DKB; ++q) {
+        const long c = c0 + (long)max(k1 - q, 0) * sz;
+        tc[q] = a.t[c]; sc[q] = a.s[c]; tw[q] = a.t[c - 1]; sw[q] = a.s[c - 1];
+        ts[q] = a.t[c - sy]; ss[q] = a.s[c - sy];
+      }
+#pragma unroll
+      for (int q = 0; q < DKB; ++q) {
+        if (k1 - q >= 0) {
+          const long c = c0 + (long)(k1 - q) * sz;
+          const T b = a.ga * (tc[q] - a.tref) - a.gb * (sc[q] - a.sref);
+          const T bw = a.ga * (tw[q] - a.tref) - a.gb * (sw[q] - a.sref);
+          const double dbx = (double)(b - bw);
+          a.px[c] = (T)(-dz * (0.5 * dbx + sx)) * rdx;
+          sx += dbx;
+          if (vpt) {
+            const T bs = a.ga * (ts[q] - a.tref) - a.gb * (ss[q] - a.sref);
+            const double dby = (double)(b - bs);
+            a.py[c] = (T)(-dz * (0.5 * dby + sy_)) * rdy;
+            sy_ += dby;
+          }
+        }
       }
     }
   }
@@ -107,161 +144,361 @@ __device__ inline T rec(T m3, T m2, T m1, T p0, T p1, T p2, T vel, T eps) {
   return tz::rec6<T, SCHEME>(m3, m2, m1, p0, p1, p2, vel, eps);
 }
 
+// Tendency + QAB2 kernel: 32 x 8 column tiles marching up the levels.  At
+// each level the workgroup stages the planes it reads horizontally (T, S
+// with three halo cells, zeta, u, v and w on face k + 1) in LDS (two
+// buffers, so the next level's plane loads need no barrier after the last
+// reads of this one), computes every tracer face flux of the tile once (the
+// east and north edge faces in a second round by the first wavefront) and
+// then the cell, u-point and v-point tendencies.  Vertical reconstructions
+// use per-thread register windows along z, and the fluxes through the lower
+// face are carried up from the level below.
+constexpr int TTX = 32, TTY = 8;
+constexpr int P_TX = TTX + 6, P_TY = TTY + 6;       // T, S: x, y in [-3, T + 2]
+constexpr int P_ZX = TTX + 5, P_ZY = TTY + 5;       // zeta: [-2, T + 2]
+constexpr int P_UX = TTX + 2, P_UY = TTY + 1;       // u: x in [-1, TTX], y in [-1, TTY)
+constexpr int P_VX = TTX + 1, P_VY = TTY + 2;       // v: x in [-1, TTX), y in [-1, TTY]
+constexpr int P_WX = TTX + 1, P_WY = TTY + 1;       // w: x, y in [-1, T)
+constexpr int O_T = 0, O_S = O_T + P_TX * P_TY, O_Z = O_S + P_TX * P_TY;
+constexpr int O_U = O_Z + P_ZX * P_ZY, O_V = O_U + P_UX * P_UY, O_W = O_V + P_VX * P_VY;
+constexpr int PLANES = O_W + P_WX * P_WY;
+constexpr int F_X = (TTX + 1) * TTY, F_Y = TTX * (TTY + 1);   // per tracer
+
+// Tile of workgroup blockIdx.x: workgroups are dealt round-robin to the 8
+// XCDs; renumbering gives each XCD a contiguous run of tiles (x fastest),
+// so the halo rows shared by neighbouring tiles stay in one L2.
+__device__ inline int hydro_tile_index() {
+  const int n = (int)gridDim.x, b = (int)blockIdx.x;
+  const int q = n / 8, r = n % 8, x = b % 8;
+  return x * q + min(x, r) + b / 8;
+}
+
+// Staging of a W x H box of a padded field whose first point is (ia, ja):
+// each thread fetches a fixed number of points into registers (all fetches
+// of a level are in flight together), then stores them to LDS (row length
+// W).  Points past the padded upper edges are not fetched; their LDS entries
+// are never read.
+constexpr int TNT = TTX * TTY;
+
+// A workgroup-uniform pointer made opaque to the compiler's address
+// folding, so that p[off] with a 32-bit per-thread offset keeps the base in
+// scalar registers (a global load with a scalar base and a vector offset)
+// instead of being merged into a 64-bit per-thread address.
+template <class T>
+using global_ptr = __attribute__((address_space(1))) T*;
+
+template <class T>
+__device__ inline global_ptr<T> uniform_ptr(T* p) {
+  const unsigned long long v = (unsigned long long)p;
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+  return (global_ptr<T>)(((unsigned long long)hi << 32) | lo);
+}
+
+// Element of a uniform base at a 32-bit byte offset (the padded fields of
+// this kernel hold fewer than 2^32 bytes).
+template <class T>
+__device__ inline __attribute__((address_space(1))) T& at(global_ptr<T> p, unsigned off) {
+  return *(global_ptr<T>)((__attribute__((address_space(1))) char*)p + off);
+}
+
+constexpr int box_n(int w, int h) { return (w * h + TNT - 1) / TNT; }
+
+template <class T, int W, int H>
+__device__ inline void box_fetch(T (&r)[box_n(W, H)], global_ptr<const T> fb, int sy, int imax, int jmax,
+                                 int tid) {
+#pragma unroll
+  for (int n = 0; n < box_n(W, H); ++n) {
+    const int e = tid + n * TNT;
+    const int x = e % W, y = e / W;
+    r[n] = (e < W * H && x <= imax && y <= jmax) ? at(fb, (unsigned)(y * sy + x) * (unsigned)sizeof(T)) : T(0);
+  }
+}
+
+template <class T, int W, int H>
+__device__ inline void box_store(T* dst, const T (&r)[box_n(W, H)], int tid) {
+#pragma unroll
+  for (int n = 0; n < box_n(W, H); ++n) {
+    const int e = tid + n * TNT;
+    if (e < W * H) dst[e] = r[n];
+  }
+}
+
+// The registers of one level's staged planes.
+template <class T>
+struct Stage {
+  T t[box_n(P_TX, P_TY)], s[box_n(P_TX, P_TY)], z[box_n(P_ZX, P_ZY)];
+  T u[box_n(P_UX, P_UY)], v[box_n(P_VX, P_VY)], w[box_n(P_WX, P_WY)];
+};
+
+template <class T>
+__device__ inline void stage_fetch(Stage<T>& r, const HydroBufs<T>& a, int i0, int j0, int k,
+                                   int tid) {
+  const Dims& d = a.d;
+  const long kz = (long)k * d.sz;
+  // recomputed at every level: hoisting the per-thread offsets and
+  // predicates out of the level loop would hold ~30 more registers
+  asm volatile("" : "+v"(tid));
+  const int ix = d.nx + d.h - 1 - i0, jy = d.ny + d.h - 1 - j0;   // last padded point
+  const int sy = (int)d.sy;
+  const long b3 = pidx(d, i0 - 3, j0 - 3, 0) + kz, b2 = pidx(d, i0 - 2, j0 - 2, 0) + kz;
+  const long b1 = pidx(d, i0 - 1, j0 - 1, 0) + kz;
+  box_fetch<T, P_TX, P_TY>(r.t, uniform_ptr(a.t + b3), sy, ix + 3, jy + 3, tid);
+  box_fetch<T, P_TX, P_TY>(r.s, uniform_ptr(a.s + b3), sy, ix + 3, jy + 3, tid);
+  box_fetch<T, P_ZX, P_ZY>(r.z, uniform_ptr(a.zeta + b2), sy, ix + 2, jy + 2, tid);
+  box_fetch<T, P_UX, P_UY>(r.u, uniform_ptr(a.u + b1), sy, ix + 1, jy + 1, tid);
+  box_fetch<T, P_VX, P_VY>(r.v, uniform_ptr(a.v + b1), sy, ix + 1, jy + 1, tid);
+  box_fetch<T, P_WX, P_WY>(r.w, uniform_ptr(a.w + b1 + d.sz), sy, ix + 1, jy + 1, tid);
+}
+
+template <class T>
+__device__ inline void stage_store(T* S, const Stage<T>& r, int tid) {
+  box_store<T, P_TX, P_TY>(S + O_T, r.t, tid);
+  box_store<T, P_TX, P_TY>(S + O_S, r.s, tid);
+  box_store<T, P_ZX, P_ZY>(S + O_Z, r.z, tid);
+  box_store<T, P_UX, P_UY>(S + O_U, r.u, tid);
+  box_store<T, P_VX, P_VY>(S + O_V, r.v, tid);
+  box_store<T, P_WX, P_WY>(S + O_W, r.w, tid);
+}
+
 template <class T, int SCHEME>
-__global__ void __launch_bounds__(HTX * HTY) hydro_tend_kernel(HydroBufs<T> a, HydroStep<T> st) {
+__global__ void __launch_bounds__(TTX * TTY) hydro_tend_kernel(HydroBufs<T> a, HydroStep<T> st) {
+  __shared__ T P[2][PLANES];
+  __shared__ T FX[2][F_X];
+  __shared__ T FY[2][F_Y];
   const Dims d = a.d;
-  const int i = (int)(blockIdx.x * HTX + threadIdx.x);
-  const int j = (int)(blockIdx.y * HTY + threadIdx.y);
-  if (i >= d.nx || j >= d.ny) return;
+  const int nbx = (d.nx + TTX - 1) / TTX;
+  const int tile = hydro_tile_index();
+  const int i0 = (tile % nbx) * TTX, j0 = (tile / nbx) * TTY;
+  const int tx = (int)threadIdx.x, ty = (int)threadIdx.y, tid = ty * TTX + tx;
+  const int i = i0 + tx, j = j0 + ty;
+  const bool active = i < d.nx && j < d.ny;
   const HydroMetric& m = a.m;
-  const long sy = d.sy, sz = d.sz;
+  const long sz = d.sz;
   const bool vpt = j > 0;     // v point on y face j (face 0 is a wall)
   const T eps = a.eps;
   const T dy = (T)m.dy, rdy = T(1) / dy;
   const T dz = (T)m.dz, rdz = T(1) / dz;
-  const T rdxc = T(1) / (T)m.dxc[j + d.h];
-  const T fc = (T)m.fc[j + d.h], ff = (T)m.ff[j + d.h];
+  const int jm = min(j, d.ny - 1) + d.h;
+  const T rdxc = T(1) / (T)m.dxc[jm];
+  const T fc = (T)m.fc[jm], ff = (T)m.ff[jm];
   const T Ax = dy * dz;
-  const T Ay0 = (T)m.dxf[j + d.h] * dz, Ay1 = (T)m.dxf[j + 1 + d.h] * dz;
-  const T Az = (T)m.areac[j + d.h];
+  const T Ay0 = (T)m.dxf[jm] * dz;
+  const T Az = (T)m.areac[jm];
   const T rvol = T(1) / (Az * dz);
   const T nu = a.nu, kappa = a.kappa;
   const T dt = st.dt, a1 = st.a1, a0 = st.a0;
   const bool first = st.first != 0;
 
-  const long c0 = pidx(d, i, j, 0);
+  // own column: field pointers advanced by whole levels (uniform) plus a
+  // 32-bit per-thread byte offset
+  const unsigned cb = (unsigned)pidx(d, min(i, d.nx - 1), min(j, d.ny - 1), 0) * (unsigned)sizeof(T);
   // register windows along z: q[o] = q_{k-2+o}
   T uw[6], vw[6], tw[6], sw[6];
 #pragma unroll
   for (int o = 0; o < 6; ++o) {
-    const long c = c0 + (long)(o - 2) * sz;
-    uw[o] = a.u[c];
-    vw[o] = a.v[c];
-    tw[o] = a.t[c];
-    sw[o] = a.s[c];
+    const long kz = (long)(o - 2) * sz;
+    uw[o] = at(uniform_ptr(a.u + kz), cb);
+    vw[o] = at(uniform_ptr(a.v + kz), cb);
+    tw[o] = at(uniform_ptr(a.t + kz), cb);
+    sw[o] = at(uniform_ptr(a.s + kz), cb);
   }
   // quantities on face k carried up from the level below (floor: zero)
   T Fu = T(0), Fv = T(0), Ft = T(0), Fs = T(0), Nu = T(0), Nv = T(0);
   T Wu = T(0), Wv = T(0);
   double gu = 0.0, gv = 0.0;
-  const long c2 = (long)j * d.nx + i;
+  const long c2 = (long)min(j, d.ny - 1) * d.nx + min(i, d.nx - 1);
 
+  // own positions in the staged planes
+  const int lt = (ty + 3) * P_TX + tx + 3;
+  const int lz = (ty + 2) * P_ZX + tx + 2;
+  const int lu = (ty + 1) * P_UX + tx + 1;
+  const int lv = (ty + 1) * P_VX + tx + 1;
+  const int lw = (ty + 1) * P_WX + tx + 1;
+
+  Stage<T> stg;
+  stage_fetch(stg, a, i0, j0, 0, tid);
   for (int k = 0; k < d.nz; ++k) {
-    const long c = c0 + (long)k * sz;
-    const long cf = c + sz;  // face k + 1
-    const T w_c = a.w[cf];
-    const T Wu1 = T(0.5) * (a.w[cf - 1] + w_c);
-    const T Wv1 = vpt ? T(0.5) * (a.w[cf - sy] + w_c) : T(0);
-    // fluxes through face k + 1
-    T Fu1, Fv1, Ft1, Fs1, Nu1, Nv1;
-    if (k + 1 < d.nz) {
-      Fu1 = Wu1 * rec<T, SCHEME>(uw[0], uw[1], uw[2], uw[3], uw[4], uw[5], Wu1, eps);
-      Fv1 = Wv1 * rec<T, SCHEME>(vw[0], vw[1], vw[2], vw[3], vw[4], vw[5], Wv1, eps);
-      Ft1 = (w_c * rec<T, SCHEME>(tw[0], tw[1], tw[2], tw[3], tw[4], tw[5], w_c, eps) -
-             kappa * (tw[3] - tw[2]) * rdz) * Az;
-      Fs1 = (w_c * rec<T, SCHEME>(sw[0], sw[1], sw[2], sw[3], sw[4], sw[5], w_c, eps) -
-             kappa * (sw[3] - sw[2]) * rdz) * Az;
-      Nu1 = nu * (uw[3] - uw[2]) * rdz;
-      Nv1 = nu * (vw[3] - vw[2]) * rdz;
-    } else {
-      Fu1 = Wu1 * uw[2];
-      Fv1 = Wv1 * vw[2];
-      Ft1 = w_c * tw[2] * Az;
-      Fs1 = w_c * sw[2] * Az;
-      Nu1 = (T)a.taux[c2];
-      Nv1 = (T)a.tauy[c2];
-    }
+    T* S = P[k & 1];
+    const long kz = (long)k * sz;
+    stage_store(S, stg, tid);
+    __syncthreads();
+    // the next level's planes are fetched while this level computes
+    if (k + 1 < d.nz) stage_fetch(stg, a, i0, j0, k + 1, tid);
 
-    const T u_c = uw[2], v_c = vw[2];
-    const T u_e = a.u[c + 1], u_w = a.u[c - 1];
-    const T v_w = a.v[c - 1], v_n = a.v[c + sy], v_nw = a.v[c - 1 + sy];
-    const T ke = T(0.25) * (u_c * u_c + u_e * u_e + v_c * v_c + v_n * v_n);
-
-    // ---- u point (x face i, row j)
+    // ---- tracer fluxes through the x faces (west of each column) and the
+    // y faces (south of each row) of the tile; then the east and north edge
+    // faces by the first wavefront
     {
-      const T vb = T(0.25) * (v_w + v_c + v_nw + v_n);
-      const T zh = rec<T, SCHEME>(a.zeta[c - 2 * sy], a.zeta[c - sy], a.zeta[c], a.zeta[c + sy],
-                                  a.zeta[c + 2 * sy], a.zeta[c + 3 * sy], vb, eps);
-      const T ke_w = T(0.25) * (u_w * u_w + u_c * u_c + v_w * v_w + v_nw * v_nw);
-      T G = zh * vb + fc * vb;
-      G -= (ke - ke_w) * rdxc;
-      G -= a.px[c];
-      G -= (Fu1 - Fu) * rdz - u_c * (Wu1 - Wu) * rdz;
-      G += (Nu1 - Nu) * rdz;
-      T comb = a1 * G;
-      if (!first) comb -= a0 * a.Gu[c];
-      a.Gu[c] = G;
-      a.uo[c] = u_c + dt * comb;
-      gu += (double)comb;
-    }
-    // ---- v point (x centre i, y face j)
-    if (vpt) {
-      const T u_s = a.u[c - sy], u_se = a.u[c - sy + 1];
-      const T v_s = a.v[c - sy];
-      const T ub = T(0.25) * (u_s + u_se + u_c + u_e);
-      const T zh = rec<T, SCHEME>(a.zeta[c - 2], a.zeta[c - 1], a.zeta[c], a.zeta[c + 1],
-                                  a.zeta[c + 2], a.zeta[c + 3], ub, eps);
-      const T ke_s = T(0.25) * (u_s * u_s + u_se * u_se + v_s * v_s + v_c * v_c);
-      T G = -(zh * ub) - ff * ub;
-      G -= (ke - ke_s) * rdy;
-      G -= a.py[c];
-      G -= (Fv1 - Fv) * rdz - v_c * (Wv1 - Wv) * rdz;
-      G += (Nv1 - Nv) * rdz;
-      T comb = a1 * G;
-      if (!first) comb -= a0 * a.Gv[c];
-      a.Gv[c] = G;
-      a.vo[c] = v_c + dt * comb;
-      gv += (double)comb;
-    } else {
-      a.Gv[c] = T(0);
-      a.vo[c] = T(0);
-    }
-    // ---- tracers at centre (i, j)
-    {
-      const bool south = j > 0, north = j + 1 < d.ny;
+      const T* St = S + O_T;
+      const T* Ss = S + O_S;
+      if (i <= d.nx && j < d.ny) {
+        const T uf = S[O_U + lu];
 #pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        const T* f = q ? a.s : a.t;
-        const T cc = q ? sw[2] : tw[2];
-        const T cm3 = f[c - 3], cm2 = f[c - 2], cm1 = f[c - 1];
-        const T cp1 = f[c + 1], cp2 = f[c + 2], cp3 = f[c + 3];
-        const T fx0 = u_c * rec<T, SCHEME>(cm3, cm2, cm1, cc, cp1, cp2, u_c, eps) * Ax;
-        const T fx1 = u_e * rec<T, SCHEME>(cm2, cm1, cc, cp1, cp2, cp3, u_e, eps) * Ax;
-        const T sm3 = f[c - 3 * sy], sm2 = f[c - 2 * sy], sm1 = f[c - sy];
-        const T sp1 = f[c + sy], sp2 = f[c + 2 * sy], sp3 = f[c + 3 * sy];
-        const T fy0 = south ? v_c * rec<T, SCHEME>(sm3, sm2, sm1, cc, sp1, sp2, v_c, eps) * Ay0
-                            : T(0);
-        const T fy1 = north ? v_n * rec<T, SCHEME>(sm2, sm1, cc, sp1, sp2, sp3, v_n, eps) * Ay1
-                            : T(0);
-        const T Fz0 = q ? Fs : Ft, Fz1 = q ? Fs1 : Ft1;
-        const T G = -((fx1 - fx0) + (fy1 - fy0) + (Fz1 - Fz0)) * rvol;
-        T* Gq = q ? a.Gs : a.Gt;
-        T comb = a1 * G;
-        if (!first) comb -= a0 * Gq[c];
-        Gq[c] = G;
-        (q ? a.so : a.to)[c] = cc + dt * comb;
+        for (int q = 0; q < 2; ++q) {
+          const T* f = q ? Ss : St;
+          FX[q][ty * (TTX + 1) + tx] =
+              uf * rec<T, SCHEME>(f[lt - 3], f[lt - 2], f[lt - 1], f[lt], f[lt + 1], f[lt + 2], uf,
+                                  eps) * Ax;
+        }
+      }
+      if (i < d.nx && j <= d.ny) {
+        const T vf = S[O_V + lv];
+        const bool open = j > 0 && j < d.ny;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const T* f = q ? Ss : St;
+          FY[q][ty * TTX + tx] =
+              open ? vf * rec<T, SCHEME>(f[lt - 3 * P_TX], f[lt - 2 * P_TX], f[lt - P_TX], f[lt],
+                                         f[lt + P_TX], f[lt + 2 * P_TX], vf, eps) * Ay0
+                   : T(0);
+        }
+      }
+      if (tid < TTY + TTX) {
+        if (tid < TTY) {           // x face i0 + TTX of row j0 + tid
+          const int ey = tid;
+          if (i0 + TTX <= d.nx && j0 + ey < d.ny) {
+            const T uf = S[O_U + (ey + 1) * P_UX + TTX + 1];
+            const int le = (ey + 3) * P_TX + TTX + 3;
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+              const T* f = q ? Ss : St;
+              FX[q][ey * (TTX + 1) + TTX] =
+                  uf * rec<T, SCHEME>(f[le - 3], f[le - 2], f[le - 1], f[le], f[le + 1], f[le + 2],
+                                      uf, eps) * Ax;
+            }
+          }
+        } else {                   // y face j0 + TTY of column i0 + ex
+          const int ex = tid - TTY;
+          const int jf = j0 + TTY;
+          if (jf <= d.ny && i0 + ex < d.nx) {
+            const T vf = S[O_V + (TTY + 1) * P_VX + ex + 1];
+            const int le = (TTY + 3) * P_TX + ex + 3;
+            const bool open = jf < d.ny;
+            const T Ay = (T)m.dxf[jf + d.h] * dz;
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+              const T* f = q ? Ss : St;
+              FY[q][TTY * TTX + ex] =
+                  open ? vf * rec<T, SCHEME>(f[le - 3 * P_TX], f[le - 2 * P_TX], f[le - P_TX],
+                                             f[le], f[le + P_TX], f[le + 2 * P_TX], vf, eps) * Ay
+                       : T(0);
+            }
+          }
+        }
       }
     }
+    __syncthreads();
 
-    // ---- carry face k + 1 up; shift the windows
-    Fu = Fu1; Fv = Fv1; Ft = Ft1; Fs = Fs1; Nu = Nu1; Nv = Nv1; Wu = Wu1; Wv = Wv1;
+    if (active) {
+      const T* U = S + O_U;
+      const T* V = S + O_V;
+      const T* Z = S + O_Z;
+      const T* Wp = S + O_W;
+      const T w_c = Wp[lw];
+      const T Wu1 = T(0.5) * (Wp[lw - 1] + w_c);
+      const T Wv1 = vpt ? T(0.5) * (Wp[lw - P_WX] + w_c) : T(0);
+      // fluxes through face k + 1
+      T Fu1, Fv1, Ft1, Fs1, Nu1, Nv1;
+      if (k + 1 < d.nz) {
+        Fu1 = Wu1 * rec<T, SCHEME>(uw[0], uw[1], uw[2], uw[3], uw[4], uw[5], Wu1, eps);
+        Fv1 = Wv1 * rec<T, SCHEME>(vw[0], vw[1], vw[2], vw[3], vw[4], vw[5], Wv1, eps);
+        Ft1 = (w_c * rec<T, SCHEME>(tw[0], tw[1], tw[2], tw[3], tw[4], tw[5], w_c, eps) -
+               kappa * (tw[3] - tw[2]) * rdz) * Az;
+        Fs1 = (w_c * rec<T, SCHEME>(sw[0], sw[1], sw[2], sw[3], sw[4], sw[5], w_c, eps) -
+               kappa * (sw[3] - sw[2]) * rdz) * Az;
+        Nu1 = nu * (uw[3] - uw[2]) * rdz;
+        Nv1 = nu * (vw[3] - vw[2]) * rdz;
+      } else {
+        Fu1 = Wu1 * uw[2];
+        Fv1 = Wv1 * vw[2];
+        Ft1 = w_c * tw[2] * Az;
+        Fs1 = w_c * sw[2] * Az;
+        Nu1 = (T)a.taux[c2];
+        Nv1 = (T)a.tauy[c2];
+      }
+
+      const T u_c = uw[2], v_c = vw[2];
+      const T u_e = U[lu + 1], u_w = U[lu - 1];
+      const T v_w = V[lv - 1], v_n = V[lv + P_VX], v_nw = V[lv - 1 + P_VX];
+      const T ke = T(0.25) * (u_c * u_c + u_e * u_e + v_c * v_c + v_n * v_n);
+
+      // ---- u point (x face i, row j)
+      {
+        const T vb = T(0.25) * (v_w + v_c + v_nw + v_n);
+        const T zh = rec<T, SCHEME>(Z[lz - 2 * P_ZX], Z[lz - P_ZX], Z[lz], Z[lz + P_ZX],
+                                    Z[lz + 2 * P_ZX], Z[lz + 3 * P_ZX], vb, eps);
+        const T ke_w = T(0.25) * (u_w * u_w + u_c * u_c + v_w * v_w + v_nw * v_nw);
+        T G = zh * vb + fc * vb;
+        G -= (ke - ke_w) * rdxc;
+        G -= at(uniform_ptr(a.px + kz), cb);
+        G -= (Fu1 - Fu) * rdz - u_c * (Wu1 - Wu) * rdz;
+        G += (Nu1 - Nu) * rdz;
+        T comb = a1 * G;
+        if (!first) comb -= a0 * at(uniform_ptr(a.Gu + kz), cb);
+        at(uniform_ptr(a.Gu + kz), cb) = G;
+        at(uniform_ptr(a.uo + kz), cb) = u_c + dt * comb;
+        gu += (double)comb;
+      }
+      // ---- v point (x centre i, y face j)
+      if (vpt) {
+        const T u_s = U[lu - P_UX], u_se = U[lu - P_UX + 1];
+        const T v_s = V[lv - P_VX];
+        const T ub = T(0.25) * (u_s + u_se + u_c + u_e);
+        const T zh = rec<T, SCHEME>(Z[lz - 2], Z[lz - 1], Z[lz], Z[lz + 1], Z[lz + 2], Z[lz + 3],
+                                    ub, eps);
+        const T ke_s = T(0.25) * (u_s * u_s + u_se * u_se + v_s * v_s + v_c * v_c);
+        T G = -(zh * ub) - ff * ub;
+        G -= (ke - ke_s) * rdy;
+        G -= at(uniform_ptr(a.py + kz), cb);
+        G -= (Fv1 - Fv) * rdz - v_c * (Wv1 - Wv) * rdz;
+        G += (Nv1 - Nv) * rdz;
+        T comb = a1 * G;
+        if (!first) comb -= a0 * at(uniform_ptr(a.Gv + kz), cb);
+        at(uniform_ptr(a.Gv + kz), cb) = G;
+        at(uniform_ptr(a.vo + kz), cb) = v_c + dt * comb;
+        gv += (double)comb;
+      } else {
+        at(uniform_ptr(a.Gv + kz), cb) = T(0);
+        at(uniform_ptr(a.vo + kz), cb) = T(0);
+      }
+      // ---- tracers at centre (i, j)
 #pragma unroll
-    for (int o = 0; o < 5; ++o) {
-      uw[o] = uw[o + 1];
-      vw[o] = vw[o + 1];
-      tw[o] = tw[o + 1];
-      sw[o] = sw[o + 1];
-    }
-    if (k + 1 < d.nz) {
-      const long cn = c + 4 * sz;  // level k + 4 (at most nz + 2, inside the halo)
-      uw[5] = a.u[cn];
-      vw[5] = a.v[cn];
-      tw[5] = a.t[cn];
-      sw[5] = a.s[cn];
+      for (int q = 0; q < 2; ++q) {
+        const T cc = q ? sw[2] : tw[2];
+        const T fx0 = FX[q][ty * (TTX + 1) + tx], fx1 = FX[q][ty * (TTX + 1) + tx + 1];
+        const T fy0 = FY[q][ty * TTX + tx], fy1 = FY[q][(ty + 1) * TTX + tx];
+        const T Fz0 = q ? Fs : Ft, Fz1 = q ? Fs1 : Ft1;
+        const T G = -((fx1 - fx0) + (fy1 - fy0) + (Fz1 - Fz0)) * rvol;
+        global_ptr<T> Gq = uniform_ptr((q ? a.Gs : a.Gt) + kz);
+        T comb = a1 * G;
+        if (!first) comb -= a0 * at(Gq, cb);
+        at(Gq, cb) = G;
+        at(uniform_ptr((q ? a.so : a.to) + kz), cb) = cc + dt * comb;
+      }
+
+      // ---- carry face k + 1 up; shift the windows
+      Fu = Fu1; Fv = Fv1; Ft = Ft1; Fs = Fs1; Nu = Nu1; Nv = Nv1; Wu = Wu1; Wv = Wv1;
+#pragma unroll
+      for (int o = 0; o < 5; ++o) {
+        uw[o] = uw[o + 1];
+        vw[o] = vw[o + 1];
+        tw[o] = tw[o + 1];
+        sw[o] = sw[o + 1];
+      }
+      if (k + 1 < d.nz) {
+        const long kn = kz + 4 * sz;  // level k + 4 (at most nz + 2, inside the halo)
+        uw[5] = at(uniform_ptr(a.u + kn), cb);
+        vw[5] = at(uniform_ptr(a.v + kn), cb);
+        tw[5] = at(uniform_ptr(a.t + kn), cb);
+        sw[5] = at(uniform_ptr(a.s + kn), cb);
+      }
     }
   }
-  a.gub[c2] = gu * m.dz;
-  a.gvb[c2] = vpt ? gv * m.dz : 0.0;
+  if (active) {
+    a.gub[c2] = gu * m.dz;
+    a.gvb[c2] = vpt ? gv * m.dz : 0.0;
+  }
 }
 
 // Halo images of the prognostic fields: x periodic; y walls with even
@@ -314,18 +551,17 @@ hipError_t launch_hydro_diag(const HydroBufs<T>& a, hipStream_t s) {
 template <class T>
 hipError_t launch_hydro_tendency(const HydroBufs<T>& a, const HydroStep<T>& st, int scheme,
                                  hipStream_t s) {
-  dim3 grid((a.d.nx + HTX - 1) / HTX, (a.d.ny + HTY - 1) / HTY);
+  const dim3 grid((unsigned)(((a.d.nx + TTX - 1) / TTX) * ((a.d.ny + TTY - 1) / TTY)));
+  const dim3 block(TTX, TTY);
   switch (scheme) {
     case tz::SCHEME_NONE:
-      hipLaunchKernelGGL((hydro_tend_kernel<T, tz::SCHEME_NONE>), grid, dim3(HTX, HTY), 0, s, a, st);
+      hipLaunchKernelGGL((hydro_tend_kernel<T, tz::SCHEME_NONE>), grid, block, 0, s, a, st);
       break;
     case tz::SCHEME_LINEAR:
-      hipLaunchKernelGGL((hydro_tend_kernel<T, tz::SCHEME_LINEAR>), grid, dim3(HTX, HTY), 0, s, a,
-                         st);
+      hipLaunchKernelGGL((hydro_tend_kernel<T, tz::SCHEME_LINEAR>), grid, block, 0, s, a, st);
       break;
     default:
-      hipLaunchKernelGGL((hydro_tend_kernel<T, tz::SCHEME_WENOZ>), grid, dim3(HTX, HTY), 0, s, a,
-                         st);
+      hipLaunchKernelGGL((hydro_tend_kernel<T, tz::SCHEME_WENOZ>), grid, block, 0, s, a, st);
   }
   return hipGetLastError();
 }
