@@ -34,6 +34,7 @@
 // z), and the halo fill of the prognostic fields.
 #include "oc_internal.h"
 #include "weno_dev.h"
+#include "gaddr.h"
 
 namespace oc {
 
@@ -179,28 +180,6 @@ __device__ inline int hydro_tile_index() {
 // W).  Points past the padded upper edges are not fetched; their LDS entries
 // are never read.
 constexpr int TNT = TTX * TTY;
-
-// A workgroup-uniform pointer made opaque to the compiler's address
-// folding, so that p[off] with a 32-bit per-thread offset keeps the base in
-// scalar registers (a global load with a scalar base and a vector offset)
-// instead of being merged into a 64-bit per-thread address.
-template <class T>
-using global_ptr = __attribute__((address_space(1))) T*;
-
-template <class T>
-__device__ inline global_ptr<T> uniform_ptr(T* p) {
-  const unsigned long long v = (unsigned long long)p;
-  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
-  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
-  return (global_ptr<T>)(((unsigned long long)hi << 32) | lo);
-}
-
-// Element of a uniform base at a 32-bit byte offset (the padded fields of
-// this kernel hold fewer than 2^32 bytes).
-template <class T>
-__device__ inline __attribute__((address_space(1))) T& at(global_ptr<T> p, unsigned off) {
-  return *(global_ptr<T>)((__attribute__((address_space(1))) char*)p + off);
-}
 
 constexpr int box_n(int w, int h) { return (w * h + TNT - 1) / TNT; }
 
