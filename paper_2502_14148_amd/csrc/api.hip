@@ -494,27 +494,30 @@ int tendency_call(oc_model* m, int in, int out, int stage, double dt, int combin
 
 // The FFT/DCT solve of the whole box applied to a dense FP64 field: sb.p =
 // L^-1 src (the preconditioner of the immersed-boundary iteration); the last
-// pass also leaves the partial sums of src . sb.p in cg.part (*npart).
+// pass also leaves the partial sums of src . sb.p in cg.part (*npart).  The
+// passes do nothing once the iteration's stop flag is set.
 int fft_solve_dense(oc_model* m, const double* src, int* npart, hipStream_t s) {
+  SpecBufs sb = m->sb;
+  sb.stop = m->cg.scal + CG_DONE;
   {
     ProfScope ps(m, OC_PROF_FFT_X_FWD, s);
-    OC_CHECK_HIP(launch_poisson_x_forward_dense(m->dims, src, m->sb, s));
+    OC_CHECK_HIP(launch_poisson_x_forward_dense(m->dims, src, sb, s));
   }
   {
     ProfScope ps(m, OC_PROF_FFT_Y_FWD, s);
-    OC_CHECK_HIP(launch_poisson_y(m->dims, m->sb, -1, s));
+    OC_CHECK_HIP(launch_poisson_y(m->dims, sb, -1, s));
   }
   {
     ProfScope ps(m, OC_PROF_Z_SOLVE, s);
-    OC_CHECK_HIP(launch_poisson_spectral(m->dims, m->sb, s));
+    OC_CHECK_HIP(launch_poisson_spectral(m->dims, sb, s));
   }
   {
     ProfScope ps(m, OC_PROF_FFT_Y_INV, s);
-    OC_CHECK_HIP(launch_poisson_y(m->dims, m->sb, 1, s));
+    OC_CHECK_HIP(launch_poisson_y(m->dims, sb, 1, s));
   }
   {
     ProfScope ps(m, OC_PROF_FFT_X_INV, s);
-    OC_CHECK_HIP(launch_poisson_x_inverse_dot(m->dims, m->sb, src, m->cg.part, IB_PART_CAP, npart,
+    OC_CHECK_HIP(launch_poisson_x_inverse_dot(m->dims, sb, src, m->cg.part, IB_PART_CAP, npart,
                                               s));
   }
   return OC_OK;
@@ -524,7 +527,12 @@ int fft_solve_dense(oc_model* m, const double* src, int* npart, hipStream_t s) {
 // masked Poisson equation, preconditioned by the FFT solve of the whole box
 // (the residual is zero in immersed cells; the result is masked), until
 // |r| <= cg_tol |b| or cg_maxiter iterations.  The scalars of an iteration
-// stay on the device; the host reads the stop flag once per iteration.
+// stay on the device, and every kernel of an iteration does nothing once the
+// stop flag is set, so the host need not look at the flag after every
+// iteration: it first looks after one iteration fewer than the previous
+// solve took, then after every iteration (solves of successive substeps
+// take similar counts).  Queued iterations past convergence cost launches
+// only.
 template <class T>
 int pressure_call_immersed(oc_model* m, int which, double dt_eff, hipStream_t s) {
   T* u = (T*)m->state[which][0];
@@ -552,6 +560,7 @@ int pressure_call_immersed(oc_model* m, int which, double dt_eff, hipStream_t s)
   }
   const double rdx2 = 1.0 / (m->dx * m->dx), rdy2 = 1.0 / (m->dy * m->dy);
   const double rdz2 = 1.0 / (m->dz * m->dz);
+  const int first_look = std::max(1, m->cg_iterations - 1);
   for (int it = 0; it < maxit; ++it) {
     {
       ProfScope pc(m, OC_PROF_CG, s);
@@ -560,10 +569,12 @@ int pressure_call_immersed(oc_model* m, int which, double dt_eff, hipStream_t s)
       OC_CHECK_HIP(launch_ib_update(d, cg, s));
       OC_CHECK_HIP(launch_ib_finalize(cg, CG_FIN_RES, tol2, maxit, s));
     }
-    OC_CHECK_HIP(hipMemcpyAsync(m->cg_host, cg.scal, CG_NSCAL * sizeof(double),
-                                hipMemcpyDeviceToHost, s));
-    OC_CHECK_HIP(hipStreamSynchronize(s));
-    if (m->cg_host[CG_DONE] != 0.0) break;
+    if (it + 1 >= first_look || it + 1 == maxit) {   // the last iteration always looks
+      OC_CHECK_HIP(hipMemcpyAsync(m->cg_host, cg.scal, CG_NSCAL * sizeof(double),
+                                  hipMemcpyDeviceToHost, s));
+      OC_CHECK_HIP(hipStreamSynchronize(s));
+      if (m->cg_host[CG_DONE] != 0.0) break;
+    }
     rc = fft_solve_dense(m, cg.r, &npart, s);
     if (rc) return rc;
     {

@@ -92,36 +92,57 @@ __global__ void __launch_bounds__(IB_NT) ib_rhs_kernel(Dims d, const T* __restri
 }
 
 // aq = A q (the masked 7-point operator, zero in immersed cells); partial
-// sums of q . aq.
+// sums of q . aq.  Work items are 32 x 8 column tiles of IB_KC levels; each
+// workgroup takes items b, b + IB_NPART, ... (XCD-contiguous numbering) and
+// marches its columns up the levels, so q of a column is fetched once and
+// carried in registers as the z neighbours of the next levels; the four
+// in-plane neighbours come through the caches.  Every neighbour is loaded
+// and weighted by its face's open flag; z neighbours beyond a wall are read
+// from the periodic image, which the flag then discards.
+constexpr int IB_TX = 32, IB_TY = 8, IB_KC = 16;
+
 __global__ void __launch_bounds__(IB_NT) ib_apply_kernel(Dims d, const uint8_t* __restrict__ bits,
                                                          double rdx2, double rdy2, double rdz2,
                                                          CgBufs cg) {
   __shared__ double sh[IB_NT];
   if (cg.scal[CG_DONE] != 0.0) return;
-  const long N = (long)d.nx * d.ny * d.nz;
-  const long plane = (long)d.nx * d.ny;
+  const int nbx = (d.nx + IB_TX - 1) / IB_TX, nby = (d.ny + IB_TY - 1) / IB_TY;
+  const int nbz = (d.nz + IB_KC - 1) / IB_KC;
+  const int items = nbx * nby * nbz;
+  const unsigned plane = (unsigned)d.nx * d.ny;
   const double* __restrict__ q = cg.q;
+  const int tx = threadIdx.x % IB_TX, ty = threadIdx.x / IB_TX;
+  const unsigned nb = gridDim.x, b0 = blockIdx.x;
+  const int vb = (int)((nb % 8 == 0) ? (b0 % 8) * (nb / 8) + b0 / 8 : b0);
   double acc = 0.0;
-  for (long n = first_cell(); n < N; n += (long)gridDim.x * IB_NT) {
-    // every neighbour is loaded (all loads in flight at once) and weighted
-    // by its face's open flag; z neighbours beyond a wall are read from the
-    // periodic image, which the flag then discards
-    const unsigned fb = bits[n];
-    const double q0 = q[n];
-    int i, j, k;
-    cell_of(d, n, i, j, k);
-    const double qxm = q[(i == 0) ? n + d.nx - 1 : n - 1];
-    const double qxp = q[(i + 1 == d.nx) ? n - (d.nx - 1) : n + 1];
-    const double qym = q[(j == 0) ? n + plane - d.nx : n - d.nx];
-    const double qyp = q[(j + 1 == d.ny) ? n - plane + d.nx : n + d.nx];
-    const double qzm = q[(k == 0) ? n + (long)(d.nz - 1) * plane : n - plane];
-    const double qzp = q[(k + 1 == d.nz) ? n - (long)(d.nz - 1) * plane : n + plane];
-    auto on = [fb](unsigned bit) { return (fb & bit) ? 1.0 : 0.0; };
-    const double a = (on(IB_XM) * (qxm - q0) + on(IB_XP) * (qxp - q0)) * rdx2 +
-                     (on(IB_YM) * (qym - q0) + on(IB_YP) * (qyp - q0)) * rdy2 +
-                     (on(IB_ZM) * (qzm - q0) + on(IB_ZP) * (qzp - q0)) * rdz2;
-    cg.aq[n] = a;
-    acc += q0 * a;
+  for (int item = vb; item < items; item += (int)nb) {
+    const int i = (item % nbx) * IB_TX + tx;
+    const int j = ((item / nbx) % nby) * IB_TY + ty;
+    const int kb = (item / (nbx * nby)) * IB_KC, ke = min(kb + IB_KC, d.nz);
+    if (i >= d.nx || j >= d.ny) continue;
+    // in-plane offsets of the own cell and its x, y neighbours (periodic)
+    const unsigned c = (unsigned)j * d.nx + i;
+    const unsigned cxm = (i == 0) ? c + d.nx - 1 : c - 1;
+    const unsigned cxp = (i + 1 == d.nx) ? c - (d.nx - 1) : c + 1;
+    const unsigned cym = (j == 0) ? c + plane - d.nx : c - d.nx;
+    const unsigned cyp = (j + 1 == d.ny) ? c - plane + d.nx : c + d.nx;
+    double qm = q[(kb == 0 ? (unsigned)(d.nz - 1) : (unsigned)(kb - 1)) * plane + c];
+    double q0 = q[(unsigned)kb * plane + c];
+    for (int k = kb; k < ke; ++k) {
+      const unsigned pk = (unsigned)k * plane;
+      const double qp = q[(k + 1 == d.nz ? 0u : pk + plane) + c];
+      const unsigned fb = bits[pk + c];
+      const double qxm = q[pk + cxm], qxp = q[pk + cxp];
+      const double qym = q[pk + cym], qyp = q[pk + cyp];
+      auto on = [fb](unsigned bit) { return (fb & bit) ? 1.0 : 0.0; };
+      const double a = (on(IB_XM) * (qxm - q0) + on(IB_XP) * (qxp - q0)) * rdx2 +
+                       (on(IB_YM) * (qym - q0) + on(IB_YP) * (qyp - q0)) * rdy2 +
+                       (on(IB_ZM) * (qm - q0) + on(IB_ZP) * (qp - q0)) * rdz2;
+      cg.aq[pk + c] = a;
+      acc += q0 * a;
+      qm = q0;
+      q0 = qp;
+    }
   }
   const double s = block_sum(acc, sh);
   if (threadIdx.x == 0) cg.part[blockIdx.x] = s;

@@ -141,6 +141,8 @@ struct SpecBufs {
   const double* lamz;
   int nxh;                   // nx / 2 + 1 stored wavenumbers
   int nxp;                   // row pitch: nxh rounded up to 8 (128-byte rows)
+  const double* stop = nullptr;  // optional device flag: while *stop != 0 the
+                                 // passes return at once (a converged iteration)
 };
 
 // Row pitch of the half spectrum in complex elements: column groups of 8 start

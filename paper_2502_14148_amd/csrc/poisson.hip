@@ -142,6 +142,7 @@ __global__ void __launch_bounds__(NT) fwd_x_kernel(Dims d, const T* __restrict__
                                                    const double* __restrict__ rdzc, SpecBufs sb,
                                                    const PoissonSlots* __restrict__ bs,
                                                    const double* __restrict__ dense) {
+  if (sb.stop && *sb.stop != 0.0) return;
   if (bs) {
     const int z = blockIdx.z;
     u = (const T*)bs->u[z];
@@ -217,6 +218,7 @@ __global__ void __launch_bounds__(NT) fwd_x_kernel(Dims d, const T* __restrict__
 template <int N, int DIR>
 __global__ void __launch_bounds__(NT) y_kernel(Dims d, SpecBufs sb,
                                                const PoissonSlots* __restrict__ bs) {
+  if (sb.stop && *sb.stop != 0.0) return;
   if (bs) sb.spec = bs->spec[blockIdx.z];
   constexpr int W = YZCfg<N>::W;
   __shared__ double2 buf[W * N];
@@ -254,6 +256,7 @@ __device__ inline int makhoul_pos(int m, int n) {
 template <int N, bool BOUNDED>
 __global__ void __launch_bounds__(NT) z_kernel(Dims d, SpecBufs sb, double norm,
                                                const PoissonSlots* __restrict__ bs) {
+  if (sb.stop && *sb.stop != 0.0) return;
   if (bs) sb.spec = bs->spec[blockIdx.z];
   constexpr int W = YZCfg<N>::W;
   constexpr int PER = (W * N + NT - 1) / NT;
@@ -482,6 +485,7 @@ __global__ void __launch_bounds__(NT) inv_x_kernel(Dims d, SpecBufs sb,
                                                    const PoissonSlots* __restrict__ bs,
                                                    const double* __restrict__ rdot,
                                                    double* __restrict__ part) {
+  if (sb.stop && *sb.stop != 0.0) return;
   if (bs) {
     sb.spec = bs->spec[blockIdx.z];
     sb.p = bs->p[blockIdx.z];
