@@ -111,6 +111,7 @@ __global__ void __launch_bounds__(IB_NT) ib_apply_kernel(Dims d, const uint8_t* 
   const int items = nbx * nby * nbz;
   const unsigned plane = (unsigned)d.nx * d.ny;
   const double* __restrict__ q = cg.q;
+  double* __restrict__ aq = cg.aq;
   const int tx = threadIdx.x % IB_TX, ty = threadIdx.x / IB_TX;
   const unsigned nb = gridDim.x, b0 = blockIdx.x;
   const int vb = (int)((nb % 8 == 0) ? (b0 % 8) * (nb / 8) + b0 / 8 : b0);
@@ -138,7 +139,7 @@ __global__ void __launch_bounds__(IB_NT) ib_apply_kernel(Dims d, const uint8_t* 
       const double a = (on(IB_XM) * (qxm - q0) + on(IB_XP) * (qxp - q0)) * rdx2 +
                        (on(IB_YM) * (qym - q0) + on(IB_YP) * (qyp - q0)) * rdy2 +
                        (on(IB_ZM) * (qm - q0) + on(IB_ZP) * (qp - q0)) * rdz2;
-      cg.aq[pk + c] = a;
+      aq[pk + c] = a;
       acc += q0 * a;
       qm = q0;
       q0 = qp;
