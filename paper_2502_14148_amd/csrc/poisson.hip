@@ -15,7 +15,7 @@
 //   5. x: complex-to-real inverse FFT -> p.
 // Then a projection kernel applies u -= dt_eff grad p.
 //
-// Transforms are radix-4/2/3 Stockham passes in LDS, one radix-R butterfly
+// Transforms are radix-8/4/2/3 Stockham passes in LDS, one radix-R butterfly
 // per thread per pass, twiddles from FP64 tables.
 #include "oc_internal.h"
 
@@ -48,6 +48,24 @@ __device__ inline void dft(double2* v) {
     v[2] = csub(a, c);
     v[1] = cadd(b, mul_i<DIR>(d));
     v[3] = csub(b, mul_i<DIR>(d));
+  } else if (R == 8) {
+    // two length-4 DFTs of the even and odd terms, combined with the
+    // eighth roots of unity w^k, w = exp(DIR 2 pi i / 8)
+    double2 e[4] = {v[0], v[2], v[4], v[6]}, o[4] = {v[1], v[3], v[5], v[7]};
+    dft<4, DIR>(e);
+    dft<4, DIR>(o);
+    const double h = 0.70710678118654752440, s = DIR;  // sqrt(2)/2
+    const double2 o1 = make_double2(h * (o[1].x - s * o[1].y), h * (o[1].y + s * o[1].x));
+    const double2 o2 = mul_i<DIR>(o[2]);
+    const double2 o3 = make_double2(h * (-o[3].x - s * o[3].y), h * (-o[3].y + s * o[3].x));
+    v[0] = cadd(e[0], o[0]);
+    v[4] = csub(e[0], o[0]);
+    v[1] = cadd(e[1], o1);
+    v[5] = csub(e[1], o1);
+    v[2] = cadd(e[2], o2);
+    v[6] = csub(e[2], o2);
+    v[3] = cadd(e[3], o3);
+    v[7] = csub(e[3], o3);
   } else {  // R == 3
     const double h = 0.86602540378443864676;  // sqrt(3)/2
     double2 t = cadd(v[1], v[2]), s = csub(v[1], v[2]);
@@ -104,13 +122,19 @@ __device__ inline void stockham_pass(double2* buf, int ls, int es, const double2
   __syncthreads();
 }
 
-template <int N, int NS, int L, int NT, int DIR, bool LINE_FAST>
+// Radix MAXR (4 or 8) while it divides what remains, then 4, 2, 3.  Radix 8
+// saves a quarter of the LDS round trips; it pays in the y and z passes
+// (eight interleaved lines: one butterfly per thread) and not in the x
+// passes, whose few lines leave half the threads idle at radix 8.
+template <int N, int NS, int L, int NT, int DIR, bool LINE_FAST, int MAXR = 4>
 __device__ inline void fft_lines(double2* buf, int ls, int es, const double2* __restrict__ tw) {
   if constexpr (NS < N) {
     constexpr int REM = N / NS;
-    constexpr int R = (REM % 4 == 0) ? 4 : ((REM % 2 == 0) ? 2 : 3);
+    constexpr int R = (MAXR >= 8 && REM % 8 == 0)
+                          ? 8
+                          : ((REM % 4 == 0) ? 4 : ((REM % 2 == 0) ? 2 : 3));
     stockham_pass<N, R, NS, L, NT, DIR, LINE_FAST>(buf, ls, es, tw);
-    fft_lines<N, NS * R, L, NT, DIR, LINE_FAST>(buf, ls, es, tw);
+    fft_lines<N, NS * R, L, NT, DIR, LINE_FAST, MAXR>(buf, ls, es, tw);
   }
 }
 
@@ -237,7 +261,7 @@ __global__ void __launch_bounds__(NT) y_kernel(Dims d, SpecBufs sb,
                              : make_double2(0.0, 0.0);
   }
   __syncthreads();
-  fft_lines<N, 1, W, NT, DIR, true>(buf, 1, W, tws);
+  fft_lines<N, 1, W, NT, DIR, true, 8>(buf, 1, W, tws);
   for (int t = threadIdx.x; t < W * N; t += NT) {
     const int c = t % W, y = t / W;
     if (kx0 + c < nxh) sb.spec[((long)k * d.ny + y) * nxp + kx0 + c] = buf[t];
@@ -277,7 +301,7 @@ __global__ void __launch_bounds__(NT) z_kernel(Dims d, SpecBufs sb, double norm,
                                        : make_double2(0.0, 0.0);
   }
   __syncthreads();
-  fft_lines<N, 1, W, NT, -1, true>(buf, 1, W, tws);
+  fft_lines<N, 1, W, NT, -1, true, 8>(buf, 1, W, tws);
   // spectral division
   double2 val[PER];
 #pragma unroll
@@ -321,7 +345,7 @@ __global__ void __launch_bounds__(NT) z_kernel(Dims d, SpecBufs sb, double norm,
     }
     __syncthreads();
   }
-  fft_lines<N, 1, W, NT, 1, true>(buf, 1, W, tws);
+  fft_lines<N, 1, W, NT, 1, true, 8>(buf, 1, W, tws);
   for (int t = threadIdx.x; t < W * N; t += NT) {
     const int c = t % W, z = t / W;
     const int pos = BOUNDED ? makhoul_pos(z, N) : z;
