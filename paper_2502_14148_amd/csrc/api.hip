@@ -1076,10 +1076,12 @@ int free_surface_call(oc_model* m, double dt, int N, int M, const double* a, hip
   OC_CHECK_HIP(launch_baro_fill(m->vbar, 0.0, n2, s));
   const double dtau = dt / N;
   const double gH = m->md.g * m->md.depth;
-  for (int n = 0; n < M; ++n) {
+  for (int n = 0; n < M;) {
+    const int ns = std::min(baro_max_fused(), M - n);
     BaroBufs b = baro_bufs(m);
-    OC_CHECK_HIP(launch_baro_substep(b, dtau, gH, a[n], s));
+    OC_CHECK_HIP(launch_baro_substeps(b, dtau, gH, a + n, ns, s));
     m->bcur = 1 - m->bcur;
+    n += ns;
   }
   // correction of the baroclinic velocity: its depth integral becomes Ubar
   const double dz = m->gd.lz / m->gd.nz;

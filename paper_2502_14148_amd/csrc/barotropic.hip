@@ -1,60 +1,124 @@
 // Split-explicit barotropic substeps of the hydrostatic model on gfx950
 // (hydrostatic time-discretisation appendix of arXiv 2502.14148).
 //
-// One launch per substep; a substep reads (eta, U, V)^n from one buffer set
-// and writes (eta, U, V)^{n+1} to the other.  Each workgroup recomputes
-// eta^{n+1} on a one-cell halo (left column, bottom row) of its tile, so the
-// forward (eta) and backward (U, V) halves of the substep fuse into one
-// kernel without a grid-wide barrier.  The running averages are accumulated
-// in place in FP64.  All 2D arrays are dense FP64, x fastest; x is
-// periodic, y has walls (V = 0 on faces 0 and ny).
+// A launch advances up to BHS substeps (temporal blocking, below); it reads
+// (eta, U, V)^n from one buffer set and writes the state after its last
+// substep to the other.  Each workgroup recomputes the substeps on a halo
+// around its tile, so neither the forward (eta) and backward (U, V) halves
+// of a substep nor successive substeps need a grid-wide barrier.  The
+// running averages are accumulated in place in FP64.  All 2D arrays are
+// dense FP64, x fastest; x is periodic, y has walls (V = 0 on faces 0 and
+// ny).
 #include "oc_internal.h"
 
 namespace oc {
 
 namespace {
 
-constexpr int BTX = 32, BTY = 8;
+// Own tile of a workgroup (one cell per thread) and the substeps per launch:
+// on the 1440 x 560 sector 32 x 32 with 4 took 0.89 ms per 59 substeps
+// (plus correction and restart), 32 x 16 0.95, 32 x 8 1.10; halos of 2, 3,
+// 5, 6, 8 on 32 x 8 or 32 x 16 tiles were slower or no faster.
+constexpr int BTX = 32, BTY = 32;
 
-// transport divergence at cell (i, j)
-__device__ inline double baro_div(const BaroBufs& b, int i, int j) {
-  const int ip = (i + 1 == b.nx) ? 0 : i + 1;
-  const long r = (long)j * b.nx;
-  const double fx = b.len_u[j] * (b.U[r + ip] - b.U[r + i]);
-  const double fy = b.len_v[j + 1] * b.V[r + b.nx + i] - b.len_v[j] * b.V[r + i];
-  return (fx + fy) / b.area[j];
-}
+// Up to BHS substeps in one launch (temporal blocking).  A workgroup owns a
+// BTX x BTY tile and stages eta, U, V, GU, GV on the tile widened by BHS
+// cells on every side (plus the U column and V row beyond) in LDS.  Each
+// substep is valid on a region one cell narrower per side than the last
+// (eta needs U, V one cell right/above; U, V need eta one cell left/below),
+// so after ns <= BHS substeps the own tile is exact.  Rows outside the
+// domain hold zeros and the wall faces V(0), V(ny) stay zero; x wraps
+// periodically.  The running averages of the own cells take the substeps'
+// terms one at a time, in substep order.
+constexpr int BHS = 4;
+constexpr int BEX = BTX + 2 * BHS, BEY = BTY + 2 * BHS;   // widened tile
+constexpr int BPX = BEX + 1, BPY = BEY + 1;               // + U column, V row
+struct BaroWeights {
+  double w[BHS];
+};
 
-__global__ void __launch_bounds__(BTX * BTY) baro_substep_kernel(BaroBufs b, double dtau, double gH,
-                                                                 double wn) {
-  __shared__ double eta1[BTY + 1][BTX + 1];
-  const int i0 = blockIdx.x * BTX, j0 = blockIdx.y * BTY;
+__global__ void __launch_bounds__(BTX * BTY) baro_multi_kernel(BaroBufs b, double dtau,
+                                                               double gH, BaroWeights wts,
+                                                               int ns) {
+  __shared__ double E[BPY][BPX], Us[BPY][BPX], Vs[BPY][BPX], Gu[BPY][BPX], Gv[BPY][BPX];
+  const int i0 = blockIdx.x * BTX - BHS, j0 = blockIdx.y * BTY - BHS;   // corner of the widened tile
   const int tid = threadIdx.x;
-  // eta^{n+1} on the tile plus its left column and bottom row
-  for (int e = tid; e < (BTX + 1) * (BTY + 1); e += BTX * BTY) {
-    const int ly = e / (BTX + 1), lx = e - ly * (BTX + 1);
-    int i = i0 - 1 + lx;
-    if (i < 0) i += b.nx;
-    const int j = j0 - 1 + ly;
-    double v = 0.0;
-    if (j >= 0 && j < b.ny && i < b.nx) v = b.eta[(long)j * b.nx + i] - dtau * baro_div(b, i, j);
-    eta1[ly][lx] = v;
+  for (int e = tid; e < BPX * BPY; e += BTX * BTY) {
+    const int y = e / BPX, x = e - y * BPX;
+    int gi = (i0 + x) % b.nx;
+    if (gi < 0) gi += b.nx;
+    const int gj = j0 + y;
+    double ev = 0.0, uv = 0.0, vv = 0.0, gu = 0.0, gv = 0.0;
+    if (gj >= 0 && gj < b.ny) {
+      const long c = (long)gj * b.nx + gi;
+      ev = b.eta[c];
+      uv = b.U[c];
+      gu = b.GU[c];
+      if (gj > 0) {
+        vv = b.V[c];
+        gv = b.GV[c];
+      }
+    }
+    E[y][x] = ev;
+    Us[y][x] = uv;
+    Vs[y][x] = vv;
+    Gu[y][x] = gu;
+    Gv[y][x] = gv;
+  }
+  // own cell of this thread and its running averages
+  const int tx = tid % BTX, ty = tid / BTX;
+  const int oi = i0 + BHS + tx, oj = j0 + BHS + ty;
+  const bool own = oi < b.nx && oj < b.ny;
+  const long oc = (long)oj * b.nx + oi;
+  double ea = 0.0, ua = 0.0, va = 0.0;
+  if (own) {
+    ea = b.etab[oc];
+    ua = b.Ub[oc];
+    va = b.Vb[oc];
   }
   __syncthreads();
-  const int tx = tid % BTX, ty = tid / BTX;
-  const int i = i0 + tx, j = j0 + ty;
-  if (i >= b.nx || j >= b.ny) return;
-  const long c = (long)j * b.nx + i;
-  const double en = eta1[ty + 1][tx + 1];
-  const double un = b.U[c] - dtau * (gH * (en - eta1[ty + 1][tx]) / b.dx_u[j] - b.GU[c]);
-  double vn = 0.0;  // the southern wall face j = 0 stays closed
-  if (j > 0) vn = b.V[c] - dtau * (gH * (en - eta1[ty][tx + 1]) / b.dy_v[j] - b.GV[c]);
-  b.eta1[c] = en;
-  b.U1[c] = un;
-  b.V1[c] = vn;
-  b.etab[c] += wn * en;
-  b.Ub[c] += wn * un;
-  b.Vb[c] += wn * vn;
+  for (int sstep = 0; sstep < ns; ++sstep) {
+    // eta^{n+1} = eta^n - dtau div(U^n, V^n) on rows 0..BEY-1, columns 0..BEX-1
+    for (int e = tid; e < BEX * BEY; e += BTX * BTY) {
+      const int y = e / BEX, x = e - y * BEX;
+      const int gj = j0 + y;
+      if (gj >= 0 && gj < b.ny) {
+        const double fx = b.len_u[gj] * (Us[y][x + 1] - Us[y][x]);
+        const double fy = b.len_v[gj + 1] * Vs[y + 1][x] - b.len_v[gj] * Vs[y][x];
+        E[y][x] = E[y][x] - dtau * ((fx + fy) / b.area[gj]);
+      }
+    }
+    __syncthreads();
+    // eta is not written again before the next substep's first barrier
+    const double wn = wts.w[sstep];
+    if (own) ea += wn * E[BHS + ty][BHS + tx];
+    // U^{n+1}, V^{n+1} from eta^{n+1} (columns / rows 1.. of the widened tile)
+    for (int e = tid; e < BEX * BEY; e += BTX * BTY) {
+      const int y = e / BEX, x = e - y * BEX;
+      const int gj = j0 + y;
+      if (gj >= 0 && gj < b.ny) {
+        const double en = E[y][x];
+        if (x > 0) Us[y][x] = Us[y][x] - dtau * (gH * (en - E[y][x - 1]) / b.dx_u[gj] - Gu[y][x]);
+        if (y > 0)
+          Vs[y][x] = (gj > 0)
+                         ? Vs[y][x] - dtau * (gH * (en - E[y - 1][x]) / b.dy_v[gj] - Gv[y][x])
+                         : 0.0;
+      }
+    }
+    __syncthreads();
+    // U and V are not written again before the next substep's second barrier
+    if (own) {
+      ua += wn * Us[BHS + ty][BHS + tx];
+      va += wn * Vs[BHS + ty][BHS + tx];
+    }
+  }
+  if (!own) return;
+  b.eta1[oc] = E[BHS + ty][BHS + tx];
+  b.U1[oc] = Us[BHS + ty][BHS + tx];
+  b.V1[oc] = Vs[BHS + ty][BHS + tx];
+  b.etab[oc] = ea;
+  b.Ub[oc] = ua;
+  b.Vb[oc] = va;
 }
 
 __global__ void baro_fill_kernel(double* a, double v, long n) {
@@ -98,10 +162,15 @@ hipError_t launch_baro_copy(double* dst, const double* src, long n, hipStream_t 
   return hipGetLastError();
 }
 
-hipError_t launch_baro_substep(const BaroBufs& b, double dtau, double gH, double wn,
-                               hipStream_t s) {
+int baro_max_fused() { return BHS; }
+
+hipError_t launch_baro_substeps(const BaroBufs& b, double dtau, double gH, const double* wn,
+                                int ns, hipStream_t s) {
+  if (ns < 1 || ns > BHS) return hipErrorInvalidValue;
+  BaroWeights w{};
+  for (int q = 0; q < ns; ++q) w.w[q] = wn[q];
   dim3 grid((b.nx + BTX - 1) / BTX, (b.ny + BTY - 1) / BTY);
-  hipLaunchKernelGGL(baro_substep_kernel, grid, dim3(BTX * BTY), 0, s, b, dtau, gH, wn);
+  hipLaunchKernelGGL(baro_multi_kernel, grid, dim3(BTX * BTY), 0, s, b, dtau, gH, w, ns);
   return hipGetLastError();
 }
 

@@ -173,7 +173,11 @@ struct BaroBufs {
 
 hipError_t launch_baro_fill(double* a, double v, long n, hipStream_t s);
 hipError_t launch_baro_copy(double* dst, const double* src, long n, hipStream_t s);
-hipError_t launch_baro_substep(const BaroBufs& b, double dtau, double gH, double wn, hipStream_t s);
+// ns (1..baro_max_fused()) barotropic substeps in one launch, with the
+// averaging weights wn[0..ns-1] (host array).
+int baro_max_fused();
+hipError_t launch_baro_substeps(const BaroBufs& b, double dtau, double gH, const double* wn,
+                                int ns, hipStream_t s);
 template <class T>
 hipError_t launch_baro_correct(const Dims& d, T* f, const double* bar, int j_lo, int j_hi,
                                double dz, double depth, hipStream_t s);

@@ -570,7 +570,7 @@ __global__ void __launch_bounds__(NT) inv_x_kernel(Dims d, SpecBufs sb,
 // pressure of the plane below in a register, so p is fetched once per cell
 // (plus one plane per chunk).
 // ---------------------------------------------------------------------------
-constexpr int PJ_X = 64, PJ_Y = 4, PJ_KC = 16;
+constexpr int PJ_X = 64, PJ_Y = 4, PJ_KC = 8;
 
 // mask != null (immersed boundary): velocities on closed faces are set to 0.
 template <class T>
