@@ -140,12 +140,25 @@ __global__ void baro_correct_kernel(Dims d, T* __restrict__ f, const double* __r
   const int j = j_lo + blockIdx.y;
   if (i >= d.nx || j >= j_hi) return;
   const long c0 = pidx(d, i, j, 0);
+  // levels fetched CKB at a time so that their loads are in flight together
+  constexpr int CKB = 10;
   double sum = 0.0;
-  for (int k = 0; k < d.nz; ++k) sum += (double)f[c0 + (long)k * d.sz];
+  for (int k0 = 0; k0 < d.nz; k0 += CKB) {
+    T x[CKB];
+#pragma unroll
+    for (int q = 0; q < CKB; ++q) x[q] = f[c0 + (long)min(k0 + q, d.nz - 1) * d.sz];
+#pragma unroll
+    for (int q = 0; q < CKB; ++q)
+      if (k0 + q < d.nz) sum += (double)x[q];
+  }
   const double corr = (bar[(long)j * d.nx + i] - dz * sum) * inv_h;
-  for (int k = 0; k < d.nz; ++k) {
-    const long c = c0 + (long)k * d.sz;
-    f[c] = (T)((double)f[c] + corr);
+  for (int k0 = 0; k0 < d.nz; k0 += CKB) {
+    T x[CKB];
+#pragma unroll
+    for (int q = 0; q < CKB; ++q) x[q] = f[c0 + (long)min(k0 + q, d.nz - 1) * d.sz];
+#pragma unroll
+    for (int q = 0; q < CKB; ++q)
+      if (k0 + q < d.nz) f[c0 + (long)(k0 + q) * d.sz] = (T)((double)x[q] + corr);
   }
 }
 
