@@ -46,11 +46,19 @@ constexpr int HTX = 64, HTY = 4;
 // loads).
 constexpr int DKB = 8;
 
+// Column scans over the columns i, j in [-2, n + 2] (what the tendency
+// kernel reads of zeta and w).  Workgroups are renumbered XCD-contiguous
+// (x fastest), so the neighbouring rows a column reads were fetched into the
+// same L2 by the workgroups just before it.
 template <class T>
 __global__ void __launch_bounds__(HTX * HTY) hydro_diag_kernel(HydroBufs<T> a) {
   const Dims d = a.d;
-  const int i = -2 + (int)(blockIdx.x * HTX + threadIdx.x);
-  const int j = -2 + (int)(blockIdx.y * HTY + threadIdx.y);
+  const int nbx = (d.nx + 5 + HTX - 1) / HTX;
+  const int n = (int)gridDim.x, b = (int)blockIdx.x;
+  const int q = n / 8, r = n % 8, x8 = b % 8;
+  const int t = x8 * q + min(x8, r) + b / 8;
+  const int i = -2 + (t % nbx) * HTX + (int)threadIdx.x;
+  const int j = -2 + (t / nbx) * HTY + (int)threadIdx.y;
   if (i > d.nx + 2 || j > d.ny + 2) return;
   const HydroMetric& m = a.m;
   const T dy = (T)m.dy;
@@ -528,8 +536,9 @@ __global__ void hydro_halo_kernel(Dims d, T* u, T* v, T* t, T* s) {
 
 template <class T>
 hipError_t launch_hydro_diag(const HydroBufs<T>& a, hipStream_t s) {
-  dim3 grid((a.d.nx + 5 + HTX - 1) / HTX, (a.d.ny + 5 + HTY - 1) / HTY);
-  hipLaunchKernelGGL(hydro_diag_kernel<T>, grid, dim3(HTX, HTY), 0, s, a);
+  const unsigned nb =
+      (unsigned)(((a.d.nx + 5 + HTX - 1) / HTX) * ((a.d.ny + 5 + HTY - 1) / HTY));
+  hipLaunchKernelGGL(hydro_diag_kernel<T>, dim3(nb), dim3(HTX, HTY), 0, s, a);
   return hipGetLastError();
 }
 
