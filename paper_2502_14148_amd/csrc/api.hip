@@ -262,6 +262,15 @@ int validate_pair(const oc_grid_desc& g, const oc_model_desc& m) {
     set_error("the hydrostatic model runs on lat-lon grids");
     return OC_ERR_UNSUPPORTED;
   }
+  if (m.kind == OC_HYDROSTATIC) {
+    // its tendency kernel addresses a field by 32-bit byte offsets
+    const Dims hd = make_dims(g.nx, g.ny, g.nz, true, halo_width(m.advection));
+    const long esz = m.precision == OC_FP64 ? 8 : 4;
+    if ((long)hd.px * hd.py * hd.pz * esz >= (1L << 32)) {
+      set_error("the hydrostatic model needs fields of fewer than 2^32 bytes with halos");
+      return OC_ERR_UNSUPPORTED;
+    }
+  }
   if (m.implicit_z && (m.kind != OC_NONHYDROSTATIC || g.topology_z != OC_BOUNDED)) {
     set_error("implicit vertical diffusion needs the nonhydrostatic model with walls in z");
     return OC_ERR_UNSUPPORTED;
@@ -1172,14 +1181,6 @@ int oc_model_create(const oc_grid* g, const oc_model_desc* md, void* workspace,
   if (rc) return rc;
   rc = validate_pair(g->d, *md);
   if (rc) return rc;
-  if (md->kind == OC_HYDROSTATIC) {
-    const Dims hd = make_dims(g->d.nx, g->d.ny, g->d.nz, true, halo_width(md->advection));
-    const long esz = md->precision == OC_FP64 ? 8 : 4;
-    if ((long)hd.px * hd.py * hd.pz * esz >= (1L << 32)) {
-      set_error("the hydrostatic model needs fields of fewer than 2^32 bytes with halos");
-      return OC_ERR_UNSUPPORTED;
-    }
-  }
   if (((uintptr_t)workspace) % 256) { set_error("workspace must be 256-byte aligned"); return OC_ERR_ARG; }
   const Layout L = make_layout(g->d, *md);
   if (workspace_bytes < L.total) {

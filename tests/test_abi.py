@@ -91,6 +91,26 @@ def test_hydrostatic_pairing_is_validated():
     assert lib.oc_grid_create(ctypes.byref(bad), ctypes.byref(g)) == -1
 
 
+def test_hydrostatic_field_size_limit():
+    """The hydrostatic kernels address a field by 32-bit byte offsets: a
+    4096 x 2048 x 64 sector (4102 x 2054 x 70 points with halos) fits in
+    FP32 (2.4 GB per field) and is refused in FP64 (4.7 GB)."""
+    lib = oc.load_library()
+    g = ctypes.c_void_p()
+    gd = oc.GridDesc(4096, 2048, 64, oc.OC_BOUNDED, 0, 360, -70, 140, -3000, 3000, oc.OC_LATLON,
+                     6.371e6)
+    assert lib.oc_grid_create(ctypes.byref(gd), ctypes.byref(g)) == 0
+    md = oc.ModelDesc()
+    md.kind, md.precision, md.advection, md.weno_eps, md.weno_q = oc.OC_HYDROSTATIC, 1, 1, 1e-15, 2
+    md.ntracers, md.buoyancy, md.depth = 2, 1, 3000.0
+    nbytes = ctypes.c_uint64()
+    assert lib.oc_model_workspace_size(g, ctypes.byref(md), ctypes.byref(nbytes)) == 0
+    md.precision = oc.OC_FP64
+    assert lib.oc_model_workspace_size(g, ctypes.byref(md), ctypes.byref(nbytes)) == -5
+    assert "2^32" in lib.oc_last_error().decode()
+    assert lib.oc_grid_destroy(g) == 0
+
+
 def test_ensemble_and_hydrostatic_step_argument_checks():
     lib = oc.load_library()
     nbytes = ctypes.c_uint64()
