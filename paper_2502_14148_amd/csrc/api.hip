@@ -44,7 +44,7 @@ namespace {
 struct Layout {
   uint64_t state[2][MAXF], G[MAXF];
   uint64_t spec, p, twx, twy, twz, dctz, lamx, lamy, lamz, staging, diag;
-  uint64_t baro[13], metric, hzeta, hpx, hpy, hmet;
+  uint64_t baro[15], metric, hzeta, hpx, hpy, hmet;
   uint64_t gc[MAXF];
   uint64_t les_nu, les_kap[OC_MAX_TRACERS], les_d2;
   uint64_t mask, ibits, cg_x, cg_r, cg_q, cg_aq, cg_part, cg_scal;
@@ -82,10 +82,10 @@ Layout make_layout(const oc_grid_desc& g, const oc_model_desc& m) {
     L.lamy = off; off += align256((uint64_t)g.ny * 8);
     L.lamz = off; off += align256((uint64_t)g.nz * 8);
   } else {
-    // eta[2], U[2], V[2], GU, GV, etabar, Ubar, Vbar, tau_x, tau_y
-    // (V-like: ny + 1 rows)
+    // eta[2], U[2], V[2], GU, GV, etabar, Ubar, Vbar, tau_x, tau_y, and the
+    // upper levels' partial column sums of GU, GV (V-like: ny + 1 rows)
     const uint64_t a2 = align256((uint64_t)(g.ny + 1) * g.nx * 8);
-    for (int q = 0; q < 13; ++q) { L.baro[q] = off; off += a2; }
+    for (int q = 0; q < 15; ++q) { L.baro[q] = off; off += a2; }
     L.metric = off; off += align256((uint64_t)(5 * (g.ny + 1)) * 8);
     L.hzeta = off; off += fb;
     L.hpx = off; off += fb;
@@ -1021,6 +1021,8 @@ HydroBufs<T> hydro_bufs(oc_model* m, int in, int out) {
   a.tauy = m->tauy;
   a.gub = m->gubt;
   a.gvb = m->gvbt;
+  a.gub1 = m->gub1;
+  a.gvb1 = m->gvb1;
   return a;
 }
 
@@ -1261,6 +1263,8 @@ int oc_model_create(const oc_grid* g, const oc_model_desc* md, void* workspace,
   m->hmet = (double*)(m->ws + L.hmet);
   m->taux = (double*)(m->ws + L.baro[11]);
   m->tauy = (double*)(m->ws + L.baro[12]);
+  m->gub1 = (double*)(m->ws + L.baro[13]);
+  m->gvb1 = (double*)(m->ws + L.baro[14]);
   m->hfirst = 1;
   m->hstale = 1;
   m->net = nullptr;

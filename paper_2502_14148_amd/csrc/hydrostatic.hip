@@ -260,9 +260,11 @@ __global__ void __launch_bounds__(TTX * TTY, hydro_tend_waves<T>())
   __shared__ T FX[2][F_X];
   __shared__ T FY[2][F_Y];
   const Dims d = a.d;
-  const int nbx = (d.nx + TTX - 1) / TTX;
-  const int tile = hydro_tile_index();
+  const int nbx = (d.nx + TTX - 1) / TTX, nby = (d.ny + TTY - 1) / TTY;
+  const int item = hydro_tile_index();            // chunk-major over (chunk, tile)
+  const int tile = item % (nbx * nby), chunk = item / (nbx * nby);
   const int i0 = (tile % nbx) * TTX, j0 = (tile / nbx) * TTY;
+  const int kb = chunk * st.kc, ke = min(kb + st.kc, d.nz);
   const int tx = (int)threadIdx.x, ty = (int)threadIdx.y, tid = ty * TTX + tx;
   const int i = i0 + tx, j = j0 + ty;
   const bool active = i < d.nx && j < d.ny;
@@ -286,19 +288,40 @@ __global__ void __launch_bounds__(TTX * TTY, hydro_tend_waves<T>())
   // own column: field pointers advanced by whole levels (uniform) plus a
   // 32-bit per-thread byte offset
   const unsigned cb = (unsigned)pidx(d, min(i, d.nx - 1), min(j, d.ny - 1), 0) * (unsigned)sizeof(T);
-  // register windows along z: q[o] = q_{k-2+o}
+  // register windows along z: q[o] = q_{k-2+o}, from level kb - 3 (one
+  // below the window, for the bottom face of an upper chunk)
   T uw[6], vw[6], tw[6], sw[6];
+  T u3, v3, t3, s3;
 #pragma unroll
-  for (int o = 0; o < 6; ++o) {
-    const long kz = (long)(o - 2) * sz;
-    uw[o] = at(uniform_ptr(a.u + kz), cb);
-    vw[o] = at(uniform_ptr(a.v + kz), cb);
-    tw[o] = at(uniform_ptr(a.t + kz), cb);
-    sw[o] = at(uniform_ptr(a.s + kz), cb);
+  for (int o = -1; o < 6; ++o) {
+    const long kz = (long)(kb + o - 2) * sz;
+    const T uu = at(uniform_ptr(a.u + kz), cb), vv = at(uniform_ptr(a.v + kz), cb);
+    const T tt = at(uniform_ptr(a.t + kz), cb), ss = at(uniform_ptr(a.s + kz), cb);
+    if (o < 0) {
+      u3 = uu; v3 = vv; t3 = tt; s3 = ss;
+    } else {
+      uw[o] = uu; vw[o] = vv; tw[o] = tt; sw[o] = ss;
+    }
   }
-  // quantities on face k carried up from the level below (floor: zero)
+  // quantities on face k carried up from the level below (floor: zero; the
+  // bottom face of an upper chunk is computed here as the chunk below
+  // computes its top face)
   T Fu = T(0), Fv = T(0), Ft = T(0), Fs = T(0), Nu = T(0), Nv = T(0);
   T Wu = T(0), Wv = T(0);
+  if (kb > 0 && active) {
+    const long kf = (long)kb * sz;   // face kb
+    const T w_c = at(uniform_ptr(a.w + kf), cb);
+    Wu = T(0.5) * (at(uniform_ptr(a.w + kf - 1), cb) + w_c);
+    Wv = vpt ? T(0.5) * (at(uniform_ptr(a.w + kf - d.sy), cb) + w_c) : T(0);
+    Fu = Wu * rec<T, SCHEME>(u3, uw[0], uw[1], uw[2], uw[3], uw[4], Wu, eps);
+    Fv = Wv * rec<T, SCHEME>(v3, vw[0], vw[1], vw[2], vw[3], vw[4], Wv, eps);
+    Ft = (w_c * rec<T, SCHEME>(t3, tw[0], tw[1], tw[2], tw[3], tw[4], w_c, eps) -
+          kappa * (tw[2] - tw[1]) * rdz) * Az;
+    Fs = (w_c * rec<T, SCHEME>(s3, sw[0], sw[1], sw[2], sw[3], sw[4], w_c, eps) -
+          kappa * (sw[2] - sw[1]) * rdz) * Az;
+    Nu = nu * (uw[2] - uw[1]) * rdz;
+    Nv = nu * (vw[2] - vw[1]) * rdz;
+  }
   double gu = 0.0, gv = 0.0;
   const long c2 = (long)min(j, d.ny - 1) * d.nx + min(i, d.nx - 1);
 
@@ -310,14 +333,14 @@ __global__ void __launch_bounds__(TTX * TTY, hydro_tend_waves<T>())
   const int lw = (ty + 1) * P_WX + tx + 1;
 
   Stage<T> stg;
-  stage_fetch(stg, a, i0, j0, 0, tid);
-  for (int k = 0; k < d.nz; ++k) {
+  stage_fetch(stg, a, i0, j0, kb, tid);
+  for (int k = kb; k < ke; ++k) {
     T* S = P[k & 1];
     const long kz = (long)k * sz;
     stage_store(S, stg, tid);
     __syncthreads();
     // the next level's planes are fetched while this level computes
-    if (k + 1 < d.nz) stage_fetch(stg, a, i0, j0, k + 1, tid);
+    if (k + 1 < ke) stage_fetch(stg, a, i0, j0, k + 1, tid);
 
     // ---- tracer fluxes through the x faces (west of each column) and the
     // y faces (south of each row) of the tile; then the east and north edge
@@ -489,9 +512,27 @@ __global__ void __launch_bounds__(TTX * TTY, hydro_tend_waves<T>())
     }
   }
   if (active) {
-    a.gub[c2] = gu * m.dz;
-    a.gvb[c2] = vpt ? gv * m.dz : 0.0;
+    // partial column sums of this chunk (the lower chunk's into gub, gvb)
+    (chunk == 0 ? a.gub : a.gub1)[c2] = gu;
+    (chunk == 0 ? a.gvb : a.gvb1)[c2] = vpt ? gv : 0.0;
   }
+}
+
+// Slow forcing of the barotropic mode from the chunks' partial column sums
+// (added in chunk order), times dz.
+__global__ void hydro_gsum_kernel(double* __restrict__ gub, double* __restrict__ gvb,
+                                  const double* __restrict__ gub1,
+                                  const double* __restrict__ gvb1, long n, int nchunks,
+                                  double dz) {
+  const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  double su = gub[c], sv = gvb[c];
+  if (nchunks > 1) {
+    su += gub1[c];
+    sv += gvb1[c];
+  }
+  gub[c] = su * dz;
+  gvb[c] = sv * dz;
 }
 
 // Halo images of the prognostic fields: x periodic; y walls with even
@@ -545,18 +586,28 @@ hipError_t launch_hydro_diag(const HydroBufs<T>& a, hipStream_t s) {
 template <class T>
 hipError_t launch_hydro_tendency(const HydroBufs<T>& a, const HydroStep<T>& st, int scheme,
                                  hipStream_t s) {
-  const dim3 grid((unsigned)(((a.d.nx + TTX - 1) / TTX) * ((a.d.ny + TTY - 1) / TTY)));
+  // two chunks of levels (when there are at least 16): the grid then holds
+  // twice the workgroups of one march, so its last round of resident
+  // workgroups is fuller
+  HydroStep<T> sc = st;
+  const int nchunks = a.d.nz >= 16 ? 2 : 1;
+  sc.kc = (a.d.nz + nchunks - 1) / nchunks;
+  const dim3 grid((unsigned)(((a.d.nx + TTX - 1) / TTX) * ((a.d.ny + TTY - 1) / TTY) * nchunks));
   const dim3 block(TTX, TTY);
   switch (scheme) {
     case tz::SCHEME_NONE:
-      hipLaunchKernelGGL((hydro_tend_kernel<T, tz::SCHEME_NONE>), grid, block, 0, s, a, st);
+      hipLaunchKernelGGL((hydro_tend_kernel<T, tz::SCHEME_NONE>), grid, block, 0, s, a, sc);
       break;
     case tz::SCHEME_LINEAR:
-      hipLaunchKernelGGL((hydro_tend_kernel<T, tz::SCHEME_LINEAR>), grid, block, 0, s, a, st);
+      hipLaunchKernelGGL((hydro_tend_kernel<T, tz::SCHEME_LINEAR>), grid, block, 0, s, a, sc);
       break;
     default:
-      hipLaunchKernelGGL((hydro_tend_kernel<T, tz::SCHEME_WENOZ>), grid, block, 0, s, a, st);
+      hipLaunchKernelGGL((hydro_tend_kernel<T, tz::SCHEME_WENOZ>), grid, block, 0, s, a, sc);
   }
+  const long n2 = (long)a.d.nx * a.d.ny;
+  hipLaunchKernelGGL(hydro_gsum_kernel, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, s,
+                     a.gub, a.gvb, (const double*)a.gub1, (const double*)a.gvb1, n2, nchunks,
+                     a.m.dz);
   return hipGetLastError();
 }
 

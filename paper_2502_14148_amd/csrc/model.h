@@ -70,6 +70,8 @@ struct oc_model {
   double* vbt[2];
   double* gubt;
   double* gvbt;
+  double* gub1;   // partial column sums of the upper levels (two-chunk tendency)
+  double* gvb1;
   double* etab;
   double* ubar;
   double* vbar;

@@ -208,12 +208,14 @@ struct HydroBufs {
   T* w; T* zeta; T* px; T* py;                      // diagnostic fields
   const double* taux; const double* tauy;           // kinematic surface stress
   double* gub; double* gvb;                         // slow forcing of U, V
+  double* gub1; double* gvb1;                       // partial sums of the upper levels
 };
 
 template <class T>
 struct HydroStep {
   T dt, a1, a0;             // X~ = X + dt (a1 G^n - a0 G^{n-1})
   int first;                // 1: G^{n-1} is not read
+  int kc;                   // levels per chunk (set by the launcher)
 };
 
 template <class T>

@@ -96,10 +96,11 @@ def test_step_parity_other_schemes(gpu_lib, scheme):
     _check_run(gpu_lib, _phys(nx=64, ny=16, nz=8, advection=scheme), "fp64", 2, seed=2)
 
 
-@pytest.mark.parametrize("n", [(40, 8, 9), (56, 24, 8), (24, 16, 8)])
+@pytest.mark.parametrize("n", [(40, 8, 9), (56, 24, 8), (24, 16, 8), (40, 16, 17), (64, 8, 16)])
 def test_ragged_small_grid(gpu_lib, n):
     # column tiles of 32 x 8 (latitude-longitude grids have nx, ny multiples
-    # of 8): a ragged last tile in x, or one partial tile
+    # of 8): a ragged last tile in x, or one partial tile; with nz >= 16 the
+    # levels are marched in two chunks (9 + 8 and 8 + 8 levels here)
     _check_run(gpu_lib, _phys(nx=n[0], ny=n[1], nz=n[2]), "fp64", 2, seed=3)
 
 
