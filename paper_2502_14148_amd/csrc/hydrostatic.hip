@@ -66,46 +66,37 @@ __global__ void __launch_bounds__(HTX * HTY) hydro_diag_kernel(HydroBufs<T> a) {
   const long sy = d.sy, sz = d.sz;
   const long c0 = pidx(d, i, j, 0);
 
-  // vertical vorticity at corner (x face i, y face j)
+  // vertical vorticity at corner (x face i, y face j) and, on the columns
+  // i in [-1, nx), j in [0, ny), w on the faces from the floor up: one pass
+  // over the levels, so that u and v are fetched once for both
   {
     const T dxj = (T)m.dxc[j + d.h], dxjm = (T)m.dxc[j - 1 + d.h];
     const T rza = T(1) / (T)m.areaz[j + d.h];
+    const bool wcol = i >= -1 && i < d.nx && j >= 0 && j < d.ny;
+    const int jw = wcol ? j : 0;   // metric row of w (any valid row elsewhere)
+    const T dxf0 = (T)m.dxf[jw + d.h], dxf1 = (T)m.dxf[jw + 1 + d.h];
+    const T rar = T(1) / (T)m.areac[jw + d.h];
+    double wacc = 0.0;
+    if (wcol) a.w[c0] = T(0);
     for (int k0 = 0; k0 < d.nz; k0 += DKB) {
-      T v0[DKB], v1[DKB], u0[DKB], u1[DKB];
+      T v0[DKB], v1[DKB], u0[DKB], u1[DKB], ue[DKB], vn[DKB];
 #pragma unroll
       for (int q = 0; q < DKB; ++q) {
         const long c = c0 + (long)min(k0 + q, d.nz - 1) * sz;
         v0[q] = a.v[c]; v1[q] = a.v[c - 1]; u0[q] = a.u[c]; u1[q] = a.u[c - sy];
+        ue[q] = wcol ? a.u[c + 1] : T(0);
+        vn[q] = wcol ? a.v[c + sy] : T(0);
       }
 #pragma unroll
       for (int q = 0; q < DKB; ++q) {
         if (k0 + q < d.nz) {
           const T circ = dy * (v0[q] - v1[q]) - (dxj * u0[q] - dxjm * u1[q]);
           a.zeta[c0 + (long)(k0 + q) * sz] = circ * rza;
-        }
-      }
-    }
-  }
-
-  // w on the faces of columns i in [-1, nx), j in [0, ny)
-  if (i >= -1 && i < d.nx && j >= 0 && j < d.ny) {
-    const T dxf0 = (T)m.dxf[j + d.h], dxf1 = (T)m.dxf[j + 1 + d.h];
-    const T rar = T(1) / (T)m.areac[j + d.h];
-    double wacc = 0.0;
-    a.w[c0] = T(0);
-    for (int k0 = 0; k0 < d.nz; k0 += DKB) {
-      T ue[DKB], uc[DKB], vn[DKB], vc[DKB];
-#pragma unroll
-      for (int q = 0; q < DKB; ++q) {
-        const long c = c0 + (long)min(k0 + q, d.nz - 1) * sz;
-        ue[q] = a.u[c + 1]; uc[q] = a.u[c]; vn[q] = a.v[c + sy]; vc[q] = a.v[c];
-      }
-#pragma unroll
-      for (int q = 0; q < DKB; ++q) {
-        if (k0 + q < d.nz) {
-          const T div = (dy * (ue[q] - uc[q]) + (dxf1 * vn[q] - dxf0 * vc[q])) * rar;
-          wacc -= dz * (double)div;
-          a.w[c0 + (long)(k0 + q + 1) * sz] = (T)wacc;
+          if (wcol) {
+            const T div = (dy * (ue[q] - u0[q]) + (dxf1 * vn[q] - dxf0 * v0[q])) * rar;
+            wacc -= dz * (double)div;
+            a.w[c0 + (long)(k0 + q + 1) * sz] = (T)wacc;
+          }
         }
       }
     }
