@@ -528,22 +528,16 @@ __global__ void hydro_gsum_kernel(double* __restrict__ gub, double* __restrict__
 
 // Halo images of the prognostic fields: x periodic; y walls with even
 // mirrors for u, T, S and an odd mirror about the wall faces for v (whose
-// wall faces are set to zero); z walls with even mirrors.  One thread per
-// padded point; interior points return at once.
+// wall faces are set to zero); z walls with even mirrors.
 template <class T>
-__global__ void hydro_halo_kernel(Dims d, T* u, T* v, T* t, T* s) {
-  const long n = (long)d.px * d.py * d.pz;
-  const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n) return;
-  const int pi = (int)(p % d.px);
-  const int pj = (int)((p / d.px) % d.py);
-  const int pk = (int)(p / ((long)d.px * d.py));
-  const int i = pi - d.h, j = pj - d.h, k = pk - d.h;
+__device__ inline void hydro_halo_point(const Dims& d, T* u, T* v, T* t, T* s, int i, int j,
+                                        int k) {
   const bool xin = i >= 0 && i < d.nx, yin = j >= 0 && j < d.ny, zin = k >= 0 && k < d.nz;
   const bool vwall = (j == 0 || j == d.ny);
   const bool c_interior = xin && yin && zin;
   const bool v_interior = xin && zin && j > 0 && j < d.ny;
   if (c_interior && v_interior) return;
+  const long p = pidx(d, i, j, k);
   const int si = (i < 0) ? i + d.nx : (i >= d.nx ? i - d.nx : i);
   const int sk = (k < 0) ? -1 - k : (k >= d.nz ? 2 * d.nz - 1 - k : k);
   if (!c_interior) {
@@ -561,6 +555,24 @@ __global__ void hydro_halo_kernel(Dims d, T* u, T* v, T* t, T* s) {
       const T sg = (j < 0 || j > d.ny) ? T(-1) : T(1);
       v[p] = sg * v[pidx(d, si, sj, sk)];
     }
+  }
+}
+
+// One workgroup per padded row (j, k): rows outside the interior, and the
+// rows of v's wall faces (j = 0, ny), are filled across their whole length;
+// the other rows have only their x halos.
+template <class T>
+__global__ void __launch_bounds__(64) hydro_halo_kernel(Dims d, T* u, T* v, T* t, T* s) {
+  const int j = (int)(blockIdx.x % (unsigned)d.py) - d.h;
+  const int k = (int)(blockIdx.x / (unsigned)d.py) - d.h;
+  const bool full = j <= 0 || j >= d.ny || k < 0 || k >= d.nz;
+  if (full) {
+    for (int i = (int)threadIdx.x - d.h; i < d.nx + d.h; i += 64)
+      hydro_halo_point(d, u, v, t, s, i, j, k);
+  } else if ((int)threadIdx.x < 2 * d.h) {
+    const int x = (int)threadIdx.x;
+    const int i = x < d.h ? x - d.h : d.nx + (x - d.h);
+    hydro_halo_point(d, u, v, t, s, i, j, k);
   }
 }
 
@@ -604,9 +616,8 @@ hipError_t launch_hydro_tendency(const HydroBufs<T>& a, const HydroStep<T>& st, 
 
 template <class T>
 hipError_t launch_hydro_halo(const Dims& d, T* u, T* v, T* t, T* sf, hipStream_t s) {
-  const long n = (long)d.px * d.py * d.pz;
-  hipLaunchKernelGGL(hydro_halo_kernel<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, d, u,
-                     v, t, sf);
+  const unsigned rows = (unsigned)((long)d.py * d.pz);
+  hipLaunchKernelGGL(hydro_halo_kernel<T>, dim3(rows), dim3(64), 0, s, d, u, v, t, sf);
   return hipGetLastError();
 }
 
