@@ -16,9 +16,9 @@ namespace oc {
 namespace {
 
 // Own tile of a workgroup (one cell per thread) and the substeps per launch:
-// on the 1440 x 560 sector 32 x 32 with 4 took 0.89 ms per 59 substeps
-// (plus correction and restart), 32 x 16 0.95, 32 x 8 1.10; halos of 2, 3,
-// 5, 6, 8 on 32 x 8 or 32 x 16 tiles were slower or no faster.
+// on the 1440 x 560 sector, 32 x 32 tiles took 0.82 ms per 59 substeps (plus
+// correction and restart) with 6 substeps per launch, 0.83 with 5, 0.86
+// with 4; 32 x 16 tiles 0.95 and 32 x 8 tiles 1.10 with 4.
 constexpr int BTX = 32, BTY = 32;
 
 // Up to BHS substeps in one launch (temporal blocking).  A workgroup owns a
@@ -30,7 +30,7 @@ constexpr int BTX = 32, BTY = 32;
 // domain hold zeros and the wall faces V(0), V(ny) stay zero; x wraps
 // periodically.  The running averages of the own cells take the substeps'
 // terms one at a time, in substep order.
-constexpr int BHS = 4;
+constexpr int BHS = 6;
 constexpr int BEX = BTX + 2 * BHS, BEY = BTY + 2 * BHS;   // widened tile
 constexpr int BPX = BEX + 1, BPY = BEY + 1;               // + U column, V row
 struct BaroWeights {
