@@ -98,3 +98,94 @@ def test_closure_tendency_conserves_columns():
     for k in ("u", "v", "T"):
         assert np.max(np.abs(G[k].sum(axis=0))) < 1e-10
     assert np.all(G["w"][0] == 0) and np.all(G["w"][-1] == 0)
+
+
+def _box_cov(a, b, r):
+    """Brute-force <a b> - <a><b> over each r^3 box with plain loops."""
+    nz, ny, nx = a.shape
+    out = np.zeros((nz // r, ny // r, nx // r))
+    for K in range(nz // r):
+        for J in range(ny // r):
+            for I in range(nx // r):
+                sa = sb = sab = 0.0
+                for k in range(K * r, K * r + r):
+                    for j in range(J * r, J * r + r):
+                        for i in range(I * r, I * r + r):
+                            sa += a[k, j, i]
+                            sb += b[k, j, i]
+                            sab += a[k, j, i] * b[k, j, i]
+                n = r ** 3
+                out[K, J, I] = sab / n - (sa / n) * (sb / n)
+    return out
+
+
+def test_subgrid_fluxes_centre_values_closed_form():
+    """Face i lies on the left of cell i, so the centre value of a face field
+    f(i) = i^2 is the mean of faces i and i + 1: i^2 + i + 1/2 (a mean with
+    the left neighbour, i^2 - i + 1/2, changes every covariance below by
+    2 Var(i)).  Same along y for v and along z for w (faces k and k + 1 of a
+    walled column).  Coarse boxes away from the periodic seam are compared
+    with the fluxes of those closed-form centre values."""
+    n, r = 8, 4
+    idx = np.arange(n, dtype=np.float64)
+    one = np.ones((n, n, n))
+    ii = one * idx[None, None, :]
+    jj = one * idx[None, :, None]
+    kk = one * idx[:, None, None]
+    u = ii ** 2                                   # x faces
+    v = jj ** 2                                   # y faces
+    kf = np.arange(n + 1, dtype=np.float64)
+    w = (np.ones((n + 1, n, n)) * kf[:, None, None]) ** 2 + ii[:1]   # z faces, varies in x too
+    b = kk + 2.0 * jj - ii
+    F = cl.subgrid_fluxes(u, v, w, b, r)
+    uc = ii ** 2 + ii + 0.5
+    vc = jj ** 2 + jj + 0.5
+    wc = kk ** 2 + kk + 0.5 + ii
+    want = [_box_cov(q, wc, r) for q in (uc, vc, wc, b)]
+    # boxes whose x and y ranges do not reach the last (seam) column/row
+    sel = (slice(None), slice(0, n // r - 1), slice(0, n // r - 1))
+    for q in range(4):
+        assert np.max(np.abs(F[q][sel] - want[q][sel])) < 1e-9, q
+    # the left-neighbour mean would differ by 2 Var(i) = (r^2 - 1) / 6 in tau_uw
+    # wherever wc varies with i inside the box as i itself does
+    assert abs(_box_cov(ii ** 2 - ii + 0.5, wc, r)[0, 0, 0] - want[0][0, 0, 0]) > 0.1
+
+
+def test_closure_tendency_of_a_single_flux_impulse():
+    """One nonzero flux value d at centre (k0, j0, i0): tau_uw reaches the two
+    x faces of that cell (i0, i0 + 1) at a quarter of d on the z faces k0 and
+    k0 + 1 (half from the x average, half from the z average), so G_u is
+    -d / (4 dz) at level k0 - 1, 0 at k0 and +d / (4 dz) at k0 + 1 on those
+    two faces and zero elsewhere; v likewise on y faces j0, j0 + 1; J_bw
+    reaches only the cell's own column (the z average alone), giving
+    -+d / (2 dz g alpha) at k0 -+ 1; tau_ww differences to the w faces k0
+    (-d / dz) and k0 + 1 (+d / dz)."""
+    ph = _phys(8)
+    dz = ph.spacing[2]
+    k0, j0, i0, d = 3, 2, 5, 1.75
+    for comp in range(4):
+        F = np.zeros((4, ph.nz, ph.ny, ph.nx))
+        F[comp, k0, j0, i0] = d
+        G = cl.closure_tendency(F, ph)
+        if comp in (0, 1):
+            name = "u" if comp == 0 else "v"
+            want = np.zeros((ph.nz, ph.ny, ph.nx))
+            for e in (0, 1):
+                jj, ii = (j0, i0 + e) if comp == 0 else (j0 + e, i0)
+                want[k0 - 1, jj, ii] = -d / (4 * dz)
+                want[k0 + 1, jj, ii] = d / (4 * dz)
+        elif comp == 3:
+            name = "T"
+            c = d / (ph.g * ph.alpha)
+            want = np.zeros((ph.nz, ph.ny, ph.nx))
+            want[k0 - 1, j0, i0] = -c / (2 * dz)
+            want[k0 + 1, j0, i0] = c / (2 * dz)
+        else:
+            name = "w"
+            want = np.zeros((ph.nz + 1, ph.ny, ph.nx))
+            want[k0, j0, i0] = -d / dz
+            want[k0 + 1, j0, i0] = d / dz
+        assert np.max(np.abs(G[name] - want)) < 1e-15, (comp, name)
+        for other in ("u", "v", "w", "T"):
+            if other != name:
+                assert not np.any(G[other]), (comp, other)
