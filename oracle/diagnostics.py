@@ -37,3 +37,26 @@ def cfl(state, dt, ph):
     return dt * max(float(np.max(np.abs(interior(state["u"], ph, "u")))) / dx,
                     float(np.max(np.abs(interior(state["v"], ph, "v")))) / dy,
                     float(np.max(np.abs(interior(state["w"], ph, "w")))) / float(np.min(dzc)))
+
+
+def momentum_integrals(state, ph):
+    """Volume integrals of u, v and w over their own control volumes: u and v
+    faces carry the volume of the cell they sit beside in z (dx dy dzc[k]), a
+    w face the volume dx dy dzf[k] between the centres either side of it
+    (finite-volume appendix: the discrete integral is the sum of value times
+    control volume)."""
+    dx, dy, _ = ph.spacing
+    dzc, dzf = z_spacings(ph)
+    u = interior(state["u"], ph, "u")
+    v = interior(state["v"], ph, "v")
+    w = interior(state["w"], ph, "w")
+    nwf = w.shape[0]
+    return (float(np.sum(u * dzc[:, None, None])) * dx * dy,
+            float(np.sum(v * dzc[:, None, None])) * dx * dy,
+            float(np.sum(w * dzf[:nwf, None, None])) * dx * dy)
+
+
+def cfl_rate(state, ph):
+    """The advective CFL number per unit time step, max(max|u|/dx,
+    max|v|/dy, max|w|/dz_min): cfl(state, dt, ph) = dt * cfl_rate(state, ph)."""
+    return cfl(state, 1.0, ph)

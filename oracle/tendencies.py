@@ -239,15 +239,31 @@ def w_tendency(s, ph):
     return G
 
 
-def tendencies(s, ph):
+def tendencies(s, ph, workers=1):
     """All tendencies of the prognostic fields of a padded state dict, with
-    the eddy-viscosity LES closure's contribution when one is configured."""
-    G = {"u": u_tendency(s, ph), "v": v_tendency(s, ph), "w": w_tendency(s, ph)}
+    the eddy-viscosity LES closure's contribution when one is configured.
+
+    workers > 1 evaluates the fields' tendencies (independent computations)
+    on that many threads; NumPy releases the interpreter lock inside its
+    array operations, so large grids run in parallel.  Every value is
+    computed by the same operations either way."""
+    jobs = {"u": lambda: u_tendency(s, ph), "v": lambda: v_tendency(s, ph),
+            "w": lambda: w_tendency(s, ph)}
+    for name in ph.tracers:
+        jobs[name] = (lambda n: lambda: tracer_tendency(s[n], s, ph, ph.top_flux.get(n, 0.0)))(name)
+    if workers > 1:
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(max_workers=workers) as ex:
+            fut = {n: ex.submit(f) for n, f in jobs.items()}
+            T = {n: f.result() for n, f in fut.items()}
+    else:
+        T = {n: f() for n, f in jobs.items()}
+    G = {"u": T["u"], "v": T["v"], "w": T["w"]}
     if immersed.has_immersed(ph):
         # velocities on closed faces do not change
         G["u"], G["v"], G["w"] = immersed.mask_velocities(G["u"], G["v"], G["w"], ph)
     for name in ph.tracers:
-        G[name] = tracer_tendency(s[name], s, ph, ph.top_flux.get(name, 0.0))
+        G[name] = T[name]
     kind = getattr(ph, "les", "none")
     if kind != "none":
         from .les import les_tendencies

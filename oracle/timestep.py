@@ -36,9 +36,10 @@ def state_interior(state, ph):
     return {n: interior(state[n], ph, n) for n in fields_of(ph)}
 
 
-def rk3_substage(state, G_prev, m, dt, ph, project_velocity=True):
-    """One substage (m = 0, 1, 2).  Returns (new padded state, G^m, p)."""
-    G = tendencies(state, ph)
+def rk3_substage(state, G_prev, m, dt, ph, project_velocity=True, workers=1):
+    """One substage (m = 0, 1, 2).  Returns (new padded state, G^m, p).
+    workers: threads for the tendencies (see tendencies.tendencies)."""
+    G = tendencies(state, ph, workers)
     X = state_interior(state, ph)
     new = {}
     for n in fields_of(ph):
@@ -57,12 +58,12 @@ def rk3_substage(state, G_prev, m, dt, ph, project_velocity=True):
     return make_state(new, ph), G, p
 
 
-def rk3_step(state, dt, ph, project_velocity=True):
+def rk3_step(state, dt, ph, project_velocity=True, workers=1):
     """One full RK3 time step; returns (new state, last pressure)."""
     G = None
     p = None
     for m in range(3):
-        state, G, p = rk3_substage(state, G, m, dt, ph, project_velocity)
+        state, G, p = rk3_substage(state, G, m, dt, ph, project_velocity, workers)
     return state, p
 
 
