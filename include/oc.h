@@ -80,7 +80,7 @@ enum { OC_U = 0, OC_V = 1, OC_W = 2, OC_TRACER0 = 3 };
 enum { OC_ETA = 16, OC_UBT = 17, OC_VBT = 18, OC_GUBT = 19, OC_GVBT = 20, OC_TAUX = 21,
        OC_TAUY = 22 };
 #define OC_MAX_TRACERS 4
-#define OC_NDIAG 8
+#define OC_NDIAG 12
 
 /* Grid: RectilinearGrid or LatitudeLongitudeGrid of the library subsection.
  *   OC_RECTILINEAR: domain [x0, x0+lx) x [y0, y0+ly) x [z0, z0+lz) in meters;
@@ -345,11 +345,10 @@ int oc_hydrostatic_step(oc_model* m, double dt, int32_t N, int32_t M, const doub
  * precision, nx and ny multiples of 8.
  * Flags: OC_ENS_TUNE times the candidate launch configurations (column tile
  * 32x8, 16x8 or 8x8; one workgroup per tile or a persistent grid draining an
- * atomic work queue; k-chunk length) at creation and keeps the fastest; with
- * the environment variable OC_TUNE_CACHE naming a file, choices are read
- * from and appended to it (JSON lines keyed by GPU architecture, precision
- * and member sizes).  OC_ENS_GRAPH captures one RK3 step per buffer parity
- * as a HIP graph on the first call (again when dt changes) and replays it.
+ * atomic work queue; k-chunk length) at creation and keeps the fastest, as
+ * oc_autotune with no cache does.  OC_ENS_GRAPH captures one RK3 step per
+ * buffer parity as a HIP graph on the first call (again when dt or the
+ * launch configuration changes) and replays it.
  * Workspace: caller-owned device memory of oc_ensemble_workspace_size bytes
  * (member tables, work list, Poisson pointer tables). */
 typedef struct oc_ensemble oc_ensemble;
@@ -366,9 +365,31 @@ int oc_ensemble_create(oc_model* const* members, int32_t count, void* workspace,
 int oc_ensemble_step(oc_ensemble* e, double dt, int32_t nsteps, void* stream);
 /* The launch configuration in use: out[0] tile (0: 32x8, 1: 16x8, 2: 8x8),
  * out[1] persistent grid (0/1), out[2] workgroups of the persistent grid,
- * out[3] k-chunk divisor, out[4] 0 default / 1 timed / 2 from the cache,
- * out[5] work items per launch; *ms (optional) the timed launch. */
+ * out[3] k-chunk divisor, out[4] 0 default / 1 timed / 2 from the cache /
+ * 3 set by oc_ensemble_set_tuning, out[5] work items per launch; *ms
+ * (optional) the timed launch. */
 int oc_ensemble_tuning(const oc_ensemble* e, int32_t* out, double* ms);
+/* The project's autotuner (the batching form of the build: tile shapes of
+ * the fused tendency launch picked by measurement).  Synchronous: waits for
+ * the device, then times every candidate (column tile 32x8, 16x8, 8x8; flat
+ * or persistent grid; k-chunk divisor 256, 1024, 4096) on substage-1
+ * launches that read the members' current states and write only buffers
+ * that the next step overwrites, and keeps the fastest.  cache_path (host
+ * string, may be NULL): a JSON-lines file, one object per choice,
+ * {"key": arch|precision|sizes, "tile": t, "persistent": p, "kc_div": k,
+ * "ms": x}; a line with this ensemble's key is used instead of timing (the
+ * last such line wins), and a timed choice is appended.  An unreadable or
+ * unwritable file is treated as absent.  Captured graphs are dropped and
+ * recaptured on the next step.  Errors: OC_ERR_ARG (NULL ensemble),
+ * OC_ERR_DEVICE. */
+int oc_autotune(oc_ensemble* e, const char* cache_path);
+/* Force a launch configuration (host array of 3): tuning[0] tile (0: 32x8,
+ * 1: 16x8, 2: 8x8), tuning[1] persistent grid (0/1), tuning[2] k-chunk
+ * divisor (>= 1: a member's k chunk is nz * tiles / divisor levels, clamped
+ * to 4..64).  Synchronous like oc_autotune; results do not depend on the
+ * configuration.  Errors: OC_ERR_ARG (values outside these ranges, or a tile
+ * that does not divide some member's nx and ny). */
+int oc_ensemble_set_tuning(oc_ensemble* e, const int32_t* tuning);
 int oc_ensemble_destroy(oc_ensemble* e);
 
 /* ---- Learned subgrid closure (an MLP trained on coarse-grained fluxes) ----
@@ -448,11 +469,28 @@ int oc_closure_features(oc_model* m, const double* stats, float* x, void* stream
  * (different precision, domain or tracer storage). */
 int oc_coarse_grain(oc_model* fine, oc_model* coarse, float* fluxes, void* stream);
 
-/* FP64 diagnostics of the current state, synchronous; out (host) receives
- * OC_NDIAG doubles: [0] max|div u| * min(spacing), [1] max|u|, [2] max|v|,
- * [3] max|w|, [4..7] volume integral of tracers 0..3 (0 if absent).
- * Returns OC_ERR_NONFINITE if any state value is NaN/Inf. */
+/* FP64 diagnostics of the current state of a nonhydrostatic model, with
+ * every sum taken in one fixed order (deterministic), synchronous; out (host)
+ * receives OC_NDIAG doubles:
+ *   [0] max|div u| * min(spacing) (the discrete divergence of the
+ *       pressure-correction method, dimensionless once divided by max|u|),
+ *   [1] max|u|, [2] max|v|, [3] max|w|,
+ *   [4..7] volume integrals of tracers 0..3 (0 if absent): the sum of cell
+ *       value times cell volume, the finite-volume integral,
+ *   [8..10] volume integrals of u, v, w over their own control volumes
+ *       (u, v: the cell's volume; w: dx dy times the spacing of the centres
+ *       either side of the face),
+ *   [11] the advective CFL rate max(max|u|/dx, max|v|/dy, max|w|/dz_min) in
+ *       1/s; the CFL number of a step dt is dt times it.
+ * Errors: OC_ERR_NONFINITE if any state value is NaN or Inf (the values are
+ * still written), OC_ERR_UNSUPPORTED for a hydrostatic model. */
 int oc_diagnostics(oc_model* m, double* out, void* stream);
+
+/* Synchronise `stream` and report what the device has done since the last
+ * check: OC_ERR_DEVICE for a HIP error (message from the runtime), then, for
+ * a nonhydrostatic model, OC_ERR_NONFINITE if the current state holds a NaN
+ * or Inf (the NaN guard of oc_diagnostics).  OC_OK otherwise. */
+int oc_sync_check(oc_model* m, void* stream);
 
 #ifdef __cplusplus
 }

@@ -23,7 +23,7 @@ void set_error(const char* fmt, ...) {
 }
 
 static const int DIAG_BLOCKS = 1024;
-static const int DIAG_PARTS = 9;
+static const int DIAG_PARTS = 12;
 
 }  // namespace oc
 
@@ -268,6 +268,24 @@ int validate_pair(const oc_grid_desc& g, const oc_model_desc& m) {
     const long esz = m.precision == OC_FP64 ? 8 : 4;
     if ((long)hd.px * hd.py * hd.pz * esz >= (1L << 32)) {
       set_error("the hydrostatic model needs fields of fewer than 2^32 bytes with halos");
+      return OC_ERR_UNSUPPORTED;
+    }
+  }
+  if (m.kind == OC_NONHYDROSTATIC) {
+    // the tendency kernel addresses the state, tendency, closure and mask
+    // fields by 32-bit byte offsets from the lowest of them
+    const Layout L = make_layout(g, m);
+    const Dims nd = make_dims(g.nx, g.ny, g.nz, g.topology_z == OC_BOUNDED,
+                              halo_width(m.advection));
+    const uint64_t fb = (uint64_t)padded_elems(nd) * (m.precision == OC_FP64 ? 8 : 4);
+    const int nf = 3 + m.ntracers;
+    uint64_t hi = L.G[nf - 1] + fb;
+    const int ngc = m.closure ? 4 : (m.les ? nf : 0);
+    if (ngc) hi = std::max(hi, L.gc[ngc - 1] + fb);
+    if (m.immersed) hi = std::max(hi, L.mask + fb);
+    if (hi > 0xFFFFFFFFull) {
+      set_error("the fields of the tendency kernel span %llu bytes; at most 2^32 - 1 are "
+                "addressable", (unsigned long long)hi);
       return OC_ERR_UNSUPPORTED;
     }
   }
@@ -757,8 +775,8 @@ int diagnostics_call(oc_model* m, double* out, hipStream_t s) {
   for (int q = 0; q < m->nf; ++q) f[q] = (T*)m->state[m->cur][q];
   const int nz = m->dims.nz;
   OC_CHECK_HIP(launch_diagnostics<T>(m->dims, f, m->nf, 1.0 / m->dx, 1.0 / m->dy,
-                                     m->zt64 + zt_rdzc(nz), m->zt64 + zt_dzc(nz), m->diag_part,
-                                     DIAG_BLOCKS, s));
+                                     m->zt64 + zt_rdzc(nz), m->zt64 + zt_dzc(nz),
+                                     m->zt64 + zt_dzf(nz), m->diag_part, DIAG_BLOCKS, s));
   std::vector<double> part((size_t)DIAG_BLOCKS * DIAG_PARTS);
   OC_CHECK_HIP(hipMemcpyAsync(part.data(), m->diag_part, part.size() * 8, hipMemcpyDeviceToHost, s));
   OC_CHECK_HIP(hipStreamSynchronize(s));
@@ -768,7 +786,7 @@ int diagnostics_call(oc_model* m, double* out, hipStream_t s) {
       double x = part[(size_t)b * DIAG_PARTS + q];
       acc[q] = (q < 4) ? std::fmax(acc[q], x) : acc[q] + x;
     }
-  // tracer sums are already weighted by the layer thickness
+  // sums are already weighted by the layer thickness
   const double area = m->dx * m->dy;
   out[0] = acc[0] * std::fmin(m->dx, std::fmin(m->dy, m->dzmin));
   out[1] = acc[1];
@@ -779,6 +797,8 @@ int diagnostics_call(oc_model* m, double* out, hipStream_t s) {
     const double off = (OC_TRACER0 + q < m->nf) ? m->offset[OC_TRACER0 + q] : 0.0;
     out[4 + q] = (acc[4 + q] + off * ncell * m->dz) * area;
   }
+  for (int q = 0; q < 3; ++q) out[8 + q] = acc[9 + q] * area;
+  out[11] = std::fmax(acc[1] / m->dx, std::fmax(acc[2] / m->dy, acc[3] / m->dzmin));
   if (acc[8] > 0) {
     set_error("state holds %g non-finite cells", acc[8]);
     return OC_ERR_NONFINITE;
@@ -1533,7 +1553,25 @@ int oc_pressure_stats(oc_model* m, int32_t* iterations, double* rel_residual, vo
 
 int oc_diagnostics(oc_model* m, double* out, void* stream) {
   if (!m || !out) { set_error("NULL argument"); return OC_ERR_ARG; }
+  if (m->kind != OC_NONHYDROSTATIC) {
+    set_error("diagnostics are defined for the nonhydrostatic (rectilinear) model");
+    return OC_ERR_UNSUPPORTED;
+  }
   hipStream_t s = (hipStream_t)stream;
+  return (m->esz == 8) ? diagnostics_call<double>(m, out, s) : diagnostics_call<float>(m, out, s);
+}
+
+int oc_sync_check(oc_model* m, void* stream) {
+  if (!m) { set_error("model is NULL"); return OC_ERR_ARG; }
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e != hipSuccess) {
+    set_error("device error: %s", hipGetErrorString(e));
+    return OC_ERR_DEVICE;
+  }
+  if (m->kind != OC_NONHYDROSTATIC) return OC_OK;
+  double out[OC_NDIAG];
   return (m->esz == 8) ? diagnostics_call<double>(m, out, s) : diagnostics_call<float>(m, out, s);
 }
 

@@ -39,7 +39,7 @@ struct oc_ensemble {
   };
   std::vector<Class> classes;
   EnsTuning tn;
-  int tuned;               // 0 default, 1 timed, 2 from the cache
+  int tuned;               // 0 default, 1 timed, 2 from the cache, 3 set by the caller
   double tune_ms;
   std::vector<int> cur0;
   int phase;
@@ -193,6 +193,8 @@ void fill_member_params(const oc_ensemble* e, std::vector<EnsMember<T>>& hm, dou
       }
       for (int q = 0; q < MAXF; ++q) fs.closure[q] = nullptr;
       fs.mask = nullptr;
+      // within 4 GiB: every member passed the model checks
+      (void)fieldset_offsets(fs, (uint64_t)padded_elems(m->dims) * sizeof(T));
     }
     for (int st = 0; st < 3; ++st) {
       TendParams<T> p = tend_params<T>(m);
@@ -366,22 +368,22 @@ int time_candidate(oc_ensemble* e, const EnsTuning& tn, double& ms) {
 }
 
 template <class T>
-int tune(oc_ensemble* e, int do_tune) {
+EnsTuning default_tuning(const oc_ensemble* e) {
   EnsTuning def;
   def.tile = 0;
   for (const oc_model* m : e->mem)
     if (!tile_fits(m, 0)) def.tile = tile_fits(m, 1) ? std::max(def.tile, 1) : 2;
   def.persistent = 0;
   def.kc_div = 1024;
-  def.nblocks = 0;
-  e->tn = def;
-  e->tuned = 0;
-  e->tune_ms = 0.0;
-  if (!do_tune) {
-    e->tn.nblocks = persistent_blocks<T>(e->tn);
-    return OC_OK;
-  }
-  const char* path = std::getenv("OC_TUNE_CACHE");
+  def.nblocks = persistent_blocks<T>(def);
+  return def;
+}
+
+// Time every candidate launch configuration and keep the fastest, or take the
+// choice recorded under this ensemble's key in the cache file `path` (NULL:
+// no cache).  A timed choice is appended to the cache.
+template <class T>
+int tune(oc_ensemble* e, const char* path) {
   const std::string key = tune_key(e);
   EnsTuning c;
   double ms = 0.0;
@@ -397,7 +399,7 @@ int tune(oc_ensemble* e, int do_tune) {
     }
   }
   double best = 1e30;
-  EnsTuning bt = def;
+  EnsTuning bt = default_tuning<T>(e);
   for (int tile = 0; tile < 3; ++tile) {
     bool ok = true;
     for (const oc_model* m : e->mem) ok = ok && tile_fits(m, tile);
@@ -424,8 +426,13 @@ int tune(oc_ensemble* e, int do_tune) {
 
 template <class T>
 int ens_setup(oc_ensemble* e) {
-  int rc = tune<T>(e, e->flags & OC_ENS_TUNE);
-  if (rc) return rc;
+  e->tn = default_tuning<T>(e);
+  e->tuned = 0;
+  e->tune_ms = 0.0;
+  if (e->flags & OC_ENS_TUNE) {
+    int rc = tune<T>(e, nullptr);
+    if (rc) return rc;
+  }
   return upload_tables<T>(e, e->tn, e->table_dt);
 }
 
@@ -500,6 +507,29 @@ int ens_step(oc_ensemble* e, double dt, int nsteps, hipStream_t s) {
   }
   for (size_t i = 0; i < e->mem.size(); ++i) e->mem[i]->cur = e->cur0[i] ^ e->phase;
   return OC_OK;
+}
+
+// A new launch configuration: wait for queued work (the tables and the
+// timing launches write device memory that it may still read), restart the
+// buffer parities from where the members stand, then either time the
+// candidates (`set` == NULL) or take `set`, and rebuild the tables; graphs
+// are captured again on the next step.
+template <class T>
+int ens_retune(oc_ensemble* e, const char* path, const EnsTuning* set) {
+  OC_CHECK_HIP(hipDeviceSynchronize());
+  for (size_t i = 0; i < e->mem.size(); ++i) e->cur0[i] = e->mem[i]->cur;
+  e->phase = 0;
+  drop_graphs(e);
+  if (set) {
+    e->tn = *set;
+    e->tn.nblocks = persistent_blocks<T>(e->tn);
+    e->tuned = 3;
+    e->tune_ms = 0.0;
+  } else {
+    int rc = tune<T>(e, path);
+    if (rc) return rc;
+  }
+  return upload_tables<T>(e, e->tn, e->table_dt);
 }
 
 }  // namespace
@@ -610,6 +640,31 @@ int oc_ensemble_tuning(const oc_ensemble* e, int32_t* out, double* ms) {
   out[5] = e->nitems;
   if (ms) *ms = e->tune_ms;
   return OC_OK;
+}
+
+int oc_autotune(oc_ensemble* e, const char* cache_path) {
+  if (!e) { set_error("ensemble is NULL"); return OC_ERR_ARG; }
+  return e->esz == 8 ? ens_retune<double>(e, cache_path, nullptr)
+                     : ens_retune<float>(e, cache_path, nullptr);
+}
+
+int oc_ensemble_set_tuning(oc_ensemble* e, const int32_t* tuning) {
+  if (!e || !tuning) { set_error("NULL argument"); return OC_ERR_ARG; }
+  EnsTuning t;
+  t.tile = tuning[0];
+  t.persistent = tuning[1];
+  t.kc_div = tuning[2];
+  t.nblocks = 0;
+  if (t.tile < 0 || t.tile > 2 || (t.persistent != 0 && t.persistent != 1) || t.kc_div < 1) {
+    set_error("need tile in 0..2, persistent 0 or 1 and kc_div >= 1");
+    return OC_ERR_ARG;
+  }
+  for (const oc_model* m : e->mem)
+    if (!tile_fits(m, t.tile)) {
+      set_error("tile %d does not divide every member's nx and ny", t.tile);
+      return OC_ERR_ARG;
+    }
+  return e->esz == 8 ? ens_retune<double>(e, nullptr, &t) : ens_retune<float>(e, nullptr, &t);
 }
 
 int oc_ensemble_destroy(oc_ensemble* e) {

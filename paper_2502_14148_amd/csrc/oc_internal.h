@@ -37,9 +37,10 @@ __host__ __device__ inline long pidx(const Dims& d, int i, int j, int k) {
 // mirror for data centred in z (wface = false) or an odd mirror about the
 // wall faces for w (wface = true).  Wall faces of w are never images.  A
 // point within h of both ends of a short axis has an image at each end.
+// own = false: the images only (the caller stores the point itself).
 template <class T>
 __device__ inline void store_with_images(T* __restrict__ f, const Dims& d, int i, int j, int k,
-                                         T val, bool wface) {
+                                         T val, bool wface, bool own = true) {
   const int H = d.h;
   // element offsets of the images along each axis (0: none; an image is
   // never at offset 0)
@@ -59,8 +60,8 @@ __device__ inline void store_with_images(T* __restrict__ f, const Dims& d, int i
     if (k >= d.nz - H + 1 && k <= d.nz - 1) zb = (long)(2 * d.nz - 2 * k) * d.sz;  // 2nz - k
   }
   T* __restrict__ p0 = f + pidx(d, i, j, k);
-  auto plane = [&](T* q, T v) {
-    q[0] = v;
+  auto plane = [&](T* q, T v, bool self) {
+    if (self) q[0] = v;
     if (xa) q[xa] = v;
     if (xb) q[xb] = v;
     if (ya) {
@@ -74,9 +75,9 @@ __device__ inline void store_with_images(T* __restrict__ f, const Dims& d, int i
       if (xb) q[yb + xb] = v;
     }
   };
-  plane(p0, val);
-  if (za) plane(p0 + za, zs * val);
-  if (zb) plane(p0 + zb, zs * val);
+  plane(p0, val, own);
+  if (za) plane(p0 + za, zs * val, true);
+  if (zb) plane(p0 + zb, zs * val, true);
 }
 
 inline Dims make_dims(int nx, int ny, int nz, int zb, int h) {
@@ -126,7 +127,43 @@ struct FieldSet {
                            // padded layout, added to G; null when off
   const T* mask;           // immersed boundary: 1 in fluid, 0 in immersed
                            // cells (padded, with halo images); null when off
+  // Buffer addressing of the tendency kernels (set by fieldset_offsets):
+  // every field above lies within 4 GiB of `base`; byte offsets from it.
+  const char* base;
+  uint32_t oin[MAXF], oout[MAXF], oG[MAXF], oclo[MAXF], omask;
 };
+
+// Fill the buffer-addressing members of fs: base = the lowest field pointer,
+// offsets in bytes.  False if some field of `bytes` bytes (one padded field)
+// does not end within 4 GiB of base.
+template <class T>
+inline bool fieldset_offsets(FieldSet<T>& fs, uint64_t bytes) {
+  const char* lo = nullptr;
+  auto see = [&](const void* p) {
+    if (p && (!lo || (const char*)p < lo)) lo = (const char*)p;
+  };
+  for (int q = 0; q < MAXF; ++q) {
+    see(fs.in[q]); see(fs.out[q]); see(fs.G[q]); see(fs.closure[q]);
+  }
+  see(fs.mask);
+  if (!lo) return false;
+  fs.base = lo;
+  bool ok = true;
+  auto off = [&](const void* p) -> uint32_t {
+    if (!p) return 0u;
+    const uint64_t o = (uint64_t)((const char*)p - lo);
+    if (o + bytes > 0xFFFFFFFFull) ok = false;
+    return (uint32_t)o;
+  };
+  for (int q = 0; q < MAXF; ++q) {
+    fs.oin[q] = off(fs.in[q]);
+    fs.oout[q] = off(fs.out[q]);
+    fs.oG[q] = off(fs.G[q]);
+    fs.oclo[q] = off(fs.closure[q]);
+  }
+  fs.omask = off(fs.mask);
+  return ok;
+}
 
 // Spectral-solve tables and buffers (FP64).
 struct SpecBufs {
@@ -500,8 +537,8 @@ hipError_t launch_pack(const Dims& d, int nzf, int nyf, const T* padded, void* d
                        int to_dense, double offset, hipStream_t s);
 template <class T>
 hipError_t launch_diagnostics(const Dims& d, T* const* fields, int nf, double rdx, double rdy,
-                              const double* rdzc, const double* dzc, double* scratch,
-                              int nblocks, hipStream_t s);
+                              const double* rdzc, const double* dzc, const double* dzf,
+                              double* scratch, int nblocks, hipStream_t s);
 
 bool fft_length_supported(int n);
 

@@ -102,10 +102,11 @@ hipError_t launch_pack(const Dims& d, int nzf, int nyf, const T* padded, void* d
 
 // ---------------------------------------------------------------------------
 // Diagnostics: per-block partials in a fixed order (deterministic), reduced
-// on the host.  Per block: max|div|, max|u|, max|v|, max|w|, sum tracers
-// (up to 4), non-finite count.
+// on the host in block order.  Per block: max|div|, max|u|, max|v|, max|w|,
+// thickness-weighted sums of tracers 0..3, the non-finite count, and the
+// thickness-weighted sums of u, v (cell thickness) and w (face spacing).
 // ---------------------------------------------------------------------------
-constexpr int NPART = 9;
+constexpr int NPART = 12;
 
 template <class T>
 struct DiagArgs {
@@ -113,39 +114,43 @@ struct DiagArgs {
   int nf;
 };
 
+// Accumulate cell (i, j, k) into the partials acc[NPART].
 template <class T>
-__global__ void __launch_bounds__(256) diag_kernel(Dims d, DiagArgs<T> a, double rdx, double rdy,
-                                                   const double* __restrict__ rdzc,
-                                                   const double* __restrict__ dzc, double* part) {
-  __shared__ double red[NPART][256];
-  double acc[NPART];
-  for (int q = 0; q < NPART; ++q) acc[q] = 0.0;
-  const long n = (long)d.nx * d.ny * d.nz;
-  for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < n;
-       t += (long)gridDim.x * blockDim.x) {
-    int i = (int)(t % d.nx);
-    int j = (int)((t / d.nx) % d.ny);
-    int k = (int)(t / ((long)d.nx * d.ny));
-    long c = pidx(d, i, j, k);
-    const int ip = (i + 1) % d.nx, jp = (j + 1) % d.ny;
-    double uu = (double)a.f[0][c], vv = (double)a.f[1][c], ww = (double)a.f[2][c];
-    double wt;
-    if (d.zb) wt = (k + 1 == d.nz) ? 0.0 : (double)a.f[2][c + d.sz];
-    else wt = (double)a.f[2][pidx(d, i, j, (k + 1) % d.nz)];
-    double div = ((double)a.f[0][pidx(d, ip, j, k)] - uu) * rdx +
-                 ((double)a.f[1][pidx(d, i, jp, k)] - vv) * rdy + (wt - ww) * rdzc[k];
-    acc[0] = fmax(acc[0], fabs(div));
-    acc[1] = fmax(acc[1], fabs(uu));
-    acc[2] = fmax(acc[2], fabs(vv));
-    acc[3] = fmax(acc[3], fabs(ww));
-    bool bad = !isfinite(uu) || !isfinite(vv) || !isfinite(ww);
-    for (int q = 3; q < a.nf; ++q) {
-      double x = (double)a.f[q][c];
-      acc[1 + q] += x * dzc[k];  // layer thickness weight
-      bad = bad || !isfinite(x);
-    }
-    if (bad) acc[8] += 1.0;
+__device__ inline void diag_cell(const Dims& d, const DiagArgs<T>& a, double rdx, double rdy,
+                                 const double* __restrict__ rdzc, const double* __restrict__ dzc,
+                                 const double* __restrict__ dzf, int i, int j, int k,
+                                 double* acc) {
+  const long c = pidx(d, i, j, k);
+  const int ip = (i + 1) % d.nx, jp = (j + 1) % d.ny;
+  const double uu = (double)a.f[0][c], vv = (double)a.f[1][c], ww = (double)a.f[2][c];
+  double wt;
+  if (d.zb) wt = (k + 1 == d.nz) ? 0.0 : (double)a.f[2][c + d.sz];
+  else wt = (double)a.f[2][pidx(d, i, j, (k + 1) % d.nz)];
+  const double div = ((double)a.f[0][pidx(d, ip, j, k)] - uu) * rdx +
+                     ((double)a.f[1][pidx(d, i, jp, k)] - vv) * rdy + (wt - ww) * rdzc[k];
+  acc[0] = fmax(acc[0], fabs(div));
+  acc[1] = fmax(acc[1], fabs(uu));
+  acc[2] = fmax(acc[2], fabs(vv));
+  acc[3] = fmax(acc[3], fabs(ww));
+  bool bad = !isfinite(uu) || !isfinite(vv) || !isfinite(ww);
+  for (int q = 3; q < a.nf; ++q) {
+    const double x = (double)a.f[q][c];
+    acc[1 + q] += x * dzc[k];  // layer thickness weight
+    bad = bad || !isfinite(x);
   }
+  if (bad) acc[8] += 1.0;
+  // momentum: u and v cells have the thickness of cell k; w face k (the
+  // bottom wall face is 0 in a bounded z) the spacing of the centres either
+  // side of it
+  acc[9] += uu * dzc[k];
+  acc[10] += vv * dzc[k];
+  acc[11] += ww * dzf[k];
+}
+
+// Block-wide reduction of acc[NPART] in a fixed order (maxima for 0..3, sums
+// otherwise); thread q < NPART writes partial q to out[q].
+__device__ inline void diag_block_reduce(double* acc, double* out) {
+  __shared__ double red[NPART][256];
   for (int q = 0; q < NPART; ++q) red[q][threadIdx.x] = acc[q];
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
@@ -157,18 +162,36 @@ __global__ void __launch_bounds__(256) diag_kernel(Dims d, DiagArgs<T> a, double
     }
     __syncthreads();
   }
-  if (threadIdx.x < NPART) part[(long)blockIdx.x * NPART + threadIdx.x] = red[threadIdx.x][0];
+  if (threadIdx.x < NPART) out[threadIdx.x] = red[threadIdx.x][0];
+}
+
+template <class T>
+__global__ void __launch_bounds__(256) diag_kernel(Dims d, DiagArgs<T> a, double rdx, double rdy,
+                                                   const double* __restrict__ rdzc,
+                                                   const double* __restrict__ dzc,
+                                                   const double* __restrict__ dzf, double* part) {
+  double acc[NPART];
+  for (int q = 0; q < NPART; ++q) acc[q] = 0.0;
+  const long n = (long)d.nx * d.ny * d.nz;
+  for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+       t += (long)gridDim.x * blockDim.x) {
+    const int i = (int)(t % d.nx);
+    const int j = (int)((t / d.nx) % d.ny);
+    const int k = (int)(t / ((long)d.nx * d.ny));
+    diag_cell(d, a, rdx, rdy, rdzc, dzc, dzf, i, j, k, acc);
+  }
+  diag_block_reduce(acc, part + (long)blockIdx.x * NPART);
 }
 
 template <class T>
 hipError_t launch_diagnostics(const Dims& d, T* const* fields, int nf, double rdx, double rdy,
-                              const double* rdzc, const double* dzc, double* scratch,
-                              int nblocks, hipStream_t s) {
+                              const double* rdzc, const double* dzc, const double* dzf,
+                              double* scratch, int nblocks, hipStream_t s) {
   DiagArgs<T> a;
   for (int q = 0; q < nf; ++q) a.f[q] = fields[q];
   a.nf = nf;
   hipLaunchKernelGGL(diag_kernel<T>, dim3(nblocks), dim3(256), 0, s, d, a, rdx, rdy, rdzc, dzc,
-                     scratch);
+                     dzf, scratch);
   return hipGetLastError();
 }
 
@@ -179,10 +202,11 @@ template hipError_t launch_pack<float>(const Dims&, int, int, const float*, void
 template hipError_t launch_pack<double>(const Dims&, int, int, const double*, void*, int, int,
                                         double, hipStream_t);
 template hipError_t launch_diagnostics<float>(const Dims&, float* const*, int, double, double,
-                                              const double*, const double*, double*, int,
-                                              hipStream_t);
+                                              const double*, const double*, const double*,
+                                              double*, int, hipStream_t);
 template hipError_t launch_diagnostics<double>(const Dims&, double* const*, int, double, double,
-                                               const double*, const double*, double*, int,
-                                               hipStream_t);
+                                               const double*, const double*, const double*,
+                                               double*, int, hipStream_t);
+
 
 }  // namespace oc

@@ -321,12 +321,14 @@ def ensemble_physics(sizes=(64, 96, 128), per_size: int = 16, seed: int = 0,
 
 
 def random_state(ph: Physics, seed: int = 0, vel: float = 1.0, tracer_scale: float = 1.0,
-                 divergence_free: bool = True):
+                 divergence_free: bool = True, tracer_means=None):
     """Rough random state for parity tests (every cell independent).
 
     Velocities are the curl of an i.i.d. potential (divergence-free) unless
     `divergence_free` is False, in which case they are i.i.d. Gaussian (w = 0
-    on walls).  Tracers are i.i.d. Gaussian around distinct means.
+    on walls).  Tracers are i.i.d. Gaussian around distinct means: 0, 10,
+    20, ... or, if given, tracer_means (one per tracer, e.g. the equation of
+    state's reference values).
     """
     rng = np.random.default_rng(seed)
     nz, ny, nx = ph.nz, ph.ny, ph.nx
@@ -352,7 +354,8 @@ def random_state(ph: Physics, seed: int = 0, vel: float = 1.0, tracer_scale: flo
         w[-1] = 0.0
     out = {"u": u, "v": v, "w": w}
     for idx, name in enumerate(ph.tracers):
-        out[name] = (10.0 * idx + tracer_scale * rng.standard_normal((nz, ny, nx)))
+        mean = 10.0 * idx if tracer_means is None else float(tracer_means[idx])
+        out[name] = (mean + tracer_scale * rng.standard_normal((nz, ny, nx)))
     return out
 
 

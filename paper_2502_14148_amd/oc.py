@@ -24,7 +24,7 @@ ADVECTION = {"none": 0, "weno5z": 1, "weno5_linear": 2, "weno7z": 3, "weno7_line
              "weno9z": 5, "weno9_linear": 6}
 OC_F32, OC_F64 = 0, 1
 OC_MAX_TRACERS = 4
-OC_NDIAG = 8
+OC_NDIAG = 12
 
 EXPORTS = ("oc_last_error", "oc_grid_create", "oc_grid_destroy", "oc_model_workspace_size",
            "oc_model_create", "oc_model_destroy", "oc_set_state", "oc_get_state",
@@ -37,8 +37,9 @@ EXPORTS = ("oc_last_error", "oc_grid_create", "oc_grid_destroy", "oc_model_works
            "oc_ensemble_workspace_size", "oc_ensemble_create", "oc_ensemble_step",
            "oc_ensemble_tuning", "oc_ensemble_destroy", "oc_closure_features",
            "oc_coarse_grain", "oc_implicit_vertical_diffusion", "oc_set_immersed",
-           "oc_pressure_stats")
+           "oc_pressure_stats", "oc_sync_check", "oc_autotune", "oc_ensemble_set_tuning")
 OC_ENS_TUNE, OC_ENS_GRAPH = 1, 2
+ENS_TILES = ("32x8", "16x8", "8x8")
 OC_MLP_NPARAM = 195076
 MLP_SHAPES = (("W1", (256, 500)), ("b1", (256,)), ("W2", (256, 256)), ("b2", (256,)),
               ("W3", (4, 256)), ("b3", (4,)))
@@ -133,6 +134,9 @@ def load_library(path=_LIB_PATH):
         "oc_set_immersed": [vp, vp, vp],
         "oc_pressure_stats": [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double),
                               vp],
+        "oc_sync_check": [vp, vp],
+        "oc_autotune": [vp, ctypes.c_char_p],
+        "oc_ensemble_set_tuning": [vp, ctypes.POINTER(ctypes.c_int32)],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -326,7 +330,13 @@ class Model:
         out = (ctypes.c_double * OC_NDIAG)()
         _check(_lib.oc_diagnostics(self._model, out, _stream()))
         return {"div_scaled_by_dx": out[0], "max_u": out[1], "max_v": out[2], "max_w": out[3],
-                "tracer_integrals": list(out[4:4 + len(self.ph.tracers)])}
+                "tracer_integrals": list(out[4:4 + len(self.ph.tracers)]),
+                "momentum": (out[8], out[9], out[10]), "cfl_rate": out[11]}
+
+    def sync_check(self):
+        """Synchronise the current stream; raises on a device error or a
+        non-finite state (OC_ERR_NONFINITE)."""
+        _check(_lib.oc_sync_check(self._model, _stream()))
 
     def profile(self, enable=True):
         _check(_lib.oc_profile(self._model, 1 if enable else 0))
@@ -495,6 +505,19 @@ class Ensemble:
         out = (ctypes.c_int32 * 6)()
         ms = ctypes.c_double()
         _check(_lib.oc_ensemble_tuning(self._h, out, ctypes.byref(ms)))
-        return {"tile": ("32x8", "16x8", "8x8")[out[0]], "persistent": bool(out[1]),
+        return {"tile": ENS_TILES[out[0]], "persistent": bool(out[1]),
                 "nblocks": out[2], "kc_div": out[3],
-                "source": ("default", "timed", "cache")[out[4]], "items": out[5], "ms": ms.value}
+                "source": ("default", "timed", "cache", "set")[out[4]], "items": out[5],
+                "ms": ms.value}
+
+    def autotune(self, cache_path=None):
+        """Time the launch configurations (or read the choice from the
+        JSON-lines cache file) and keep the fastest."""
+        p = None if cache_path is None else os.fsencode(str(cache_path))
+        _check(_lib.oc_autotune(self._h, p))
+        return self.tuning()
+
+    def set_tuning(self, tile="32x8", persistent=False, kc_div=1024):
+        t = (ctypes.c_int32 * 3)(ENS_TILES.index(tile), 1 if persistent else 0, kc_div)
+        _check(_lib.oc_ensemble_set_tuning(self._h, t))
+        return self.tuning()

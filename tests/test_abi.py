@@ -271,3 +271,11 @@ def test_immersed_validation():
     assert lib.oc_grid_destroy(g) == 0
     assert lib.oc_set_immersed(None, None, None) == -1
     assert lib.oc_pressure_stats(None, None, None, None) == -1
+
+
+def test_new_calls_reject_null_arguments():
+    lib = oc.load_library()
+    assert lib.oc_sync_check(None, None) == -1
+    assert lib.oc_autotune(None, None) == -1
+    assert lib.oc_ensemble_set_tuning(None, None) == -1
+    assert lib.oc_diagnostics(None, None, None) == -1

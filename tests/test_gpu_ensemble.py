@@ -101,17 +101,68 @@ def test_ensemble_member_matches_oracle(gpu_lib):
         assert rel_l2(got, want) < 1e-12, (f, rel_l2(got, want))
 
 
-def test_autotune_cache_roundtrip(gpu_lib, tmp_path, monkeypatch):
+def test_autotune_cache_roundtrip(gpu_lib, tmp_path):
     path = tmp_path / "tune.jsonl"
-    monkeypatch.setenv("OC_TUNE_CACHE", str(path))
     mem = _members(SIZES[:3], seed=4)
     ms = _models(gpu_lib, mem, "fp32")
-    t1 = gpu_lib.Ensemble(ms, tune=True).tuning()
+    e1 = gpu_lib.Ensemble(ms)
+    assert e1.tuning()["source"] == "default"
+    t1 = e1.autotune(path)
     assert t1["source"] == "timed" and path.exists()
-    t2 = gpu_lib.Ensemble(ms, tune=True).tuning()
+    e2 = gpu_lib.Ensemble(ms)
+    t2 = e2.autotune(path)
     assert t2["source"] == "cache"
     for k in ("tile", "persistent", "kc_div"):
         assert t1[k] == t2[k]
+    # no cache: timed again, nothing written
+    n_lines = len(path.read_text().splitlines())
+    assert e2.autotune(None)["source"] == "timed"
+    assert len(path.read_text().splitlines()) == n_lines
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("tile,kc_div", [("32x8", 1024), ("16x8", 256), ("8x8", 4096)])
+def test_persistent_grid_equals_members_stepped_alone(gpu_lib, precision, tile, kc_div):
+    """The persistent work-queue launch (workgroups resident on every CU
+    drain an atomic counter, reset inside the captured graph), forced through
+    oc_ensemble_set_tuning, gives the members' own oc_rk3_step results bit
+    for bit, over several graph replays and across a change of the launch
+    configuration."""
+    mem = _members(SIZES, seed=6)
+    ens_models = _models(gpu_lib, mem, precision)
+    ref_models = _models(gpu_lib, mem, precision)
+    e = gpu_lib.Ensemble(ens_models, graph=True)
+    t = e.set_tuning(tile, persistent=True, kc_div=kc_div)
+    assert t["persistent"] and t["source"] == "set" and t["tile"] == tile
+    assert t["nblocks"] >= 256
+    dt = 2.0
+    e.step(dt, 3)
+    for m in ref_models:
+        m.rk3_step(dt, 3)
+    _assert_same(ens_models, ref_models)
+    # the flat grid of the same tile continues from there
+    e.set_tuning(tile, persistent=False, kc_div=kc_div)
+    e.step(dt, 2)
+    for m in ref_models:
+        m.rk3_step(dt, 2)
+    _assert_same(ens_models, ref_models)
+    # and the persistent grid again, without graphs
+    e2 = gpu_lib.Ensemble(ens_models, graph=False)
+    e2.set_tuning(tile, persistent=True, kc_div=kc_div)
+    e2.step(dt, 1)
+    for m in ref_models:
+        m.rk3_step(dt, 1)
+    _assert_same(ens_models, ref_models)
+
+
+def test_set_tuning_rejects_bad_values(gpu_lib):
+    mem = _members([(32, 32, 32), (16, 16, 16)], seed=7)
+    e = gpu_lib.Ensemble(_models(gpu_lib, mem, "fp32"))
+    with pytest.raises(gpu_lib.OcError, match="OC_ERR_ARG"):
+        e.set_tuning("32x8", kc_div=1024)   # does not divide the 16 x 16 member
+    with pytest.raises(gpu_lib.OcError, match="OC_ERR_ARG"):
+        e.set_tuning("8x8", kc_div=0)
+    assert e.set_tuning("16x8", kc_div=1024)["tile"] == "16x8"
 
 
 def test_full_size_uneven_ensemble(gpu_lib):

@@ -86,3 +86,58 @@ def test_full_size_step_divergence_and_heat_budget(gpu_lib, kind):
     want = -jt * ph.lx * ph.ly * dt
     got = d["tracer_integrals"][0] - before
     assert abs(got - want) < 1e-4 * abs(want), (got, want)
+
+
+def _fp32_step_vs_oracle(gpu_lib, s):
+    """One FP32-mixed RK3 step (dt = 1 s) of the 256^3 free convection from
+    the FP32-rounded state s, and the FP64 oracle's step from the same
+    values; returns (initial, GPU result, oracle result) interiors."""
+    import torch
+    from oracle import fv
+    ph = _physics("uniform")
+    s32 = {k: v.astype(np.float32).astype(np.float64) for k, v in s.items()}
+    m = gpu_lib.Model(ph, "fp32")
+    m.set_states(s32)
+    m.rk3_step(1.0, 1)
+    got = {n: m.get_state(n) for n in m.fields}
+    del m
+    torch.cuda.empty_cache()
+    st, _ = timestep.rk3_step(timestep.make_state(s32, ph), 1.0, ph, workers=5)
+    ref = {n: fv.interior(st[n], ph, n) for n in got}
+    return ph, s32, got, ref
+
+
+@pytest.mark.timeout(900)
+def test_fp32_step_256cubed_benchmark_state(gpu_lib):
+    """The benchmark's own 256^3 state (1e-3 m/s velocity noise, T the
+    stratified profile, S uniform): raw fields to 1e-5 relative L2; the
+    changes over the step to the bar of tests/fp32_bounds.py, which here is
+    set by rounding the stored T (|T - 20| up to 1.3 K, while one step moves T
+    by ~5e-6 K) and is still far below what a T that never changed would
+    give; S is uniform, so its change is the roundoff of -S0 div u on both
+    sides and stays below the FP32 quantum of S itself."""
+    from tests.fp32_bounds import check_anomaly
+    ph, s0, got, ref = _fp32_step_vs_oracle(gpu_lib, inputs.convection_initial(_physics("uniform"),
+                                                                               seed=0))
+    for name in ("u", "v", "w", "T", "S"):
+        err = rel_l2(got[name], ref[name])
+        assert err <= 1e-5, (name, err)
+    for name in ("u", "v", "w", "T"):
+        check_anomaly(got[name], ref[name], s0[name], 1, ph, name, "fp32", "256^3 benchmark state")
+    assert np.max(np.abs(got["S"] - s0["S"])) < 0.25 * np.spacing(np.float32(35.0))
+
+
+@pytest.mark.timeout(900)
+def test_fp32_step_256cubed_energetic_state(gpu_lib):
+    """256^3 with 0.2 m/s velocity noise and 0.2 K / 0.2 g/kg tracer noise
+    (CFL ~ 0.1 per step): every field changes by percents in one step, so the
+    change of every field, S included, is held to about 1e-5."""
+    from tests.fp32_bounds import check_anomaly
+    ph0 = _physics("uniform")
+    s = inputs.convection_initial(ph0, seed=11, noise=0.2, tracer_noise=0.2)
+    ph, s0, got, ref = _fp32_step_vs_oracle(gpu_lib, s)
+    for name in ("u", "v", "w", "T", "S"):
+        err = rel_l2(got[name], ref[name])
+        assert err <= 1e-5, (name, err)
+        e, bar = check_anomaly(got[name], ref[name], s0[name], 1, ph, name, "fp32", "256^3 energetic")
+        assert bar < 3e-5, (name, bar)

@@ -3,7 +3,11 @@ vector-invariant momentum, flux-form tracers on the shell, QAB2, coupling to
 the split-explicit barotropic mode) against the FP64 oracle.
 
 Bars: FP64 state 1e-12 relative L2; FP32 state 1e-5 relative L2 (the FP32
-run starts from the FP64 state rounded to FP32).  Tendencies G^n, which
+run starts from the FP64 state rounded to FP32).  The change of every field
+over the run is compared too: 1e-10 in FP64; in FP32 the bar of
+tests/fp32_bounds.py, 1e-5 plus what rounding the stored state costs (T of
+2-22 K changes by ~1e-4 K per 600 s step on these coarse test grids, so
+that floor dominates, yet a field that is never updated still fails).  Tendencies G^n, which
 difference nearly equal FP32 values (kinetic energy, buoyancy), are held to
 1e-4 in FP32."""
 import numpy as np
@@ -11,6 +15,7 @@ import pytest
 
 from paper_2502_14148_amd import inputs
 from oracle import hydrostatic as hso
+from tests.fp32_bounds import anomaly_tolerance
 
 pytestmark = pytest.mark.gpu
 
@@ -61,10 +66,18 @@ def _check_run(gpu_lib, ph, precision, nsteps, seed, dt=600.0, N=10):
     for k in ("u", "v", "T", "S"):
         got = m.get_state(k)
         assert rel_l2(got, ref[k]) < tol, (k, rel_l2(got, ref[k]))
-        if k in ("T", "S") and precision == "fp64":
-            # the change of the tracers, not hidden by their mean
-            d_ref = ref[k] - s[k]
-            assert rel_l2(got - s[k], d_ref) < 1e-10, (k, rel_l2(got - s[k], d_ref))
+        # the change over the run, not hidden by the mean of the field
+        d_ref = ref[k] - s[k]
+        err = rel_l2(got - s[k], d_ref)
+        if precision == "fp64":
+            assert err < 1e-10, (k, err)
+        else:
+            # two FP32 stores per step (the QAB2 combine, then the barotropic
+            # correction of u, v); T and S are stored about (t_ref, s_ref)
+            off = {"T": ph.t_ref, "S": ph.s_ref}.get(k, 0.0)
+            bar = anomaly_tolerance(ref[k], s[k], nsteps, off, stores_per_step=2)
+            assert bar < 0.1, (k, "the run changes the field too little to test", bar)
+            assert err <= bar, (k, err, bar)
     for k in ("eta", "U", "V"):
         got = m.get_state(k)[0]
         assert rel_l2(got, ref[k]) < tol, (k, rel_l2(got, ref[k]))

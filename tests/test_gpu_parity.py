@@ -1,12 +1,17 @@
 """GPU parity: the HIP path through the C ABI against the FP64 oracle on the
 same seeded inputs.  Bar: relative L2 <= 1e-12 per field in FP64, <= 1e-5 in
-FP32-mixed (the FP32 run starts from the FP64 input rounded to FP32)."""
+FP32-mixed (the FP32 run starts from the FP64 input rounded to FP32).  Step
+tests also compare the change of every field over the run, x - x(0), whose
+bar (tests/fp32_bounds.py) is 1e-5 plus what rounding the stored state costs;
+the states here change enough that the bar is close to 1e-5, so a field that
+is never updated fails."""
 import numpy as np
 import pytest
 
 from paper_2502_14148_amd import inputs
 from paper_2502_14148_amd.inputs import Physics
 from oracle import fv, tendencies as td, timestep, pressure
+from tests.fp32_bounds import check_anomaly
 
 pytestmark = pytest.mark.gpu
 
@@ -33,9 +38,12 @@ def box(n=16, **kw):
 CASES = {
     "box16_weno5z": lambda: (box(16), lambda ph: inputs.random_state(ph, seed=1)),
     "box32_smooth": lambda: (box(32), lambda ph: inputs.smooth_random_state(ph, seed=2)),
-    "conv_32x32x16": lambda: (small_convection(), lambda ph: inputs.random_state(ph, seed=3, vel=1e-2)),
-    "conv_ragged_64x32x8": lambda: (small_convection(64, 32, 8),
-                                   lambda ph: inputs.random_state(ph, seed=4, vel=1e-2)),
+    # convection cases: tracers about the equation of state's reference values
+    # (the FP32 storage offsets), velocities of CFL ~ 0.05 at dt = 1 s
+    "conv_32x32x16": lambda: (small_convection(), lambda ph: inputs.random_state(
+        ph, seed=3, vel=0.1, tracer_means=(ph.t_ref, ph.s_ref))),
+    "conv_ragged_64x32x8": lambda: (small_convection(64, 32, 8), lambda ph: inputs.random_state(
+        ph, seed=4, vel=0.1, tracer_means=(ph.t_ref, ph.s_ref))),
     "conv_96x16x32_linear": lambda: (small_convection(96, 16, 32, nu=1e-3, kappa=2e-3),
                                     lambda ph: inputs.smooth_random_state(ph, seed=5)),
     "box8_none": lambda: (box(8, advection="none", nu=0.05, kappa=0.01, f=0.3),
@@ -89,7 +97,7 @@ def test_tendency_parity(gpu_lib, case, precision):
     for name in m.fields:
         got = m.get_tendency(name)
         err = rel_l2(got, G[name])
-        assert err <= TOL[precision] * (10 if precision == "fp32" else 1), (case, name, err)
+        assert err <= TOL[precision], (case, name, err)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
@@ -133,8 +141,11 @@ def test_rk3_step_parity(gpu_lib, case, dt, nsteps, precision):
         st, _ = timestep.rk3_step(st, dt, ph)
     for name in m.fields:
         ref = fv.interior(st[name], ph, name)
-        err = rel_l2(m.get_state(name), ref)
+        got = m.get_state(name)
+        err = rel_l2(got, ref)
         assert err <= TOL[precision], (case, name, err)
+        check_anomaly(got, ref, fv.interior(timestep.make_state(s, ph)[name], ph, name), nsteps,
+                      ph, name, precision, case)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
@@ -145,23 +156,35 @@ def test_periodic_box_ten_steps(gpu_lib, precision):
     m = gpu_lib.Model(ph, precision)
     m.set_states(s)
     m.rk3_step(0.01, 10)
-    st = timestep.run(timestep.make_state(s, ph), 0.01, 10, ph)
+    st0 = timestep.make_state(s, ph)
+    st = timestep.run(st0, 0.01, 10, ph)
     for name in m.fields:
-        err = rel_l2(m.get_state(name), fv.interior(st[name], ph, name))
+        ref = fv.interior(st[name], ph, name)
+        got = m.get_state(name)
+        err = rel_l2(got, ref)
         assert err <= TOL[precision], (name, err)
+        check_anomaly(got, ref, fv.interior(st0[name], ph, name), 10, ph, name, precision)
 
 
 def test_convection_ten_steps_fp64_and_fp32(gpu_lib):
     """Free convection, 64 x 64 x 32 at 2 m x 2 m x 1 m, 10 steps of 1 s:
-    FP64 and FP32-mixed against the same FP64 oracle run."""
+    FP64 and FP32-mixed against the same FP64 oracle run (per precision, from
+    that precision's initial values).  Velocity noise 0.05 m/s and tracer
+    noise 0.05 (K, g/kg) on the stratified T and uniform S, so every field,
+    S included, changes by percents over the run and its anomaly is held to
+    about 1e-5."""
     ph = small_convection(64, 64, 32)
-    s = inputs.convection_initial(ph, seed=7)
-    st = timestep.run(timestep.make_state(s, ph), 1.0, 10, ph)
-    ref = {n: fv.interior(st[n], ph, n) for n in ("u", "v", "w", "T", "S")}
+    s = inputs.convection_initial(ph, seed=7, noise=0.05, tracer_noise=0.05)
     for precision in ("fp64", "fp32"):
+        s_p = _prep(s, ph, precision)
+        st0 = timestep.make_state(s_p, ph)
+        st = timestep.run(st0, 1.0, 10, ph)
         m = gpu_lib.Model(ph, precision)
-        m.set_states(_prep(s, ph, precision))
+        m.set_states(s_p)
         m.rk3_step(1.0, 10)
         for name in m.fields:
-            err = rel_l2(m.get_state(name), ref[name])
+            ref = fv.interior(st[name], ph, name)
+            got = m.get_state(name)
+            err = rel_l2(got, ref)
             assert err <= TOL[precision], (precision, name, err)
+            check_anomaly(got, ref, fv.interior(st0[name], ph, name), 10, ph, name, precision)
