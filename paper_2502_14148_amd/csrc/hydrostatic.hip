@@ -147,8 +147,8 @@ __device__ inline T rec(T m3, T m2, T m1, T p0, T p1, T p2, T vel, T eps) {
 // Tendency + QAB2 kernel: 32 x 8 column tiles marching up the levels.  At
 // each level the workgroup stages the planes it reads horizontally (T, S
 // with three halo cells, zeta, u, v and w on face k + 1) in LDS (two
-// buffers, so the next level's plane loads need no barrier after the last
-// reads of this one), computes every tracer face flux of the tile once (the
+// buffers: the next level's planes are copied in by the buffer unit while
+// this level computes), computes every tracer face flux of the tile once (the
 // east and north edge faces in a second round by the first wavefront) and
 // then the cell, u-point and v-point tendencies.  Vertical reconstructions
 // use per-thread register windows along z, and the fluxes through the lower
@@ -159,9 +159,6 @@ constexpr int P_ZX = TTX + 5, P_ZY = TTY + 5;       // zeta: [-2, T + 2]
 constexpr int P_UX = TTX + 2, P_UY = TTY + 1;       // u: x in [-1, TTX], y in [-1, TTY)
 constexpr int P_VX = TTX + 1, P_VY = TTY + 2;       // v: x in [-1, TTX), y in [-1, TTY]
 constexpr int P_WX = TTX + 1, P_WY = TTY + 1;       // w: x, y in [-1, T)
-constexpr int O_T = 0, O_S = O_T + P_TX * P_TY, O_Z = O_S + P_TX * P_TY;
-constexpr int O_U = O_Z + P_ZX * P_ZY, O_V = O_U + P_UX * P_UY, O_W = O_V + P_VX * P_VY;
-constexpr int PLANES = O_W + P_WX * P_WY;
 constexpr int F_X = (TTX + 1) * TTY, F_Y = TTX * (TTY + 1);   // per tracer
 
 // Tile of workgroup blockIdx.x: workgroups are dealt round-robin to the 8
@@ -173,71 +170,78 @@ __device__ inline int hydro_tile_index() {
   return x * q + min(x, r) + b / 8;
 }
 
-// Staging of a W x H box of a padded field whose first point is (ia, ja):
-// each thread fetches a fixed number of points into registers (all fetches
-// of a level are in flight together), then stores them to LDS (row length
-// W).  Points past the padded upper edges are not fetched; their LDS entries
-// are never read.
 constexpr int TNT = TTX * TTY;
 
-constexpr int box_n(int w, int h) { return (w * h + TNT - 1) / TNT; }
+// Load-to-LDS copy of a W x H box of a padded field (NT = TNT threads,
+// elements of ES bytes): dword j of the box lands in LDS dword j, copied by
+// the buffer unit itself (one dword per lane, 64 consecutive dwords per
+// wave), so the staging costs neither registers nor vector instructions
+// after the per-lane offsets are set up once per tile.  Full rounds of TNT
+// dwords, then 64-dword chunks dealt to the waves; points past the padded
+// upper edges copy the last valid point into entries that are never read.
+// LEN: the box's padded length in elements.
+template <int W, int H, int ES>
+struct BoxCopy {
+  static constexpr int DPE = ES / 4, D = W * H * DPE;
+  static constexpr int NR = D / TNT, REM = D - NR * TNT, NCH = (REM + 63) / 64;
+  static constexpr int NWV = TNT / 64, MAXC = (NCH + NWV - 1) / NWV;
+  static constexpr int LEN = (NR * TNT + NCH * 64) / DPE;
+  uint32_t off[NR + MAXC];
 
-template <class T, int W, int H>
-__device__ inline void box_fetch(T (&r)[box_n(W, H)], global_ptr<const T> fb, int sy, int imax, int jmax,
-                                 int tid) {
+  // x <= imax and y <= jmax: the box points inside the padded field
+  __device__ inline void init(int sy, int imax, int jmax, int tid, int wave, int lane) {
+    auto at_dword = [&](int j) -> uint32_t {
+      if (j > D - 1) j = D - 1;
+      const int e = j / DPE, half = j - e * DPE;
+      const int y = min(e / W, jmax), x = min(e % W, imax);
+      return (uint32_t)((y * sy + x) * ES + half * 4);
+    };
 #pragma unroll
-  for (int n = 0; n < box_n(W, H); ++n) {
-    const int e = tid + n * TNT;
-    const int x = e % W, y = e / W;
-    r[n] = (e < W * H && x <= imax && y <= jmax) ? at(fb, (unsigned)(y * sy + x) * (unsigned)sizeof(T)) : T(0);
-  }
-}
-
-template <class T, int W, int H>
-__device__ inline void box_store(T* dst, const T (&r)[box_n(W, H)], int tid) {
+    for (int r = 0; r < NR; ++r) off[r] = at_dword(r * TNT + tid);
 #pragma unroll
-  for (int n = 0; n < box_n(W, H); ++n) {
-    const int e = tid + n * TNT;
-    if (e < W * H) dst[e] = r[n];
+    for (int c = 0; c < MAXC; ++c) off[NR + c] = at_dword(NR * TNT + (wave + c * NWV) * 64 + lane);
   }
-}
 
-// The registers of one level's staged planes.
-template <class T>
-struct Stage {
-  T t[box_n(P_TX, P_TY)], s[box_n(P_TX, P_TY)], z[box_n(P_ZX, P_ZY)];
-  T u[box_n(P_UX, P_UY)], v[box_n(P_VX, P_VY)], w[box_n(P_WX, P_WY)];
+  // copy the box whose first point is at `base` into LDS at dst
+  template <class T>
+  __device__ inline void issue(const T* base, T* dst, int wave) const {
+    const __amdgpu_buffer_rsrc_t r =
+        __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)0xFFFFFFFF, 0x00020000);
+#pragma unroll
+    for (int q = 0; q < NR; ++q)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (void*)(dst + (q * TNT + wave * 64) / DPE), 4,
+                                               off[q], 0, 0, 0);
+#pragma unroll
+    for (int c = 0; c < MAXC; ++c) {
+      const int ch = wave + c * NWV;
+      if (ch < NCH)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (void*)(dst + (NR * TNT + ch * 64) / DPE), 4,
+                                                 off[NR + c], 0, 0, 0);
+    }
+  }
 };
 
+// The copies of one level's staged planes (T, S share a shape) and their
+// places in an LDS level buffer.
 template <class T>
-__device__ inline void stage_fetch(Stage<T>& r, const HydroBufs<T>& a, int i0, int j0, int k,
-                                   int tid) {
-  const Dims& d = a.d;
-  const long kz = (long)k * d.sz;
-  // recomputed at every level: hoisting the per-thread offsets and
-  // predicates out of the level loop would hold ~30 more registers
-  asm volatile("" : "+v"(tid));
-  const int ix = d.nx + d.h - 1 - i0, jy = d.ny + d.h - 1 - j0;   // last padded point
-  const int sy = (int)d.sy;
-  const long b3 = pidx(d, i0 - 3, j0 - 3, 0) + kz, b2 = pidx(d, i0 - 2, j0 - 2, 0) + kz;
-  const long b1 = pidx(d, i0 - 1, j0 - 1, 0) + kz;
-  box_fetch<T, P_TX, P_TY>(r.t, uniform_ptr(a.t + b3), sy, ix + 3, jy + 3, tid);
-  box_fetch<T, P_TX, P_TY>(r.s, uniform_ptr(a.s + b3), sy, ix + 3, jy + 3, tid);
-  box_fetch<T, P_ZX, P_ZY>(r.z, uniform_ptr(a.zeta + b2), sy, ix + 2, jy + 2, tid);
-  box_fetch<T, P_UX, P_UY>(r.u, uniform_ptr(a.u + b1), sy, ix + 1, jy + 1, tid);
-  box_fetch<T, P_VX, P_VY>(r.v, uniform_ptr(a.v + b1), sy, ix + 1, jy + 1, tid);
-  box_fetch<T, P_WX, P_WY>(r.w, uniform_ptr(a.w + b1 + d.sz), sy, ix + 1, jy + 1, tid);
-}
+struct StageCopy {
+  static constexpr int ES = (int)sizeof(T);
+  BoxCopy<P_TX, P_TY, ES> ts;
+  BoxCopy<P_ZX, P_ZY, ES> z;
+  BoxCopy<P_UX, P_UY, ES> u;
+  BoxCopy<P_VX, P_VY, ES> v;
+  BoxCopy<P_WX, P_WY, ES> w;
+  static constexpr int L_T = 0, L_S = L_T + BoxCopy<P_TX, P_TY, ES>::LEN;
+  static constexpr int L_Z = L_S + BoxCopy<P_TX, P_TY, ES>::LEN;
+  static constexpr int L_U = L_Z + BoxCopy<P_ZX, P_ZY, ES>::LEN;
+  static constexpr int L_V = L_U + BoxCopy<P_UX, P_UY, ES>::LEN;
+  static constexpr int L_W = L_V + BoxCopy<P_VX, P_VY, ES>::LEN;
+  static constexpr int LEN = L_W + BoxCopy<P_WX, P_WY, ES>::LEN;
+};
 
-template <class T>
-__device__ inline void stage_store(T* S, const Stage<T>& r, int tid) {
-  box_store<T, P_TX, P_TY>(S + O_T, r.t, tid);
-  box_store<T, P_TX, P_TY>(S + O_S, r.s, tid);
-  box_store<T, P_ZX, P_ZY>(S + O_Z, r.z, tid);
-  box_store<T, P_UX, P_UY>(S + O_U, r.u, tid);
-  box_store<T, P_VX, P_VY>(S + O_V, r.v, tid);
-  box_store<T, P_WX, P_WY>(S + O_W, r.w, tid);
-}
+// Wait for this wave's outstanding vector-memory operations (the
+// load-to-LDS copies among them).
+__device__ inline void wait_vm() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
 // FP32: registers capped for five wavefronts per SIMD (a few spilled values,
 // 4 % faster than four wavefronts); FP64 keeps its registers.
@@ -247,7 +251,8 @@ constexpr int hydro_tend_waves() { return sizeof(T) == 4 ? 5 : 1; }
 template <class T, int SCHEME>
 __global__ void __launch_bounds__(TTX * TTY, hydro_tend_waves<T>())
     hydro_tend_kernel(HydroBufs<T> a, HydroStep<T> st) {
-  __shared__ T P[2][PLANES];
+  using SC = StageCopy<T>;
+  __shared__ T P[2][SC::LEN];
   __shared__ T FX[2][F_X];
   __shared__ T FY[2][F_Y];
   const Dims d = a.d;
@@ -323,24 +328,49 @@ __global__ void __launch_bounds__(TTX * TTY, hydro_tend_waves<T>())
   const int lv = (ty + 1) * P_VX + tx + 1;
   const int lw = (ty + 1) * P_WX + tx + 1;
 
-  Stage<T> stg;
-  stage_fetch(stg, a, i0, j0, kb, tid);
+  // load-to-LDS copies of the staged planes: per-lane offsets for this tile
+  // (clamped at the last padded point), then the planes of level kb
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  SC cp;
+  {
+    const int ix = d.nx + d.h - 1 - i0, jy = d.ny + d.h - 1 - j0;   // last padded point
+    const int sy = (int)d.sy;
+    cp.ts.init(sy, ix + 3, jy + 3, tid, wave, lane);
+    cp.z.init(sy, ix + 2, jy + 2, tid, wave, lane);
+    cp.u.init(sy, ix + 1, jy + 1, tid, wave, lane);
+    cp.v.init(sy, ix + 1, jy + 1, tid, wave, lane);
+    cp.w.init(sy, ix + 1, jy + 1, tid, wave, lane);
+  }
+  const long b3 = pidx(d, i0 - 3, j0 - 3, 0), b2 = pidx(d, i0 - 2, j0 - 2, 0);
+  const long b1 = pidx(d, i0 - 1, j0 - 1, 0);
+  auto copy_level = [&](int kk) {
+    T* S = P[kk & 1];
+    const long kz = (long)kk * sz;
+    cp.ts.issue(a.t + b3 + kz, S + SC::L_T, wave);
+    cp.ts.issue(a.s + b3 + kz, S + SC::L_S, wave);
+    cp.z.issue(a.zeta + b2 + kz, S + SC::L_Z, wave);
+    cp.u.issue(a.u + b1 + kz, S + SC::L_U, wave);
+    cp.v.issue(a.v + b1 + kz, S + SC::L_V, wave);
+    cp.w.issue(a.w + b1 + kz + sz, S + SC::L_W, wave);   // w on face k + 1
+  };
+  copy_level(kb);
+  wait_vm();
+  __syncthreads();
   for (int k = kb; k < ke; ++k) {
     T* S = P[k & 1];
     const long kz = (long)k * sz;
-    stage_store(S, stg, tid);
-    __syncthreads();
-    // the next level's planes are fetched while this level computes
-    if (k + 1 < ke) stage_fetch(stg, a, i0, j0, k + 1, tid);
+    // the next level's planes are copied while this level computes (into the
+    // other buffer, whose last readers finished before the previous barrier)
+    if (k + 1 < ke) copy_level(k + 1);
 
     // ---- tracer fluxes through the x faces (west of each column) and the
     // y faces (south of each row) of the tile; then the east and north edge
     // faces by the first wavefront
     {
-      const T* St = S + O_T;
-      const T* Ss = S + O_S;
+      const T* St = S + SC::L_T;
+      const T* Ss = S + SC::L_S;
       if (i <= d.nx && j < d.ny) {
-        const T uf = S[O_U + lu];
+        const T uf = S[SC::L_U + lu];
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
           const T* f = q ? Ss : St;
@@ -350,7 +380,7 @@ __global__ void __launch_bounds__(TTX * TTY, hydro_tend_waves<T>())
         }
       }
       if (i < d.nx && j <= d.ny) {
-        const T vf = S[O_V + lv];
+        const T vf = S[SC::L_V + lv];
         const bool open = j > 0 && j < d.ny;
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
@@ -365,7 +395,7 @@ __global__ void __launch_bounds__(TTX * TTY, hydro_tend_waves<T>())
         if (tid < TTY) {           // x face i0 + TTX of row j0 + tid
           const int ey = tid;
           if (i0 + TTX <= d.nx && j0 + ey < d.ny) {
-            const T uf = S[O_U + (ey + 1) * P_UX + TTX + 1];
+            const T uf = S[SC::L_U + (ey + 1) * P_UX + TTX + 1];
             const int le = (ey + 3) * P_TX + TTX + 3;
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
@@ -379,7 +409,7 @@ __global__ void __launch_bounds__(TTX * TTY, hydro_tend_waves<T>())
           const int ex = tid - TTY;
           const int jf = j0 + TTY;
           if (jf <= d.ny && i0 + ex < d.nx) {
-            const T vf = S[O_V + (TTY + 1) * P_VX + ex + 1];
+            const T vf = S[SC::L_V + (TTY + 1) * P_VX + ex + 1];
             const int le = (TTY + 3) * P_TX + ex + 3;
             const bool open = jf < d.ny;
             const T Ay = (T)m.dxf[jf + d.h] * dz;
@@ -398,10 +428,10 @@ __global__ void __launch_bounds__(TTX * TTY, hydro_tend_waves<T>())
     __syncthreads();
 
     if (active) {
-      const T* U = S + O_U;
-      const T* V = S + O_V;
-      const T* Z = S + O_Z;
-      const T* Wp = S + O_W;
+      const T* U = S + SC::L_U;
+      const T* V = S + SC::L_V;
+      const T* Z = S + SC::L_Z;
+      const T* Wp = S + SC::L_W;
       const T w_c = Wp[lw];
       const T Wu1 = T(0.5) * (Wp[lw - 1] + w_c);
       const T Wv1 = vpt ? T(0.5) * (Wp[lw - P_WX] + w_c) : T(0);
@@ -501,6 +531,10 @@ __global__ void __launch_bounds__(TTX * TTY, hydro_tend_waves<T>())
         sw[5] = at(uniform_ptr(a.s + kn), cb);
       }
     }
+    // the copies of level k + 1 have landed (this wave's), and every wave is
+    // done with this level's planes and flux arrays
+    wait_vm();
+    __syncthreads();
   }
   if (active) {
     // partial column sums of this chunk (the lower chunk's into gub, gvb)

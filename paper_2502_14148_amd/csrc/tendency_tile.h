@@ -49,6 +49,42 @@
 namespace oc {
 namespace tz {
 
+// ---- buffer addressing -----------------------------------------------------
+// One buffer resource spans all fields of a model (byte offsets below 4 GiB
+// from FieldSet::base): loads and stores take a per-lane 32-bit offset (the
+// column, fixed over the march) and a wave-uniform one (field and level), so
+// no per-lane 64-bit address arithmetic is spent on them.  Whole planes of a
+// level are copied into LDS by the buffer unit itself (load-to-LDS), one
+// dword per lane, 64 consecutive dwords per wave, while the previous level is
+// being computed.
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+__device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const char* base) {
+  // raw buffer, no stride, the whole 32-bit range; word 3 as for every gfx9
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(base), (short)0, (int)0xFFFFFFFF,
+                                           0x00020000);
+}
+
+template <class T>
+__device__ inline T bload(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  if constexpr (sizeof(T) == 4)
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+  else
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+
+template <class T>
+__device__ inline void bstore(T v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  if constexpr (sizeof(T) == 4)
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, voff, soff, 0);
+  else
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
+}
+
+// Wait for this wave's outstanding vector-memory operations (the load-to-LDS
+// copies among them).
+__device__ inline void wait_vm() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
 // advective flux vel * W(q) with q read from LDS at q[L + o*s], o = -R..R-1
 template <class T, int SCHEME, int R>
 __device__ inline T flux_lds(const T* q, int L, int s, T vel, T eps) {
@@ -106,18 +142,12 @@ __device__ inline void slot_fluxes(T* S, const SlotOff& o, int L, int sd, int se
     const T adv = interp_lds<T, R>(vd, L, sd);
     S[o.Fself + fi] = flux_lds<T, SCHEME, R>(vd, L, sd, adv, eps) - nu * (vd[L] - vd[L - sd]) * rd;
   }
-#if OC_TEND_FLUXBAR
-  __builtin_amdgcn_sched_barrier(0);
-#endif
   {
     const T* vd = S + o.vd;
     const T* ve = S + o.ve;
     const T adv = interp_lds<T, R>(vd, L, se);
     S[o.Fcross + fi] = flux_lds<T, SCHEME, R>(ve, L, sd, adv, eps) - nu * (ve[L] - ve[L - sd]) * rd;
   }
-#if OC_TEND_FLUXBAR
-  __builtin_amdgcn_sched_barrier(0);
-#endif
   {
     const T adv = S[o.az + fi];
     const T* wk = S + o.wk;
@@ -127,14 +157,30 @@ __device__ inline void slot_fluxes(T* S, const SlotOff& o, int L, int sd, int se
   const T kap = IMM ? kappa * (S[om + L] * S[om + L - sd]) : kappa;
 #pragma unroll
   for (int q = 0; q < NTR; ++q) {
-#if OC_TEND_FLUXBAR
-    __builtin_amdgcn_sched_barrier(0);
-#endif
     const T* c = S + o.c0 + q * PL;
     S[o.Fc0 + q * o.Fstride + fi] =
         flux_lds<T, SCHEME, R>(c, L, sd, un, eps) - kap * (c[L] - c[L - sd]) * rd;
   }
 }
+
+// Shape of the load-to-LDS copy of one (TX + 2R) x (TY + 2R) plane of
+// elements of ES bytes by NT threads: NR rounds in which every lane copies one
+// dword, then NCH chunks of 64 dwords, chunk c copied by wave c % (NT / 64)
+// (lanes past the plane copy its last dword into the padding).  PLP: the
+// plane's padded length in elements.
+template <int PX, int PY, int NT, int ES>
+struct PlaneCopy {
+  static constexpr int DPE = ES / 4;
+  static constexpr int PLD = PX * PY * DPE;
+  static constexpr int NR = PLD / NT;
+  static constexpr int REM = PLD - NR * NT;
+  static constexpr int NCH = (REM + 63) / 64;
+  static constexpr int NWV = NT / 64;
+  static constexpr int MAXC = (NCH + NWV - 1) / NWV;   // chunks per wave, at most
+  static constexpr int PLP = (NR * NT + NCH * 64) / DPE;
+  static_assert(NT % 64 == 0, "whole wavefronts");
+  static_assert((NR * NT + NCH * 64) % DPE == 0, "whole elements");
+};
 
 // One column tile: tile b of an nbx x nby x nbz decomposition (k chunks of
 // kc levels) of the grid d, whose halo width d.h is at least R.
@@ -144,27 +190,36 @@ __device__ inline void slot_fluxes(T* S, const SlotOff& o, int L, int sd, int se
 // IMM: grid-fitted immersed boundary (fs.mask, 1 in fluid cells): zero
 // velocity tendencies on faces next to an immersed cell, no diffusive tracer
 // flux through them, no top flux into an immersed top cell.
+//
+// LDS: the planes of level k (u, v, the tracers, the mask) in one of two
+// buffers by the parity of k, w in a ring of three (levels k, k + 1 in use,
+// k + 2 being copied), the z-interpolated u at x faces and v at y faces, the
+// edge rings, and the x- and y-face flux arrays.  The copies of level k + 1
+// (w: k + 2) are issued when level k starts and are waited for at its end,
+// where the face velocities of level k + 1 are also written: two barriers
+// per level (fluxes -> tendencies, level -> next level).
 template <class T, int SCHEME, int NTR, int TX, int TY, int R, bool CLO = false,
           bool IMM = false>
 __device__ __attribute__((always_inline)) inline void tendency_tile(
     const Dims& d, const FieldSet<T>& fs, const TendParams<T>& P, int nbx, int nby, int nbz,
     int kc, int b) {
   constexpr int NT = TX * TY;
-  constexpr int PX = TX + 2 * R, PY = TY + 2 * R, PL = PX * PY;
+  constexpr int ES = (int)sizeof(T);
+  constexpr int PX = TX + 2 * R, PY = TY + 2 * R;
+  using PC = PlaneCopy<PX, PY, NT, ES>;
+  constexpr int PLP = PC::PLP;
   constexpr int NXS = (TX + 1) * TY, NYS = TX * (TY + 1);
   constexpr int NF = 3 + NTR;
-  constexpr int NFILL = (PL + NT - 1) / NT;
   constexpr int NW = 2 * R;            // register window: levels k-R+1 .. k+R
   constexpr int NI = 2 * R - 2;        // levels of the z interpolation to face k
   constexpr int NE = TX + TY;          // edge columns (x) and rows (y)
   constexpr int NRING = (R == 3) ? 4 : 8;
   static_assert(NRING >= NI, "edge ring too short");
-  // LDS map: u, v (level k), w (levels k, k+1), tracers (level k), the
-  // z-interpolated u at x faces and v at y faces, the edge rings, then the
-  // x-face fluxes (NF arrays of NXS) and y-face fluxes (NF arrays of NYS)
-  constexpr int OU = 0, OV = PL, OW = 2 * PL, OC = 4 * PL;
-  constexpr int OM = (4 + NTR) * PL;   // mask plane (level k), IMM only
-  constexpr int OAX = (4 + NTR + (IMM ? 1 : 0)) * PL, OAY = OAX + NXS;
+  constexpr int NPL = 2 + NTR + (IMM ? 1 : 0);   // planes per level buffer
+  // LDS map (elements)
+  constexpr int OLB = 0;                         // 2 level buffers of NPL planes
+  constexpr int OWR = 2 * NPL * PLP;             // w ring of 3 planes
+  constexpr int OAX = OWR + 3 * PLP, OAY = OAX + NXS;
   constexpr int OER = OAY + NYS;
   constexpr int OFX = OER + NRING * NE, OFY = OFX + NF * NXS;
   constexpr int NLDS = OFY + NF * NYS;
@@ -178,101 +233,146 @@ __device__ __attribute__((always_inline)) inline void tendency_tile(
   const int ke = min(kb + kc, d.nz);
 
   const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int tx = tid % TX, ty = tid / TX;
   const int gi = i0 + tx, gj = j0 + ty;
   const int Lc = (ty + R) * PX + (tx + R);  // own position in an LDS plane
   const T eps = P.eps;
-  const long sz = d.sz;
   const int sy = (int)d.sy;
   const int hh = d.h;
+  const uint32_t lvb = (uint32_t)d.sz * ES;     // bytes per level
+  const __amdgpu_buffer_rsrc_t rs = make_rsrc(fs.base);
 
-  // 32-bit offsets of the plane elements this thread loads, relative to the
-  // tile corner (i0-R, j0-R) of a level; the same for every level
-  int goff[NFILL];
-#pragma unroll
-  for (int r = 0; r < NFILL; ++r) {
-    const int e = tid + r * NT;
+  // per-lane byte offsets of the copied plane dwords, relative to the tile
+  // corner (i0-R, j0-R) of a level: the same for every field and level
+  auto dword_off = [&](int j) -> uint32_t {
+    if (j > PC::PLD - 1) j = PC::PLD - 1;
+    const int e = j / PC::DPE, half = j - e * PC::DPE;
     const int ly = e / PX, lx = e - ly * PX;
-    goff[r] = ly * sy + lx;
-  }
-  const long corner = (long)(j0 - R + hh) * sy + (i0 - R + hh);
-  auto fill = [&](int dst, const T* __restrict__ src, int kk) {
-    const T* __restrict__ base = src + (long)(kk + hh) * sz + corner;
+    return (uint32_t)((ly * sy + lx) * ES + half * 4);
+  };
+  uint32_t goff[PC::NR + PC::MAXC];
 #pragma unroll
-    for (int r = 0; r < NFILL; ++r) {
-      const int e = tid + r * NT;
-      if (PL % NT == 0 || e < PL) S[dst + e] = base[goff[r]];
+  for (int r = 0; r < PC::NR; ++r) goff[r] = dword_off(r * NT + tid);
+#pragma unroll
+  for (int c = 0; c < PC::MAXC; ++c)
+    goff[PC::NR + c] = dword_off(PC::NR * NT + (wave + c * PC::NWV) * 64 + lane);
+  const uint32_t corner = (uint32_t)(((j0 - R + hh) * sy + (i0 - R + hh)) * ES);
+  // copy plane `src` (byte offset of the field) at level kk into LDS plane dst
+  auto copy_plane = [&](int dst, uint32_t src, int kk) {
+    const uint32_t so = src + (uint32_t)(kk + hh) * lvb + corner;
+#pragma unroll
+    for (int r = 0; r < PC::NR; ++r)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (void*)(S + dst + (r * NT + wave * 64) / PC::DPE),
+                                               4, goff[r], so, 0, 0);
+#pragma unroll
+    for (int c = 0; c < PC::MAXC; ++c) {
+      const int ch = wave + c * PC::NWV;
+      if (ch < PC::NCH)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(
+            rs, (void*)(S + dst + (PC::NR * NT + ch * 64) / PC::DPE), 4, goff[PC::NR + c], so, 0,
+            0);
     }
   };
-  auto rw = [](int kk) { return OW + (kk & 1) * PL; };
+  auto lbuf = [](int kk) { return OLB + (kk & 1) * NPL * PLP; };
+  auto wring = [](int kk) { return OWR + (kk % 3) * PLP; };
+  // planes of level kk (u, v, tracers, mask) into its buffer
+  auto copy_level = [&](int kk) {
+    const int lb = lbuf(kk);
+    copy_plane(lb, fs.oin[0], kk);
+    copy_plane(lb + PLP, fs.oin[1], kk);
+#pragma unroll
+    for (int q = 0; q < NTR; ++q) copy_plane(lb + (2 + q) * PLP, fs.oin[3 + q], kk);
+    if (IMM) copy_plane(lb + (2 + NTR) * PLP, fs.omask, kk);
+  };
 
-  const T* __restrict__ gu = fs.in[0];
-  const T* __restrict__ gv = fs.in[1];
-  const T* __restrict__ gw = fs.in[2];
+  // own column: byte offset within a level
+  const uint32_t col = (uint32_t)(((gj + hh) * sy + (gi + hh)) * ES);
+  auto lvl = [&](int kk) { return (uint32_t)(kk + hh) * lvb; };
 
   // ---- edge rings: thread e < TY owns the u column right of the tile (row
   // j0+e), thread TY <= e < NE the v row above it (column i0+e-TY); each
   // keeps levels k-R+1 .. k+R-2 of it in a private LDS ring
   const bool edge = tid < NE;
-  const T* __restrict__ ecol = nullptr;
+  uint32_t ecol = 0;   // field and column byte offset (per lane), level 0
   if (edge) {
-    ecol = (tid < TY) ? gu + ((long)(j0 + tid + hh) * sy + (i0 + TX + hh))
-                      : gv + ((long)(j0 + TY + hh) * sy + (i0 + tid - TY + hh));
+    ecol = (tid < TY) ? fs.oin[0] + (uint32_t)(((j0 + tid + hh) * sy + (i0 + TX + hh)) * ES)
+                      : fs.oin[1] + (uint32_t)(((j0 + TY + hh) * sy + (i0 + tid - TY + hh)) * ES);
   }
   auto ering = [&](int kk) { return OER + (kk & (NRING - 1)) * NE + tid; };
 
   // ---- register windows: levels k-R+1..k+R of the own column (index o is
   // level k-R+1+o)
-  const int col = (gj + hh) * sy + (gi + hh);   // offset within a level
   T wu[NW], wv[NW], ww[NW], wc[NTR][NW];
 #pragma unroll
   for (int o = 0; o < NW; ++o) {
-    const long lv = (long)(kb - R + 1 + o + hh) * sz;
-    wu[o] = (gu + lv)[col];
-    wv[o] = (gv + lv)[col];
-    ww[o] = (gw + lv)[col];
+    const uint32_t lv = lvl(kb - R + 1 + o);
+    wu[o] = bload<T>(rs, col, fs.oin[0] + lv);
+    wv[o] = bload<T>(rs, col, fs.oin[1] + lv);
+    ww[o] = bload<T>(rs, col, fs.oin[2] + lv);
 #pragma unroll
-    for (int q = 0; q < NTR; ++q) wc[q][o] = (fs.in[3 + q] + lv)[col];
+    for (int q = 0; q < NTR; ++q) wc[q][o] = bload<T>(rs, col, fs.oin[3 + q] + lv);
   }
   if (edge) {
 #pragma unroll
     for (int o = 0; o < NI - 1; ++o) {
       const int kk = kb - R + 1 + o;
-      S[ering(kk)] = ecol[(long)(kk + hh) * sz];
+      S[ering(kk)] = bload<T>(rs, ecol, lvl(kk));
     }
   }
   // immersed boundary: the own column's mask at levels k-1, k, k+1
   T mkm = T(1), mk0 = T(1), mkp = T(1);
   if (IMM) {
-    mkm = (fs.mask + (long)(kb - 1 + hh) * sz)[col];
-    mk0 = (fs.mask + (long)(kb + hh) * sz)[col];
-    mkp = (fs.mask + (long)(kb + 1 + hh) * sz)[col];
+    mkm = bload<T>(rs, col, fs.omask + lvl(kb - 1));
+    mk0 = bload<T>(rs, col, fs.omask + lvl(kb));
+    mkp = bload<T>(rs, col, fs.omask + lvl(kb + 1));
   }
 
-  // ---- prologue: w at level kb
-  fill(rw(kb), gw, kb);
+  // u and v interpolated in z to face kk (levels kk-R+1 .. kk+R-2): own
+  // column from the register window, edge columns from their rings (the
+  // ring already holds level kk+R-2)
+  auto face_velocities = [&](int kk) {
+    S[OAX + ty * (TX + 1) + tx] = interpc<T, R>(wu);
+    S[OAY + ty * TX + tx] = interpc<T, R>(wv);
+    if (edge) {
+      T a[NI];
+#pragma unroll
+      for (int o = 0; o < NI; ++o) a[o] = S[ering(kk - R + 1 + o)];
+      const int fi = (tid < TY) ? OAX + tid * (TX + 1) + TX : OAY + TY * TX + (tid - TY);
+      S[fi] = interpc<T, R>(a);
+    }
+  };
+
+  // ---- prologue: the planes of level kb, w at kb and kb + 1, and the
+  // face velocities of level kb
+  copy_level(kb);
+  copy_plane(wring(kb), fs.oin[2], kb);
+  copy_plane(wring(kb + 1), fs.oin[2], kb + 1);
+  if (edge) S[ering(kb + R - 2)] = bload<T>(rs, ecol, lvl(kb + R - 2));
+  face_velocities(kb);
+  wait_vm();
   __syncthreads();
 
   // bottom z fluxes of the first level (face kb; w: centre kb-1), from the
   // levels kb-R..kb+R-1
   T fzb_u, fzb_v, fzb_w, fzb_c[NTR];
   {
-    const long lv = (long)(kb - R + hh) * sz;
-    const T* wp = S + rw(kb);
+    const uint32_t lv = lvl(kb - R);
+    const T* wp = S + wring(kb);
     const bool wall = d.zb && kb == 0;
     T z[NW];
     const T wt_u = interp_lds<T, R>(wp, Lc, 1);
     const T wt_v = interp_lds<T, R>(wp, Lc, PX);
     const T rzb = P.rdzf[kb];  // face kb
-    z[0] = (gu + lv)[col];
+    z[0] = bload<T>(rs, col, fs.oin[0] + lv);
 #pragma unroll
     for (int o = 1; o < NW; ++o) z[o] = wu[o - 1];
     fzb_u = wall ? T(0) : flux_reg<T, SCHEME, R>(z, wt_u, eps) - P.nuz * (z[R] - z[R - 1]) * rzb;
-    z[0] = (gv + lv)[col];
+    z[0] = bload<T>(rs, col, fs.oin[1] + lv);
 #pragma unroll
     for (int o = 1; o < NW; ++o) z[o] = wv[o - 1];
     fzb_v = wall ? T(0) : flux_reg<T, SCHEME, R>(z, wt_v, eps) - P.nuz * (z[R] - z[R - 1]) * rzb;
-    z[0] = (gw + lv)[col];
+    z[0] = bload<T>(rs, col, fs.oin[2] + lv);
 #pragma unroll
     for (int o = 1; o < NW; ++o) z[o] = ww[o - 1];
     const T wb = interpc<T, R>(z + 1);
@@ -280,7 +380,7 @@ __device__ __attribute__((always_inline)) inline void tendency_tile(
     const T wface = z[R];
 #pragma unroll
     for (int q = 0; q < NTR; ++q) {
-      z[0] = (fs.in[3 + q] + lv)[col];
+      z[0] = bload<T>(rs, col, fs.oin[3 + q] + lv);
 #pragma unroll
       for (int o = 1; o < NW; ++o) z[o] = wc[q][o - 1];
       fzb_c[q] = wall ? T(0)
@@ -290,43 +390,54 @@ __device__ __attribute__((always_inline)) inline void tendency_tile(
   }
 
   for (int k = kb; k < ke; ++k) {
-    __syncthreads();  // consumers of the previous level are done
-    fill(OU, gu, k);
-    fill(OV, gv, k);
-    fill(rw(k + 1), gw, k + 1);
+    // The planes of level k and w at k, k + 1 are in LDS (waited for at the
+    // end of the previous level).  Loads are issued in the order they are
+    // needed (vector-memory loads complete in issue order): the edge column
+    // of this level, the previous tendencies and closure tendencies of this
+    // level, the own column's next level, then the copies for level k + 1.
+    const bool more = k + 1 < ke;
+    const uint32_t lv = lvl(k);
+    T enext = T(0);
+    if (edge && more) enext = bload<T>(rs, ecol, lvl(k + R - 1));
+    T gprev[NF], gclo[NF];
 #pragma unroll
-    for (int q = 0; q < NTR; ++q) fill(OC + q * PL, fs.in[3 + q], k);
-    if (IMM) fill(OM, fs.mask, k);
-    // u and v interpolated in z to face k (levels k-R+1 .. k+R-2): own
-    // column from the register window, edge columns from their rings
-    S[OAX + ty * (TX + 1) + tx] = interpc<T, R>(wu);
-    S[OAY + ty * TX + tx] = interpc<T, R>(wv);
-    if (edge) {
-      S[ering(k + R - 2)] = ecol[(long)(k + R - 2 + hh) * sz];
-      T a[NI];
-#pragma unroll
-      for (int o = 0; o < NI; ++o) a[o] = S[ering(k - R + 1 + o)];
-      const int fi = (tid < TY) ? OAX + tid * (TX + 1) + TX : OAY + TY * TX + (tid - TY);
-      S[fi] = interpc<T, R>(a);
+    for (int f = 0; f < NF; ++f) {
+      gprev[f] = (P.combine && P.stage > 0) ? bload<T>(rs, col, fs.oG[f] + lv) : T(0);
+      gclo[f] = (CLO && fs.closure[f]) ? bload<T>(rs, col, fs.oclo[f] + lv) : T(0);
     }
-    __syncthreads();
-
-    // ---- x and y face fluxes
+    T nu_ = T(0), nv_ = T(0), nw_ = T(0), nc_[NTR];
+    T nmk = T(1);
+    if (more) {
+      const uint32_t ln = lvl(k + R + 1);
+      nu_ = bload<T>(rs, col, fs.oin[0] + ln);
+      nv_ = bload<T>(rs, col, fs.oin[1] + ln);
+      nw_ = bload<T>(rs, col, fs.oin[2] + ln);
+#pragma unroll
+      for (int q = 0; q < NTR; ++q) nc_[q] = bload<T>(rs, col, fs.oin[3 + q] + ln);
+      if (IMM) nmk = bload<T>(rs, col, fs.omask + lvl(k + 2));
+      copy_level(k + 1);
+      copy_plane(wring(k + 2), fs.oin[2], k + 2);
+    }
+    const int lb = lbuf(k);
+    const int OU = lb, OV = lb + PLP, OC = lb + 2 * PLP, OM = lb + (2 + NTR) * PLP;
+    const int OWk = wring(k), OWk1 = wring(k + 1);
+    // ---- x and y face fluxes (the face velocities of level k were written
+    // before the barrier that ended the previous level)
     SlotOff ox, oy;
     ox.vd = OU; ox.ve = OV; ox.az = OAX;
-    ox.wk = rw(k); ox.c0 = OC;
+    ox.wk = OWk; ox.c0 = OC;
     ox.Fself = OFX + 0 * NXS; ox.Fcross = OFX + 1 * NXS; ox.Fw = OFX + 2 * NXS;
     ox.Fc0 = OFX + 3 * NXS; ox.Fstride = NXS;
     oy.vd = OV; oy.ve = OU; oy.az = OAY;
-    oy.wk = rw(k); oy.c0 = OC;
+    oy.wk = OWk; oy.c0 = OC;
     oy.Fself = OFY + 1 * NYS; oy.Fcross = OFY + 0 * NYS; oy.Fw = OFY + 2 * NYS;
     oy.Fc0 = OFY + 3 * NYS; oy.Fstride = NYS;
     // main rounds: the left x face and the bottom y face of the own cell
-    slot_fluxes<T, SCHEME, NTR, PL, R, IMM>(S, ox, Lc, 1, PX, ty * (TX + 1) + tx, P.rdx, P.nu,
-                                            P.kappa, eps, OM);
+    slot_fluxes<T, SCHEME, NTR, PLP, R, IMM>(S, ox, Lc, 1, PX, ty * (TX + 1) + tx, P.rdx, P.nu,
+                                             P.kappa, eps, OM);
     __builtin_amdgcn_sched_barrier(0);
-    slot_fluxes<T, SCHEME, NTR, PL, R, IMM>(S, oy, Lc, PX, 1, ty * TX + tx, P.rdy, P.nu, P.kappa,
-                                            eps, OM);
+    slot_fluxes<T, SCHEME, NTR, PLP, R, IMM>(S, oy, Lc, PX, 1, ty * TX + tx, P.rdy, P.nu,
+                                             P.kappa, eps, OM);
     __builtin_amdgcn_sched_barrier(0);
     // edge round: right x faces of the last column, top y faces of the last row
     if (edge) {
@@ -339,8 +450,8 @@ __device__ __attribute__((always_inline)) inline void tendency_tile(
       oe.Fself = xs ? ox.Fself : oy.Fself; oe.Fcross = xs ? ox.Fcross : oy.Fcross;
       oe.Fw = xs ? ox.Fw : oy.Fw; oe.Fc0 = xs ? ox.Fc0 : oy.Fc0;
       oe.Fstride = xs ? NXS : NYS;
-      slot_fluxes<T, SCHEME, NTR, PL, R, IMM>(S, oe, L, xs ? 1 : PX, xs ? PX : 1, fi,
-                                              xs ? P.rdx : P.rdy, P.nu, P.kappa, eps, OM);
+      slot_fluxes<T, SCHEME, NTR, PLP, R, IMM>(S, oe, L, xs ? 1 : PX, xs ? PX : 1, fi,
+                                               xs ? P.rdx : P.rdy, P.nu, P.kappa, eps, OM);
     }
 
     // ---- z fluxes through the top face of level k (w: at centre k)
@@ -350,7 +461,7 @@ __device__ __attribute__((always_inline)) inline void tendency_tile(
     const T rzft = P.rdzf[k + 1], rzc = P.rdzc[k], rzf = P.rdzf[k];
     T fzt_u, fzt_v, fzt_w, fzt_c[NTR];
     {
-      const T* wp = S + rw(k + 1);
+      const T* wp = S + OWk1;
       const T wt_u = interp_lds<T, R>(wp, Lc, 1);
       const T wt_v = interp_lds<T, R>(wp, Lc, PX);
       fzt_u = top_wall ? T(0)
@@ -403,12 +514,10 @@ __device__ __attribute__((always_inline)) inline void tendency_tile(
 #pragma unroll
       for (int q = 0; q < NTR; ++q) G[3 + q] += -(fzt_c[q] - fzb_c[q]) * rzc - P.toff[q] * divu;
 
-      const long lv = (long)(k + hh) * sz;
 #pragma unroll
       for (int f = 0; f < NF; ++f) {
         // plus the closure tendency computed beforehand
-        const T g = (CLO && fs.closure[f]) ? G[f] + (fs.closure[f] + lv)[col] : G[f];
-        T* __restrict__ Gf = fs.G[f] + lv;
+        const T g = (CLO && fs.closure[f]) ? G[f] + gclo[f] : G[f];
         if (P.combine) {
           T x;
           if (f == 0) x = wu[R - 1];
@@ -416,16 +525,16 @@ __device__ __attribute__((always_inline)) inline void tendency_tile(
           else if (f == 2) x = ww[R - 1];
           else x = wc[f - 3][R - 1];
           T incr = P.gam * g;
-          if (P.stage > 0) incr -= P.zet * Gf[col];
+          if (P.stage > 0) incr -= P.zet * gprev[f];
           x = x + P.dt * incr;
           if (f == 2 && bottom_wall) x = T(0);
+          bstore<T>(x, rs, col, fs.oout[f] + lv);
+          // tracers: final values, so their halo images too
           if (f >= 3 && P.images)
-            store_with_images(fs.out[f], d, gi, gj, k, x, false);  // tracers: final values
-          else
-            (fs.out[f] + lv)[col] = x;
-          if (P.stage < 2) Gf[col] = g;
+            store_with_images((T*)(fs.base + fs.oout[f]), d, gi, gj, k, x, false, false);
+          if (P.stage < 2) bstore<T>(g, rs, col, fs.oG[f] + lv);
         } else {
-          Gf[col] = g;
+          bstore<T>(g, rs, col, fs.oG[f] + lv);
         }
       }
     }
@@ -436,13 +545,12 @@ __device__ __attribute__((always_inline)) inline void tendency_tile(
     fzb_w = fzt_w;
 #pragma unroll
     for (int q = 0; q < NTR; ++q) fzb_c[q] = fzt_c[q];
-    if (IMM && k + 1 < ke) {
-      mkm = mk0;
-      mk0 = mkp;
-      mkp = (fs.mask + (long)(k + 2 + hh) * sz)[col];
-    }
-    if (k + 1 < ke) {
-      const long lv = (long)(k + R + 1 + hh) * sz;
+    if (more) {
+      if (IMM) {
+        mkm = mk0;
+        mk0 = mkp;
+        mkp = nmk;
+      }
 #pragma unroll
       for (int o = 0; o < NW - 1; ++o) {
         wu[o] = wu[o + 1];
@@ -451,12 +559,20 @@ __device__ __attribute__((always_inline)) inline void tendency_tile(
 #pragma unroll
         for (int q = 0; q < NTR; ++q) wc[q][o] = wc[q][o + 1];
       }
-      wu[NW - 1] = (gu + lv)[col];
-      wv[NW - 1] = (gv + lv)[col];
-      ww[NW - 1] = (gw + lv)[col];
+      wu[NW - 1] = nu_;
+      wv[NW - 1] = nv_;
+      ww[NW - 1] = nw_;
 #pragma unroll
-      for (int q = 0; q < NTR; ++q) wc[q][NW - 1] = (fs.in[3 + q] + lv)[col];
+      for (int q = 0; q < NTR; ++q) wc[q][NW - 1] = nc_[q];
+      // the face velocities of level k + 1 (every reader of level k's passed
+      // the barrier before the tendencies)
+      if (edge) S[ering(k + R - 1)] = enext;
+      face_velocities(k + 1);
     }
+    // the copies of level k + 1 have landed (this wave's), and every wave is
+    // done with the planes of level k
+    wait_vm();
+    __syncthreads();
   }
 }
 
@@ -494,6 +610,8 @@ hipError_t launch_tendency_radius(const Dims& d, const FieldSet<T>& fs, const Te
   if (kc > d.nz) kc = d.nz;
   const int nbz = (d.nz + kc - 1) / kc;
   const dim3 grid(nbx * nby * nbz);
+  FieldSet<T> fb = fs;
+  if (!fieldset_offsets(fb, (uint64_t)padded_elems(d) * sizeof(T))) return hipErrorInvalidValue;
   bool clo = false;
   for (int f = 0; f < MAXF; ++f) clo = clo || fs.closure[f] != nullptr;
   const bool imm = fs.mask != nullptr;
@@ -502,13 +620,13 @@ hipError_t launch_tendency_radius(const Dims& d, const FieldSet<T>& fs, const Te
   if (imm) {                                                                                  \
     if constexpr (R == 3)                                                                     \
       hipLaunchKernelGGL((tz::tendency_zmarch<T, SCH, NTR_, TX_, TY_, R, false, true>), grid,  \
-                         dim3(TX_ * TY_), 0, s, d, fs, p, nbx, nby, nbz, kc);                 \
+                         dim3(TX_ * TY_), 0, s, d, fb, p, nbx, nby, nbz, kc);                 \
   } else if (clo)                                                                             \
     hipLaunchKernelGGL((tz::tendency_zmarch<T, SCH, NTR_, TX_, TY_, R, true>), grid,           \
-                       dim3(TX_ * TY_), 0, s, d, fs, p, nbx, nby, nbz, kc);                   \
+                       dim3(TX_ * TY_), 0, s, d, fb, p, nbx, nby, nbz, kc);                   \
   else                                                                                        \
     hipLaunchKernelGGL((tz::tendency_zmarch<T, SCH, NTR_, TX_, TY_, R, false>), grid,          \
-                       dim3(TX_ * TY_), 0, s, d, fs, p, nbx, nby, nbz, kc)
+                       dim3(TX_ * TY_), 0, s, d, fb, p, nbx, nby, nbz, kc)
 #define OC_TZ_NTR(SCH, TX_, TY_)                \
   switch (p.ntr) {                              \
     case 1: OC_TZ(SCH, 1, TX_, TY_); break;     \

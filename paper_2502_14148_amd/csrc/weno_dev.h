@@ -25,6 +25,9 @@ __device__ inline double rcp(double x) {
   return __builtin_fma(r, e, r);
 }
 
+__device__ inline float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ inline double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 template <class T>
 __device__ inline T interp4(T a0, T a1, T a2, T a3) {
   return ((a1 + a2) * T(7) - (a0 + a3)) * T(1.0 / 12.0);
@@ -32,6 +35,22 @@ __device__ inline T interp4(T a0, T a1, T a2, T a3) {
 
 // Reconstruction at the interface between q_{-1} and q_0 from the six values
 // q_{-3..2}; `vel` selects the upwind side.
+//
+// WENO-Z form used here (equal to the textbook form in exact arithmetic):
+// with the upwind-ordered stencil (a, b, c, d, e) and its differences
+// d1 = b - a, ..., d4 = e - d,
+//   * candidates as deviations from the upwind neighbour c:
+//       r0 - c = (5 d2 - 2 d1)/6, r1 - c = (d2 + 2 d3)/6, r2 - c = (4 d3 - d4)/6;
+//   * four times the Jiang-Shu indicators plus eps:
+//       s_k = 13/3 t_k^2 + u_k^2 + 4 eps, t = (d2 - d1, d3 - d2, d4 - d3),
+//       u = (3 d2 - d1, d2 + d3, d4 - 3 d3)
+//     (the weights only see ratios, so the common factor 4 drops out);
+//   * WENO-Z weights d_k (1 + (tau / s_k)^2), tau = |s_0 - s_2|, multiplied
+//     through by s_1^2:  a_k = s_1^2 + (tau s_1 / s_k)^2, a_1 = s_1^2 + tau^2,
+//     so two reciprocals (of s_0 and s_2) replace three;
+//   * W = c + sum d_k a_k (r_k - c) / sum d_k a_k.
+// FP32 range: tau s_1 / s_k stays below 1.8e19 for indicators up to ~1e2 in
+// the field's units squared next to an exactly flat stencil.
 template <class T, int SCHEME>
 __device__ inline T rec6(T m3, T m2, T m1, T p0, T p1, T p2, T vel, T eps) {
   const bool pos = vel > T(0);
@@ -42,21 +61,27 @@ __device__ inline T rec6(T m3, T m2, T m1, T p0, T p1, T p2, T vel, T eps) {
   const T e = pos ? p1 : m2;
   if (SCHEME == SCHEME_LINEAR)
     return (T(2) * a - T(13) * b + T(47) * c + T(27) * d - T(3) * e) * T(1.0 / 60.0);
-  const T r0 = T(2) * a - T(7) * b + T(11) * c;
-  const T r1 = -b + T(5) * c + T(2) * d;
-  const T r2 = T(2) * c + T(5) * d - e;
-  const T t0 = a - T(2) * b + c, u0 = a - T(4) * b + T(3) * c;
-  const T t1 = b - T(2) * c + d, u1 = b - d;
-  const T t2 = c - T(2) * d + e, u2 = T(3) * c - T(4) * d + e;
-  const T b0 = T(13.0 / 12.0) * t0 * t0 + T(0.25) * u0 * u0;
-  const T b1 = T(13.0 / 12.0) * t1 * t1 + T(0.25) * u1 * u1;
-  const T b2 = T(13.0 / 12.0) * t2 * t2 + T(0.25) * u2 * u2;
-  const T tau = fabs(b0 - b2);
-  const T q0 = tau * rcp(b0 + eps), q1 = tau * rcp(b1 + eps), q2 = tau * rcp(b2 + eps);
-  const T w0 = T(0.1) * (T(1) + q0 * q0);
-  const T w1 = T(0.6) * (T(1) + q1 * q1);
-  const T w2 = T(0.3) * (T(1) + q2 * q2);
-  return (w0 * r0 + w1 * r1 + w2 * r2) * rcp(T(6) * (w0 + w1 + w2));
+  const T d1 = b - a, d2 = c - b, d3 = d - c, d4 = e - d;
+  // ideal weights (1/10, 6/10, 3/10) folded into the candidate deviations
+  const T e0 = T(5.0 / 60.0) * d2 - T(2.0 / 60.0) * d1;
+  const T e1 = T(6.0 / 60.0) * d2 + T(12.0 / 60.0) * d3;
+  const T e2 = T(12.0 / 60.0) * d3 - T(3.0 / 60.0) * d4;
+  const T t0 = d2 - d1, t1 = d3 - d2, t2 = d4 - d3;
+  const T u0 = T(3) * d2 - d1, u1 = d2 + d3, u2 = d4 - T(3) * d3;
+  const T e4 = T(4) * eps;
+  const T s0 = fmad(T(13.0 / 3.0) * t0, t0, fmad(u0, u0, e4));
+  const T s1 = fmad(T(13.0 / 3.0) * t1, t1, fmad(u1, u1, e4));
+  const T s2 = fmad(T(13.0 / 3.0) * t2, t2, fmad(u2, u2, e4));
+  const T tau = fabs(s0 - s2);
+  const T s1s = s1 * s1;
+  const T g0 = tau * (s1 * rcp(s0));
+  const T g2 = tau * (s1 * rcp(s2));
+  const T a0 = fmad(g0, g0, s1s);
+  const T a1 = fmad(tau, tau, s1s);
+  const T a2 = fmad(g2, g2, s1s);
+  const T num = a0 * e0 + a1 * e1 + a2 * e2;
+  const T den = T(0.1) * a0 + T(0.6) * a1 + T(0.3) * a2;
+  return fmad(num, rcp(den), c);
 }
 
 // Centred reconstruction of order 2R - 2 at the midpoint of a[R-2] and

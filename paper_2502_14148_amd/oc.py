@@ -90,6 +90,9 @@ def load_library(path=_LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise OcError(f"{path} is missing: build it with `python -m paper_2502_14148_amd.build`")
+    # PyTorch ships its own HIP runtime under the same soname: it must be the
+    # one loaded, or device memory from torch is foreign to the library
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     vp, i32, i64p = ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)
     lib.oc_last_error.restype = ctypes.c_char_p
