@@ -486,6 +486,21 @@ int oc_coarse_grain(oc_model* fine, oc_model* coarse, float* fluxes, void* strea
  * still written), OC_ERR_UNSUPPORTED for a hydrostatic model. */
 int oc_diagnostics(oc_model* m, double* out, void* stream);
 
+/* For callers that cannot allocate device memory or wait for the device
+ * (code under HIP graph capture, tight serving loops): the values of
+ * oc_diagnostics, computed and finished on the device, written
+ * asynchronously on `stream` to out (device memory, OC_NDIAG + 1 doubles:
+ * out[0 .. OC_NDIAG-1] as oc_diagnostics, out[OC_NDIAG] the number of
+ * non-finite state values, which the caller checks instead of an error
+ * code).  Partial sums go to a library-held device array of 256 levels x 12
+ * doubles (24 KiB) per GPU, kept until the process ends; every call on that
+ * GPU shares it, so calls that overlap on one GPU race.  Nothing is
+ * allocated, copied to the host or waited for; sums are taken level by level
+ * in a fixed order (maxima and the count equal oc_diagnostics', sums agree to
+ * rounding).  Errors: OC_ERR_ARG (NULL), OC_ERR_UNSUPPORTED (hydrostatic
+ * model), OC_ERR_SHAPE (more than 256 levels), OC_ERR_DEVICE. */
+int oc_diagnostics_noalloc(oc_model* m, double* out, void* stream);
+
 /* Synchronise `stream` and report what the device has done since the last
  * check: OC_ERR_DEVICE for a HIP error (message from the runtime), then, for
  * a nonhydrostatic model, OC_ERR_NONFINITE if the current state holds a NaN

@@ -1561,6 +1561,49 @@ int oc_diagnostics(oc_model* m, double* out, void* stream) {
   return (m->esz == 8) ? diagnostics_call<double>(m, out, s) : diagnostics_call<float>(m, out, s);
 }
 
+int oc_diagnostics_noalloc(oc_model* m, double* out, void* stream) {
+  if (!m || !out) { set_error("NULL argument"); return OC_ERR_ARG; }
+  if (m->kind != OC_NONHYDROSTATIC) {
+    set_error("diagnostics are defined for the nonhydrostatic (rectilinear) model");
+    return OC_ERR_UNSUPPORTED;
+  }
+  if (m->dims.nz > DIAG_MAX_LEVELS) {
+    set_error("nz = %d exceeds the %d levels of the diagnostics scratch", m->dims.nz,
+              DIAG_MAX_LEVELS);
+    return OC_ERR_SHAPE;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const int nz = m->dims.nz;
+  DiagFinish f;
+  f.hmin = std::fmin(m->dx, std::fmin(m->dy, m->dzmin));
+  f.area = m->dx * m->dy;
+  f.rdx = 1.0 / m->dx;
+  f.rdy = 1.0 / m->dy;
+  f.rdzmin = 1.0 / m->dzmin;
+  const double ncell = (double)m->dims.nx * m->dims.ny * nz;
+  for (int q = 0; q < 4; ++q)
+    f.toff[q] = (OC_TRACER0 + q < m->nf) ? m->offset[OC_TRACER0 + q] * ncell * m->dz : 0.0;
+  hipError_t e;
+  if (m->esz == 8) {
+    double* fl[MAXF];
+    for (int q = 0; q < m->nf; ++q) fl[q] = (double*)m->state[m->cur][q];
+    e = launch_diagnostics_noalloc<double>(m->dims, fl, m->nf, 1.0 / m->dx, 1.0 / m->dy,
+                                           m->zt64 + zt_rdzc(nz), m->zt64 + zt_dzc(nz),
+                                           m->zt64 + zt_dzf(nz), f, out, s);
+  } else {
+    float* fl[MAXF];
+    for (int q = 0; q < m->nf; ++q) fl[q] = (float*)m->state[m->cur][q];
+    e = launch_diagnostics_noalloc<float>(m->dims, fl, m->nf, 1.0 / m->dx, 1.0 / m->dy,
+                                          m->zt64 + zt_rdzc(nz), m->zt64 + zt_dzc(nz),
+                                          m->zt64 + zt_dzf(nz), f, out, s);
+  }
+  if (e != hipSuccess) {
+    set_error("diagnostics launch failed: %s", hipGetErrorString(e));
+    return OC_ERR_DEVICE;
+  }
+  return OC_OK;
+}
+
 int oc_sync_check(oc_model* m, void* stream) {
   if (!m) { set_error("model is NULL"); return OC_ERR_ARG; }
   hipStream_t s = (hipStream_t)stream;

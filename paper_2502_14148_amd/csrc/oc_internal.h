@@ -535,6 +535,20 @@ int vertical_factors_len(int nz);
 template <class T>
 hipError_t launch_pack(const Dims& d, int nzf, int nyf, const T* padded, void* dense, int dtype,
                        int to_dense, double offset, hipStream_t s);
+// Diagnostics partials per workgroup or level, and the levels the
+// allocation-free variant's scratch array holds.
+constexpr int DIAG_NPART = 12;
+constexpr int DIAG_MAX_LEVELS = 256;
+// Host constants that finish the diagnostics on the device.
+struct DiagFinish {
+  double hmin, area, rdx, rdy, rdzmin;
+  double toff[4];   // storage offset x cells x dz per tracer (0 if absent)
+};
+template <class T>
+hipError_t launch_diagnostics_noalloc(const Dims& d, T* const* fields, int nf, double rdx,
+                                      double rdy, const double* rdzc, const double* dzc,
+                                      const double* dzf, const DiagFinish& f, double* out,
+                                      hipStream_t s);
 template <class T>
 hipError_t launch_diagnostics(const Dims& d, T* const* fields, int nf, double rdx, double rdy,
                               const double* rdzc, const double* dzc, const double* dzf,

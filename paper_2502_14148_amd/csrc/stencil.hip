@@ -1,6 +1,8 @@
 // Stencil kernels of the nonhydrostatic model on gfx950: halo fill (C-grid
 // staggering of the finite-volume appendix of arXiv 2502.14148, face i left
 // of cell i), dense <-> padded copies and FP64 diagnostics.
+#include <mutex>
+
 #include "oc_internal.h"
 
 namespace oc {
@@ -107,6 +109,7 @@ hipError_t launch_pack(const Dims& d, int nzf, int nyf, const T* padded, void* d
 // thickness-weighted sums of u, v (cell thickness) and w (face spacing).
 // ---------------------------------------------------------------------------
 constexpr int NPART = 12;
+static_assert(NPART == DIAG_NPART, "partials per block");
 
 template <class T>
 struct DiagArgs {
@@ -195,6 +198,100 @@ hipError_t launch_diagnostics(const Dims& d, T* const* fields, int nf, double rd
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Diagnostics without allocation or host synchronisation: one workgroup per
+// level writes that level's partials to `scratch` (a file-scope device array
+// of DIAG_MAX_LEVELS x NPART doubles per GPU), then one workgroup reduces the
+// levels in order and writes the finished values to the caller's device
+// buffer.  Calls that overlap on one GPU share (and race on) the array.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) double scratch[DIAG_MAX_LEVELS * NPART];
+
+template <class T>
+__global__ void __launch_bounds__(256) diag_level_kernel(Dims d, DiagArgs<T> a, double rdx,
+                                                         double rdy,
+                                                         const double* __restrict__ rdzc,
+                                                         const double* __restrict__ dzc,
+                                                         const double* __restrict__ dzf,
+                                                         double* part) {
+  double acc[NPART];
+  for (int q = 0; q < NPART; ++q) acc[q] = 0.0;
+  const int k = blockIdx.x;
+  const int n = d.nx * d.ny;
+  for (int t = threadIdx.x; t < n; t += blockDim.x)
+    diag_cell(d, a, rdx, rdy, rdzc, dzc, dzf, t % d.nx, t / d.nx, k, acc);
+  diag_block_reduce(acc, part + (long)k * NPART);
+}
+
+// Reduce the nz levels' partials in level order and finish the values as
+// oc_diagnostics does on the host: out[0] max|div| * hmin, [1..3] max|u|,
+// |v|, |w|, [4..7] tracer integrals (stored sums + offset x cells x dz, times
+// dx dy), [8..10] momentum integrals, [11] CFL rate, [12] non-finite count.
+__global__ void diag_finish_kernel(const double* __restrict__ part, int nz, DiagFinish f,
+                                   double* __restrict__ out) {
+  __shared__ double acc[NPART];
+  const int q = threadIdx.x;
+  if (q < NPART) {
+    double x = 0.0;
+    for (int k = 0; k < nz; ++k) {
+      const double y = part[(long)k * NPART + q];
+      x = (q < 4) ? fmax(x, y) : x + y;
+    }
+    acc[q] = x;
+  }
+  __syncthreads();
+  if (q == 0) {
+    out[0] = acc[0] * f.hmin;
+    out[1] = acc[1];
+    out[2] = acc[2];
+    out[3] = acc[3];
+    for (int t = 0; t < 4; ++t) out[4 + t] = (acc[4 + t] + f.toff[t]) * f.area;
+    for (int t = 0; t < 3; ++t) out[8 + t] = acc[9 + t] * f.area;
+    out[11] = fmax(acc[1] * f.rdx, fmax(acc[2] * f.rdy, acc[3] * f.rdzmin));
+    out[12] = acc[8];
+  }
+}
+
+// The array's device address on each GPU, looked up once per device with that
+// device current (the host-side name of a __device__ array is not a device
+// address).
+static double* g_scratch[64];
+static std::mutex g_scratch_mu;
+
+static hipError_t scratch_address(double** p) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* q = nullptr;
+    e = hipGetSymbolAddress(&q, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch[dev] = (double*)q;
+  }
+  *p = g_scratch[dev];
+  return hipSuccess;
+}
+
+template <class T>
+hipError_t launch_diagnostics_noalloc(const Dims& d, T* const* fields, int nf, double rdx,
+                                      double rdy, const double* rdzc, const double* dzc,
+                                      const double* dzf, const DiagFinish& f, double* out,
+                                      hipStream_t s) {
+  if (d.nz > DIAG_MAX_LEVELS) return hipErrorInvalidValue;
+  double* part = nullptr;
+  hipError_t e = scratch_address(&part);
+  if (e != hipSuccess) return e;
+  DiagArgs<T> a;
+  for (int q = 0; q < nf; ++q) a.f[q] = fields[q];
+  a.nf = nf;
+  hipLaunchKernelGGL(diag_level_kernel<T>, dim3(d.nz), dim3(256), 0, s, d, a, rdx, rdy, rdzc,
+                     dzc, dzf, part);
+  hipLaunchKernelGGL(diag_finish_kernel, dim3(1), dim3(64), 0, s, part, d.nz, f, out);
+  return hipGetLastError();
+}
+
 template hipError_t launch_halo_fill<float>(const Dims&, float* const*, const int*, int, hipStream_t);
 template hipError_t launch_halo_fill<double>(const Dims&, double* const*, const int*, int, hipStream_t);
 template hipError_t launch_pack<float>(const Dims&, int, int, const float*, void*, int, int,
@@ -207,6 +304,13 @@ template hipError_t launch_diagnostics<float>(const Dims&, float* const*, int, d
 template hipError_t launch_diagnostics<double>(const Dims&, double* const*, int, double, double,
                                                const double*, const double*, const double*,
                                                double*, int, hipStream_t);
-
+template hipError_t launch_diagnostics_noalloc<float>(const Dims&, float* const*, int, double,
+                                                      double, const double*, const double*,
+                                                      const double*, const DiagFinish&, double*,
+                                                      hipStream_t);
+template hipError_t launch_diagnostics_noalloc<double>(const Dims&, double* const*, int, double,
+                                                       double, const double*, const double*,
+                                                       const double*, const DiagFinish&, double*,
+                                                       hipStream_t);
 
 }  // namespace oc

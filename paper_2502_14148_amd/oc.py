@@ -37,7 +37,8 @@ EXPORTS = ("oc_last_error", "oc_grid_create", "oc_grid_destroy", "oc_model_works
            "oc_ensemble_workspace_size", "oc_ensemble_create", "oc_ensemble_step",
            "oc_ensemble_tuning", "oc_ensemble_destroy", "oc_closure_features",
            "oc_coarse_grain", "oc_implicit_vertical_diffusion", "oc_set_immersed",
-           "oc_pressure_stats", "oc_sync_check", "oc_autotune", "oc_ensemble_set_tuning")
+           "oc_pressure_stats", "oc_sync_check", "oc_autotune", "oc_ensemble_set_tuning",
+           "oc_diagnostics_noalloc")
 OC_ENS_TUNE, OC_ENS_GRAPH = 1, 2
 ENS_TILES = ("32x8", "16x8", "8x8")
 OC_MLP_NPARAM = 195076
@@ -138,6 +139,7 @@ def load_library(path=_LIB_PATH):
         "oc_pressure_stats": [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double),
                               vp],
         "oc_sync_check": [vp, vp],
+        "oc_diagnostics_noalloc": [vp, vp, vp],
         "oc_autotune": [vp, ctypes.c_char_p],
         "oc_ensemble_set_tuning": [vp, ctypes.POINTER(ctypes.c_int32)],
     }
@@ -335,6 +337,16 @@ class Model:
         return {"div_scaled_by_dx": out[0], "max_u": out[1], "max_v": out[2], "max_w": out[3],
                 "tracer_integrals": list(out[4:4 + len(self.ph.tracers)]),
                 "momentum": (out[8], out[9], out[10]), "cfl_rate": out[11]}
+
+    def diagnostics_noalloc(self, out):
+        """Enqueue the diagnostics into `out` (FP64 device tensor of
+        OC_NDIAG + 1 values: the oc_diagnostics values, then the count of
+        non-finite state values); no allocation, no synchronisation."""
+        assert out.is_cuda and out.dtype.is_floating_point and out.element_size() == 8
+        assert out.is_contiguous() and out.numel() >= OC_NDIAG + 1
+        _check(_lib.oc_diagnostics_noalloc(self._model, ctypes.c_void_p(out.data_ptr()),
+                                           _stream()))
+        return out
 
     def sync_check(self):
         """Synchronise the current stream; raises on a device error or a
