@@ -625,21 +625,24 @@ def main():
     ap.add_argument("--ensemble-steps", type=int, default=20)
     ap.add_argument("--hydro-steps", type=int, default=20)
     ap.add_argument("--calibrate-copy", action="store_true",
-                    help="first run one plain 512 MiB device copy (counter calibration)")
+                    help="first run one plain 1 GiB device copy (counter calibration)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
 
     if a.calibrate_copy:
+        # HBM counter calibration: an elementwise copy of 1 GiB whose source
+        # was written before 1 GiB of other data, so that none of it is left
+        # in the 256 MB last-level cache when the copy reads it
         import torch
-        src = torch.ones(128 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        src = torch.ones(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        flush = torch.zeros_like(src)
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
-        dst.copy_(src)                      # runtime copy kernel
         torch.mul(src, 1.0, out=dst)        # elementwise copy kernel
         torch.cuda.synchronize()
-        del src, dst
+        del src, flush, dst
 
     if a.no_main:
         out = {"note": "the 256^3 nonhydrostatic leg was skipped (--no-main)"}
