@@ -245,8 +245,14 @@ __device__ inline void wait_vm() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory
 
 // FP32: registers capped for five wavefronts per SIMD (a few spilled values,
 // 4 % faster than four wavefronts); FP64 keeps its registers.
+#ifndef OC_HYDRO_WAVES32
+#define OC_HYDRO_WAVES32 5
+#endif
+#ifndef OC_HYDRO_CHUNKS
+#define OC_HYDRO_CHUNKS 2
+#endif
 template <class T>
-constexpr int hydro_tend_waves() { return sizeof(T) == 4 ? 5 : 1; }
+constexpr int hydro_tend_waves() { return sizeof(T) == 4 ? OC_HYDRO_WAVES32 : 1; }
 
 template <class T, int SCHEME>
 __global__ void __launch_bounds__(TTX * TTY, hydro_tend_waves<T>())
@@ -627,7 +633,7 @@ hipError_t launch_hydro_tendency(const HydroBufs<T>& a, const HydroStep<T>& st, 
   // twice the workgroups of one march, so its last round of resident
   // workgroups is fuller
   HydroStep<T> sc = st;
-  const int nchunks = a.d.nz >= 16 ? 2 : 1;
+  const int nchunks = a.d.nz >= 16 ? OC_HYDRO_CHUNKS : 1;
   sc.kc = (a.d.nz + nchunks - 1) / nchunks;
   const dim3 grid((unsigned)(((a.d.nx + TTX - 1) / TTX) * ((a.d.ny + TTY - 1) / TTY) * nchunks));
   const dim3 block(TTX, TTY);

@@ -76,7 +76,7 @@ __device__ inline void les_fill(T* S, const T* const* fld, int nf, const Dims& d
 #pragma unroll
   for (int f = 0; f < NFMAX; ++f)
     if (f < nf) {
-      const T* __restrict__ src = fld[f] + base;
+      const auto src = glb(fld[f]) + base;
 #pragma unroll
       for (int r = 0; r < NR; ++r)
         if (PL % NT == 0 || threadIdx.x + r * NT < PL) v[f][r] = src[goff[r]];
@@ -133,8 +133,8 @@ __device__ inline void les_viscosity_cell(const Dims& d, const LesArgs<T>& a, in
   auto U = [&](int di, int dj, int dk) { return r(0, di, dj, dk); };
   auto V = [&](int di, int dj, int dk) { return r(1, di, dj, dk); };
   auto W = [&](int di, int dj, int dk) { return r(2, di, dj, dk); };
-  const T rdx = a.rdx, rdy = a.rdy, rzc = a.rdzc[k];
-  const T rzf0 = a.rdzf[k], rzf1 = a.rdzf[k + 1];
+  const T rdx = a.rdx, rdy = a.rdy, rzc = glb(a.rdzc)[k];
+  const T rzf0 = glb(a.rdzf)[k], rzf1 = glb(a.rdzf)[k + 1];
   const bool wall0 = d.zb && k == 0, wall1 = d.zb && k + 1 == d.nz;
   const T ux = (U(1, 0, 0) - U(0, 0, 0)) * rdx;
   const T vy = (V(0, 1, 0) - V(0, 0, 0)) * rdy;
@@ -183,7 +183,7 @@ __device__ inline void les_viscosity_cell(const Dims& d, const LesArgs<T>& a, in
     }
     T fac = T(0);
     if (s2 > T(0)) fac = fmax(T(0), T(1) - a.cb * n2 / s2);
-    nu = a.delta2[k] * sqrt(s2) * sqrt(fac);
+    nu = glb(a.delta2)[k] * sqrt(s2) * sqrt(fac);
   } else {
     // AMD: the gradient tensor at the centre (edge values averaged)
     T G[3][3];
@@ -258,7 +258,7 @@ __device__ inline void les_flux_cell(const Dims& d, const LesArgs<T>& a, int i, 
   auto W = [&](int di, int dj, int dk) { return r(2, di, dj, dk); };
   auto N = [&](int di, int dj, int dk) { return r(3, di, dj, dk); };
   const T rdx = a.rdx, rdy = a.rdy;
-  const T rzc = a.rdzc[k], rzf0 = a.rdzf[k], rzf1 = a.rdzf[k + 1];
+  const T rzc = glb(a.rdzc)[k], rzf0 = glb(a.rdzf)[k], rzf1 = glb(a.rdzf)[k + 1];
   const bool wall0 = d.zb && k == 0, wall1 = d.zb && k + 1 == d.nz;
   // edge viscosities: means of the four surrounding centres
   auto n_ffc = [&](int p, int q) {  // x face i + p, y face j + q
@@ -289,14 +289,14 @@ __device__ inline void les_flux_cell(const Dims& d, const LesArgs<T>& a, int i, 
     const T t0 = T(2) * N(-1, 0, 0) * (U(0, 0, 0) - U(-1, 0, 0)) * rdx;
     const T t1 = T(2) * N(0, 0, 0) * (U(1, 0, 0) - U(0, 0, 0)) * rdx;
     const T g = (t1 - t0) * rdx + (txy(0, 1) - txy(0, 0)) * rdy + (txz(0, 1) - txz(0, 0)) * rzc;
-    a.gc[0][c] = g;
+    glb(a.gc[0])[c] = g;
   }
   // v at y face j
   {
     const T t0 = T(2) * N(0, -1, 0) * (V(0, 0, 0) - V(0, -1, 0)) * rdy;
     const T t1 = T(2) * N(0, 0, 0) * (V(0, 1, 0) - V(0, 0, 0)) * rdy;
     const T g = (txy(1, 0) - txy(0, 0)) * rdx + (t1 - t0) * rdy + (tyz(0, 1) - tyz(0, 0)) * rzc;
-    a.gc[1][c] = g;
+    glb(a.gc[1])[c] = g;
   }
   // w at z face k (the w cell spans the centres k-1, k: thickness dzf_k);
   // txz and tyz on face k are the q = 0 stresses of the edges with x face
@@ -304,11 +304,11 @@ __device__ inline void les_flux_cell(const Dims& d, const LesArgs<T>& a, int i, 
   {
     T g = T(0);
     if (!wall0) {
-      const T t0 = T(2) * N(0, 0, -1) * (W(0, 0, 0) - W(0, 0, -1)) * a.rdzc[k - 1];
+      const T t0 = T(2) * N(0, 0, -1) * (W(0, 0, 0) - W(0, 0, -1)) * glb(a.rdzc)[k - 1];
       const T t1 = T(2) * N(0, 0, 0) * (W(0, 0, 1) - W(0, 0, 0)) * rzc;
       g = (txz(1, 0) - txz(0, 0)) * rdx + (tyz(1, 0) - tyz(0, 0)) * rdy + (t1 - t0) * rzf0;
     }
-    a.gc[2][c] = g;
+    glb(a.gc[2])[c] = g;
   }
   // tracers: d_i(kappa d_i c), face diffusivities the mean of two centres
   for (int q = 0; q < a.ntr; ++q) {
@@ -323,7 +323,7 @@ __device__ inline void les_flux_cell(const Dims& d, const LesArgs<T>& a, int i, 
     const T fyp = T(0.5) * (k0 + K(0, 1, 0)) * (C(0, 1, 0) - c0) * rdy;
     const T fzm = wall0 ? T(0) : T(0.5) * (K(0, 0, -1) + k0) * (c0 - C(0, 0, -1)) * rzf0;
     const T fzp = wall1 ? T(0) : T(0.5) * (k0 + K(0, 0, 1)) * (C(0, 0, 1) - c0) * rzf1;
-    a.gc[3 + q][c] = s * ((fxp - fxm) * rdx + (fyp - fym) * rdy + (fzp - fzm) * rzc);
+    glb(a.gc[3 + q])[c] = s * ((fxp - fxm) * rdx + (fyp - fym) * rdy + (fzp - fzm) * rzc);
   }
 }
 

@@ -28,6 +28,36 @@ struct Dims {
   int h;           // halo width
 };
 
+// Every buffer the kernels address lives in device (global) memory.  Pointers
+// that reach a kernel through a struct or a table are generic to the
+// compiler, which then issues flat loads and stores: these count against the
+// LDS counter too and stall LDS waits behind global traffic.  The cast makes
+// them global operations.
+template <class T>
+__device__ inline __attribute__((address_space(1))) T* glb(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+
+// double2 (a class type) cannot live in a qualified address space: complex
+// values go through a native vector type.
+typedef double oc_dbl2 __attribute__((ext_vector_type(2)));
+__device__ inline double2 ld2(const double2* p, long i) {
+  const oc_dbl2 v = ((const __attribute__((address_space(1))) oc_dbl2*)p)[i];
+  return make_double2(v.x, v.y);
+}
+__device__ inline void st2(double2* p, long i, double2 x) {
+  ((__attribute__((address_space(1))) oc_dbl2*)p)[i] = oc_dbl2{x.x, x.y};
+}
+
+// Four consecutive elements in one 16- (FP32) or 32-byte (FP64) load; the
+// address need only be element-aligned.
+template <class T>
+using v4u = T __attribute__((ext_vector_type(4), aligned(sizeof(T))));
+template <class T>
+__device__ inline v4u<T> ld4(const T* p, long i) {
+  return *(const __attribute__((address_space(1))) v4u<T>*)(p + i);
+}
+
 __host__ __device__ inline long pidx(const Dims& d, int i, int j, int k) {
   return (long)(k + d.h) * d.sz + (long)(j + d.h) * d.sy + (long)(i + d.h);
 }
@@ -59,8 +89,8 @@ __device__ inline void store_with_images(T* __restrict__ f, const Dims& d, int i
     if (k >= 1 && k <= H) za = (long)(-2 * k) * d.sz;          // image -k
     if (k >= d.nz - H + 1 && k <= d.nz - 1) zb = (long)(2 * d.nz - 2 * k) * d.sz;  // 2nz - k
   }
-  T* __restrict__ p0 = f + pidx(d, i, j, k);
-  auto plane = [&](T* q, T v, bool self) {
+  auto* __restrict__ p0 = glb(f) + pidx(d, i, j, k);
+  auto plane = [&](decltype(p0) q, T v, bool self) {
     if (self) q[0] = v;
     if (xa) q[xa] = v;
     if (xb) q[xb] = v;

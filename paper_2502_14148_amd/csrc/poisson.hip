@@ -147,7 +147,7 @@ __device__ inline void stage_twiddles(double2* tws, const double2* __restrict__ 
 #pragma unroll
   for (int q = 0; q < (N + NT - 1) / NT; ++q) {
     const int t = threadIdx.x + q * NT;
-    if (N % NT == 0 || t < N) tws[t] = tw[t];
+    if (N % NT == 0 || t < N) tws[t] = ld2(tw, t);
   }
 }
 template <int N> struct XCfg { static constexpr int LP = (N >= 1024) ? 1 : 1024 / N; };
@@ -166,7 +166,7 @@ __global__ void __launch_bounds__(NT) fwd_x_kernel(Dims d, const T* __restrict__
                                                    const double* __restrict__ rdzc, SpecBufs sb,
                                                    const PoissonSlots* __restrict__ bs,
                                                    const double* __restrict__ dense) {
-  if (sb.stop && *sb.stop != 0.0) return;
+  if (sb.stop && *glb(sb.stop) != 0.0) return;
   if (bs) {
     const int z = blockIdx.z;
     u = (const T*)bs->u[z];
@@ -179,44 +179,59 @@ __global__ void __launch_bounds__(NT) fwd_x_kernel(Dims d, const T* __restrict__
   __shared__ double2 tws[N];
   stage_twiddles<N>(tws, sb.twx);
   const int k = blockIdx.y;
-  const double rdz = dense ? 0.0 : rdzc[k];  // the dense path carries no spacing table
   const int npairs = d.ny / 2;
   const int pair0 = blockIdx.x * LP;
-  // compile-time trip counts, so that every load of the tile is in flight
-  // before the first one is used
-  constexpr int LOADS = (LP * N + NT - 1) / NT;
+  // A thread takes four consecutive points of both lines of a pair (16-byte
+  // row loads; rows carry no alignment, the loads need none) and stores
+  // the packed values (line 2pr, line 2pr+1) at buf[l N + i .. + 3].
+  // Compile-time trip counts, so that every load is in flight before the
+  // first one is used.
+  constexpr int NQ = N / 4, QUADS = LP * NQ, QPT = (QUADS + NT - 1) / NT;
+  static_assert(N % 4 == 0, "four points per thread");
 #pragma unroll
-  for (int q = 0; q < LOADS; ++q) {
+  for (int q = 0; q < QPT; ++q) {
     const int t = threadIdx.x + q * NT;
-    if ((LP * N) % NT != 0 && t >= LP * N) break;
-    const int l = t / N, i = t % N;
+    if (QUADS % NT != 0 && t >= QUADS) break;
+    const int l = t / NQ, i = 4 * (t % NQ);
     const int pr = pair0 + l;
-    double2 z = make_double2(0.0, 0.0);
+    double de[4] = {0.0, 0.0, 0.0, 0.0}, dod[4] = {0.0, 0.0, 0.0, 0.0};
     if (pr < npairs && dense) {
       const long o = ((long)k * d.ny + 2 * pr) * d.nx + i;
-      z = make_double2(dense[o], dense[o + d.nx]);
-    } else if (pr < npairs) {
-      double dv[2];
+      const v4u<double> xe = ld4(dense, o), xo = ld4(dense, o + d.nx);
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int j = 2 * pr + h;
-        const long c = pidx(d, i, j, k);
-        const int ip = (i + 1 == d.nx) ? 0 : i + 1;
-        const int jp = (j + 1 == d.ny) ? 0 : j + 1;
-        double wb = (double)w[c];
-        double wt;
-        if (d.zb) {
-          if (k == 0) wb = 0.0;
-          wt = (k + 1 == d.nz) ? 0.0 : (double)w[c + d.sz];
-        } else {
-          wt = (double)w[pidx(d, i, j, (k + 1 == d.nz) ? 0 : k + 1)];
-        }
-        dv[h] = (((double)u[pidx(d, ip, j, k)] - (double)u[c]) * rdx +
-                 ((double)v[pidx(d, i, jp, k)] - (double)v[c]) * rdy + (wt - wb) * rdz) * inv_dt;
+      for (int m = 0; m < 4; ++m) { de[m] = xe[m]; dod[m] = xo[m]; }
+    } else if (pr < npairs) {
+      const double rdz = rdzc[k];
+      const int j = 2 * pr;
+      const long c = pidx(d, i, j, k);
+      // x neighbour of the fourth point, the line above the pair and the
+      // level above (periodic wraps; above a top wall w is 0)
+      const long ie = (i + 4 == d.nx) ? 4 - d.nx : 4;
+      const long jn = (j + 2 == d.ny) ? -(long)(d.ny - 2) * d.sy : 2 * d.sy;
+      const bool top_wall = d.zb && k + 1 == d.nz;
+      const long kn = (k + 1 == d.nz) ? -(long)(d.nz - 1) * d.sz : d.sz;
+      const long co = c + d.sy;
+      const v4u<T> ue = ld4(u, c), uo = ld4(u, co);
+      const T uee = glb(u)[c + ie], uoe = glb(u)[co + ie];
+      const v4u<T> ve = ld4(v, c), vo = ld4(v, co), vn = ld4(v, c + jn);
+      const v4u<T> we = ld4(w, c), wo = ld4(w, co);
+      v4u<T> wte = {T(0), T(0), T(0), T(0)}, wto = wte;
+      if (!top_wall) { wte = ld4(w, c + kn); wto = ld4(w, co + kn); }
+      const bool bottom_wall = d.zb && k == 0;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const double upe = (double)(m < 3 ? ue[m + 1] : uee);
+        const double upo = (double)(m < 3 ? uo[m + 1] : uoe);
+        const double wbe = bottom_wall ? 0.0 : (double)we[m];
+        const double wbo = bottom_wall ? 0.0 : (double)wo[m];
+        de[m] = ((upe - (double)ue[m]) * rdx + ((double)vo[m] - (double)ve[m]) * rdy +
+                 ((double)wte[m] - wbe) * rdz) * inv_dt;
+        dod[m] = ((upo - (double)uo[m]) * rdx + ((double)vn[m] - (double)vo[m]) * rdy +
+                  ((double)wto[m] - wbo) * rdz) * inv_dt;
       }
-      z = make_double2(dv[0], dv[1]);
     }
-    buf[t] = z;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) buf[l * N + i + m] = make_double2(de[m], dod[m]);
   }
   __syncthreads();
   fft_lines<N, 1, LP, NT, -1, false>(buf, N, 1, tws);
@@ -231,8 +246,8 @@ __global__ void __launch_bounds__(NT) fwd_x_kernel(Dims d, const T* __restrict__
     double2 x1 = cscale(cadd(a, b), 0.5);
     double2 x2 = cscale(mul_i<-1>(csub(a, b)), 0.5);
     const long base = ((long)k * d.ny + 2 * pr) * sb.nxp + kx;
-    sb.spec[base] = x1;
-    sb.spec[base + sb.nxp] = x2;
+    st2(sb.spec, base, x1);
+    st2(sb.spec, base + sb.nxp, x2);
   }
 }
 
@@ -242,7 +257,7 @@ __global__ void __launch_bounds__(NT) fwd_x_kernel(Dims d, const T* __restrict__
 template <int N, int DIR>
 __global__ void __launch_bounds__(NT) y_kernel(Dims d, SpecBufs sb,
                                                const PoissonSlots* __restrict__ bs) {
-  if (sb.stop && *sb.stop != 0.0) return;
+  if (sb.stop && *glb(sb.stop) != 0.0) return;
   if (bs) sb.spec = bs->spec[blockIdx.z];
   constexpr int W = YZCfg<N>::W;
   __shared__ double2 buf[W * N];
@@ -251,20 +266,23 @@ __global__ void __launch_bounds__(NT) y_kernel(Dims d, SpecBufs sb,
   const int k = blockIdx.y;
   const int kx0 = blockIdx.x * W;
   const int nxh = sb.nxh, nxp = sb.nxp;
+  double2* plane = sb.spec + (long)k * d.ny * nxp + kx0;
   constexpr int PER = (W * N + NT - 1) / NT;
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int t = threadIdx.x + q * NT;
     if ((W * N) % NT != 0 && t >= W * N) break;
     const int c = t % W, y = t / W;
-    buf[t] = (kx0 + c < nxh) ? sb.spec[((long)k * d.ny + y) * nxp + kx0 + c]
-                             : make_double2(0.0, 0.0);
+    buf[t] = (kx0 + c < nxh) ? ld2(plane, (long)y * nxp + c) : make_double2(0.0, 0.0);
   }
   __syncthreads();
   fft_lines<N, 1, W, NT, DIR, true, 8>(buf, 1, W, tws);
-  for (int t = threadIdx.x; t < W * N; t += NT) {
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int t = threadIdx.x + q * NT;
+    if ((W * N) % NT != 0 && t >= W * N) break;
     const int c = t % W, y = t / W;
-    if (kx0 + c < nxh) sb.spec[((long)k * d.ny + y) * nxp + kx0 + c] = buf[t];
+    if (kx0 + c < nxh) st2(plane, (long)y * nxp + c, buf[t]);
   }
 }
 
@@ -277,79 +295,107 @@ __device__ inline int makhoul_pos(int m, int n) {
   return (m & 1) ? (n - 1 - (m >> 1)) : (m >> 1);
 }
 
+// The division, and on walls the DCT post- and pre-processing around it,
+// in place and without a barrier: the post-processing of mode k reads V_k
+// and V_{N-k}, and the pre-processing of the inverse writes the same two, so
+// one thread owns the pair (k, N-k); the first pair of a column is the two
+// self-paired modes k = 0 and k = N/2.  On periodic z the pair is (k, k+N/2).
+//   X_k = (e_k V_k + conj(e_k) V_{N-k}) / 2,  e_k = exp(-i pi k / 2N)
+//   Y_k = X_k norm / lam_k  (0 for the singular mode)
+//   V'_k = conj(e_k) (Y_k - i Y_{N-k}),  Y_N = 0
+// The factors norm / lam and e_k of a thread's pairs are fetched and formed
+// before the forward transform, so that their latency hides behind the tile
+// load; e_{N-k} = -i conj(e_k).
 template <int N, bool BOUNDED>
-__global__ void __launch_bounds__(NT) z_kernel(Dims d, SpecBufs sb, double norm,
-                                               const PoissonSlots* __restrict__ bs) {
-  if (sb.stop && *sb.stop != 0.0) return;
+struct ZPairs {
+  static constexpr int W = YZCfg<N>::W;
+  static constexpr int NU = W * N / 2;          // pairs per column block
+  static constexpr int UPT = (NU + NT - 1) / NT;  // pairs per thread
+  static_assert(NT % W == 0, "a thread keeps one column");
+  double sa[UPT], sb[UPT];
+
+  __device__ inline void load(const SpecBufs& b, int j, int kx0, double norm) {
+    const int c = (int)threadIdx.x % W;
+    const double lxy = (kx0 + c < b.nxh ? glb(b.lamx)[kx0 + c] : 1.0) + glb(b.lamy)[j];
+#pragma unroll
+    for (int q = 0; q < UPT; ++q) {
+      const int u = min(((int)threadIdx.x + q * NT) / W, N / 2 - 1);
+      const int kb = BOUNDED ? (u == 0 ? N / 2 : N - u) : u + N / 2;
+      const double la = lxy + glb(b.lamz)[u], lb = lxy + glb(b.lamz)[kb];
+      sa[q] = (la == 0.0) ? 0.0 : norm / la;
+      sb[q] = (lb == 0.0) ? 0.0 : norm / lb;
+    }
+  }
+
+  __device__ inline void apply(double2* buf, const double2* __restrict__ dctz) const {
+    const double h = 0.70710678118654752440;
+#pragma unroll
+    for (int q = 0; q < UPT; ++q) {
+      const int t = (int)threadIdx.x + q * NT;
+      if (NU % NT != 0 && t >= NU) break;
+      const int c = t % W, u = t / W;
+      const bool self = (u == 0);
+      const int kb = BOUNDED ? (self ? N / 2 : N - u) : u + N / 2;
+      const double2 va = buf[u * W + c], vb = buf[kb * W + c];
+      double2 ra, rb;
+      if (BOUNDED) {
+        const double2 ea = ld2(dctz, u);
+        const double2 eb = self ? make_double2(h, -h) : make_double2(-ea.y, -ea.x);
+        const double2 pa = self ? va : vb, pb = self ? vb : va;
+        const double2 xa = cscale(cadd(cmul(ea, va), cmul(cconj(ea), pa)), 0.5);
+        const double2 xb = cscale(cadd(cmul(eb, vb), cmul(cconj(eb), pb)), 0.5);
+        const double2 ya = cscale(xa, sa[q]), yb = cscale(xb, sb[q]);
+        const double2 qa = self ? make_double2(0.0, 0.0) : yb, qb = self ? yb : ya;
+        ra = cmul(cconj(ea), csub(ya, mul_i<1>(qa)));
+        rb = cmul(cconj(eb), csub(yb, mul_i<1>(qb)));
+      } else {
+        ra = cscale(va, sa[q]);
+        rb = cscale(vb, sb[q]);
+      }
+      buf[u * W + c] = ra;
+      buf[kb * W + c] = rb;
+    }
+  }
+};
+
+// Four waves per SIMD: four blocks per CU, as many as the LDS holds.
+template <int N, bool BOUNDED>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4)))
+    z_kernel(Dims d, SpecBufs sb, double norm, const PoissonSlots* __restrict__ bs) {
+  if (sb.stop && *glb(sb.stop) != 0.0) return;
   if (bs) sb.spec = bs->spec[blockIdx.z];
   constexpr int W = YZCfg<N>::W;
   constexpr int PER = (W * N + NT - 1) / NT;
   __shared__ double2 buf[W * N];
   __shared__ double2 tws[N];
-  stage_twiddles<N>(tws, sb.twz);
   const int j = blockIdx.y;
   const int kx0 = blockIdx.x * W;
   const int nxh = sb.nxh, nxp = sb.nxp;
+  ZPairs<N, BOUNDED> pairs;
+  pairs.load(sb, j, kx0, norm);
+  stage_twiddles<N>(tws, sb.twz);
   const long zs = (long)d.ny * nxp;
+  double2* col = sb.spec + (long)j * nxp + kx0;
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int t = threadIdx.x + q * NT;
     if ((W * N) % NT != 0 && t >= W * N) break;
     const int c = t % W, z = t / W;
     const int pos = BOUNDED ? makhoul_pos(z, N) : z;
-    buf[pos * W + c] = (kx0 + c < nxh) ? sb.spec[(long)z * zs + (long)j * nxp + kx0 + c]
-                                       : make_double2(0.0, 0.0);
+    buf[pos * W + c] = (kx0 + c < nxh) ? ld2(col, (long)z * zs + c) : make_double2(0.0, 0.0);
   }
   __syncthreads();
   fft_lines<N, 1, W, NT, -1, true, 8>(buf, 1, W, tws);
-  // spectral division
-  double2 val[PER];
-#pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    const int t = threadIdx.x + q * NT;
-    if (t >= W * N) continue;
-    const int c = t % W, kz = t / W;
-    double2 x = buf[t];
-    if (BOUNDED) {
-      // X_k = (e^{-i pi k/2N} V_k + e^{i pi k/2N} V_{N-k}) / 2
-      double2 e = sb.dctz[kz];
-      double2 vb = buf[((N - kz) % N) * W + c];
-      x = cscale(cadd(cmul(e, x), cmul(cconj(e), vb)), 0.5);
-    }
-    const int kx = kx0 + c;
-    double lam = (kx < nxh ? sb.lamx[kx] : 1.0) + sb.lamy[j] + sb.lamz[kz];
-    val[q] = (lam == 0.0) ? make_double2(0.0, 0.0) : cscale(x, norm / lam);
-  }
+  pairs.apply(buf, sb.dctz);
   __syncthreads();
-#pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    const int t = threadIdx.x + q * NT;
-    if (t < W * N) buf[t] = val[q];
-  }
-  __syncthreads();
-  if (BOUNDED) {
-    // V_k = e^{i pi k/2N} (X_k - i X_{N-k}), X_N = 0
-#pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int t = threadIdx.x + q * NT;
-      if (t >= W * N) continue;
-      const int c = t % W, kz = t / W;
-      double2 xn = (kz == 0) ? make_double2(0.0, 0.0) : buf[(N - kz) * W + c];
-      val[q] = cmul(cconj(sb.dctz[kz]), csub(buf[t], mul_i<1>(xn)));
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int t = threadIdx.x + q * NT;
-      if (t < W * N) buf[t] = val[q];
-    }
-    __syncthreads();
-  }
   fft_lines<N, 1, W, NT, 1, true, 8>(buf, 1, W, tws);
-  for (int t = threadIdx.x; t < W * N; t += NT) {
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int t = threadIdx.x + q * NT;
+    if ((W * N) % NT != 0 && t >= W * N) break;
     const int c = t % W, z = t / W;
     const int pos = BOUNDED ? makhoul_pos(z, N) : z;
-    if (kx0 + c < nxh) sb.spec[(long)z * zs + (long)j * nxp + kx0 + c] = buf[pos * W + c];
+    if (kx0 + c < nxh) st2(col, (long)z * zs + c, buf[pos * W + c]);
   }
 }
 
@@ -509,11 +555,13 @@ __global__ void __launch_bounds__(NT) inv_x_kernel(Dims d, SpecBufs sb,
                                                    const PoissonSlots* __restrict__ bs,
                                                    const double* __restrict__ rdot,
                                                    double* __restrict__ part) {
-  if (sb.stop && *sb.stop != 0.0) return;
+  if (sb.stop && *glb(sb.stop) != 0.0) return;
   if (bs) {
     sb.spec = bs->spec[blockIdx.z];
     sb.p = bs->p[blockIdx.z];
   }
+  const auto pout = glb(sb.p);
+  const auto grdot = glb(rdot);
   constexpr int LP = XCfg<N>::LP;
   __shared__ double2 buf[LP * N];
   __shared__ double2 tws[N];
@@ -533,7 +581,7 @@ __global__ void __launch_bounds__(NT) inv_x_kernel(Dims d, SpecBufs sb,
       const long base = ((long)k * d.ny + 2 * pr) * sb.nxp;
       const bool lo = n <= N / 2;
       const int m = lo ? n : N - n;
-      double2 x1 = sb.spec[base + m], x2 = sb.spec[base + sb.nxp + m];
+      double2 x1 = ld2(sb.spec, base + m), x2 = ld2(sb.spec, base + sb.nxp + m);
       if (!lo) { x1 = cconj(x1); x2 = cconj(x2); }
       z = cadd(x1, mul_i<1>(x2));  // Z = X1 + i X2
     }
@@ -547,9 +595,9 @@ __global__ void __launch_bounds__(NT) inv_x_kernel(Dims d, SpecBufs sb,
     const int pr = pair0 + l;
     if (pr >= npairs) continue;
     const long base = ((long)k * d.ny + 2 * pr) * d.nx + i;
-    sb.p[base] = buf[t].x;
-    sb.p[base + d.nx] = buf[t].y;
-    if (rdot) acc += rdot[base] * buf[t].x + rdot[base + d.nx] * buf[t].y;
+    pout[base] = buf[t].x;
+    pout[base + d.nx] = buf[t].y;
+    if (rdot) acc += grdot[base] * buf[t].x + grdot[base + d.nx] * buf[t].y;
   }
   if (rdot) {
     __shared__ double red[NT];
@@ -560,7 +608,7 @@ __global__ void __launch_bounds__(NT) inv_x_kernel(Dims d, SpecBufs sb,
       if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
       __syncthreads();
     }
-    if (threadIdx.x == 0) part[blockIdx.y * gridDim.x + blockIdx.x] = red[0];
+    if (threadIdx.x == 0) glb(part)[blockIdx.y * gridDim.x + blockIdx.x] = red[0];
   }
 }
 
@@ -599,7 +647,9 @@ __global__ void __launch_bounds__(PJ_X * PJ_Y) project_kernel(
   const int k0 = (lin / (int)gridDim.x) * PJ_KC;
   const int k1 = min(k0 + PJ_KC, d.nz);
   const long plane = (long)d.nx * d.ny;
-  const double* __restrict__ pc = p + (long)j * d.nx + i;
+  const auto pc = glb(p) + (long)j * d.nx + i;
+  const auto gu = glb(u), gv = glb(v), gw = glb(w);
+  const auto gmask = glb(mask);
   const long oxm = ((i == 0) ? d.nx - 1 : i - 1) - i;
   const long oym = (long)(((j == 0) ? d.ny - 1 : j - 1) - j) * d.nx;
   // pressure below the first plane of the chunk (periodic wrap in z)
@@ -620,9 +670,9 @@ __global__ void __launch_bounds__(PJ_X * PJ_Y) project_kernel(
         pxm[q] = pc[t + oxm];
         pym[q] = pc[t + oym];
         const long c = pidx(d, i, j, kb + q);
-        uu[q] = u[c];
-        vv[q] = v[c];
-        ww[q] = w[c];
+        uu[q] = gu[c];
+        vv[q] = gv[c];
+        ww[q] = gw[c];
       }
     }
 #pragma unroll
@@ -636,10 +686,10 @@ __global__ void __launch_bounds__(PJ_X * PJ_Y) project_kernel(
         pb = p0[q];
         if (mask) {
           const long c = pidx(d, i, j, k);
-          const T m0 = mask[c];
-          un = un * (m0 * mask[c - 1]);
-          vn = vn * (m0 * mask[c - d.sy]);
-          if (!d.zb || k > 0) wn = wn * (m0 * mask[c - d.sz]);
+          const T m0 = gmask[c];
+          un = un * (m0 * gmask[c - 1]);
+          vn = vn * (m0 * gmask[c - d.sy]);
+          if (!d.zb || k > 0) wn = wn * (m0 * gmask[c - d.sz]);
         }
         // the final velocities, with their halo images
         store_with_images(u, d, i, j, k, un, false);

@@ -363,7 +363,7 @@ __device__ __attribute__((always_inline)) inline void tendency_tile(
     T z[NW];
     const T wt_u = interp_lds<T, R>(wp, Lc, 1);
     const T wt_v = interp_lds<T, R>(wp, Lc, PX);
-    const T rzb = P.rdzf[kb];  // face kb
+    const T rzb = glb(P.rdzf)[kb];  // face kb
     z[0] = bload<T>(rs, col, fs.oin[0] + lv);
 #pragma unroll
     for (int o = 1; o < NW; ++o) z[o] = wu[o - 1];
@@ -376,7 +376,7 @@ __device__ __attribute__((always_inline)) inline void tendency_tile(
 #pragma unroll
     for (int o = 1; o < NW; ++o) z[o] = ww[o - 1];
     const T wb = interpc<T, R>(z + 1);
-    fzb_w = flux_reg<T, SCHEME, R>(z, wb, eps) - P.nuz * (z[R] - z[R - 1]) * P.rdzc[kb - 1];
+    fzb_w = flux_reg<T, SCHEME, R>(z, wb, eps) - P.nuz * (z[R] - z[R - 1]) * glb(P.rdzc)[kb - 1];
     const T wface = z[R];
 #pragma unroll
     for (int q = 0; q < NTR; ++q) {
@@ -458,7 +458,7 @@ __device__ __attribute__((always_inline)) inline void tendency_tile(
     const bool top_wall = d.zb && (k + 1 == d.nz);
     // inverse spacings of this level (uniform across the workgroup): the top
     // face k+1, the cell k, and face k (the thickness of the w cell)
-    const T rzft = P.rdzf[k + 1], rzc = P.rdzc[k], rzf = P.rdzf[k];
+    const T rzft = glb(P.rdzf)[k + 1], rzc = glb(P.rdzc)[k], rzf = glb(P.rdzf)[k];
     T fzt_u, fzt_v, fzt_w, fzt_c[NTR];
     {
       const T* wp = S + OWk1;
