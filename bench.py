@@ -85,6 +85,63 @@ def measured_traffic():
     return rec["traffic_bytes_per_launch"] if rec.get("source_sha256") == src else None
 
 
+def record_counters(fetch_dir, write_dir):
+    """Write the counter record (COUNTERS) from the two rocprofv3 counter
+    runs of this script with `--steps 1 --warmup 0 --calibrate-copy`, one
+    with `--pmc FETCH_SIZE` (output in fetch_dir), one with `--pmc
+    WRITE_SIZE` (write_dir).  The calibration copy is the non-library kernel
+    with the largest FETCH_SIZE (the fills before it fetch nothing); the
+    scale factors map its counters onto the 1 GiB it reads and writes."""
+    import csv
+    import glob
+
+    def rows(d, counter):
+        f = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+        if not f:
+            raise SystemExit(f"no counter_collection.csv under {d}")
+        out = []
+        for r in csv.DictReader(open(f[0])):
+            if r["Counter_Name"] == counter:
+                name = r.get("Kernel_Name") or r.get("Kernel-Name")
+                out.append((int(r["Dispatch_Id"]), name, float(r["Counter_Value"])))
+        return sorted(out)
+
+    fr, wr = rows(fetch_dir, "FETCH_SIZE"), rows(write_dir, "WRITE_SIZE")
+    ours = lambda n: "oc::" in n
+    copy_name = max((r for r in fr if not ours(r[1])), key=lambda r: r[2])[1]
+    fetch_copy = max(r[2] for r in fr if r[1] == copy_name)
+    write_copy = max(r[2] for r in wr if r[1] == copy_name)
+    gib_kib = 1024.0 * 1024.0
+    ff, wf = gib_kib / fetch_copy, gib_kib / write_copy
+    key = "tendency_zmarch<float, 1, 2, 32, 8, 3, false, false>"
+    tf = [r[2] for r in fr if key in r[1]]
+    tw = [r[2] for r in wr if key in r[1]]
+    if not tf or len(tf) != len(tw) or len(tf) % 3:
+        raise SystemExit(f"expected whole RK3 steps of tendency launches, got {len(tf)}, {len(tw)}")
+    per_sub = lambda v: [sum(v[s::3]) / len(v[s::3]) for s in range(3)]
+    fk, wk = sum(tf) / len(tf), sum(tw) / len(tw)
+    rec = {
+        "kernel": "tendency_zmarch<float, WENO-Z, 2 tracers, 32x8, R = 3>",
+        "workload": "256^3 free convection FP32",
+        "source_sha256": tendency_source_sha256(),
+        "sources": [os.path.relpath(f, ROOT) for f in TENDENCY_SRC],
+        "fetch_kib_per_launch_raw": fk,
+        "write_kib_per_launch_raw": wk,
+        "fetch_kib_per_substage_raw": per_sub(tf),
+        "write_kib_per_substage_raw": per_sub(tw),
+        "fetch_factor": ff,
+        "write_factor": wf,
+        "calibration": (f"elementwise copy of 1 GiB whose source was written before another "
+                        f"1 GiB (no last-level-cache hits): FETCH_SIZE {fetch_copy:.0f} KiB, "
+                        f"WRITE_SIZE {write_copy:.0f} KiB"),
+        "traffic_bytes_per_launch": (fk * ff + wk * wf) * 1024.0,
+    }
+    with open(COUNTERS, "w") as f:
+        json.dump(rec, f, indent=1)
+        f.write("\n")
+    print(json.dumps(rec))
+
+
 def algorithmic_tendency_bytes(ncells, nfields, esz, steps):
     """Bytes the fused tendency + RK3 kernel must move per RK3 step: every
     field read once and written once per substage, plus the G^{m-1} read
@@ -626,7 +683,13 @@ def main():
     ap.add_argument("--hydro-steps", type=int, default=20)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--record-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write the tendency kernel's counter record from two rocprofv3 "
+                         "counter runs (no GPU work)")
     a = ap.parse_args()
+    if a.record_counters:
+        record_counters(*a.record_counters)
+        return
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)

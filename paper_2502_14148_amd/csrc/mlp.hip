@@ -600,17 +600,24 @@ __global__ void __launch_bounds__(256) closure_mlp_fused_kernel(Dims d, const T*
 // The same network for grids whose x rows hold a multiple of 64 cells: the
 // 64 cells of a workgroup share one x row, so the standardised BF16 values
 // of (u, v, w, b) over their whole 5 x 5 x 68 neighbourhood region are
-// loaded once (coalesced along x) into LDS, and every k chunk of features is
-// copied out of that region (im2col in LDS).  Weight chunks are 32 deep.
-constexpr int RG_X = FZ_BM + 4, RG_P = RG_X + 4, RG_K = 32, RG_WP = RG_K + 8;
+// loaded once (coalesced along x) into LDS, and every 32-deep k chunk of
+// features is copied out of that region (im2col in LDS, double-buffered
+// column blocks, one barrier per chunk).  Each wave's B operands (its 64
+// output rows of the weights, k contiguous) go from global memory (L2)
+// straight into registers in the MFMA operand layout, RG_D chunks ahead of
+// their use: no weight staging in LDS, and the second layer runs without
+// barriers.  The weight prefetch crosses from the first layer into the
+// second.
+constexpr int RG_X = FZ_BM + 4, RG_P = RG_X + 4, RG_D = 2;
+constexpr int RG_S1 = MLP_KIN / 32, RG_S2 = MLP_NH / 32;   // k chunks per layer
 
 template <class T>
-__global__ void __launch_bounds__(256) closure_mlp_region_kernel(Dims d, const T* u, const T* v,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+closure_mlp_region_kernel(Dims d, const T* u, const T* v,
                                                                 const T* w, const T* tt,
                                                                 const T* ss, ClosureStats st,
                                                                 MlpParams p, float* y) {
   __shared__ __bf16 Rg[4][25][RG_P];         // (var, 5 dk + dj, x - (i0 - 2))
-  __shared__ __bf16 Ws[MLP_NH][RG_WP];       // weight chunk, rows = outputs
   __shared__ __bf16 Hs[FZ_BM][FZ_HP];        // activations; layer 1 stages features here
   const long c0 = (long)blockIdx.x * FZ_BM;
   const int tid = threadIdx.x;
@@ -622,8 +629,28 @@ __global__ void __launch_bounds__(256) closure_mlp_region_kernel(Dims d, const T
   const float* b2 = p.master + MLP_OFF_B2;
   const float* b3 = p.master + MLP_OFF_B3;
 
-  // ---- the neighbourhood region, standardised, in BF16
-  for (int e = tid; e < 25 * RG_X; e += 256) {
+  // this wave's B operands of k chunk s (s < RG_S1: W1; then W2): lane
+  // holds 8 consecutive k of output row wv 64 + 16 j + lane % 16
+  auto load_b = [&](int s, bf16x8* b) {
+    const bool l1 = s < RG_S1;
+    const __bf16* W = l1 ? p.W1b : p.W2b;
+    const int ldw = l1 ? MLP_KIN : MLP_NH;
+    const int kk = (l1 ? s : s - RG_S1) * 32;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      b[j] = *(const __attribute__((address_space(1))) bf16x8*)(
+          W + (long)(wv * 64 + j * 16 + (lane & 15)) * ldw + kk + 8 * (lane >> 4));
+  };
+  bf16x8 wb[RG_D][4];
+#pragma unroll
+  for (int s = 0; s < RG_D; ++s) load_b(s, wb[s]);
+
+  // ---- the neighbourhood region, standardised, in BF16 (compile-time trip
+  // count: every load of the region is in flight before the first is used)
+#pragma unroll
+  for (int q = 0; q < (25 * RG_X + 255) / 256; ++q) {
+    const int e = tid + q * 256;
+    if (e >= 25 * RG_X) break;
     const int row = e / RG_X, x = e - row * RG_X;
     const int dk = row / 5, dj = row - dk * 5;
     const long pp = pidx(d, i0 - 2 + x, j0 - 2 + dj, k0c - 2 + dk);
@@ -641,29 +668,17 @@ __global__ void __launch_bounds__(256) closure_mlp_region_kernel(Dims d, const T
 #pragma unroll
       for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
   };
-  auto mma = [&](int ka) {   // one 32-deep k step: A = Hs columns [ka, ka + 32)
-    bf16x8 a[4], b[4];
+  // one 32-deep k chunk: A = Hs columns [ka, ka + 32), B from registers
+  auto mma = [&](int ka, const bf16x8* b) {
+    bf16x8 a[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
       a[i] = *(const bf16x8*)&Hs[i * 16 + (lane & 15)][ka + 8 * (lane >> 4)];
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-      b[j] = *(const bf16x8*)&Ws[wv * 64 + j * 16 + (lane & 15)][8 * (lane >> 4)];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j)
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
-  };
-  bf16x8 wreg[4];   // weight chunk rows (tid >> 2) + 64 c, k offset 8 (tid & 3)
-  auto load_w = [&](const __bf16* W, int ldw, int kk) {
-#pragma unroll
-    for (int c = 0; c < 4; ++c)
-      wreg[c] = *(const bf16x8*)(W + (long)((tid >> 2) + 64 * c) * ldw + kk + (tid & 3) * 8);
-  };
-  auto stash_w = [&]() {
-#pragma unroll
-    for (int c = 0; c < 4; ++c) *(bf16x8*)&Ws[(tid >> 2) + 64 * c][(tid & 3) * 8] = wreg[c];
   };
   auto store_h = [&](const float* bias) {
 #pragma unroll
@@ -692,30 +707,30 @@ __global__ void __launch_bounds__(256) closure_mlp_region_kernel(Dims d, const T
   };
 
   // ---- layer 1: 16 chunks of 32 features, staged alternately in columns
-  // [0, 32) and [32, 64) of Hs
+  // [0, 32) and [32, 64) of Hs.  A wave writes a column block only after
+  // the barrier of the chunk in between, which every wave reaches after its
+  // products of the chunk that last read the block.
   zero();
-  load_w(p.W1b, MLP_KIN, 0);
   __syncthreads();                  // the region is complete
-  for (int kk = 0; kk < MLP_KIN; kk += RG_K) {
-    stage_x(kk);
-    stash_w();
+#pragma unroll
+  for (int s = 0; s < RG_S1; ++s) {
+    stage_x(s * 32);
     __syncthreads();
-    if (kk + RG_K < MLP_KIN) load_w(p.W1b, MLP_KIN, kk + RG_K);
-    mma(kk % 64);
-    __syncthreads();
+    mma((s * 32) % 64, wb[s % RG_D]);
+    if (s + RG_D < RG_S1 + RG_S2) load_b(s + RG_D, wb[s % RG_D]);
   }
+  __syncthreads();                  // every wave's last feature reads are done
   store_h(b1);
+  __syncthreads();
 
-  // ---- layer 2
+  // ---- layer 2: A = the activations in Hs, no barriers
   zero();
-  load_w(p.W2b, MLP_NH, 0);
-  for (int kk = 0; kk < MLP_NH; kk += RG_K) {
-    stash_w();
-    __syncthreads();
-    if (kk + RG_K < MLP_NH) load_w(p.W2b, MLP_NH, kk + RG_K);
-    mma(kk);
-    __syncthreads();
+#pragma unroll
+  for (int s = RG_S1; s < RG_S1 + RG_S2; ++s) {
+    mma((s - RG_S1) * 32, wb[s % RG_D]);
+    if (s + RG_D < RG_S1 + RG_S2) load_b(s + RG_D, wb[s % RG_D]);
   }
+  __syncthreads();                  // every wave's reads of the layer-1 activations are done
   store_h(b2);
   __syncthreads();
 
