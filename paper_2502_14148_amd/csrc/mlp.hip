@@ -11,6 +11,7 @@
 namespace oc {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 __device__ void mlp_write_bf16(const MlpParams& p, int t, float w) {
@@ -32,10 +33,32 @@ namespace {
 
 constexpr int BM = 64, BN = 64, BK = 32, LDP = BK + 8;  // LDS rows padded by 8 bf16
 
-__device__ inline float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+// erf(z / sqrt 2) and exp(-z^2 / 2) by Abramowitz & Stegun, formula 7.1.26
+// (absolute error of erf at most 1.5e-7, far below the BF16 rounding the
+// activations get next): for x >= 0, erf x = 1 - t P(t) exp(-x^2),
+// t = 1 / (1 + p x), P a quartic; erf is odd.  About a dozen full-rate
+// instructions, a reciprocal and an exponential: the activation epilogues
+// are the bulk of the fused kernel's vector instructions.
+struct ErfGauss {
+  float erf, g;
+};
+__device__ inline ErfGauss erf_gauss(float z) {
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f * 0.70710678118654752f, fabsf(z), 1.0f));
+  float q = fmaf(1.061405429f, t, -1.453152027f);
+  q = fmaf(q, t, 1.421413741f);
+  q = fmaf(q, t, -0.284496736f);
+  q = fmaf(q, t, 0.254829592f);
+  const float g = __builtin_amdgcn_exp2f(z * z * (-0.5f * 1.44269504088896341f));
+  return {copysignf(fmaf(-(q * t), g, 1.0f), z), g};
+}
+// exact-erf GELU, z Phi(z), and its derivative
+__device__ inline float gelu(float z) {
+  const float h = 0.5f * z;
+  return fmaf(h, erf_gauss(z).erf, h);
+}
 __device__ inline float gelu_prime(float z) {
-  return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) +
-         z * __expf(-0.5f * z * z) * 0.39894228040143268f;
+  const ErfGauss r = erf_gauss(z);
+  return fmaf(0.5f, r.erf, 0.5f) + z * r.g * 0.39894228040143268f;
 }
 
 // Epilogue of one output element (m, n) of a GEMM.
@@ -610,6 +633,28 @@ __global__ void __launch_bounds__(256) closure_mlp_fused_kernel(Dims d, const T*
 // second.
 constexpr int RG_X = FZ_BM + 4, RG_P = RG_X + 4, RG_D = 2;
 constexpr int RG_S1 = MLP_KIN / 32, RG_S2 = MLP_NH / 32;   // k chunks per layer
+constexpr int RG_ROWS = 4 * 25 + 1;                         // + a row of zeros
+
+// Element offset in the region buffer of input feature f: variable f / 125
+// (u, v, w, b), row 25 var + 5 dk + dj and column di, where (dk, dj, di) are
+// the base-5 digits of f % 125; the padding features past the 500 inputs
+// read the row of zeros.
+struct RgOffsets {
+  unsigned short v[MLP_KIN];
+};
+constexpr RgOffsets make_rg_offsets() {
+  RgOffsets t{};
+  for (int f = 0; f < MLP_KIN; ++f) {
+    if (f >= MLP_NIN) {
+      t.v[f] = (unsigned short)((RG_ROWS - 1) * RG_P);
+      continue;
+    }
+    const int var = f / 125, o = f % 125;
+    t.v[f] = (unsigned short)((var * 25 + o / 5) * RG_P + o % 5);
+  }
+  return t;
+}
+__constant__ RgOffsets kRgOff = make_rg_offsets();
 
 template <class T>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
@@ -617,7 +662,7 @@ closure_mlp_region_kernel(Dims d, const T* u, const T* v,
                                                                 const T* w, const T* tt,
                                                                 const T* ss, ClosureStats st,
                                                                 MlpParams p, float* y) {
-  __shared__ __bf16 Rg[4][25][RG_P];         // (var, 5 dk + dj, x - (i0 - 2))
+  __shared__ __bf16 Rg[RG_ROWS][RG_P];       // (25 var + 5 dk + dj, x - (i0 - 2)); zero row
   __shared__ __bf16 Hs[FZ_BM][FZ_HP];        // activations; layer 1 stages features here
   const long c0 = (long)blockIdx.x * FZ_BM;
   const int tid = threadIdx.x;
@@ -654,12 +699,13 @@ closure_mlp_region_kernel(Dims d, const T* u, const T* v,
     const int row = e / RG_X, x = e - row * RG_X;
     const int dk = row / 5, dj = row - dk * 5;
     const long pp = pidx(d, i0 - 2 + x, j0 - 2 + dj, k0c - 2 + dk);
-    Rg[0][row][x] = (__bf16)(((float)u[pp] - st.in_mean[0]) * st.in_rstd[0]);
-    Rg[1][row][x] = (__bf16)(((float)v[pp] - st.in_mean[1]) * st.in_rstd[1]);
-    Rg[2][row][x] = (__bf16)(((float)w[pp] - st.in_mean[2]) * st.in_rstd[2]);
+    Rg[row][x] = (__bf16)(((float)u[pp] - st.in_mean[0]) * st.in_rstd[0]);
+    Rg[25 + row][x] = (__bf16)(((float)v[pp] - st.in_mean[1]) * st.in_rstd[1]);
+    Rg[50 + row][x] = (__bf16)(((float)w[pp] - st.in_mean[2]) * st.in_rstd[2]);
     const float b = st.g_alpha * ((float)tt[pp] - st.t_ref) - st.g_beta * ((float)ss[pp] - st.s_ref);
-    Rg[3][row][x] = (__bf16)((b - st.in_mean[3]) * st.in_rstd[3]);
+    Rg[75 + row][x] = (__bf16)((b - st.in_mean[3]) * st.in_rstd[3]);
   }
+  if (tid < RG_P) Rg[RG_ROWS - 1][tid] = (__bf16)0.0f;
 
   f32x4 acc[4][4];
   auto zero = [&]() {
@@ -668,7 +714,10 @@ closure_mlp_region_kernel(Dims d, const T* u, const T* v,
 #pragma unroll
       for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
   };
-  // one 32-deep k chunk: A = Hs columns [ka, ka + 32), B from registers
+  // one 32-deep k chunk, computed transposed: C^T = W H^T, weights (from
+  // registers) as the first operand and the cells' features or
+  // activations (Hs columns [ka, ka + 32)) as the second, so that a lane's
+  // four results are four consecutive outputs of one cell
   auto mma = [&](int ka, const bf16x8* b) {
     bf16x8 a[4];
 #pragma unroll
@@ -678,31 +727,30 @@ closure_mlp_region_kernel(Dims d, const T* u, const T* v,
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[j], a[i], acc[i][j], 0, 0, 0);
   };
+  // acc[i][j][e]: cell 16 i + lane % 16, output wv 64 + 16 j + 4 (lane / 16) + e
   auto store_h = [&](const float* bias) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) {
+      const int n = wv * 64 + j * 16 + 4 * (lane >> 4);
+      const f32x4 bn = *(const __attribute__((address_space(1))) f32x4*)(bias + n);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int n = wv * 64 + j * 16 + (lane & 15);
-        const float bn = bias[n];
+      for (int i = 0; i < 4; ++i) {
+        bf16x4 h;
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
-          Hs[i * 16 + 4 * (lane >> 4) + e][n] = (__bf16)gelu(acc[i][j][e] + bn);
+        for (int e = 0; e < 4; ++e) h[e] = (__bf16)gelu(acc[i][j][e] + bn[e]);
+        *(bf16x4*)&Hs[i * 16 + (lane & 15)][n] = h;
       }
+    }
   };
   // features [kk, kk + 32) of cell `lane`: wave wv writes features kk + 8 wv .. + 7
   auto stage_x = [&](int kk) {
-    int f = __builtin_amdgcn_readfirstlane(kk + 8 * wv);
-    int var = f / 125, o = f - var * 125;
-    int dk = o / 25, dj = (o - dk * 25) / 5, di = o - dk * 25 - dj * 5;
+    const int f0 = __builtin_amdgcn_readfirstlane(kk + 8 * wv);
+    const __bf16* rg = &Rg[0][0] + lane;
     bf16x8 xv;
 #pragma unroll
-    for (int q = 0; q < 8; ++q, ++f) {
-      xv[q] = f < MLP_NIN ? Rg[var < 3 ? var : 3][dk * 5 + dj][lane + di] : (__bf16)0.0f;
-      if (++di == 5) { di = 0; if (++dj == 5) { dj = 0; if (++dk == 5) { dk = 0; ++var; } } }
-    }
+    for (int q = 0; q < 8; ++q) xv[q] = rg[kRgOff.v[f0 + q]];
     *(bf16x8*)&Hs[lane][kk % 64 + 8 * wv] = xv;
   };
 
