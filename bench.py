@@ -10,6 +10,7 @@ oracle timed on a bounded sample of the same workload.
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 256] [--no-cpu]
 """
 import argparse
+import re
 import json
 import os
 import sys
@@ -113,15 +114,17 @@ def record_counters(fetch_dir, write_dir):
     write_copy = max(r[2] for r in wr if r[1] == copy_name)
     gib_kib = 1024.0 * 1024.0
     ff, wf = gib_kib / fetch_copy, gib_kib / write_copy
-    key = "tendency_zmarch<float, 1, 2, 32, 8, 3, false, false>"
-    tf = [r[2] for r in fr if key in r[1]]
-    tw = [r[2] for r in wr if key in r[1]]
+    # the FP32 WENO-Z kernel with two tracers, plain (no mask, no closure), any tile
+    key = re.compile(r"tendency_zmarch<float, 1, 2, (\d+), (\d+), 3, false, false>")
+    tf = [r[2] for r in fr if key.search(r[1])]
+    tw = [r[2] for r in wr if key.search(r[1])]
+    tile = next(key.search(r[1]).groups() for r in fr if key.search(r[1])) if tf else ("?", "?")
     if not tf or len(tf) != len(tw) or len(tf) % 3:
         raise SystemExit(f"expected whole RK3 steps of tendency launches, got {len(tf)}, {len(tw)}")
     per_sub = lambda v: [sum(v[s::3]) / len(v[s::3]) for s in range(3)]
     fk, wk = sum(tf) / len(tf), sum(tw) / len(tw)
     rec = {
-        "kernel": "tendency_zmarch<float, WENO-Z, 2 tracers, 32x8, R = 3>",
+        "kernel": f"tendency_zmarch<float, WENO-Z, 2 tracers, {tile[0]}x{tile[1]}, R = 3>",
         "workload": "256^3 free convection FP32",
         "source_sha256": tendency_source_sha256(),
         "sources": [os.path.relpath(f, ROOT) for f in TENDENCY_SRC],

@@ -598,7 +598,8 @@ __global__ void __launch_bounds__(TX * TY)
 }  // namespace tz
 
 // Launch the single-model kernel of radius R; scheme is tz::SCHEME_*.
-template <class T, int R, int WTX, int WTY>
+// Tracer counts above MAXNTR are not instantiated (refused).
+template <class T, int R, int WTX, int WTY, int MAXNTR = 4>
 hipError_t launch_tendency_radius(const Dims& d, const FieldSet<T>& fs, const TendParams<T>& p,
                                   int scheme, hipStream_t s) {
   const bool wide = (d.nx % WTX == 0) && (d.ny % WTY == 0);
@@ -616,6 +617,7 @@ hipError_t launch_tendency_radius(const Dims& d, const FieldSet<T>& fs, const Te
   for (int f = 0; f < MAXF; ++f) clo = clo || fs.closure[f] != nullptr;
   const bool imm = fs.mask != nullptr;
   if (imm && (R != 3 || clo)) return hipErrorInvalidValue;
+  if (p.ntr > MAXNTR) return hipErrorInvalidValue;
 #define OC_TZ(SCH, NTR_, TX_, TY_)                                                            \
   if (imm) {                                                                                  \
     if constexpr (R == 3)                                                                     \
@@ -627,12 +629,12 @@ hipError_t launch_tendency_radius(const Dims& d, const FieldSet<T>& fs, const Te
   else                                                                                        \
     hipLaunchKernelGGL((tz::tendency_zmarch<T, SCH, NTR_, TX_, TY_, R, false>), grid,          \
                        dim3(TX_ * TY_), 0, s, d, fb, p, nbx, nby, nbz, kc)
-#define OC_TZ_NTR(SCH, TX_, TY_)                \
-  switch (p.ntr) {                              \
-    case 1: OC_TZ(SCH, 1, TX_, TY_); break;     \
-    case 2: OC_TZ(SCH, 2, TX_, TY_); break;     \
-    case 3: OC_TZ(SCH, 3, TX_, TY_); break;     \
-    default: OC_TZ(SCH, 4, TX_, TY_); break;    \
+#define OC_TZ_NTR(SCH, TX_, TY_)                                  \
+  switch (p.ntr) {                                                \
+    case 1: OC_TZ(SCH, 1, TX_, TY_); break;                       \
+    case 2: if constexpr (MAXNTR >= 2) { OC_TZ(SCH, 2, TX_, TY_); } break; \
+    case 3: if constexpr (MAXNTR >= 3) { OC_TZ(SCH, 3, TX_, TY_); } break; \
+    default: if constexpr (MAXNTR >= 4) { OC_TZ(SCH, 4, TX_, TY_); } break; \
   }
 #define OC_TZ_TX(SCH)                                        \
   if (wide) { OC_TZ_NTR(SCH, WTX, WTY) } else { OC_TZ_NTR(SCH, 8, 8) }
