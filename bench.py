@@ -682,7 +682,7 @@ def main():
     ap.add_argument("--no-immersed", action="store_true")
     ap.add_argument("--no-main", action="store_true",
                     help="skip the 256^3 step (profiling the other legs alone)")
-    ap.add_argument("--ensemble-steps", type=int, default=20)
+    ap.add_argument("--ensemble-steps", type=int, default=200)
     ap.add_argument("--hydro-steps", type=int, default=20)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain 1 GiB device copy (counter calibration)")

@@ -3,9 +3,10 @@ the GPU through the C ABI.
 
 1. Truth: two high-resolution free-convection runs (a training seed and a
    held-out seed) are spun up and then continued over an evaluation window;
-   every `save_every` fine steps the state is coarse-grained by the ratio r
-   (oc_coarse_grain: integral-preserving averages and the vertical subgrid
-   fluxes <q w> - <q><w>, q = u, v, w, b).
+   every `save_every` fine steps (the training run: every `train_every`)
+   the state is coarse-grained by the ratio r (oc_coarse_grain:
+   integral-preserving averages and the vertical subgrid fluxes
+   <q w> - <q><w>, q = u, v, w, b).
 2. Training: the network (500 -> 256 -> 256 -> 4, BF16 MFMA) is trained with
    Adam on the training run's coarse snapshots: oc_closure_features gives the
    standardised 5x5x5 neighbourhoods, the targets are the standardised
@@ -186,14 +187,19 @@ def score(prof, truth):
 
 def experiment(fine=256, ratio=4, dt=10.0, spinup=8640, window=2000, save_every=4, epochs=2,
                batch=4096, lr=1e-3, train_seed=1, test_seed=2, nus=(1e-4, 1e-3, 1e-2),
-               extent=None):
+               extent=None, train_every=None):
+    """train_every: fine steps between the training run's snapshots (default
+    save_every, the spacing of the held-out run's snapshots, which is also
+    the coarse runs' time step in fine steps)."""
+    train_every = train_every or save_every
     nc = fine // ratio
     L = extent or (2.0 * fine, 2.0 * fine, 1.0 * fine)
     fph = inputs.convection_physics((fine, fine, fine), L)
     cph = inputs.convection_physics((nc, nc, nc), L)
     cph.closure = True
     _log(f"truth runs {fine}^3 (train seed {train_seed}, held-out seed {test_seed})")
-    tr_snaps, tr_flux, _, t_tr = truth_run(fph, cph, train_seed, dt, spinup, window, save_every, True)
+    tr_snaps, tr_flux, _, t_tr = truth_run(fph, cph, train_seed, dt, spinup, window, train_every,
+                                           True)
     te_snaps, te_flux, te_prof, t_te = truth_run(fph, cph, test_seed, dt, spinup, window,
                                                  save_every, True)
     mean, std = input_stats(cph, tr_snaps[::max(1, len(tr_snaps) // 20)])
@@ -219,6 +225,7 @@ def experiment(fine=256, ratio=4, dt=10.0, spinup=8640, window=2000, save_every=
     coarse_cs = nc ** 3 * (ns - 1)
     return {"fine": fine, "coarse": nc, "ratio": ratio, "dt_fine_s": dt, "dt_coarse_s": dtc,
             "spinup_steps": spinup, "window_fine_steps": window, "snapshots": ns,
+            "training_snapshots": len(tr_snaps), "training_snapshot_every_fine_steps": train_every,
             "cell_step_ratio": fine_cs / coarse_cs,
             "train_loss_first": losses[0], "train_loss_last": float(np.mean(losses[-5:])),
             "heldout_loss": hl, "runs": res,
@@ -235,11 +242,13 @@ def main():
     ap.add_argument("--spinup", type=int, default=8640)
     ap.add_argument("--window", type=int, default=2000)
     ap.add_argument("--save-every", type=int, default=4)
+    ap.add_argument("--train-every", type=int, default=1,
+                    help="fine steps between training snapshots (1: 2001 snapshots)")
     ap.add_argument("--epochs", type=int, default=2)
     ap.add_argument("--lr", type=float, default=1e-3)
     a = ap.parse_args()
     out = experiment(fine=a.fine, ratio=a.ratio, dt=a.dt, spinup=a.spinup, window=a.window,
-                     save_every=a.save_every, epochs=a.epochs, lr=a.lr)
+                     save_every=a.save_every, epochs=a.epochs, lr=a.lr, train_every=a.train_every)
     print(json.dumps(out))
 
 

@@ -263,7 +263,9 @@ __global__ void __launch_bounds__(NT) y_kernel(Dims d, SpecBufs sb,
   __shared__ double2 buf[W * N];
   __shared__ double2 tws[N];
   stage_twiddles<N>(tws, sb.twy);
-  const int k = blockIdx.y;
+  // the forward pass takes the planes in the reverse of the order the x pass
+  // wrote them, so it starts on the ones most likely still in the caches
+  const int k = DIR < 0 ? (int)gridDim.y - 1 - (int)blockIdx.y : (int)blockIdx.y;
   const int kx0 = blockIdx.x * W;
   const int nxh = sb.nxh, nxp = sb.nxp;
   double2* plane = sb.spec + (long)k * d.ny * nxp + kx0;
