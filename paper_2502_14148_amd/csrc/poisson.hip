@@ -126,15 +126,114 @@ __device__ inline void stockham_pass(double2* buf, int ls, int es, const double2
 // saves a quarter of the LDS round trips; it pays in the y and z passes
 // (eight interleaved lines: one butterfly per thread) and not in the x
 // passes, whose few lines leave half the threads idle at radix 8.
+template <int REM, int MAXR>
+constexpr int pass_radix() {
+  return (MAXR >= 8 && REM % 8 == 0) ? 8 : ((REM % 4 == 0) ? 4 : ((REM % 2 == 0) ? 2 : 3));
+}
+
 template <int N, int NS, int L, int NT, int DIR, bool LINE_FAST, int MAXR = 4>
 __device__ inline void fft_lines(double2* buf, int ls, int es, const double2* __restrict__ tw) {
   if constexpr (NS < N) {
-    constexpr int REM = N / NS;
-    constexpr int R = (MAXR >= 8 && REM % 8 == 0)
-                          ? 8
-                          : ((REM % 4 == 0) ? 4 : ((REM % 2 == 0) ? 2 : 3));
+    constexpr int R = pass_radix<N / NS, MAXR>();
     stockham_pass<N, R, NS, L, NT, DIR, LINE_FAST>(buf, ls, es, tw);
     fft_lines<N, NS * R, L, NT, DIR, LINE_FAST, MAXR>(buf, ls, es, tw);
+  }
+}
+
+// Interleaved lines (buf[n * L + line], consecutive threads on consecutive
+// lines) whose first pass takes its inputs from global memory, load(line, n),
+// instead of from a staged copy in LDS: the tile's load and the first pass
+// share one trip, and only the pass's outputs go to LDS.  (The first pass
+// has no twiddles; the barrier after it also covers the twiddle staging.)
+template <int N, int L, int NT, int DIR, int MAXR, class Load>
+__device__ inline void first_pass_from(double2* buf, const Load& load) {
+  constexpr int R = pass_radix<N, MAXR>();
+  constexpr int M = N / R, NB = L * M, BPT = (NB + NT - 1) / NT;
+  double2 v[BPT][R];
+#pragma unroll
+  for (int q = 0; q < BPT; ++q) {
+    const int b = threadIdx.x + q * NT;
+    if (NB % NT == 0 || b < NB) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[q][r] = load(b % L, b / L + r * M);
+      dft<R, DIR>(v[q]);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < BPT; ++q) {
+    const int b = threadIdx.x + q * NT;
+    if (NB % NT == 0 || b < NB) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[((b / L) * R + r) * L + b % L] = v[q][r];
+    }
+  }
+  __syncthreads();
+}
+template <int N, int L, int NT, int DIR, int MAXR, class Load>
+__device__ inline void fft_lines_from(double2* buf, const double2* __restrict__ tw,
+                                      const Load& load) {
+  first_pass_from<N, L, NT, DIR, MAXR>(buf, load);
+  fft_lines<N, pass_radix<N, MAXR>(), L, NT, DIR, true, MAXR>(buf, 1, L, tw);
+}
+
+// The same lines whose last pass hands its outputs to store(line, n, value)
+// (global memory) instead of writing them back to LDS.
+template <int N, int NS, int L, int NT, int DIR, int MAXR, class Store>
+__device__ inline void fft_lines_to(double2* buf, const double2* __restrict__ tw,
+                                    const Store& store) {
+  constexpr int R = pass_radix<N / NS, MAXR>();
+  if constexpr (NS * R < N) {
+    stockham_pass<N, R, NS, L, NT, DIR, true>(buf, 1, L, tw);
+    fft_lines_to<N, NS * R, L, NT, DIR, MAXR>(buf, tw, store);
+  } else {
+    constexpr int M = N / R, NB = L * M, BPT = (NB + NT - 1) / NT;
+#pragma unroll
+    for (int q = 0; q < BPT; ++q) {
+      const int b = threadIdx.x + q * NT;
+      if (NB % NT == 0 || b < NB) {
+        const int line = b % L, jj = b / L, k = jj % NS;
+        double2 v[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          double2 x = buf[(jj + r * M) * L + line];
+          if (r > 0 && NS > 1) {
+            double2 w = tw[(r * k) * (N / (NS * R))];
+            if (DIR > 0) w = cconj(w);
+            x = cmul(x, w);
+          }
+          v[r] = x;
+        }
+        dft<R, DIR>(v);
+        const int d = (jj / NS) * NS * R + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r) store(line, d + r * NS, v[r]);
+      }
+    }
+  }
+}
+
+// Both: the first pass from global memory, the last one to it.
+template <int N, int L, int NT, int DIR, int MAXR, class Load, class Store>
+__device__ inline void fft_lines_io(double2* buf, const double2* __restrict__ tw, const Load& load,
+                                    const Store& store) {
+  constexpr int R = pass_radix<N, MAXR>();
+  if constexpr (R == N) {   // one pass
+    constexpr int NB = L, BPT = (NB + NT - 1) / NT;
+#pragma unroll
+    for (int q = 0; q < BPT; ++q) {
+      const int b = threadIdx.x + q * NT;
+      if (NB % NT == 0 || b < NB) {
+        double2 v[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[r] = load(b, r);
+        dft<R, DIR>(v);
+#pragma unroll
+        for (int r = 0; r < R; ++r) store(b, r, v[r]);
+      }
+    }
+  } else {
+    first_pass_from<N, L, NT, DIR, MAXR>(buf, load);
+    fft_lines_to<N, R, L, NT, DIR, MAXR>(buf, tw, store);
   }
 }
 
@@ -269,32 +368,25 @@ __global__ void __launch_bounds__(NT) y_kernel(Dims d, SpecBufs sb,
   const int kx0 = blockIdx.x * W;
   const int nxh = sb.nxh, nxp = sb.nxp;
   double2* plane = sb.spec + (long)k * d.ny * nxp + kx0;
-  constexpr int PER = (W * N + NT - 1) / NT;
-#pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    const int t = threadIdx.x + q * NT;
-    if ((W * N) % NT != 0 && t >= W * N) break;
-    const int c = t % W, y = t / W;
-    buf[t] = (kx0 + c < nxh) ? ld2(plane, (long)y * nxp + c) : make_double2(0.0, 0.0);
-  }
-  __syncthreads();
-  fft_lines<N, 1, W, NT, DIR, true, 8>(buf, 1, W, tws);
-#pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    const int t = threadIdx.x + q * NT;
-    if ((W * N) % NT != 0 && t >= W * N) break;
-    const int c = t % W, y = t / W;
-    if (kx0 + c < nxh) st2(plane, (long)y * nxp + c, buf[t]);
-  }
+  const int ncol = nxh - kx0;   // valid columns of this block (W or fewer)
+  fft_lines_io<N, W, NT, DIR, 8>(
+      buf, tws,
+      [&](int c, int y) {
+        return c < ncol ? ld2(plane, (long)y * nxp + c) : make_double2(0.0, 0.0);
+      },
+      [&](int c, int y, double2 x) {
+        if (c < ncol) st2(plane, (long)y * nxp + c, x);
+      });
 }
 
 // ---------------------------------------------------------------------------
 // Pass 3: along z, forward transform, division by the eigenvalue (with the
 // 1/(nx ny nz) normalisation of the unnormalised inverses), inverse.
 // ---------------------------------------------------------------------------
-__device__ inline int makhoul_pos(int m, int n) {
-  // DCT-II via an N-point FFT: v[n'] = x[2n'], v[N-1-n'] = x[2n'+1]
-  return (m & 1) ? (n - 1 - (m >> 1)) : (m >> 1);
+// DCT-II via an N-point FFT (Makhoul): v[n'] = x[2n'], v[N-1-n'] = x[2n'+1];
+// the source level of position p
+__device__ inline int makhoul_src(int p, int n) {
+  return (p < n / 2) ? 2 * p : 2 * (n - 1 - p) + 1;
 }
 
 // The division, and on walls the DCT post- and pre-processing around it,
@@ -367,7 +459,6 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4)))
   if (sb.stop && *glb(sb.stop) != 0.0) return;
   if (bs) sb.spec = bs->spec[blockIdx.z];
   constexpr int W = YZCfg<N>::W;
-  constexpr int PER = (W * N + NT - 1) / NT;
   __shared__ double2 buf[W * N];
   __shared__ double2 tws[N];
   const int j = blockIdx.y;
@@ -378,27 +469,18 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4)))
   stage_twiddles<N>(tws, sb.twz);
   const long zs = (long)d.ny * nxp;
   double2* col = sb.spec + (long)j * nxp + kx0;
-#pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    const int t = threadIdx.x + q * NT;
-    if ((W * N) % NT != 0 && t >= W * N) break;
-    const int c = t % W, z = t / W;
-    const int pos = BOUNDED ? makhoul_pos(z, N) : z;
-    buf[pos * W + c] = (kx0 + c < nxh) ? ld2(col, (long)z * zs + c) : make_double2(0.0, 0.0);
-  }
-  __syncthreads();
-  fft_lines<N, 1, W, NT, -1, true, 8>(buf, 1, W, tws);
+  const int ncol = nxh - kx0;   // valid columns of this block (W or fewer)
+  // transform position n holds level makhoul_src(n) (DCT-II by Makhoul's
+  // reordering) on walls, level n when periodic
+  auto level = [](int n) { return BOUNDED ? makhoul_src(n, N) : n; };
+  fft_lines_from<N, W, NT, -1, 8>(buf, tws, [&](int c, int n) {
+    return c < ncol ? ld2(col, (long)level(n) * zs + c) : make_double2(0.0, 0.0);
+  });
   pairs.apply(buf, sb.dctz);
   __syncthreads();
-  fft_lines<N, 1, W, NT, 1, true, 8>(buf, 1, W, tws);
-#pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    const int t = threadIdx.x + q * NT;
-    if ((W * N) % NT != 0 && t >= W * N) break;
-    const int c = t % W, z = t / W;
-    const int pos = BOUNDED ? makhoul_pos(z, N) : z;
-    if (kx0 + c < nxh) st2(col, (long)z * zs + c, buf[pos * W + c]);
-  }
+  fft_lines_to<N, 1, W, NT, 1, 8>(buf, tws, [&](int c, int n, double2 x) {
+    if (c < ncol) st2(col, (long)level(n) * zs + c, x);
+  });
 }
 
 // ---------------------------------------------------------------------------
