@@ -721,25 +721,95 @@ int implicit_call(oc_model* m, int which, int st, hipStream_t s) {
 }
 
 template <class T>
+int rk3_step_enqueue(oc_model* m, double dt, hipStream_t s) {
+  for (int st = 0; st < 3; ++st) {
+    const int in = m->cur, out = 1 - m->cur;
+    int rc = tendency_call<T>(m, in, out, st, dt, 1, s);
+    if (rc) return rc;
+    if (m->md.implicit_z) {
+      rc = implicit_call<T>(m, out, st, s);
+      if (rc) return rc;
+    }
+    // the projection writes the velocity halos, the tendency kernel those
+    // of the tracers
+    rc = pressure_call<T>(m, out, (RK_GAMMA[st] - RK_ZETA[st]) * dt, s);
+    if (rc) return rc;
+    m->cur = out;
+  }
+  return OC_OK;
+}
+
+// Graphs are replaced only after the device has finished every launch of
+// them (a replaced graph may still be running on the caller's stream).
+void drop_step_graph(oc_model* m, int p) {
+  if (!m->gexec[p]) return;
+  (void)hipDeviceSynchronize();
+  (void)hipGraphExecDestroy(m->gexec[p]);
+  m->gexec[p] = nullptr;
+}
+void drop_step_graphs(oc_model* m) {
+  drop_step_graph(m, 0);
+  drop_step_graph(m, 1);
+}
+
+// Capture one RK3 step from buffer parity p as a graph (nothing runs).
+template <class T>
+int capture_step_graph(oc_model* m, double dt, int p) {
+  drop_step_graph(m, p);
+  if (!m->gcap && hipStreamCreateWithFlags(&m->gcap, hipStreamNonBlocking) != hipSuccess) {
+    m->gcap = nullptr;
+    set_error("capture stream creation failed");
+    return OC_ERR_DEVICE;
+  }
+  hipGraph_t g;
+  OC_CHECK_HIP(hipStreamBeginCapture(m->gcap, hipStreamCaptureModeThreadLocal));
+  const int cur0 = m->cur;
+  m->cur = p;
+  const int rc = rk3_step_enqueue<T>(m, dt, m->gcap);
+  m->cur = cur0;
+  const hipError_t ce = hipStreamEndCapture(m->gcap, &g);
+  if (rc) {
+    if (ce == hipSuccess) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (ce != hipSuccess) {
+    set_error("graph capture failed: %s", hipGetErrorString(ce));
+    return OC_ERR_DEVICE;
+  }
+  const hipError_t ie = hipGraphInstantiate(&m->gexec[p], g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ie != hipSuccess) {
+    m->gexec[p] = nullptr;
+    set_error("graph instantiation failed: %s", hipGetErrorString(ie));
+    return OC_ERR_DEVICE;
+  }
+  m->gdt[p] = dt;
+  return OC_OK;
+}
+
+// Several steps in one call replay a captured step (one graph launch instead
+// of 21 or more kernel launches); a single step, a profiled run and the
+// immersed-boundary path (its iteration reads its residual on the host) are
+// launched directly.
+template <class T>
 int rk3_steps(oc_model* m, double dt, int nsteps, hipStream_t s) {
   if (m->md.implicit_z) {
     int rc = implicit_factors<T>(m, dt, 0, s);
     if (rc) return rc;
   }
+  const bool graphs = nsteps >= 2 && !m->prof_on && !m->md.immersed;
   for (int n = 0; n < nsteps; ++n) {
-    for (int st = 0; st < 3; ++st) {
-      const int in = m->cur, out = 1 - m->cur;
-      int rc = tendency_call<T>(m, in, out, st, dt, 1, s);
-      if (rc) return rc;
-      if (m->md.implicit_z) {
-        rc = implicit_call<T>(m, out, st, s);
+    if (graphs) {
+      const int p = m->cur;
+      if (!m->gexec[p] || m->gdt[p] != dt) {
+        int rc = capture_step_graph<T>(m, dt, p);
         if (rc) return rc;
       }
-      // the projection writes the velocity halos, the tendency kernel those
-      // of the tracers
-      rc = pressure_call<T>(m, out, (RK_GAMMA[st] - RK_ZETA[st]) * dt, s);
+      OC_CHECK_HIP(hipGraphLaunch(m->gexec[p], s));
+      m->cur ^= 1;   // three substages
+    } else {
+      int rc = rk3_step_enqueue<T>(m, dt, s);
       if (rc) return rc;
-      m->cur = out;
     }
   }
   return OC_OK;
@@ -1373,6 +1443,8 @@ int oc_model_destroy(oc_model* m) {
   if (m) {
     for (hipEvent_t e : m->ev_pool) (void)hipEventDestroy(e);
     if (m->cg_host) (void)hipHostFree(m->cg_host);
+    drop_step_graphs(m);
+    if (m->gcap) (void)hipStreamDestroy(m->gcap);
   }
   delete m;
   return OC_OK;
@@ -1651,6 +1723,7 @@ int oc_hydrostatic_step(oc_model* m, double dt, int32_t N, int32_t M, const doub
 
 int oc_model_set_closure(oc_model* m, oc_mlp* net, const double* stats, void* stream) {
   if (!m) { set_error("model is NULL"); return OC_ERR_ARG; }
+  drop_step_graphs(m);   // captured steps launch the closure kernels with these arguments
   if (!net) { m->net = nullptr; return OC_OK; }
   if (m->kind != OC_NONHYDROSTATIC || !m->dims.zb || !m->md.buoyancy || !m->md.closure ||
       m->stretched) {

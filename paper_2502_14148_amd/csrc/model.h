@@ -111,6 +111,12 @@ struct oc_model {
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used;
   std::vector<int> prof_cls;  // class of each recorded (start, stop) pair
+  // whole RK3 steps captured as HIP graphs, one per starting buffer parity,
+  // for the time step gdt[p] (the kernels take both as arguments); gcap is
+  // the capture stream, which never runs work
+  hipStream_t gcap = nullptr;
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  double gdt[2] = {0.0, 0.0};
 };
 
 namespace oc {
