@@ -238,8 +238,13 @@ int oc_get_tendency(oc_model* m, int32_t field, void* buf, int32_t dtype,
 
 /* Pressure correction of the current velocity as a predictor:
  * rhs = div(u)/dt_eff, solve lap p = rhs (mean-zero p), u -= dt_eff grad p
- * at interior faces, halos refilled.  p is kept in FP64 (oc_get_pressure,
- * shape (nz, ny, nx), dtype OC_F64).  Errors: OC_ERR_ARG if dt_eff <= 0. */
+ * at interior faces, halos refilled.  Errors: OC_ERR_ARG if dt_eff <= 0.
+ * oc_get_pressure copies the p of the model's last solve (this call, or the
+ * last substage of oc_rk3_step / oc_ensemble_step) to buf: FP64, shape
+ * (nz, ny, nx).  Without an immersed boundary the solve keeps p only as its
+ * x-spectrum (the projection transforms it on the fly), and the first
+ * oc_get_pressure after a solve enqueues the inverse x transform on
+ * `stream` before the copy; with on_device = 0 it waits for the copy. */
 int oc_pressure_solve(oc_model* m, double dt_eff, void* stream);
 int oc_get_pressure(oc_model* m, double* buf, int32_t on_device, void* stream);
 
@@ -292,6 +297,11 @@ enum {
 #define OC_NPROF 15
 int oc_profile(oc_model* m, int32_t enable);
 int oc_profile_read(oc_model* m, double* ms, int64_t* launches);
+/* Restrict the event recording to the classes whose bit (1 << OC_PROF_*) is
+ * set in `classes` (a model starts with all of them): a run that times only
+ * one kernel class records two events per launch of that class and none
+ * around the others.  Bits at or above OC_NPROF: OC_ERR_ARG. */
+int oc_profile_classes(oc_model* m, uint32_t classes);
 
 /* Split-explicit barotropic mode of the hydrostatic model (hydrostatic
  * time-discretisation appendix): M forward-backward substeps of length

@@ -373,7 +373,8 @@ struct ProfScope {
   oc_model* m;
   hipStream_t s;
   bool on;
-  ProfScope(oc_model* m_, int cls, hipStream_t s_) : m(m_), s(s_), on(m_->prof_on != 0) {
+  ProfScope(oc_model* m_, int cls, hipStream_t s_)
+      : m(m_), s(s_), on(m_->prof_on != 0 && ((m_->prof_mask >> cls) & 1u)) {
     if (!on) return;
     while (m->ev_pool.size() < m->ev_used + 2) {
       hipEvent_t e;
@@ -571,6 +572,7 @@ int pressure_call_immersed(oc_model* m, int which, double dt_eff, hipStream_t s)
   const double tol2 = m->md.cg_tol * m->md.cg_tol;
   const int maxit = m->md.cg_maxiter;
   const double* z = m->sb.p;
+  m->p_pending = false;   // sb.p is the iteration's work vector, then the solution
   {
     ProfScope pc(m, OC_PROF_CG, s);
     OC_CHECK_HIP(launch_ib_rhs<T>(d, u, v, w, m->ibits, 1.0 / dt_eff, 1.0 / m->dx,
@@ -660,14 +662,12 @@ int pressure_call(oc_model* m, int which, double dt_eff, hipStream_t s) {
     OC_CHECK_HIP(launch_poisson_y(m->dims, m->sb, 1, s));
   }
   {
-    ProfScope ps(m, OC_PROF_FFT_X_INV, s);
-    OC_CHECK_HIP(launch_poisson_x_inverse(m->dims, m->sb, s));
-  }
-  {
     ProfScope ps(m, OC_PROF_PROJECT, s);
-    OC_CHECK_HIP(launch_project<T>(m->dims, (T*)m->state[which][0], (T*)m->state[which][1],
-                                   (T*)m->state[which][2], dt_eff, sp, m->sb.p, s));
+    OC_CHECK_HIP(launch_poisson_x_inverse_project<T>(m->dims, m->sb, (T*)m->state[which][0],
+                                                     (T*)m->state[which][1],
+                                                     (T*)m->state[which][2], dt_eff, sp, s));
   }
+  m->p_pending = true;
   return OC_OK;
 }
 
@@ -807,6 +807,7 @@ int rk3_steps(oc_model* m, double dt, int nsteps, hipStream_t s) {
       }
       OC_CHECK_HIP(hipGraphLaunch(m->gexec[p], s));
       m->cur ^= 1;   // three substages
+      m->p_pending = true;   // the replayed solves leave p as a spectrum
     } else {
       int rc = rk3_step_enqueue<T>(m, dt, s);
       if (rc) return rc;
@@ -1312,6 +1313,7 @@ int oc_model_create(const oc_grid* g, const oc_model_desc* md, void* workspace,
   for (int q = 0; q < MAXF; ++q) m->G[q] = m->ws + L.G[q];
   m->cur = 0;
   m->prof_on = 0;
+  m->prof_mask = (1u << OC_NPROF) - 1;
   m->ev_used = 0;
   m->dx = g->d.lx / g->d.nx;
   m->dy = g->d.ly / g->d.ny;
@@ -1460,6 +1462,13 @@ int oc_profile(oc_model* m, int32_t enable) {
   return OC_OK;
 }
 
+int oc_profile_classes(oc_model* m, uint32_t classes) {
+  if (!m) { set_error("model is NULL"); return OC_ERR_ARG; }
+  if (classes >> OC_NPROF) { set_error("unknown profiling class bit"); return OC_ERR_ARG; }
+  m->prof_mask = classes;
+  return OC_OK;
+}
+
 int oc_profile_read(oc_model* m, double* ms, int64_t* launches) {
   if (!m || !ms || !launches) { set_error("NULL argument"); return OC_ERR_ARG; }
   for (int c = 0; c < OC_NPROF; ++c) { ms[c] = 0.0; launches[c] = 0; }
@@ -1571,6 +1580,10 @@ int oc_get_pressure(oc_model* m, double* buf, int32_t on_device, void* stream) {
   if (m->kind != OC_NONHYDROSTATIC) { set_error("nonhydrostatic model only"); return OC_ERR_UNSUPPORTED; }
   hipStream_t s = (hipStream_t)stream;
   const size_t bytes = (size_t)m->dims.nz * m->dims.ny * m->dims.nx * 8;
+  if (m->p_pending) {
+    OC_CHECK_HIP(launch_poisson_x_inverse(m->dims, m->sb, s));
+    m->p_pending = false;
+  }
   OC_CHECK_HIP(hipMemcpyAsync(buf, m->sb.p, bytes,
                               on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
   if (!on_device) OC_CHECK_HIP(hipStreamSynchronize(s));

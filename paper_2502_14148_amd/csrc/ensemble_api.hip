@@ -264,9 +264,9 @@ int enqueue_step(oc_ensemble* e, int p, double dt, hipStream_t s) {
       OC_CHECK_HIP(launch_poisson_y(m0->dims, m0->sb, -1, s, bs, ns));
       OC_CHECK_HIP(launch_poisson_spectral(m0->dims, m0->sb, s, bs, ns));
       OC_CHECK_HIP(launch_poisson_y(m0->dims, m0->sb, 1, s, bs, ns));
-      OC_CHECK_HIP(launch_poisson_x_inverse(m0->dims, m0->sb, s, bs, ns));
-      OC_CHECK_HIP(launch_project<T>(m0->dims, (T*)nullptr, (T*)nullptr, (T*)nullptr, dt_eff,
-                                     sp, nullptr, s, bs, ns));
+      OC_CHECK_HIP(launch_poisson_x_inverse_project<T>(m0->dims, m0->sb, (T*)nullptr,
+                                                       (T*)nullptr, (T*)nullptr, dt_eff, sp, s,
+                                                       bs, ns));
     }
   }
   return OC_OK;
@@ -505,7 +505,10 @@ int ens_step(oc_ensemble* e, double dt, int nsteps, hipStream_t s) {
     }
     e->phase ^= 1;
   }
-  for (size_t i = 0; i < e->mem.size(); ++i) e->mem[i]->cur = e->cur0[i] ^ e->phase;
+  for (size_t i = 0; i < e->mem.size(); ++i) {
+    e->mem[i]->cur = e->cur0[i] ^ e->phase;
+    if (nsteps > 0) e->mem[i]->p_pending = true;   // p left as a spectrum
+  }
   return OC_OK;
 }
 

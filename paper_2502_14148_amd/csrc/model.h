@@ -108,6 +108,7 @@ struct oc_model {
   double cg_residual;
   // per-kernel-class event timing
   int prof_on;
+  uint32_t prof_mask;         // classes that record events (bit OC_PROF_*)
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used;
   std::vector<int> prof_cls;  // class of each recorded (start, stop) pair
@@ -117,6 +118,9 @@ struct oc_model {
   hipStream_t gcap = nullptr;
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   double gdt[2] = {0.0, 0.0};
+  // the last solve's p is still only in sb.spec (the fused inverse x pass
+  // and projection does not write it); oc_get_pressure transforms it first
+  bool p_pending = false;
 };
 
 namespace oc {

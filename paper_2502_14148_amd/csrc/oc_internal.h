@@ -463,6 +463,13 @@ template <class T>
 hipError_t launch_project(const Dims& d, T* u, T* v, T* w, double scale, const Spacing& sp,
                           const double* p, hipStream_t s, const PoissonSlots* bs = nullptr,
                           int nslots = 1, const T* mask = nullptr);
+// The inverse x pass fused with the projection: u, v, w -= scale grad p with
+// p taken from sb.spec on the fly; sb.p is not written (launch
+// launch_poisson_x_inverse on the same spectrum for it).
+template <class T>
+hipError_t launch_poisson_x_inverse_project(const Dims& d, const SpecBufs& sb, T* u, T* v, T* w,
+                                            double scale, const Spacing& sp, hipStream_t s,
+                                            const PoissonSlots* bs = nullptr, int nslots = 1);
 // The forward x transform of a dense FP64 (nz, ny, nx) field into sb.spec
 // (the first pass of the FFT solve applied to a given right-hand side).
 hipError_t launch_poisson_x_forward_dense(const Dims& d, const double* src, const SpecBufs& sb,

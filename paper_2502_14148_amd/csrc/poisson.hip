@@ -19,6 +19,8 @@
 // per thread per pass, twiddles from FP64 tables.
 #include "oc_internal.h"
 
+#include <algorithm>
+
 namespace oc {
 
 __device__ inline double2 cmul(double2 a, double2 b) {
@@ -785,6 +787,146 @@ __global__ void __launch_bounds__(PJ_X * PJ_Y) project_kernel(
 }
 
 // ---------------------------------------------------------------------------
+// Pass 5 fused with the projection (the FFT/DCT solve of the whole box).  A
+// workgroup takes RB = 2 LP - 1 rows, j0 .. j0 + RB - 1, and a chunk of PX_KC
+// levels.  At every level it transforms LP packed lines back to p: line l
+// holds rows j0 - 1 + 2l and j0 + 2l (Z = X_a + i X_b of their Hermitian half
+// rows), so the row below the block (periodic in y) comes along in line 0.
+// It then subtracts scale * grad p from u, v and w of its rows: p at i - 1
+// and j - 1 come from the lines in LDS, p of the level below from registers
+// (the level below the chunk is transformed once more first).  p is not
+// written: the spectrum stays in its buffer, and the stand-alone pass 5
+// turns it into p when p is asked for.  The chunk length kc is chosen by the
+// launcher so that the grid fits in one round of resident workgroups.
+// ---------------------------------------------------------------------------
+
+template <class T, int N>
+__global__ void __launch_bounds__(NT) inv_x_project_kernel(
+    Dims d, SpecBufs sb, T* __restrict__ u, T* __restrict__ v, T* __restrict__ w, double scale,
+    double rdx, double rdy, const double* __restrict__ rdzf, int kc,
+    const PoissonSlots* __restrict__ bs) {
+  if (bs) {
+    const int z = blockIdx.z;
+    u = (T*)bs->u[z];
+    v = (T*)bs->v[z];
+    w = (T*)bs->w[z];
+    sb.spec = bs->spec[z];
+  }
+  constexpr int L = XCfg<N>::LP, RB = 2 * L - 1, CELLS = RB * N;
+  constexpr int CPT = (CELLS + NT - 1) / NT;
+  constexpr int R0 = pass_radix<N, 4>();
+  __shared__ double2 buf[L * N];
+  __shared__ double2 tws[N];
+  stage_twiddles<N>(tws, sb.twx);
+  // Workgroups are dealt round-robin to the 8 XCDs: XCD x takes tiles
+  // x, x + 8, ...; renumber them so that each XCD works on a contiguous run
+  // (row blocks fastest, then the level chunk), whose shared rows and levels
+  // stay in its L2
+  const int ntile = (int)(gridDim.x * gridDim.y);
+  const int bid = (int)(blockIdx.x + blockIdx.y * gridDim.x), xcd = bid % 8;
+  const int lin = xcd * (ntile / 8) + min(xcd, ntile % 8) + bid / 8;
+  const int j0 = (lin % (int)gridDim.x) * RB;
+  const int k0 = (lin / (int)gridDim.x) * kc;
+  const int k1 = min(k0 + kc, d.nz);
+  const int nxp = sb.nxp, ny = d.ny;
+  const auto gu = glb(u), gv = glb(v), gw = glb(w);
+  // The first Stockham pass, one radix-R0 butterfly per thread (L N / R0 =
+  // 1024 / R0 <= NT), takes its points from registers: fetch(k) issues the
+  // loads of level k, first() combines each row pair (with the Hermitian
+  // extension) and writes the pass's outputs.  The loads of level k + 1 are
+  // issued right after level k's first pass, so they travel while level k
+  // is transformed and projected.
+  constexpr int M0 = N / R0;
+  static_assert(L * M0 <= NT, "one first-pass butterfly per thread");
+  const int bl = (int)threadIdx.x / M0, bj = (int)threadIdx.x % M0;
+  const bool bact = (int)threadIdx.x < L * M0;
+  const int ja = (bl == 0 && j0 == 0) ? ny - 1 : j0 - 1 + 2 * bl, jb = j0 + 2 * bl;
+  const bool has_a = bact && ja < ny, has_b = bact && jb < ny;
+  double2 fa[R0], fb[R0];
+  auto fetch = [&](int k) {
+    const long lvl = (long)k * ny;
+#pragma unroll
+    for (int r = 0; r < R0; ++r) {
+      const int n = bj + r * M0, m = n <= N / 2 ? n : N - n;
+      fa[r] = has_a ? ld2(sb.spec, (lvl + ja) * nxp + m) : make_double2(0.0, 0.0);
+      fb[r] = has_b ? ld2(sb.spec, (lvl + jb) * nxp + m) : make_double2(0.0, 0.0);
+    }
+  };
+  auto first = [&]() {
+    if (bact) {
+      double2 x[R0];
+#pragma unroll
+      for (int r = 0; r < R0; ++r) {
+        const bool lo = bj + r * M0 <= N / 2;
+        x[r] = cadd(lo ? fa[r] : cconj(fa[r]), mul_i<1>(lo ? fb[r] : cconj(fb[r])));
+      }
+      dft<R0, 1>(x);
+#pragma unroll
+      for (int r = 0; r < R0; ++r) buf[bl * N + bj * R0 + r] = x[r];
+    }
+    __syncthreads();
+  };
+  auto rest = [&]() { fft_lines<N, R0, L, NT, 1, false>(buf, N, 1, tws); };
+  // p at row r of the block (r = -1: the row below) and column i
+  auto pat = [&](int r, int i) -> double {
+    const double2 z = buf[((r + 1) >> 1) * N + i];
+    return (r & 1) ? z.x : z.y;
+  };
+  double pb[CPT];
+  const bool below = !d.zb || k0 > 0;
+  if (!below) fetch(k0);
+  if (below) {
+    fetch(k0 > 0 ? k0 - 1 : d.nz - 1);
+    first();
+    fetch(k0);
+    rest();
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+      const int c = threadIdx.x + q * NT;
+      pb[q] = (CELLS % NT == 0 || c < CELLS) ? pat(c / N, c % N) : 0.0;
+    }
+  }
+  for (int k = k0; k < k1; ++k) {
+    // this level's velocities, in flight during the transform
+    T uu[CPT], vv[CPT], ww[CPT];
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+      const int c = threadIdx.x + q * NT;
+      const int j = j0 + c / N;
+      if ((CELLS % NT == 0 || c < CELLS) && j < ny) {
+        const long o = pidx(d, c % N, j, k);
+        uu[q] = gu[o];
+        vv[q] = gv[o];
+        ww[q] = gw[o];
+      }
+    }
+    if (below || k > k0) __syncthreads();   // the lines of the level below are read
+    first();
+    if (k + 1 < k1) fetch(k + 1);   // the next level's loads, in flight meanwhile
+    rest();
+    const double rz = rdzf[k];
+    const bool wk = !d.zb || k > 0;
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+      const int c = threadIdx.x + q * NT;
+      const int r = c / N, i = c % N, j = j0 + r;
+      if ((CELLS % NT == 0 || c < CELLS) && j < ny) {
+        const double p0 = pat(r, i);
+        const double pxm = pat(r, i == 0 ? N - 1 : i - 1);
+        const double pym = pat(r - 1, i);
+        const T un = (T)((double)uu[q] - scale * (p0 - pxm) * rdx);
+        const T vn = (T)((double)vv[q] - scale * (p0 - pym) * rdy);
+        const T wn = wk ? (T)((double)ww[q] - scale * (p0 - pb[q]) * rz) : ww[q];
+        pb[q] = p0;
+        store_with_images(u, d, i, j, k, un, false);
+        store_with_images(v, d, i, j, k, vn, false);
+        store_with_images(w, d, i, j, k, wn, true);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Launchers: dispatch on the (compile-time) transform lengths.
 // ---------------------------------------------------------------------------
 bool fft_length_supported(int n) {
@@ -890,6 +1032,44 @@ hipError_t launch_poisson_x_inverse(const Dims& d, const SpecBufs& sb, hipStream
   return hipGetLastError();
 }
 
+// Workgroups of a kernel (NT threads) resident on the whole device at once
+// (0 if the runtime cannot say).
+static int resident_slots(const void* kernel) {
+  int dev = 0, ncu = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, NT, 0) != hipSuccess)
+    return 0;
+  return std::max(0, ncu * per_cu);
+}
+// Levels per workgroup of the fused inverse pass: the fewest that let the
+// grid (ncol row blocks x chunks) fit in one round of the resident
+// workgroups, since every chunk transforms one level more than it projects.
+static int px_chunk(int nz, int ncol, int slots) {
+  if (slots <= 0) return nz;
+  const int chunks = std::max(1, slots / std::max(1, ncol));
+  return (nz + chunks - 1) / chunks;
+}
+
+template <class T>
+hipError_t launch_poisson_x_inverse_project(const Dims& d, const SpecBufs& sb, T* u, T* v, T* w,
+                                            double scale, const Spacing& sp, hipStream_t s,
+                                            const PoissonSlots* bs, int nslots) {
+#define OC_LAUNCH_XIP(N)                                                                   \
+  {                                                                                        \
+    constexpr int RB = 2 * XCfg<N>::LP - 1;                                                \
+    const int nblk = (d.ny + RB - 1) / RB;                                                 \
+    static const int slots = resident_slots((const void*)inv_x_project_kernel<T, N>);     \
+    const int kc = px_chunk(d.nz, nblk * nslots, slots);                                   \
+    dim3 grid(nblk, (d.nz + kc - 1) / kc, nslots);                                         \
+    hipLaunchKernelGGL((inv_x_project_kernel<T, N>), grid, dim3(NT), 0, s, d, sb, u, v, w, \
+                       scale, sp.rdx, sp.rdy, sp.rdzf, kc, bs);                            \
+  }
+  OC_FFT_DISPATCH(d.nx, OC_LAUNCH_XIP)
+#undef OC_LAUNCH_XIP
+  return hipGetLastError();
+}
+
 hipError_t launch_poisson_x_inverse_dot(const Dims& d, const SpecBufs& sb, const double* rdot,
                                         double* part, int part_cap, int* npart, hipStream_t s) {
 #define OC_LAUNCH_XID(N)                                                                   \
@@ -924,6 +1104,14 @@ template hipError_t launch_poisson_x_forward<double>(const Dims&, const double*,
                                                      const double*, double, Spacing,
                                                      const SpecBufs&, hipStream_t,
                                                      const PoissonSlots*, int);
+template hipError_t launch_poisson_x_inverse_project<float>(const Dims&, const SpecBufs&, float*,
+                                                            float*, float*, double,
+                                                            const Spacing&, hipStream_t,
+                                                            const PoissonSlots*, int);
+template hipError_t launch_poisson_x_inverse_project<double>(const Dims&, const SpecBufs&,
+                                                             double*, double*, double*, double,
+                                                             const Spacing&, hipStream_t,
+                                                             const PoissonSlots*, int);
 template hipError_t launch_project<float>(const Dims&, float*, float*, float*, double,
                                           const Spacing&, const double*, hipStream_t,
                                           const PoissonSlots*, int, const float*);

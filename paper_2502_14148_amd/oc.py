@@ -29,7 +29,7 @@ OC_NDIAG = 12
 EXPORTS = ("oc_last_error", "oc_grid_create", "oc_grid_destroy", "oc_model_workspace_size",
            "oc_model_create", "oc_model_destroy", "oc_set_state", "oc_get_state",
            "oc_tendencies", "oc_get_tendency", "oc_pressure_solve", "oc_get_pressure",
-           "oc_rk3_step", "oc_diagnostics", "oc_profile", "oc_profile_read",
+           "oc_rk3_step", "oc_diagnostics", "oc_profile", "oc_profile_read", "oc_profile_classes",
            "oc_free_surface_substeps", "oc_hydrostatic_step", "oc_mlp_workspace_size",
            "oc_mlp_create",
            "oc_mlp_destroy", "oc_mlp_set_params", "oc_mlp_get_params", "oc_mlp_forward",
@@ -113,6 +113,7 @@ def load_library(path=_LIB_PATH):
         "oc_rk3_step": [vp, ctypes.c_double, i32, vp],
         "oc_diagnostics": [vp, ctypes.POINTER(ctypes.c_double), vp],
         "oc_profile": [vp, i32],
+        "oc_profile_classes": [vp, ctypes.c_uint32],
         "oc_profile_read": [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)],
         "oc_free_surface_substeps": [vp, ctypes.c_double, i32, i32, ctypes.POINTER(ctypes.c_double), vp],
         "oc_hydrostatic_step": [vp, ctypes.c_double, i32, i32, ctypes.POINTER(ctypes.c_double), i32,
@@ -353,7 +354,14 @@ class Model:
         non-finite state (OC_ERR_NONFINITE)."""
         _check(_lib.oc_sync_check(self._model, _stream()))
 
-    def profile(self, enable=True):
+    def profile(self, enable=True, classes=None):
+        """Start (clearing the totals) or stop event timing; `classes` (names
+        from PROF_CLASSES) restricts the recording to those kernel classes,
+        None records all of them."""
+        if enable:
+            mask = (1 << len(PROF_CLASSES)) - 1 if classes is None else \
+                sum(1 << PROF_CLASSES.index(c) for c in set(classes))
+            _check(_lib.oc_profile_classes(self._model, mask))
         _check(_lib.oc_profile(self._model, 1 if enable else 0))
 
     def profile_read(self):
