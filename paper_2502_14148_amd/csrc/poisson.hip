@@ -489,123 +489,128 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4)))
 // Pass 3 on a stretched z (the mixed FFT-tridiagonal solver): every (kx, ky)
 // mode solves along z
 //   lo_k p_{k-1} + (lam_x + lam_y - lo_k - up_k) p_k + up_k p_{k+1} = r_k / (nx ny)
-// in LDS, PCR_W modes per workgroup, each equation kept normalised to a unit
-// diagonal (a x_{k-s} + x_k + c x_{k+s} = r): parallel cyclic reduction
-// rounds until every mode has split into S interleaved systems of about 8
-// equations, then one Thomas elimination per system and thread.  The systems
-// are strictly diagonally dominant (lam_x + lam_y < 0): no pivoting.  The horizontally
+// with each equation scaled to a unit diagonal, a_k x_{k-1} + x_k + c_k x_{k+1}
+// = d_k.  PCR_W modes per workgroup and 32 threads per mode, each owning a
+// chunk of TD_M consecutive levels (levels past nz are rows x = 0, which
+// leave the others unchanged).  Partition method: a thread eliminates its
+// chunk's interior in registers, downwards and then upwards, until every
+// row reads  a''_i x_first + x_i + c''_i x_last = d''_i  and the chunk's
+// first and last rows couple only to the neighbouring chunks' last and
+// first unknowns.  Those two rows per chunk form a tridiagonal system of
+// 64 unknowns per mode, solved by parallel cyclic reduction in LDS; then
+// every thread substitutes its chunk's interior.  The systems are strictly
+// diagonally dominant (lam_x + lam_y < 0): no pivoting.  The horizontally
 // uniform mode is singular (no-flux walls) and is integrated directly: the
 // face gradient obeys g_{k+1} = g_k + dzc_k r_k from g_0 = 0, then p_k =
 // p_{k-1} + dzf_k g_k, and the volume-weighted mean is removed.
 // ---------------------------------------------------------------------------
 constexpr int PCR_W = 8, PCR_NMAX = 256;
+constexpr int TD_P = NT / PCR_W, TD_M = PCR_NMAX / TD_P, TD_R = 2 * TD_P;
+static_assert(TD_M >= 3, "the partition method needs three rows per chunk");
+static_assert(PCR_W * TD_R >= PCR_NMAX && PCR_W * TD_R == 2 * NT, "reduced-row layout");
 
 __global__ void __launch_bounds__(NT) z_tridiag_kernel(Dims d, SpecBufs sb, double norm,
                                                        const double* __restrict__ lo,
                                                        const double* __restrict__ up,
                                                        const double* __restrict__ dzc,
                                                        const double* __restrict__ dzf) {
-  __shared__ double sa[PCR_W * PCR_NMAX];
-  __shared__ double sc[PCR_W * PCR_NMAX];
-  __shared__ double2 sr[PCR_W * PCR_NMAX];
-  constexpr int PER = PCR_W * PCR_NMAX / NT;
-  const int nz = d.nz, neq = PCR_W * nz;
+  // reduced rows, mode-major: row 2p (chunk p's first) and 2p + 1 (its last)
+  __shared__ double sa[PCR_W * TD_R], sc[PCR_W * TD_R];
+  __shared__ double2 sr[PCR_W * TD_R];   // also the uniform mode's column
+  const int nz = d.nz;
   const int j = blockIdx.y, kx0 = blockIdx.x * PCR_W;
   const int nxh = sb.nxh, nxp = sb.nxp;
   const long zs = (long)d.ny * nxp;
+  // consecutive threads on consecutive modes: a wave loads eight 128-byte
+  // level rows per instruction
+  const int c = (int)threadIdx.x % PCR_W, pc = (int)threadIdx.x / PCR_W;
+  const int kx = kx0 + c, z0 = pc * TD_M;
+  const bool live = kx < nxh && (kx | j) != 0;
+  const double lam = live ? sb.lamx[kx] + sb.lamy[j] : 0.0;
+  const long col = (long)j * nxp + kx;
+  double a[TD_M], cc[TD_M];
+  double2 r[TD_M];
 #pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    const int e = threadIdx.x + q * NT;
-    if (e >= neq) break;
-    const int c = e % PCR_W, z = e / PCR_W, kx = kx0 + c;
-    double a = 0.0, cc = 0.0;
-    double2 r = make_double2(0.0, 0.0);
-    if (kx < nxh && (kx | j) != 0) {
+  for (int i = 0; i < TD_M; ++i) {
+    const int z = z0 + i;
+    a[i] = 0.0;
+    cc[i] = 0.0;
+    r[i] = make_double2(0.0, 0.0);
+    if (live && z < nz) {
       const double l = lo[z], u = up[z];
-      const double ib = 1.0 / (sb.lamx[kx] + sb.lamy[j] - l - u);
-      a = l * ib;
-      cc = u * ib;
-      r = cscale(sb.spec[z * zs + (long)j * nxp + kx], norm * ib);
+      const double ib = 1.0 / (lam - l - u);
+      a[i] = l * ib;
+      cc[i] = u * ib;
+      r[i] = cscale(ld2(sb.spec, z * zs + col), norm * ib);
     }
-    sa[e] = a;
-    sc[e] = cc;
-    sr[e] = r;
   }
-  __syncthreads();
-  // reduction rounds until the stride S splits every mode into S interleaved
-  // systems of at most nz / S equations (about 8; S * PCR_W <= NT threads)
-  int S = 1;
-  while (S * 8 < nz && S * PCR_W * 2 <= NT) S <<= 1;
-  for (int st = 1; st < S; st <<= 1) {
-    double na[PER], nc[PER];
-    double2 nr[PER];
+  // downwards: rows i >= 1 become a_i x_first + x_i + c_i x_{i+1} = r_i
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int e = threadIdx.x + q * NT;
-      if (e >= neq) break;
-      const int z = e / PCR_W;
-      const double a = sa[e], c = sc[e];
+  for (int i = 2; i < TD_M; ++i) {
+    const double ib = 1.0 / (1.0 - a[i] * cc[i - 1]);
+    r[i] = cscale(csub(r[i], cscale(r[i - 1], a[i])), ib);
+    a[i] = -a[i] * a[i - 1] * ib;
+    cc[i] *= ib;
+  }
+  // upwards: rows 1 .. TD_M - 2 become a_i x_first + x_i + c_i x_last = r_i
+#pragma unroll
+  for (int i = TD_M - 3; i >= 1; --i) {
+    r[i] = csub(r[i], cscale(r[i + 1], cc[i]));
+    a[i] -= cc[i] * a[i + 1];
+    cc[i] = -cc[i] * cc[i + 1];
+  }
+  // the first row: a_0 x_{first-1} + x_first + c_0 x_last = r_0
+  {
+    const double ib = 1.0 / (1.0 - cc[0] * a[1]);
+    r[0] = cscale(csub(r[0], cscale(r[1], cc[0])), ib);
+    a[0] *= ib;
+    cc[0] = -cc[0] * cc[1] * ib;
+  }
+  const int e0 = c * TD_R + 2 * pc;
+  sa[e0] = a[0];
+  sc[e0] = cc[0];
+  sr[e0] = r[0];
+  sa[e0 + 1] = a[TD_M - 1];
+  sc[e0 + 1] = cc[TD_M - 1];
+  sr[e0 + 1] = r[TD_M - 1];
+  __syncthreads();
+  // cyclic reduction of the reduced systems: thread t takes rows t and
+  // t + NT (both of mode t / TD_R resp. t / TD_R + NT / TD_R)
+  for (int st = 1; st < TD_R; st <<= 1) {
+    double na[2], nc[2];
+    double2 nr[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int e = (int)threadIdx.x + h * NT, q = e % TD_R;
+      const double ae = sa[e], ce = sc[e];
       double am = 0.0, cm = 0.0, ap = 0.0, cp = 0.0;
-      double2 rm = make_double2(0.0, 0.0), rp = make_double2(0.0, 0.0);
-      if (z >= st) {
-        const int m = e - st * PCR_W;
-        am = sa[m];
-        cm = sc[m];
-        rm = sr[m];
-      }
-      if (z + st < nz) {
-        const int m = e + st * PCR_W;
-        ap = sa[m];
-        cp = sc[m];
-        rp = sr[m];
-      }
-      const double ib = 1.0 / (1.0 - a * cm - c * ap);
-      na[q] = -a * am * ib;
-      nc[q] = -c * cp * ib;
-      nr[q] = cscale(csub(csub(sr[e], cscale(rm, a)), cscale(rp, c)), ib);
+      double2 rm = make_double2(0.0, 0.0), rp = rm;
+      if (q >= st) { am = sa[e - st]; cm = sc[e - st]; rm = sr[e - st]; }
+      if (q + st < TD_R) { ap = sa[e + st]; cp = sc[e + st]; rp = sr[e + st]; }
+      const double ib = 1.0 / (1.0 - ae * cm - ce * ap);
+      na[h] = -ae * am * ib;
+      nc[h] = -ce * cp * ib;
+      nr[h] = cscale(csub(csub(sr[e], cscale(rm, ae)), cscale(rp, ce)), ib);
     }
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int e = threadIdx.x + q * NT;
-      if (e >= neq) break;
-      sa[e] = na[q];
-      sc[e] = nc[q];
-      sr[e] = nr[q];
+    for (int h = 0; h < 2; ++h) {
+      const int e = (int)threadIdx.x + h * NT;
+      sa[e] = na[h];
+      sc[e] = nc[h];
+      sr[e] = nr[h];
     }
     __syncthreads();
   }
-  // Thomas elimination of each interleaved system (equations z = res,
-  // res + S, ... of mode c), one thread per system, in place in LDS
-  if ((int)threadIdx.x < PCR_W * S) {
-    const int c = threadIdx.x % PCR_W, res = threadIdx.x / PCR_W;
-    double cp = 0.0;
-    double2 rp = make_double2(0.0, 0.0);
-    int zl = res;
-    for (int z = res; z < nz; z += S) {
-      const int e = z * PCR_W + c;
-      const double a = sa[e];
-      const double ib = 1.0 / (1.0 - a * cp);
-      cp = sc[e] * ib;
-      rp = cscale(csub(sr[e], cscale(rp, a)), ib);
-      sc[e] = cp;
-      sr[e] = rp;
-      zl = z;
-    }
-    double2 xz = make_double2(0.0, 0.0);
-    for (int z = zl; z >= 0; z -= S) {
-      const int e = z * PCR_W + c;
-      xz = csub(sr[e], cscale(xz, sc[e]));
-      sr[e] = xz;
-    }
-  }
-  __syncthreads();
+  // the chunk's first and last unknowns, then its interior
+  const double2 xf = sr[e0], xl = sr[e0 + 1];
 #pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    const int e = threadIdx.x + q * NT;
-    if (e >= neq) break;
-    const int c = e % PCR_W, z = e / PCR_W, kx = kx0 + c;
-    if (kx < nxh && (kx | j) != 0) sb.spec[z * zs + (long)j * nxp + kx] = sr[e];
+  for (int i = 0; i < TD_M; ++i) {
+    const int z = z0 + i;
+    double2 x = xf;
+    if (i == TD_M - 1) x = xl;
+    else if (i > 0) x = csub(csub(r[i], cscale(xf, a[i])), cscale(xl, cc[i]));
+    if (live && z < nz) st2(sb.spec, z * zs + col, x);
   }
   if (blockIdx.x != 0 || j != 0) return;  // uniform within the workgroup
   // ---- the horizontally uniform mode (kx = 0, ky = 0)
@@ -788,8 +793,8 @@ __global__ void __launch_bounds__(PJ_X * PJ_Y) project_kernel(
 
 // ---------------------------------------------------------------------------
 // Pass 5 fused with the projection (the FFT/DCT solve of the whole box).  A
-// workgroup takes RB = 2 LP - 1 rows, j0 .. j0 + RB - 1, and a chunk of PX_KC
-// levels.  At every level it transforms LP packed lines back to p: line l
+// workgroup takes rb <= RB = 2 LP - 1 rows, j0 .. j0 + rb - 1 (the rows are
+// dealt evenly to the fewest blocks of at most RB), and a chunk of levels.  At every level it transforms LP packed lines back to p: line l
 // holds rows j0 - 1 + 2l and j0 + 2l (Z = X_a + i X_b of their Hermitian half
 // rows), so the row below the block (periodic in y) comes along in line 0.
 // It then subtracts scale * grad p from u, v and w of its rows: p at i - 1
@@ -803,7 +808,7 @@ __global__ void __launch_bounds__(PJ_X * PJ_Y) project_kernel(
 template <class T, int N>
 __global__ void __launch_bounds__(NT) inv_x_project_kernel(
     Dims d, SpecBufs sb, T* __restrict__ u, T* __restrict__ v, T* __restrict__ w, double scale,
-    double rdx, double rdy, const double* __restrict__ rdzf, int kc,
+    double rdx, double rdy, const double* __restrict__ rdzf, int rb, int kc,
     const PoissonSlots* __restrict__ bs) {
   if (bs) {
     const int z = blockIdx.z;
@@ -825,10 +830,10 @@ __global__ void __launch_bounds__(NT) inv_x_project_kernel(
   const int ntile = (int)(gridDim.x * gridDim.y);
   const int bid = (int)(blockIdx.x + blockIdx.y * gridDim.x), xcd = bid % 8;
   const int lin = xcd * (ntile / 8) + min(xcd, ntile % 8) + bid / 8;
-  const int j0 = (lin % (int)gridDim.x) * RB;
+  const int j0 = (lin % (int)gridDim.x) * rb;   // rb <= RB rows per block
   const int k0 = (lin / (int)gridDim.x) * kc;
   const int k1 = min(k0 + kc, d.nz);
-  const int nxp = sb.nxp, ny = d.ny;
+  const int nxp = sb.nxp, ny = d.ny, jend = min(ny, j0 + rb);
   const auto gu = glb(u), gv = glb(v), gw = glb(w);
   // The first Stockham pass, one radix-R0 butterfly per thread (L N / R0 =
   // 1024 / R0 <= NT), takes its points from registers: fetch(k) issues the
@@ -841,7 +846,7 @@ __global__ void __launch_bounds__(NT) inv_x_project_kernel(
   const int bl = (int)threadIdx.x / M0, bj = (int)threadIdx.x % M0;
   const bool bact = (int)threadIdx.x < L * M0;
   const int ja = (bl == 0 && j0 == 0) ? ny - 1 : j0 - 1 + 2 * bl, jb = j0 + 2 * bl;
-  const bool has_a = bact && ja < ny, has_b = bact && jb < ny;
+  const bool has_a = bact && (bl == 0 || ja < jend), has_b = bact && jb < jend;
   double2 fa[R0], fb[R0];
   auto fetch = [&](int k) {
     const long lvl = (long)k * ny;
@@ -893,7 +898,7 @@ __global__ void __launch_bounds__(NT) inv_x_project_kernel(
     for (int q = 0; q < CPT; ++q) {
       const int c = threadIdx.x + q * NT;
       const int j = j0 + c / N;
-      if ((CELLS % NT == 0 || c < CELLS) && j < ny) {
+      if ((CELLS % NT == 0 || c < CELLS) && j < jend) {
         const long o = pidx(d, c % N, j, k);
         uu[q] = gu[o];
         vv[q] = gv[o];
@@ -910,7 +915,7 @@ __global__ void __launch_bounds__(NT) inv_x_project_kernel(
     for (int q = 0; q < CPT; ++q) {
       const int c = threadIdx.x + q * NT;
       const int r = c / N, i = c % N, j = j0 + r;
-      if ((CELLS % NT == 0 || c < CELLS) && j < ny) {
+      if ((CELLS % NT == 0 || c < CELLS) && j < jend) {
         const double p0 = pat(r, i);
         const double pxm = pat(r, i == 0 ? N - 1 : i - 1);
         const double pym = pat(r - 1, i);
@@ -1058,12 +1063,12 @@ hipError_t launch_poisson_x_inverse_project(const Dims& d, const SpecBufs& sb, T
 #define OC_LAUNCH_XIP(N)                                                                   \
   {                                                                                        \
     constexpr int RB = 2 * XCfg<N>::LP - 1;                                                \
-    const int nblk = (d.ny + RB - 1) / RB;                                                 \
+    const int nblk = (d.ny + RB - 1) / RB, rb = (d.ny + nblk - 1) / nblk;                  \
     static const int slots = resident_slots((const void*)inv_x_project_kernel<T, N>);     \
     const int kc = px_chunk(d.nz, nblk * nslots, slots);                                   \
     dim3 grid(nblk, (d.nz + kc - 1) / kc, nslots);                                         \
     hipLaunchKernelGGL((inv_x_project_kernel<T, N>), grid, dim3(NT), 0, s, d, sb, u, v, w, \
-                       scale, sp.rdx, sp.rdy, sp.rdzf, kc, bs);                            \
+                       scale, sp.rdx, sp.rdy, sp.rdzf, rb, kc, bs);                        \
   }
   OC_FFT_DISPATCH(d.nx, OC_LAUNCH_XIP)
 #undef OC_LAUNCH_XIP
