@@ -794,45 +794,61 @@ __global__ void __launch_bounds__(PJ_X * PJ_Y) project_kernel(
 // ---------------------------------------------------------------------------
 // Pass 5 fused with the projection (the FFT/DCT solve of the whole box).  A
 // workgroup takes rb <= RB = 2 LP - 1 rows, j0 .. j0 + rb - 1 (the rows are
-// dealt evenly to the fewest blocks of at most RB), and a chunk of levels.  At every level it transforms LP packed lines back to p: line l
+// dealt evenly to the fewest blocks of at most RB; a block of one member is
+// a column), and a chunk of the column's levels.  At every level it transforms LP packed lines back to p: line l
 // holds rows j0 - 1 + 2l and j0 + 2l (Z = X_a + i X_b of their Hermitian half
 // rows), so the row below the block (periodic in y) comes along in line 0.
 // It then subtracts scale * grad p from u, v and w of its rows: p at i - 1
 // and j - 1 come from the lines in LDS, p of the level below from registers
 // (the level below the chunk is transformed once more first).  p is not
 // written: the spectrum stays in its buffer, and the stand-alone pass 5
-// turns it into p when p is asked for.  The chunk length kc is chosen by the
-// launcher so that the grid fits in one round of resident workgroups.
+// turns it into p when p is asked for.  The grid is one round of resident
+// workgroups (at least one per column), the chunks dealt evenly to the
+// columns and each column's levels evenly to its chunks.
 // ---------------------------------------------------------------------------
+
+// Lines per workgroup of the fused pass: four at length 256 (7 rows of
+// 256), else about 512 / N, so that a thread owns at most four cells of a
+// level at the shorter lengths (more cells per thread cost registers and
+// resident waves there).
+template <int N> struct PXCfg { static constexpr int L = N >= 256 ? 4 : (512 / N > 2 ? 512 / N : 2); };
 
 template <class T, int N>
 __global__ void __launch_bounds__(NT) inv_x_project_kernel(
     Dims d, SpecBufs sb, T* __restrict__ u, T* __restrict__ v, T* __restrict__ w, double scale,
-    double rdx, double rdy, const double* __restrict__ rdzf, int rb, int kc,
+    double rdx, double rdy, const double* __restrict__ rdzf, int rb, int nblk, int ncol,
     const PoissonSlots* __restrict__ bs) {
+  // Workgroups are dealt round-robin to the 8 XCDs: XCD x takes workgroups
+  // x, x + 8, ...; renumber them so that each XCD works on a contiguous run
+  // (the chunks of a column, then the next column), whose shared rows and
+  // levels stay in its L2
+  const int nwg = (int)gridDim.x, bid = (int)blockIdx.x, xcd = bid % 8;
+  const int wg = xcd * (nwg / 8) + min(xcd, nwg % 8) + bid / 8;
+  // the grid's nwg chunks dealt to the ncol columns (the first nwg % ncol
+  // columns take one more), each column's levels dealt evenly to its chunks
+  int colm, ch, nch;
+  if (nwg <= ncol) {
+    colm = wg; ch = 0; nch = 1;
+  } else {
+    const int q = nwg / ncol, rem = nwg % ncol;
+    if (wg < rem * (q + 1)) { colm = wg / (q + 1); ch = wg % (q + 1); nch = q + 1; }
+    else { colm = rem + (wg - rem * (q + 1)) / q; ch = (wg - rem * (q + 1)) % q; nch = q; }
+  }
   if (bs) {
-    const int z = blockIdx.z;
+    const int z = colm / nblk;
     u = (T*)bs->u[z];
     v = (T*)bs->v[z];
     w = (T*)bs->w[z];
     sb.spec = bs->spec[z];
   }
-  constexpr int L = XCfg<N>::LP, RB = 2 * L - 1, CELLS = RB * N;
+  constexpr int L = PXCfg<N>::L, RB = 2 * L - 1, CELLS = RB * N;
   constexpr int CPT = (CELLS + NT - 1) / NT;
   constexpr int R0 = pass_radix<N, 4>();
   __shared__ double2 buf[L * N];
   __shared__ double2 tws[N];
   stage_twiddles<N>(tws, sb.twx);
-  // Workgroups are dealt round-robin to the 8 XCDs: XCD x takes tiles
-  // x, x + 8, ...; renumber them so that each XCD works on a contiguous run
-  // (row blocks fastest, then the level chunk), whose shared rows and levels
-  // stay in its L2
-  const int ntile = (int)(gridDim.x * gridDim.y);
-  const int bid = (int)(blockIdx.x + blockIdx.y * gridDim.x), xcd = bid % 8;
-  const int lin = xcd * (ntile / 8) + min(xcd, ntile % 8) + bid / 8;
-  const int j0 = (lin % (int)gridDim.x) * rb;   // rb <= RB rows per block
-  const int k0 = (lin / (int)gridDim.x) * kc;
-  const int k1 = min(k0 + kc, d.nz);
+  const int j0 = (colm % nblk) * rb;   // rb <= RB rows per block
+  const int k0 = (int)((long)ch * d.nz / nch), k1 = (int)((long)(ch + 1) * d.nz / nch);
   const int nxp = sb.nxp, ny = d.ny, jend = min(ny, j0 + rb);
   const auto gu = glb(u), gv = glb(v), gw = glb(w);
   // The first Stockham pass, one radix-R0 butterfly per thread (L N / R0 =
@@ -1047,14 +1063,6 @@ static int resident_slots(const void* kernel) {
     return 0;
   return std::max(0, ncu * per_cu);
 }
-// Levels per workgroup of the fused inverse pass: the fewest that let the
-// grid (ncol row blocks x chunks) fit in one round of the resident
-// workgroups, since every chunk transforms one level more than it projects.
-static int px_chunk(int nz, int ncol, int slots) {
-  if (slots <= 0) return nz;
-  const int chunks = std::max(1, slots / std::max(1, ncol));
-  return (nz + chunks - 1) / chunks;
-}
 
 template <class T>
 hipError_t launch_poisson_x_inverse_project(const Dims& d, const SpecBufs& sb, T* u, T* v, T* w,
@@ -1062,13 +1070,13 @@ hipError_t launch_poisson_x_inverse_project(const Dims& d, const SpecBufs& sb, T
                                             const PoissonSlots* bs, int nslots) {
 #define OC_LAUNCH_XIP(N)                                                                   \
   {                                                                                        \
-    constexpr int RB = 2 * XCfg<N>::LP - 1;                                                \
+    constexpr int RB = 2 * PXCfg<N>::L - 1;                                                \
     const int nblk = (d.ny + RB - 1) / RB, rb = (d.ny + nblk - 1) / nblk;                  \
     static const int slots = resident_slots((const void*)inv_x_project_kernel<T, N>);     \
-    const int kc = px_chunk(d.nz, nblk * nslots, slots);                                   \
-    dim3 grid(nblk, (d.nz + kc - 1) / kc, nslots);                                         \
-    hipLaunchKernelGGL((inv_x_project_kernel<T, N>), grid, dim3(NT), 0, s, d, sb, u, v, w, \
-                       scale, sp.rdx, sp.rdy, sp.rdzf, rb, kc, bs);                        \
+    const int ncol = nblk * nslots;                                                        \
+    const int grid = std::max(ncol, std::min(slots, ncol * d.nz));                         \
+    hipLaunchKernelGGL((inv_x_project_kernel<T, N>), dim3(grid), dim3(NT), 0, s, d, sb, u, \
+                       v, w, scale, sp.rdx, sp.rdy, sp.rdzf, rb, nblk, ncol, bs);          \
   }
   OC_FFT_DISPATCH(d.nx, OC_LAUNCH_XIP)
 #undef OC_LAUNCH_XIP
