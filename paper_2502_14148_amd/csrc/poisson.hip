@@ -802,21 +802,27 @@ __global__ void __launch_bounds__(PJ_X * PJ_Y) project_kernel(
 // and j - 1 come from the lines in LDS, p of the level below from registers
 // (the level below the chunk is transformed once more first).  p is not
 // written: the spectrum stays in its buffer, and the stand-alone pass 5
-// turns it into p when p is asked for.  The grid is one round of resident
-// workgroups (at least one per column), the chunks dealt evenly to the
-// columns and each column's levels evenly to its chunks.
+// turns it into p when p is asked for.  Every column has the same number of
+// chunks (chosen at launch against the resident workgroups), each column's
+// levels dealt evenly to them.
 // ---------------------------------------------------------------------------
 
-// Lines per workgroup of the fused pass: four at length 256 (7 rows of
-// 256), else about 512 / N, so that a thread owns at most four cells of a
-// level at the shorter lengths (more cells per thread cost registers and
-// resident waves there).
-template <int N> struct PXCfg { static constexpr int L = N >= 256 ? 4 : (512 / N > 2 ? 512 / N : 2); };
+// Lines per level and levels per transform of the fused pass: four lines
+// (7 rows) at length 256, about 512 / N at the shorter lengths, which keeps
+// a thread's cells per level at four or fewer and its registers near 150
+// (three waves per SIMD).  Length 96 transforms two levels at once: with
+// one, fewer than half of the threads have a first-pass butterfly, and two
+// cost no resident wave there (measured in the 48-member ensemble: 223 ->
+// 200 us per launch; at 128 and 64 the second level costs a wave and time).
+template <int N> struct PXCfg {
+  static constexpr int L = N >= 256 ? 4 : (512 / N > 2 ? 512 / N : 2);
+  static constexpr int LV = N == 96 ? 2 : 1;
+};
 
 template <class T, int N>
 __global__ void __launch_bounds__(NT) inv_x_project_kernel(
     Dims d, SpecBufs sb, T* __restrict__ u, T* __restrict__ v, T* __restrict__ w, double scale,
-    double rdx, double rdy, const double* __restrict__ rdzf, int rb, int nblk, int ncol,
+    double rdx, double rdy, const double* __restrict__ rdzf, int rb, int nblk, int nch,
     const PoissonSlots* __restrict__ bs) {
   // Workgroups are dealt round-robin to the 8 XCDs: XCD x takes workgroups
   // x, x + 8, ...; renumber them so that each XCD works on a contiguous run
@@ -824,16 +830,8 @@ __global__ void __launch_bounds__(NT) inv_x_project_kernel(
   // levels stay in its L2
   const int nwg = (int)gridDim.x, bid = (int)blockIdx.x, xcd = bid % 8;
   const int wg = xcd * (nwg / 8) + min(xcd, nwg % 8) + bid / 8;
-  // the grid's nwg chunks dealt to the ncol columns (the first nwg % ncol
-  // columns take one more), each column's levels dealt evenly to its chunks
-  int colm, ch, nch;
-  if (nwg <= ncol) {
-    colm = wg; ch = 0; nch = 1;
-  } else {
-    const int q = nwg / ncol, rem = nwg % ncol;
-    if (wg < rem * (q + 1)) { colm = wg / (q + 1); ch = wg % (q + 1); nch = q + 1; }
-    else { colm = rem + (wg - rem * (q + 1)) / q; ch = (wg - rem * (q + 1)) % q; nch = q; }
-  }
+  // nch chunks per column, each column's levels dealt evenly to them
+  const int colm = wg / nch, ch = wg % nch;
   if (bs) {
     const int z = colm / nblk;
     u = (T*)bs->u[z];
@@ -841,36 +839,45 @@ __global__ void __launch_bounds__(NT) inv_x_project_kernel(
     w = (T*)bs->w[z];
     sb.spec = bs->spec[z];
   }
-  constexpr int L = PXCfg<N>::L, RB = 2 * L - 1, CELLS = RB * N;
-  constexpr int CPT = (CELLS + NT - 1) / NT;
+  constexpr int L = PXCfg<N>::L, LV = PXCfg<N>::LV, LT = L * LV;
+  constexpr int RB = 2 * L - 1, CELLS = RB * N;
   constexpr int R0 = pass_radix<N, 4>();
-  __shared__ double2 buf[L * N];
+  __shared__ double2 buf[LT * N];
   __shared__ double2 tws[N];
   stage_twiddles<N>(tws, sb.twx);
   const int j0 = (colm % nblk) * rb;   // rb <= RB rows per block
   const int k0 = (int)((long)ch * d.nz / nch), k1 = (int)((long)(ch + 1) * d.nz / nch);
   const int nxp = sb.nxp, ny = d.ny, jend = min(ny, j0 + rb);
   const auto gu = glb(u), gv = glb(v), gw = glb(w);
-  // The first Stockham pass, one radix-R0 butterfly per thread (L N / R0 =
-  // 1024 / R0 <= NT), takes its points from registers: fetch(k) issues the
-  // loads of level k, first() combines each row pair (with the Hermitian
-  // extension) and writes the pass's outputs.  The loads of level k + 1 are
-  // issued right after level k's first pass, so they travel while level k
-  // is transformed and projected.
+  // The chunk's levels as a stream: the level below the chunk (if there is
+  // one), then k0 .. k1 - 1.  An iteration transforms LV consecutive ones
+  // and projects those that belong to the chunk.
+  const bool below = !d.zb || k0 > 0;
+  const int kb = k0 > 0 ? k0 - 1 : d.nz - 1;
+  const int ns = k1 - k0 + (below ? 1 : 0);
+  auto lev = [&](int sv) { return below ? (sv == 0 ? kb : k0 + sv - 1) : k0 + sv; };
+  // The first Stockham pass, one radix-R0 butterfly per thread (LT N / R0 <=
+  // NT), takes its points from registers: fetch(s) issues the loads of the
+  // iteration starting at stream index s, first() combines each row pair
+  // (with the Hermitian extension) and writes the pass's outputs.  The next
+  // iteration's loads are issued right after this one's first pass, so they
+  // travel while this one is transformed and projected.
   constexpr int M0 = N / R0;
-  static_assert(L * M0 <= NT, "one first-pass butterfly per thread");
+  static_assert(LT * M0 <= NT, "one first-pass butterfly per thread");
   const int bl = (int)threadIdx.x / M0, bj = (int)threadIdx.x % M0;
-  const bool bact = (int)threadIdx.x < L * M0;
-  const int ja = (bl == 0 && j0 == 0) ? ny - 1 : j0 - 1 + 2 * bl, jb = j0 + 2 * bl;
-  const bool has_a = bact && (bl == 0 || ja < jend), has_b = bact && jb < jend;
+  const bool bact = (int)threadIdx.x < LT * M0;
+  const int bv = bl / L, blv = bl % L;   // the line's level in the iteration, its index
+  const int ja = (blv == 0 && j0 == 0) ? ny - 1 : j0 - 1 + 2 * blv, jb = j0 + 2 * blv;
+  const bool has_a = bact && (blv == 0 || ja < jend), has_b = bact && jb < jend;
   double2 fa[R0], fb[R0];
-  auto fetch = [&](int k) {
-    const long lvl = (long)k * ny;
+  auto fetch = [&](int s) {
+    const bool ok = s + bv < ns;
+    const long lvl = (long)(ok ? lev(s + bv) : 0) * ny;
 #pragma unroll
     for (int r = 0; r < R0; ++r) {
       const int n = bj + r * M0, m = n <= N / 2 ? n : N - n;
-      fa[r] = has_a ? ld2(sb.spec, (lvl + ja) * nxp + m) : make_double2(0.0, 0.0);
-      fb[r] = has_b ? ld2(sb.spec, (lvl + jb) * nxp + m) : make_double2(0.0, 0.0);
+      fa[r] = (ok && has_a) ? ld2(sb.spec, (lvl + ja) * nxp + m) : make_double2(0.0, 0.0);
+      fb[r] = (ok && has_b) ? ld2(sb.spec, (lvl + jb) * nxp + m) : make_double2(0.0, 0.0);
     }
   };
   auto first = [&]() {
@@ -887,62 +894,72 @@ __global__ void __launch_bounds__(NT) inv_x_project_kernel(
     }
     __syncthreads();
   };
-  auto rest = [&]() { fft_lines<N, R0, L, NT, 1, false>(buf, N, 1, tws); };
-  // p at row r of the block (r = -1: the row below) and column i
-  auto pat = [&](int r, int i) -> double {
-    const double2 z = buf[((r + 1) >> 1) * N + i];
+  auto rest = [&]() { fft_lines<N, R0, LT, NT, 1, false>(buf, N, 1, tws); };
+  // p of the iteration's level vv at row r of the block (r = -1: the row
+  // below) and column i
+  auto pat = [&](int vv, int r, int i) -> double {
+    const double2 z = buf[(vv * L + ((r + 1) >> 1)) * N + i];
     return (r & 1) ? z.x : z.y;
   };
-  double pb[CPT];
-  const bool below = !d.zb || k0 > 0;
-  if (!below) fetch(k0);
-  if (below) {
-    fetch(k0 > 0 ? k0 - 1 : d.nz - 1);
-    first();
-    fetch(k0);
-    rest();
+  // a thread's cells of a level: c = tid + q NT
+  constexpr int CPL = (CELLS + NT - 1) / NT;
+  double pb[CPL];   // p of the level below the iteration's first level
+  fetch(0);
+  for (int s = 0; s < ns; s += LV) {
+    // the velocities of the projected levels, in flight during the transform
+    T uu[LV][CPL], vv[LV][CPL], ww[LV][CPL];
 #pragma unroll
-    for (int q = 0; q < CPT; ++q) {
-      const int c = threadIdx.x + q * NT;
-      pb[q] = (CELLS % NT == 0 || c < CELLS) ? pat(c / N, c % N) : 0.0;
-    }
-  }
-  for (int k = k0; k < k1; ++k) {
-    // this level's velocities, in flight during the transform
-    T uu[CPT], vv[CPT], ww[CPT];
+    for (int lv = 0; lv < LV; ++lv) {
+      const int sv = s + lv;
+      if (sv < ns && !(below && sv == 0)) {
+        const int k = lev(sv);
 #pragma unroll
-    for (int q = 0; q < CPT; ++q) {
-      const int c = threadIdx.x + q * NT;
-      const int j = j0 + c / N;
-      if ((CELLS % NT == 0 || c < CELLS) && j < jend) {
-        const long o = pidx(d, c % N, j, k);
-        uu[q] = gu[o];
-        vv[q] = gv[o];
-        ww[q] = gw[o];
+        for (int q = 0; q < CPL; ++q) {
+          const int c = threadIdx.x + q * NT, j = j0 + c / N;
+          if ((CELLS % NT == 0 || c < CELLS) && j < jend) {
+            const long o = pidx(d, c % N, j, k);
+            uu[lv][q] = gu[o];
+            vv[lv][q] = gv[o];
+            ww[lv][q] = gw[o];
+          }
+        }
       }
     }
-    if (below || k > k0) __syncthreads();   // the lines of the level below are read
+    if (s > 0) __syncthreads();   // the lines of the previous iteration are read
     first();
-    if (k + 1 < k1) fetch(k + 1);   // the next level's loads, in flight meanwhile
+    if (s + LV < ns) fetch(s + LV);
     rest();
-    const double rz = rdzf[k];
-    const bool wk = !d.zb || k > 0;
 #pragma unroll
-    for (int q = 0; q < CPT; ++q) {
-      const int c = threadIdx.x + q * NT;
-      const int r = c / N, i = c % N, j = j0 + r;
-      if ((CELLS % NT == 0 || c < CELLS) && j < jend) {
-        const double p0 = pat(r, i);
-        const double pxm = pat(r, i == 0 ? N - 1 : i - 1);
-        const double pym = pat(r - 1, i);
-        const T un = (T)((double)uu[q] - scale * (p0 - pxm) * rdx);
-        const T vn = (T)((double)vv[q] - scale * (p0 - pym) * rdy);
-        const T wn = wk ? (T)((double)ww[q] - scale * (p0 - pb[q]) * rz) : ww[q];
-        pb[q] = p0;
-        store_with_images(u, d, i, j, k, un, false);
-        store_with_images(v, d, i, j, k, vn, false);
-        store_with_images(w, d, i, j, k, wn, true);
+    for (int lv = 0; lv < LV; ++lv) {
+      const int sv = s + lv;
+      if (sv < ns && !(below && sv == 0)) {
+        const int k = lev(sv);
+        const double rz = rdzf[k];
+        const bool wk = !d.zb || k > 0;
+#pragma unroll
+        for (int q = 0; q < CPL; ++q) {
+          const int c = threadIdx.x + q * NT;
+          const int r = c / N, i = c % N, j = j0 + r;
+          if ((CELLS % NT == 0 || c < CELLS) && j < jend) {
+            const double p0 = pat(lv, r, i);
+            const double pxm = pat(lv, r, i == 0 ? N - 1 : i - 1);
+            const double pym = pat(lv, r - 1, i);
+            const double pzm = lv == 0 ? pb[q] : pat(lv - 1, r, i);
+            const T un = (T)((double)uu[lv][q] - scale * (p0 - pxm) * rdx);
+            const T vn = (T)((double)vv[lv][q] - scale * (p0 - pym) * rdy);
+            const T wn = wk ? (T)((double)ww[lv][q] - scale * (p0 - pzm) * rz) : ww[lv][q];
+            store_with_images(u, d, i, j, k, un, false);
+            store_with_images(v, d, i, j, k, vn, false);
+            store_with_images(w, d, i, j, k, wn, true);
+          }
+        }
       }
+    }
+    // p of the iteration's last level, below the next iteration's first
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) {
+      const int c = threadIdx.x + q * NT;
+      if (CELLS % NT == 0 || c < CELLS) pb[q] = pat(LV - 1, c / N, c % N);
     }
   }
 }
@@ -1053,6 +1070,22 @@ hipError_t launch_poisson_x_inverse(const Dims& d, const SpecBufs& sb, hipStream
   return hipGetLastError();
 }
 
+// Chunks per column of the fused inverse pass: a workgroup's time grows
+// with its levels (one more than its chunk holds: the level below), and
+// the grid runs in rounds of `slots` resident workgroups, so take the
+// count that minimises rounds x (levels per chunk + 1).
+static int px_chunks(int nz, int ncol, int slots) {
+  if (slots <= 0) return 1;
+  int best = 1;
+  long best_cost = -1;
+  for (int n = 1; n <= nz; ++n) {
+    const long rounds = ((long)ncol * n + slots - 1) / slots;
+    const long cost = rounds * ((nz + n - 1) / n + 1);
+    if (best_cost < 0 || cost < best_cost) { best = n; best_cost = cost; }
+  }
+  return best;
+}
+
 // Workgroups of a kernel (NT threads) resident on the whole device at once
 // (0 if the runtime cannot say).
 static int resident_slots(const void* kernel) {
@@ -1073,10 +1106,9 @@ hipError_t launch_poisson_x_inverse_project(const Dims& d, const SpecBufs& sb, T
     constexpr int RB = 2 * PXCfg<N>::L - 1;                                                \
     const int nblk = (d.ny + RB - 1) / RB, rb = (d.ny + nblk - 1) / nblk;                  \
     static const int slots = resident_slots((const void*)inv_x_project_kernel<T, N>);     \
-    const int ncol = nblk * nslots;                                                        \
-    const int grid = std::max(ncol, std::min(slots, ncol * d.nz));                         \
-    hipLaunchKernelGGL((inv_x_project_kernel<T, N>), dim3(grid), dim3(NT), 0, s, d, sb, u, \
-                       v, w, scale, sp.rdx, sp.rdy, sp.rdzf, rb, nblk, ncol, bs);          \
+    const int ncol = nblk * nslots, nch = px_chunks(d.nz, ncol, slots);                    \
+    hipLaunchKernelGGL((inv_x_project_kernel<T, N>), dim3(ncol * nch), dim3(NT), 0, s, d, sb, \
+                       u, v, w, scale, sp.rdx, sp.rdy, sp.rdzf, rb, nblk, nch, bs);        \
   }
   OC_FFT_DISPATCH(d.nx, OC_LAUNCH_XIP)
 #undef OC_LAUNCH_XIP
