@@ -169,7 +169,7 @@ POISSON_BYTES_PER_CELL = {"fft_x_fwd": 20, "fft_y_fwd": 16, "z_solve": 16, "fft_
                           "fft_x_inv": 16, "project": 32}
 
 
-def poisson_hbm(prof, ncells):
+def poisson_hbm(prof, ncells, copy_gbs=None):
     out = {}
     for k, b in POISSON_BYTES_PER_CELL.items():
         ms, n = prof[k]
@@ -177,7 +177,33 @@ def poisson_hbm(prof, ncells):
             gbs = b * ncells / (ms / 1e3 / n) / 1e9
             out[k] = {"avg_launch_us": round(ms / n * 1e3, 1), "achieved_gbs": round(gbs, 1),
                       "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_cell": b}
+            if copy_gbs:
+                out[k]["frac_of_copy"] = round(gbs / copy_gbs, 4)
     return out
+
+
+def copy_rate_gbs(mib=1024, reps=10):
+    """Achieved HBM rate of a plain device copy (torch's elementwise kernel)
+    of `mib` MiB, read + write bytes over time: the practical ceiling of a
+    pass with equal reads and writes, reported beside the published peak."""
+    import torch
+    n = mib * 1024 * 1024 // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * n * 4 * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return gbs
 
 
 def run_gpu(ph, s, precision, steps, warmup):
@@ -659,8 +685,11 @@ def main_leg(a):
     achieved_gbs = tbytes / t_launch / 1e9
     # headline: the tendency kernel's algorithmic HBM bytes per launch over
     # its average launch time, against the HBM peak; the VALU figure beside it
+    copy_gbs = copy_rate_gbs()
     roofline = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
+                "copy_kernel_gbs": round(copy_gbs, 1),
+                "frac_of_copy": round(achieved_gbs / copy_gbs, 4),
                 "traffic": measured_traffic(),
                 "kernel": "tendency_rk3 (FP32, WENO5-Z, 256^3)",
                 "avg_launch_ms": t_launch * 1e3,
@@ -682,7 +711,7 @@ def main_leg(a):
                    "grid": [n, n, n], "extent_m": [2.0 * n, 2.0 * n, 1.0 * n], "dt_s": 1.0},
         "roofline": roofline,
         "kernels_ms_per_step": {k: v[0] / a.steps for k, v in prof32.items()},
-        "poisson_hbm": poisson_hbm(prof32, ncells),
+        "poisson_hbm": poisson_hbm(prof32, ncells, copy_gbs),
         "fp64_path": res,
         "wall_s_timed": wall32,
         "final_max_w": diag32["max_w"],

@@ -45,6 +45,8 @@ def _assert_same(ms_a, ms_b):
         for f in FIELDS:
             x, y = a.get_state(f), b.get_state(f)
             assert np.array_equal(x, y), (ia, f, np.abs(x - y).max())
+        # the last substage's pressure, kept as a spectrum until it is read
+        assert np.array_equal(a.get_pressure(), b.get_pressure()), ia
 
 
 SIZES = [(32, 32, 32), (64, 32, 16), (32, 32, 32), (16, 16, 64), (96, 96, 32)]

@@ -212,3 +212,24 @@ def test_multi_step_graph_replays_match_direct_launches(gpu_lib, precision):
         for name in direct.fields:
             assert np.array_equal(direct.get_state(name), replay.get_state(name)), (dt, n, name)
         assert np.array_equal(direct.get_pressure(), replay.get_pressure()), (dt, n)
+
+
+def test_profile_classes_restrict_event_recording(gpu_lib):
+    """oc_profile_classes: events around the chosen kernel classes only; the
+    default records every class of the step."""
+    ph, s = make_case("conv_32x32x16")
+    m = gpu_lib.Model(ph, "fp32")
+    m.set_states(_prep(s, ph, "fp32"))
+    m.profile(True, classes=("tendency",))
+    m.rk3_step(1.0, 2)
+    m.profile(False)
+    p = m.profile_read()
+    assert p["tendency"][1] == 6 and p["tendency"][0] > 0
+    assert all(n == 0 for k, (_, n) in p.items() if k != "tendency"), p
+    m.profile(True)
+    m.rk3_step(1.0, 1)
+    m.profile(False)
+    p = m.profile_read()
+    for k in ("tendency", "fft_x_fwd", "fft_y_fwd", "z_solve", "fft_y_inv", "project"):
+        assert p[k][1] == 3, (k, p[k])
+    assert p["fft_x_inv"][1] == 0   # fused into the projection
