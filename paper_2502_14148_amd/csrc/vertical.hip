@@ -109,7 +109,13 @@ __global__ void __launch_bounds__(64 * VCH) vimplicit_kernel(Dims d, VImplicitAr
   // the chunk is the wavefront index: uniform, so the tables are scalar loads
   const int lane = threadIdx.x & 63;
   const int c = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int col = blockIdx.x * 64 + lane;
+  // Workgroups are dealt round-robin to the 8 XCDs (XCD x takes x, x + 8,
+  // ...); renumber the column groups so that each XCD takes a contiguous run
+  // of them: neighbouring groups share the cache lines at their ends (rows
+  // are not 128-byte aligned), which then meet in one L2
+  const int ng = (int)gridDim.x, bx = (int)blockIdx.x, xcd = bx % 8;
+  const int grp = xcd * (ng / 8) + min(xcd, ng % 8) + bx / 8;
+  const int col = grp * 64 + lane;
   const bool valid = col < d.nx * d.ny;
   const int i = valid ? col % d.nx : 0, j = valid ? col / d.nx : 0;
   const int q0 = c * C;
