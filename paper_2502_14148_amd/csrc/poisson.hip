@@ -793,11 +793,12 @@ __global__ void __launch_bounds__(PJ_X * PJ_Y) project_kernel(
 
 // ---------------------------------------------------------------------------
 // Pass 5 fused with the projection (the FFT/DCT solve of the whole box).  A
-// workgroup takes rb <= RB = 2 LP - 1 rows, j0 .. j0 + rb - 1 (the rows are
+// workgroup takes rb <= RB = 2 L - 1 rows, j0 .. j0 + rb - 1 (the rows are
 // dealt evenly to the fewest blocks of at most RB; a block of one member is
-// a column), and a chunk of the column's levels.  At every level it transforms LP packed lines back to p: line l
-// holds rows j0 - 1 + 2l and j0 + 2l (Z = X_a + i X_b of their Hermitian half
-// rows), so the row below the block (periodic in y) comes along in line 0.
+// a column), and a chunk of the column's levels.  At every level it
+// transforms L packed lines back to p: line l holds rows j0 - 1 + 2l and
+// j0 + 2l (Z = X_a + i X_b of their Hermitian half rows), so the row below
+// the block (periodic in y) comes along in line 0.
 // It then subtracts scale * grad p from u, v and w of its rows: p at i - 1
 // and j - 1 come from the lines in LDS, p of the level below from registers
 // (the level below the chunk is transformed once more first).  p is not
